@@ -1,0 +1,177 @@
+/*
+ * graphlet4 -- batch fully dynamic counting of all induced 4-vertex
+ * graphlets on one AMD MI355X (gfx950).
+ *
+ * What is computed.  For a simple undirected graph G = (V, E) on a fixed
+ * vertex set V = {0..n-1}, the eleven counts
+ *     I_c = |{ S subset of V : |S| = 4, G[S] isomorphic to class c }|
+ * indexed by gc_class below: the six connected induced 4-graphlets of Fig. 1
+ * of the paper (3-path g1, 3-star g2, 4-cycle g3, tailed triangle g4,
+ * diamond g5, 4-clique g6) and the five disconnected graphs on four vertices.
+ * Problem 1 asks to maintain these under batches B = A u D of edge
+ * insertions A and deletions D, giving the counts of (V, E + A - D).
+ *
+ * How.  Alg. 2 (FDGC): per batch the library marks the region of change
+ * around the changed pairs, counts its graphlets before (G_b) and after
+ * (G_a) the batch with a per-edge static counter (triangles, 4-cliques,
+ * 4-cycles and combinatorics) in one fused pass on the GPU, adds C_a - C_b
+ * to the maintained connected counts (Lemma 2) and then applies the batch to
+ * the resident graph.  The five disconnected classes are not local; they
+ * follow from the connected counts and the global totals n, m,
+ * W = sum_v C(deg v, 2) and the triangle count, which are maintained too.
+ *
+ * Batch semantics (stream model of Sec. 3, batch protocol of Sec. 5):
+ *   - (u, v) and (v, u) name the same edge; self loops are ignored;
+ *   - repeated pairs inside the insertions (or the deletions) collapse;
+ *   - a pair that is both inserted and deleted by one batch is dropped and
+ *     leaves the graph unchanged;
+ *   - inserting an existing edge or deleting a missing one has no effect;
+ *   - an id outside [0, n) rejects the whole batch (GC_EINVAL) and leaves
+ *     the graph and its counts unchanged.
+ *
+ * Conventions.  Every function returns GC_OK (0) or a negative gc_status.
+ * On error the graph is unchanged and gc_last_error() describes the cause
+ * (thread-local string).  Input arrays are borrowed for the duration of the
+ * call only: host arrays are copied before the call returns; device arrays
+ * (the _dev variants) must stay valid until the call returns.  A handle owns
+ * all of its device memory; it is not re-entrant (one call at a time per
+ * handle), distinct handles may be used from distinct threads.
+ *
+ * Counts are int64.  For n > 121977 the empty class exceeds 2^63 - 1: its
+ * int64 value is then the low 64 bits (two's complement) and bit c of the
+ * overflow mask is set; gc_get_counts_exact returns every class exactly as a
+ * 128-bit (hi, lo) pair.
+ */
+#ifndef GRAPHLET4_H
+#define GRAPHLET4_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gc_graph gc_graph;
+
+typedef enum {
+  GC_OK = 0,
+  GC_EINVAL = -1,   /* bad argument or vertex id out of range */
+  GC_ENOMEM = -2,   /* device or host allocation failed */
+  GC_EDEVICE = -3,  /* HIP runtime error, or no usable gfx950 device */
+  GC_EBUSY = -4,    /* server queue full */
+  GC_ESTATE = -5    /* handle unusable after an earlier device failure */
+} gc_status;
+
+typedef enum {
+  GC_P4 = 0,       /* 3-path (g1) */
+  GC_STAR = 1,     /* 3-star (g2) */
+  GC_C4 = 2,       /* 4-cycle (g3) */
+  GC_PAW = 3,      /* tailed triangle (g4) */
+  GC_DIAMOND = 4,  /* diamond (g5) */
+  GC_K4 = 5,       /* 4-clique (g6) */
+  GC_TRI_ISO = 6,  /* triangle + isolated vertex */
+  GC_P3_ISO = 7,   /* 2-path + isolated vertex */
+  GC_2K2 = 8,      /* two disjoint edges */
+  GC_K2_2ISO = 9,  /* one edge + two isolated vertices */
+  GC_EMPTY = 10,   /* no edge */
+  GC_NUM_CLASSES = 11
+} gc_class;
+
+typedef struct {
+  /* Region of change: vertices within `radius` hops of a changed pair,
+   * counted on the subgraph they induce.  Alg. 2 uses 3-hop balls; 2 hops
+   * already contain every 4-vertex set that holds a changed pair and is
+   * connected in either version, so 2 is exact and the default.  0 counts
+   * the whole graph (also exact).  1 is NOT exact and exists only so that
+   * tests can show that the region matters. */
+  int32_t radius;
+  /* Free space left in every adjacency row when it is (re)built, as a
+   * fraction of its length (default 0.25). */
+  float slack;
+  /* HIP device ordinal (default 0). */
+  int32_t device;
+  /* hipStream_t to run on (NULL = the library's own stream). */
+  void* stream;
+} gc_options;
+
+typedef struct {
+  int64_t offered_ins, offered_del;  /* as submitted */
+  int64_t eff_ins, eff_del;          /* effective insertions / deletions */
+  int64_t loops, dups, cancelled, ins_existing, del_missing;
+  int64_t touched_vertices;          /* endpoints of effective changes */
+  int64_t region_vertices, region_entries;  /* region size (entries = 2 x edges) */
+  int64_t wedge_bound;               /* 4-cycle wedge work bound */
+  int64_t max_out_degree;
+  int64_t tier_tri_small, tier_tri_large, tier_c4_small, tier_c4_mid, tier_c4_large;
+  uint32_t overflow_mask;            /* classes whose count left int64 */
+  float ms_total;                    /* wall time of the call */
+  float ms_prepare;                  /* ingest, merge, region (device) */
+  float ms_tri, ms_edge, ms_c4;      /* counting kernels (device) */
+  float ms_finish;                   /* combine + purge (device) */
+} gc_batch_stats;
+
+/* One batch for one graph of a pool (host pointers). */
+typedef struct {
+  const int32_t* ins_src; const int32_t* ins_dst; int64_t n_ins;
+  const int32_t* del_src; const int32_t* del_dst; int64_t n_del;
+} gc_batch_desc;
+
+/* Fills *opt with the defaults (radius 2, slack 0.25, device 0, own stream). */
+int gc_options_default(gc_options* opt);
+
+/* Builds the resident graph on n vertices from m edge pairs (src[i],
+ * dst[i]) (host arrays; loops ignored, repeats collapse) and returns its
+ * counts.  Following Alg. 2's initialisation (F = 0), this is one batch
+ * inserting every edge into the empty graph on n vertices.
+ * n must be in [1, 2^30); opt may be NULL; counts may be NULL. */
+int gc_graph_init(int64_t n, const int32_t* src, const int32_t* dst, int64_t m,
+                  const gc_options* opt, gc_graph** out, int64_t counts[11]);
+
+/* Several independent graphs in one handle ("pool"): graph g has n[g]
+ * vertices and m[g] edges.  Batches for all of them are then applied
+ * together by gc_apply_batches (one pass of device work for all graphs).
+ * counts (k x 11) may be NULL. */
+int gc_pool_init(int32_t k, const int64_t* n, const int32_t* const* src, const int32_t* const* dst,
+                 const int64_t* m, const gc_options* opt, gc_graph** out, int64_t (*counts)[11]);
+
+/* Applies one batch (host arrays) to a single-graph handle and returns the
+ * counts after it (Problem 1).  stats may be NULL. */
+int gc_apply_batch(gc_graph* g, const int32_t* ins_src, const int32_t* ins_dst, int64_t n_ins,
+                   const int32_t* del_src, const int32_t* del_dst, int64_t n_del,
+                   int64_t counts[11], gc_batch_stats* stats);
+
+/* Same with device arrays (int32, on the handle's device). */
+int gc_apply_batch_dev(gc_graph* g, const int32_t* ins_src, const int32_t* ins_dst, int64_t n_ins,
+                       const int32_t* del_src, const int32_t* del_dst, int64_t n_del,
+                       int64_t counts[11], gc_batch_stats* stats);
+
+/* Applies batch[g] to graph g of a pool, for all k graphs at once; counts
+ * is k x 11 (may be NULL).  The batches are independent; the result for
+ * each graph equals k separate gc_apply_batch calls. */
+int gc_apply_batches(gc_graph* pool, const gc_batch_desc* batch, int64_t (*counts)[11],
+                     gc_batch_stats* stats);
+
+/* Current counts of graph `graph` (0 for a single-graph handle). */
+int gc_get_counts(const gc_graph* g, int32_t graph, int64_t counts[11], uint32_t* overflow_mask);
+int gc_get_counts_exact(const gc_graph* g, int32_t graph, int64_t hi[11], uint64_t lo[11]);
+
+/* Static recount of graph `graph` from scratch on the GPU (the baseline of
+ * Sec. 4.1); does not change the maintained counts.  For checking. */
+int gc_recount_exact(gc_graph* g, int32_t graph, int64_t hi[11], uint64_t lo[11]);
+
+/* Number of graphs, vertices and edges. */
+int gc_graph_info(const gc_graph* g, int32_t* num_graphs, int32_t graph, int64_t* n, int64_t* m);
+
+/* Copies the edges of graph `graph` (each once, external ids) into host
+ * arrays of capacity cap; *m_out = edge count (GC_EINVAL if cap < m). */
+int gc_export_edges(gc_graph* g, int32_t graph, int32_t* src, int32_t* dst, int64_t cap, int64_t* m_out);
+
+int gc_graph_free(gc_graph* g);
+
+const char* gc_strerror(int code);
+const char* gc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRAPHLET4_H */

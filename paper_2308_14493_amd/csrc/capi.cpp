@@ -1,0 +1,898 @@
+// C ABI of the graphlet-4 library: handle management, the per-batch
+// pipeline (ingest -> merge -> region -> count -> combine -> purge) on one
+// HIP stream, and the exact 128-bit finalisation of the eleven counts.
+#include "../../include/graphlet4.h"
+#include "gc_kernels.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+struct GcError {
+  int code;
+};
+
+[[noreturn]] void raise(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  throw GcError{code};
+}
+
+#define HIPCHK(x)                                                                           \
+  do {                                                                                      \
+    hipError_t e_ = (x);                                                                    \
+    if (e_ != hipSuccess) raise(GC_EDEVICE, "%s failed: %s", #x, hipGetErrorString(e_));     \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  // grow-only; contents are not preserved
+  void ensure(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (bytes <= cap) return;
+    release();
+    size_t nb = std::max(bytes, cap + cap / 2);
+    hipError_t e = hipMalloc(&p, nb);
+    if (e != hipSuccess) {
+      p = nullptr;
+      raise(GC_ENOMEM, "hipMalloc(%zu bytes) failed: %s", nb, hipGetErrorString(e));
+    }
+    cap = nb;
+  }
+  template <class T> T* as() const { return (T*)p; }
+  void swap(DevBuf& o) { std::swap(p, o.p); std::swap(cap, o.cap); }
+};
+
+int bits_for(int64_t x) {  // smallest b >= 1 with x <= 2^b
+  int b = 1;
+  while (b < 62 && (1ll << b) < x) ++b;
+  return b;
+}
+
+typedef __int128 i128;
+
+i128 c2w(i128 x) { return x * (x - 1) / 2; }
+i128 c4w(i128 x) { return x * (x - 1) * (x - 2) * (x - 3) / 24; }
+
+// The five disconnected classes from the connected counts and global totals
+// (sums over all 4-subsets of: triangles, 2-paths, disjoint edge pairs,
+// edges, subsets), in exact 128-bit arithmetic.
+void finalize(const long long* st, int64_t n, i128 I[11]) {
+  for (int c = 0; c < 6; ++c) I[c] = st[ST_F0 + c];
+  const i128 T = st[ST_T], W = st[ST_W], m = st[ST_M], nn = n;
+  I[6] = T * (nn - 3) - I[3] - 2 * I[4] - 4 * I[5];
+  I[7] = W * (nn - 3) - 3 * I[6] - 3 * I[1] - 2 * I[0] - 4 * I[2] - 5 * I[3] - 8 * I[4] - 12 * I[5];
+  I[8] = (c2w(m) - W) - I[0] - 2 * I[2] - I[3] - 2 * I[4] - 3 * I[5];
+  I[9] = m * c2w(nn - 2) - 2 * I[8] - 2 * I[7] - 3 * I[6] - 3 * I[1] - 3 * I[0] - 4 * I[2] - 4 * I[3] -
+         5 * I[4] - 6 * I[5];
+  i128 s = 0;
+  for (int c = 0; c < 10; ++c) s += I[c];
+  I[10] = c4w(nn) - s;
+}
+
+void to_int64(const i128 I[11], int64_t out[11], uint32_t* mask) {
+  uint32_t mk = 0;
+  for (int c = 0; c < 11; ++c) {
+    out[c] = (int64_t)(uint64_t)I[c];
+    if (I[c] > (i128)INT64_MAX || I[c] < (i128)INT64_MIN) mk |= 1u << c;
+  }
+  if (mask) *mask = mk;
+}
+
+constexpr int TRI_SMALL = 64;
+constexpr int C4_SMALL = 256;
+constexpr int C4_MID = 4096;
+constexpr int TL_LDS_MAX = 2048;
+
+}  // namespace
+
+struct gc_graph {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  gc_options opt{};
+  bool broken = false;
+
+  int32_t k = 1;
+  std::vector<int64_t> gbase, gn;
+  int64_t N = 0;
+  int bits = 1;
+
+  // resident graph
+  DevBuf off, len, cap, col, top, gid, ext2int, int2ext;
+  int64_t arena_cap = 0, arena_top = 0, entries = 0;
+
+  // small device state
+  DevBuf state, state_tmp, sig, ctr, bstats, tables;
+  std::vector<long long> hstate;
+
+  // batch scratch
+  DevBuf bin, keys, keys_alt, dirA, dirA_alt, dirD, dirD_alt;
+  DevBuf a_beg, na, d_beg, nd, mark, tix;
+  DevBuf touched, dest, newcap, tlen, tpre, scratch, sort_tmp, scan_tmp;
+
+  // region and counting
+  DevBuf roff, rcol, rlow, dB, dA, t, level, rlist, rlen, lists;
+  DevBuf c4_dense, c4_touch, tri_scratch;
+  int32_t c4_slots = 0, tri_slots = 0;
+  int64_t tri_slot_words = 0;
+
+  void* pin = nullptr;
+  size_t pin_cap = 0;
+  hipEvent_t ev[8] = {};
+
+  ~gc_graph() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (pin) (void)hipHostFree(pin);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+
+  PoolDev pd() const {
+    PoolDev P;
+    P.N = N;
+    P.off = off.as<int64_t>();
+    P.len = len.as<int32_t>();
+    P.cap = cap.as<int32_t>();
+    P.col = col.as<uint32_t>();
+    P.arena_cap = arena_cap;
+    P.arena_top = top.as<unsigned long long>();
+    P.gid = gid.as<int32_t>();
+    P.ext2int = ext2int.as<int32_t>();
+    return P;
+  }
+  RegionDev rd() const {
+    RegionDev R;
+    R.roff = roff.as<int64_t>();
+    R.rcol = rcol.as<uint32_t>();
+    R.rlow = rlow.as<int32_t>();
+    R.dB = dB.as<int32_t>();
+    R.dA = dA.as<int32_t>();
+    R.t = t.as<unsigned long long>();
+    return R;
+  }
+  void* pinned(size_t bytes) {
+    if (bytes > pin_cap) {
+      if (pin) (void)hipHostFree(pin);
+      pin = nullptr;
+      size_t nb = std::max(bytes, pin_cap * 2);
+      HIPCHK(hipHostMalloc(&pin, nb, hipHostMallocDefault));
+      pin_cap = nb;
+    }
+    return pin;
+  }
+  void sync() { HIPCHK(hipStreamSynchronize(stream)); }
+  int64_t m_total() const {
+    int64_t s = 0;
+    for (int g = 0; g < k; ++g) s += hstate[g * ST_STRIDE + ST_M];
+    return s;
+  }
+};
+
+namespace {
+
+void zero_small(gc_graph* G) {
+  fill_u64(G->ctr.as<unsigned long long>(), 0ull, C_COUNT, G->stream);
+  fill_u64(G->bstats.as<unsigned long long>(), 0ull, BS_COUNT, G->stream);
+  fill_u64(G->sig.as<unsigned long long>(), 0ull, (int64_t)G->k * 2 * SG_N, G->stream);
+}
+
+// Region + per-vertex pass + counting + combine into `state_d`.  `radius` < 0
+// counts every vertex.  Host copy of the counters goes to hc.
+void run_count(gc_graph* G, int radius, long long* state_d, BatchWork& W, std::vector<unsigned long long>& hc,
+               int64_t union_entries, bool timed) {
+  hipStream_t s = G->stream;
+  const int64_t N = G->N;
+  G->roff.ensure((N + 1) * sizeof(int64_t));
+  G->rcol.ensure(std::max<int64_t>(union_entries, 1) * sizeof(uint32_t));
+  G->t.ensure(std::max<int64_t>(union_entries, 1) * sizeof(unsigned long long));
+  G->scan_tmp.ensure(scan_tmp_bytes(N + 1) + 64);
+  PoolDev P = G->pd();
+  RegionDev R = G->rd();
+  launch_region(P, W, radius, G->level.as<int32_t>(), G->rlist.as<int32_t>(), G->rlen.as<int32_t>(), s);
+  launch_region_fill(P, R, W, radius, G->level.as<int32_t>(), G->rlist.as<int32_t>(), G->rlen.as<int32_t>(),
+                     G->scan_tmp.p, s);
+  launch_degrees(R, G->gid.as<int32_t>(), G->rlist.as<int32_t>(), G->ctr.as<unsigned long long>(),
+                 G->sig.as<unsigned long long>(), G->lists.as<int32_t>(), N, TRI_SMALL, C4_SMALL, C4_MID,
+                 G->bstats.as<unsigned long long>(), s);
+  if (timed) HIPCHK(hipEventRecord(G->ev[1], s));
+  hc.assign(C_COUNT, 0);
+  HIPCHK(hipMemcpyAsync(hc.data(), G->ctr.p, C_COUNT * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  G->sync();
+  if ((int64_t)hc[C_ER] > union_entries) raise(GC_EDEVICE, "region larger than the union view");
+
+  CountArgs A;
+  A.R = R;
+  A.gid = G->gid.as<int32_t>();
+  A.lists = G->lists.as<int32_t>();
+  A.list_stride = N;
+  A.c = G->ctr.as<unsigned long long>();
+  A.sig = G->sig.as<unsigned long long>();
+  A.bstats = G->bstats.as<unsigned long long>();
+  A.N = N;
+  // large 4-cycle tier: dense counters per resident workgroup
+  const int64_t ncl = (int64_t)hc[C_LIST0 + L_C4_L];
+  if (ncl > 0) {
+    int64_t per = N * (int64_t)(sizeof(unsigned long long) + sizeof(int32_t));
+    int64_t budget = (int64_t)8 << 30;
+    int64_t slots = std::max<int64_t>(1, std::min<int64_t>(512, budget / std::max<int64_t>(per, 1)));
+    slots = std::min(slots, std::max<int64_t>(ncl, 1));
+    if (slots > G->c4_slots) {
+      G->c4_dense.release();
+      G->c4_touch.release();
+      G->c4_dense.ensure((size_t)(slots * N) * sizeof(unsigned long long));
+      G->c4_touch.ensure((size_t)(slots * N) * sizeof(int32_t));
+      fill_u64(G->c4_dense.as<unsigned long long>(), 0ull, slots * N, s);
+      G->c4_slots = (int32_t)slots;
+    }
+  }
+  A.c4_dense = G->c4_dense.as<unsigned long long>();
+  A.c4_touch = G->c4_touch.as<int32_t>();
+  A.slots = std::max(1, G->c4_slots);
+  // triangles above the LDS tier: scratch slots in global memory
+  const int64_t maxdp = (int64_t)hc[C_MAXDP];
+  if (maxdp > TL_LDS_MAX) {
+    if (maxdp > 32767) raise(GC_EINVAL, "oriented out-degree %lld exceeds the supported 32767", (long long)maxdp);
+    int64_t words = 16 * maxdp;
+    int32_t slots = 256;
+    if (words > G->tri_slot_words || slots > G->tri_slots) {
+      G->tri_scratch.release();
+      G->tri_scratch.ensure((size_t)(words * slots) * sizeof(uint32_t));
+      G->tri_slot_words = words;
+      G->tri_slots = slots;
+    }
+  }
+  A.tri_scratch = G->tri_scratch.as<uint32_t>();
+  A.tri_slot_words = G->tri_slot_words;
+  // the global-scratch triangle kernel runs with at most tri_slots workgroups
+  if (A.slots > 0 && maxdp > TL_LDS_MAX) A.slots = std::min(A.slots, G->tri_slots);
+  CountArgs A2 = A;
+  A2.slots = std::max(1, G->c4_slots);
+  (void)A2;
+  launch_count(A, hc.data(), s, timed ? &G->ev[2] : nullptr);
+  launch_combine(G->sig.as<unsigned long long>(), state_d, G->k, s);
+}
+
+BatchWork make_work(gc_graph* G) {
+  BatchWork W;
+  W.c = G->ctr.as<unsigned long long>();
+  W.dirA = G->dirA.as<unsigned long long>();
+  W.dirD = G->dirD.as<unsigned long long>();
+  W.a_beg = G->a_beg.as<int32_t>();
+  W.na = G->na.as<int32_t>();
+  W.d_beg = G->d_beg.as<int32_t>();
+  W.nd = G->nd.as<int32_t>();
+  W.mark = G->mark.as<int32_t>();
+  W.tix = G->tix.as<int32_t>();
+  W.touched = G->touched.as<int32_t>();
+  W.dest = G->dest.as<int64_t>();
+  W.newcap = G->newcap.as<int32_t>();
+  W.tlen = G->tlen.as<int32_t>();
+  W.tpre = G->tpre.as<int64_t>();
+  W.scratch = G->scratch.as<uint32_t>();
+  return W;
+}
+
+void alloc_vertex_arrays(gc_graph* G) {
+  const int64_t N = G->N;
+  hipStream_t s = G->stream;
+  for (DevBuf* b : {&G->a_beg, &G->na, &G->d_beg, &G->nd, &G->mark, &G->tix}) {
+    b->ensure(N * sizeof(int32_t));
+    fill_u32(b->as<uint32_t>(), 0u, N, s);
+  }
+  for (DevBuf* b : {&G->rlow, &G->dB, &G->dA, &G->level, &G->rlist, &G->rlen}) b->ensure(N * sizeof(int32_t));
+  G->lists.ensure((size_t)L_NUM * N * sizeof(int32_t));
+  G->state.ensure((size_t)G->k * ST_STRIDE * sizeof(long long));
+  G->state_tmp.ensure((size_t)G->k * ST_STRIDE * sizeof(long long));
+  G->sig.ensure((size_t)G->k * 2 * SG_N * sizeof(unsigned long long));
+  G->ctr.ensure(C_COUNT * sizeof(unsigned long long));
+  G->bstats.ensure(BS_COUNT * sizeof(unsigned long long));
+  G->top.ensure(sizeof(unsigned long long));
+}
+
+// fresh arena with new slack; keeps ids
+void compact(gc_graph* G, int64_t extra) {
+  hipStream_t s = G->stream;
+  const int64_t N = G->N;
+  DevBuf ncap, noff, ncol;
+  ncap.ensure(N * sizeof(int32_t));
+  noff.ensure((N + 1) * sizeof(int64_t));
+  PoolDev P = G->pd();
+  P.cap = ncap.as<int32_t>();
+  launch_caps(P, G->opt.slack, s);
+  G->scan_tmp.ensure(scan_tmp_bytes(N + 1) + 64);
+  exclusive_scan_i32_to_i64(ncap.as<int32_t>(), noff.as<int64_t>(), N, G->scan_tmp.p, s);
+  int64_t used = 0;
+  HIPCHK(hipMemcpyAsync(&used, noff.as<int64_t>() + N, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  G->sync();
+  int64_t capn = std::max<int64_t>(4 * used, used + extra + (1 << 20));
+  ncol.ensure((size_t)capn * sizeof(uint32_t));
+  launch_compact(G->pd(), noff.as<int64_t>(), ncol.as<uint32_t>(), s);
+  G->sync();
+  G->col.swap(ncol);
+  G->off.swap(noff);
+  G->cap.swap(ncap);
+  G->arena_cap = capn;
+  G->arena_top = used;
+  HIPCHK(hipMemcpyAsync(G->top.p, &G->arena_top, sizeof(int64_t), hipMemcpyHostToDevice, s));
+  G->sync();
+}
+
+void read_state(gc_graph* G) {
+  G->hstate.resize((size_t)G->k * ST_STRIDE);
+  HIPCHK(hipMemcpyAsync(G->hstate.data(), G->state.p, G->hstate.size() * sizeof(long long), hipMemcpyDeviceToHost,
+                        G->stream));
+  G->sync();
+}
+
+void setup_handle(gc_graph* G, const gc_options* opt) {
+  if (opt) G->opt = *opt; else gc_options_default(&G->opt);
+  if (G->opt.radius < 0 || G->opt.radius > 4) raise(GC_EINVAL, "radius must be in [0, 4]");
+  if (!(G->opt.slack >= 0.0f && G->opt.slack <= 16.0f)) raise(GC_EINVAL, "slack must be in [0, 16]");
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (G->opt.device < 0 || G->opt.device >= ndev) raise(GC_EDEVICE, "device %d not present", G->opt.device);
+  G->device = G->opt.device;
+  HIPCHK(hipSetDevice(G->device));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, G->device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    raise(GC_EDEVICE, "device %d is %s; this library is built for gfx950", G->device, prop.gcnArchName);
+  if (G->opt.stream) {
+    G->stream = (hipStream_t)G->opt.stream;
+  } else {
+    HIPCHK(hipStreamCreateWithFlags(&G->stream, hipStreamNonBlocking));
+    G->own_stream = true;
+  }
+  for (auto& e : G->ev) HIPCHK(hipEventCreate(&e));
+}
+
+// Build k graphs from host edge lists and count them (one insertion batch
+// into the empty graph: version b is empty, every entry carries F_NEW).
+void build(gc_graph* G, int32_t k, const int64_t* n, const int32_t* const* src, const int32_t* const* dst,
+           const int64_t* m) {
+  hipStream_t s = G->stream;
+  G->k = k;
+  G->gbase.assign(k, 0);
+  G->gn.assign(n, n + k);
+  int64_t N = 0, M = 0, maxn = 1;
+  for (int g = 0; g < k; ++g) {
+    if (n[g] < 1) raise(GC_EINVAL, "graph %d: n must be >= 1", g);
+    if (m[g] < 0) raise(GC_EINVAL, "graph %d: negative edge count", g);
+    if (m[g] > 0 && (!src || !src[g] || !dst || !dst[g])) raise(GC_EINVAL, "graph %d: null edge arrays", g);
+    G->gbase[g] = N;
+    N += n[g];
+    M += m[g];
+    maxn = std::max(maxn, n[g]);
+    for (int64_t i = 0; i < m[g]; ++i)
+      if (src[g][i] < 0 || src[g][i] >= n[g] || dst[g][i] < 0 || dst[g][i] >= n[g])
+        raise(GC_EINVAL, "graph %d: edge %lld has a vertex id outside [0, %lld)", g, (long long)i, (long long)n[g]);
+  }
+  if (N >= GC_MAX_VERTICES) raise(GC_EINVAL, "total vertex count must be below 2^30");
+  G->N = N;
+  G->bits = bits_for(N);
+  const int lbits = bits_for(maxn + 1);
+  const int gbits = k > 1 ? bits_for(k) : 0;
+  if (gbits + 2 * lbits > 64) raise(GC_EINVAL, "graphs too large for one pool");
+
+  alloc_vertex_arrays(G);
+  // per-vertex graph ids
+  {
+    std::vector<int32_t> gid(N);
+    for (int g = 0; g < k; ++g) std::fill(gid.begin() + G->gbase[g], gid.begin() + G->gbase[g] + n[g], g);
+    G->gid.ensure(N * sizeof(int32_t));
+    HIPCHK(hipMemcpyAsync(G->gid.p, gid.data(), N * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    G->sync();
+  }
+  // upload the edge lists and the segment tables
+  DevBuf esrc, edst, seg, gb;
+  esrc.ensure(std::max<int64_t>(M, 1) * sizeof(int32_t));
+  edst.ensure(std::max<int64_t>(M, 1) * sizeof(int32_t));
+  std::vector<int64_t> hseg(k + 1, 0);
+  for (int g = 0; g < k; ++g) {
+    hseg[g + 1] = hseg[g] + m[g];
+    if (m[g]) {
+      HIPCHK(hipMemcpyAsync(esrc.as<int32_t>() + hseg[g], src[g], m[g] * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(edst.as<int32_t>() + hseg[g], dst[g], m[g] * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    }
+  }
+  seg.ensure((k + 1) * sizeof(int64_t));
+  gb.ensure(k * sizeof(int64_t));
+  HIPCHK(hipMemcpyAsync(seg.p, hseg.data(), (k + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(gb.p, G->gbase.data(), k * sizeof(int64_t), hipMemcpyHostToDevice, s));
+
+  zero_small(G);
+  DevBuf ek, ek2, uniq, deg;
+  ek.ensure(std::max<int64_t>(M, 1) * 8);
+  ek2.ensure(std::max<int64_t>(M, 1) * 8);
+  uniq.ensure(std::max<int64_t>(M, 1) * 8);
+  deg.ensure(N * sizeof(int32_t));
+  fill_u32(deg.as<uint32_t>(), 0u, N, s);
+  G->sort_tmp.ensure(radix_sort_tmp_bytes(std::max<int64_t>(2 * M, N)) + 64);
+  launch_init_keys(esrc.as<int32_t>(), edst.as<int32_t>(), M, seg.as<int64_t>(), gb.as<int64_t>(), k, G->bits,
+                   ek.as<unsigned long long>(), s);
+  unsigned long long* sk =
+      radix_sort_u64(ek.as<unsigned long long>(), ek2.as<unsigned long long>(), G->sort_tmp.p, M, nullptr,
+                     2 * G->bits, s);
+  launch_init_unique(sk, M, G->bits, uniq.as<unsigned long long>(), G->ctr.as<unsigned long long>(),
+                     deg.as<int32_t>(), s);
+  // rank: (graph, degree, local id)
+  G->ext2int.ensure(N * sizeof(int32_t));
+  G->int2ext.ensure(N * sizeof(int32_t));
+  DevBuf rk, rk2;
+  rk.ensure(N * 8);
+  rk2.ensure(N * 8);
+  launch_rank(deg.as<int32_t>(), G->gid.as<int32_t>(), gb.as<int64_t>(), N, lbits, gbits + 2 * lbits,
+              rk.as<unsigned long long>(), rk2.as<unsigned long long>(), G->sort_tmp.p, G->ext2int.as<int32_t>(),
+              G->int2ext.as<int32_t>(), s);
+  // directed entries in internal ids
+  DevBuf dir, dir2;
+  dir.ensure(std::max<int64_t>(2 * M, 1) * 8);
+  dir2.ensure(std::max<int64_t>(2 * M, 1) * 8);
+  G->len.ensure(N * sizeof(int32_t));
+  fill_u32(G->len.as<uint32_t>(), 0u, N, s);
+  launch_init_dir(uniq.as<unsigned long long>(), M, G->ctr.as<unsigned long long>(), G->bits, G->ext2int.as<int32_t>(),
+                  dir.as<unsigned long long>(), G->len.as<int32_t>(), s);
+  unsigned long long mu = 0;
+  HIPCHK(hipMemcpyAsync(&mu, G->ctr.as<unsigned long long>() + C_DIRA, 8, hipMemcpyDeviceToHost, s));
+  G->sync();
+  const int64_t nd = 2 * (int64_t)mu;
+  unsigned long long* sd = radix_sort_u64(dir.as<unsigned long long>(), dir2.as<unsigned long long>(), G->sort_tmp.p,
+                                          nd, nullptr, 2 * G->bits, s);
+  // rows with slack
+  G->cap.ensure(N * sizeof(int32_t));
+  G->off.ensure((N + 1) * sizeof(int64_t));
+  DevBuf rstart;
+  rstart.ensure((N + 1) * sizeof(int64_t));
+  G->scan_tmp.ensure(scan_tmp_bytes(N + 1) + 64);
+  PoolDev P = G->pd();
+  launch_caps(P, G->opt.slack, s);
+  exclusive_scan_i32_to_i64(P.len, rstart.as<int64_t>(), N, G->scan_tmp.p, s);
+  exclusive_scan_i32_to_i64(P.cap, P.off, N, G->scan_tmp.p, s);
+  int64_t used = 0;
+  HIPCHK(hipMemcpyAsync(&used, P.off + N, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  G->sync();
+  G->arena_cap = std::max<int64_t>(4 * used, used + (1 << 20));
+  G->col.ensure((size_t)G->arena_cap * sizeof(uint32_t));
+  G->arena_top = used;
+  HIPCHK(hipMemcpyAsync(G->top.p, &G->arena_top, sizeof(int64_t), hipMemcpyHostToDevice, s));
+  P = G->pd();
+  launch_init_csr(P, sd, nd, G->ctr.as<unsigned long long>(), G->bits, rstart.as<int64_t>(), G->opt.slack,
+                  G->scan_tmp.p, GC_F_NEW, s);
+  // the fill kernel reads the number of edges from ctr[C_DIRA]
+  // count: whole graph, version b empty
+  fill_u64((unsigned long long*)G->state.p, 0ull, (int64_t)k * ST_STRIDE, s);
+  zero_small(G);
+  BatchWork W = make_work(G);
+  std::vector<unsigned long long> hc;
+  run_count(G, -1, G->state.as<long long>(), W, hc, nd, false);
+  launch_all_flags(P, 0u, GC_ID, s);
+  G->sync();
+  G->entries = nd;
+  read_state(G);
+  for (int g = 0; g < k; ++g) G->hstate[g * ST_STRIDE + ST_N] = n[g];
+}
+
+struct HostBatch {
+  // concatenated over graphs
+  std::vector<int64_t> ins_seg, del_seg;
+  int64_t n_ins = 0, n_del = 0;
+};
+
+void fill_stats(gc_graph* G, gc_batch_stats* st, const std::vector<unsigned long long>& hb,
+                const std::vector<unsigned long long>& hc, int64_t n_ins, int64_t n_del, bool timed,
+                double ms_total, uint32_t ovf) {
+  if (!st) return;
+  std::memset(st, 0, sizeof(*st));
+  st->offered_ins = n_ins;
+  st->offered_del = n_del;
+  st->eff_ins = (int64_t)hb[BS_EFF_INS];
+  st->eff_del = (int64_t)hb[BS_EFF_DEL];
+  st->loops = (int64_t)hb[BS_LOOPS];
+  st->dups = (int64_t)hb[BS_DUPS];
+  st->cancelled = (int64_t)hb[BS_CANCEL];
+  st->ins_existing = (int64_t)hb[BS_INS_EXIST];
+  st->del_missing = (int64_t)hb[BS_DEL_MISS];
+  st->touched_vertices = (int64_t)hc[C_TOUCH];
+  st->region_vertices = (int64_t)hc[C_RLIST];
+  st->region_entries = (int64_t)hc[C_ER];
+  st->wedge_bound = (int64_t)hb[BS_WEDGES];
+  st->max_out_degree = (int64_t)hc[C_MAXDP];
+  st->tier_tri_small = (int64_t)hc[C_LIST0 + L_TRI_S];
+  st->tier_tri_large = (int64_t)hc[C_LIST0 + L_TRI_L];
+  st->tier_c4_small = (int64_t)hc[C_LIST0 + L_C4_S];
+  st->tier_c4_mid = (int64_t)hc[C_LIST0 + L_C4_M];
+  st->tier_c4_large = (int64_t)hc[C_LIST0 + L_C4_L];
+  st->overflow_mask = ovf;
+  st->ms_total = (float)ms_total;
+  if (timed) {
+    float a = 0;
+    (void)hipEventElapsedTime(&a, G->ev[0], G->ev[1]); st->ms_prepare = a;
+    (void)hipEventElapsedTime(&a, G->ev[2], G->ev[3]); st->ms_tri = a;
+    (void)hipEventElapsedTime(&a, G->ev[3], G->ev[4]); st->ms_edge = a;
+    (void)hipEventElapsedTime(&a, G->ev[4], G->ev[5]); st->ms_c4 = a;
+    (void)hipEventElapsedTime(&a, G->ev[5], G->ev[6]); st->ms_finish = a;
+  }
+}
+
+// One batch per graph of the pool.  Host arrays when dev == false.
+void apply(gc_graph* G, const gc_batch_desc* b, bool dev, int64_t (*counts)[11], gc_batch_stats* stats) {
+  using clk = std::chrono::steady_clock;
+  const auto t0 = clk::now();
+  if (G->broken) raise(GC_ESTATE, "handle unusable after an earlier device failure");
+  HIPCHK(hipSetDevice(G->device));
+  hipStream_t s = G->stream;
+  const int k = G->k;
+  HostBatch H;
+  H.ins_seg.assign(k + 1, 0);
+  H.del_seg.assign(k + 1, 0);
+  for (int g = 0; g < k; ++g) {
+    if (b[g].n_ins < 0 || b[g].n_del < 0) raise(GC_EINVAL, "negative batch size");
+    if ((b[g].n_ins && (!b[g].ins_src || !b[g].ins_dst)) || (b[g].n_del && (!b[g].del_src || !b[g].del_dst)))
+      raise(GC_EINVAL, "null batch array");
+    if (!dev) {
+      const int64_t n = G->gn[g];
+      for (int64_t i = 0; i < b[g].n_ins; ++i)
+        if (b[g].ins_src[i] < 0 || b[g].ins_src[i] >= n || b[g].ins_dst[i] < 0 || b[g].ins_dst[i] >= n)
+          raise(GC_EINVAL, "insertion %lld of graph %d has a vertex id outside [0, %lld)", (long long)i, g,
+                (long long)n);
+      for (int64_t i = 0; i < b[g].n_del; ++i)
+        if (b[g].del_src[i] < 0 || b[g].del_src[i] >= n || b[g].del_dst[i] < 0 || b[g].del_dst[i] >= n)
+          raise(GC_EINVAL, "deletion %lld of graph %d has a vertex id outside [0, %lld)", (long long)i, g,
+                (long long)n);
+    }
+    H.ins_seg[g + 1] = H.ins_seg[g] + b[g].n_ins;
+    H.del_seg[g + 1] = H.del_seg[g] + b[g].n_del;
+  }
+  const int64_t ni = H.ins_seg[k], ndl = H.del_seg[k];
+  const int64_t total = ni + ndl;
+  const bool timed = stats != nullptr;
+
+  // upload: [ins_seg | del_seg | gbase | gn] int64, then the four id arrays
+  const size_t tab_words = (size_t)(4 * k + 2);
+  const size_t bytes = tab_words * 8 + (dev ? 0 : (size_t)(2 * total) * sizeof(int32_t));
+  char* pin = (char*)G->pinned(bytes + 64);
+  int64_t* tab = (int64_t*)pin;
+  std::memcpy(tab, H.ins_seg.data(), (k + 1) * 8);
+  std::memcpy(tab + k + 1, H.del_seg.data(), (k + 1) * 8);
+  std::memcpy(tab + 2 * k + 2, G->gbase.data(), k * 8);
+  std::memcpy(tab + 3 * k + 2, G->gn.data(), k * 8);
+  G->bin.ensure(bytes + 64);
+  BatchIn B;
+  B.n_ins = ni;
+  B.n_del = ndl;
+  B.k = k;
+  char* dbase = (char*)G->bin.p;
+  B.ins_seg = (const int64_t*)dbase;
+  B.del_seg = B.ins_seg + k + 1;
+  B.gbase = B.ins_seg + 2 * k + 2;
+  B.gn = B.ins_seg + 3 * k + 2;
+  if (dev) {
+    B.iu = b[0].ins_src; B.iv = b[0].ins_dst; B.du = b[0].del_src; B.dv = b[0].del_dst;
+  } else {
+    int32_t* ids = (int32_t*)(pin + tab_words * 8);
+    int32_t* d_ids = (int32_t*)(dbase + tab_words * 8);
+    int32_t *iu = ids, *iv = ids + ni, *du = ids + 2 * ni, *dv = ids + 2 * ni + ndl;
+    for (int g = 0; g < k; ++g) {
+      if (b[g].n_ins) {
+        std::memcpy(iu + H.ins_seg[g], b[g].ins_src, b[g].n_ins * 4);
+        std::memcpy(iv + H.ins_seg[g], b[g].ins_dst, b[g].n_ins * 4);
+      }
+      if (b[g].n_del) {
+        std::memcpy(du + H.del_seg[g], b[g].del_src, b[g].n_del * 4);
+        std::memcpy(dv + H.del_seg[g], b[g].del_dst, b[g].n_del * 4);
+      }
+    }
+    B.iu = d_ids; B.iv = d_ids + ni; B.du = d_ids + 2 * ni; B.dv = d_ids + 2 * ni + ndl;
+  }
+  HIPCHK(hipMemcpyAsync(G->bin.p, pin, bytes, hipMemcpyHostToDevice, s));
+
+  // scratch sizes
+  const int64_t max_touched = std::max<int64_t>(2 * total, 1);
+  const int64_t union_bound = G->entries + 2 * ni;
+  G->keys.ensure(std::max<int64_t>(total, 1) * 8);
+  G->keys_alt.ensure(std::max<int64_t>(total, 1) * 8);
+  G->dirA.ensure(std::max<int64_t>(2 * ni, 1) * 8);
+  G->dirA_alt.ensure(std::max<int64_t>(2 * ni, 1) * 8);
+  G->dirD.ensure(std::max<int64_t>(2 * ndl, 1) * 8);
+  G->dirD_alt.ensure(std::max<int64_t>(2 * ndl, 1) * 8);
+  G->touched.ensure(max_touched * 4);
+  G->dest.ensure(max_touched * 8);
+  G->newcap.ensure(max_touched * 4);
+  G->tlen.ensure(max_touched * 4);
+  G->tpre.ensure((max_touched + 1) * 8);
+  G->scratch.ensure(std::max<int64_t>(union_bound, 1) * 4);
+  G->sort_tmp.ensure(radix_sort_tmp_bytes(std::max<int64_t>(total, 2 * std::max(ni, ndl))) + 64);
+  G->scan_tmp.ensure(scan_tmp_bytes(std::max<int64_t>(max_touched, G->N) + 1) + 64);
+
+  // arena reserve: enough for every touched row to move
+  const int64_t need = (int64_t)((1.0 + G->opt.slack) * (double)union_bound) + 8 * max_touched + 1024;
+  if (G->arena_cap - G->arena_top < need) compact(G, need);
+
+  zero_small(G);
+  if (timed) HIPCHK(hipEventRecord(G->ev[0], s));
+  PoolDev P = G->pd();
+  unsigned long long* bst = G->bstats.as<unsigned long long>();
+  unsigned long long* ctr = G->ctr.as<unsigned long long>();
+  launch_ingest_keys(P, B, G->bits, G->keys.as<unsigned long long>(), bst, s);
+  unsigned long long* sk = radix_sort_u64(G->keys.as<unsigned long long>(), G->keys_alt.as<unsigned long long>(),
+                                          G->sort_tmp.p, total, nullptr, 2 * G->bits + 1, s);
+  launch_ingest_classify(P, sk, total, G->bits, G->dirA.as<unsigned long long>(), G->dirD.as<unsigned long long>(),
+                         ctr, bst, s);
+  if (dev) {
+    unsigned long long err = 0;
+    HIPCHK(hipMemcpyAsync(&err, bst + BS_ERR, 8, hipMemcpyDeviceToHost, s));
+    G->sync();
+    if (err) raise(GC_EINVAL, "batch has %llu vertex ids outside the graph", err);
+  }
+  unsigned long long* sA = radix_sort_u64(G->dirA.as<unsigned long long>(), G->dirA_alt.as<unsigned long long>(),
+                                          G->sort_tmp.p, 2 * ni, ctr + C_DIRA, 2 * G->bits, s);
+  unsigned long long* sD = radix_sort_u64(G->dirD.as<unsigned long long>(), G->dirD_alt.as<unsigned long long>(),
+                                          G->sort_tmp.p, 2 * ndl, ctr + C_DIRD, 2 * G->bits, s);
+  BatchWork W = make_work(G);
+  W.dirA = sA;
+  W.dirD = sD;
+  launch_mark_rows(sA, 2 * ni, ctr, C_DIRA, G->bits, W.a_beg, W.na, W.mark, W.touched, W.tix, s);
+  launch_mark_rows(sD, 2 * ndl, ctr, C_DIRD, G->bits, W.d_beg, W.nd, W.mark, W.touched, W.tix, s);
+  launch_merge(P, W, max_touched, 2 * ni, G->bits, G->opt.slack, bst, G->scan_tmp.p, s);
+  launch_flag_del(P, W, 2 * ndl, G->bits, bst, s);
+
+  std::vector<unsigned long long> hc;
+  const int radius = G->opt.radius == 0 ? -1 : G->opt.radius;
+  run_count(G, radius, G->state.as<long long>(), W, hc, union_bound, timed);
+  launch_purge(P, W, max_touched, G->bits, G->scan_tmp.p, s);
+  if (timed) HIPCHK(hipEventRecord(G->ev[6], s));
+
+  std::vector<unsigned long long> hb(BS_COUNT);
+  G->hstate.resize((size_t)k * ST_STRIDE);
+  HIPCHK(hipMemcpyAsync(hb.data(), bst, BS_COUNT * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&G->arena_top, G->top.p, 8, hipMemcpyDeviceToHost, s));
+  std::vector<long long> st((size_t)k * ST_STRIDE);
+  HIPCHK(hipMemcpyAsync(st.data(), G->state.p, st.size() * 8, hipMemcpyDeviceToHost, s));
+  G->sync();
+  if (hb[BS_ARENA_OVF] || hb[BS_ERR]) {
+    G->broken = true;
+    raise(GC_EDEVICE, "device-side inconsistency (arena overflow %llu, errors %llu)", hb[BS_ARENA_OVF], hb[BS_ERR]);
+  }
+  for (int g = 0; g < k; ++g) st[g * ST_STRIDE + ST_N] = G->gn[g];
+  G->hstate = st;
+  G->entries += 2 * ((int64_t)hb[BS_EFF_INS] - (int64_t)hb[BS_EFF_DEL]);
+  uint32_t ovf_all = 0;
+  for (int g = 0; g < k; ++g) {
+    i128 I[11];
+    finalize(&G->hstate[g * ST_STRIDE], G->gn[g], I);
+    uint32_t mk = 0;
+    int64_t tmp[11];
+    to_int64(I, counts ? counts[g] : tmp, &mk);
+    ovf_all |= mk;
+  }
+  const double ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  fill_stats(G, stats, hb, hc, ni, ndl, timed, ms, ovf_all);
+}
+
+template <class F>
+int guard(F f) {
+  try {
+    f();
+    return GC_OK;
+  } catch (const GcError& e) {
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return GC_ENOMEM;
+  } catch (...) {
+    g_err = "unexpected exception";
+    return GC_EDEVICE;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int gc_options_default(gc_options* opt) {
+  if (!opt) return GC_EINVAL;
+  opt->radius = 2;
+  opt->slack = 0.25f;
+  opt->device = 0;
+  opt->stream = nullptr;
+  return GC_OK;
+}
+
+int gc_pool_init(int32_t k, const int64_t* n, const int32_t* const* src, const int32_t* const* dst, const int64_t* m,
+                 const gc_options* opt, gc_graph** out, int64_t (*counts)[11]) {
+  return guard([&] {
+    if (!out) raise(GC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (k < 1 || !n || !m) raise(GC_EINVAL, "need k >= 1 graphs with sizes");
+    gc_graph* G = new gc_graph();
+    try {
+      setup_handle(G, opt);
+      build(G, k, n, src, dst, m);
+    } catch (...) {
+      delete G;
+      throw;
+    }
+    if (counts)
+      for (int g = 0; g < k; ++g) {
+        i128 I[11];
+        finalize(&G->hstate[g * ST_STRIDE], G->gn[g], I);
+        to_int64(I, counts[g], nullptr);
+      }
+    *out = G;
+  });
+}
+
+int gc_graph_init(int64_t n, const int32_t* src, const int32_t* dst, int64_t m, const gc_options* opt, gc_graph** out,
+                  int64_t counts[11]) {
+  const int32_t* s[1] = {src};
+  const int32_t* d[1] = {dst};
+  return gc_pool_init(1, &n, s, d, &m, opt, out, counts ? (int64_t(*)[11])counts : nullptr);
+}
+
+int gc_apply_batch(gc_graph* g, const int32_t* ins_src, const int32_t* ins_dst, int64_t n_ins, const int32_t* del_src,
+                   const int32_t* del_dst, int64_t n_del, int64_t counts[11], gc_batch_stats* stats) {
+  return guard([&] {
+    if (!g) raise(GC_EINVAL, "graph is NULL");
+    if (g->k != 1) raise(GC_EINVAL, "handle holds %d graphs: use gc_apply_batches", g->k);
+    gc_batch_desc b{ins_src, ins_dst, n_ins, del_src, del_dst, n_del};
+    apply(g, &b, false, counts ? (int64_t(*)[11])counts : nullptr, stats);
+  });
+}
+
+int gc_apply_batch_dev(gc_graph* g, const int32_t* ins_src, const int32_t* ins_dst, int64_t n_ins,
+                       const int32_t* del_src, const int32_t* del_dst, int64_t n_del, int64_t counts[11],
+                       gc_batch_stats* stats) {
+  return guard([&] {
+    if (!g) raise(GC_EINVAL, "graph is NULL");
+    if (g->k != 1) raise(GC_EINVAL, "handle holds %d graphs: use gc_apply_batches", g->k);
+    gc_batch_desc b{ins_src, ins_dst, n_ins, del_src, del_dst, n_del};
+    apply(g, &b, true, counts ? (int64_t(*)[11])counts : nullptr, stats);
+  });
+}
+
+int gc_apply_batches(gc_graph* pool, const gc_batch_desc* batch, int64_t (*counts)[11], gc_batch_stats* stats) {
+  return guard([&] {
+    if (!pool || !batch) raise(GC_EINVAL, "NULL argument");
+    apply(pool, batch, false, counts, stats);
+  });
+}
+
+int gc_get_counts(const gc_graph* g, int32_t graph, int64_t counts[11], uint32_t* overflow_mask) {
+  return guard([&] {
+    if (!g || !counts) raise(GC_EINVAL, "NULL argument");
+    if (graph < 0 || graph >= g->k) raise(GC_EINVAL, "graph index out of range");
+    i128 I[11];
+    finalize(&g->hstate[graph * ST_STRIDE], g->gn[graph], I);
+    to_int64(I, counts, overflow_mask);
+  });
+}
+
+int gc_get_counts_exact(const gc_graph* g, int32_t graph, int64_t hi[11], uint64_t lo[11]) {
+  return guard([&] {
+    if (!g || !hi || !lo) raise(GC_EINVAL, "NULL argument");
+    if (graph < 0 || graph >= g->k) raise(GC_EINVAL, "graph index out of range");
+    i128 I[11];
+    finalize(&g->hstate[graph * ST_STRIDE], g->gn[graph], I);
+    for (int c = 0; c < 11; ++c) { lo[c] = (uint64_t)I[c]; hi[c] = (int64_t)(I[c] >> 64); }
+  });
+}
+
+int gc_recount_exact(gc_graph* g, int32_t graph, int64_t hi[11], uint64_t lo[11]) {
+  return guard([&] {
+    if (!g || !hi || !lo) raise(GC_EINVAL, "NULL argument");
+    if (graph < 0 || graph >= g->k) raise(GC_EINVAL, "graph index out of range");
+    if (g->broken) raise(GC_ESTATE, "handle unusable after an earlier device failure");
+    HIPCHK(hipSetDevice(g->device));
+    hipStream_t s = g->stream;
+    PoolDev P = g->pd();
+    launch_all_flags(P, GC_F_NEW, GC_ID, s);
+    fill_u64((unsigned long long*)g->state_tmp.p, 0ull, (int64_t)g->k * ST_STRIDE, s);
+    zero_small(g);
+    BatchWork W = make_work(g);
+    std::vector<unsigned long long> hc;
+    run_count(g, -1, g->state_tmp.as<long long>(), W, hc, g->entries, false);
+    launch_all_flags(P, 0u, GC_ID, s);
+    std::vector<long long> st((size_t)g->k * ST_STRIDE);
+    HIPCHK(hipMemcpyAsync(st.data(), g->state_tmp.p, st.size() * 8, hipMemcpyDeviceToHost, s));
+    g->sync();
+    i128 I[11];
+    finalize(&st[graph * ST_STRIDE], g->gn[graph], I);
+    for (int c = 0; c < 11; ++c) { lo[c] = (uint64_t)I[c]; hi[c] = (int64_t)(I[c] >> 64); }
+  });
+}
+
+int gc_graph_info(const gc_graph* g, int32_t* num_graphs, int32_t graph, int64_t* n, int64_t* m) {
+  return guard([&] {
+    if (!g) raise(GC_EINVAL, "NULL argument");
+    if (num_graphs) *num_graphs = g->k;
+    if (graph < 0 || graph >= g->k) raise(GC_EINVAL, "graph index out of range");
+    if (n) *n = g->gn[graph];
+    if (m) *m = g->hstate[graph * ST_STRIDE + ST_M];
+  });
+}
+
+int gc_export_edges(gc_graph* g, int32_t graph, int32_t* src, int32_t* dst, int64_t capn, int64_t* m_out) {
+  return guard([&] {
+    if (!g || !m_out) raise(GC_EINVAL, "NULL argument");
+    if (graph < 0 || graph >= g->k) raise(GC_EINVAL, "graph index out of range");
+    HIPCHK(hipSetDevice(g->device));
+    const int64_t m = g->hstate[graph * ST_STRIDE + ST_M];
+    *m_out = m;
+    if (capn < m) raise(GC_EINVAL, "capacity %lld below the edge count %lld", (long long)capn, (long long)m);
+    if (m > 0 && (!src || !dst)) raise(GC_EINVAL, "NULL output arrays");
+    hipStream_t s = g->stream;
+    const int64_t N = g->N;
+    DevBuf cnt, pre, es, ed, gb;
+    cnt.ensure(N * 4);
+    pre.ensure((N + 1) * 8);
+    const int64_t total = g->entries / 2;
+    es.ensure(std::max<int64_t>(total, 1) * 4);
+    ed.ensure(std::max<int64_t>(total, 1) * 4);
+    gb.ensure(g->k * 8);
+    HIPCHK(hipMemcpyAsync(gb.p, g->gbase.data(), g->k * 8, hipMemcpyHostToDevice, s));
+    PoolDev P = g->pd();
+    launch_upper_count(P, cnt.as<int32_t>(), s);
+    g->scan_tmp.ensure(scan_tmp_bytes(N + 1) + 64);
+    exclusive_scan_i32_to_i64(cnt.as<int32_t>(), pre.as<int64_t>(), N, g->scan_tmp.p, s);
+    launch_export(P, g->int2ext.as<int32_t>(), gb.as<int64_t>(), pre.as<int64_t>(), es.as<int32_t>(),
+                  ed.as<int32_t>(), s);
+    int64_t range[2];
+    HIPCHK(hipMemcpyAsync(&range[0], pre.as<int64_t>() + g->gbase[graph], 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&range[1], pre.as<int64_t>() + g->gbase[graph] + g->gn[graph], 8, hipMemcpyDeviceToHost, s));
+    g->sync();
+    if (range[1] - range[0] != m) raise(GC_EDEVICE, "edge count mismatch (%lld vs %lld)",
+                                        (long long)(range[1] - range[0]), (long long)m);
+    if (m) {
+      HIPCHK(hipMemcpyAsync(src, es.as<int32_t>() + range[0], m * 4, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(dst, ed.as<int32_t>() + range[0], m * 4, hipMemcpyDeviceToHost, s));
+    }
+    g->sync();
+  });
+}
+
+int gc_graph_free(gc_graph* g) {
+  if (!g) return GC_OK;
+  (void)hipSetDevice(g->device);
+  delete g;
+  return GC_OK;
+}
+
+const char* gc_strerror(int code) {
+  switch (code) {
+    case GC_OK: return "ok";
+    case GC_EINVAL: return "invalid argument";
+    case GC_ENOMEM: return "out of memory";
+    case GC_EDEVICE: return "device error";
+    case GC_EBUSY: return "busy";
+    case GC_ESTATE: return "handle unusable";
+  }
+  return "unknown error";
+}
+
+const char* gc_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

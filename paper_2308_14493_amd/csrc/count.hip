@@ -1,0 +1,620 @@
+// Counting kernels: the local static counter applied to the region, fused
+// over the two versions (G_b before, G_a after the batch; Alg. 2 counts both
+// and adds C_a - C_b).  Every structure is enumerated once in the union view
+// and its presence in each version is read off the flags of its entries.
+//
+// Per-edge counting (the PGD approach of Sec. 3: iterate over edges, count
+// triangles, 4-cliques and 4-cycles, derive the rest by combinatorics):
+//   triangles  oriented by id: u < v < w found at u, with v in N+(u) and
+//              w in N+(u) & N+(v).  Each triangle adds 1 to t of its three
+//              edges (t_e = common neighbours of the endpoints of e).
+//   4-cliques  u < v < w < x, x in N+(u) & N+(v) & N+(w).
+//   4-cycles   counted once, at the largest vertex v, through the opposite
+//              vertex w < v: c(v,w) = #{u < v adjacent to both}, and
+//              sum_w C(c(v,w), 2).
+//   the non-induced counts follow:
+//     N_K13 = sum_v C(d,3)        N_P4 = sum_e (d_u-1)(d_v-1) - 3T
+//     N_paw = sum_tri (d_u + d_v + d_w - 6)   N_dia = sum_e C(t_e, 2)
+//     N_K4, N_C4 as enumerated.
+//
+// Tiers (work lists built by the per-vertex pass):
+//   tri  S: out-degree <= 64, one wave per vertex, bit matrices in LDS
+//   tri  L: larger out-degree, one workgroup per vertex, LDS hash
+//   c4   S / M: wedge bound <= 256 / <= 4096, LDS hash per wave / workgroup
+//   c4   L: one workgroup per vertex, dense counters in global memory
+#include "gc_kernels.h"
+
+namespace {
+
+__device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
+
+__device__ __forceinline__ uint32_t hash32(uint32_t x) { return x * 2654435761u; }
+
+__device__ __forceinline__ int32_t ld_relaxed(int32_t* p) { return __atomic_load_n(p, __ATOMIC_RELAXED); }
+
+// find key in an open-addressing table of size mask+1 (keys -1 = empty)
+__device__ __forceinline__ int lookup_slot(const int32_t* keys, const int16_t* vals, uint32_t mask, int shift,
+                                           uint32_t key) {
+  uint32_t h = hash32(key) >> shift;
+  while (true) {
+    int32_t k = keys[h];
+    if (k == (int32_t)key) return vals[h];
+    if (k == -1) return -1;
+    h = (h + 1) & mask;
+  }
+}
+
+// add `add` to the counter of key (insert on first use)
+template <class V>
+__device__ __forceinline__ void hash_add(int32_t* keys, V* vals, uint32_t mask, int shift, uint32_t key, V add) {
+  uint32_t h = hash32(key) >> shift;
+  while (true) {
+    int32_t k = ld_relaxed(&keys[h]);
+    if (k == (int32_t)key) { atomicAdd(&vals[h], add); return; }
+    if (k == -1) {
+      int32_t old = atomicCAS(&keys[h], -1, (int32_t)key);
+      if (old == -1 || old == (int32_t)key) { atomicAdd(&vals[h], add); return; }
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+__device__ __forceinline__ int log2i(uint32_t x) { return 31 - __clz(x); }
+
+// Segment search for wave-flattened loops: every lane holds one segment
+// with exclusive prefix `excl`; returns the lane whose segment holds idx
+// (largest lane with excl <= idx).  All 64 lanes must call it.
+__device__ __forceinline__ int seg_of(int32_t excl, int32_t idx) {
+  int lo = 0, hi = 64;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    int mid = (lo + hi) >> 1;
+    int32_t e = __shfl(excl, mid);
+    if (e <= idx) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ unsigned long long pack2(uint32_t b, uint32_t a) {
+  return (unsigned long long)b | ((unsigned long long)a << 32);
+}
+
+// flush lane-private sums of a wave whose lanes all work for graph g
+__device__ __forceinline__ void flush2(unsigned long long* sig, int g, int k, int64_t& b, int64_t& a) {
+  flush_sig(sig, g, 0, k, b);
+  flush_sig(sig, g, 1, k, a);
+  b = 0; a = 0;
+}
+
+// ------------------------------------------------------ triangles, tier S
+constexpr int TS_WAVES = 4;
+
+__global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
+  __shared__ int32_t hkey[TS_WAVES][128];
+  __shared__ int16_t hval[TS_WAVES][128];
+  __shared__ uint32_t fsl[TS_WAVES][64];
+  __shared__ unsigned long long EB[TS_WAVES][64], EA[TS_WAVES][64], TB[TS_WAVES][64], TA[TS_WAVES][64];
+  const int w = threadIdx.x >> 6, l = lane_id();
+  const RegionDev& R = A.R;
+  const int64_t n = (int64_t)A.c[C_LIST0 + L_TRI_S];
+  const int32_t* list = A.lists + L_TRI_S * A.list_stride;
+  int cur_g = -1;
+  int64_t tb_ = 0, ta_ = 0, pb_ = 0, pa_ = 0, kb_ = 0, ka_ = 0;
+  for (int64_t it = (int64_t)blockIdx.x * TS_WAVES + w; it < n; it += (int64_t)gridDim.x * TS_WAVES) {
+    const int32_t u = list[it];
+    const int g = A.gid[u];
+    if (g != cur_g) {
+      if (cur_g >= 0) { flush2(A.sig, cur_g, SG_T, tb_, ta_); flush2(A.sig, cur_g, SG_PAW, pb_, pa_); flush2(A.sig, cur_g, SG_K4, kb_, ka_); }
+      cur_g = g;
+    }
+    const int64_t ub = R.roff[u] + R.rlow[u];
+    const int32_t dp = (int32_t)(R.roff[u + 1] - ub);
+    uint32_t vi = 0, fi = 0;
+    if (l < dp) { const uint32_t x = R.rcol[ub + l]; vi = x & GC_ID; fi = x & GC_FLAGS; }
+    hkey[w][l] = -1; hkey[w][l + 64] = -1;
+    EB[w][l] = 0; EA[w][l] = 0; TB[w][l] = 0; TA[w][l] = 0;
+    fsl[w][l] = fi;
+    wave_sync();
+    if (l < dp) {
+      uint32_t h = hash32(vi) >> 25;
+      while (atomicCAS(&hkey[w][h], -1, (int32_t)vi) != -1) h = (h + 1) & 127u;
+      hval[w][h] = (int16_t)l;
+    }
+    wave_sync();
+    int64_t sb = 0;
+    int32_t sl = 0;
+    if (l < dp) { sb = R.roff[vi] + R.rlow[vi]; sl = (int32_t)(R.roff[vi + 1] - sb); }
+    const int32_t incl = wave_incl_scan32(sl);
+    const int32_t total = __shfl(incl, 63);
+    const int32_t excl = incl - sl;
+    for (int32_t base = 0; base < total; base += 64) {
+      const int32_t idx = base + l;
+      const int i = seg_of(excl, idx);
+      const int64_t sbi = __shfl(sb, i);
+      const int32_t exi = __shfl(excl, i);
+      if (idx < total) {
+        const int64_t pos = sbi + (idx - exi);
+        const uint32_t y = R.rcol[pos];
+        const int j = lookup_slot(hkey[w], hval[w], 127u, 25, y & GC_ID);
+        if (j >= 0) {
+          const uint32_t fy = y & GC_FLAGS;
+          const unsigned long long bj = 1ull << j, bi = 1ull << i;
+          if (!(fy & GC_F_NEW)) { atomicOr(&EB[w][i], bj); atomicOr(&TB[w][j], bi); }
+          if (!(fy & GC_F_DEL)) { atomicOr(&EA[w][i], bj); atomicOr(&TA[w][j], bi); }
+          const uint32_t ab = fsl[w][i] | fsl[w][j] | fy;
+          const uint32_t xb = !(ab & GC_F_NEW), xa = !(ab & GC_F_DEL);
+          if (xb | xa) atomicAdd(&R.t[pos], pack2(xb, xa));
+        }
+      }
+    }
+    wave_sync();
+    const uint64_t Pb = __ballot(l < dp && !(fi & GC_F_NEW));
+    const uint64_t Pa = __ballot(l < dp && !(fi & GC_F_DEL));
+    if (l < dp) {
+      const bool pb = (Pb >> l) & 1ull, pa = (Pa >> l) & 1ull;
+      const uint64_t rb = EB[w][l] & Pb, ra = EA[w][l] & Pa;
+      const uint64_t cb = TB[w][l] & Pb, ca = TA[w][l] & Pa;
+      const int32_t midb = pb ? __popcll(rb) : 0, mida = pa ? __popcll(ra) : 0;
+      const int32_t tub = pb ? __popcll(rb | cb) : 0, tua = pa ? __popcll(ra | ca) : 0;
+      int64_t k4b = 0, k4a = 0;
+      if (pb) for (uint64_t m = rb; m; m &= m - 1) k4b += __popcll(rb & EB[w][__builtin_ctzll(m)] & Pb);
+      if (pa) for (uint64_t m = ra; m; m &= m - 1) k4a += __popcll(ra & EA[w][__builtin_ctzll(m)] & Pa);
+      tb_ += midb; ta_ += mida;
+      pb_ += (int64_t)midb * (R.dB[u] - 6) + (int64_t)tub * R.dB[vi];
+      pa_ += (int64_t)mida * (R.dA[u] - 6) + (int64_t)tua * R.dA[vi];
+      kb_ += k4b; ka_ += k4a;
+      if (tub | tua) atomicAdd(&R.t[ub + l], pack2(tub, tua));
+    }
+    wave_sync();
+  }
+  if (cur_g >= 0) { flush2(A.sig, cur_g, SG_T, tb_, ta_); flush2(A.sig, cur_g, SG_PAW, pb_, pa_); flush2(A.sig, cur_g, SG_K4, kb_, ka_); }
+}
+
+// ------------------------------------------------------ triangles, tier L
+// One workgroup per vertex u; N+(u) in a hash; each wave takes a v in N+(u),
+// finds the triangle mates w in N+(v) & N+(u) (marks + list), then the
+// 4-cliques through (u, v, w) by probing N+(w) against the marks.
+constexpr int TL_MAX = 2048;   // out-degree handled from LDS
+constexpr int TL_WAVES = 4;
+
+struct TriL {
+  uint32_t* ids;      // [dp]
+  int32_t* hkey;      // [H]
+  int16_t* hval;      // [H]
+  uint32_t* tuc;      // [dp] packed 16-bit halves (b low, a high)
+  uint8_t* mark;      // [4][dp]
+  int16_t* lst;       // [4][dp]
+};
+
+__device__ void tri_large_vertex(const CountArgs& A, const TriL& S, int32_t u, int64_t ub, int32_t dp, int32_t dstride,
+                                 int64_t& tb_, int64_t& ta_, int64_t& pb_, int64_t& pa_, int64_t& kb_, int64_t& ka_) {
+  const RegionDev& R = A.R;
+  const int w = threadIdx.x >> 6, l = lane_id();
+  int H = 1;
+  while (H < 2 * dp) H <<= 1;
+  const uint32_t hmask = (uint32_t)H - 1u;
+  const int shift = 32 - log2i((uint32_t)H);
+  for (int32_t k = threadIdx.x; k < dp; k += blockDim.x) { S.ids[k] = R.rcol[ub + k]; S.tuc[k] = 0; }
+  for (int32_t k = threadIdx.x; k < H; k += blockDim.x) S.hkey[k] = -1;
+  for (int32_t k = threadIdx.x; k < TL_WAVES * dstride; k += blockDim.x) S.mark[k] = 0;
+  __syncthreads();
+  for (int32_t k = threadIdx.x; k < dp; k += blockDim.x) {
+    const uint32_t id = S.ids[k] & GC_ID;
+    uint32_t h = hash32(id) >> shift;
+    while (atomicCAS(&S.hkey[h], -1, (int32_t)id) != -1) h = (h + 1) & hmask;
+    S.hval[h] = (int16_t)k;
+  }
+  __syncthreads();
+  const int32_t dBu = R.dB[u], dAu = R.dA[u];
+  uint8_t* mark = S.mark + w * dstride;
+  int16_t* lst = S.lst + w * dstride;
+  for (int32_t i = w; i < dp; i += TL_WAVES) {
+    const uint32_t xi = S.ids[i];
+    const uint32_t v = xi & GC_ID, fi = xi & GC_FLAGS;
+    const int64_t sb = R.roff[v] + R.rlow[v];
+    const int32_t sl = (int32_t)(R.roff[v + 1] - sb);
+    const int32_t dBv = R.dB[v], dAv = R.dA[v];
+    uint32_t acc_i = 0;
+    int32_t nl = 0;
+    for (int32_t k0 = 0; k0 < sl; k0 += 64) {
+      const int32_t k = k0 + l;
+      int j = -1;
+      uint32_t y = 0;
+      if (k < sl) { y = R.rcol[sb + k]; j = lookup_slot(S.hkey, S.hval, hmask, shift, y & GC_ID); }
+      const uint64_t m = __ballot(j >= 0);
+      if (j >= 0) {
+        const uint32_t fy = y & GC_FLAGS;
+        mark[j] = (uint8_t)(1u + (fy >> 30));
+        lst[nl + __popcll(m & lanemask_lt())] = (int16_t)j;
+        const uint32_t ab = fi | (S.ids[j] & GC_FLAGS) | fy;
+        const uint32_t xb = !(ab & GC_F_NEW), xa = !(ab & GC_F_DEL);
+        if (xb | xa) {
+          atomicAdd(&R.t[sb + k], pack2(xb, xa));
+          atomicAdd(&S.tuc[j], xb | (xa << 16));
+          acc_i += xb | (xa << 16);
+          const uint32_t wv = y & GC_ID;
+          tb_ += xb; ta_ += xa;
+          if (xb) pb_ += (int64_t)dBu + dBv + R.dB[wv] - 6;
+          if (xa) pa_ += (int64_t)dAu + dAv + R.dA[wv] - 6;
+        }
+      }
+      nl += __popcll(m);
+    }
+    acc_i = (uint32_t)wave_sum32((int32_t)acc_i);
+    if (l == 0 && acc_i) atomicAdd(&S.tuc[i], acc_i);
+    wave_sync();
+    // 4-cliques through (u, v, w) with w a triangle mate: probe N+(w)
+    for (int32_t g0 = 0; g0 < nl; g0 += 64) {
+      const int32_t q = g0 + l;
+      int32_t jq = -1;
+      int64_t sb2 = 0;
+      int32_t sl2 = 0;
+      if (q < nl) {
+        jq = lst[q];
+        const uint32_t vj = S.ids[jq] & GC_ID;
+        sb2 = R.roff[vj] + R.rlow[vj];
+        sl2 = (int32_t)(R.roff[vj + 1] - sb2);
+      }
+      const int32_t incl = wave_incl_scan32(sl2);
+      const int32_t tot = __shfl(incl, 63);
+      const int32_t excl = incl - sl2;
+      for (int32_t base = 0; base < tot; base += 64) {
+        const int32_t idx = base + l;
+        const int s = seg_of(excl, idx);
+        const int64_t sbs = __shfl(sb2, s);
+        const int32_t exs = __shfl(excl, s);
+        const int32_t js = __shfl(jq, s);
+        if (idx < tot) {
+          const uint32_t z = R.rcol[sbs + (idx - exs)];
+          const int kk = lookup_slot(S.hkey, S.hval, hmask, shift, z & GC_ID);
+          if (kk >= 0 && mark[kk]) {
+            const uint32_t ab = fi | (S.ids[js] & GC_FLAGS) | (S.ids[kk] & GC_FLAGS) |
+                                ((uint32_t)(mark[js] - 1u) << 30) | ((uint32_t)(mark[kk] - 1u) << 30) |
+                                (z & GC_FLAGS);
+            kb_ += !(ab & GC_F_NEW);
+            ka_ += !(ab & GC_F_DEL);
+          }
+        }
+      }
+    }
+    wave_sync();
+    for (int32_t q = l; q < nl; q += 64) mark[lst[q]] = 0;
+    wave_sync();
+  }
+  __syncthreads();
+  for (int32_t k = threadIdx.x; k < dp; k += blockDim.x) {
+    const uint32_t c = S.tuc[k];
+    if (c) atomicAdd(&R.t[ub + k], pack2(c & 0xFFFFu, c >> 16));
+  }
+  __syncthreads();
+}
+
+template <bool GLOBAL>
+__global__ __launch_bounds__(256) void k_tri_large(CountArgs A) {
+  const RegionDev& R = A.R;
+  const int64_t n = (int64_t)A.c[C_LIST0 + L_TRI_L];
+  const int32_t* list = A.lists + L_TRI_L * A.list_stride;
+  int cur_g = -1;
+  int64_t tb_ = 0, ta_ = 0, pb_ = 0, pa_ = 0, kb_ = 0, ka_ = 0;
+  TriL S;
+  int32_t dstride;
+  if constexpr (GLOBAL) {
+    // slot layout: ids | tuc | hkey | hval | mark | lst, sized by tri_slot_words
+    const int64_t W = A.tri_slot_words;
+    uint32_t* base = A.tri_scratch + (int64_t)blockIdx.x * W;
+    const int32_t cap = (int32_t)(W / 16);  // out-degree capacity of a slot
+    dstride = cap;
+    S.ids = base;
+    S.tuc = base + cap;
+    S.hkey = (int32_t*)(base + 2 * cap);
+    S.hval = (int16_t*)(base + 2 * cap + 4 * cap);
+    S.mark = (uint8_t*)(base + 2 * cap + 4 * cap + 2 * cap);
+    S.lst = (int16_t*)(base + 2 * cap + 4 * cap + 2 * cap + cap);
+  } else {
+    __shared__ uint32_t ids[TL_MAX];
+    __shared__ uint32_t tuc[TL_MAX];
+    __shared__ int32_t hkey[2 * TL_MAX];
+    __shared__ int16_t hval[2 * TL_MAX];
+    __shared__ uint8_t mark[TL_WAVES * TL_MAX];
+    __shared__ int16_t lst[TL_WAVES * TL_MAX];
+    S.ids = ids; S.tuc = tuc; S.hkey = hkey; S.hval = hval; S.mark = mark; S.lst = lst;
+    dstride = TL_MAX;
+  }
+  for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+    const int32_t u = list[it];
+    const int64_t ub = R.roff[u] + R.rlow[u];
+    const int32_t dp = (int32_t)(R.roff[u + 1] - ub);
+    if (GLOBAL ? dp <= TL_MAX : dp > TL_MAX) continue;
+    const int g = A.gid[u];
+    if (g != cur_g) {
+      if (cur_g >= 0) { flush2(A.sig, cur_g, SG_T, tb_, ta_); flush2(A.sig, cur_g, SG_PAW, pb_, pa_); flush2(A.sig, cur_g, SG_K4, kb_, ka_); }
+      cur_g = g;
+    }
+    tri_large_vertex(A, S, u, ub, dp, dstride, tb_, ta_, pb_, pa_, kb_, ka_);
+  }
+  if (cur_g >= 0) { flush2(A.sig, cur_g, SG_T, tb_, ta_); flush2(A.sig, cur_g, SG_PAW, pb_, pa_); flush2(A.sig, cur_g, SG_K4, kb_, ka_); }
+}
+
+// ------------------------------------------------------------ edge pass
+// After all triangles: per upper entry u -> w present in version x,
+//   S2 += (d_x(u) - 1)(d_x(w) - 1),   DIA += C(t_x, 2).
+constexpr int EP_RUN = 16;
+
+__global__ __launch_bounds__(256) void k_edge_pass(CountArgs A) {
+  const RegionDev& R = A.R;
+  const int64_t E = (int64_t)A.c[C_ER];
+  int cur_g = -1;
+  int64_t s2b = 0, s2a = 0, db = 0, da = 0;
+  for (int64_t run = gtid(); run * EP_RUN < E; run += gstride()) {
+    const int64_t p0 = run * EP_RUN;
+    const int64_t p1 = p0 + EP_RUN < E ? p0 + EP_RUN : E;
+    int64_t u = upper_bound_i64(R.roff, A.N, p0);
+    int64_t nxt = R.roff[u + 1];
+    for (int64_t p = p0; p < p1; ++p) {
+      while (nxt <= p) { ++u; nxt = R.roff[u + 1]; }
+      const uint32_t x = R.rcol[p];
+      const uint32_t wv = x & GC_ID;
+      if (wv <= (uint32_t)u) continue;
+      const int g = A.gid[u];
+      if (g != cur_g) {
+        if (cur_g >= 0) {
+          atomicAdd(&A.sig[SIG_IDX(cur_g, 0, SG_S2)], (unsigned long long)s2b);
+          atomicAdd(&A.sig[SIG_IDX(cur_g, 1, SG_S2)], (unsigned long long)s2a);
+          atomicAdd(&A.sig[SIG_IDX(cur_g, 0, SG_DIA)], (unsigned long long)db);
+          atomicAdd(&A.sig[SIG_IDX(cur_g, 1, SG_DIA)], (unsigned long long)da);
+          s2b = s2a = db = da = 0;
+        }
+        cur_g = g;
+      }
+      const unsigned long long tt = R.t[p];
+      if (!(x & GC_F_NEW)) {
+        s2b += (int64_t)(R.dB[u] - 1) * (R.dB[wv] - 1);
+        db += c2((int64_t)(tt & 0xFFFFFFFFull));
+      }
+      if (!(x & GC_F_DEL)) {
+        s2a += (int64_t)(R.dA[u] - 1) * (R.dA[wv] - 1);
+        da += c2((int64_t)(tt >> 32));
+      }
+    }
+  }
+  // wave-uniform graph: one atomic per wave, else per lane
+  const int g0 = __shfl(cur_g, 0);
+  const bool uniform = __ballot(cur_g == g0 || cur_g < 0) == ~0ull && g0 >= 0;
+  if (uniform) {
+    flush_sig(A.sig, g0, 0, SG_S2, s2b); flush_sig(A.sig, g0, 1, SG_S2, s2a);
+    flush_sig(A.sig, g0, 0, SG_DIA, db); flush_sig(A.sig, g0, 1, SG_DIA, da);
+  } else if (cur_g >= 0) {
+    atomicAdd(&A.sig[SIG_IDX(cur_g, 0, SG_S2)], (unsigned long long)s2b);
+    atomicAdd(&A.sig[SIG_IDX(cur_g, 1, SG_S2)], (unsigned long long)s2a);
+    atomicAdd(&A.sig[SIG_IDX(cur_g, 0, SG_DIA)], (unsigned long long)db);
+    atomicAdd(&A.sig[SIG_IDX(cur_g, 1, SG_DIA)], (unsigned long long)da);
+  }
+}
+
+// ------------------------------------------------------------ 4-cycles
+// Segment of the wedges through u for apex v: entries of row u below v.
+__device__ __forceinline__ void c4_segment(const RegionDev& R, uint32_t v, uint32_t u, int64_t& sb, int32_t& sl) {
+  sb = R.roff[u];
+  const int32_t L = (int32_t)(R.roff[u + 1] - sb);
+  sl = lower_bound_id(R.rcol + sb, L, v);
+}
+
+// Wave-flattened walk over the wedges (v, u, w) for the lower neighbours
+// u in positions [g0, g0 + 64) of row v; calls f(w, add_b, add_a).
+template <class F>
+__device__ __forceinline__ void c4_group(const RegionDev& R, uint32_t v, int64_t rb, int32_t nlow, int32_t g0, F f) {
+  const int l = lane_id();
+  const int32_t q = g0 + l;
+  int64_t sb = 0;
+  int32_t sl = 0;
+  uint32_t fvu = 0;
+  if (q < nlow) {
+    const uint32_t x = R.rcol[rb + q];
+    fvu = x & GC_FLAGS;
+    c4_segment(R, v, x & GC_ID, sb, sl);
+  }
+  const int32_t incl = wave_incl_scan32(sl);
+  const int32_t tot = __shfl(incl, 63);
+  const int32_t excl = incl - sl;
+  for (int32_t base = 0; base < tot; base += 64) {
+    const int32_t idx = base + l;
+    const int s = seg_of(excl, idx);
+    const int64_t sbs = __shfl(sb, s);
+    const int32_t exs = __shfl(excl, s);
+    const uint32_t fs = __shfl(fvu, s);
+    if (idx < tot) {
+      const uint32_t y = R.rcol[sbs + (idx - exs)];
+      const uint32_t ab = fs | (y & GC_FLAGS);
+      const uint32_t xb = !(ab & GC_F_NEW), xa = !(ab & GC_F_DEL);
+      if (xb | xa) f(y & GC_ID, xb, xa);
+    }
+  }
+}
+
+constexpr int C4S_SLOTS = 512;
+constexpr int C4S_WAVES = 4;
+
+__global__ __launch_bounds__(256) void k_c4_small(CountArgs A) {
+  __shared__ int32_t hkey[C4S_WAVES][C4S_SLOTS];
+  __shared__ uint32_t hcnt[C4S_WAVES][C4S_SLOTS];
+  const int w = threadIdx.x >> 6, l = lane_id();
+  const RegionDev& R = A.R;
+  const int64_t n = (int64_t)A.c[C_LIST0 + L_C4_S];
+  const int32_t* list = A.lists + L_C4_S * A.list_stride;
+  int cur_g = -1;
+  int64_t cb_ = 0, ca_ = 0;
+  for (int s = l; s < C4S_SLOTS; s += 64) { hkey[w][s] = -1; hcnt[w][s] = 0; }
+  wave_sync();
+  for (int64_t it = (int64_t)blockIdx.x * C4S_WAVES + w; it < n; it += (int64_t)gridDim.x * C4S_WAVES) {
+    const int32_t v = list[it];
+    const int g = A.gid[v];
+    if (g != cur_g) { if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_); cur_g = g; }
+    const int64_t rb = R.roff[v];
+    const int32_t nlow = R.rlow[v];
+    int32_t* hk = hkey[w];
+    uint32_t* hc = hcnt[w];
+    for (int32_t g0 = 0; g0 < nlow; g0 += 64)
+      c4_group(R, (uint32_t)v, rb, nlow, g0, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
+        hash_add<uint32_t>(hk, hc, C4S_SLOTS - 1, 23, wid, xb | (xa << 16));
+      });
+    wave_sync();
+    for (int s = l; s < C4S_SLOTS; s += 64) {
+      if (hk[s] != -1) {
+        const uint32_t c = hc[s];
+        cb_ += c2(c & 0xFFFFu);
+        ca_ += c2(c >> 16);
+        hk[s] = -1; hc[s] = 0;
+      }
+    }
+    wave_sync();
+  }
+  if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_);
+}
+
+constexpr int C4M_SLOTS = 8192;
+
+__global__ __launch_bounds__(256) void k_c4_mid(CountArgs A) {
+  __shared__ int32_t hkey[C4M_SLOTS];
+  __shared__ uint32_t hcnt[C4M_SLOTS];
+  const int w = threadIdx.x >> 6;
+  const RegionDev& R = A.R;
+  const int64_t n = (int64_t)A.c[C_LIST0 + L_C4_M];
+  const int32_t* list = A.lists + L_C4_M * A.list_stride;
+  int cur_g = -1;
+  int64_t cb_ = 0, ca_ = 0;
+  for (int s = threadIdx.x; s < C4M_SLOTS; s += blockDim.x) { hkey[s] = -1; hcnt[s] = 0; }
+  __syncthreads();
+  for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+    const int32_t v = list[it];
+    const int g = A.gid[v];
+    if (g != cur_g) { if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_); cur_g = g; }
+    const int64_t rb = R.roff[v];
+    const int32_t nlow = R.rlow[v];
+    for (int32_t g0 = w * 64; g0 < nlow; g0 += 64 * 4)
+      c4_group(R, (uint32_t)v, rb, nlow, g0, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
+        hash_add<uint32_t>(hkey, hcnt, C4M_SLOTS - 1, 19, wid, xb | (xa << 16));
+      });
+    __syncthreads();
+    for (int s = threadIdx.x; s < C4M_SLOTS; s += blockDim.x) {
+      if (hkey[s] != -1) {
+        const uint32_t c = hcnt[s];
+        cb_ += c2(c & 0xFFFFu);
+        ca_ += c2(c >> 16);
+        hkey[s] = -1; hcnt[s] = 0;
+      }
+    }
+    __syncthreads();
+  }
+  if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_);
+}
+
+__global__ __launch_bounds__(256) void k_c4_large(CountArgs A, unsigned long long* qhead) {
+  __shared__ int64_t s_item;
+  __shared__ int32_t s_nt;
+  const int w = threadIdx.x >> 6;
+  const RegionDev& R = A.R;
+  const int64_t n = (int64_t)A.c[C_LIST0 + L_C4_L];
+  const int32_t* list = A.lists + L_C4_L * A.list_stride;
+  unsigned long long* cnt = A.c4_dense + (int64_t)blockIdx.x * A.N;
+  int32_t* touch = A.c4_touch + (int64_t)blockIdx.x * A.N;
+  int cur_g = -1;
+  int64_t cb_ = 0, ca_ = 0;
+  while (true) {
+    if (threadIdx.x == 0) { s_item = (int64_t)atomicAdd(qhead, 1ull); s_nt = 0; }
+    __syncthreads();
+    const int64_t item = s_item;
+    if (item >= n) break;
+    const int32_t v = list[item];
+    const int g = A.gid[v];
+    if (g != cur_g) { if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_); cur_g = g; }
+    const int64_t rb = R.roff[v];
+    const int32_t nlow = R.rlow[v];
+    for (int32_t g0 = w * 64; g0 < nlow; g0 += 64 * 4)
+      c4_group(R, (uint32_t)v, rb, nlow, g0, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
+        const unsigned long long old = atomicAdd(&cnt[wid], pack2(xb, xa));
+        if (old == 0ull) touch[atomicAdd(&s_nt, 1)] = (int32_t)wid;
+      });
+    __syncthreads();
+    const int32_t nt = s_nt;
+    for (int32_t k = threadIdx.x; k < nt; k += blockDim.x) {
+      const int32_t wid = touch[k];
+      const unsigned long long c = cnt[wid];
+      cnt[wid] = 0ull;
+      cb_ += c2((int64_t)(c & 0xFFFFFFFFull));
+      ca_ += c2((int64_t)(c >> 32));
+    }
+    __syncthreads();
+  }
+  if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_);
+}
+
+// --------------------------------------------------------------- combine
+// C' = C_a - C_b on the six connected classes (Alg. 2), through the
+// non-induced counts of each version and the triangular relation between
+// non-induced and induced counts (copies of pattern X inside class Y).
+__global__ void k_combine(const unsigned long long* sig, long long* state, int32_t k) {
+  const int64_t g = gtid();
+  if (g >= k) return;
+  int64_t N[2][6], T[2], W[2], D1[2];
+  for (int x = 0; x < 2; ++x) {
+    const unsigned long long* s = sig + SIG_IDX(g, x, 0);
+    const int64_t t = (int64_t)s[SG_T];
+    N[x][0] = (int64_t)s[SG_S2] - 3 * t;      // 3-paths
+    N[x][1] = (int64_t)s[SG_S1];              // 3-stars
+    N[x][2] = (int64_t)s[SG_C4];              // 4-cycles
+    N[x][3] = (int64_t)s[SG_PAW];             // paws
+    N[x][4] = (int64_t)s[SG_DIA];             // diamonds
+    N[x][5] = (int64_t)s[SG_K4];              // 4-cliques
+    T[x] = t; W[x] = (int64_t)s[SG_W]; D1[x] = (int64_t)s[SG_D1];
+  }
+  int64_t d[6];
+  for (int c = 0; c < 6; ++c) d[c] = N[1][c] - N[0][c];
+  int64_t I[6];
+  I[5] = d[5];
+  I[4] = d[4] - 6 * I[5];
+  I[3] = d[3] - 4 * I[4] - 12 * I[5];
+  I[2] = d[2] - I[4] - 3 * I[5];
+  I[0] = d[0] - 2 * I[3] - 4 * I[2] - 6 * I[4] - 12 * I[5];
+  I[1] = d[1] - I[3] - 2 * I[4] - 4 * I[5];
+  long long* st = state + g * ST_STRIDE;
+  for (int c = 0; c < 6; ++c) st[ST_F0 + c] += I[c];
+  st[ST_T] += T[1] - T[0];
+  st[ST_W] += W[1] - W[0];
+  st[ST_M] += (D1[1] - D1[0]) / 2;
+}
+
+inline unsigned cap_grid(int64_t want, unsigned cap) {
+  if (want < 1) want = 1;
+  return (unsigned)(want > cap ? cap : want);
+}
+
+}  // namespace
+
+void launch_count(const CountArgs& A, const unsigned long long* hc, hipStream_t s, hipEvent_t* ev) {
+  const int64_t E = (int64_t)hc[C_ER];
+  if (ev) (void)hipEventRecord(ev[0], s);
+  fill_u64(A.R.t, 0ull, E, s);
+  const int64_t nts = (int64_t)hc[C_LIST0 + L_TRI_S], ntl = (int64_t)hc[C_LIST0 + L_TRI_L];
+  if (nts) hipLaunchKernelGGL(k_tri_small, dim3(cap_grid((nts + 3) / 4, 8192)), dim3(256), 0, s, A);
+  if (ntl) {
+    hipLaunchKernelGGL(k_tri_large<false>, dim3(cap_grid(ntl, 2048)), dim3(256), 0, s, A);
+    if ((int64_t)hc[C_MAXDP] > TL_MAX)
+      hipLaunchKernelGGL(k_tri_large<true>, dim3(cap_grid(ntl, (unsigned)A.slots)), dim3(256), 0, s, A);
+  }
+  if (ev) (void)hipEventRecord(ev[1], s);
+  if (E) hipLaunchKernelGGL(k_edge_pass, dim3(cap_grid((E / EP_RUN + 255) / 256, 8192)), dim3(256), 0, s, A);
+  if (ev) (void)hipEventRecord(ev[2], s);
+  const int64_t ncs = (int64_t)hc[C_LIST0 + L_C4_S], ncm = (int64_t)hc[C_LIST0 + L_C4_M],
+                ncl = (int64_t)hc[C_LIST0 + L_C4_L];
+  if (ncs) hipLaunchKernelGGL(k_c4_small, dim3(cap_grid((ncs + 3) / 4, 8192)), dim3(256), 0, s, A);
+  if (ncm) hipLaunchKernelGGL(k_c4_mid, dim3(cap_grid(ncm, 4096)), dim3(256), 0, s, A);
+  if (ncl)
+    hipLaunchKernelGGL(k_c4_large, dim3(cap_grid(ncl, (unsigned)A.slots)), dim3(256), 0, s, A,
+                       (unsigned long long*)(A.c + C_QHEAD));
+  if (ev) (void)hipEventRecord(ev[3], s);
+}
+
+void launch_combine(const unsigned long long* sig, long long* state, int32_t k, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine, dim3((k + 63) / 64), dim3(64), 0, s, sig, state, k);
+}

@@ -1,0 +1,159 @@
+// Internal declarations of the graphlet-4 library (not part of the C ABI).
+//
+// Data model.  A pool holds one or more graphs in one vertex id space.  Graph
+// g owns internal ids [base_g, base_g + n_g); inside a graph, internal ids are
+// the vertices sorted by (degree at build time, external id), so "id order"
+// is a degree order and every row of the adjacency is sorted ascending by id.
+// Any fixed total order makes the oriented enumerations below exact; the
+// degree order only bounds their cost.
+//
+// Rows live in an arena of uint32 entries with per-row slack:
+//   off[v] (int64), len[v] (int32), cap[v] (int32);  entry = id | flags
+// During a batch the arena holds the union view of the graph before (version
+// b) and after (version a) the batch; two flag bits mark the entries that
+// exist in one version only:
+//   F_NEW  (bit 30): inserted by the batch, absent from version b
+//   F_DEL  (bit 31): deleted by the batch, absent from version a
+// A structure (edge, wedge, triangle, 4-clique) exists in version x iff none
+// of its entries carries x's absence bit, i.e. the OR of its entries' flags
+// decides both versions at once.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define GC_F_NEW 0x40000000u
+#define GC_F_DEL 0x80000000u
+#define GC_FLAGS 0xC0000000u
+#define GC_ID    0x3FFFFFFFu
+#define GC_MAX_VERTICES (1 << 30)
+
+// Sigma terms accumulated per graph and version (u64, two's complement):
+enum {
+  SG_S1 = 0,   // sum_v C(d,3)                      -> non-induced 3-stars
+  SG_S2 = 1,   // sum_e (d_u - 1)(d_v - 1)          -> 3-paths + 3 T
+  SG_T = 2,    // triangles
+  SG_DIA = 3,  // sum_e C(t_e, 2)                   -> non-induced diamonds
+  SG_PAW = 4,  // sum_tri (d_u + d_v + d_w - 6)     -> non-induced paws
+  SG_K4 = 5,   // 4-cliques
+  SG_C4 = 6,   // 4-cycles
+  SG_W = 7,    // sum_v C(d,2)
+  SG_D1 = 8,   // sum_v d  (twice the edge count)
+  SG_N = 9
+};
+// per graph: sig[g][version][term], version 0 = b (before), 1 = a (after)
+#define SIG_IDX(g, x, k) (((int64_t)(g) * 2 + (x)) * SG_N + (k))
+
+// Device state per graph (int64): F_conn[6], T, W, m, n
+enum { ST_F0 = 0, ST_T = 6, ST_W = 7, ST_M = 8, ST_N = 9, ST_STRIDE = 16 };
+
+// Per-batch statistics written by kernels (u64 counters on the device).
+enum {
+  BS_LOOPS = 0, BS_DUPS, BS_CANCEL, BS_INS_EXIST, BS_DEL_MISS, BS_EFF_INS, BS_EFF_DEL,
+  BS_TOUCHED, BS_REGION_V, BS_REGION_E, BS_ERR, BS_ARENA_OVF, BS_MAXDPLUS, BS_TRI_S,
+  BS_TRI_L, BS_C4_S, BS_C4_M, BS_C4_L, BS_F1, BS_NR, BS_WEDGES, BS_TRIPROBE, BS_COUNT
+};
+
+struct PoolDev {
+  int64_t N;           // vertices in the pool
+  int64_t* off;        // [N]
+  int32_t* len;        // [N]
+  int32_t* cap;        // [N]
+  uint32_t* col;       // [arena_cap]
+  int64_t arena_cap;
+  unsigned long long* arena_top;  // bump pointer (device scalar)
+  int32_t* gid;        // [N] graph of each internal vertex
+  int32_t* ext2int;    // [N] pool-global external id -> internal id
+};
+
+// Region-restricted union view in compact CSR form.
+struct RegionDev {
+  int64_t* roff;       // [N + 1]
+  uint32_t* rcol;      // [E_R]
+  int32_t* rlow;       // [N] entries with id < v (N-(v) is the row prefix)
+  int32_t* dB;         // [N] degree in version b inside the region
+  int32_t* dA;         // [N] degree in version a inside the region
+  unsigned long long* t;  // [E_R] per upper entry: t_b | t_a << 32
+};
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ int32_t wave_sum32(int32_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ int32_t wave_incl_scan32(int32_t v) {
+  const int l = lane_id();
+  for (int o = 1; o < 64; o <<= 1) {
+    int32_t t = __shfl_up(v, o);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+__device__ __forceinline__ int64_t wave_incl_scan64(int64_t v) {
+  const int l = lane_id();
+  for (int o = 1; o < 64; o <<= 1) {
+    int64_t t = __shfl_up(v, o);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+__device__ __forceinline__ int32_t wave_max32(int32_t v) {
+  for (int o = 32; o > 0; o >>= 1) { int32_t t = __shfl_xor(v, o); v = t > v ? t : v; }
+  return v;
+}
+
+__host__ __device__ __forceinline__ int64_t c2(int64_t x) { return x * (x - 1) / 2; }
+__host__ __device__ __forceinline__ int64_t c3(int64_t x) { return x * (x - 1) * (x - 2) / 6; }
+
+// First index in sorted row[0..n) whose id is >= key (flags ignored).
+__device__ __forceinline__ int32_t lower_bound_id(const uint32_t* row, int32_t n, uint32_t key) {
+  int32_t lo = 0, hi = n;
+  while (lo < hi) {
+    int32_t mid = (lo + hi) >> 1;
+    if ((row[mid] & GC_ID) < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Largest i in [0, n) with pre[i] <= x (pre ascending, pre[0] <= x).
+__device__ __forceinline__ int64_t upper_bound_i64(const int64_t* pre, int64_t n, int64_t x) {
+  int64_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) >> 1;
+    if (pre[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Flush per-lane partial sums for graph g into sig (one atomic per wave).
+__device__ __forceinline__ void flush_sig(unsigned long long* sig, int g, int x, int k, int64_t v) {
+  v = wave_sum64(v);
+  if (lane_id() == 0 && v != 0) atomicAdd(&sig[SIG_IDX(g, x, k)], (unsigned long long)v);
+}
+
+// ------------------------------------------------------------ launchers
+// sort.hip / scan utilities
+size_t radix_sort_tmp_bytes(int64_t max_count);
+// Sorts keys[0..count) ascending on bits [0, bits); count may live on the
+// device (d_count != nullptr, max_count is then an upper bound).  Returns the
+// buffer that holds the result (keys or alt).
+unsigned long long* radix_sort_u64(unsigned long long* keys, unsigned long long* alt,
+                                   void* tmp, int64_t max_count, const unsigned long long* d_count,
+                                   int bits, hipStream_t s);
+size_t scan_tmp_bytes(int64_t n);
+// out[i] = sum_{j<i} in[j] for i in [0, n]; out has n + 1 entries.
+void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t s);
+void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t s);
+
+// fill helpers (kernels, capturable)
+void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+void fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);

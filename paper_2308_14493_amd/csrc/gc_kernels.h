@@ -1,0 +1,98 @@
+// Launcher declarations shared by the kernel files and the host code.
+#pragma once
+#include "gc_internal.h"
+
+// device counters (u64) of one batch
+enum {
+  C_DIRA = 0,     // directed insert entries (2 per effective insertion)
+  C_DIRD,         // directed delete entries
+  C_TOUCH,        // rows touched by the batch
+  C_RLIST,        // region vertices
+  C_LVL0,         // C_LVL0 + k: end of level-k vertices in the region list (k = 0..4)
+  C_ER = C_LVL0 + 6,  // region entries
+  C_MAXDP,        // max oriented out-degree
+  C_MAXW,         // max wedge bound
+  C_LIST0,        // C_LIST0 + L_*: work list sizes
+  C_QHEAD = C_LIST0 + 8,  // dynamic queue head of the large 4-cycle tier
+  C_COUNT = C_QHEAD + 2
+};
+enum { L_TRI_S = 0, L_TRI_L, L_C4_S, L_C4_M, L_C4_L, L_NUM };
+
+struct BatchIn {
+  const int32_t* iu; const int32_t* iv; const int32_t* du; const int32_t* dv;
+  int64_t n_ins, n_del;
+  const int64_t* ins_seg;  // [k+1] insertion segment per graph
+  const int64_t* del_seg;  // [k+1]
+  const int64_t* gbase;    // [k] first vertex of each graph
+  const int64_t* gn;       // [k] vertex count of each graph
+  int32_t k;
+};
+
+struct BatchWork {
+  unsigned long long* c;       // counters
+  unsigned long long* dirA;    // sorted directed insert entries (row << bits | col)
+  unsigned long long* dirD;
+  int32_t* a_beg; int32_t* na; int32_t* d_beg; int32_t* nd; int32_t* mark; int32_t* tix;  // [N]
+  int32_t* touched;            // [max_touched]
+  int64_t* dest; int32_t* newcap; int32_t* tlen; int64_t* tpre;  // [max_touched (+1)]
+  uint32_t* scratch;           // copy of the touched rows
+};
+
+// graph.hip
+void launch_ingest_keys(const PoolDev& P, const BatchIn& B, int bits, unsigned long long* keys,
+                        unsigned long long* bstats, hipStream_t s);
+void launch_ingest_classify(const PoolDev& P, const unsigned long long* keys, int64_t total, int bits,
+                            unsigned long long* dirA, unsigned long long* dirD, unsigned long long* c,
+                            unsigned long long* bstats, hipStream_t s);
+void launch_mark_rows(const unsigned long long* dir, int64_t max_n, unsigned long long* c, int which, int bits,
+                      int32_t* beg, int32_t* cnt, int32_t* mark, int32_t* touched, int32_t* tix, hipStream_t s);
+void launch_merge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int64_t max_dirA, int bits, float slack,
+                  unsigned long long* bstats, void* scan_tmp, hipStream_t s);
+void launch_flag_del(const PoolDev& P, const BatchWork& W, int64_t max_dirD, int bits, unsigned long long* bstats,
+                     hipStream_t s);
+void launch_purge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int bits, void* scan_tmp, hipStream_t s);
+void launch_region(const PoolDev& P, const BatchWork& W, int radius, int32_t* level, int32_t* rlist, int32_t* rlen,
+                   hipStream_t s);
+void launch_region_fill(const PoolDev& P, const RegionDev& R, const BatchWork& W, int radius, const int32_t* level,
+                        const int32_t* rlist, const int32_t* rlen, void* scan_tmp, hipStream_t s);
+void launch_degrees(const RegionDev& R, const int32_t* gid, const int32_t* rlist, unsigned long long* c,
+                    unsigned long long* sig, int32_t* lists, int64_t list_stride, int32_t tri_small, int32_t c4_small,
+                    int32_t c4_mid, unsigned long long* bstats, hipStream_t s);
+void launch_init_keys(const int32_t* src, const int32_t* dst, int64_t m, const int64_t* seg, const int64_t* gbase,
+                      int32_t k, int bits, unsigned long long* keys, hipStream_t s);
+void launch_init_unique(const unsigned long long* keys, int64_t m, int bits, unsigned long long* uniq,
+                        unsigned long long* c, int32_t* deg, hipStream_t s);
+void launch_rank(const int32_t* deg, const int32_t* gid, const int64_t* gbase, int64_t N, int lbits, int total_bits,
+                 unsigned long long* keys, unsigned long long* alt, void* sort_tmp, int32_t* ext2int, int32_t* int2ext,
+                 hipStream_t s);
+void launch_init_dir(const unsigned long long* uniq, int64_t max_m, unsigned long long* c, int bits,
+                     const int32_t* ext2int, unsigned long long* dir, int32_t* len, hipStream_t s);
+void launch_init_csr(const PoolDev& P, const unsigned long long* dir, int64_t max_dir, unsigned long long* c, int bits,
+                     int64_t* rstart, float slack, void* scan_tmp, uint32_t flag, hipStream_t s);
+void launch_caps(const PoolDev& P, float slack, hipStream_t s);  // P.cap <- len + slack
+void launch_all_flags(const PoolDev& P, uint32_t set, uint32_t keep, hipStream_t s);
+void launch_compact(const PoolDev& P, int64_t* noff, uint32_t* ncol, hipStream_t s);
+void launch_upper_count(const PoolDev& P, int32_t* cnt, hipStream_t s);
+void launch_export(const PoolDev& P, const int32_t* int2ext, const int64_t* gbase, const int64_t* pre, int32_t* src,
+                   int32_t* dst, hipStream_t s);
+
+// count.hip
+struct CountArgs {
+  RegionDev R;
+  const int32_t* gid;
+  const int32_t* lists;     // L_NUM lists of list_stride entries
+  int64_t list_stride;
+  const unsigned long long* c;
+  unsigned long long* sig;
+  unsigned long long* bstats;
+  // per-slot scratch of the large tiers
+  unsigned long long* c4_dense;   // [slots][N]
+  int32_t* c4_touch;              // [slots][N]
+  int64_t N;
+  int32_t slots;
+  uint32_t* tri_scratch;          // [slots][tri_slot_words] for out-degrees above the LDS tier
+  int64_t tri_slot_words;
+};
+void launch_count(const CountArgs& A, const unsigned long long* host_counts, hipStream_t s,
+                  hipEvent_t* ev /* nullable: 4 events around tri, edge, c4 */);
+void launch_combine(const unsigned long long* sig, long long* state, int32_t k, hipStream_t s);

@@ -1,0 +1,750 @@
+// Graph-side kernels: batch ingest, merge of a batch into the slack CSR
+// (tombstone phase before counting, purge phase after), region-of-change
+// marking, the region CSR and its per-vertex pass, and the initial build.
+//
+// Batch semantics (the stream model of Sec. 3 and the batch protocol of
+// Sec. 5): pairs are unordered, self loops are not edges, repeats collapse,
+// a pair both inserted and deleted by one batch is dropped, and only the
+// effective part A' = A - E, D' = D & E changes the graph.
+#include "gc_kernels.h"
+
+namespace {
+
+constexpr int TPB = 256;
+
+__device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
+__device__ __forceinline__ int64_t gwave() { return gtid() >> 6; }
+__device__ __forceinline__ int64_t gwaves() { return gstride() >> 6; }
+
+__device__ __forceinline__ int64_t ctr(const unsigned long long* c, int k) { return (int64_t)c[k]; }
+
+// Is (a, b) an edge of the pre-batch graph?  Binary search in the shorter row.
+__device__ __forceinline__ bool edge_exists(const PoolDev& P, uint32_t a, uint32_t b) {
+  if (P.len[b] < P.len[a]) { uint32_t t = a; a = b; b = t; }
+  const uint32_t* row = P.col + P.off[a];
+  int32_t n = P.len[a];
+  int32_t p = lower_bound_id(row, n, b);
+  return p < n && (row[p] & GC_ID) == b;
+}
+
+// ------------------------------------------------------------- ingest
+__global__ void k_ingest_keys(PoolDev P, BatchIn B, int bits, unsigned long long* __restrict__ keys,
+                              unsigned long long* __restrict__ bstats) {
+  const int64_t total = B.n_ins + B.n_del;
+  const uint64_t idmask = (1ull << bits) - 1ull;
+  for (int64_t i = gtid(); i < total; i += gstride()) {
+    const bool del = i >= B.n_ins;
+    const int64_t j = del ? i - B.n_ins : i;
+    int32_t u = del ? B.du[j] : B.iu[j];
+    int32_t v = del ? B.dv[j] : B.iv[j];
+    // graph segment of this entry
+    const int64_t* seg = del ? B.del_seg : B.ins_seg;
+    int lo = 0, hi = B.k;
+    while (hi - lo > 1) { int mid = (lo + hi) >> 1; if (seg[mid] <= j) lo = mid; else hi = mid; }
+    const int64_t base = B.gbase[lo], n = B.gn[lo];
+    if (u < 0 || v < 0 || u >= n || v >= n) {
+      atomicAdd(&bstats[BS_ERR], 1ull);
+      keys[i] = ~0ull;
+      continue;
+    }
+    if (u == v) {
+      atomicAdd(&bstats[BS_LOOPS], 1ull);
+      keys[i] = ~0ull;
+      continue;
+    }
+    uint64_t a = (uint64_t)(uint32_t)P.ext2int[base + u];
+    uint64_t b = (uint64_t)(uint32_t)P.ext2int[base + v];
+    uint64_t mn = a < b ? a : b, mx = a < b ? b : a;
+    keys[i] = (((mn << bits) | (mx & idmask)) << 1) | (del ? 1ull : 0ull);
+  }
+}
+
+// After sorting: one decision per distinct pair (at its first key).
+__global__ void k_ingest_classify(PoolDev P, const unsigned long long* __restrict__ keys, int64_t total, int bits,
+                                  unsigned long long* __restrict__ dirA, unsigned long long* __restrict__ dirD,
+                                  unsigned long long* __restrict__ c, unsigned long long* __restrict__ bstats) {
+  const uint64_t idmask = (1ull << bits) - 1ull;
+  for (int64_t i = gtid(); i < total; i += gstride()) {
+    const unsigned long long key = keys[i];
+    if (key == ~0ull) continue;
+    const unsigned long long pair = key >> 1;
+    const int op = (int)(key & 1ull);
+    const unsigned long long prev = i > 0 ? keys[i - 1] : ~0ull;
+    if (prev == key) { atomicAdd(&bstats[BS_DUPS], 1ull); continue; }
+    if (i > 0 && (prev >> 1) == pair) continue;  // deletion key of a pair already seen as insertion
+    bool has_ins = op == 0, has_del = op == 1;
+    if (has_ins) {
+      // look for the deletion key of the same pair further on
+      const unsigned long long want = (pair << 1) | 1ull;
+      int64_t lo = i + 1, hi = total;
+      while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (keys[mid] < want) lo = mid + 1; else hi = mid; }
+      has_del = lo < total && keys[lo] == want;
+    }
+    if (has_ins && has_del) { atomicAdd(&bstats[BS_CANCEL], 1ull); continue; }
+    const uint32_t a = (uint32_t)(pair >> bits), b = (uint32_t)(pair & idmask);
+    const bool ex = edge_exists(P, a, b);
+    if (has_ins) {
+      if (ex) { atomicAdd(&bstats[BS_INS_EXIST], 1ull); continue; }
+      unsigned long long p = atomicAdd(&c[C_DIRA], 2ull);
+      dirA[p] = ((unsigned long long)a << bits) | b;
+      dirA[p + 1] = ((unsigned long long)b << bits) | a;
+      atomicAdd(&bstats[BS_EFF_INS], 1ull);
+    } else {
+      if (!ex) { atomicAdd(&bstats[BS_DEL_MISS], 1ull); continue; }
+      unsigned long long p = atomicAdd(&c[C_DIRD], 2ull);
+      dirD[p] = ((unsigned long long)a << bits) | b;
+      dirD[p + 1] = ((unsigned long long)b << bits) | a;
+      atomicAdd(&bstats[BS_EFF_DEL], 1ull);
+    }
+  }
+}
+
+// Row segments of a sorted directed list; touched-row list (each row once).
+__global__ void k_mark_rows(const unsigned long long* __restrict__ dir, const unsigned long long* c, int which,
+                            int bits, int32_t* __restrict__ beg, int32_t* __restrict__ cnt,
+                            int32_t* __restrict__ mark, int32_t* __restrict__ touched,
+                            int32_t* __restrict__ tix, unsigned long long* __restrict__ cc) {
+  const int64_t n = ctr(c, which);
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    const uint32_t row = (uint32_t)(dir[i] >> bits);
+    if (i > 0 && (uint32_t)(dir[i - 1] >> bits) == row) continue;
+    const unsigned long long nxt = (unsigned long long)(row + 1) << bits;
+    int64_t lo = i + 1, hi = n;
+    while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (dir[mid] < nxt) lo = mid + 1; else hi = mid; }
+    beg[row] = (int32_t)i;
+    cnt[row] = (int32_t)(lo - i);
+    const int bit = which == C_DIRA ? 1 : 2;
+    if (atomicOr(&mark[row], bit) == 0) {
+      unsigned long long p = atomicAdd(&cc[C_TOUCH], 1ull);
+      touched[p] = (int32_t)row;
+      tix[row] = (int32_t)p;
+    }
+  }
+}
+
+// --------------------------------------------------- tombstone merge
+// Plan: rows that receive insertions get a destination (in place when the
+// slack suffices, else a fresh bump-allocated segment).
+__global__ void k_plan_rows(PoolDev P, const int32_t* __restrict__ touched, const unsigned long long* c,
+                            int64_t max_touched, const int32_t* __restrict__ na, float slack,
+                            int64_t* __restrict__ dest, int32_t* __restrict__ newcap, int32_t* __restrict__ tlen,
+                            unsigned long long* __restrict__ bstats) {
+  const int64_t nt = ctr(c, C_TOUCH);
+  for (int64_t i = gtid(); i < max_touched; i += gstride()) {
+    if (i >= nt) { tlen[i] = 0; continue; }
+    const int32_t r = touched[i];
+    const int32_t add = na[r];
+    const int32_t L = P.len[r];
+    tlen[i] = L;  // copied to scratch for the merge and again for the purge
+    if (add == 0) { dest[i] = P.off[r]; newcap[i] = P.cap[r]; continue; }
+    const int32_t nl = L + add;
+    if (nl <= P.cap[r]) { dest[i] = P.off[r]; newcap[i] = P.cap[r]; continue; }
+    int64_t nc = (int64_t)nl + (int64_t)((float)nl * slack) + 4;
+    unsigned long long pos = atomicAdd(P.arena_top, (unsigned long long)nc);
+    if ((int64_t)pos + nc > P.arena_cap) {
+      atomicAdd(&bstats[BS_ARENA_OVF], 1ull);
+      dest[i] = -1;
+      newcap[i] = P.cap[r];
+      continue;
+    }
+    dest[i] = (int64_t)pos;
+    newcap[i] = (int32_t)nc;
+  }
+}
+
+// Flat copy of the touched rows into scratch (positions from tpre).
+__global__ void k_copy_rows(PoolDev P, const int32_t* __restrict__ touched, const unsigned long long* c,
+                            const int64_t* __restrict__ tpre, uint32_t* __restrict__ scratch) {
+  const int64_t nt = ctr(c, C_TOUCH);
+  if (nt == 0) return;
+  const int64_t total = tpre[nt];
+  for (int64_t i = gtid(); i < total; i += gstride()) {
+    const int64_t t = upper_bound_i64(tpre, nt, i);
+    const int32_t r = touched[t];
+    scratch[i] = P.col[P.off[r] + (i - tpre[t])];
+  }
+}
+
+// Merge: old entries shift right by the insertions before them; insertions
+// land after the old entries before them.  Inserted entries carry F_NEW.
+__global__ void k_merge_old(PoolDev P, const int32_t* __restrict__ touched, const unsigned long long* c,
+                            const int64_t* __restrict__ tpre, const uint32_t* __restrict__ scratch,
+                            const unsigned long long* __restrict__ dirA, int bits,
+                            const int32_t* __restrict__ a_beg, const int32_t* __restrict__ na,
+                            const int64_t* __restrict__ dest) {
+  const int64_t nt = ctr(c, C_TOUCH);
+  if (nt == 0) return;
+  const int64_t total = tpre[nt];
+  const uint64_t idmask = (1ull << bits) - 1ull;
+  for (int64_t i = gtid(); i < total; i += gstride()) {
+    const int64_t t = upper_bound_i64(tpre, nt, i);
+    const int32_t r = touched[t];
+    const int32_t cntA = na[r];
+    if (cntA == 0 || dest[t] < 0) continue;
+    const int64_t k = i - tpre[t];
+    const uint32_t x = scratch[i];
+    const uint32_t id = x & GC_ID;
+    const unsigned long long* A = dirA + a_beg[r];
+    int32_t lo = 0, hi = cntA;
+    while (lo < hi) { int32_t mid = (lo + hi) >> 1; if ((uint32_t)(A[mid] & idmask) < id) lo = mid + 1; else hi = mid; }
+    P.col[dest[t] + k + lo] = x;
+  }
+}
+
+__global__ void k_merge_new(PoolDev P, const unsigned long long* c, const unsigned long long* __restrict__ dirA,
+                            int bits, const int32_t* __restrict__ a_beg, const int32_t* __restrict__ tix,
+                            const int64_t* __restrict__ tpre, const uint32_t* __restrict__ scratch,
+                            const int64_t* __restrict__ dest) {
+  const int64_t n = ctr(c, C_DIRA);
+  const uint64_t idmask = (1ull << bits) - 1ull;
+  for (int64_t j = gtid(); j < n; j += gstride()) {
+    const uint32_t r = (uint32_t)(dirA[j] >> bits);
+    const uint32_t id = (uint32_t)(dirA[j] & idmask);
+    const int32_t t = tix[r];
+    if (dest[t] < 0) continue;
+    const int32_t q = (int32_t)(j - a_beg[r]);
+    const uint32_t* old = scratch + tpre[t];
+    const int32_t L = (int32_t)(tpre[t + 1] - tpre[t]);
+    int32_t p = lower_bound_id(old, L, id);
+    P.col[dest[t] + q + p] = id | GC_F_NEW;
+  }
+}
+
+__global__ void k_commit_rows(PoolDev P, const int32_t* __restrict__ touched, const unsigned long long* c,
+                              const int32_t* __restrict__ na, const int64_t* __restrict__ dest,
+                              const int32_t* __restrict__ newcap) {
+  const int64_t nt = ctr(c, C_TOUCH);
+  for (int64_t i = gtid(); i < nt; i += gstride()) {
+    const int32_t r = touched[i];
+    if (na[r] == 0 || dest[i] < 0) continue;
+    P.off[r] = dest[i];
+    P.cap[r] = newcap[i];
+    P.len[r] += na[r];
+  }
+}
+
+__global__ void k_flag_del(PoolDev P, const unsigned long long* c, const unsigned long long* __restrict__ dirD,
+                           int bits, unsigned long long* __restrict__ bstats) {
+  const int64_t n = ctr(c, C_DIRD);
+  const uint64_t idmask = (1ull << bits) - 1ull;
+  for (int64_t j = gtid(); j < n; j += gstride()) {
+    const uint32_t r = (uint32_t)(dirD[j] >> bits);
+    const uint32_t id = (uint32_t)(dirD[j] & idmask);
+    uint32_t* row = P.col + P.off[r];
+    int32_t p = lower_bound_id(row, P.len[r], id);
+    if (p < P.len[r] && (row[p] & GC_ID) == id) row[p] |= GC_F_DEL;
+    else atomicAdd(&bstats[BS_ERR], 1ull);
+  }
+}
+
+// ------------------------------------------------------------- purge
+// Remove F_DEL entries and clear F_NEW in the touched rows (from a scratch
+// copy of the union rows); reset the per-row batch arrays.
+__global__ void k_touched_len(PoolDev P, const int32_t* __restrict__ touched, const unsigned long long* c,
+                              int64_t max_touched, int32_t* __restrict__ tlen) {
+  const int64_t nt = ctr(c, C_TOUCH);
+  for (int64_t i = gtid(); i < max_touched; i += gstride()) tlen[i] = i < nt ? P.len[touched[i]] : 0;
+}
+
+__global__ void k_purge_rows(PoolDev P, const int32_t* __restrict__ touched, const unsigned long long* c,
+                             const int64_t* __restrict__ tpre, const uint32_t* __restrict__ scratch,
+                             const unsigned long long* __restrict__ dirD, int bits,
+                             const int32_t* __restrict__ d_beg, const int32_t* __restrict__ nd) {
+  const int64_t nt = ctr(c, C_TOUCH);
+  if (nt == 0) return;
+  const int64_t total = tpre[nt];
+  const uint64_t idmask = (1ull << bits) - 1ull;
+  for (int64_t i = gtid(); i < total; i += gstride()) {
+    const int64_t t = upper_bound_i64(tpre, nt, i);
+    const int32_t r = touched[t];
+    const uint32_t x = scratch[i];
+    if (x & GC_F_DEL) continue;
+    const int64_t k = i - tpre[t];
+    const int32_t cntD = nd[r];
+    int32_t lo = 0;
+    if (cntD) {
+      const unsigned long long* D = dirD + d_beg[r];
+      const uint32_t id = x & GC_ID;
+      int32_t hi = cntD;
+      while (lo < hi) { int32_t mid = (lo + hi) >> 1; if ((uint32_t)(D[mid] & idmask) < id) lo = mid + 1; else hi = mid; }
+    }
+    P.col[P.off[r] + k - lo] = x & GC_ID;
+  }
+}
+
+__global__ void k_purge_commit(PoolDev P, const int32_t* __restrict__ touched, const unsigned long long* c,
+                               int32_t* __restrict__ a_beg, int32_t* __restrict__ na, int32_t* __restrict__ d_beg,
+                               int32_t* __restrict__ nd, int32_t* __restrict__ mark, int32_t* __restrict__ tix) {
+  const int64_t nt = ctr(c, C_TOUCH);
+  for (int64_t i = gtid(); i < nt; i += gstride()) {
+    const int32_t r = touched[i];
+    P.len[r] -= nd[r];
+    a_beg[r] = 0; na[r] = 0; d_beg[r] = 0; nd[r] = 0; mark[r] = 0; tix[r] = 0;
+  }
+}
+
+// ------------------------------------------------------------ region
+// Levels: 0 = endpoint of a changed pair, k = first reached after k hops,
+// LV_OUT = outside.  The region is every vertex with level <= radius; the
+// counting runs on the subgraph induced on it (an induced superset of the
+// changed 4-sets, see region_mark in the host code for the radius).
+constexpr int32_t LV_OUT = 0x7fffffff;
+
+__global__ void k_level0(const int32_t* __restrict__ touched, const unsigned long long* c,
+                         int32_t* __restrict__ level, int32_t* __restrict__ rlist, unsigned long long* __restrict__ cc) {
+  const int64_t nt = ctr(c, C_TOUCH);
+  for (int64_t i = gtid(); i < nt; i += gstride()) {
+    const int32_t r = touched[i];
+    level[r] = 0;
+    rlist[i] = r;
+  }
+  if (gtid() == 0) { cc[C_RLIST] = (unsigned long long)nt; cc[C_LVL0 + 1] = (unsigned long long)nt; cc[C_LVL0] = 0; }
+}
+
+// Expand the vertices of list range [lvl_beg, lvl_end) by one hop.
+__global__ void k_expand(PoolDev P, int lvl, int32_t* __restrict__ level, int32_t* __restrict__ rlist,
+                         unsigned long long* __restrict__ cc) {
+  const int64_t b = ctr(cc, C_LVL0 + lvl), e = ctr(cc, C_LVL0 + lvl + 1);
+  for (int64_t i = b + gwave(); i < e; i += gwaves()) {
+    const int32_t v = rlist[i];
+    const uint32_t* row = P.col + P.off[v];
+    const int32_t L = P.len[v];
+    for (int32_t k = lane_id(); k < L; k += 64) {
+      const uint32_t w = row[k] & GC_ID;
+      if (level[w] == LV_OUT && atomicCAS(&level[w], LV_OUT, lvl + 1) == LV_OUT) {
+        unsigned long long p = atomicAdd(&cc[C_RLIST], 1ull);
+        rlist[p] = (int32_t)w;
+      }
+    }
+  }
+}
+
+__global__ void k_level_end(unsigned long long* cc, int lvl) {
+  if (gtid() == 0) cc[C_LVL0 + lvl + 1] = cc[C_RLIST];
+}
+
+// Whole-graph region: every vertex with a non-empty row.
+__global__ void k_all_rows(PoolDev P, int32_t* __restrict__ rlist, unsigned long long* __restrict__ cc) {
+  for (int64_t v = gtid(); v < P.N; v += gstride()) {
+    if (P.len[v] > 0) {
+      unsigned long long p = atomicAdd(&cc[C_RLIST], 1ull);
+      rlist[p] = (int32_t)v;
+    }
+  }
+}
+
+// Region row lengths (entries whose other end is in the region).
+__global__ void k_region_len(PoolDev P, const int32_t* __restrict__ rlist, const unsigned long long* cc,
+                             const int32_t* __restrict__ level, int32_t radius, int32_t* __restrict__ rlen) {
+  const int64_t n = ctr(cc, C_RLIST);
+  for (int64_t i = gwave(); i < n; i += gwaves()) {
+    const int32_t v = rlist[i];
+    const int32_t L = P.len[v];
+    if (radius < 0 || level[v] < radius) { if (lane_id() == 0) rlen[v] = L; continue; }
+    const uint32_t* row = P.col + P.off[v];
+    int32_t cnt = 0;
+    for (int32_t k = lane_id(); k < L; k += 64) cnt += level[row[k] & GC_ID] <= radius;
+    cnt = wave_sum32(cnt);
+    if (lane_id() == 0) rlen[v] = cnt;
+  }
+}
+
+__global__ void k_region_fill(PoolDev P, RegionDev R, const int32_t* __restrict__ rlist, const unsigned long long* cc,
+                              const int32_t* __restrict__ level, int32_t radius) {
+  const int64_t n = ctr(cc, C_RLIST);
+  for (int64_t i = gwave(); i < n; i += gwaves()) {
+    const int32_t v = rlist[i];
+    const int32_t L = P.len[v];
+    const uint32_t* row = P.col + P.off[v];
+    uint32_t* out = R.rcol + R.roff[v];
+    if (radius < 0 || level[v] < radius) {
+      for (int32_t k = lane_id(); k < L; k += 64) out[k] = row[k];
+      continue;
+    }
+    int32_t base = 0;
+    for (int32_t k0 = 0; k0 < L; k0 += 64) {
+      const int32_t k = k0 + lane_id();
+      uint32_t x = 0;
+      bool keep = false;
+      if (k < L) { x = row[k]; keep = level[x & GC_ID] <= radius; }
+      const uint64_t m = __ballot(keep);
+      if (keep) out[base + __popcll(m & lanemask_lt())] = x;
+      base += __popcll(m);
+    }
+  }
+}
+
+// Per-vertex pass over the region: degrees per version, N- split, the
+// 3-star and wedge terms, and the work lists of the counting kernels.
+__global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const int32_t* __restrict__ rlist,
+                          unsigned long long* __restrict__ cc, unsigned long long* __restrict__ sig,
+                          int32_t* __restrict__ lists, int64_t list_stride, int32_t tri_small, int32_t c4_small,
+                          int32_t c4_mid, unsigned long long* __restrict__ bstats) {
+  const int64_t n = ctr(cc, C_RLIST);
+  int cur_g = -1;
+  int64_t s1b = 0, s1a = 0, wb = 0, wa = 0, d1b = 0, d1a = 0, wedges = 0;
+  int32_t maxdp = 0;
+  int64_t maxw = 0;
+  for (int64_t i = gwave(); i < n; i += gwaves()) {
+    const int32_t v = rlist[i];
+    const int64_t b = R.roff[v];
+    const int32_t L = (int32_t)(R.roff[v + 1] - b);
+    const uint32_t* row = R.rcol + b;
+    int32_t db = 0, da = 0, low = 0;
+    int64_t wsum = 0;
+    for (int32_t k = lane_id(); k < L; k += 64) {
+      const uint32_t x = row[k];
+      db += !(x & GC_F_NEW);
+      da += !(x & GC_F_DEL);
+      const uint32_t w = x & GC_ID;
+      if (w < (uint32_t)v) { low += 1; wsum += R.roff[w + 1] - R.roff[w]; }
+    }
+    db = wave_sum32(db); da = wave_sum32(da); low = wave_sum32(low);
+    wsum = wave_sum64(wsum);
+    if (lane_id() == 0) {
+      R.dB[v] = db; R.dA[v] = da; R.rlow[v] = low;
+      const int g = gid[v];
+      if (g != cur_g) {
+        if (cur_g >= 0) {
+          atomicAdd(&sig[SIG_IDX(cur_g, 0, SG_S1)], (unsigned long long)s1b);
+          atomicAdd(&sig[SIG_IDX(cur_g, 1, SG_S1)], (unsigned long long)s1a);
+          atomicAdd(&sig[SIG_IDX(cur_g, 0, SG_W)], (unsigned long long)wb);
+          atomicAdd(&sig[SIG_IDX(cur_g, 1, SG_W)], (unsigned long long)wa);
+          atomicAdd(&sig[SIG_IDX(cur_g, 0, SG_D1)], (unsigned long long)d1b);
+          atomicAdd(&sig[SIG_IDX(cur_g, 1, SG_D1)], (unsigned long long)d1a);
+        }
+        cur_g = g; s1b = s1a = wb = wa = d1b = d1a = 0;
+      }
+      s1b += c3(db); s1a += c3(da); wb += c2(db); wa += c2(da); d1b += db; d1a += da;
+      const int32_t dplus = L - low;
+      if (dplus >= 2) {
+        const int which = dplus <= tri_small ? L_TRI_S : L_TRI_L;
+        unsigned long long p = atomicAdd(&cc[C_LIST0 + which], 1ull);
+        lists[which * list_stride + p] = v;
+        maxdp = dplus > maxdp ? dplus : maxdp;
+      }
+      if (low >= 2 && wsum >= 2) {
+        const int which = wsum <= c4_small ? L_C4_S : (wsum <= c4_mid ? L_C4_M : L_C4_L);
+        unsigned long long p = atomicAdd(&cc[C_LIST0 + which], 1ull);
+        lists[which * list_stride + p] = v;
+        maxw = wsum > maxw ? wsum : maxw;
+        wedges += wsum;
+      }
+    }
+  }
+  if (lane_id() == 0) {
+    if (cur_g >= 0) {
+      atomicAdd(&sig[SIG_IDX(cur_g, 0, SG_S1)], (unsigned long long)s1b);
+      atomicAdd(&sig[SIG_IDX(cur_g, 1, SG_S1)], (unsigned long long)s1a);
+      atomicAdd(&sig[SIG_IDX(cur_g, 0, SG_W)], (unsigned long long)wb);
+      atomicAdd(&sig[SIG_IDX(cur_g, 1, SG_W)], (unsigned long long)wa);
+      atomicAdd(&sig[SIG_IDX(cur_g, 0, SG_D1)], (unsigned long long)d1b);
+      atomicAdd(&sig[SIG_IDX(cur_g, 1, SG_D1)], (unsigned long long)d1a);
+    }
+    if (maxdp) atomicMax(&cc[C_MAXDP], (unsigned long long)maxdp);
+    if (maxw) atomicMax(&cc[C_MAXW], (unsigned long long)maxw);
+    if (wedges) atomicAdd(&bstats[BS_WEDGES], (unsigned long long)wedges);
+  }
+}
+
+__global__ void k_region_total(const int64_t* roff, int64_t N, unsigned long long* cc) {
+  if (gtid() == 0) cc[C_ER] = (unsigned long long)roff[N];
+}
+
+// ------------------------------------------------------------ init build
+__global__ void k_init_keys(const int32_t* __restrict__ src, const int32_t* __restrict__ dst, int64_t m,
+                            const int64_t* __restrict__ seg, const int64_t* __restrict__ gbase, int32_t k,
+                            int bits, unsigned long long* __restrict__ keys) {
+  const uint64_t idmask = (1ull << bits) - 1ull;
+  for (int64_t i = gtid(); i < m; i += gstride()) {
+    int lo = 0, hi = k;
+    while (hi - lo > 1) { int mid = (lo + hi) >> 1; if (seg[mid] <= i) lo = mid; else hi = mid; }
+    const uint64_t u = (uint64_t)(gbase[lo] + src[i]), v = (uint64_t)(gbase[lo] + dst[i]);
+    if (u == v) { keys[i] = ~0ull; continue; }
+    const uint64_t a = u < v ? u : v, b = u < v ? v : u;
+    keys[i] = (a << bits) | (b & idmask);
+  }
+}
+
+// unique edges -> degree count (external ids)
+__global__ void k_init_unique(const unsigned long long* __restrict__ keys, int64_t m, int bits,
+                              unsigned long long* __restrict__ uniq, unsigned long long* __restrict__ cc,
+                              int32_t* __restrict__ deg) {
+  const uint64_t idmask = (1ull << bits) - 1ull;
+  for (int64_t i = gtid(); i < m; i += gstride()) {
+    const unsigned long long k = keys[i];
+    if (k == ~0ull || (i > 0 && keys[i - 1] == k)) continue;
+    unsigned long long p = atomicAdd(&cc[C_DIRA], 1ull);
+    uniq[p] = k;
+    atomicAdd(&deg[k >> bits], 1);
+    atomicAdd(&deg[k & idmask], 1);
+  }
+}
+
+// rank keys: (graph, degree, local id)
+__global__ void k_rank_keys(const int32_t* __restrict__ deg, const int32_t* __restrict__ gid,
+                            const int64_t* __restrict__ gbase, int64_t N, int lbits,
+                            unsigned long long* __restrict__ keys) {
+  for (int64_t v = gtid(); v < N; v += gstride()) {
+    const int g = gid[v];
+    const uint64_t local = (uint64_t)(v - gbase[g]);
+    keys[v] = ((uint64_t)g << (2 * lbits)) | ((uint64_t)deg[v] << lbits) | local;
+  }
+}
+
+__global__ void k_rank_assign(const unsigned long long* __restrict__ sorted, const int64_t* __restrict__ gbase,
+                              int64_t N, int lbits, int32_t* __restrict__ ext2int) {
+  const uint64_t lmask = (1ull << lbits) - 1ull;
+  for (int64_t p = gtid(); p < N; p += gstride()) {
+    const unsigned long long k = sorted[p];
+    const int g = (int)(k >> (2 * lbits));
+    const int64_t ext = gbase[g] + (int64_t)(k & lmask);
+    ext2int[ext] = (int32_t)p;
+  }
+}
+
+__global__ void k_init_dir(const unsigned long long* __restrict__ uniq, const unsigned long long* cc, int bits,
+                           const int32_t* __restrict__ ext2int, unsigned long long* __restrict__ dir,
+                           int32_t* __restrict__ len) {
+  const int64_t m = ctr(cc, C_DIRA);
+  const uint64_t idmask = (1ull << bits) - 1ull;
+  for (int64_t i = gtid(); i < m; i += gstride()) {
+    const uint64_t a = (uint64_t)(uint32_t)ext2int[uniq[i] >> bits];
+    const uint64_t b = (uint64_t)(uint32_t)ext2int[uniq[i] & idmask];
+    dir[2 * i] = (a << bits) | b;
+    dir[2 * i + 1] = (b << bits) | a;
+    atomicAdd(&len[a], 1);
+    atomicAdd(&len[b], 1);
+  }
+}
+
+__global__ void k_init_caps(PoolDev P, float slack) {
+  for (int64_t v = gtid(); v < P.N; v += gstride()) {
+    const int32_t L = P.len[v];
+    P.cap[v] = L + (int32_t)((float)L * slack) + (L > 0 ? 2 : 0);
+  }
+}
+
+// entries carry F_NEW: at build time the graph before is empty
+__global__ void k_init_fill(PoolDev P, const unsigned long long* __restrict__ dir, const unsigned long long* cc,
+                            int bits, const int64_t* __restrict__ rstart, uint32_t flag) {
+  const int64_t n = 2 * ctr(cc, C_DIRA);
+  const uint64_t idmask = (1ull << bits) - 1ull;
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    const uint32_t r = (uint32_t)(dir[i] >> bits);
+    P.col[P.off[r] + (i - rstart[r])] = (uint32_t)(dir[i] & idmask) | flag;
+  }
+}
+
+__global__ void k_set_top(PoolDev P, const int64_t* off_end) {
+  if (gtid() == 0) *P.arena_top = (unsigned long long)*off_end;
+}
+
+// set or clear flag bits on every entry of every row
+__global__ void k_all_flags(PoolDev P, uint32_t set, uint32_t keep) {
+  for (int64_t v = gwave(); v < P.N; v += gwaves()) {
+    uint32_t* row = P.col + P.off[v];
+    const int32_t L = P.len[v];
+    for (int32_t k = lane_id(); k < L; k += 64) row[k] = (row[k] & keep) | set;
+  }
+}
+
+// compaction: copy rows into a fresh arena with new offsets
+__global__ void k_compact_copy(PoolDev P, const int64_t* __restrict__ noff, uint32_t* __restrict__ ncol) {
+  for (int64_t v = gwave(); v < P.N; v += gwaves()) {
+    const uint32_t* row = P.col + P.off[v];
+    uint32_t* out = ncol + noff[v];
+    const int32_t L = P.len[v];
+    for (int32_t k = lane_id(); k < L; k += 64) out[k] = row[k];
+  }
+}
+
+// edge list export (internal -> external ids, each edge once)
+__global__ void k_export_edges(PoolDev P, const int32_t* __restrict__ int2ext, const int64_t* __restrict__ gbase,
+                               const int64_t* __restrict__ pre, int32_t* __restrict__ src, int32_t* __restrict__ dst) {
+  for (int64_t v = gwave(); v < P.N; v += gwaves()) {
+    const uint32_t* row = P.col + P.off[v];
+    const int32_t L = P.len[v];
+    const int g = P.gid[v];
+    int64_t base = pre[v];
+    for (int32_t k0 = 0; k0 < L; k0 += 64) {
+      const int32_t k = k0 + lane_id();
+      bool up = false;
+      uint32_t w = 0;
+      if (k < L) { w = row[k] & GC_ID; up = w > (uint32_t)v; }
+      const uint64_t m = __ballot(up);
+      if (up) {
+        const int64_t p = base + __popcll(m & lanemask_lt());
+        src[p] = (int32_t)(int2ext[v] - gbase[g]);
+        dst[p] = (int32_t)(int2ext[w] - gbase[g]);
+      }
+      base += __popcll(m);
+    }
+  }
+}
+
+__global__ void k_upper_count(PoolDev P, int32_t* __restrict__ cnt) {
+  for (int64_t v = gwave(); v < P.N; v += gwaves()) {
+    const uint32_t* row = P.col + P.off[v];
+    const int32_t L = P.len[v];
+    int32_t c = 0;
+    for (int32_t k = lane_id(); k < L; k += 64) c += (row[k] & GC_ID) > (uint32_t)v;
+    c = wave_sum32(c);
+    if (lane_id() == 0) cnt[v] = c;
+  }
+}
+
+__global__ void k_invert_perm(const int32_t* __restrict__ ext2int, int64_t N, int32_t* __restrict__ int2ext) {
+  for (int64_t e = gtid(); e < N; e += gstride()) int2ext[ext2int[e]] = (int32_t)e;
+}
+
+inline unsigned grid_for(int64_t n, int per = TPB, unsigned cap = 65535u * 4) {
+  int64_t g = (n + per - 1) / per;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+// ================================================================ launchers
+void launch_ingest_keys(const PoolDev& P, const BatchIn& B, int bits, unsigned long long* keys,
+                        unsigned long long* bstats, hipStream_t s) {
+  int64_t n = B.n_ins + B.n_del;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_ingest_keys, dim3(grid_for(n)), dim3(TPB), 0, s, P, B, bits, keys, bstats);
+}
+
+void launch_ingest_classify(const PoolDev& P, const unsigned long long* keys, int64_t total, int bits,
+                            unsigned long long* dirA, unsigned long long* dirD, unsigned long long* c,
+                            unsigned long long* bstats, hipStream_t s) {
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_ingest_classify, dim3(grid_for(total)), dim3(TPB), 0, s, P, keys, total, bits, dirA, dirD, c,
+                     bstats);
+}
+
+void launch_mark_rows(const unsigned long long* dir, int64_t max_n, unsigned long long* c, int which, int bits,
+                      int32_t* beg, int32_t* cnt, int32_t* mark, int32_t* touched, int32_t* tix, hipStream_t s) {
+  if (max_n == 0) return;
+  hipLaunchKernelGGL(k_mark_rows, dim3(grid_for(max_n)), dim3(TPB), 0, s, dir, c, which, bits, beg, cnt, mark,
+                     touched, tix, c);
+}
+
+void launch_merge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int64_t max_dirA, int bits, float slack,
+                  unsigned long long* bstats, void* scan_tmp, hipStream_t s) {
+  if (max_touched == 0) return;
+  hipLaunchKernelGGL(k_plan_rows, dim3(grid_for(max_touched)), dim3(TPB), 0, s, P, W.touched, W.c, max_touched,
+                     W.na, slack, W.dest, W.newcap, W.tlen, bstats);
+  exclusive_scan_i32_to_i64(W.tlen, W.tpre, max_touched, scan_tmp, s);
+  const unsigned g = 4096;
+  hipLaunchKernelGGL(k_copy_rows, dim3(g), dim3(TPB), 0, s, P, W.touched, W.c, W.tpre, W.scratch);
+  hipLaunchKernelGGL(k_merge_old, dim3(g), dim3(TPB), 0, s, P, W.touched, W.c, W.tpre, W.scratch, W.dirA, bits,
+                     W.a_beg, W.na, W.dest);
+  if (max_dirA)
+    hipLaunchKernelGGL(k_merge_new, dim3(grid_for(max_dirA)), dim3(TPB), 0, s, P, W.c, W.dirA, bits, W.a_beg, W.tix,
+                       W.tpre, W.scratch, W.dest);
+  hipLaunchKernelGGL(k_commit_rows, dim3(grid_for(max_touched)), dim3(TPB), 0, s, P, W.touched, W.c, W.na, W.dest,
+                     W.newcap);
+}
+
+void launch_flag_del(const PoolDev& P, const BatchWork& W, int64_t max_dirD, int bits, unsigned long long* bstats,
+                     hipStream_t s) {
+  if (max_dirD == 0) return;
+  hipLaunchKernelGGL(k_flag_del, dim3(grid_for(max_dirD)), dim3(TPB), 0, s, P, W.c, W.dirD, bits, bstats);
+}
+
+void launch_purge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int bits, void* scan_tmp, hipStream_t s) {
+  if (max_touched == 0) return;
+  // lengths of the union rows, then a copy, then the compaction
+  hipLaunchKernelGGL(k_touched_len, dim3(grid_for(max_touched)), dim3(TPB), 0, s, P, W.touched, W.c, max_touched,
+                     W.tlen);
+  exclusive_scan_i32_to_i64(W.tlen, W.tpre, max_touched, scan_tmp, s);
+  hipLaunchKernelGGL(k_copy_rows, dim3(4096), dim3(TPB), 0, s, P, W.touched, W.c, W.tpre, W.scratch);
+  hipLaunchKernelGGL(k_purge_rows, dim3(4096), dim3(TPB), 0, s, P, W.touched, W.c, W.tpre, W.scratch, W.dirD, bits,
+                     W.d_beg, W.nd);
+  hipLaunchKernelGGL(k_purge_commit, dim3(grid_for(max_touched)), dim3(TPB), 0, s, P, W.touched, W.c, W.a_beg, W.na,
+                     W.d_beg, W.nd, W.mark, W.tix);
+}
+
+void launch_region(const PoolDev& P, const BatchWork& W, int radius, int32_t* level, int32_t* rlist, int32_t* rlen,
+                   hipStream_t s) {
+  const int64_t N = P.N;
+  fill_u32((uint32_t*)rlen, 0u, N, s);
+  if (radius < 0) {
+    hipLaunchKernelGGL(k_all_rows, dim3(grid_for(N)), dim3(TPB), 0, s, P, rlist, W.c);
+    hipLaunchKernelGGL(k_region_len, dim3(4096), dim3(TPB), 0, s, P, rlist, W.c, level, -1, rlen);
+    return;
+  }
+  fill_u32((uint32_t*)level, (uint32_t)LV_OUT, N, s);
+  hipLaunchKernelGGL(k_level0, dim3(grid_for(N)), dim3(TPB), 0, s, W.touched, W.c, level, rlist, W.c);
+  for (int l = 0; l < radius; ++l) {
+    hipLaunchKernelGGL(k_expand, dim3(4096), dim3(TPB), 0, s, P, l, level, rlist, W.c);
+    hipLaunchKernelGGL(k_level_end, dim3(1), dim3(64), 0, s, W.c, l + 1);
+  }
+  hipLaunchKernelGGL(k_region_len, dim3(4096), dim3(TPB), 0, s, P, rlist, W.c, level, radius, rlen);
+}
+
+void launch_region_fill(const PoolDev& P, const RegionDev& R, const BatchWork& W, int radius, const int32_t* level,
+                        const int32_t* rlist, const int32_t* rlen, void* scan_tmp, hipStream_t s) {
+  exclusive_scan_i32_to_i64(rlen, R.roff, P.N, scan_tmp, s);
+  hipLaunchKernelGGL(k_region_total, dim3(1), dim3(64), 0, s, R.roff, P.N, W.c);
+  hipLaunchKernelGGL(k_region_fill, dim3(4096), dim3(TPB), 0, s, P, R, rlist, W.c, level, radius);
+}
+
+void launch_degrees(const RegionDev& R, const int32_t* gid, const int32_t* rlist, unsigned long long* c,
+                    unsigned long long* sig, int32_t* lists, int64_t list_stride, int32_t tri_small, int32_t c4_small,
+                    int32_t c4_mid, unsigned long long* bstats, hipStream_t s) {
+  hipLaunchKernelGGL(k_degrees, dim3(4096), dim3(TPB), 0, s, R, gid, rlist, c, sig, lists, list_stride, tri_small,
+                     c4_small, c4_mid, bstats);
+}
+
+// ---------------------------------------------------------------- build
+void launch_init_keys(const int32_t* src, const int32_t* dst, int64_t m, const int64_t* seg, const int64_t* gbase,
+                      int32_t k, int bits, unsigned long long* keys, hipStream_t s) {
+  if (m == 0) return;
+  hipLaunchKernelGGL(k_init_keys, dim3(grid_for(m)), dim3(TPB), 0, s, src, dst, m, seg, gbase, k, bits, keys);
+}
+void launch_init_unique(const unsigned long long* keys, int64_t m, int bits, unsigned long long* uniq,
+                        unsigned long long* c, int32_t* deg, hipStream_t s) {
+  if (m == 0) return;
+  hipLaunchKernelGGL(k_init_unique, dim3(grid_for(m)), dim3(TPB), 0, s, keys, m, bits, uniq, c, deg);
+}
+void launch_rank(const int32_t* deg, const int32_t* gid, const int64_t* gbase, int64_t N, int lbits, int total_bits,
+                 unsigned long long* keys, unsigned long long* alt, void* sort_tmp, int32_t* ext2int, int32_t* int2ext,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_rank_keys, dim3(grid_for(N)), dim3(TPB), 0, s, deg, gid, gbase, N, lbits, keys);
+  unsigned long long* sorted = radix_sort_u64(keys, alt, sort_tmp, N, nullptr, total_bits, s);
+  hipLaunchKernelGGL(k_rank_assign, dim3(grid_for(N)), dim3(TPB), 0, s, sorted, gbase, N, lbits, ext2int);
+  hipLaunchKernelGGL(k_invert_perm, dim3(grid_for(N)), dim3(TPB), 0, s, ext2int, N, int2ext);
+}
+void launch_init_dir(const unsigned long long* uniq, int64_t max_m, unsigned long long* c, int bits,
+                     const int32_t* ext2int, unsigned long long* dir, int32_t* len, hipStream_t s) {
+  if (max_m == 0) return;
+  hipLaunchKernelGGL(k_init_dir, dim3(grid_for(max_m)), dim3(TPB), 0, s, uniq, c, bits, ext2int, dir, len);
+}
+void launch_init_csr(const PoolDev& P, const unsigned long long* dir, int64_t max_dir, unsigned long long* c, int bits,
+                     int64_t* rstart, float slack, void* scan_tmp, uint32_t flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_caps, dim3(grid_for(P.N)), dim3(TPB), 0, s, P, slack);
+  exclusive_scan_i32_to_i64(P.len, rstart, P.N, scan_tmp, s);
+  exclusive_scan_i32_to_i64(P.cap, P.off, P.N, scan_tmp, s);
+  hipLaunchKernelGGL(k_set_top, dim3(1), dim3(64), 0, s, P, P.off + P.N);
+  if (max_dir)
+    hipLaunchKernelGGL(k_init_fill, dim3(grid_for(max_dir)), dim3(TPB), 0, s, P, dir, c, bits, rstart, flag);
+}
+void launch_caps(const PoolDev& P, float slack, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_caps, dim3(grid_for(P.N)), dim3(TPB), 0, s, P, slack);
+}
+void launch_all_flags(const PoolDev& P, uint32_t set, uint32_t keep, hipStream_t s) {
+  hipLaunchKernelGGL(k_all_flags, dim3(4096), dim3(TPB), 0, s, P, set, keep);
+}
+void launch_compact(const PoolDev& P, int64_t* noff, uint32_t* ncol, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact_copy, dim3(4096), dim3(TPB), 0, s, P, noff, ncol);
+}
+void launch_upper_count(const PoolDev& P, int32_t* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_upper_count, dim3(4096), dim3(TPB), 0, s, P, cnt);
+}
+void launch_export(const PoolDev& P, const int32_t* int2ext, const int64_t* gbase, const int64_t* pre, int32_t* src,
+                   int32_t* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_export_edges, dim3(4096), dim3(TPB), 0, s, P, int2ext, gbase, pre, src, dst);
+}

@@ -1,0 +1,194 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle.
+
+Every count is an exact integer, so the bar is equality after every batch:
+the tiny Erdos-Renyi workload against stored brute-force counts, random
+streams (clean and messy batches) against the static recount of the oracle,
+the edge set against the oracle's set semantics, and the region radius
+variants against each other.  Radius 1 must fail somewhere (the region is
+load-bearing).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from graphgen import (erdos_renyi, er_batches, rmat_graph, rmat_batches, chung_lu_graph,
+                      chung_lu_batches, raw_noise_batch, BatchStream)
+from oracle import native
+from oracle.semantics import apply_batch as oracle_apply, BatchRejected
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def G(*a, **k):
+    from paper_2308_14493_amd.graphlet4 import Graph
+    return Graph(*a, **k)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def esorted(E):
+    E = sorted(E)
+    return (np.array([u for u, v in E], np.int32), np.array([v for u, v in E], np.int32))
+
+
+def edge_set(src, dst):
+    return {(min(int(a), int(b)), max(int(a), int(b))) for a, b in zip(src, dst)}
+
+
+def test_er150_golden():
+    say("case er150 golden")
+    g = json.load(open(os.path.join(HERE, "golden", "er150_counts.json")))
+    n = g["n"]
+    s, d = erdos_renyi(n, 6 / 149, 0)
+    with G(n, s, d) as gr:
+        assert gr.counts() == g["counts"][0]
+        for i, (b, want) in enumerate(zip(er_batches(n, s, d), g["counts"][1:])):
+            got = gr.apply_batch(*b)
+            assert got == want, "batch %d" % i
+        assert gr.recount() == g["counts"][-1]
+
+
+def _messy_stream(n, s, d, seed, nb=6):
+    rng = np.random.default_rng(seed)
+    E = edge_set(s, d)
+    out = []
+    for i in range(nb):
+        if i % 2 == 0:
+            es, ed = esorted(E)
+            out.append(raw_noise_batch(n, es, ed, int(rng.integers(2, 12)), seed * 100 + i))
+        else:
+            k = int(rng.integers(1, 30))
+            el = sorted(E)
+            pick = rng.choice(len(el), min(k, len(el)), replace=False) if el else []
+            dsrc = np.array([el[p][0] for p in pick], np.int32)
+            ddst = np.array([el[p][1] for p in pick], np.int32)
+            out.append((rng.integers(0, n, k).astype(np.int32), rng.integers(0, n, k).astype(np.int32), dsrc, ddst))
+        oracle_apply(E, n, *out[-1])
+    return out
+
+
+@pytest.mark.parametrize("radius", [2, 3, 0])
+@pytest.mark.parametrize("seed", range(6))
+def test_random_streams(seed, radius):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(8, 70))
+    p = float(rng.choice([0.05, 0.15, 0.3, 0.6]))
+    say("case random n=%d p=%.2f seed=%d radius=%d" % (n, p, seed, radius))
+    s, d = erdos_renyi(n, p, seed)
+    E = edge_set(s, d)
+    with G(n, s, d, radius=radius) as gr:
+        assert gr.counts() == native.static_counts(n, s, d)
+        for b in _messy_stream(n, s, d, seed):
+            got = gr.apply_batch(*b)
+            oracle_apply(E, n, *b)
+            es, ed = esorted(E)
+            assert got == native.static_counts(n, es, ed)
+        gs, gd = gr.edges()
+        assert edge_set(gs, gd) == E
+
+
+@pytest.mark.parametrize("scale,ef,seed", [(9, 8, 1), (11, 8, 2), (12, 16, 3)])
+def test_rmat_streams(scale, ef, seed):
+    say("case rmat scale=%d ef=%d seed=%d" % (scale, ef, seed))
+    n, s, d, samp = rmat_graph(scale, ef, seed)
+    sizes = [2, 10, 100, 1000]
+    batches = rmat_batches(n, s, d, samp, sizes, seed + 7)
+    E = edge_set(s, d)
+    with G(n, s, d) as gr:
+        assert gr.counts() == native.static_counts(n, s, d)
+        for b, sz in zip(batches, sizes):
+            got, st = gr.apply_batch(*b, stats=True)
+            oracle_apply(E, n, *b)
+            es, ed = esorted(E)
+            say("  batch %d region_v=%d region_e=%d" % (sz, st["region_vertices"], st["region_entries"]))
+            assert got == native.static_counts(n, es, ed)
+        assert gr.recount() == gr.counts()
+
+
+def test_chung_lu_small():
+    say("case chung-lu n=20000 m=60000")
+    n, s, d, _ = chung_lu_graph(20000, 60000, 2.1, 2000.0, 5)
+    batches = chung_lu_batches(n, s, d, [10, 300, 3000], 6)
+    E = edge_set(s, d)
+    with G(n, s, d) as gr:
+        assert gr.counts() == native.static_counts(n, s, d)
+        for b in batches:
+            got = gr.apply_batch(*b)
+            oracle_apply(E, n, *b)
+            es, ed = esorted(E)
+            assert got == native.static_counts(n, es, ed)
+
+
+def test_radius_one_is_wrong_somewhere():
+    say("case radius-1 negative control")
+    bad = 0
+    for seed in range(6):
+        rng = np.random.default_rng(seed)
+        n = 40
+        s, d = erdos_renyi(n, 0.12, seed)
+        E = edge_set(s, d)
+        with G(n, s, d, radius=1) as gr:
+            for b in _messy_stream(n, s, d, seed):
+                got = gr.apply_batch(*b)
+                oracle_apply(E, n, *b)
+                es, ed = esorted(E)
+                bad += got[:6] != native.static_counts(n, es, ed)[:6]
+    assert bad > 0
+
+
+def test_bad_id_rejected_state_unchanged():
+    say("case invalid ids")
+    from paper_2308_14493_amd.graphlet4 import GraphletError
+    n = 30
+    s, d = erdos_renyi(n, 0.2, 3)
+    with G(n, s, d) as gr:
+        before = gr.counts()
+        with pytest.raises(GraphletError) as e:
+            gr.apply_batch([1, 2], [3, 30], [], [])
+        assert e.value.code == -1
+        with pytest.raises(GraphletError):
+            gr.apply_batch([], [], [-1], [2])
+        assert gr.counts() == before
+        assert gr.recount() == before
+
+
+def test_zero_slack_relocation():
+    """slack 0: every insertion moves its row to fresh arena space."""
+    say("case zero slack")
+    n, s, d, samp = rmat_graph(10, 8, 4)
+    batches = rmat_batches(n, s, d, samp, [50, 400, 400, 2000], 9)
+    E = edge_set(s, d)
+    with G(n, s, d, slack=0.0) as gr:
+        for b in batches:
+            got = gr.apply_batch(*b)
+            oracle_apply(E, n, *b)
+        es, ed = esorted(E)
+        assert got == native.static_counts(n, es, ed)
+        gs, gd = gr.edges()
+        assert edge_set(gs, gd) == E
+
+
+def test_pool_matches_separate():
+    say("case pool of 5 graphs")
+    from paper_2308_14493_amd.graphlet4 import Graph
+    rng = np.random.default_rng(11)
+    ns, ss, ds, bs = [], [], [], []
+    for i in range(5):
+        n, s, d, samp = rmat_graph(int(rng.integers(6, 11)), int(rng.choice([4, 8])), 100 + i)
+        ns.append(n); ss.append(s); ds.append(d)
+        bs.append(rmat_batches(n, s, d, samp, [int(rng.integers(5, 300))], 200 + i)[0])
+    with Graph.pool(ns, ss, ds) as pool:
+        for i in range(5):
+            assert pool.counts(i) == native.static_counts(ns[i], ss[i], ds[i])
+        got = pool.apply_batches(bs)
+    for i in range(5):
+        E = edge_set(ss[i], ds[i])
+        oracle_apply(E, ns[i], *bs[i])
+        es, ed = esorted(E)
+        assert got[i] == native.static_counts(ns[i], es, ed)

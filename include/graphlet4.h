@@ -100,13 +100,15 @@ typedef struct {
   int64_t loops, dups, cancelled, ins_existing, del_missing;
   int64_t touched_vertices;          /* endpoints of effective changes */
   int64_t region_vertices, region_entries;  /* region size (entries = 2 x edges) */
-  int64_t wedge_bound;               /* 4-cycle wedge work bound */
+  int64_t wedges;                    /* 4-cycle wedges enumerated */
+  int64_t c4_entries_small, c4_entries_mid, c4_entries_large;  /* adjacency entries read per 4-cycle tier */
   int64_t max_out_degree;
-  int64_t tier_tri_small, tier_tri_large, tier_c4_small, tier_c4_mid, tier_c4_large;
+  int64_t tier_tri_small, tier_tri_large, tier_c4_small, tier_c4_mid, tier_c4_large;  /* vertices per tier */
   uint32_t overflow_mask;            /* classes whose count left int64 */
   float ms_total;                    /* wall time of the call */
-  float ms_prepare;                  /* ingest, merge, region (device) */
-  float ms_tri, ms_edge, ms_c4;      /* counting kernels (device) */
+  float ms_prepare;                  /* ingest, merge, region, per-vertex pass (device) */
+  float ms_tri, ms_edge;             /* triangle/4-clique kernels, edge pass (device) */
+  float ms_c4_small, ms_c4_mid, ms_c4_large;  /* 4-cycle tiers (device) */
   float ms_finish;                   /* combine + purge (device) */
 } gc_batch_stats;
 

@@ -141,7 +141,7 @@ struct gc_graph {
 
   void* pin = nullptr;
   size_t pin_cap = 0;
-  hipEvent_t ev[8] = {};
+  hipEvent_t ev[10] = {};
 
   ~gc_graph() {
     if (stream) (void)hipStreamSynchronize(stream);
@@ -237,8 +237,8 @@ void run_count(gc_graph* G, int radius, long long* state_d, BatchWork& W, std::v
   const int64_t ncl = (int64_t)hc[C_LIST0 + L_C4_L];
   if (ncl > 0) {
     int64_t per = N * (int64_t)(sizeof(unsigned long long) + sizeof(int32_t));
-    int64_t budget = (int64_t)8 << 30;
-    int64_t slots = std::max<int64_t>(1, std::min<int64_t>(512, budget / std::max<int64_t>(per, 1)));
+    int64_t budget = (int64_t)32 << 30;
+    int64_t slots = std::max<int64_t>(1, std::min<int64_t>(1024, budget / std::max<int64_t>(per, 1)));
     slots = std::min(slots, std::max<int64_t>(ncl, 1));
     if (slots > G->c4_slots) {
       G->c4_dense.release();
@@ -267,11 +267,7 @@ void run_count(gc_graph* G, int radius, long long* state_d, BatchWork& W, std::v
   }
   A.tri_scratch = G->tri_scratch.as<uint32_t>();
   A.tri_slot_words = G->tri_slot_words;
-  // the global-scratch triangle kernel runs with at most tri_slots workgroups
-  if (A.slots > 0 && maxdp > TL_LDS_MAX) A.slots = std::min(A.slots, G->tri_slots);
-  CountArgs A2 = A;
-  A2.slots = std::max(1, G->c4_slots);
-  (void)A2;
+  A.tri_slots = std::max(1, G->tri_slots);
   launch_count(A, hc.data(), s, timed ? &G->ev[2] : nullptr);
   launch_combine(G->sig.as<unsigned long long>(), state_d, G->k, s);
 }
@@ -519,7 +515,10 @@ void fill_stats(gc_graph* G, gc_batch_stats* st, const std::vector<unsigned long
   st->touched_vertices = (int64_t)hc[C_TOUCH];
   st->region_vertices = (int64_t)hc[C_RLIST];
   st->region_entries = (int64_t)hc[C_ER];
-  st->wedge_bound = (int64_t)hb[BS_WEDGES];
+  st->wedges = (int64_t)hb[BS_WEDGES];
+  st->c4_entries_small = (int64_t)hb[BS_C4_S];
+  st->c4_entries_mid = (int64_t)hb[BS_C4_M];
+  st->c4_entries_large = (int64_t)hb[BS_C4_L];
   st->max_out_degree = (int64_t)hc[C_MAXDP];
   st->tier_tri_small = (int64_t)hc[C_LIST0 + L_TRI_S];
   st->tier_tri_large = (int64_t)hc[C_LIST0 + L_TRI_L];
@@ -533,8 +532,10 @@ void fill_stats(gc_graph* G, gc_batch_stats* st, const std::vector<unsigned long
     (void)hipEventElapsedTime(&a, G->ev[0], G->ev[1]); st->ms_prepare = a;
     (void)hipEventElapsedTime(&a, G->ev[2], G->ev[3]); st->ms_tri = a;
     (void)hipEventElapsedTime(&a, G->ev[3], G->ev[4]); st->ms_edge = a;
-    (void)hipEventElapsedTime(&a, G->ev[4], G->ev[5]); st->ms_c4 = a;
-    (void)hipEventElapsedTime(&a, G->ev[5], G->ev[6]); st->ms_finish = a;
+    (void)hipEventElapsedTime(&a, G->ev[4], G->ev[5]); st->ms_c4_small = a;
+    (void)hipEventElapsedTime(&a, G->ev[5], G->ev[6]); st->ms_c4_mid = a;
+    (void)hipEventElapsedTime(&a, G->ev[6], G->ev[7]); st->ms_c4_large = a;
+    (void)hipEventElapsedTime(&a, G->ev[7], G->ev[8]); st->ms_finish = a;
   }
 }
 
@@ -664,7 +665,7 @@ void apply(gc_graph* G, const gc_batch_desc* b, bool dev, int64_t (*counts)[11],
   const int radius = G->opt.radius == 0 ? -1 : G->opt.radius;
   run_count(G, radius, G->state.as<long long>(), W, hc, union_bound, timed);
   launch_purge(P, W, max_touched, G->bits, G->scan_tmp.p, s);
-  if (timed) HIPCHK(hipEventRecord(G->ev[6], s));
+  if (timed) HIPCHK(hipEventRecord(G->ev[8], s));
 
   std::vector<unsigned long long> hb(BS_COUNT);
   G->hstate.resize((size_t)k * ST_STRIDE);

@@ -600,7 +600,7 @@ void launch_count(const CountArgs& A, const unsigned long long* hc, hipStream_t 
   if (ntl) {
     hipLaunchKernelGGL(k_tri_large<false>, dim3(cap_grid(ntl, 2048)), dim3(256), 0, s, A);
     if ((int64_t)hc[C_MAXDP] > TL_MAX)
-      hipLaunchKernelGGL(k_tri_large<true>, dim3(cap_grid(ntl, (unsigned)A.slots)), dim3(256), 0, s, A);
+      hipLaunchKernelGGL(k_tri_large<true>, dim3(cap_grid(ntl, (unsigned)A.tri_slots)), dim3(256), 0, s, A);
   }
   if (ev) (void)hipEventRecord(ev[1], s);
   if (E) hipLaunchKernelGGL(k_edge_pass, dim3(cap_grid((E / EP_RUN + 255) / 256, 8192)), dim3(256), 0, s, A);
@@ -608,11 +608,13 @@ void launch_count(const CountArgs& A, const unsigned long long* hc, hipStream_t 
   const int64_t ncs = (int64_t)hc[C_LIST0 + L_C4_S], ncm = (int64_t)hc[C_LIST0 + L_C4_M],
                 ncl = (int64_t)hc[C_LIST0 + L_C4_L];
   if (ncs) hipLaunchKernelGGL(k_c4_small, dim3(cap_grid((ncs + 3) / 4, 8192)), dim3(256), 0, s, A);
+  if (ev) (void)hipEventRecord(ev[3], s);
   if (ncm) hipLaunchKernelGGL(k_c4_mid, dim3(cap_grid(ncm, 4096)), dim3(256), 0, s, A);
+  if (ev) (void)hipEventRecord(ev[4], s);
   if (ncl)
     hipLaunchKernelGGL(k_c4_large, dim3(cap_grid(ncl, (unsigned)A.slots)), dim3(256), 0, s, A,
                        (unsigned long long*)(A.c + C_QHEAD));
-  if (ev) (void)hipEventRecord(ev[3], s);
+  if (ev) (void)hipEventRecord(ev[5], s);
 }
 
 void launch_combine(const unsigned long long* sig, long long* state, int32_t k, hipStream_t s) {

@@ -89,10 +89,11 @@ struct CountArgs {
   unsigned long long* c4_dense;   // [slots][N]
   int32_t* c4_touch;              // [slots][N]
   int64_t N;
-  int32_t slots;
+  int32_t slots;                  // workgroups of the large 4-cycle tier
+  int32_t tri_slots;              // workgroups of the global-scratch triangle tier
   uint32_t* tri_scratch;          // [slots][tri_slot_words] for out-degrees above the LDS tier
   int64_t tri_slot_words;
 };
 void launch_count(const CountArgs& A, const unsigned long long* host_counts, hipStream_t s,
-                  hipEvent_t* ev /* nullable: 4 events around tri, edge, c4 */);
+                  hipEvent_t* ev /* nullable: 6 events between the kernel phases */);
 void launch_combine(const unsigned long long* sig, long long* state, int32_t k, hipStream_t s);

@@ -398,7 +398,12 @@ __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const in
       db += !(x & GC_F_NEW);
       da += !(x & GC_F_DEL);
       const uint32_t w = x & GC_ID;
-      if (w < (uint32_t)v) { low += 1; wsum += R.roff[w + 1] - R.roff[w]; }
+      if (w < (uint32_t)v) {
+        // wedges (v, w, .) below v: entries of row w smaller than v
+        low += 1;
+        const int64_t wb = R.roff[w];
+        wsum += lower_bound_id(R.rcol + wb, (int32_t)(R.roff[w + 1] - wb), (uint32_t)v);
+      }
     }
     db = wave_sum32(db); da = wave_sum32(da); low = wave_sum32(low);
     wsum = wave_sum64(wsum);
@@ -430,6 +435,7 @@ __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const in
         lists[which * list_stride + p] = v;
         maxw = wsum > maxw ? wsum : maxw;
         wedges += wsum;
+        atomicAdd(&bstats[BS_C4_S + which - L_C4_S], (unsigned long long)(wsum + low));
       }
     }
   }

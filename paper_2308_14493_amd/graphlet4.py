@@ -31,9 +31,11 @@ class BatchStats(ctypes.Structure):
     _fields_ = [(n, _I64) for n in (
         "offered_ins", "offered_del", "eff_ins", "eff_del", "loops", "dups", "cancelled",
         "ins_existing", "del_missing", "touched_vertices", "region_vertices", "region_entries",
-        "wedge_bound", "max_out_degree", "tier_tri_small", "tier_tri_large", "tier_c4_small",
+        "wedges", "c4_entries_small", "c4_entries_mid", "c4_entries_large",
+        "max_out_degree", "tier_tri_small", "tier_tri_large", "tier_c4_small",
         "tier_c4_mid", "tier_c4_large")] + [("overflow_mask", ctypes.c_uint32)] + [
-        (n, ctypes.c_float) for n in ("ms_total", "ms_prepare", "ms_tri", "ms_edge", "ms_c4", "ms_finish")]
+        (n, ctypes.c_float) for n in ("ms_total", "ms_prepare", "ms_tri", "ms_edge", "ms_c4_small",
+                                      "ms_c4_mid", "ms_c4_large", "ms_finish")]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
@@ -64,6 +66,13 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("libgraphlet4.so is not built (python -m paper_2308_14493_amd.build)")
+    # One HIP runtime per process: torch ships its own libamdhip64 (same
+    # soname); importing it first lets the library bind to that copy
+    # instead of loading a second runtime that cannot open the device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     lib.gc_options_default.argtypes = [ctypes.POINTER(Options)]
     lib.gc_graph_init.argtypes = [_I64, _P, _P, _I64, ctypes.POINTER(Options), ctypes.POINTER(_P), _P]
@@ -178,8 +187,11 @@ class Graph:
         lib = load()
         st = BatchStats()
         out = np.zeros(11, np.int64)
+        import torch
         for t in (ins_src, ins_dst, del_src, del_dst):
-            assert t.dtype.is_floating_point is False and t.is_cuda and t.is_contiguous()
+            assert t.dtype == torch.int32 and t.is_cuda and t.is_contiguous()
+        # the library runs on its own stream: the producer's work must be done
+        torch.cuda.current_stream().synchronize()
         _check(lib.gc_apply_batch_dev(self._h, ins_src.data_ptr(), ins_dst.data_ptr(), ins_src.numel(),
                                       del_src.data_ptr(), del_dst.data_ptr(), del_src.numel(),
                                       out.ctypes.data, ctypes.byref(st) if stats else None))

@@ -192,3 +192,22 @@ def test_pool_matches_separate():
         oracle_apply(E, ns[i], *bs[i])
         es, ed = esorted(E)
         assert got[i] == native.static_counts(ns[i], es, ed)
+
+
+def test_device_arrays_match_host_arrays():
+    say("case device-array entry point")
+    import torch
+    n, s, d, samp = rmat_graph(10, 8, 21)
+    bs = rmat_batches(n, s, d, samp, [30, 300], 22)
+    with G(n, s, d) as a, G(n, s, d) as b:
+        for bt in bs:
+            want = a.apply_batch(*bt)
+            t = [torch.as_tensor(np.asarray(x, np.int32)).cuda() for x in bt]
+            assert b.apply_batch_dev(*t) == want
+        from paper_2308_14493_amd.graphlet4 import GraphletError
+        t = [torch.tensor([0], dtype=torch.int32).cuda(), torch.tensor([n], dtype=torch.int32).cuda(),
+             torch.zeros(0, dtype=torch.int32).cuda(), torch.zeros(0, dtype=torch.int32).cuda()]
+        before = b.counts()
+        with pytest.raises(GraphletError):
+            b.apply_batch_dev(*t)
+        assert b.counts() == before == b.recount()

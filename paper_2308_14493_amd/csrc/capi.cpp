@@ -104,7 +104,6 @@ void to_int64(const i128 I[11], int64_t out[11], uint32_t* mask) {
 constexpr int TRI_SMALL = 64;
 constexpr int C4_SMALL = 256;
 constexpr int C4_MID = 4096;
-constexpr int TL_LDS_MAX = 2048;
 
 }  // namespace
 
@@ -137,7 +136,7 @@ struct gc_graph {
   DevBuf roff, rcol, rlow, dB, dA, t, level, rlist, rlen, lists;
   DevBuf c4_dense, c4_touch, tri_scratch;
   int32_t c4_slots = 0, tri_slots = 0;
-  int64_t tri_slot_words = 0;
+  int64_t tri_cap = 0;
 
   void* pin = nullptr;
   size_t pin_cap = 0;
@@ -254,19 +253,18 @@ void run_count(gc_graph* G, int radius, long long* state_d, BatchWork& W, std::v
   A.slots = std::max(1, G->c4_slots);
   // triangles above the LDS tier: scratch slots in global memory
   const int64_t maxdp = (int64_t)hc[C_MAXDP];
-  if (maxdp > TL_LDS_MAX) {
+  if (maxdp > tri_lds_max()) {
     if (maxdp > 32767) raise(GC_EINVAL, "oriented out-degree %lld exceeds the supported 32767", (long long)maxdp);
-    int64_t words = 16 * maxdp;
-    int32_t slots = 256;
-    if (words > G->tri_slot_words || slots > G->tri_slots) {
+    const int32_t slots = 256;
+    if (maxdp > G->tri_cap || slots > G->tri_slots) {
       G->tri_scratch.release();
-      G->tri_scratch.ensure((size_t)(words * slots) * sizeof(uint32_t));
-      G->tri_slot_words = words;
+      G->tri_scratch.ensure((size_t)(tri_scratch_words64(maxdp) * slots) * sizeof(unsigned long long));
+      G->tri_cap = maxdp;
       G->tri_slots = slots;
     }
   }
-  A.tri_scratch = G->tri_scratch.as<uint32_t>();
-  A.tri_slot_words = G->tri_slot_words;
+  A.tri_scratch = G->tri_scratch.as<unsigned long long>();
+  A.tri_cap = G->tri_cap;
   A.tri_slots = std::max(1, G->tri_slots);
   launch_count(A, hc.data(), s, timed ? &G->ev[2] : nullptr);
   launch_combine(G->sig.as<unsigned long long>(), state_d, G->k, s);

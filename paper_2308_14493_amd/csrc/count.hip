@@ -172,115 +172,187 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
 }
 
 // ------------------------------------------------------ triangles, tier L
-// One workgroup per vertex u; N+(u) in a hash; each wave takes a v in N+(u),
-// finds the triangle mates w in N+(v) & N+(u) (marks + list), then the
-// 4-cliques through (u, v, w) by probing N+(w) against the marks.
-constexpr int TL_MAX = 2048;   // out-degree handled from LDS
+// One workgroup per vertex u with out-degree above 64.  N+(u) goes into a
+// hash (slot = position in the sorted suffix, i.e. id order).  Each wave
+// takes a v = N+(u)[i] and probes N+(v): a hit j is a triangle (u, v, w_j);
+// it updates t of the three edges and records the edge v -> w_j as bit j of
+// row i of the bit matrix E (the graph induced on N+(u), union view).
+// 4-cliques u < v_i < v_j < v_k then follow from AND-popcounts of rows:
+//   K4_x(u) = sum_{i in P_x} sum_{j in E[i] & P_x} |E[i] & E[j] & P_x|
+// with P_x the slots whose edge from u exists in version x.  Edges among
+// N+(u) that exist in one version only are few; the triangles of E that
+// contain such an edge absent from version x are removed from K4_x one by
+// one (each once, at its first such edge in list order).  If the list
+// overflows, the matrix is rebuilt per version instead.
+constexpr int TL_MAX = 512;    // out-degree handled from LDS
+constexpr int TL_W = TL_MAX / 64;
 constexpr int TL_WAVES = 4;
+constexpr int TL_EXC = 512;    // version-specific edges tracked per vertex
 
 struct TriL {
-  uint32_t* ids;      // [dp]
-  int32_t* hkey;      // [H]
-  int16_t* hval;      // [H]
-  uint32_t* tuc;      // [dp] packed 16-bit halves (b low, a high)
-  uint8_t* mark;      // [4][dp]
-  int16_t* lst;       // [4][dp]
+  unsigned long long* E;   // [dp][W] row bitsets
+  unsigned long long* P;   // [2][W] slot masks of versions b, a
+  uint32_t* ids;           // [dp]
+  int32_t* hkey;           // [H]
+  int16_t* hval;           // [H]
+  uint32_t* tuc;           // [dp] packed 16-bit halves (b low, a high)
+  uint32_t* exc;           // [TL_EXC] i << 17 | j << 2 | flags >> 30
+  int32_t* nexc;           // [1]
+  int32_t W;               // words per row
 };
 
-__device__ void tri_large_vertex(const CountArgs& A, const TriL& S, int32_t u, int64_t ub, int32_t dp, int32_t dstride,
+__device__ __forceinline__ bool Ebit(const TriL& S, int32_t p, int32_t q) {  // edge between slots p != q
+  if (p > q) { int32_t t = p; p = q; q = t; }
+  return (S.E[(int64_t)p * S.W + (q >> 6)] >> (q & 63)) & 1ull;
+}
+
+// set E bits for every probe hit of N+(v_i) present in version `only`
+// (only = 0: union, and also do the triangle bookkeeping)
+__device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL& S, uint32_t hmask, int shift,
+                                                int32_t i, int only, int32_t dBu, int32_t dAu, int64_t& tb_,
+                                                int64_t& ta_, int64_t& pb_, int64_t& pa_) {
+  const RegionDev& R = A.R;
+  const int l = lane_id();
+  const uint32_t xi = S.ids[i];
+  const uint32_t v = xi & GC_ID, fi = xi & GC_FLAGS;
+  const int64_t sb = R.roff[v] + R.rlow[v];
+  const int32_t sl = (int32_t)(R.roff[v + 1] - sb);
+  const int32_t dBv = R.dB[v], dAv = R.dA[v];
+  uint32_t acc_i = 0;
+  unsigned long long* Ei = S.E + (int64_t)i * S.W;
+  for (int32_t k0 = 0; k0 < sl; k0 += 64) {
+    const int32_t k = k0 + l;
+    if (k >= sl) break;
+    const uint32_t y = R.rcol[sb + k];
+    const int j = lookup_slot(S.hkey, S.hval, hmask, shift, y & GC_ID);
+    if (j < 0) continue;
+    const uint32_t fy = y & GC_FLAGS;
+    if (only) {
+      if (!(fy & (only == 1 ? GC_F_NEW : GC_F_DEL))) atomicOr(&Ei[j >> 6], 1ull << (j & 63));
+      continue;
+    }
+    atomicOr(&Ei[j >> 6], 1ull << (j & 63));
+    if (fy) {
+      const int32_t p = atomicAdd(S.nexc, 1);
+      if (p < TL_EXC) S.exc[p] = ((uint32_t)i << 17) | ((uint32_t)j << 2) | (fy >> 30);
+    }
+    const uint32_t ab = fi | (S.ids[j] & GC_FLAGS) | fy;
+    const uint32_t xb = !(ab & GC_F_NEW), xa = !(ab & GC_F_DEL);
+    if (xb | xa) {
+      atomicAdd(&R.t[sb + k], pack2(xb, xa));
+      atomicAdd(&S.tuc[j], xb | (xa << 16));
+      acc_i += xb | (xa << 16);
+      const uint32_t wv = y & GC_ID;
+      tb_ += xb; ta_ += xa;
+      if (xb) pb_ += (int64_t)dBu + dBv + R.dB[wv] - 6;
+      if (xa) pa_ += (int64_t)dAu + dAv + R.dA[wv] - 6;
+    }
+  }
+  if (!only) {
+    acc_i = (uint32_t)wave_sum32((int32_t)acc_i);
+    if (l == 0 && acc_i) atomicAdd(&S.tuc[i], acc_i);
+  }
+}
+
+// sum over i in mask, j in E[i] & mask of |E[i] & E[j] & mask|  (one wave's rows)
+__device__ __forceinline__ int64_t k4_rows(const TriL& S, const unsigned long long* mask, int32_t dp) {
+  const int w = threadIdx.x >> 6, l = lane_id();
+  int64_t cnt = 0;
+  for (int32_t i = w; i < dp; i += TL_WAVES) {
+    if (!((mask[i >> 6] >> (i & 63)) & 1ull)) continue;
+    const unsigned long long* Ei = S.E + (int64_t)i * S.W;
+    for (int32_t w0 = i >> 6; w0 < S.W; ++w0) {
+      const unsigned long long m = Ei[w0] & mask[w0];
+      if (!m) continue;
+      if ((m >> l) & 1ull) {
+        const int32_t j = w0 * 64 + l;
+        const unsigned long long* Ej = S.E + (int64_t)j * S.W;
+        for (int32_t q = j >> 6; q < S.W; ++q) cnt += __popcll(Ei[q] & Ej[q] & mask[q]);
+      }
+    }
+  }
+  return cnt;
+}
+
+__device__ void tri_large_vertex(const CountArgs& A, const TriL& S, int32_t u, int64_t ub, int32_t dp,
                                  int64_t& tb_, int64_t& ta_, int64_t& pb_, int64_t& pa_, int64_t& kb_, int64_t& ka_) {
   const RegionDev& R = A.R;
-  const int w = threadIdx.x >> 6, l = lane_id();
+  const int w = threadIdx.x >> 6;
+  const int32_t W = S.W;
   int H = 1;
   while (H < 2 * dp) H <<= 1;
   const uint32_t hmask = (uint32_t)H - 1u;
   const int shift = 32 - log2i((uint32_t)H);
   for (int32_t k = threadIdx.x; k < dp; k += blockDim.x) { S.ids[k] = R.rcol[ub + k]; S.tuc[k] = 0; }
   for (int32_t k = threadIdx.x; k < H; k += blockDim.x) S.hkey[k] = -1;
-  for (int32_t k = threadIdx.x; k < TL_WAVES * dstride; k += blockDim.x) S.mark[k] = 0;
+  for (int64_t k = threadIdx.x; k < (int64_t)dp * W; k += blockDim.x) S.E[k] = 0ull;
+  for (int32_t k = threadIdx.x; k < 2 * W; k += blockDim.x) S.P[k] = 0ull;
+  if (threadIdx.x == 0) *S.nexc = 0;
   __syncthreads();
   for (int32_t k = threadIdx.x; k < dp; k += blockDim.x) {
-    const uint32_t id = S.ids[k] & GC_ID;
+    const uint32_t x = S.ids[k];
+    const uint32_t id = x & GC_ID;
     uint32_t h = hash32(id) >> shift;
     while (atomicCAS(&S.hkey[h], -1, (int32_t)id) != -1) h = (h + 1) & hmask;
     S.hval[h] = (int16_t)k;
+    if (!(x & GC_F_NEW)) atomicOr(&S.P[k >> 6], 1ull << (k & 63));
+    if (!(x & GC_F_DEL)) atomicOr(&S.P[W + (k >> 6)], 1ull << (k & 63));
   }
   __syncthreads();
   const int32_t dBu = R.dB[u], dAu = R.dA[u];
-  uint8_t* mark = S.mark + w * dstride;
-  int16_t* lst = S.lst + w * dstride;
-  for (int32_t i = w; i < dp; i += TL_WAVES) {
-    const uint32_t xi = S.ids[i];
-    const uint32_t v = xi & GC_ID, fi = xi & GC_FLAGS;
-    const int64_t sb = R.roff[v] + R.rlow[v];
-    const int32_t sl = (int32_t)(R.roff[v + 1] - sb);
-    const int32_t dBv = R.dB[v], dAv = R.dA[v];
-    uint32_t acc_i = 0;
-    int32_t nl = 0;
-    for (int32_t k0 = 0; k0 < sl; k0 += 64) {
-      const int32_t k = k0 + l;
-      int j = -1;
-      uint32_t y = 0;
-      if (k < sl) { y = R.rcol[sb + k]; j = lookup_slot(S.hkey, S.hval, hmask, shift, y & GC_ID); }
-      const uint64_t m = __ballot(j >= 0);
-      if (j >= 0) {
-        const uint32_t fy = y & GC_FLAGS;
-        mark[j] = (uint8_t)(1u + (fy >> 30));
-        lst[nl + __popcll(m & lanemask_lt())] = (int16_t)j;
-        const uint32_t ab = fi | (S.ids[j] & GC_FLAGS) | fy;
-        const uint32_t xb = !(ab & GC_F_NEW), xa = !(ab & GC_F_DEL);
-        if (xb | xa) {
-          atomicAdd(&R.t[sb + k], pack2(xb, xa));
-          atomicAdd(&S.tuc[j], xb | (xa << 16));
-          acc_i += xb | (xa << 16);
-          const uint32_t wv = y & GC_ID;
-          tb_ += xb; ta_ += xa;
-          if (xb) pb_ += (int64_t)dBu + dBv + R.dB[wv] - 6;
-          if (xa) pa_ += (int64_t)dAu + dAv + R.dA[wv] - 6;
-        }
-      }
-      nl += __popcll(m);
-    }
-    acc_i = (uint32_t)wave_sum32((int32_t)acc_i);
-    if (l == 0 && acc_i) atomicAdd(&S.tuc[i], acc_i);
-    wave_sync();
-    // 4-cliques through (u, v, w) with w a triangle mate: probe N+(w)
-    for (int32_t g0 = 0; g0 < nl; g0 += 64) {
-      const int32_t q = g0 + l;
-      int32_t jq = -1;
-      int64_t sb2 = 0;
-      int32_t sl2 = 0;
-      if (q < nl) {
-        jq = lst[q];
-        const uint32_t vj = S.ids[jq] & GC_ID;
-        sb2 = R.roff[vj] + R.rlow[vj];
-        sl2 = (int32_t)(R.roff[vj + 1] - sb2);
-      }
-      const int32_t incl = wave_incl_scan32(sl2);
-      const int32_t tot = __shfl(incl, 63);
-      const int32_t excl = incl - sl2;
-      for (int32_t base = 0; base < tot; base += 64) {
-        const int32_t idx = base + l;
-        const int s = seg_of(excl, idx);
-        const int64_t sbs = __shfl(sb2, s);
-        const int32_t exs = __shfl(excl, s);
-        const int32_t js = __shfl(jq, s);
-        if (idx < tot) {
-          const uint32_t z = R.rcol[sbs + (idx - exs)];
-          const int kk = lookup_slot(S.hkey, S.hval, hmask, shift, z & GC_ID);
-          if (kk >= 0 && mark[kk]) {
-            const uint32_t ab = fi | (S.ids[js] & GC_FLAGS) | (S.ids[kk] & GC_FLAGS) |
-                                ((uint32_t)(mark[js] - 1u) << 30) | ((uint32_t)(mark[kk] - 1u) << 30) |
-                                (z & GC_FLAGS);
-            kb_ += !(ab & GC_F_NEW);
-            ka_ += !(ab & GC_F_DEL);
+  for (int32_t i = w; i < dp; i += TL_WAVES) tri_large_probe(A, S, hmask, shift, i, 0, dBu, dAu, tb_, ta_, pb_, pa_);
+  __syncthreads();
+  const int32_t ne = *S.nexc;
+  const unsigned long long* Pb = S.P;
+  const unsigned long long* Pa = S.P + W;
+  if (ne <= TL_EXC) {
+    bool same = true;
+    for (int32_t q = 0; q < W; ++q) same &= Pb[q] == Pa[q];
+    const int64_t cb = k4_rows(S, Pb, dp);
+    const int64_t ca = same ? cb : k4_rows(S, Pa, dp);
+    kb_ += cb;
+    ka_ += ca;
+    // triangles of E (inside P_x) holding an edge absent from version x
+    const int l = lane_id();
+    for (int32_t e = w; e < ne; e += TL_WAVES) {
+      const uint32_t ex = S.exc[e];
+      const int32_t i = (int32_t)(ex >> 17), j = (int32_t)((ex >> 2) & 0x7FFF);
+      const uint32_t fl = (ex & 3u) << 30;
+      for (int x = 0; x < 2; ++x) {
+        const uint32_t absent = x == 0 ? GC_F_NEW : GC_F_DEL;
+        if (!(fl & absent)) continue;
+        const unsigned long long* Px = x == 0 ? Pb : Pa;
+        if (!((Px[i >> 6] >> (i & 63)) & 1ull) || !((Px[j >> 6] >> (j & 63)) & 1ull)) continue;
+        int64_t sub = 0;
+        for (int32_t k = l; k < dp; k += 64) {
+          if (k == i || k == j || !((Px[k >> 6] >> (k & 63)) & 1ull)) continue;
+          if (!Ebit(S, i, k) || !Ebit(S, j, k)) continue;
+          // count once: skip if an earlier listed edge of this triangle is absent from x
+          bool first = true;
+          for (int32_t f = 0; f < e && first; ++f) {
+            const uint32_t ef = S.exc[f];
+            if (!(((ef & 3u) << 30) & absent)) continue;
+            const int32_t fi = (int32_t)(ef >> 17), fj = (int32_t)((ef >> 2) & 0x7FFF);
+            if ((fi == i && fj == k) || (fi == k && fj == i) || (fi == j && fj == k) || (fi == k && fj == j))
+              first = false;
           }
+          sub += first;
         }
+        if (x == 0) kb_ -= sub; else ka_ -= sub;
       }
     }
-    wave_sync();
-    for (int32_t q = l; q < nl; q += 64) mark[lst[q]] = 0;
-    wave_sync();
+  } else {
+    // too many version-specific edges: rebuild E per version and count
+    for (int x = 0; x < 2; ++x) {
+      __syncthreads();
+      for (int64_t k = threadIdx.x; k < (int64_t)dp * W; k += blockDim.x) S.E[k] = 0ull;
+      __syncthreads();
+      int64_t d0 = 0;
+      for (int32_t i = w; i < dp; i += TL_WAVES) tri_large_probe(A, S, hmask, shift, i, x + 1, dBu, dAu, d0, d0, d0, d0);
+      __syncthreads();
+      const int64_t c = k4_rows(S, x == 0 ? Pb : Pa, dp);
+      if (x == 0) kb_ += c; else ka_ += c;
+    }
   }
   __syncthreads();
   for (int32_t k = threadIdx.x; k < dp; k += blockDim.x) {
@@ -288,6 +360,13 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL& S, int32_t u, i
     if (c) atomicAdd(&R.t[ub + k], pack2(c & 0xFFFFu, c >> 16));
   }
   __syncthreads();
+}
+
+// global-scratch slot layout (u64 words): E [cap*W] | P [2W] | then u32 words:
+// ids [cap] | tuc [cap] | hkey [4 cap] | hval [2 cap] | exc [TL_EXC] | nexc [2]
+__host__ __device__ inline int64_t tri_slot_words64(int64_t cap) {
+  const int64_t W = (cap + 63) / 64;
+  return cap * W + 2 * W + (cap + cap + 4 * cap + 2 * cap + TL_EXC + 2 + 1) / 2 + 8;
 }
 
 template <bool GLOBAL>
@@ -298,28 +377,31 @@ __global__ __launch_bounds__(256) void k_tri_large(CountArgs A) {
   int cur_g = -1;
   int64_t tb_ = 0, ta_ = 0, pb_ = 0, pa_ = 0, kb_ = 0, ka_ = 0;
   TriL S;
-  int32_t dstride;
   if constexpr (GLOBAL) {
-    // slot layout: ids | tuc | hkey | hval | mark | lst, sized by tri_slot_words
-    const int64_t W = A.tri_slot_words;
-    uint32_t* base = A.tri_scratch + (int64_t)blockIdx.x * W;
-    const int32_t cap = (int32_t)(W / 16);  // out-degree capacity of a slot
-    dstride = cap;
-    S.ids = base;
-    S.tuc = base + cap;
-    S.hkey = (int32_t*)(base + 2 * cap);
-    S.hval = (int16_t*)(base + 2 * cap + 4 * cap);
-    S.mark = (uint8_t*)(base + 2 * cap + 4 * cap + 2 * cap);
-    S.lst = (int16_t*)(base + 2 * cap + 4 * cap + 2 * cap + cap);
+    const int64_t cap = A.tri_cap;
+    const int64_t W = (cap + 63) / 64;
+    unsigned long long* base = (unsigned long long*)A.tri_scratch + (int64_t)blockIdx.x * tri_slot_words64(cap);
+    S.W = (int32_t)W;
+    S.E = base;
+    S.P = base + cap * W;
+    uint32_t* u32 = (uint32_t*)(S.P + 2 * W);
+    S.ids = u32;
+    S.tuc = u32 + cap;
+    S.hkey = (int32_t*)(u32 + 2 * cap);
+    S.hval = (int16_t*)(u32 + 6 * cap);
+    S.exc = u32 + 8 * cap;
+    S.nexc = (int32_t*)(u32 + 8 * cap + TL_EXC);
   } else {
+    __shared__ unsigned long long E[TL_MAX * TL_W];
+    __shared__ unsigned long long P[2 * TL_W];
     __shared__ uint32_t ids[TL_MAX];
     __shared__ uint32_t tuc[TL_MAX];
     __shared__ int32_t hkey[2 * TL_MAX];
     __shared__ int16_t hval[2 * TL_MAX];
-    __shared__ uint8_t mark[TL_WAVES * TL_MAX];
-    __shared__ int16_t lst[TL_WAVES * TL_MAX];
-    S.ids = ids; S.tuc = tuc; S.hkey = hkey; S.hval = hval; S.mark = mark; S.lst = lst;
-    dstride = TL_MAX;
+    __shared__ uint32_t exc[TL_EXC];
+    __shared__ int32_t nexc;
+    S.E = E; S.P = P; S.ids = ids; S.tuc = tuc; S.hkey = hkey; S.hval = hval; S.exc = exc; S.nexc = &nexc;
+    S.W = TL_W;
   }
   for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
     const int32_t u = list[it];
@@ -331,7 +413,8 @@ __global__ __launch_bounds__(256) void k_tri_large(CountArgs A) {
       if (cur_g >= 0) { flush2(A.sig, cur_g, SG_T, tb_, ta_); flush2(A.sig, cur_g, SG_PAW, pb_, pa_); flush2(A.sig, cur_g, SG_K4, kb_, ka_); }
       cur_g = g;
     }
-    tri_large_vertex(A, S, u, ub, dp, dstride, tb_, ta_, pb_, pa_, kb_, ka_);
+    if constexpr (!GLOBAL) S.W = (dp + 63) / 64;
+    tri_large_vertex(A, S, u, ub, dp, tb_, ta_, pb_, pa_, kb_, ka_);
   }
   if (cur_g >= 0) { flush2(A.sig, cur_g, SG_T, tb_, ta_); flush2(A.sig, cur_g, SG_PAW, pb_, pa_); flush2(A.sig, cur_g, SG_K4, kb_, ka_); }
 }
@@ -590,6 +673,9 @@ inline unsigned cap_grid(int64_t want, unsigned cap) {
 }
 
 }  // namespace
+
+int64_t tri_scratch_words64(int64_t cap) { return tri_slot_words64(cap); }
+int32_t tri_lds_max() { return TL_MAX; }
 
 void launch_count(const CountArgs& A, const unsigned long long* hc, hipStream_t s, hipEvent_t* ev) {
   const int64_t E = (int64_t)hc[C_ER];

@@ -91,9 +91,11 @@ struct CountArgs {
   int64_t N;
   int32_t slots;                  // workgroups of the large 4-cycle tier
   int32_t tri_slots;              // workgroups of the global-scratch triangle tier
-  uint32_t* tri_scratch;          // [slots][tri_slot_words] for out-degrees above the LDS tier
-  int64_t tri_slot_words;
+  unsigned long long* tri_scratch;  // [tri_slots][tri_scratch_words64(tri_cap)] above the LDS tier
+  int64_t tri_cap;                  // out-degree capacity of a scratch slot
 };
 void launch_count(const CountArgs& A, const unsigned long long* host_counts, hipStream_t s,
                   hipEvent_t* ev /* nullable: 6 events between the kernel phases */);
+int64_t tri_scratch_words64(int64_t cap);  // u64 words of one triangle scratch slot
+int32_t tri_lds_max();                      // largest out-degree of the LDS triangle tier
 void launch_combine(const unsigned long long* sig, long long* state, int32_t k, hipStream_t s);

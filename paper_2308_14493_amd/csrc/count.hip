@@ -592,12 +592,60 @@ __global__ __launch_bounds__(256) void k_c4_mid(CountArgs A) {
   if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_);
 }
 
+// Large tier: each hub v is split into work items by the rank of the
+// opposite vertex w.  Items 0..K-1 cover the windows [v-(k+1)WIN, v-kWIN),
+// counted with dense LDS counters; the hits concentrate there because the
+// ids are a degree order and a wedge reaches w with odds growing with deg w.
+// Item K covers w < v - K*WIN with dense counters in global memory.  Rows
+// are sorted, so each item's slice of a row is found by binary search.
+constexpr int C4W_WIN = 8192;
+constexpr int C4W_K = 8;
+
+template <class F>
+__device__ __forceinline__ void c4_group_range(const RegionDev& R, int64_t rb, int32_t nlow, int32_t g0,
+                                               uint32_t lo, uint32_t hi, F f) {
+  const int l = lane_id();
+  const int32_t q = g0 + l;
+  int64_t sb = 0;
+  int32_t sl = 0;
+  uint32_t fvu = 0;
+  if (q < nlow) {
+    const uint32_t x = R.rcol[rb + q];
+    fvu = x & GC_FLAGS;
+    const uint32_t u = x & GC_ID;
+    const int64_t b = R.roff[u];
+    const int32_t L = (int32_t)(R.roff[u + 1] - b);
+    const int32_t p0 = lo ? lower_bound_id(R.rcol + b, L, lo) : 0;
+    const int32_t p1 = lower_bound_id(R.rcol + b, L, hi);
+    sb = b + p0;
+    sl = p1 - p0;
+  }
+  const int32_t incl = wave_incl_scan32(sl);
+  const int32_t tot = __shfl(incl, 63);
+  const int32_t excl = incl - sl;
+  for (int32_t base = 0; base < tot; base += 64) {
+    const int32_t idx = base + l;
+    const int s = seg_of(excl, idx);
+    const int64_t sbs = __shfl(sb, s);
+    const int32_t exs = __shfl(excl, s);
+    const uint32_t fs = __shfl(fvu, s);
+    if (idx < tot) {
+      const uint32_t y = R.rcol[sbs + (idx - exs)];
+      const uint32_t ab = fs | (y & GC_FLAGS);
+      const uint32_t xb = !(ab & GC_F_NEW), xa = !(ab & GC_F_DEL);
+      if (xb | xa) f(y & GC_ID, xb, xa);
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_c4_large(CountArgs A, unsigned long long* qhead) {
+  __shared__ unsigned long long win[C4W_WIN];
   __shared__ int64_t s_item;
   __shared__ int32_t s_nt;
   const int w = threadIdx.x >> 6;
   const RegionDev& R = A.R;
   const int64_t n = (int64_t)A.c[C_LIST0 + L_C4_L];
+  const int64_t items = n * (C4W_K + 1);
   const int32_t* list = A.lists + L_C4_L * A.list_stride;
   unsigned long long* cnt = A.c4_dense + (int64_t)blockIdx.x * A.N;
   int32_t* touch = A.c4_touch + (int64_t)blockIdx.x * A.N;
@@ -607,27 +655,49 @@ __global__ __launch_bounds__(256) void k_c4_large(CountArgs A, unsigned long lon
     if (threadIdx.x == 0) { s_item = (int64_t)atomicAdd(qhead, 1ull); s_nt = 0; }
     __syncthreads();
     const int64_t item = s_item;
-    if (item >= n) break;
-    const int32_t v = list[item];
+    if (item >= items) break;
+    const int32_t v = list[item / (C4W_K + 1)];
+    const int k = (int)(item % (C4W_K + 1));
     const int g = A.gid[v];
     if (g != cur_g) { if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_); cur_g = g; }
     const int64_t rb = R.roff[v];
     const int32_t nlow = R.rlow[v];
-    for (int32_t g0 = w * 64; g0 < nlow; g0 += 64 * 4)
-      c4_group(R, (uint32_t)v, rb, nlow, g0, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
-        const unsigned long long old = atomicAdd(&cnt[wid], pack2(xb, xa));
-        if (old == 0ull) touch[atomicAdd(&s_nt, 1)] = (int32_t)wid;
-      });
-    __syncthreads();
-    const int32_t nt = s_nt;
-    for (int32_t k = threadIdx.x; k < nt; k += blockDim.x) {
-      const int32_t wid = touch[k];
-      const unsigned long long c = cnt[wid];
-      cnt[wid] = 0ull;
-      cb_ += c2((int64_t)(c & 0xFFFFFFFFull));
-      ca_ += c2((int64_t)(c >> 32));
+    if (k < C4W_K) {
+      const int64_t hi64 = (int64_t)v - (int64_t)k * C4W_WIN;
+      if (hi64 <= 0) continue;  // uniform: nothing below this window
+      const int64_t lo64 = hi64 - C4W_WIN > 0 ? hi64 - C4W_WIN : 0;
+      const uint32_t lo = (uint32_t)lo64, hi = (uint32_t)hi64;
+      for (int s = threadIdx.x; s < C4W_WIN; s += blockDim.x) win[s] = 0ull;
+      __syncthreads();
+      for (int32_t g0 = w * 64; g0 < nlow; g0 += 64 * 4)
+        c4_group_range(R, rb, nlow, g0, lo, hi, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
+          atomicAdd(&win[wid - lo], pack2(xb, xa));
+        });
+      __syncthreads();
+      for (int s = threadIdx.x; s < C4W_WIN; s += blockDim.x) {
+        const unsigned long long c = win[s];
+        if (c) { cb_ += c2((int64_t)(c & 0xFFFFFFFFull)); ca_ += c2((int64_t)(c >> 32)); }
+      }
+      __syncthreads();
+    } else {
+      const int64_t hi64 = (int64_t)v - (int64_t)C4W_K * C4W_WIN;
+      if (hi64 <= 0) continue;
+      for (int32_t g0 = w * 64; g0 < nlow; g0 += 64 * 4)
+        c4_group_range(R, rb, nlow, g0, 0u, (uint32_t)hi64, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
+          const unsigned long long old = atomicAdd(&cnt[wid], pack2(xb, xa));
+          if (old == 0ull) touch[atomicAdd(&s_nt, 1)] = (int32_t)wid;
+        });
+      __syncthreads();
+      const int32_t nt = s_nt;
+      for (int32_t q = threadIdx.x; q < nt; q += blockDim.x) {
+        const int32_t wid = touch[q];
+        const unsigned long long c = cnt[wid];
+        cnt[wid] = 0ull;
+        cb_ += c2((int64_t)(c & 0xFFFFFFFFull));
+        ca_ += c2((int64_t)(c >> 32));
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_);
 }

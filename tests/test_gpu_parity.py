@@ -211,3 +211,24 @@ def test_device_arrays_match_host_arrays():
         with pytest.raises(GraphletError):
             b.apply_batch_dev(*t)
         assert b.counts() == before == b.recount()
+
+
+@pytest.mark.parametrize("scale,ef,seed", [(17, 8, 31)])
+def test_rmat_large_ids(scale, ef, seed):
+    """n above the rank windows of the large 4-cycle tier (8 x 8192), so
+    hub work items cover every window and the global tail."""
+    say("case rmat scale=%d ef=%d seed=%d (windows + tail)" % (scale, ef, seed))
+    n, s, d, samp = rmat_graph(scale, ef, seed)
+    sizes = [50, 5000]
+    batches = rmat_batches(n, s, d, samp, sizes, seed + 1)
+    E = edge_set(s, d)
+    with G(n, s, d) as gr:
+        got0, st = gr.counts(), None
+        assert got0 == native.static_counts(n, s, d)
+        for b in batches:
+            got, st = gr.apply_batch(*b, stats=True)
+            oracle_apply(E, n, *b)
+            es, ed = esorted(E)
+            say("  tiers c4 large=%d entries=%d" % (st["tier_c4_large"], st["c4_entries_large"]))
+            assert st["tier_c4_large"] > 0
+            assert got == native.static_counts(n, es, ed)

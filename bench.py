@@ -114,9 +114,9 @@ def main():
             lat.append((t2 - t1) * 1e3)
             offered += b[0].size + b[2].size
             stats.append(st)
-        log("step %d: batch %d updates, %.2f ms (tri %.2f edge %.2f c4 %.2f/%.2f/%.2f prep %.2f fin %.2f) region_e=%d"
+        log("step %d: batch %d updates, %.2f ms (tri %.2f edge %.2f c4 %.2f/%.2f/%.2f prep %.2f fin %.2f) region_e=%d c4_tail=%d/%d"
             % (i, b[0].size + b[2].size, (t2 - t1) * 1e3, st["ms_tri"], st["ms_edge"], st["ms_c4_small"],
-               st["ms_c4_mid"], st["ms_c4_large"], st["ms_prepare"], st["ms_finish"], st["region_entries"]))
+               st["ms_c4_mid"], st["ms_c4_large"], st["ms_prepare"], st["ms_finish"], st["region_entries"], st["c4_tail_wedges"], st["wedges"]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - tstart
     value = offered / elapsed

@@ -102,6 +102,7 @@ typedef struct {
   int64_t region_vertices, region_entries;  /* region size (entries = 2 x edges) */
   int64_t wedges;                    /* 4-cycle wedges enumerated */
   int64_t c4_entries_small, c4_entries_mid, c4_entries_large;  /* adjacency entries read per 4-cycle tier */
+  int64_t c4_tail_wedges;            /* wedges of the large tier counted in global memory */
   int64_t max_out_degree;
   int64_t tier_tri_small, tier_tri_large, tier_c4_small, tier_c4_mid, tier_c4_large;  /* vertices per tier */
   uint32_t overflow_mask;            /* classes whose count left int64 */

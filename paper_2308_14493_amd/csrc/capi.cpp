@@ -236,9 +236,9 @@ void run_count(gc_graph* G, int radius, long long* state_d, BatchWork& W, std::v
   const int64_t ncl = (int64_t)hc[C_LIST0 + L_C4_L];
   if (ncl > 0) {
     int64_t per = N * (int64_t)(sizeof(unsigned long long) + sizeof(int32_t));
-    int64_t budget = (int64_t)32 << 30;
-    int64_t slots = std::max<int64_t>(1, std::min<int64_t>(1024, budget / std::max<int64_t>(per, 1)));
-    slots = std::min(slots, std::max<int64_t>(ncl, 1));
+    // one resident 1024-thread block per CU is enough to fill the chip
+    int64_t budget = (int64_t)16 << 30;
+    int64_t slots = std::max<int64_t>(1, std::min<int64_t>(256, budget / std::max<int64_t>(per, 1)));
     if (slots > G->c4_slots) {
       G->c4_dense.release();
       G->c4_touch.release();
@@ -517,6 +517,7 @@ void fill_stats(gc_graph* G, gc_batch_stats* st, const std::vector<unsigned long
   st->c4_entries_small = (int64_t)hb[BS_C4_S];
   st->c4_entries_mid = (int64_t)hb[BS_C4_M];
   st->c4_entries_large = (int64_t)hb[BS_C4_L];
+  st->c4_tail_wedges = (int64_t)hb[BS_TRIPROBE];
   st->max_out_degree = (int64_t)hc[C_MAXDP];
   st->tier_tri_small = (int64_t)hc[C_LIST0 + L_TRI_S];
   st->tier_tri_large = (int64_t)hc[C_LIST0 + L_TRI_L];

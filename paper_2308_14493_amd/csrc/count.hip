@@ -598,51 +598,69 @@ __global__ __launch_bounds__(256) void k_c4_mid(CountArgs A) {
 // ids are a degree order and a wedge reaches w with odds growing with deg w.
 // Item K covers w < v - K*WIN with dense counters in global memory.  Rows
 // are sorted, so each item's slice of a row is found by binary search.
-constexpr int C4W_WIN = 8192;
-constexpr int C4W_K = 8;
+// The wedges of an item are spread over all 1024 threads of the block: one
+// lower neighbour u per thread, a block scan of the slice lengths, then a
+// flat walk with a binary search of each index in the scanned lengths.
+constexpr int C4W_WIN = 16384;
+constexpr int C4W_K = 16;
+constexpr int C4W_T = 1024;
 
+struct C4Chunk {
+  int64_t sb[C4W_T];
+  int32_t pre[C4W_T + 1];
+  uint32_t fl[C4W_T];
+  int32_t wsum[C4W_T / 64];
+};
+
+// walk the wedges (v, u, w) with w in [lo, hi) for u = row v positions
+// [0, nlow); f(w, add_b, add_a) per wedge present in some version
 template <class F>
-__device__ __forceinline__ void c4_group_range(const RegionDev& R, int64_t rb, int32_t nlow, int32_t g0,
-                                               uint32_t lo, uint32_t hi, F f) {
-  const int l = lane_id();
-  const int32_t q = g0 + l;
-  int64_t sb = 0;
-  int32_t sl = 0;
-  uint32_t fvu = 0;
-  if (q < nlow) {
-    const uint32_t x = R.rcol[rb + q];
-    fvu = x & GC_FLAGS;
-    const uint32_t u = x & GC_ID;
-    const int64_t b = R.roff[u];
-    const int32_t L = (int32_t)(R.roff[u + 1] - b);
-    const int32_t p0 = lo ? lower_bound_id(R.rcol + b, L, lo) : 0;
-    const int32_t p1 = lower_bound_id(R.rcol + b, L, hi);
-    sb = b + p0;
-    sl = p1 - p0;
-  }
-  const int32_t incl = wave_incl_scan32(sl);
-  const int32_t tot = __shfl(incl, 63);
-  const int32_t excl = incl - sl;
-  for (int32_t base = 0; base < tot; base += 64) {
-    const int32_t idx = base + l;
-    const int s = seg_of(excl, idx);
-    const int64_t sbs = __shfl(sb, s);
-    const int32_t exs = __shfl(excl, s);
-    const uint32_t fs = __shfl(fvu, s);
-    if (idx < tot) {
-      const uint32_t y = R.rcol[sbs + (idx - exs)];
-      const uint32_t ab = fs | (y & GC_FLAGS);
-      const uint32_t xb = !(ab & GC_F_NEW), xa = !(ab & GC_F_DEL);
-      if (xb | xa) f(y & GC_ID, xb, xa);
+__device__ __forceinline__ void c4_block_walk(const RegionDev& R, int64_t rb, int32_t nlow, uint32_t lo, uint32_t hi,
+                                              C4Chunk& C, F f) {
+  const int t = threadIdx.x, l = lane_id(), wv = t >> 6;
+  for (int32_t c0 = 0; c0 < nlow; c0 += C4W_T) {
+    const int32_t q = c0 + t;
+    int32_t sl = 0;
+    if (q < nlow) {
+      const uint32_t x = R.rcol[rb + q];
+      const uint32_t u = x & GC_ID;
+      const int64_t b = R.roff[u];
+      const int32_t L = (int32_t)(R.roff[u + 1] - b);
+      const int32_t p1 = lower_bound_id(R.rcol + b, L, hi);
+      const int32_t p0 = lo ? lower_bound_id(R.rcol + b, p1, lo) : 0;
+      C.sb[t] = b + p0;
+      C.fl[t] = x & GC_FLAGS;
+      sl = p1 - p0;
     }
+    const int32_t inc = wave_incl_scan32(sl);
+    if (l == 63) C.wsum[wv] = inc;
+    __syncthreads();
+    int32_t before = 0;
+    for (int k = 0; k < wv; ++k) before += C.wsum[k];
+    C.pre[t] = before + inc - sl;
+    if (t == C4W_T - 1) C.pre[C4W_T] = before + inc;
+    __syncthreads();
+    const int32_t tot = C.pre[C4W_T];
+    for (int32_t base = 0; base < tot; base += C4W_T) {
+      const int32_t idx = base + t;
+      if (idx < tot) {
+        int32_t a = 0, z = C4W_T;  // largest a with pre[a] <= idx
+        while (z - a > 1) { const int32_t m = (a + z) >> 1; if (C.pre[m] <= idx) a = m; else z = m; }
+        const uint32_t y = R.rcol[C.sb[a] + (idx - C.pre[a])];
+        const uint32_t ab = C.fl[a] | (y & GC_FLAGS);
+        const uint32_t xb = !(ab & GC_F_NEW), xa = !(ab & GC_F_DEL);
+        if (xb | xa) f(y & GC_ID, xb, xa);
+      }
+    }
+    __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(256) void k_c4_large(CountArgs A, unsigned long long* qhead) {
+__global__ __launch_bounds__(C4W_T) void k_c4_large(CountArgs A, unsigned long long* qhead) {
   __shared__ unsigned long long win[C4W_WIN];
+  __shared__ C4Chunk C;
   __shared__ int64_t s_item;
   __shared__ int32_t s_nt;
-  const int w = threadIdx.x >> 6;
   const RegionDev& R = A.R;
   const int64_t n = (int64_t)A.c[C_LIST0 + L_C4_L];
   const int64_t items = n * (C4W_K + 1);
@@ -650,8 +668,9 @@ __global__ __launch_bounds__(256) void k_c4_large(CountArgs A, unsigned long lon
   unsigned long long* cnt = A.c4_dense + (int64_t)blockIdx.x * A.N;
   int32_t* touch = A.c4_touch + (int64_t)blockIdx.x * A.N;
   int cur_g = -1;
-  int64_t cb_ = 0, ca_ = 0;
+  int64_t cb_ = 0, ca_ = 0, tail_ = 0;
   while (true) {
+    __syncthreads();  // every thread has read the previous item before it is replaced
     if (threadIdx.x == 0) { s_item = (int64_t)atomicAdd(qhead, 1ull); s_nt = 0; }
     __syncthreads();
     const int64_t item = s_item;
@@ -669,11 +688,9 @@ __global__ __launch_bounds__(256) void k_c4_large(CountArgs A, unsigned long lon
       const uint32_t lo = (uint32_t)lo64, hi = (uint32_t)hi64;
       for (int s = threadIdx.x; s < C4W_WIN; s += blockDim.x) win[s] = 0ull;
       __syncthreads();
-      for (int32_t g0 = w * 64; g0 < nlow; g0 += 64 * 4)
-        c4_group_range(R, rb, nlow, g0, lo, hi, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
-          atomicAdd(&win[wid - lo], pack2(xb, xa));
-        });
-      __syncthreads();
+      c4_block_walk(R, rb, nlow, lo, hi, C, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
+        atomicAdd(&win[wid - lo], pack2(xb, xa));
+      });
       for (int s = threadIdx.x; s < C4W_WIN; s += blockDim.x) {
         const unsigned long long c = win[s];
         if (c) { cb_ += c2((int64_t)(c & 0xFFFFFFFFull)); ca_ += c2((int64_t)(c >> 32)); }
@@ -682,12 +699,11 @@ __global__ __launch_bounds__(256) void k_c4_large(CountArgs A, unsigned long lon
     } else {
       const int64_t hi64 = (int64_t)v - (int64_t)C4W_K * C4W_WIN;
       if (hi64 <= 0) continue;
-      for (int32_t g0 = w * 64; g0 < nlow; g0 += 64 * 4)
-        c4_group_range(R, rb, nlow, g0, 0u, (uint32_t)hi64, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
-          const unsigned long long old = atomicAdd(&cnt[wid], pack2(xb, xa));
-          if (old == 0ull) touch[atomicAdd(&s_nt, 1)] = (int32_t)wid;
-        });
-      __syncthreads();
+      c4_block_walk(R, rb, nlow, 0u, (uint32_t)hi64, C, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
+        ++tail_;
+        const unsigned long long old = atomicAdd(&cnt[wid], pack2(xb, xa));
+        if (old == 0ull) touch[atomicAdd(&s_nt, 1)] = (int32_t)wid;
+      });
       const int32_t nt = s_nt;
       for (int32_t q = threadIdx.x; q < nt; q += blockDim.x) {
         const int32_t wid = touch[q];
@@ -700,6 +716,8 @@ __global__ __launch_bounds__(256) void k_c4_large(CountArgs A, unsigned long lon
     }
   }
   if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_);
+  tail_ = wave_sum64(tail_);
+  if (lane_id() == 0 && tail_) atomicAdd(&A.bstats[BS_TRIPROBE], (unsigned long long)tail_);
 }
 
 // --------------------------------------------------------------- combine
@@ -768,7 +786,7 @@ void launch_count(const CountArgs& A, const unsigned long long* hc, hipStream_t 
   if (ncm) hipLaunchKernelGGL(k_c4_mid, dim3(cap_grid(ncm, 4096)), dim3(256), 0, s, A);
   if (ev) (void)hipEventRecord(ev[4], s);
   if (ncl)
-    hipLaunchKernelGGL(k_c4_large, dim3(cap_grid(ncl, (unsigned)A.slots)), dim3(256), 0, s, A,
+    hipLaunchKernelGGL(k_c4_large, dim3(cap_grid(ncl * (C4W_K + 1), (unsigned)A.slots)), dim3(C4W_T), 0, s, A,
                        (unsigned long long*)(A.c + C_QHEAD));
   if (ev) (void)hipEventRecord(ev[5], s);
 }

@@ -31,7 +31,7 @@ class BatchStats(ctypes.Structure):
     _fields_ = [(n, _I64) for n in (
         "offered_ins", "offered_del", "eff_ins", "eff_del", "loops", "dups", "cancelled",
         "ins_existing", "del_missing", "touched_vertices", "region_vertices", "region_entries",
-        "wedges", "c4_entries_small", "c4_entries_mid", "c4_entries_large",
+        "wedges", "c4_entries_small", "c4_entries_mid", "c4_entries_large", "c4_tail_wedges",
         "max_out_degree", "tier_tri_small", "tier_tri_large", "tier_c4_small",
         "tier_c4_mid", "tier_c4_large")] + [("overflow_mask", ctypes.c_uint32)] + [
         (n, ctypes.c_float) for n in ("ms_total", "ms_prepare", "ms_tri", "ms_edge", "ms_c4_small",

@@ -173,21 +173,19 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
 
 // ------------------------------------------------------ triangles, tier L
 // One workgroup per vertex u with out-degree above 64.  N+(u) goes into a
-// hash (slot = position in the sorted suffix, i.e. id order).  Each wave
-// takes a v = N+(u)[i] and probes N+(v): a hit j is a triangle (u, v, w_j);
-// it updates t of the three edges and records the edge v -> w_j as bit j of
-// row i of the bit matrix E (the graph induced on N+(u), union view).
-// 4-cliques u < v_i < v_j < v_k then follow from AND-popcounts of rows:
+// hash (slot = position in the sorted suffix, i.e. id order).  The waves
+// walk the lists N+(v_i) of 64 slots i at a time, flattened over lanes: a
+// hit j is a triangle (u, v_i, w_j); it updates t of the three edges and
+// records the edge v_i -> w_j as bit j of row i of the bit matrix E (the
+// graph induced on N+(u), union view).  4-cliques u < v_i < v_j < v_k then
+// follow from AND-popcounts of rows:
 //   K4_x(u) = sum_{i in P_x} sum_{j in E[i] & P_x} |E[i] & E[j] & P_x|
 // with P_x the slots whose edge from u exists in version x.  Edges among
 // N+(u) that exist in one version only are few; the triangles of E that
 // contain such an edge absent from version x are removed from K4_x one by
 // one (each once, at its first such edge in list order).  If the list
 // overflows, the matrix is rebuilt per version instead.
-constexpr int TL_MAX = 512;    // out-degree handled from LDS
-constexpr int TL_W = TL_MAX / 64;
-constexpr int TL_WAVES = 4;
-constexpr int TL_EXC = 512;    // version-specific edges tracked per vertex
+constexpr int TL_EXC = 256;    // version-specific edges tracked per vertex
 
 struct TriL {
   unsigned long long* E;   // [dp][W] row bitsets
@@ -206,26 +204,44 @@ __device__ __forceinline__ bool Ebit(const TriL& S, int32_t p, int32_t q) {  // 
   return (S.E[(int64_t)p * S.W + (q >> 6)] >> (q & 63)) & 1ull;
 }
 
-// set E bits for every probe hit of N+(v_i) present in version `only`
-// (only = 0: union, and also do the triangle bookkeeping)
+// One wave: slots [g0, g0 + 64) of N+(u), their out-lists flattened over
+// lanes.  only = 0: union matrix plus all triangle bookkeeping; only = 1/2:
+// matrix of version b / a alone.
 __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL& S, uint32_t hmask, int shift,
-                                                int32_t i, int only, int32_t dBu, int32_t dAu, int64_t& tb_,
-                                                int64_t& ta_, int64_t& pb_, int64_t& pa_) {
+                                                int32_t g0, int32_t dp, int only, int32_t dBu, int32_t dAu,
+                                                int64_t& tb_, int64_t& ta_, int64_t& pb_, int64_t& pa_) {
   const RegionDev& R = A.R;
   const int l = lane_id();
-  const uint32_t xi = S.ids[i];
-  const uint32_t v = xi & GC_ID, fi = xi & GC_FLAGS;
-  const int64_t sb = R.roff[v] + R.rlow[v];
-  const int32_t sl = (int32_t)(R.roff[v + 1] - sb);
-  const int32_t dBv = R.dB[v], dAv = R.dA[v];
-  uint32_t acc_i = 0;
-  unsigned long long* Ei = S.E + (int64_t)i * S.W;
-  for (int32_t k0 = 0; k0 < sl; k0 += 64) {
-    const int32_t k = k0 + l;
-    if (k >= sl) break;
-    const uint32_t y = R.rcol[sb + k];
+  const int32_t i0 = g0 + l;
+  int64_t sb = 0;
+  int32_t sl = 0, dBv = 0, dAv = 0;
+  uint32_t fi = 0;
+  if (i0 < dp) {
+    const uint32_t xi = S.ids[i0];
+    const uint32_t v = xi & GC_ID;
+    fi = xi & GC_FLAGS;
+    sb = R.roff[v] + R.rlow[v];
+    sl = (int32_t)(R.roff[v + 1] - sb);
+    dBv = R.dB[v];
+    dAv = R.dA[v];
+  }
+  const int32_t incl = wave_incl_scan32(sl);
+  const int32_t tot = __shfl(incl, 63);
+  const int32_t excl = incl - sl;
+  for (int32_t base = 0; base < tot; base += 64) {
+    const int32_t idx = base + l;
+    const int s = seg_of(excl, idx);
+    const int64_t sbs = __shfl(sb, s);
+    const int32_t exs = __shfl(excl, s);
+    const uint32_t fs = __shfl(fi, s);
+    const int32_t dBs = __shfl(dBv, s), dAs = __shfl(dAv, s);
+    if (idx >= tot) continue;
+    const int32_t i = g0 + s;
+    const int64_t pos = sbs + (idx - exs);
+    const uint32_t y = R.rcol[pos];
     const int j = lookup_slot(S.hkey, S.hval, hmask, shift, y & GC_ID);
     if (j < 0) continue;
+    unsigned long long* Ei = S.E + (int64_t)i * S.W;
     const uint32_t fy = y & GC_FLAGS;
     if (only) {
       if (!(fy & (only == 1 ? GC_F_NEW : GC_F_DEL))) atomicOr(&Ei[j >> 6], 1ull << (j & 63));
@@ -236,29 +252,25 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL& 
       const int32_t p = atomicAdd(S.nexc, 1);
       if (p < TL_EXC) S.exc[p] = ((uint32_t)i << 17) | ((uint32_t)j << 2) | (fy >> 30);
     }
-    const uint32_t ab = fi | (S.ids[j] & GC_FLAGS) | fy;
+    const uint32_t ab = fs | (S.ids[j] & GC_FLAGS) | fy;
     const uint32_t xb = !(ab & GC_F_NEW), xa = !(ab & GC_F_DEL);
     if (xb | xa) {
-      atomicAdd(&R.t[sb + k], pack2(xb, xa));
+      atomicAdd(&R.t[pos], pack2(xb, xa));
       atomicAdd(&S.tuc[j], xb | (xa << 16));
-      acc_i += xb | (xa << 16);
+      atomicAdd(&S.tuc[i], xb | (xa << 16));
       const uint32_t wv = y & GC_ID;
       tb_ += xb; ta_ += xa;
-      if (xb) pb_ += (int64_t)dBu + dBv + R.dB[wv] - 6;
-      if (xa) pa_ += (int64_t)dAu + dAv + R.dA[wv] - 6;
+      if (xb) pb_ += (int64_t)dBu + dBs + R.dB[wv] - 6;
+      if (xa) pa_ += (int64_t)dAu + dAs + R.dA[wv] - 6;
     }
-  }
-  if (!only) {
-    acc_i = (uint32_t)wave_sum32((int32_t)acc_i);
-    if (l == 0 && acc_i) atomicAdd(&S.tuc[i], acc_i);
   }
 }
 
 // sum over i in mask, j in E[i] & mask of |E[i] & E[j] & mask|  (one wave's rows)
-__device__ __forceinline__ int64_t k4_rows(const TriL& S, const unsigned long long* mask, int32_t dp) {
+__device__ __forceinline__ int64_t k4_rows(const TriL& S, const unsigned long long* mask, int32_t dp, int nwaves) {
   const int w = threadIdx.x >> 6, l = lane_id();
   int64_t cnt = 0;
-  for (int32_t i = w; i < dp; i += TL_WAVES) {
+  for (int32_t i = w; i < dp; i += nwaves) {
     if (!((mask[i >> 6] >> (i & 63)) & 1ull)) continue;
     const unsigned long long* Ei = S.E + (int64_t)i * S.W;
     for (int32_t w0 = i >> 6; w0 < S.W; ++w0) {
@@ -278,6 +290,7 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL& S, int32_t u, i
                                  int64_t& tb_, int64_t& ta_, int64_t& pb_, int64_t& pa_, int64_t& kb_, int64_t& ka_) {
   const RegionDev& R = A.R;
   const int w = threadIdx.x >> 6;
+  const int nwaves = blockDim.x >> 6;
   const int32_t W = S.W;
   int H = 1;
   while (H < 2 * dp) H <<= 1;
@@ -300,7 +313,8 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL& S, int32_t u, i
   }
   __syncthreads();
   const int32_t dBu = R.dB[u], dAu = R.dA[u];
-  for (int32_t i = w; i < dp; i += TL_WAVES) tri_large_probe(A, S, hmask, shift, i, 0, dBu, dAu, tb_, ta_, pb_, pa_);
+  for (int32_t g0 = w * 64; g0 < dp; g0 += nwaves * 64)
+    tri_large_probe(A, S, hmask, shift, g0, dp, 0, dBu, dAu, tb_, ta_, pb_, pa_);
   __syncthreads();
   const int32_t ne = *S.nexc;
   const unsigned long long* Pb = S.P;
@@ -308,13 +322,13 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL& S, int32_t u, i
   if (ne <= TL_EXC) {
     bool same = true;
     for (int32_t q = 0; q < W; ++q) same &= Pb[q] == Pa[q];
-    const int64_t cb = k4_rows(S, Pb, dp);
-    const int64_t ca = same ? cb : k4_rows(S, Pa, dp);
+    const int64_t cb = k4_rows(S, Pb, dp, nwaves);
+    const int64_t ca = same ? cb : k4_rows(S, Pa, dp, nwaves);
     kb_ += cb;
     ka_ += ca;
     // triangles of E (inside P_x) holding an edge absent from version x
     const int l = lane_id();
-    for (int32_t e = w; e < ne; e += TL_WAVES) {
+    for (int32_t e = w; e < ne; e += nwaves) {
       const uint32_t ex = S.exc[e];
       const int32_t i = (int32_t)(ex >> 17), j = (int32_t)((ex >> 2) & 0x7FFF);
       const uint32_t fl = (ex & 3u) << 30;
@@ -348,9 +362,10 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL& S, int32_t u, i
       for (int64_t k = threadIdx.x; k < (int64_t)dp * W; k += blockDim.x) S.E[k] = 0ull;
       __syncthreads();
       int64_t d0 = 0;
-      for (int32_t i = w; i < dp; i += TL_WAVES) tri_large_probe(A, S, hmask, shift, i, x + 1, dBu, dAu, d0, d0, d0, d0);
+      for (int32_t g0 = w * 64; g0 < dp; g0 += nwaves * 64)
+        tri_large_probe(A, S, hmask, shift, g0, dp, x + 1, dBu, dAu, d0, d0, d0, d0);
       __syncthreads();
-      const int64_t c = k4_rows(S, x == 0 ? Pb : Pa, dp);
+      const int64_t c = k4_rows(S, x == 0 ? Pb : Pa, dp, nwaves);
       if (x == 0) kb_ += c; else ka_ += c;
     }
   }
@@ -369,15 +384,17 @@ __host__ __device__ inline int64_t tri_slot_words64(int64_t cap) {
   return cap * W + 2 * W + (cap + cap + 4 * cap + 2 * cap + TL_EXC + 2 + 1) / 2 + 8;
 }
 
-template <bool GLOBAL>
-__global__ __launch_bounds__(256) void k_tri_large(CountArgs A) {
+// Vertices with out-degree in (LO, CAP]; CAP = 0 selects the global-memory
+// scratch for everything above LO.
+template <int CAP, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int32_t lo_dp) {
   const RegionDev& R = A.R;
   const int64_t n = (int64_t)A.c[C_LIST0 + L_TRI_L];
   const int32_t* list = A.lists + L_TRI_L * A.list_stride;
   int cur_g = -1;
   int64_t tb_ = 0, ta_ = 0, pb_ = 0, pa_ = 0, kb_ = 0, ka_ = 0;
   TriL S;
-  if constexpr (GLOBAL) {
+  if constexpr (CAP == 0) {
     const int64_t cap = A.tri_cap;
     const int64_t W = (cap + 63) / 64;
     unsigned long long* base = (unsigned long long*)A.tri_scratch + (int64_t)blockIdx.x * tri_slot_words64(cap);
@@ -392,32 +409,36 @@ __global__ __launch_bounds__(256) void k_tri_large(CountArgs A) {
     S.exc = u32 + 8 * cap;
     S.nexc = (int32_t*)(u32 + 8 * cap + TL_EXC);
   } else {
-    __shared__ unsigned long long E[TL_MAX * TL_W];
-    __shared__ unsigned long long P[2 * TL_W];
-    __shared__ uint32_t ids[TL_MAX];
-    __shared__ uint32_t tuc[TL_MAX];
-    __shared__ int32_t hkey[2 * TL_MAX];
-    __shared__ int16_t hval[2 * TL_MAX];
+    constexpr int CW = CAP / 64;
+    __shared__ unsigned long long E[CAP * CW];
+    __shared__ unsigned long long P[2 * CW];
+    __shared__ uint32_t ids[CAP];
+    __shared__ uint32_t tuc[CAP];
+    __shared__ int32_t hkey[2 * CAP];
+    __shared__ int16_t hval[2 * CAP];
     __shared__ uint32_t exc[TL_EXC];
     __shared__ int32_t nexc;
     S.E = E; S.P = P; S.ids = ids; S.tuc = tuc; S.hkey = hkey; S.hval = hval; S.exc = exc; S.nexc = &nexc;
-    S.W = TL_W;
+    S.W = CW;
   }
   for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
     const int32_t u = list[it];
     const int64_t ub = R.roff[u] + R.rlow[u];
     const int32_t dp = (int32_t)(R.roff[u + 1] - ub);
-    if (GLOBAL ? dp <= TL_MAX : dp > TL_MAX) continue;
+    if (dp <= lo_dp || (CAP != 0 && dp > CAP)) continue;
     const int g = A.gid[u];
     if (g != cur_g) {
       if (cur_g >= 0) { flush2(A.sig, cur_g, SG_T, tb_, ta_); flush2(A.sig, cur_g, SG_PAW, pb_, pa_); flush2(A.sig, cur_g, SG_K4, kb_, ka_); }
       cur_g = g;
     }
-    if constexpr (!GLOBAL) S.W = (dp + 63) / 64;
+    if constexpr (CAP != 0) S.W = (dp + 63) / 64;
     tri_large_vertex(A, S, u, ub, dp, tb_, ta_, pb_, pa_, kb_, ka_);
   }
   if (cur_g >= 0) { flush2(A.sig, cur_g, SG_T, tb_, ta_); flush2(A.sig, cur_g, SG_PAW, pb_, pa_); flush2(A.sig, cur_g, SG_K4, kb_, ka_); }
 }
+
+constexpr int TL_MID = 256;
+constexpr int TL_MAX = 1024;
 
 // ------------------------------------------------------------ edge pass
 // After all triangles: per upper entry u -> w present in version x,
@@ -772,9 +793,11 @@ void launch_count(const CountArgs& A, const unsigned long long* hc, hipStream_t 
   const int64_t nts = (int64_t)hc[C_LIST0 + L_TRI_S], ntl = (int64_t)hc[C_LIST0 + L_TRI_L];
   if (nts) hipLaunchKernelGGL(k_tri_small, dim3(cap_grid((nts + 3) / 4, 8192)), dim3(256), 0, s, A);
   if (ntl) {
-    hipLaunchKernelGGL(k_tri_large<false>, dim3(cap_grid(ntl, 2048)), dim3(256), 0, s, A);
+    hipLaunchKernelGGL((k_tri_large<TL_MID, 256>), dim3(cap_grid(ntl, 4096)), dim3(256), 0, s, A, 64);
+    if ((int64_t)hc[C_MAXDP] > TL_MID)
+      hipLaunchKernelGGL((k_tri_large<TL_MAX, 512>), dim3(cap_grid(ntl, 1024)), dim3(512), 0, s, A, TL_MID);
     if ((int64_t)hc[C_MAXDP] > TL_MAX)
-      hipLaunchKernelGGL(k_tri_large<true>, dim3(cap_grid(ntl, (unsigned)A.tri_slots)), dim3(256), 0, s, A);
+      hipLaunchKernelGGL((k_tri_large<0, 256>), dim3(cap_grid(ntl, (unsigned)A.tri_slots)), dim3(256), 0, s, A, TL_MAX);
   }
   if (ev) (void)hipEventRecord(ev[1], s);
   if (E) hipLaunchKernelGGL(k_edge_pass, dim3(cap_grid((E / EP_RUN + 255) / 256, 8192)), dim3(256), 0, s, A);

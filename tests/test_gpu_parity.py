@@ -232,3 +232,40 @@ def test_rmat_large_ids(scale, ef, seed):
             say("  tiers c4 large=%d entries=%d" % (st["tier_c4_large"], st["c4_entries_large"]))
             assert st["tier_c4_large"] > 0
             assert got == native.static_counts(n, es, ed)
+
+
+COMP = [0, 6, 8, 7, 9, 10, 1, 3, 2, 4, 5]   # class of the complement (pinned on the CPU)
+
+
+@pytest.mark.parametrize("n,p,seed", [(900, 0.05, 41), (1300, 0.03, 42)])
+def test_dense_graph_by_complement(n, p, seed):
+    """Dense graphs (out-degrees up to ~n) exercise the large-out-degree
+    triangle tiers; the oracle counts the sparse complement and the
+    complement duality of induced classes maps the result back."""
+    say("case dense complement n=%d p=%.2f" % (n, p))
+    rng = np.random.default_rng(seed)
+    cs, cd = erdos_renyi(n, p, seed)
+    comp = edge_set(cs, cd)
+    full = {(u, v) for u in range(n) for v in range(u + 1, n)}
+    E = full - comp
+    s, d = esorted(E)
+
+    def want(Eset):
+        c = esorted(full - Eset)
+        o = native.static_counts(n, c[0], c[1])
+        return [o[COMP[k]] for k in range(11)]
+
+    with G(n, s, d) as gr:
+        got, st = gr.counts(), None
+        assert got == want(E)
+        for k in (40, 400):
+            el = sorted(E)
+            pick = rng.choice(len(el), k // 2, replace=False)
+            du = np.array([el[q][0] for q in pick], np.int32)
+            dv = np.array([el[q][1] for q in pick], np.int32)
+            iu = rng.integers(0, n, k // 2).astype(np.int32)
+            iv = rng.integers(0, n, k // 2).astype(np.int32)
+            got, st = gr.apply_batch(iu, iv, du, dv, stats=True)
+            oracle_apply(E, n, iu, iv, du, dv)
+            say("  max out-degree %d" % st["max_out_degree"])
+            assert got == want(E)

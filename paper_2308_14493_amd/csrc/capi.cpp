@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -248,6 +249,12 @@ void run_count(gc_graph* G, int radius, long long* state_d, BatchWork& W, std::v
       G->c4_slots = (int32_t)slots;
     }
   }
+  // window of the large 4-cycle tier; GC_C4_WINDOW / GC_C4_NARROW_MAX override
+  // the defaults (tests shrink them to reach every path on small graphs)
+  A.c4_win = c4_window_max();
+  A.c4_narrow_max = 65535;
+  if (const char* e = std::getenv("GC_C4_WINDOW")) A.c4_win = std::max(64, std::min(c4_window_max(), std::atoi(e)));
+  if (const char* e = std::getenv("GC_C4_NARROW_MAX")) A.c4_narrow_max = std::max(0, std::min(65535, std::atoi(e)));
   A.c4_dense = G->c4_dense.as<unsigned long long>();
   A.c4_touch = G->c4_touch.as<int32_t>();
   A.slots = std::max(1, G->c4_slots);
@@ -487,6 +494,8 @@ void build(gc_graph* G, int32_t k, const int64_t* n, const int32_t* const* src, 
   G->sync();
   G->entries = nd;
   read_state(G);
+  for (int g = 0; g < k; ++g)
+    if (G->hstate[g * ST_STRIDE + ST_ERR]) raise(GC_EDEVICE, "graph %d: inexact totals in the initial count", g);
   for (int g = 0; g < k; ++g) G->hstate[g * ST_STRIDE + ST_N] = n[g];
 }
 
@@ -673,9 +682,12 @@ void apply(gc_graph* G, const gc_batch_desc* b, bool dev, int64_t (*counts)[11],
   std::vector<long long> st((size_t)k * ST_STRIDE);
   HIPCHK(hipMemcpyAsync(st.data(), G->state.p, st.size() * 8, hipMemcpyDeviceToHost, s));
   G->sync();
-  if (hb[BS_ARENA_OVF] || hb[BS_ERR]) {
+  long long cerr = 0;
+  for (int g = 0; g < k; ++g) cerr += st[g * ST_STRIDE + ST_ERR];
+  if (hb[BS_ARENA_OVF] || hb[BS_ERR] || cerr) {
     G->broken = true;
-    raise(GC_EDEVICE, "device-side inconsistency (arena overflow %llu, errors %llu)", hb[BS_ARENA_OVF], hb[BS_ERR]);
+    raise(GC_EDEVICE, "device-side inconsistency (arena overflow %llu, errors %llu, inexact totals %lld)",
+          hb[BS_ARENA_OVF], hb[BS_ERR], cerr);
   }
   for (int g = 0; g < k; ++g) st[g * ST_STRIDE + ST_N] = G->gn[g];
   G->hstate = st;
@@ -819,6 +831,7 @@ int gc_recount_exact(gc_graph* g, int32_t graph, int64_t hi[11], uint64_t lo[11]
     std::vector<long long> st((size_t)g->k * ST_STRIDE);
     HIPCHK(hipMemcpyAsync(st.data(), g->state_tmp.p, st.size() * 8, hipMemcpyDeviceToHost, s));
     g->sync();
+    if (st[graph * ST_STRIDE + ST_ERR]) raise(GC_EDEVICE, "inexact totals in the recount");
     i128 I[11];
     finalize(&st[graph * ST_STRIDE], g->gn[graph], I);
     for (int c = 0; c < 11; ++c) { lo[c] = (uint64_t)I[c]; hi[c] = (int64_t)(I[c] >> 64); }

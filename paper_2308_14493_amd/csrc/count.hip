@@ -100,12 +100,12 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
   const int64_t n = (int64_t)A.c[C_LIST0 + L_TRI_S];
   const int32_t* list = A.lists + L_TRI_S * A.list_stride;
   int cur_g = -1;
-  int64_t tb_ = 0, ta_ = 0, pb_ = 0, pa_ = 0, kb_ = 0, ka_ = 0;
+  int64_t kb_ = 0, ka_ = 0;
   for (int64_t it = (int64_t)blockIdx.x * TS_WAVES + w; it < n; it += (int64_t)gridDim.x * TS_WAVES) {
     const int32_t u = list[it];
     const int g = A.gid[u];
     if (g != cur_g) {
-      if (cur_g >= 0) { flush2(A.sig, cur_g, SG_T, tb_, ta_); flush2(A.sig, cur_g, SG_PAW, pb_, pa_); flush2(A.sig, cur_g, SG_K4, kb_, ka_); }
+      if (cur_g >= 0) flush2(A.sig, cur_g, SG_K4, kb_, ka_);
       cur_g = g;
     }
     const int64_t ub = R.roff[u] + R.rlow[u];
@@ -155,20 +155,16 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
       const bool pb = (Pb >> l) & 1ull, pa = (Pa >> l) & 1ull;
       const uint64_t rb = EB[w][l] & Pb, ra = EA[w][l] & Pa;
       const uint64_t cb = TB[w][l] & Pb, ca = TA[w][l] & Pa;
-      const int32_t midb = pb ? __popcll(rb) : 0, mida = pa ? __popcll(ra) : 0;
       const int32_t tub = pb ? __popcll(rb | cb) : 0, tua = pa ? __popcll(ra | ca) : 0;
       int64_t k4b = 0, k4a = 0;
       if (pb) for (uint64_t m = rb; m; m &= m - 1) k4b += __popcll(rb & EB[w][__builtin_ctzll(m)] & Pb);
       if (pa) for (uint64_t m = ra; m; m &= m - 1) k4a += __popcll(ra & EA[w][__builtin_ctzll(m)] & Pa);
-      tb_ += midb; ta_ += mida;
-      pb_ += (int64_t)midb * (R.dB[u] - 6) + (int64_t)tub * R.dB[vi];
-      pa_ += (int64_t)mida * (R.dA[u] - 6) + (int64_t)tua * R.dA[vi];
       kb_ += k4b; ka_ += k4a;
       if (tub | tua) atomicAdd(&R.t[ub + l], pack2(tub, tua));
     }
     wave_sync();
   }
-  if (cur_g >= 0) { flush2(A.sig, cur_g, SG_T, tb_, ta_); flush2(A.sig, cur_g, SG_PAW, pb_, pa_); flush2(A.sig, cur_g, SG_K4, kb_, ka_); }
+  if (cur_g >= 0) flush2(A.sig, cur_g, SG_K4, kb_, ka_);
 }
 
 // ------------------------------------------------------ triangles, tier L
@@ -208,13 +204,12 @@ __device__ __forceinline__ bool Ebit(const TriL& S, int32_t p, int32_t q) {  // 
 // lanes.  only = 0: union matrix plus all triangle bookkeeping; only = 1/2:
 // matrix of version b / a alone.
 __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL& S, uint32_t hmask, int shift,
-                                                int32_t g0, int32_t dp, int only, int32_t dBu, int32_t dAu,
-                                                int64_t& tb_, int64_t& ta_, int64_t& pb_, int64_t& pa_) {
+                                                int32_t g0, int32_t dp, int only) {
   const RegionDev& R = A.R;
   const int l = lane_id();
   const int32_t i0 = g0 + l;
   int64_t sb = 0;
-  int32_t sl = 0, dBv = 0, dAv = 0;
+  int32_t sl = 0;
   uint32_t fi = 0;
   if (i0 < dp) {
     const uint32_t xi = S.ids[i0];
@@ -222,8 +217,6 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL& 
     fi = xi & GC_FLAGS;
     sb = R.roff[v] + R.rlow[v];
     sl = (int32_t)(R.roff[v + 1] - sb);
-    dBv = R.dB[v];
-    dAv = R.dA[v];
   }
   const int32_t incl = wave_incl_scan32(sl);
   const int32_t tot = __shfl(incl, 63);
@@ -234,7 +227,6 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL& 
     const int64_t sbs = __shfl(sb, s);
     const int32_t exs = __shfl(excl, s);
     const uint32_t fs = __shfl(fi, s);
-    const int32_t dBs = __shfl(dBv, s), dAs = __shfl(dAv, s);
     if (idx >= tot) continue;
     const int32_t i = g0 + s;
     const int64_t pos = sbs + (idx - exs);
@@ -258,10 +250,6 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL& 
       atomicAdd(&R.t[pos], pack2(xb, xa));
       atomicAdd(&S.tuc[j], xb | (xa << 16));
       atomicAdd(&S.tuc[i], xb | (xa << 16));
-      const uint32_t wv = y & GC_ID;
-      tb_ += xb; ta_ += xa;
-      if (xb) pb_ += (int64_t)dBu + dBs + R.dB[wv] - 6;
-      if (xa) pa_ += (int64_t)dAu + dAs + R.dA[wv] - 6;
     }
   }
 }
@@ -287,7 +275,7 @@ __device__ __forceinline__ int64_t k4_rows(const TriL& S, const unsigned long lo
 }
 
 __device__ void tri_large_vertex(const CountArgs& A, const TriL& S, int32_t u, int64_t ub, int32_t dp,
-                                 int64_t& tb_, int64_t& ta_, int64_t& pb_, int64_t& pa_, int64_t& kb_, int64_t& ka_) {
+                                 int64_t& kb_, int64_t& ka_) {
   const RegionDev& R = A.R;
   const int w = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
@@ -312,9 +300,7 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL& S, int32_t u, i
     if (!(x & GC_F_DEL)) atomicOr(&S.P[W + (k >> 6)], 1ull << (k & 63));
   }
   __syncthreads();
-  const int32_t dBu = R.dB[u], dAu = R.dA[u];
-  for (int32_t g0 = w * 64; g0 < dp; g0 += nwaves * 64)
-    tri_large_probe(A, S, hmask, shift, g0, dp, 0, dBu, dAu, tb_, ta_, pb_, pa_);
+  for (int32_t g0 = w * 64; g0 < dp; g0 += nwaves * 64) tri_large_probe(A, S, hmask, shift, g0, dp, 0);
   __syncthreads();
   const int32_t ne = *S.nexc;
   const unsigned long long* Pb = S.P;
@@ -361,9 +347,7 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL& S, int32_t u, i
       __syncthreads();
       for (int64_t k = threadIdx.x; k < (int64_t)dp * W; k += blockDim.x) S.E[k] = 0ull;
       __syncthreads();
-      int64_t d0 = 0;
-      for (int32_t g0 = w * 64; g0 < dp; g0 += nwaves * 64)
-        tri_large_probe(A, S, hmask, shift, g0, dp, x + 1, dBu, dAu, d0, d0, d0, d0);
+      for (int32_t g0 = w * 64; g0 < dp; g0 += nwaves * 64) tri_large_probe(A, S, hmask, shift, g0, dp, x + 1);
       __syncthreads();
       const int64_t c = k4_rows(S, x == 0 ? Pb : Pa, dp, nwaves);
       if (x == 0) kb_ += c; else ka_ += c;
@@ -380,7 +364,7 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL& S, int32_t u, i
 // global-scratch slot layout (u64 words): E [cap*W] | P [2W] | then u32 words:
 // ids [cap] | tuc [cap] | hkey [4 cap] | hval [2 cap] | exc [TL_EXC] | nexc [2]
 __host__ __device__ inline int64_t tri_slot_words64(int64_t cap) {
-  const int64_t W = (cap + 63) / 64;
+  const int64_t W = ((cap + 63) / 64) | 1;
   return cap * W + 2 * W + (cap + cap + 4 * cap + 2 * cap + TL_EXC + 2 + 1) / 2 + 8;
 }
 
@@ -392,11 +376,11 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int32_t lo_d
   const int64_t n = (int64_t)A.c[C_LIST0 + L_TRI_L];
   const int32_t* list = A.lists + L_TRI_L * A.list_stride;
   int cur_g = -1;
-  int64_t tb_ = 0, ta_ = 0, pb_ = 0, pa_ = 0, kb_ = 0, ka_ = 0;
+  int64_t kb_ = 0, ka_ = 0;
   TriL S;
   if constexpr (CAP == 0) {
     const int64_t cap = A.tri_cap;
-    const int64_t W = (cap + 63) / 64;
+    const int64_t W = ((cap + 63) / 64) | 1;
     unsigned long long* base = (unsigned long long*)A.tri_scratch + (int64_t)blockIdx.x * tri_slot_words64(cap);
     S.W = (int32_t)W;
     S.E = base;
@@ -410,8 +394,9 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int32_t lo_d
     S.nexc = (int32_t*)(u32 + 8 * cap + TL_EXC);
   } else {
     constexpr int CW = CAP / 64;
-    __shared__ unsigned long long E[CAP * CW];
-    __shared__ unsigned long long P[2 * CW];
+    constexpr int CWS = CW | 1;  // largest odd row stride used
+    __shared__ unsigned long long E[CAP * CWS];
+    __shared__ unsigned long long P[2 * CWS];
     __shared__ uint32_t ids[CAP];
     __shared__ uint32_t tuc[CAP];
     __shared__ int32_t hkey[2 * CAP];
@@ -419,7 +404,7 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int32_t lo_d
     __shared__ uint32_t exc[TL_EXC];
     __shared__ int32_t nexc;
     S.E = E; S.P = P; S.ids = ids; S.tuc = tuc; S.hkey = hkey; S.hval = hval; S.exc = exc; S.nexc = &nexc;
-    S.W = CW;
+    S.W = CWS;
   }
   for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
     const int32_t u = list[it];
@@ -428,71 +413,78 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int32_t lo_d
     if (dp <= lo_dp || (CAP != 0 && dp > CAP)) continue;
     const int g = A.gid[u];
     if (g != cur_g) {
-      if (cur_g >= 0) { flush2(A.sig, cur_g, SG_T, tb_, ta_); flush2(A.sig, cur_g, SG_PAW, pb_, pa_); flush2(A.sig, cur_g, SG_K4, kb_, ka_); }
+      if (cur_g >= 0) flush2(A.sig, cur_g, SG_K4, kb_, ka_);
       cur_g = g;
     }
-    if constexpr (CAP != 0) S.W = (dp + 63) / 64;
-    tri_large_vertex(A, S, u, ub, dp, tb_, ta_, pb_, pa_, kb_, ka_);
+    if constexpr (CAP != 0) S.W = ((dp + 63) / 64) | 1;  // odd row stride: rows spread over LDS banks
+    tri_large_vertex(A, S, u, ub, dp, kb_, ka_);
   }
-  if (cur_g >= 0) { flush2(A.sig, cur_g, SG_T, tb_, ta_); flush2(A.sig, cur_g, SG_PAW, pb_, pa_); flush2(A.sig, cur_g, SG_K4, kb_, ka_); }
+  if (cur_g >= 0) flush2(A.sig, cur_g, SG_K4, kb_, ka_);
 }
 
 constexpr int TL_MID = 256;
 constexpr int TL_MAX = 1024;
 
 // ------------------------------------------------------------ edge pass
-// After all triangles: per upper entry u -> w present in version x,
-//   S2 += (d_x(u) - 1)(d_x(w) - 1),   DIA += C(t_x, 2).
+// After all triangles, per upper entry u -> w present in version x, with
+// t = t_x(u, w) and d = d_x:
+//   S2  += (d_u - 1)(d_w - 1)      DIA += C(t, 2)
+//   T3  += t                        (= 3 T)
+//   PAW2 += t (d_u + d_w - 4)       (= 2 N_paw: a triangle on the edge plus a
+//                                    pendant edge at one of its ends)
 constexpr int EP_RUN = 16;
 
 __global__ __launch_bounds__(256) void k_edge_pass(CountArgs A) {
   const RegionDev& R = A.R;
   const int64_t E = (int64_t)A.c[C_ER];
   int cur_g = -1;
-  int64_t s2b = 0, s2a = 0, db = 0, da = 0;
+  int64_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // s2 b/a, dia b/a, t3 b/a, paw2 b/a
+  const int keys[4] = {SG_S2, SG_DIA, SG_T, SG_PAW};
   for (int64_t run = gtid(); run * EP_RUN < E; run += gstride()) {
     const int64_t p0 = run * EP_RUN;
     const int64_t p1 = p0 + EP_RUN < E ? p0 + EP_RUN : E;
     int64_t u = upper_bound_i64(R.roff, A.N, p0);
     int64_t nxt = R.roff[u + 1];
+    int32_t dBu = R.dB[u], dAu = R.dA[u];
     for (int64_t p = p0; p < p1; ++p) {
-      while (nxt <= p) { ++u; nxt = R.roff[u + 1]; }
+      while (nxt <= p) { ++u; nxt = R.roff[u + 1]; dBu = R.dB[u]; dAu = R.dA[u]; }
       const uint32_t x = R.rcol[p];
       const uint32_t wv = x & GC_ID;
       if (wv <= (uint32_t)u) continue;
       const int g = A.gid[u];
       if (g != cur_g) {
-        if (cur_g >= 0) {
-          atomicAdd(&A.sig[SIG_IDX(cur_g, 0, SG_S2)], (unsigned long long)s2b);
-          atomicAdd(&A.sig[SIG_IDX(cur_g, 1, SG_S2)], (unsigned long long)s2a);
-          atomicAdd(&A.sig[SIG_IDX(cur_g, 0, SG_DIA)], (unsigned long long)db);
-          atomicAdd(&A.sig[SIG_IDX(cur_g, 1, SG_DIA)], (unsigned long long)da);
-          s2b = s2a = db = da = 0;
-        }
+        if (cur_g >= 0)
+          for (int k = 0; k < 8; ++k) {
+            if (acc[k]) atomicAdd(&A.sig[SIG_IDX(cur_g, k & 1, keys[k >> 1])], (unsigned long long)acc[k]);
+            acc[k] = 0;
+          }
         cur_g = g;
       }
       const unsigned long long tt = R.t[p];
       if (!(x & GC_F_NEW)) {
-        s2b += (int64_t)(R.dB[u] - 1) * (R.dB[wv] - 1);
-        db += c2((int64_t)(tt & 0xFFFFFFFFull));
+        const int64_t t = (int64_t)(tt & 0xFFFFFFFFull);
+        const int32_t dw = R.dB[wv];
+        acc[0] += (int64_t)(dBu - 1) * (dw - 1);
+        acc[2] += c2(t);
+        acc[4] += t;
+        acc[6] += t * (dBu + dw - 4);
       }
       if (!(x & GC_F_DEL)) {
-        s2a += (int64_t)(R.dA[u] - 1) * (R.dA[wv] - 1);
-        da += c2((int64_t)(tt >> 32));
+        const int64_t t = (int64_t)(tt >> 32);
+        const int32_t dw = R.dA[wv];
+        acc[1] += (int64_t)(dAu - 1) * (dw - 1);
+        acc[3] += c2(t);
+        acc[5] += t;
+        acc[7] += t * (dAu + dw - 4);
       }
     }
   }
   // wave-uniform graph: one atomic per wave, else per lane
   const int g0 = __shfl(cur_g, 0);
   const bool uniform = __ballot(cur_g == g0 || cur_g < 0) == ~0ull && g0 >= 0;
-  if (uniform) {
-    flush_sig(A.sig, g0, 0, SG_S2, s2b); flush_sig(A.sig, g0, 1, SG_S2, s2a);
-    flush_sig(A.sig, g0, 0, SG_DIA, db); flush_sig(A.sig, g0, 1, SG_DIA, da);
-  } else if (cur_g >= 0) {
-    atomicAdd(&A.sig[SIG_IDX(cur_g, 0, SG_S2)], (unsigned long long)s2b);
-    atomicAdd(&A.sig[SIG_IDX(cur_g, 1, SG_S2)], (unsigned long long)s2a);
-    atomicAdd(&A.sig[SIG_IDX(cur_g, 0, SG_DIA)], (unsigned long long)db);
-    atomicAdd(&A.sig[SIG_IDX(cur_g, 1, SG_DIA)], (unsigned long long)da);
+  for (int k = 0; k < 8; ++k) {
+    if (uniform) flush_sig(A.sig, g0, k & 1, keys[k >> 1], acc[k]);
+    else if (cur_g >= 0 && acc[k]) atomicAdd(&A.sig[SIG_IDX(cur_g, k & 1, keys[k >> 1])], (unsigned long long)acc[k]);
   }
 }
 
@@ -702,23 +694,38 @@ __global__ __launch_bounds__(C4W_T) void k_c4_large(CountArgs A, unsigned long l
     if (g != cur_g) { if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_); cur_g = g; }
     const int64_t rb = R.roff[v];
     const int32_t nlow = R.rlow[v];
+    // c(v, w) <= nlow: 16-bit halves suffice below 65536 lower neighbours,
+    // which doubles the window held in the same 128 KB
+    const bool narrow = nlow <= A.c4_narrow_max;
+    const int64_t ws = narrow ? 2 * (int64_t)A.c4_win : (int64_t)A.c4_win;
     if (k < C4W_K) {
-      const int64_t hi64 = (int64_t)v - (int64_t)k * C4W_WIN;
+      const int64_t hi64 = (int64_t)v - (int64_t)k * ws;
       if (hi64 <= 0) continue;  // uniform: nothing below this window
-      const int64_t lo64 = hi64 - C4W_WIN > 0 ? hi64 - C4W_WIN : 0;
+      const int64_t lo64 = hi64 - ws > 0 ? hi64 - ws : 0;
       const uint32_t lo = (uint32_t)lo64, hi = (uint32_t)hi64;
-      for (int s = threadIdx.x; s < C4W_WIN; s += blockDim.x) win[s] = 0ull;
+      for (int s = threadIdx.x; s < A.c4_win; s += blockDim.x) win[s] = 0ull;
       __syncthreads();
-      c4_block_walk(R, rb, nlow, lo, hi, C, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
-        atomicAdd(&win[wid - lo], pack2(xb, xa));
-      });
-      for (int s = threadIdx.x; s < C4W_WIN; s += blockDim.x) {
-        const unsigned long long c = win[s];
-        if (c) { cb_ += c2((int64_t)(c & 0xFFFFFFFFull)); ca_ += c2((int64_t)(c >> 32)); }
+      if (narrow) {
+        uint32_t* w32 = (uint32_t*)win;
+        c4_block_walk(R, rb, nlow, lo, hi, C, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
+          atomicAdd(&w32[wid - lo], xb | (xa << 16));
+        });
+        for (int s = threadIdx.x; s < 2 * A.c4_win; s += blockDim.x) {
+          const uint32_t c = w32[s];
+          if (c) { cb_ += c2((int64_t)(c & 0xFFFFu)); ca_ += c2((int64_t)(c >> 16)); }
+        }
+      } else {
+        c4_block_walk(R, rb, nlow, lo, hi, C, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
+          atomicAdd(&win[wid - lo], pack2(xb, xa));
+        });
+        for (int s = threadIdx.x; s < A.c4_win; s += blockDim.x) {
+          const unsigned long long c = win[s];
+          if (c) { cb_ += c2((int64_t)(c & 0xFFFFFFFFull)); ca_ += c2((int64_t)(c >> 32)); }
+        }
       }
       __syncthreads();
     } else {
-      const int64_t hi64 = (int64_t)v - (int64_t)C4W_K * C4W_WIN;
+      const int64_t hi64 = (int64_t)v - (int64_t)C4W_K * ws;
       if (hi64 <= 0) continue;
       c4_block_walk(R, rb, nlow, 0u, (uint32_t)hi64, C, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
         ++tail_;
@@ -749,16 +756,20 @@ __global__ void k_combine(const unsigned long long* sig, long long* state, int32
   const int64_t g = gtid();
   if (g >= k) return;
   int64_t N[2][6], T[2], W[2], D1[2];
+  int bad = 0;
   for (int x = 0; x < 2; ++x) {
     const unsigned long long* s = sig + SIG_IDX(g, x, 0);
-    const int64_t t = (int64_t)s[SG_T];
+    const int64_t t3 = (int64_t)s[SG_T], paw2 = (int64_t)s[SG_PAW];
+    bad |= (t3 % 3 != 0) | (paw2 % 2 != 0);
+    const int64_t t = t3 / 3;
     N[x][0] = (int64_t)s[SG_S2] - 3 * t;      // 3-paths
     N[x][1] = (int64_t)s[SG_S1];              // 3-stars
     N[x][2] = (int64_t)s[SG_C4];              // 4-cycles
-    N[x][3] = (int64_t)s[SG_PAW];             // paws
+    N[x][3] = paw2 / 2;                       // paws
     N[x][4] = (int64_t)s[SG_DIA];             // diamonds
     N[x][5] = (int64_t)s[SG_K4];              // 4-cliques
     T[x] = t; W[x] = (int64_t)s[SG_W]; D1[x] = (int64_t)s[SG_D1];
+    bad |= (D1[x] % 2 != 0);
   }
   int64_t d[6];
   for (int c = 0; c < 6; ++c) d[c] = N[1][c] - N[0][c];
@@ -774,6 +785,7 @@ __global__ void k_combine(const unsigned long long* sig, long long* state, int32
   st[ST_T] += T[1] - T[0];
   st[ST_W] += W[1] - W[0];
   st[ST_M] += (D1[1] - D1[0]) / 2;
+  if (bad) st[ST_ERR] += 1;
 }
 
 inline unsigned cap_grid(int64_t want, unsigned cap) {
@@ -783,6 +795,7 @@ inline unsigned cap_grid(int64_t want, unsigned cap) {
 
 }  // namespace
 
+int32_t c4_window_max() { return C4W_WIN; }
 int64_t tri_scratch_words64(int64_t cap) { return tri_slot_words64(cap); }
 int32_t tri_lds_max() { return TL_MAX; }
 

@@ -31,9 +31,9 @@
 enum {
   SG_S1 = 0,   // sum_v C(d,3)                      -> non-induced 3-stars
   SG_S2 = 1,   // sum_e (d_u - 1)(d_v - 1)          -> 3-paths + 3 T
-  SG_T = 2,    // triangles
+  SG_T = 2,    // sum_e t_e (three times the triangles)
   SG_DIA = 3,  // sum_e C(t_e, 2)                   -> non-induced diamonds
-  SG_PAW = 4,  // sum_tri (d_u + d_v + d_w - 6)     -> non-induced paws
+  SG_PAW = 4,  // sum_e t_e (d_u + d_v - 4)         -> twice the non-induced paws
   SG_K4 = 5,   // 4-cliques
   SG_C4 = 6,   // 4-cycles
   SG_W = 7,    // sum_v C(d,2)
@@ -43,8 +43,8 @@ enum {
 // per graph: sig[g][version][term], version 0 = b (before), 1 = a (after)
 #define SIG_IDX(g, x, k) (((int64_t)(g) * 2 + (x)) * SG_N + (k))
 
-// Device state per graph (int64): F_conn[6], T, W, m, n
-enum { ST_F0 = 0, ST_T = 6, ST_W = 7, ST_M = 8, ST_N = 9, ST_STRIDE = 16 };
+// Device state per graph (int64): F_conn[6], T, W, m, n, error count
+enum { ST_F0 = 0, ST_T = 6, ST_W = 7, ST_M = 8, ST_N = 9, ST_ERR = 10, ST_STRIDE = 16 };
 
 // Per-batch statistics written by kernels (u64 counters on the device).
 enum {

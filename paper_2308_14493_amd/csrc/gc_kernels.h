@@ -90,6 +90,8 @@ struct CountArgs {
   int32_t* c4_touch;              // [slots][N]
   int64_t N;
   int32_t slots;                  // workgroups of the large 4-cycle tier
+  int32_t c4_win;                 // 64-bit counters per window of the large tier (<= c4_window_max())
+  int32_t c4_narrow_max;          // up to this many lower neighbours, 16-bit counters (2x window)
   int32_t tri_slots;              // workgroups of the global-scratch triangle tier
   unsigned long long* tri_scratch;  // [tri_slots][tri_scratch_words64(tri_cap)] above the LDS tier
   int64_t tri_cap;                  // out-degree capacity of a scratch slot
@@ -97,5 +99,6 @@ struct CountArgs {
 void launch_count(const CountArgs& A, const unsigned long long* host_counts, hipStream_t s,
                   hipEvent_t* ev /* nullable: 6 events between the kernel phases */);
 int64_t tri_scratch_words64(int64_t cap);  // u64 words of one triangle scratch slot
-int32_t tri_lds_max();                      // largest out-degree of the LDS triangle tier
+int32_t tri_lds_max();
+int32_t c4_window_max();                      // largest out-degree of the LDS triangle tier
 void launch_combine(const unsigned long long* sig, long long* state, int32_t k, hipStream_t s);

@@ -269,3 +269,23 @@ def test_dense_graph_by_complement(n, p, seed):
             oracle_apply(E, n, iu, iv, du, dv)
             say("  max out-degree %d" % st["max_out_degree"])
             assert got == want(E)
+
+
+def test_c4_windows_tail_and_wide_counters(monkeypatch):
+    """Small windows and a low 16-bit threshold force the large 4-cycle tier
+    through every window, the global tail and the 32-bit counter path."""
+    monkeypatch.setenv("GC_C4_WINDOW", "128")
+    monkeypatch.setenv("GC_C4_NARROW_MAX", "20")
+    say("case c4 windows 128, narrow <= 20")
+    n, s, d, samp = rmat_graph(13, 16, 51)
+    batches = rmat_batches(n, s, d, samp, [100, 2000], 52)
+    E = edge_set(s, d)
+    with G(n, s, d) as gr:
+        assert gr.counts() == native.static_counts(n, s, d)
+        for b in batches:
+            got, st = gr.apply_batch(*b, stats=True)
+            oracle_apply(E, n, *b)
+            es, ed = esorted(E)
+            say("  c4 large tier %d vertices, tail wedges %d" % (st["tier_c4_large"], st["c4_tail_wedges"]))
+            assert st["c4_tail_wedges"] > 0
+            assert got == native.static_counts(n, es, ed)

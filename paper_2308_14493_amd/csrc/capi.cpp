@@ -135,7 +135,8 @@ struct gc_graph {
 
   // region and counting
   DevBuf roff, rcol, rlow, dB, dA, t, level, rlist, rlen, lists;
-  DevBuf c4_dense, c4_touch, tri_scratch;
+  DevBuf c4_dense, c4_touch, c4_cur, c4_keys, c4_keys_alt, tri_scratch;
+  int64_t c4_cur_low = 0;
   int32_t c4_slots = 0, tri_slots = 0;
   int64_t tri_cap = 0;
 
@@ -207,6 +208,9 @@ void run_count(gc_graph* G, int radius, long long* state_d, BatchWork& W, std::v
   hipStream_t s = G->stream;
   const int64_t N = G->N;
   G->roff.ensure((N + 1) * sizeof(int64_t));
+  G->c4_keys.ensure(N * sizeof(unsigned long long));
+  G->c4_keys_alt.ensure(N * sizeof(unsigned long long));
+  G->sort_tmp.ensure(radix_sort_tmp_bytes(N) + 64);
   G->rcol.ensure(std::max<int64_t>(union_entries, 1) * sizeof(uint32_t));
   G->t.ensure(std::max<int64_t>(union_entries, 1) * sizeof(unsigned long long));
   G->scan_tmp.ensure(scan_tmp_bytes(N + 1) + 64);
@@ -217,7 +221,7 @@ void run_count(gc_graph* G, int radius, long long* state_d, BatchWork& W, std::v
                      G->scan_tmp.p, s);
   launch_degrees(R, G->gid.as<int32_t>(), G->rlist.as<int32_t>(), G->ctr.as<unsigned long long>(),
                  G->sig.as<unsigned long long>(), G->lists.as<int32_t>(), N, TRI_SMALL, C4_SMALL, C4_MID,
-                 G->bstats.as<unsigned long long>(), s);
+                 G->bstats.as<unsigned long long>(), G->c4_keys.as<unsigned long long>(), s);
   if (timed) HIPCHK(hipEventRecord(G->ev[1], s));
   hc.assign(C_COUNT, 0);
   HIPCHK(hipMemcpyAsync(hc.data(), G->ctr.p, C_COUNT * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
@@ -255,6 +259,22 @@ void run_count(gc_graph* G, int radius, long long* state_d, BatchWork& W, std::v
   A.c4_narrow_max = 65535;
   if (const char* e = std::getenv("GC_C4_WINDOW")) A.c4_win = std::max(64, std::min(c4_window_max(), std::atoi(e)));
   if (const char* e = std::getenv("GC_C4_NARROW_MAX")) A.c4_narrow_max = std::max(0, std::min(65535, std::atoi(e)));
+  A.c4_dense_min = 2048;
+  if (const char* e = std::getenv("GC_C4_DENSE_MIN")) A.c4_dense_min = std::max<int64_t>(0, std::atoll(e));
+  {
+    const int64_t maxlow = std::max<int64_t>(1, (int64_t)hc[C_MAXLOW]);
+    const int64_t slots = std::max(1, G->c4_slots);
+    if (ncl > 0 && (maxlow > G->c4_cur_low || G->c4_cur.cap < (size_t)(slots * 2 * maxlow * 8))) {
+      G->c4_cur.release();
+      G->c4_cur.ensure((size_t)(slots * 2 * maxlow) * sizeof(int64_t));
+      G->c4_cur_low = maxlow;
+    }
+  }
+  A.c4_cur = G->c4_cur.as<int64_t>();
+  A.c4_maxlow = std::max<int64_t>(1, G->c4_cur_low);
+  A.c4_keys = G->c4_keys.as<unsigned long long>();
+  A.c4_keys_alt = G->c4_keys_alt.as<unsigned long long>();
+  A.sort_tmp = G->sort_tmp.p;
   A.c4_dense = G->c4_dense.as<unsigned long long>();
   A.c4_touch = G->c4_touch.as<int32_t>();
   A.slots = std::max(1, G->c4_slots);

@@ -605,17 +605,17 @@ __global__ __launch_bounds__(256) void k_c4_mid(CountArgs A) {
   if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_);
 }
 
-// Large tier: each hub v is split into work items by the rank of the
-// opposite vertex w.  Items 0..K-1 cover the windows [v-(k+1)WIN, v-kWIN),
-// counted with dense LDS counters; the hits concentrate there because the
-// ids are a degree order and a wedge reaches w with odds growing with deg w.
-// Item K covers w < v - K*WIN with dense counters in global memory.  Rows
-// are sorted, so each item's slice of a row is found by binary search.
-// The wedges of an item are spread over all 1024 threads of the block: one
-// lower neighbour u per thread, a block scan of the slice lengths, then a
-// flat walk with a binary search of each index in the scanned lengths.
+// Large tier: one workgroup per hub v at a time, hubs in decreasing order of
+// wedge work.  The opposite vertices w < v are taken in windows of ids from
+// v downwards; a window with enough hits gets dense LDS counters (16-bit
+// halves while c(v, w) <= 65535 can be guaranteed, which doubles the window).
+// Hits concentrate just below v because ids are a degree order and a wedge
+// reaches w with odds growing with deg w.  Once a window is sparse, all
+// wedges below it go to dense counters in global memory (one array per
+// resident workgroup, with a touched list).  Each lower neighbour u keeps a
+// cursor in its row: one binary search for v, then a short backward gallop
+// per window, so rows are read about once.
 constexpr int C4W_WIN = 16384;
-constexpr int C4W_K = 16;
 constexpr int C4W_T = 1024;
 
 struct C4Chunk {
@@ -623,26 +623,43 @@ struct C4Chunk {
   int32_t pre[C4W_T + 1];
   uint32_t fl[C4W_T];
   int32_t wsum[C4W_T / 64];
+  long long red[C4W_T / 64][2];
 };
 
-// walk the wedges (v, u, w) with w in [lo, hi) for u = row v positions
-// [0, nlow); f(w, add_b, add_a) per wedge present in some version
-template <class F>
-__device__ __forceinline__ void c4_block_walk(const RegionDev& R, int64_t rb, int32_t nlow, uint32_t lo, uint32_t hi,
-                                              C4Chunk& C, F f) {
+// first p in [0, c) with id(row[p]) >= lo, rows sorted, id(row[c-1]) < v
+__device__ __forceinline__ int32_t gallop_down(const uint32_t* row, int32_t c, uint32_t lo) {
+  if (c == 0 || (row[c - 1] & GC_ID) < lo) return c;
+  int32_t k = 1;
+  while (c - 1 - k >= 0 && (row[c - 1 - k] & GC_ID) >= lo) k <<= 1;
+  const int32_t a = c - 1 - k > 0 ? c - 1 - k : 0;   // row[a] < lo or a == 0
+  const int32_t z = c - 1 - (k >> 1);                 // row[z] >= lo
+  return a + lower_bound_id(row + a, z - a + 1, lo);
+}
+
+// block sum of two values (all threads call; result valid in every thread)
+__device__ __forceinline__ void block_sum2(C4Chunk& C, long long& x, long long& y) {
+  const int t = threadIdx.x, wv = t >> 6;
+  x = wave_sum64(x); y = wave_sum64(y);
+  if (lane_id() == 0) { C.red[wv][0] = x; C.red[wv][1] = y; }
+  __syncthreads();
+  x = 0; y = 0;
+  for (int k = 0; k < C4W_T / 64; ++k) { x += C.red[k][0]; y += C.red[k][1]; }
+  __syncthreads();
+}
+
+// Walk the wedges (v, u_q, w) for q in [0, nlow) with w in row u_q at
+// positions [urow[q] + p0(q), urow[q] + p1(q)); f(w, add_b, add_a).
+template <class P0, class P1, class F>
+__device__ __forceinline__ void c4_block_walk(const RegionDev& R, int64_t rb, int32_t nlow, const int64_t* urow,
+                                              P0 p0f, P1 p1f, C4Chunk& C, F f) {
   const int t = threadIdx.x, l = lane_id(), wv = t >> 6;
   for (int32_t c0 = 0; c0 < nlow; c0 += C4W_T) {
     const int32_t q = c0 + t;
     int32_t sl = 0;
     if (q < nlow) {
-      const uint32_t x = R.rcol[rb + q];
-      const uint32_t u = x & GC_ID;
-      const int64_t b = R.roff[u];
-      const int32_t L = (int32_t)(R.roff[u + 1] - b);
-      const int32_t p1 = lower_bound_id(R.rcol + b, L, hi);
-      const int32_t p0 = lo ? lower_bound_id(R.rcol + b, p1, lo) : 0;
-      C.sb[t] = b + p0;
-      C.fl[t] = x & GC_FLAGS;
+      const int32_t p0 = p0f(q), p1 = p1f(q);
+      C.sb[t] = urow[q] + p0;
+      C.fl[t] = R.rcol[rb + q] & GC_FLAGS;
       sl = p1 - p0;
     }
     const int32_t inc = wave_incl_scan32(sl);
@@ -676,76 +693,101 @@ __global__ __launch_bounds__(C4W_T) void k_c4_large(CountArgs A, unsigned long l
   __shared__ int32_t s_nt;
   const RegionDev& R = A.R;
   const int64_t n = (int64_t)A.c[C_LIST0 + L_C4_L];
-  const int64_t items = n * (C4W_K + 1);
   const int32_t* list = A.lists + L_C4_L * A.list_stride;
   unsigned long long* cnt = A.c4_dense + (int64_t)blockIdx.x * A.N;
   int32_t* touch = A.c4_touch + (int64_t)blockIdx.x * A.N;
+  int64_t* urow = A.c4_cur + (int64_t)blockIdx.x * 2 * A.c4_maxlow;
+  int32_t* ucur = (int32_t*)(urow + A.c4_maxlow);
+  int32_t* unext = ucur + A.c4_maxlow;
+  const int t = threadIdx.x;
   int cur_g = -1;
   int64_t cb_ = 0, ca_ = 0, tail_ = 0;
   while (true) {
     __syncthreads();  // every thread has read the previous item before it is replaced
-    if (threadIdx.x == 0) { s_item = (int64_t)atomicAdd(qhead, 1ull); s_nt = 0; }
+    if (t == 0) { s_item = (int64_t)atomicAdd(qhead, 1ull); s_nt = 0; }
     __syncthreads();
     const int64_t item = s_item;
-    if (item >= items) break;
-    const int32_t v = list[item / (C4W_K + 1)];
-    const int k = (int)(item % (C4W_K + 1));
+    if (item >= n) break;
+    const int32_t v = list[item];
     const int g = A.gid[v];
     if (g != cur_g) { if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_); cur_g = g; }
     const int64_t rb = R.roff[v];
     const int32_t nlow = R.rlow[v];
-    // c(v, w) <= nlow: 16-bit halves suffice below 65536 lower neighbours,
-    // which doubles the window held in the same 128 KB
+    // c(v, w) <= nlow: 16-bit halves suffice up to 65535 lower neighbours
     const bool narrow = nlow <= A.c4_narrow_max;
     const int64_t ws = narrow ? 2 * (int64_t)A.c4_win : (int64_t)A.c4_win;
-    if (k < C4W_K) {
-      const int64_t hi64 = (int64_t)v - (int64_t)k * ws;
-      if (hi64 <= 0) continue;  // uniform: nothing below this window
-      const int64_t lo64 = hi64 - ws > 0 ? hi64 - ws : 0;
-      const uint32_t lo = (uint32_t)lo64, hi = (uint32_t)hi64;
-      for (int s = threadIdx.x; s < A.c4_win; s += blockDim.x) win[s] = 0ull;
-      __syncthreads();
-      if (narrow) {
-        uint32_t* w32 = (uint32_t*)win;
-        c4_block_walk(R, rb, nlow, lo, hi, C, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
-          atomicAdd(&w32[wid - lo], xb | (xa << 16));
-        });
-        for (int s = threadIdx.x; s < 2 * A.c4_win; s += blockDim.x) {
-          const uint32_t c = w32[s];
-          if (c) { cb_ += c2((int64_t)(c & 0xFFFFu)); ca_ += c2((int64_t)(c >> 16)); }
+    for (int32_t q = t; q < nlow; q += C4W_T) {
+      const uint32_t u = R.rcol[rb + q] & GC_ID;
+      const int64_t b = R.roff[u];
+      urow[q] = b;
+      ucur[q] = lower_bound_id(R.rcol + b, (int32_t)(R.roff[u + 1] - b), (uint32_t)v);
+    }
+    __syncthreads();
+    int64_t hi = v;
+    while (hi > 0) {
+      const uint32_t lo = (uint32_t)(hi - ws > 0 ? hi - ws : 0);
+      long long wtot = 0, rest = 0;
+      for (int32_t q = t; q < nlow; q += C4W_T) {
+        const int32_t c = ucur[q];
+        const int32_t p0 = gallop_down(R.rcol + urow[q], c, lo);
+        unext[q] = p0;
+        wtot += c - p0;
+        rest += p0;
+      }
+      block_sum2(C, wtot, rest);
+      if (wtot >= A.c4_dense_min) {
+        for (int s = t; s < A.c4_win; s += C4W_T) win[s] = 0ull;
+        __syncthreads();
+        if (narrow) {
+          uint32_t* w32 = (uint32_t*)win;
+          c4_block_walk(R, rb, nlow, urow, [&](int32_t q) { return unext[q]; }, [&](int32_t q) { return ucur[q]; }, C,
+                        [&](uint32_t wid, uint32_t xb, uint32_t xa) { atomicAdd(&w32[wid - lo], xb | (xa << 16)); });
+          for (int s = t; s < 2 * A.c4_win; s += C4W_T) {
+            const uint32_t c = w32[s];
+            if (c) { cb_ += c2((int64_t)(c & 0xFFFFu)); ca_ += c2((int64_t)(c >> 16)); }
+          }
+        } else {
+          c4_block_walk(R, rb, nlow, urow, [&](int32_t q) { return unext[q]; }, [&](int32_t q) { return ucur[q]; }, C,
+                        [&](uint32_t wid, uint32_t xb, uint32_t xa) { atomicAdd(&win[wid - lo], pack2(xb, xa)); });
+          for (int s = t; s < A.c4_win; s += C4W_T) {
+            const unsigned long long c = win[s];
+            if (c) { cb_ += c2((int64_t)(c & 0xFFFFFFFFull)); ca_ += c2((int64_t)(c >> 32)); }
+          }
         }
+        for (int32_t q = t; q < nlow; q += C4W_T) ucur[q] = unext[q];
+        __syncthreads();
+        hi = lo;
+        if (rest == 0) break;
       } else {
-        c4_block_walk(R, rb, nlow, lo, hi, C, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
-          atomicAdd(&win[wid - lo], pack2(xb, xa));
-        });
-        for (int s = threadIdx.x; s < A.c4_win; s += blockDim.x) {
-          const unsigned long long c = win[s];
-          if (c) { cb_ += c2((int64_t)(c & 0xFFFFFFFFull)); ca_ += c2((int64_t)(c >> 32)); }
+        // sparse from here down: every remaining wedge in global memory
+        c4_block_walk(R, rb, nlow, urow, [&](int32_t) { return 0; }, [&](int32_t q) { return ucur[q]; }, C,
+                      [&](uint32_t wid, uint32_t xb, uint32_t xa) {
+                        ++tail_;
+                        const unsigned long long old = atomicAdd(&cnt[wid], pack2(xb, xa));
+                        if (old == 0ull) touch[atomicAdd(&s_nt, 1)] = (int32_t)wid;
+                      });
+        const int32_t nt = s_nt;
+        for (int32_t q = t; q < nt; q += C4W_T) {
+          const int32_t wid = touch[q];
+          const unsigned long long c = cnt[wid];
+          cnt[wid] = 0ull;
+          cb_ += c2((int64_t)(c & 0xFFFFFFFFull));
+          ca_ += c2((int64_t)(c >> 32));
         }
+        __syncthreads();
+        break;
       }
-      __syncthreads();
-    } else {
-      const int64_t hi64 = (int64_t)v - (int64_t)C4W_K * ws;
-      if (hi64 <= 0) continue;
-      c4_block_walk(R, rb, nlow, 0u, (uint32_t)hi64, C, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
-        ++tail_;
-        const unsigned long long old = atomicAdd(&cnt[wid], pack2(xb, xa));
-        if (old == 0ull) touch[atomicAdd(&s_nt, 1)] = (int32_t)wid;
-      });
-      const int32_t nt = s_nt;
-      for (int32_t q = threadIdx.x; q < nt; q += blockDim.x) {
-        const int32_t wid = touch[q];
-        const unsigned long long c = cnt[wid];
-        cnt[wid] = 0ull;
-        cb_ += c2((int64_t)(c & 0xFFFFFFFFull));
-        ca_ += c2((int64_t)(c >> 32));
-      }
-      __syncthreads();
     }
   }
   if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_);
   tail_ = wave_sum64(tail_);
   if (lane_id() == 0 && tail_) atomicAdd(&A.bstats[BS_TRIPROBE], (unsigned long long)tail_);
+}
+
+// hubs of the large tier in decreasing order of wedge work
+__global__ void k_c4_order(const unsigned long long* sorted, const unsigned long long* c, int32_t* list) {
+  const int64_t n = (int64_t)c[C_LIST0 + L_C4_L];
+  for (int64_t i = gtid(); i < n; i += gstride()) list[i] = (int32_t)(sorted[i] & 0xFFFFFFFFull);
 }
 
 // --------------------------------------------------------------- combine
@@ -821,9 +863,14 @@ void launch_count(const CountArgs& A, const unsigned long long* hc, hipStream_t 
   if (ev) (void)hipEventRecord(ev[3], s);
   if (ncm) hipLaunchKernelGGL(k_c4_mid, dim3(cap_grid(ncm, 4096)), dim3(256), 0, s, A);
   if (ev) (void)hipEventRecord(ev[4], s);
-  if (ncl)
-    hipLaunchKernelGGL(k_c4_large, dim3(cap_grid(ncl * (C4W_K + 1), (unsigned)A.slots)), dim3(C4W_T), 0, s, A,
+  if (ncl) {
+    // order the hubs by decreasing wedge work (keys written by the per-vertex pass)
+    unsigned long long* sk = radix_sort_u64(A.c4_keys, A.c4_keys_alt, A.sort_tmp, ncl, A.c + C_LIST0 + L_C4_L, 64, s);
+    hipLaunchKernelGGL(k_c4_order, dim3(cap_grid((ncl + 255) / 256, 1024)), dim3(256), 0, s, sk, A.c,
+                       (int32_t*)(A.lists + L_C4_L * A.list_stride));
+    hipLaunchKernelGGL(k_c4_large, dim3(cap_grid(ncl, (unsigned)A.slots)), dim3(C4W_T), 0, s, A,
                        (unsigned long long*)(A.c + C_QHEAD));
+  }
   if (ev) (void)hipEventRecord(ev[5], s);
 }
 

@@ -12,6 +12,7 @@ enum {
   C_ER = C_LVL0 + 6,  // region entries
   C_MAXDP,        // max oriented out-degree
   C_MAXW,         // max wedge bound
+  C_MAXLOW,       // max lower degree in the large 4-cycle tier
   C_LIST0,        // C_LIST0 + L_*: work list sizes
   C_QHEAD = C_LIST0 + 8,  // dynamic queue head of the large 4-cycle tier
   C_COUNT = C_QHEAD + 2
@@ -57,7 +58,7 @@ void launch_region_fill(const PoolDev& P, const RegionDev& R, const BatchWork& W
                         const int32_t* rlist, const int32_t* rlen, void* scan_tmp, hipStream_t s);
 void launch_degrees(const RegionDev& R, const int32_t* gid, const int32_t* rlist, unsigned long long* c,
                     unsigned long long* sig, int32_t* lists, int64_t list_stride, int32_t tri_small, int32_t c4_small,
-                    int32_t c4_mid, unsigned long long* bstats, hipStream_t s);
+                    int32_t c4_mid, unsigned long long* bstats, unsigned long long* c4_keys, hipStream_t s);
 void launch_init_keys(const int32_t* src, const int32_t* dst, int64_t m, const int64_t* seg, const int64_t* gbase,
                       int32_t k, int bits, unsigned long long* keys, hipStream_t s);
 void launch_init_unique(const unsigned long long* keys, int64_t m, int bits, unsigned long long* uniq,
@@ -92,6 +93,12 @@ struct CountArgs {
   int32_t slots;                  // workgroups of the large 4-cycle tier
   int32_t c4_win;                 // 64-bit counters per window of the large tier (<= c4_window_max())
   int32_t c4_narrow_max;          // up to this many lower neighbours, 16-bit counters (2x window)
+  int64_t c4_dense_min;           // hits that earn a window dense LDS counters
+  int64_t* c4_cur;                // [slots][2 * c4_maxlow]: row starts, cursors, next cursors
+  int64_t c4_maxlow;              // largest lower degree of a large-tier vertex
+  unsigned long long* c4_keys;    // [N] sort keys of the large tier (written by the per-vertex pass)
+  unsigned long long* c4_keys_alt;
+  void* sort_tmp;
   int32_t tri_slots;              // workgroups of the global-scratch triangle tier
   unsigned long long* tri_scratch;  // [tri_slots][tri_scratch_words64(tri_cap)] above the LDS tier
   int64_t tri_cap;                  // out-degree capacity of a scratch slot

@@ -380,9 +380,11 @@ __global__ void k_region_fill(PoolDev P, RegionDev R, const int32_t* __restrict_
 __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const int32_t* __restrict__ rlist,
                           unsigned long long* __restrict__ cc, unsigned long long* __restrict__ sig,
                           int32_t* __restrict__ lists, int64_t list_stride, int32_t tri_small, int32_t c4_small,
-                          int32_t c4_mid, unsigned long long* __restrict__ bstats) {
+                          int32_t c4_mid, unsigned long long* __restrict__ bstats,
+                          unsigned long long* __restrict__ c4_keys) {
   const int64_t n = ctr(cc, C_RLIST);
   int cur_g = -1;
+  int32_t maxlow = 0;
   int64_t s1b = 0, s1a = 0, wb = 0, wa = 0, d1b = 0, d1a = 0, wedges = 0;
   int32_t maxdp = 0;
   int64_t maxw = 0;
@@ -436,6 +438,11 @@ __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const in
         maxw = wsum > maxw ? wsum : maxw;
         wedges += wsum;
         atomicAdd(&bstats[BS_C4_S + which - L_C4_S], (unsigned long long)(wsum + low));
+        if (which == L_C4_L) {
+          const uint64_t wk = wsum < 0xFFFFFFFFll ? (uint64_t)wsum : 0xFFFFFFFFull;
+          c4_keys[p] = ((0xFFFFFFFFull - wk) << 32) | (uint32_t)v;
+          maxlow = low > maxlow ? low : maxlow;
+        }
       }
     }
   }
@@ -450,6 +457,7 @@ __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const in
     }
     if (maxdp) atomicMax(&cc[C_MAXDP], (unsigned long long)maxdp);
     if (maxw) atomicMax(&cc[C_MAXW], (unsigned long long)maxw);
+    if (maxlow) atomicMax(&cc[C_MAXLOW], (unsigned long long)maxlow);
     if (wedges) atomicAdd(&bstats[BS_WEDGES], (unsigned long long)wedges);
   }
 }
@@ -700,9 +708,9 @@ void launch_region_fill(const PoolDev& P, const RegionDev& R, const BatchWork& W
 
 void launch_degrees(const RegionDev& R, const int32_t* gid, const int32_t* rlist, unsigned long long* c,
                     unsigned long long* sig, int32_t* lists, int64_t list_stride, int32_t tri_small, int32_t c4_small,
-                    int32_t c4_mid, unsigned long long* bstats, hipStream_t s) {
+                    int32_t c4_mid, unsigned long long* bstats, unsigned long long* c4_keys, hipStream_t s) {
   hipLaunchKernelGGL(k_degrees, dim3(4096), dim3(TPB), 0, s, R, gid, rlist, c, sig, lists, list_stride, tri_small,
-                     c4_small, c4_mid, bstats);
+                     c4_small, c4_mid, bstats, c4_keys);
 }
 
 // ---------------------------------------------------------------- build

@@ -271,12 +271,15 @@ def test_dense_graph_by_complement(n, p, seed):
             assert got == want(E)
 
 
-def test_c4_windows_tail_and_wide_counters(monkeypatch):
+@pytest.mark.parametrize("dense_min", [8, 2048, 10**12])
+def test_c4_windows_tail_and_wide_counters(monkeypatch, dense_min):
     """Small windows and a low 16-bit threshold force the large 4-cycle tier
-    through every window, the global tail and the 32-bit counter path."""
+    through many windows, the global tail and the 32-bit counter path;
+    dense_min moves the switch from dense windows to the tail."""
     monkeypatch.setenv("GC_C4_WINDOW", "128")
     monkeypatch.setenv("GC_C4_NARROW_MAX", "20")
-    say("case c4 windows 128, narrow <= 20")
+    monkeypatch.setenv("GC_C4_DENSE_MIN", str(dense_min))
+    say("case c4 windows 128, narrow <= 20, dense_min %d" % dense_min)
     n, s, d, samp = rmat_graph(13, 16, 51)
     batches = rmat_batches(n, s, d, samp, [100, 2000], 52)
     E = edge_set(s, d)
@@ -286,6 +289,8 @@ def test_c4_windows_tail_and_wide_counters(monkeypatch):
             got, st = gr.apply_batch(*b, stats=True)
             oracle_apply(E, n, *b)
             es, ed = esorted(E)
-            say("  c4 large tier %d vertices, tail wedges %d" % (st["tier_c4_large"], st["c4_tail_wedges"]))
-            assert st["c4_tail_wedges"] > 0
+            say("  c4 large tier %d vertices, tail wedges %d of %d" % (st["tier_c4_large"], st["c4_tail_wedges"],
+                                                                    st["wedges"]))
+            if dense_min > 8:
+                assert st["c4_tail_wedges"] > 0
             assert got == native.static_counts(n, es, ed)

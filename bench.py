@@ -80,6 +80,63 @@ def cpu_baseline(scale, ef, mean_batch, seed=5):
     return secs, s.size, native.threads()
 
 
+def bench_batched(args):
+    """Many independent R-MAT graphs (n log-uniform in [1e3, 2e5], edge factor
+    in {4, 8, 16}), one update batch per graph (log-uniform in [100, 1e4],
+    50/50): one pooled pass for all graphs against one call per graph.  A
+    first batch per graph warms both forms up; the second is timed."""
+    import math as _m
+    from graphgen import rmat_graph, rmat_batches
+    import paper_2308_14493_amd as pkg
+    import torch
+    rng = np.random.default_rng(4)
+    t0 = time.time()
+    work = []
+    for i in range(args.graphs):
+        n = int(round(10 ** rng.uniform(3, _m.log10(2e5))))
+        ef = int(rng.choice([4, 8, 16]))
+        sizes = [int(round(10 ** rng.uniform(2, 4))) for _ in range(2)]
+        scale = max(1, _m.ceil(_m.log2(n)))
+        gs = int(rng.integers(0, 2**31 - 1))
+        n, s, d, samp = rmat_graph(scale, ef, gs, n=n)
+        work.append((n, s, d, rmat_batches(n, s, d, samp, sizes, gs + 1)))
+    m_tot = sum(w[1].size for w in work)
+    log("generated %d graphs (sum m = %d) in %.1fs" % (len(work), m_tot, time.time() - t0))
+    pkg.load()
+    torch.cuda.init()
+    offered = sum(w[3][1][0].size + w[3][1][2].size for w in work)
+    # pooled
+    pool = pkg.Graph.pool([w[0] for w in work], [w[1] for w in work], [w[2] for w in work], radius=args.radius)
+    pool.apply_batches([w[3][0] for w in work])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pooled, pst = pool.apply_batches([w[3][1] for w in work], stats=True)
+    t_pool = time.perf_counter() - t1
+    pool.close()
+    log("pooled pass: %.2f ms for %d updates" % (t_pool * 1e3, offered))
+    # graph by graph
+    seq, t_seq = [], 0.0
+    for n, s, d, bs in work:
+        g = pkg.Graph(n, s, d, radius=args.radius)
+        g.apply_batch(*bs[0])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        seq.append(g.apply_batch(*bs[1]))
+        t_seq += time.perf_counter() - t1
+        g.close()
+    log("graph by graph: %.2f ms" % (t_seq * 1e3))
+    same = seq == pooled
+    out = {"metric": "updates/sec, %d-graph pool, one batch per graph" % len(work),
+           "value": offered / t_pool, "unit": "updates/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": t_pool * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "int64", "data": "synthetic",
+           "config": {"workload": "%d R-MAT graphs, n log-uniform [1e3, 2e5], ef {4,8,16}, sum m = %d, one batch "
+                                  "per graph log-uniform [100, 1e4], 50/50" % (len(work), m_tot), "form": "batched"},
+           "sequential_updates_per_s": offered / t_seq, "sequential_ms": t_seq * 1e3,
+           "speedup_vs_sequential": t_seq / t_pool, "results_equal": same}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +152,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recount-check", action="store_true")
     ap.add_argument("--host-steps", type=int, default=3, help="extra batches through the host-array entry point")
+    ap.add_argument("--form", choices=["plain", "batched"], default="plain",
+                    help="plain: one graph, one batch per call; batched: a pool of many graphs, one batch per "
+                         "graph per call, against the same batches applied graph by graph")
+    ap.add_argument("--graphs", type=int, default=256)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB copied device-to-device once before the batches (a plain copy kernel of known size, "
                          "for scaling hardware byte counters)")
@@ -108,6 +169,8 @@ def main():
 
     from graphgen import rmat_graph, BatchStream, log_uniform_sizes
     import paper_2308_14493_amd as pkg
+    if args.form == "batched":
+        return bench_batched(args)
 
     t0 = time.time()
     n, s, d, sampler = rmat_graph(args.scale, args.ef, args.seed)

@@ -244,6 +244,7 @@ void run_count(gc_graph* G, int radius, long long* state_d, BatchWork& W, std::v
     // one resident 1024-thread block per CU is enough to fill the chip
     int64_t budget = (int64_t)16 << 30;
     int64_t slots = std::max<int64_t>(1, std::min<int64_t>(256, budget / std::max<int64_t>(per, 1)));
+    slots = std::min<int64_t>(slots, ncl);  // small graphs: fewer hubs than workgroups
     if (slots > G->c4_slots) {
       G->c4_dense.release();
       G->c4_touch.release();

@@ -137,6 +137,92 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_served(args):
+    """Serving: the R-MAT graph resident in a server; one fixed sequence of
+    batches (sizes log-uniform in [min, max], 50/50) is offered as a Poisson
+    stream at 0.5x, 0.9x and 1.5x the saturation rate of the plain path
+    (1 / mean service time, measured on the same sequence through the server
+    one request at a time).  Between rates the inverse batches, applied in
+    reverse order, restore the graph so that every rate sees the same
+    sequence on the same graph.  Latency = submit -> counts on the host."""
+    import threading
+    from graphgen import rmat_graph, BatchStream, log_uniform_sizes, poisson_arrivals
+    import paper_2308_14493_amd as pkg
+    import torch
+    t0 = time.time()
+    n, s, d, sampler = rmat_graph(args.scale, args.ef, args.seed)
+    sizes = log_uniform_sizes(args.requests, args.min_batch, args.max_batch, args.seed + 5)
+    stream = BatchStream.from_edges(n, s, d, args.seed + 6, ins_sampler=sampler)
+    batches = [stream.next_batch(sz // 2, sz - sz // 2) for sz in sizes]
+    inverse = [(b[2], b[3], b[0], b[1]) for b in reversed(batches)]
+    offered = sum(b[0].size + b[2].size for b in batches)
+    log("generated graph and %d batches in %.1fs (sizes %s)" % (len(batches), time.time() - t0, sizes))
+    pkg.load()
+    torch.cuda.init()
+    srv = pkg.Server()
+    gid = srv.add_graph(n, s, d, radius=args.radius)
+    base = srv.counts(gid)
+
+    def closed_loop(seq):
+        out = []
+        for b in seq:
+            out.append(srv.wait(srv.submit(gid, *b)))
+        return out
+
+    closed_loop(batches[:1] + [(batches[0][2], batches[0][3], batches[0][0], batches[0][1])])  # warm-up
+    t1 = time.perf_counter()
+    plain = closed_loop(batches)
+    t_plain = time.perf_counter() - t1
+    final = srv.counts(gid)
+    closed_loop(inverse)
+    assert srv.counts(gid) == base
+    service = t_plain / len(batches)
+    runs = {}
+    for f in (0.5, 0.9, 1.5):
+        arr = poisson_arrivals(f / service, len(batches), args.seed + int(f * 10))
+        tickets, subs = [None] * len(batches), [0.0] * len(batches)
+        start = time.perf_counter()
+
+        def feeder():
+            for i, b in enumerate(batches):
+                dt = start + arr[i] - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                subs[i] = time.perf_counter()
+                tickets[i] = srv.submit(gid, *b)
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        lat, same = [], True
+        for i in range(len(batches)):
+            while tickets[i] is None:
+                time.sleep(0.0005)
+            c, st, l, q = srv.wait(tickets[i])
+            lat.append(l)
+            same &= [int(x) for x in c] == [int(x) for x in plain[i][0]]
+        end = time.perf_counter()
+        th.join()
+        assert srv.counts(gid) == final
+        runs["%.1fx" % f] = {"offered_rate_batches_per_s": f / service, "updates_per_s": offered / (end - start),
+                             "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+                             "results_equal_to_plain": bool(same)}
+        log("rate %.1fx: %s" % (f, runs["%.1fx" % f]))
+        closed_loop(inverse)
+        assert srv.counts(gid) == base
+    srv.close()
+    out = {"metric": "updates/sec + p50/p99 batch latency, served, exact 4-graphlet counts, R-MAT s%d" % args.scale,
+           "value": max(r["updates_per_s"] for r in runs.values()), "unit": "updates/s", "n_gpus": 1,
+           "steps": len(batches), "warmup": 1, "ms_per_step": service * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": "R-MAT scale %d ef %d, %d batches log-uniform [%g, %g], Poisson arrivals at "
+                                  "0.5/0.9/1.5x plain saturation" % (args.scale, args.ef, len(batches),
+                                                                     args.min_batch, args.max_batch),
+                      "form": "served"},
+           "plain_closed_loop_updates_per_s": offered / t_plain, "plain_p50_ms": percentile([p[2] for p in plain], 50),
+           "rates": runs}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,10 +238,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recount-check", action="store_true")
     ap.add_argument("--host-steps", type=int, default=3, help="extra batches through the host-array entry point")
-    ap.add_argument("--form", choices=["plain", "batched"], default="plain",
+    ap.add_argument("--form", choices=["plain", "batched", "served"], default="plain",
                     help="plain: one graph, one batch per call; batched: a pool of many graphs, one batch per "
                          "graph per call, against the same batches applied graph by graph")
     ap.add_argument("--graphs", type=int, default=256)
+    ap.add_argument("--requests", type=int, default=8, help="served form: batches per offered rate")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB copied device-to-device once before the batches (a plain copy kernel of known size, "
                          "for scaling hardware byte counters)")
@@ -171,6 +258,8 @@ def main():
     import paper_2308_14493_amd as pkg
     if args.form == "batched":
         return bench_batched(args)
+    if args.form == "served":
+        return bench_served(args)
 
     t0 = time.time()
     n, s, d, sampler = rmat_graph(args.scale, args.ef, args.seed)

@@ -171,6 +171,52 @@ int gc_export_edges(gc_graph* g, int32_t graph, int32_t* src, int32_t* dst, int6
 
 int gc_graph_free(gc_graph* g);
 
+/* ------------------------------------------------------------- serving
+ * A server keeps graphs resident on one device, each with its own stream and
+ * worker thread, and answers asynchronously submitted update batches through
+ * tickets.  Batches for different graphs run at the same time (their kernels
+ * overlap on the device); batches for one graph are applied in submission
+ * order, and each ticket's result is the counts right after its batch, the
+ * same as gc_apply_batch would return in that order.  Admission by memory:
+ * a graph is admitted only if its estimated footprint fits the free HBM
+ * (hipMemGetInfo, or hbm_budget_bytes when > 0) minus hbm_reserve_bytes,
+ * else GC_ENOMEM; a batch starts only while the estimated bytes of batches in
+ * flight stay within batch_budget_bytes (one batch always runs).  A server
+ * may be used from several host threads. */
+typedef struct gc_server gc_server;
+
+typedef struct {
+  int32_t device;              /* HIP device (default 0) */
+  int32_t max_graphs;          /* resident graphs (default 64) */
+  int64_t hbm_reserve_bytes;   /* kept free when admitting a graph (default 8 GiB) */
+  int64_t hbm_budget_bytes;    /* > 0: use this instead of the device's free memory */
+  int64_t batch_budget_bytes;  /* bytes of batches in flight (default 4 GiB) */
+} gc_server_opts;
+
+int gc_server_opts_default(gc_server_opts* opts);
+int gc_server_create(const gc_server_opts* opts /* NULL = defaults */, gc_server** out);
+
+/* Builds a resident graph (as gc_graph_init; opt->stream is ignored) and
+ * returns its id.  GC_ENOMEM: refused by memory admission; GC_EBUSY: full. */
+int gc_server_add_graph(gc_server* s, int64_t n, const int32_t* src, const int32_t* dst, int64_t m,
+                        const gc_options* opt, int32_t* graph_id);
+
+/* Queues one batch (host arrays, copied before return) for a graph. */
+int gc_server_submit(gc_server* s, int32_t graph_id, const gc_batch_desc* batch, uint64_t* ticket);
+
+/* Blocks until the ticket's batch is applied; returns its status and, when
+ * the pointers are non-NULL, the counts after it, its statistics, and
+ * latency_ms[0] = submit -> result, latency_ms[1] = submit -> start.
+ * A ticket can be waited on once. */
+int gc_server_wait(gc_server* s, uint64_t ticket, int64_t counts[11], gc_batch_stats* stats,
+                   double latency_ms[2]);
+
+/* Exact counts of a graph once every batch submitted for it is applied. */
+int gc_server_counts(gc_server* s, int32_t graph_id, int64_t hi[11], uint64_t lo[11]);
+
+/* Finishes the queued batches, stops the workers and frees every graph. */
+int gc_server_destroy(gc_server* s);
+
 const char* gc_strerror(int code);
 const char* gc_last_error(void);
 

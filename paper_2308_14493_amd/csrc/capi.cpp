@@ -108,6 +108,8 @@ constexpr int C4_MID = 4096;
 
 }  // namespace
 
+void gc_set_error(const char* msg) { g_err = msg ? msg : ""; }
+
 struct gc_graph {
   int device = 0;
   hipStream_t stream = nullptr;

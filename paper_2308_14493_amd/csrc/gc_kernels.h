@@ -109,3 +109,6 @@ int64_t tri_scratch_words64(int64_t cap);  // u64 words of one triangle scratch 
 int32_t tri_lds_max();
 int32_t c4_window_max();                      // largest out-degree of the LDS triangle tier
 void launch_combine(const unsigned long long* sig, long long* state, int32_t k, hipStream_t s);
+
+// capi.cpp: thread-local error text read by gc_last_error()
+void gc_set_error(const char* msg);

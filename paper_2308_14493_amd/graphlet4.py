@@ -56,7 +56,14 @@ _lib = None
 
 EXPORTS = ["gc_options_default", "gc_graph_init", "gc_pool_init", "gc_apply_batch", "gc_apply_batch_dev",
            "gc_apply_batches", "gc_get_counts", "gc_get_counts_exact", "gc_recount_exact", "gc_graph_info",
-           "gc_export_edges", "gc_graph_free", "gc_strerror", "gc_last_error"]
+           "gc_export_edges", "gc_graph_free", "gc_strerror", "gc_last_error",
+           "gc_server_opts_default", "gc_server_create", "gc_server_add_graph", "gc_server_submit",
+           "gc_server_wait", "gc_server_counts", "gc_server_destroy"]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("device", _I32), ("max_graphs", _I32), ("hbm_reserve_bytes", _I64),
+                ("hbm_budget_bytes", _I64), ("batch_budget_bytes", _I64)]
 
 
 def load(path: str = LIB_PATH):
@@ -86,6 +93,13 @@ def load(path: str = LIB_PATH):
     lib.gc_graph_info.argtypes = [_P, ctypes.POINTER(_I32), _I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]
     lib.gc_export_edges.argtypes = [_P, _I32, _P, _P, _I64, ctypes.POINTER(_I64)]
     lib.gc_graph_free.argtypes = [_P]
+    lib.gc_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
+    lib.gc_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)]
+    lib.gc_server_add_graph.argtypes = [_P, _I64, _P, _P, _I64, ctypes.POINTER(Options), ctypes.POINTER(_I32)]
+    lib.gc_server_submit.argtypes = [_P, _I32, ctypes.POINTER(BatchDesc), ctypes.POINTER(ctypes.c_uint64)]
+    lib.gc_server_wait.argtypes = [_P, ctypes.c_uint64, _P, ctypes.POINTER(BatchStats), _P]
+    lib.gc_server_counts.argtypes = [_P, _I32, _P, _P]
+    lib.gc_server_destroy.argtypes = [_P]
     lib.gc_strerror.argtypes = [ctypes.c_int]
     lib.gc_strerror.restype = ctypes.c_char_p
     lib.gc_last_error.restype = ctypes.c_char_p
@@ -250,3 +264,73 @@ class Graph:
         mo = _I64()
         _check(lib.gc_export_edges(self._h, graph, s.ctypes.data, d.ctypes.data, s.size, ctypes.byref(mo)))
         return s[: mo.value], d[: mo.value]
+
+
+class Server:
+    """Serving loop: resident graphs answering asynchronously submitted
+    batches through tickets (see gc_server_* in include/graphlet4.h)."""
+
+    def __init__(self, device=0, max_graphs=64, hbm_reserve_bytes=None, hbm_budget_bytes=0,
+                 batch_budget_bytes=None):
+        lib = load()
+        o = ServerOpts()
+        lib.gc_server_opts_default(ctypes.byref(o))
+        o.device = device
+        o.max_graphs = max_graphs
+        if hbm_reserve_bytes is not None:
+            o.hbm_reserve_bytes = hbm_reserve_bytes
+        o.hbm_budget_bytes = hbm_budget_bytes
+        if batch_budget_bytes is not None:
+            o.batch_budget_bytes = batch_budget_bytes
+        self._h = _P()
+        _check(lib.gc_server_create(ctypes.byref(o), ctypes.byref(self._h)))
+
+    def add_graph(self, n, src, dst, radius=None, slack=None):
+        lib = load()
+        s, d = _i32(src), _i32(dst)
+        opt = _opts(radius, slack, 0, None)
+        gid = _I32()
+        _check(lib.gc_server_add_graph(self._h, int(n), s.ctypes.data, d.ctypes.data, s.size, ctypes.byref(opt),
+                                       ctypes.byref(gid)))
+        return gid.value
+
+    def submit(self, graph, ins_src=(), ins_dst=(), del_src=(), del_dst=()):
+        lib = load()
+        iu, iv, du, dv = _i32(ins_src), _i32(ins_dst), _i32(del_src), _i32(del_dst)
+        desc = BatchDesc(iu.ctypes.data, iv.ctypes.data, iu.size, du.ctypes.data, dv.ctypes.data, du.size)
+        t = ctypes.c_uint64()
+        _check(lib.gc_server_submit(self._h, graph, ctypes.byref(desc), ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket):
+        """Returns (int64 counts, stats dict, latency ms, queueing ms)."""
+        lib = load()
+        out = np.zeros(11, np.int64)
+        st = BatchStats()
+        lat = np.zeros(2, np.float64)
+        _check(lib.gc_server_wait(self._h, ticket, out.ctypes.data, ctypes.byref(st), lat.ctypes.data))
+        return out, st.as_dict(), float(lat[0]), float(lat[1])
+
+    def counts(self, graph):
+        lib = load()
+        hi = np.zeros(11, np.int64)
+        lo = np.zeros(11, np.uint64)
+        _check(lib.gc_server_counts(self._h, graph, hi.ctypes.data, lo.ctypes.data))
+        return _join(hi, lo)
+
+    def close(self):
+        if self._h:
+            load().gc_server_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -33,3 +33,21 @@ def test_error_strings_without_device():
     assert lib.gc_options_default(ctypes.byref(o)) == 0
     assert o.radius == 2 and abs(o.slack - 0.25) < 1e-6
     assert lib.gc_options_default(None) == -1
+
+
+def test_server_admission_refusal_without_device():
+    """A fake memory budget refuses a graph before any device work."""
+    from paper_2308_14493_amd.graphlet4 import Server, GraphletError
+    with Server(hbm_budget_bytes=1024, hbm_reserve_bytes=0) as srv:
+        try:
+            srv.add_graph(100, [0, 1], [1, 2])
+        except GraphletError as e:
+            assert e.code == -2 and "HBM" in str(e)
+        else:
+            raise AssertionError("admission should refuse")
+    lib = graphlet4.load()
+    o = graphlet4.ServerOpts()
+    lib.gc_server_opts_default(ctypes.byref(o))
+    o.max_graphs = 0
+    h = ctypes.c_void_p()
+    assert lib.gc_server_create(ctypes.byref(o), ctypes.byref(h)) == -1

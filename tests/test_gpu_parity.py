@@ -294,3 +294,53 @@ def test_c4_windows_tail_and_wide_counters(monkeypatch, dense_min):
             if dense_min > 8:
                 assert st["c4_tail_wedges"] > 0
             assert got == native.static_counts(n, es, ed)
+
+
+def test_server_results_same_alone_and_in_the_mix():
+    """Requests for three graphs submitted from two host threads, interleaved:
+    every ticket's counts equal the counts of the same batch sequence applied
+    to a separate handle alone, and the oracle."""
+    import threading
+    from paper_2308_14493_amd.graphlet4 import Server, Graph
+    say("case server mix")
+    specs = []
+    n, s, d, samp = rmat_graph(10, 8, 61)
+    specs.append((n, s, d, rmat_batches(n, s, d, samp, [20, 200, 50, 300], 62)))
+    s2, d2 = erdos_renyi(150, 6 / 149, 0)
+    specs.append((150, s2, d2, er_batches(150, s2, d2, count=4)))
+    n3, s3, d3, _ = chung_lu_graph(5000, 15000, 2.1, 800.0, 63)
+    specs.append((n3, s3, d3, chung_lu_batches(n3, s3, d3, [30, 300, 100, 10], 64)))
+    alone = []
+    for n_, s_, d_, bs in specs:
+        with Graph(n_, s_, d_) as g:
+            alone.append([g.apply_batch(*b) for b in bs])
+    with Server() as srv:
+        gids = [srv.add_graph(n_, s_, d_) for n_, s_, d_, _ in specs]
+        tickets = {}
+        lock = threading.Lock()
+
+        def client(which):
+            for j in range(4):
+                for gi in which:
+                    t = srv.submit(gids[gi], *specs[gi][3][j])
+                    with lock:
+                        tickets[(gi, j)] = t
+
+        # graph 0 from one thread, graphs 1 and 2 from another (per-graph order kept)
+        th = [threading.Thread(target=client, args=([0],)), threading.Thread(target=client, args=([1, 2],))]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        for (gi, j), t in sorted(tickets.items()):
+            c, st, lat, qms = srv.wait(t)
+            assert [int(v) for v in c] == [v & ((1 << 64) - 1) if v < 2**63 else v - 2**64 for v in alone[gi][j]]
+            assert lat >= qms >= 0
+        for gi in range(3):
+            assert srv.counts(gids[gi]) == alone[gi][-1]
+    for gi, (n_, s_, d_, bs) in enumerate(specs):
+        E = edge_set(s_, d_)
+        for b in bs:
+            oracle_apply(E, n_, *b)
+        es, ed = esorted(E)
+        assert alone[gi][-1] == native.static_counts(n_, es, ed)

@@ -227,7 +227,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--ef", type=int, default=16)
     ap.add_argument("--seed", type=int, default=22)
@@ -301,10 +301,11 @@ def main():
             lat.append((t2 - t1) * 1e3)
             offered += b[0].size + b[2].size
             stats.append(st)
-        log("step %d: batch %d updates, %.2f ms (tri %.2f edge %.2f c4 %.2f/%.2f/%.2f prep %.2f fin %.2f) "
+        log("step %d: batch %d updates, %.2f ms (tri %.2f edge %.2f c4 %.2f/%.2f/%.2f prep %.2f fin %.2f) dmin %d whole %d "
             "region_e=%d c4_tail=%d/%d" % (i, b[0].size + b[2].size, (t2 - t1) * 1e3, st["ms_tri"], st["ms_edge"],
                                            st["ms_c4_small"], st["ms_c4_mid"], st["ms_c4_large"], st["ms_prepare"],
-                                           st["ms_finish"], st["region_entries"], st["c4_tail_wedges"], st["wedges"]))
+                                           st["ms_finish"], st["c4_dense_min"], st["whole_graph"], st["region_entries"],
+                                           st["c4_tail_wedges"], st["wedges"]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - tstart
     value = offered / elapsed

@@ -92,6 +92,12 @@ typedef struct {
   int32_t device;
   /* hipStream_t to run on (NULL = the library's own stream). */
   void* stream;
+  /* 1 (default): online autotuning of speed knobs; results never change.
+   * The first batches each try one density threshold of the hub windows of
+   * the 4-cycle count and the fastest per wedge is kept; per batch-size
+   * decade, once the region of change covers >= 90% of the graph, later
+   * batches of that size count the whole graph (same result, no marking). */
+  int32_t autotune;
 } gc_options;
 
 typedef struct {
@@ -105,6 +111,8 @@ typedef struct {
   int64_t c4_tail_wedges;            /* wedges of the large tier counted in global memory */
   int64_t max_out_degree;
   int64_t tier_tri_small, tier_tri_large, tier_c4_small, tier_c4_mid, tier_c4_large;  /* vertices per tier */
+  int64_t c4_dense_min;              /* hub-window density threshold used */
+  int32_t whole_graph;               /* 1: counted the whole graph instead of the region */
   uint32_t overflow_mask;            /* classes whose count left int64 */
   float ms_total;                    /* wall time of the call */
   float ms_prepare;                  /* ingest, merge, region, per-vertex pass (device) */

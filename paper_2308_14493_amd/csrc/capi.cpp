@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -136,11 +137,18 @@ struct gc_graph {
   DevBuf touched, dest, newcap, tlen, tpre, scratch, sort_tmp, scan_tmp;
 
   // region and counting
-  DevBuf roff, rcol, rlow, dB, dA, t, level, rlist, rlen, lists;
+  DevBuf roff, rcol, rlow, dB, dA, t, vpos, level, rlist, rlen, lists;
   DevBuf c4_dense, c4_touch, c4_cur, c4_keys, c4_keys_alt, tri_scratch;
   int64_t c4_cur_low = 0;
   int32_t c4_slots = 0, tri_slots = 0;
   int64_t tri_cap = 0;
+
+  // online autotuner (speed knobs only)
+  std::vector<int64_t> tune_cands{512, 1024, 2048, 4096, 8192};
+  std::vector<double> tune_ms, tune_wedges;
+  int tune_next = 0;
+  int64_t dense_min_best = 2048;
+  double region_frac[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
 
   void* pin = nullptr;
   size_t pin_cap = 0;
@@ -175,6 +183,7 @@ struct gc_graph {
     R.dB = dB.as<int32_t>();
     R.dA = dA.as<int32_t>();
     R.t = t.as<unsigned long long>();
+    R.vpos = vpos.as<int32_t>();
     return R;
   }
   void* pinned(size_t bytes) {
@@ -206,7 +215,7 @@ void zero_small(gc_graph* G) {
 // Region + per-vertex pass + counting + combine into `state_d`.  `radius` < 0
 // counts every vertex.  Host copy of the counters goes to hc.
 void run_count(gc_graph* G, int radius, long long* state_d, BatchWork& W, std::vector<unsigned long long>& hc,
-               int64_t union_entries, bool timed) {
+               int64_t union_entries, bool timed, int64_t dense_min = 2048) {
   hipStream_t s = G->stream;
   const int64_t N = G->N;
   G->roff.ensure((N + 1) * sizeof(int64_t));
@@ -215,6 +224,7 @@ void run_count(gc_graph* G, int radius, long long* state_d, BatchWork& W, std::v
   G->sort_tmp.ensure(radix_sort_tmp_bytes(N) + 64);
   G->rcol.ensure(std::max<int64_t>(union_entries, 1) * sizeof(uint32_t));
   G->t.ensure(std::max<int64_t>(union_entries, 1) * sizeof(unsigned long long));
+  G->vpos.ensure(std::max<int64_t>(union_entries, 1) * sizeof(int32_t));
   G->scan_tmp.ensure(scan_tmp_bytes(N + 1) + 64);
   PoolDev P = G->pd();
   RegionDev R = G->rd();
@@ -262,7 +272,7 @@ void run_count(gc_graph* G, int radius, long long* state_d, BatchWork& W, std::v
   A.c4_narrow_max = 65535;
   if (const char* e = std::getenv("GC_C4_WINDOW")) A.c4_win = std::max(64, std::min(c4_window_max(), std::atoi(e)));
   if (const char* e = std::getenv("GC_C4_NARROW_MAX")) A.c4_narrow_max = std::max(0, std::min(65535, std::atoi(e)));
-  A.c4_dense_min = 2048;
+  A.c4_dense_min = dense_min;
   if (const char* e = std::getenv("GC_C4_DENSE_MIN")) A.c4_dense_min = std::max<int64_t>(0, std::atoll(e));
   {
     const int64_t maxlow = std::max<int64_t>(1, (int64_t)hc[C_MAXLOW]);
@@ -693,10 +703,23 @@ void apply(gc_graph* G, const gc_batch_desc* b, bool dev, int64_t (*counts)[11],
   launch_flag_del(P, W, 2 * ndl, G->bits, bst, s);
 
   std::vector<unsigned long long> hc;
-  const int radius = G->opt.radius == 0 ? -1 : G->opt.radius;
-  run_count(G, radius, G->state.as<long long>(), W, hc, union_bound, timed);
+  int radius = G->opt.radius == 0 ? -1 : G->opt.radius;
+  int64_t dense_min = 2048;
+  int tune_idx = -1;
+  const int decade = (int)std::min<double>(7.0, std::floor(std::log10((double)total + 1.0)));
+  if (G->opt.autotune) {
+    if (G->tune_next < (int)G->tune_cands.size()) {
+      tune_idx = G->tune_next;
+      dense_min = G->tune_cands[tune_idx];
+    } else {
+      dense_min = G->dense_min_best;
+    }
+    if (radius >= 2 && G->region_frac[decade] >= 0.9) radius = -1;  // exact radii only
+  }
+  const bool timed_run = timed || (G->opt.autotune && tune_idx >= 0);
+  run_count(G, radius, G->state.as<long long>(), W, hc, union_bound, timed_run, dense_min);
   launch_purge(P, W, max_touched, G->bits, G->scan_tmp.p, s);
-  if (timed) HIPCHK(hipEventRecord(G->ev[8], s));
+  if (timed_run) HIPCHK(hipEventRecord(G->ev[8], s));
 
   std::vector<unsigned long long> hb(BS_COUNT);
   G->hstate.resize((size_t)k * ST_STRIDE);
@@ -724,8 +747,29 @@ void apply(gc_graph* G, const gc_batch_desc* b, bool dev, int64_t (*counts)[11],
     to_int64(I, counts ? counts[g] : tmp, &mk);
     ovf_all |= mk;
   }
+  if (G->opt.autotune) {
+    if (radius > 0 && union_bound > 0)
+      G->region_frac[decade] = (double)hc[C_ER] / (double)std::max<int64_t>(1, G->entries);
+    if (tune_idx >= 0) {
+      float c4ms = 0;
+      (void)hipEventElapsedTime(&c4ms, G->ev[6], G->ev[7]);
+      G->tune_ms.push_back(c4ms);
+      G->tune_wedges.push_back((double)hb[BS_WEDGES] + 1.0);
+      ++G->tune_next;
+      if (G->tune_next == (int)G->tune_cands.size()) {
+        int best = 0;
+        for (int i = 1; i < (int)G->tune_ms.size(); ++i)
+          if (G->tune_ms[i] / G->tune_wedges[i] < G->tune_ms[best] / G->tune_wedges[best]) best = i;
+        G->dense_min_best = G->tune_cands[best];
+      }
+    }
+  }
   const double ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
   fill_stats(G, stats, hb, hc, ni, ndl, timed, ms, ovf_all);
+  if (stats) {
+    stats->c4_dense_min = dense_min;
+    stats->whole_graph = radius < 0;
+  }
 }
 
 template <class F>
@@ -754,6 +798,7 @@ int gc_options_default(gc_options* opt) {
   opt->slack = 0.25f;
   opt->device = 0;
   opt->stream = nullptr;
+  opt->autotune = 1;
   return GC_OK;
 }
 

@@ -432,7 +432,7 @@ constexpr int TL_MAX = 1024;
 //   T3  += t                        (= 3 T)
 //   PAW2 += t (d_u + d_w - 4)       (= 2 N_paw: a triangle on the edge plus a
 //                                    pendant edge at one of its ends)
-constexpr int EP_RUN = 16;
+constexpr int EP_RUN = 128;
 
 __global__ __launch_bounds__(256) void k_edge_pass(CountArgs A) {
   const RegionDev& R = A.R;
@@ -649,6 +649,11 @@ __device__ __forceinline__ void block_sum2(C4Chunk& C, long long& x, long long& 
 
 // Walk the wedges (v, u_q, w) for q in [0, nlow) with w in row u_q at
 // positions [urow[q] + p0(q), urow[q] + p1(q)); f(w, add_b, add_a).
+// Short slices (the common case: u_q has few entries in the id range) are
+// walked by their own thread; long ones are spread over the whole block
+// with a scan of their lengths and a binary search per element.
+constexpr int32_t C4W_SHORT = 8;
+
 template <class P0, class P1, class F>
 __device__ __forceinline__ void c4_block_walk(const RegionDev& R, int64_t rb, int32_t nlow, const int64_t* urow,
                                               P0 p0f, P1 p1f, C4Chunk& C, F f) {
@@ -658,28 +663,41 @@ __device__ __forceinline__ void c4_block_walk(const RegionDev& R, int64_t rb, in
     int32_t sl = 0;
     if (q < nlow) {
       const int32_t p0 = p0f(q), p1 = p1f(q);
-      C.sb[t] = urow[q] + p0;
-      C.fl[t] = R.rcol[rb + q] & GC_FLAGS;
-      sl = p1 - p0;
+      const int64_t sb = urow[q] + p0;
+      const uint32_t fl = R.rcol[rb + q] & GC_FLAGS;
+      if (p1 - p0 <= C4W_SHORT) {
+        for (int64_t p = sb; p < sb + (p1 - p0); ++p) {
+          const uint32_t y = R.rcol[p];
+          const uint32_t ab = fl | (y & GC_FLAGS);
+          const uint32_t xb = !(ab & GC_F_NEW), xa = !(ab & GC_F_DEL);
+          if (xb | xa) f(y & GC_ID, xb, xa);
+        }
+      } else {
+        C.sb[t] = sb;
+        C.fl[t] = fl;
+        sl = p1 - p0;
+      }
     }
+    // long slices: block-wide flattened walk (skipped when there are none)
     const int32_t inc = wave_incl_scan32(sl);
     if (l == 63) C.wsum[wv] = inc;
     __syncthreads();
-    int32_t before = 0;
-    for (int k = 0; k < wv; ++k) before += C.wsum[k];
-    C.pre[t] = before + inc - sl;
-    if (t == C4W_T - 1) C.pre[C4W_T] = before + inc;
-    __syncthreads();
-    const int32_t tot = C.pre[C4W_T];
-    for (int32_t base = 0; base < tot; base += C4W_T) {
-      const int32_t idx = base + t;
-      if (idx < tot) {
-        int32_t a = 0, z = C4W_T;  // largest a with pre[a] <= idx
-        while (z - a > 1) { const int32_t m = (a + z) >> 1; if (C.pre[m] <= idx) a = m; else z = m; }
-        const uint32_t y = R.rcol[C.sb[a] + (idx - C.pre[a])];
-        const uint32_t ab = C.fl[a] | (y & GC_FLAGS);
-        const uint32_t xb = !(ab & GC_F_NEW), xa = !(ab & GC_F_DEL);
-        if (xb | xa) f(y & GC_ID, xb, xa);
+    int32_t before = 0, tot = 0;
+    for (int k = 0; k < C4W_T / 64; ++k) { if (k < wv) before += C.wsum[k]; tot += C.wsum[k]; }
+    if (tot > 0) {
+      C.pre[t] = before + inc - sl;
+      if (t == C4W_T - 1) C.pre[C4W_T] = before + inc;
+      __syncthreads();
+      for (int32_t base = 0; base < tot; base += C4W_T) {
+        const int32_t idx = base + t;
+        if (idx < tot) {
+          int32_t a = 0, z = C4W_T;  // largest a with pre[a] <= idx
+          while (z - a > 1) { const int32_t m = (a + z) >> 1; if (C.pre[m] <= idx) a = m; else z = m; }
+          const uint32_t y = R.rcol[C.sb[a] + (idx - C.pre[a])];
+          const uint32_t ab = C.fl[a] | (y & GC_FLAGS);
+          const uint32_t xb = !(ab & GC_F_NEW), xa = !(ab & GC_F_DEL);
+          if (xb | xa) f(y & GC_ID, xb, xa);
+        }
       }
     }
     __syncthreads();
@@ -717,10 +735,8 @@ __global__ __launch_bounds__(C4W_T) void k_c4_large(CountArgs A, unsigned long l
     const bool narrow = nlow <= A.c4_narrow_max;
     const int64_t ws = narrow ? 2 * (int64_t)A.c4_win : (int64_t)A.c4_win;
     for (int32_t q = t; q < nlow; q += C4W_T) {
-      const uint32_t u = R.rcol[rb + q] & GC_ID;
-      const int64_t b = R.roff[u];
-      urow[q] = b;
-      ucur[q] = lower_bound_id(R.rcol + b, (int32_t)(R.roff[u + 1] - b), (uint32_t)v);
+      urow[q] = R.roff[R.rcol[rb + q] & GC_ID];
+      ucur[q] = R.vpos[rb + q];
     }
     __syncthreads();
     int64_t hi = v;

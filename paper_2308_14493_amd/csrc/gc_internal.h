@@ -73,6 +73,7 @@ struct RegionDev {
   int32_t* dB;         // [N] degree in version b inside the region
   int32_t* dA;         // [N] degree in version a inside the region
   unsigned long long* t;  // [E_R] per upper entry: t_b | t_a << 32
+  int32_t* vpos;       // [E_R] per lower entry v -> w: position of v in row w
 };
 
 // ------------------------------------------------------------------ helpers

@@ -401,10 +401,13 @@ __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const in
       da += !(x & GC_F_DEL);
       const uint32_t w = x & GC_ID;
       if (w < (uint32_t)v) {
-        // wedges (v, w, .) below v: entries of row w smaller than v
+        // wedges (v, w, .) below v: entries of row w smaller than v (kept
+        // for the 4-cycle kernels as the starting cursor in row w)
         low += 1;
         const int64_t wb = R.roff[w];
-        wsum += lower_bound_id(R.rcol + wb, (int32_t)(R.roff[w + 1] - wb), (uint32_t)v);
+        const int32_t pos = lower_bound_id(R.rcol + wb, (int32_t)(R.roff[w + 1] - wb), (uint32_t)v);
+        R.vpos[b + k] = pos;
+        wsum += pos;
       }
     }
     db = wave_sum32(db); da = wave_sum32(da); low = wave_sum32(low);

@@ -24,7 +24,7 @@ _P = ctypes.c_void_p
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("radius", _I32), ("slack", ctypes.c_float), ("device", _I32), ("stream", _P)]
+    _fields_ = [("radius", _I32), ("slack", ctypes.c_float), ("device", _I32), ("stream", _P), ("autotune", _I32)]
 
 
 class BatchStats(ctypes.Structure):
@@ -33,7 +33,7 @@ class BatchStats(ctypes.Structure):
         "ins_existing", "del_missing", "touched_vertices", "region_vertices", "region_entries",
         "wedges", "c4_entries_small", "c4_entries_mid", "c4_entries_large", "c4_tail_wedges",
         "max_out_degree", "tier_tri_small", "tier_tri_large", "tier_c4_small",
-        "tier_c4_mid", "tier_c4_large")] + [("overflow_mask", ctypes.c_uint32)] + [
+        "tier_c4_mid", "tier_c4_large", "c4_dense_min")] + [("whole_graph", _I32), ("overflow_mask", ctypes.c_uint32)] + [
         (n, ctypes.c_float) for n in ("ms_total", "ms_prepare", "ms_tri", "ms_edge", "ms_c4_small",
                                       "ms_c4_mid", "ms_c4_large", "ms_finish")]
 
@@ -123,10 +123,12 @@ def _join(hi, lo):
     return [(int(h) << 64) | int(l) for h, l in zip(hi.tolist(), lo.tolist())]
 
 
-def _opts(radius, slack, device, stream):
+def _opts(radius, slack, device, stream, autotune=None):
     lib = load()
     o = Options()
     lib.gc_options_default(ctypes.byref(o))
+    if autotune is not None:
+        o.autotune = int(autotune)
     if radius is not None:
         o.radius = radius
     if slack is not None:
@@ -139,10 +141,11 @@ def _opts(radius, slack, device, stream):
 class Graph:
     """A resident graph (or a pool of graphs) on one GPU."""
 
-    def __init__(self, n, src=(), dst=(), radius=None, slack=None, device=0, stream=None, _pool=None):
+    def __init__(self, n, src=(), dst=(), radius=None, slack=None, device=0, stream=None, autotune=None,
+                 _pool=None):
         lib = load()
         self._h = _P()
-        opt = _opts(radius, slack, device, stream)
+        opt = _opts(radius, slack, device, stream, autotune)
         if _pool is None:
             s, d = _i32(src), _i32(dst)
             assert s.shape == d.shape

@@ -114,6 +114,7 @@ typedef struct {
   int64_t c4_dense_min;              /* hub-window density threshold used */
   int32_t whole_graph;               /* 1: counted the whole graph instead of the region */
   uint32_t overflow_mask;            /* classes whose count left int64 */
+  int32_t pass_batches;              /* batches that shared the counting pass (1: one batch per graph) */
   float ms_total;                    /* wall time of the call */
   float ms_prepare;                  /* ingest, merge, region, per-vertex pass (device) */
   float ms_tri, ms_edge;             /* triangle/4-clique kernels, edge pass (device) */
@@ -134,7 +135,7 @@ int gc_options_default(gc_options* opt);
  * dst[i]) (host arrays; loops ignored, repeats collapse) and returns its
  * counts.  Following Alg. 2's initialisation (F = 0), this is one batch
  * inserting every edge into the empty graph on n vertices.
- * n must be in [1, 2^30); opt may be NULL; counts may be NULL. */
+ * n must be in [1, 2^28); opt may be NULL; counts may be NULL. */
 int gc_graph_init(int64_t n, const int32_t* src, const int32_t* dst, int64_t m,
                   const gc_options* opt, gc_graph** out, int64_t counts[11]);
 
@@ -162,6 +163,19 @@ int gc_apply_batch_dev(gc_graph* g, const int32_t* ins_src, const int32_t* ins_d
 int gc_apply_batches(gc_graph* pool, const gc_batch_desc* batch, int64_t (*counts)[11],
                      gc_batch_stats* stats);
 
+/* Applies nb batches (host arrays) to a single-graph handle in order, each
+ * to the graph the previous one left, exactly as nb gc_apply_batch calls
+ * would; counts[j] (nb x 11, may be NULL) receives the counts after batch
+ * j, stats[j] (nb entries, may be NULL) its statistics.  Up to three
+ * batches share one counting pass: Lemma 2 applied to G_0 and each G_j,
+ * with the region of change taken in the union of G_0 .. G_j (a superset of
+ * each version's region, so exact) and every adjacency entry marking the
+ * versions its edge belongs to.  The arrays of all nb batches are checked
+ * first: one id outside [0, n) rejects the whole call with GC_EINVAL and
+ * leaves the graph unchanged. */
+int gc_apply_batch_seq(gc_graph* g, const gc_batch_desc* batches, int32_t nb, int64_t (*counts)[11],
+                       gc_batch_stats* stats);
+
 /* Current counts of graph `graph` (0 for a single-graph handle). */
 int gc_get_counts(const gc_graph* g, int32_t graph, int64_t counts[11], uint32_t* overflow_mask);
 int gc_get_counts_exact(const gc_graph* g, int32_t graph, int64_t hi[11], uint64_t lo[11]);
@@ -185,7 +199,10 @@ int gc_graph_free(gc_graph* g);
  * tickets.  Batches for different graphs run at the same time (their kernels
  * overlap on the device); batches for one graph are applied in submission
  * order, and each ticket's result is the counts right after its batch, the
- * same as gc_apply_batch would return in that order.  Admission by memory:
+ * same as gc_apply_batch would return in that order.  Continuous batching:
+ * when a graph's worker becomes free it takes up to three queued batches of
+ * that graph into one counting pass (gc_apply_batch_seq); a batch that fails
+ * the host-side id check fails alone.  Admission by memory:
  * a graph is admitted only if its estimated footprint fits the free HBM
  * (hipMemGetInfo, or hbm_budget_bytes when > 0) minus hbm_reserve_bytes,
  * else GC_ENOMEM; a batch starts only while the estimated bytes of batches in

@@ -127,17 +127,17 @@ struct gc_graph {
   DevBuf off, len, cap, col, top, gid, ext2int, int2ext;
   int64_t arena_cap = 0, arena_top = 0, entries = 0;
 
-  // small device state
-  DevBuf state, state_tmp, sig, ctr, bstats, tables;
+  // small device state; vout: state after each later version of a pass
+  DevBuf state, state_tmp, vout, sig, ctr, bstats, tables;
   std::vector<long long> hstate;
 
   // batch scratch
-  DevBuf bin, keys, keys_alt, dirA, dirA_alt, dirD, dirD_alt;
-  DevBuf a_beg, na, d_beg, nd, mark, tix;
+  DevBuf bin, keys, keys_alt, dirA, dirA_alt, dirD, dirD_alt, dirR, dirR_alt;
+  DevBuf a_beg, na, r_beg, nr, mark, tix;
   DevBuf touched, dest, newcap, tlen, tpre, scratch, sort_tmp, scan_tmp;
 
   // region and counting
-  DevBuf roff, rcol, rlow, dB, dA, t, vpos, level, rlist, rlen, lists;
+  DevBuf roff, rcol, rrow, rlow, dver, t, tp, vpos, level, rlist, rlen, lists;
   DevBuf c4_dense, c4_touch, c4_cur, c4_keys, c4_keys_alt, tri_scratch;
   int64_t c4_cur_low = 0;
   int32_t c4_slots = 0, tri_slots = 0;
@@ -180,9 +180,10 @@ struct gc_graph {
     R.roff = roff.as<int64_t>();
     R.rcol = rcol.as<uint32_t>();
     R.rlow = rlow.as<int32_t>();
-    R.dB = dB.as<int32_t>();
-    R.dA = dA.as<int32_t>();
+    R.rrow = rrow.as<int32_t>();
+    R.d = dver.as<int32_t>();
     R.t = t.as<unsigned long long>();
+    R.tp = tp.as<unsigned long long>();
     R.vpos = vpos.as<int32_t>();
     return R;
   }
@@ -209,12 +210,13 @@ namespace {
 void zero_small(gc_graph* G) {
   fill_u64(G->ctr.as<unsigned long long>(), 0ull, C_COUNT, G->stream);
   fill_u64(G->bstats.as<unsigned long long>(), 0ull, BS_COUNT, G->stream);
-  fill_u64(G->sig.as<unsigned long long>(), 0ull, (int64_t)G->k * 2 * SG_N, G->stream);
+  fill_u64(G->sig.as<unsigned long long>(), 0ull, (int64_t)G->k * GC_NV_MAX * SG_N, G->stream);
 }
 
-// Region + per-vertex pass + counting + combine into `state_d`.  `radius` < 0
-// counts every vertex.  Host copy of the counters goes to hc.
-void run_count(gc_graph* G, int radius, long long* state_d, BatchWork& W, std::vector<unsigned long long>& hc,
+// Region + per-vertex pass + counting over nv versions + combine into
+// `state_d` (and G->vout for every later version).  `radius` < 0 counts
+// every vertex.  Host copy of the counters goes to hc.
+void run_count(gc_graph* G, int nv, int radius, long long* state_d, BatchWork& W, std::vector<unsigned long long>& hc,
                int64_t union_entries, bool timed, int64_t dense_min = 2048) {
   hipStream_t s = G->stream;
   const int64_t N = G->N;
@@ -223,7 +225,10 @@ void run_count(gc_graph* G, int radius, long long* state_d, BatchWork& W, std::v
   G->c4_keys_alt.ensure(N * sizeof(unsigned long long));
   G->sort_tmp.ensure(radix_sort_tmp_bytes(N) + 64);
   G->rcol.ensure(std::max<int64_t>(union_entries, 1) * sizeof(uint32_t));
+  G->rrow.ensure(std::max<int64_t>(union_entries, 1) * sizeof(int32_t));
   G->t.ensure(std::max<int64_t>(union_entries, 1) * sizeof(unsigned long long));
+  if (nv > 2) G->tp.ensure(std::max<int64_t>(union_entries, 1) * 2 * sizeof(unsigned long long));
+  G->dver.ensure((size_t)N * GC_NV_MAX * sizeof(int32_t));
   G->vpos.ensure(std::max<int64_t>(union_entries, 1) * sizeof(int32_t));
   G->scan_tmp.ensure(scan_tmp_bytes(N + 1) + 64);
   PoolDev P = G->pd();
@@ -231,7 +236,7 @@ void run_count(gc_graph* G, int radius, long long* state_d, BatchWork& W, std::v
   launch_region(P, W, radius, G->level.as<int32_t>(), G->rlist.as<int32_t>(), G->rlen.as<int32_t>(), s);
   launch_region_fill(P, R, W, radius, G->level.as<int32_t>(), G->rlist.as<int32_t>(), G->rlen.as<int32_t>(),
                      G->scan_tmp.p, s);
-  launch_degrees(R, G->gid.as<int32_t>(), G->rlist.as<int32_t>(), G->ctr.as<unsigned long long>(),
+  launch_degrees(nv, R, G->gid.as<int32_t>(), G->rlist.as<int32_t>(), G->ctr.as<unsigned long long>(),
                  G->sig.as<unsigned long long>(), G->lists.as<int32_t>(), N, TRI_SMALL, C4_SMALL, C4_MID,
                  G->bstats.as<unsigned long long>(), G->c4_keys.as<unsigned long long>(), s);
   if (timed) HIPCHK(hipEventRecord(G->ev[1], s));
@@ -293,21 +298,24 @@ void run_count(gc_graph* G, int radius, long long* state_d, BatchWork& W, std::v
   A.slots = std::max(1, G->c4_slots);
   // triangles above the LDS tier: scratch slots in global memory
   const int64_t maxdp = (int64_t)hc[C_MAXDP];
-  if (maxdp > tri_lds_max()) {
+  if (maxdp > tri_lds_max(nv)) {
     if (maxdp > 32767) raise(GC_EINVAL, "oriented out-degree %lld exceeds the supported 32767", (long long)maxdp);
+    // the kernels lay out every slot for capacity tri_cap: size for the one in use
     const int32_t slots = 256;
-    if (maxdp > G->tri_cap || slots > G->tri_slots) {
+    const int64_t cap_use = std::max<int64_t>(maxdp, G->tri_cap);
+    const size_t need = (size_t)(tri_scratch_words64(nv, cap_use) * slots) * sizeof(unsigned long long);
+    if (need > G->tri_scratch.cap) {
       G->tri_scratch.release();
-      G->tri_scratch.ensure((size_t)(tri_scratch_words64(maxdp) * slots) * sizeof(unsigned long long));
-      G->tri_cap = maxdp;
-      G->tri_slots = slots;
+      G->tri_scratch.ensure(need);
     }
+    G->tri_cap = cap_use;
+    G->tri_slots = slots;
   }
   A.tri_scratch = G->tri_scratch.as<unsigned long long>();
   A.tri_cap = G->tri_cap;
   A.tri_slots = std::max(1, G->tri_slots);
-  launch_count(A, hc.data(), s, timed ? &G->ev[2] : nullptr);
-  launch_combine(G->sig.as<unsigned long long>(), state_d, G->k, s);
+  launch_count(nv, A, hc.data(), s, timed ? &G->ev[2] : nullptr);
+  launch_combine(nv, G->sig.as<unsigned long long>(), state_d, G->vout.as<long long>(), G->k, s);
 }
 
 BatchWork make_work(gc_graph* G) {
@@ -315,10 +323,11 @@ BatchWork make_work(gc_graph* G) {
   W.c = G->ctr.as<unsigned long long>();
   W.dirA = G->dirA.as<unsigned long long>();
   W.dirD = G->dirD.as<unsigned long long>();
+  W.dirR = G->dirR.as<unsigned long long>();
   W.a_beg = G->a_beg.as<int32_t>();
   W.na = G->na.as<int32_t>();
-  W.d_beg = G->d_beg.as<int32_t>();
-  W.nd = G->nd.as<int32_t>();
+  W.r_beg = G->r_beg.as<int32_t>();
+  W.nr = G->nr.as<int32_t>();
   W.mark = G->mark.as<int32_t>();
   W.tix = G->tix.as<int32_t>();
   W.touched = G->touched.as<int32_t>();
@@ -333,15 +342,16 @@ BatchWork make_work(gc_graph* G) {
 void alloc_vertex_arrays(gc_graph* G) {
   const int64_t N = G->N;
   hipStream_t s = G->stream;
-  for (DevBuf* b : {&G->a_beg, &G->na, &G->d_beg, &G->nd, &G->mark, &G->tix}) {
+  for (DevBuf* b : {&G->a_beg, &G->na, &G->r_beg, &G->nr, &G->mark, &G->tix}) {
     b->ensure(N * sizeof(int32_t));
     fill_u32(b->as<uint32_t>(), 0u, N, s);
   }
-  for (DevBuf* b : {&G->rlow, &G->dB, &G->dA, &G->level, &G->rlist, &G->rlen}) b->ensure(N * sizeof(int32_t));
+  for (DevBuf* b : {&G->rlow, &G->level, &G->rlist, &G->rlen}) b->ensure(N * sizeof(int32_t));
   G->lists.ensure((size_t)L_NUM * N * sizeof(int32_t));
   G->state.ensure((size_t)G->k * ST_STRIDE * sizeof(long long));
   G->state_tmp.ensure((size_t)G->k * ST_STRIDE * sizeof(long long));
-  G->sig.ensure((size_t)G->k * 2 * SG_N * sizeof(unsigned long long));
+  G->vout.ensure((size_t)(GC_NV_MAX - 1) * G->k * ST_STRIDE * sizeof(long long));
+  G->sig.ensure((size_t)G->k * GC_NV_MAX * SG_N * sizeof(unsigned long long));
   G->ctr.ensure(C_COUNT * sizeof(unsigned long long));
   G->bstats.ensure(BS_COUNT * sizeof(unsigned long long));
   G->top.ensure(sizeof(unsigned long long));
@@ -425,7 +435,7 @@ void build(gc_graph* G, int32_t k, const int64_t* n, const int32_t* const* src, 
       if (src[g][i] < 0 || src[g][i] >= n[g] || dst[g][i] < 0 || dst[g][i] >= n[g])
         raise(GC_EINVAL, "graph %d: edge %lld has a vertex id outside [0, %lld)", g, (long long)i, (long long)n[g]);
   }
-  if (N >= GC_MAX_VERTICES) raise(GC_EINVAL, "total vertex count must be below 2^30");
+  if (N >= GC_MAX_VERTICES) raise(GC_EINVAL, "total vertex count must be below 2^28");
   G->N = N;
   G->bits = bits_for(N);
   const int lbits = bits_for(maxn + 1);
@@ -522,7 +532,7 @@ void build(gc_graph* G, int32_t k, const int64_t* n, const int32_t* const* src, 
   zero_small(G);
   BatchWork W = make_work(G);
   std::vector<unsigned long long> hc;
-  run_count(G, -1, G->state.as<long long>(), W, hc, nd, false);
+  run_count(G, 2, -1, G->state.as<long long>(), W, hc, nd, false);
   launch_all_flags(P, 0u, GC_ID, s);
   G->sync();
   G->entries = nd;
@@ -532,26 +542,20 @@ void build(gc_graph* G, int32_t k, const int64_t* n, const int32_t* const* src, 
   for (int g = 0; g < k; ++g) G->hstate[g * ST_STRIDE + ST_N] = n[g];
 }
 
-struct HostBatch {
-  // concatenated over graphs
-  std::vector<int64_t> ins_seg, del_seg;
-  int64_t n_ins = 0, n_del = 0;
-};
-
 void fill_stats(gc_graph* G, gc_batch_stats* st, const std::vector<unsigned long long>& hb,
-                const std::vector<unsigned long long>& hc, int64_t n_ins, int64_t n_del, bool timed,
+                const std::vector<unsigned long long>& hc, int j, int nb, int64_t n_ins, int64_t n_del, bool timed,
                 double ms_total, uint32_t ovf) {
   if (!st) return;
   std::memset(st, 0, sizeof(*st));
   st->offered_ins = n_ins;
   st->offered_del = n_del;
-  st->eff_ins = (int64_t)hb[BS_EFF_INS];
-  st->eff_del = (int64_t)hb[BS_EFF_DEL];
-  st->loops = (int64_t)hb[BS_LOOPS];
-  st->dups = (int64_t)hb[BS_DUPS];
-  st->cancelled = (int64_t)hb[BS_CANCEL];
-  st->ins_existing = (int64_t)hb[BS_INS_EXIST];
-  st->del_missing = (int64_t)hb[BS_DEL_MISS];
+  st->eff_ins = (int64_t)hb[PB_IDX(j, PB_EFF_INS)];
+  st->eff_del = (int64_t)hb[PB_IDX(j, PB_EFF_DEL)];
+  st->loops = (int64_t)hb[PB_IDX(j, PB_LOOPS)];
+  st->dups = (int64_t)hb[PB_IDX(j, PB_DUPS)];
+  st->cancelled = (int64_t)hb[PB_IDX(j, PB_CANCEL)];
+  st->ins_existing = (int64_t)hb[PB_IDX(j, PB_INS_EXIST)];
+  st->del_missing = (int64_t)hb[PB_IDX(j, PB_DEL_MISS)];
   st->touched_vertices = (int64_t)hc[C_TOUCH];
   st->region_vertices = (int64_t)hc[C_RLIST];
   st->region_entries = (int64_t)hc[C_ER];
@@ -567,6 +571,7 @@ void fill_stats(gc_graph* G, gc_batch_stats* st, const std::vector<unsigned long
   st->tier_c4_mid = (int64_t)hc[C_LIST0 + L_C4_M];
   st->tier_c4_large = (int64_t)hc[C_LIST0 + L_C4_L];
   st->overflow_mask = ovf;
+  st->pass_batches = nb;
   st->ms_total = (float)ms_total;
   if (timed) {
     float a = 0;
@@ -580,87 +585,97 @@ void fill_stats(gc_graph* G, gc_batch_stats* st, const std::vector<unsigned long
   }
 }
 
-// One batch per graph of the pool.  Host arrays when dev == false.
-void apply(gc_graph* G, const gc_batch_desc* b, bool dev, int64_t (*counts)[11], gc_batch_stats* stats) {
+// Host-side check of one batch's arrays (sizes, pointers, ids in [0, n)).
+void check_batch(const gc_batch_desc& b, int64_t n, int which) {
+  if (b.n_ins < 0 || b.n_del < 0) raise(GC_EINVAL, "batch %d: negative size", which);
+  if ((b.n_ins && (!b.ins_src || !b.ins_dst)) || (b.n_del && (!b.del_src || !b.del_dst)))
+    raise(GC_EINVAL, "batch %d: null array", which);
+  for (int64_t i = 0; i < b.n_ins; ++i)
+    if (b.ins_src[i] < 0 || b.ins_src[i] >= n || b.ins_dst[i] < 0 || b.ins_dst[i] >= n)
+      raise(GC_EINVAL, "batch %d: insertion %lld has a vertex id outside [0, %lld)", which, (long long)i,
+            (long long)n);
+  for (int64_t i = 0; i < b.n_del; ++i)
+    if (b.del_src[i] < 0 || b.del_src[i] >= n || b.del_dst[i] < 0 || b.del_dst[i] >= n)
+      raise(GC_EINVAL, "batch %d: deletion %lld has a vertex id outside [0, %lld)", which, (long long)i,
+            (long long)n);
+}
+
+// One counting pass.  seq == false: b[g] is the batch of graph g of the pool
+// (G->k of them; host arrays unless dev, which needs k == 1).  seq == true:
+// b[0..nb) are successive batches of graph 0 of a single-graph handle (host
+// arrays, nb <= GC_SEQ_MAX); counts[j] and stats[j] are those after batch j.
+// The pass compares nv versions: 2 for one batch per graph, 4 for several
+// batches (versions past the last batch repeat it).
+void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int64_t (*counts)[11],
+           gc_batch_stats* stats) {
   using clk = std::chrono::steady_clock;
   const auto t0 = clk::now();
   if (G->broken) raise(GC_ESTATE, "handle unusable after an earlier device failure");
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = G->stream;
   const int k = G->k;
-  HostBatch H;
-  H.ins_seg.assign(k + 1, 0);
-  H.del_seg.assign(k + 1, 0);
-  for (int g = 0; g < k; ++g) {
-    if (b[g].n_ins < 0 || b[g].n_del < 0) raise(GC_EINVAL, "negative batch size");
-    if ((b[g].n_ins && (!b[g].ins_src || !b[g].ins_dst)) || (b[g].n_del && (!b[g].del_src || !b[g].del_dst)))
-      raise(GC_EINVAL, "null batch array");
-    if (!dev) {
-      const int64_t n = G->gn[g];
-      for (int64_t i = 0; i < b[g].n_ins; ++i)
-        if (b[g].ins_src[i] < 0 || b[g].ins_src[i] >= n || b[g].ins_dst[i] < 0 || b[g].ins_dst[i] >= n)
-          raise(GC_EINVAL, "insertion %lld of graph %d has a vertex id outside [0, %lld)", (long long)i, g,
-                (long long)n);
-      for (int64_t i = 0; i < b[g].n_del; ++i)
-        if (b[g].del_src[i] < 0 || b[g].del_src[i] >= n || b[g].del_dst[i] < 0 || b[g].del_dst[i] >= n)
-          raise(GC_EINVAL, "deletion %lld of graph %d has a vertex id outside [0, %lld)", (long long)i, g,
-                (long long)n);
-    }
-    H.ins_seg[g + 1] = H.ins_seg[g] + b[g].n_ins;
-    H.del_seg[g + 1] = H.del_seg[g] + b[g].n_del;
+  const int nseg = seq ? nb : k;        // segments of the update arrays
+  const int npass = seq ? nb : 1;       // batches acting in sequence
+  const int nv = npass > 1 ? 4 : 2;
+  std::vector<int64_t> ins_seg(nseg + 1, 0), del_seg(nseg + 1, 0);
+  for (int q = 0; q < nseg; ++q) {
+    const int64_t n = G->gn[seq ? 0 : q];
+    if (!dev) check_batch(b[q], n, q);
+    else if (b[q].n_ins < 0 || b[q].n_del < 0) raise(GC_EINVAL, "negative batch size");
+    ins_seg[q + 1] = ins_seg[q] + b[q].n_ins;
+    del_seg[q + 1] = del_seg[q] + b[q].n_del;
   }
-  const int64_t ni = H.ins_seg[k], ndl = H.del_seg[k];
+  const int64_t ni = ins_seg[nseg], ndl = del_seg[nseg];
   const int64_t total = ni + ndl;
   const bool timed = stats != nullptr;
 
   // upload: [ins_seg | del_seg | gbase | gn] int64, then the four id arrays
-  const size_t tab_words = (size_t)(4 * k + 2);
+  const size_t tab_words = (size_t)(2 * (nseg + 1) + 2 * k);
   const size_t bytes = tab_words * 8 + (dev ? 0 : (size_t)(2 * total) * sizeof(int32_t));
   char* pin = (char*)G->pinned(bytes + 64);
   int64_t* tab = (int64_t*)pin;
-  std::memcpy(tab, H.ins_seg.data(), (k + 1) * 8);
-  std::memcpy(tab + k + 1, H.del_seg.data(), (k + 1) * 8);
-  std::memcpy(tab + 2 * k + 2, G->gbase.data(), k * 8);
-  std::memcpy(tab + 3 * k + 2, G->gn.data(), k * 8);
+  std::memcpy(tab, ins_seg.data(), (nseg + 1) * 8);
+  std::memcpy(tab + nseg + 1, del_seg.data(), (nseg + 1) * 8);
+  std::memcpy(tab + 2 * (nseg + 1), G->gbase.data(), k * 8);
+  std::memcpy(tab + 2 * (nseg + 1) + k, G->gn.data(), k * 8);
   G->bin.ensure(bytes + 64);
   BatchIn B;
   B.n_ins = ni;
   B.n_del = ndl;
-  B.k = k;
+  B.k = nseg;
+  B.seq = seq ? 1 : 0;
   char* dbase = (char*)G->bin.p;
   B.ins_seg = (const int64_t*)dbase;
-  B.del_seg = B.ins_seg + k + 1;
-  B.gbase = B.ins_seg + 2 * k + 2;
-  B.gn = B.ins_seg + 3 * k + 2;
+  B.del_seg = B.ins_seg + nseg + 1;
+  B.gbase = B.ins_seg + 2 * (nseg + 1);
+  B.gn = B.gbase + k;
   if (dev) {
     B.iu = b[0].ins_src; B.iv = b[0].ins_dst; B.du = b[0].del_src; B.dv = b[0].del_dst;
   } else {
     int32_t* ids = (int32_t*)(pin + tab_words * 8);
     int32_t* d_ids = (int32_t*)(dbase + tab_words * 8);
     int32_t *iu = ids, *iv = ids + ni, *du = ids + 2 * ni, *dv = ids + 2 * ni + ndl;
-    for (int g = 0; g < k; ++g) {
-      if (b[g].n_ins) {
-        std::memcpy(iu + H.ins_seg[g], b[g].ins_src, b[g].n_ins * 4);
-        std::memcpy(iv + H.ins_seg[g], b[g].ins_dst, b[g].n_ins * 4);
+    for (int q = 0; q < nseg; ++q) {
+      if (b[q].n_ins) {
+        std::memcpy(iu + ins_seg[q], b[q].ins_src, b[q].n_ins * 4);
+        std::memcpy(iv + ins_seg[q], b[q].ins_dst, b[q].n_ins * 4);
       }
-      if (b[g].n_del) {
-        std::memcpy(du + H.del_seg[g], b[g].del_src, b[g].n_del * 4);
-        std::memcpy(dv + H.del_seg[g], b[g].del_dst, b[g].n_del * 4);
+      if (b[q].n_del) {
+        std::memcpy(du + del_seg[q], b[q].del_src, b[q].n_del * 4);
+        std::memcpy(dv + del_seg[q], b[q].del_dst, b[q].n_del * 4);
       }
     }
     B.iu = d_ids; B.iv = d_ids + ni; B.du = d_ids + 2 * ni; B.dv = d_ids + 2 * ni + ndl;
   }
   HIPCHK(hipMemcpyAsync(G->bin.p, pin, bytes, hipMemcpyHostToDevice, s));
 
-  // scratch sizes
+  // scratch sizes (dirA <= 2 insertions, dirD and dirR <= 2 deletions)
   const int64_t max_touched = std::max<int64_t>(2 * total, 1);
   const int64_t union_bound = G->entries + 2 * ni;
   G->keys.ensure(std::max<int64_t>(total, 1) * 8);
   G->keys_alt.ensure(std::max<int64_t>(total, 1) * 8);
-  G->dirA.ensure(std::max<int64_t>(2 * ni, 1) * 8);
-  G->dirA_alt.ensure(std::max<int64_t>(2 * ni, 1) * 8);
-  G->dirD.ensure(std::max<int64_t>(2 * ndl, 1) * 8);
-  G->dirD_alt.ensure(std::max<int64_t>(2 * ndl, 1) * 8);
+  for (DevBuf* d : {&G->dirA, &G->dirA_alt}) d->ensure(std::max<int64_t>(2 * ni, 1) * 8);
+  for (DevBuf* d : {&G->dirD, &G->dirD_alt, &G->dirR, &G->dirR_alt}) d->ensure(std::max<int64_t>(2 * ndl, 1) * 8);
   G->touched.ensure(max_touched * 4);
   G->dest.ensure(max_touched * 8);
   G->newcap.ensure(max_touched * 4);
@@ -681,12 +696,12 @@ void apply(gc_graph* G, const gc_batch_desc* b, bool dev, int64_t (*counts)[11],
   unsigned long long* ctr = G->ctr.as<unsigned long long>();
   launch_ingest_keys(P, B, G->bits, G->keys.as<unsigned long long>(), bst, s);
   unsigned long long* sk = radix_sort_u64(G->keys.as<unsigned long long>(), G->keys_alt.as<unsigned long long>(),
-                                          G->sort_tmp.p, total, nullptr, 2 * G->bits + 1, s);
-  launch_ingest_classify(P, sk, total, G->bits, G->dirA.as<unsigned long long>(), G->dirD.as<unsigned long long>(),
-                         ctr, bst, s);
+                                          G->sort_tmp.p, total, nullptr, 2 * G->bits + 3, s);
+  launch_ingest_classify(P, sk, total, G->bits, npass, nv, G->dirA.as<unsigned long long>(),
+                         G->dirD.as<unsigned long long>(), G->dirR.as<unsigned long long>(), ctr, bst, s);
   if (dev) {
     unsigned long long err = 0;
-    HIPCHK(hipMemcpyAsync(&err, bst + BS_ERR, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&err, bst + PB_IDX(0, PB_ERR), 8, hipMemcpyDeviceToHost, s));
     G->sync();
     if (err) raise(GC_EINVAL, "batch has %llu vertex ids outside the graph", err);
   }
@@ -694,13 +709,17 @@ void apply(gc_graph* G, const gc_batch_desc* b, bool dev, int64_t (*counts)[11],
                                           G->sort_tmp.p, 2 * ni, ctr + C_DIRA, 2 * G->bits, s);
   unsigned long long* sD = radix_sort_u64(G->dirD.as<unsigned long long>(), G->dirD_alt.as<unsigned long long>(),
                                           G->sort_tmp.p, 2 * ndl, ctr + C_DIRD, 2 * G->bits, s);
+  unsigned long long* sR = radix_sort_u64(G->dirR.as<unsigned long long>(), G->dirR_alt.as<unsigned long long>(),
+                                          G->sort_tmp.p, 2 * ndl, ctr + C_DIRR, 2 * G->bits, s);
   BatchWork W = make_work(G);
   W.dirA = sA;
   W.dirD = sD;
+  W.dirR = sR;
   launch_mark_rows(sA, 2 * ni, ctr, C_DIRA, G->bits, W.a_beg, W.na, W.mark, W.touched, W.tix, s);
-  launch_mark_rows(sD, 2 * ndl, ctr, C_DIRD, G->bits, W.d_beg, W.nd, W.mark, W.touched, W.tix, s);
+  launch_mark_rows(sD, 2 * ndl, ctr, C_DIRD, G->bits, nullptr, nullptr, W.mark, W.touched, W.tix, s);
+  launch_mark_rows(sR, 2 * ndl, ctr, C_DIRR, G->bits, W.r_beg, W.nr, W.mark, W.touched, W.tix, s);
   launch_merge(P, W, max_touched, 2 * ni, G->bits, G->opt.slack, bst, G->scan_tmp.p, s);
-  launch_flag_del(P, W, 2 * ndl, G->bits, bst, s);
+  launch_flag_rows(P, W, 2 * ndl, G->bits, bst, s);
 
   std::vector<unsigned long long> hc;
   int radius = G->opt.radius == 0 ? -1 : G->opt.radius;
@@ -717,16 +736,16 @@ void apply(gc_graph* G, const gc_batch_desc* b, bool dev, int64_t (*counts)[11],
     if (radius >= 2 && G->region_frac[decade] >= 0.9) radius = -1;  // exact radii only
   }
   const bool timed_run = timed || (G->opt.autotune && tune_idx >= 0);
-  run_count(G, radius, G->state.as<long long>(), W, hc, union_bound, timed_run, dense_min);
-  launch_purge(P, W, max_touched, G->bits, G->scan_tmp.p, s);
+  run_count(G, nv, radius, G->state.as<long long>(), W, hc, union_bound, timed_run, dense_min);
+  launch_purge(P, W, max_touched, G->bits, 1u << (GC_VSHIFT + nv - 1), G->scan_tmp.p, s);
   if (timed_run) HIPCHK(hipEventRecord(G->ev[8], s));
 
   std::vector<unsigned long long> hb(BS_COUNT);
-  G->hstate.resize((size_t)k * ST_STRIDE);
   HIPCHK(hipMemcpyAsync(hb.data(), bst, BS_COUNT * 8, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&G->arena_top, G->top.p, 8, hipMemcpyDeviceToHost, s));
-  std::vector<long long> st((size_t)k * ST_STRIDE);
+  std::vector<long long> st((size_t)k * ST_STRIDE), vo((size_t)(nv - 1) * k * ST_STRIDE);
   HIPCHK(hipMemcpyAsync(st.data(), G->state.p, st.size() * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(vo.data(), G->vout.p, vo.size() * 8, hipMemcpyDeviceToHost, s));
   G->sync();
   long long cerr = 0;
   for (int g = 0; g < k; ++g) cerr += st[g * ST_STRIDE + ST_ERR];
@@ -737,15 +756,18 @@ void apply(gc_graph* G, const gc_batch_desc* b, bool dev, int64_t (*counts)[11],
   }
   for (int g = 0; g < k; ++g) st[g * ST_STRIDE + ST_N] = G->gn[g];
   G->hstate = st;
-  G->entries += 2 * ((int64_t)hb[BS_EFF_INS] - (int64_t)hb[BS_EFF_DEL]);
-  uint32_t ovf_all = 0;
-  for (int g = 0; g < k; ++g) {
+  for (int j = 0; j < npass; ++j)
+    G->entries += 2 * ((int64_t)hb[PB_IDX(j, PB_EFF_INS)] - (int64_t)hb[PB_IDX(j, PB_EFF_DEL)]);
+  // results: per graph of the pool, or per batch of the sequence
+  const int nout = seq ? nb : k;
+  std::vector<uint32_t> ovf(nout, 0);
+  for (int o = 0; o < nout; ++o) {
+    long long* so = seq ? &vo[(size_t)o * ST_STRIDE] : &G->hstate[(size_t)o * ST_STRIDE];
+    so[ST_N] = G->gn[seq ? 0 : o];
     i128 I[11];
-    finalize(&G->hstate[g * ST_STRIDE], G->gn[g], I);
-    uint32_t mk = 0;
+    finalize(so, G->gn[seq ? 0 : o], I);
     int64_t tmp[11];
-    to_int64(I, counts ? counts[g] : tmp, &mk);
-    ovf_all |= mk;
+    to_int64(I, counts ? counts[o] : tmp, &ovf[o]);
   }
   if (G->opt.autotune) {
     if (radius > 0 && union_bound > 0)
@@ -765,10 +787,17 @@ void apply(gc_graph* G, const gc_batch_desc* b, bool dev, int64_t (*counts)[11],
     }
   }
   const double ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
-  fill_stats(G, stats, hb, hc, ni, ndl, timed, ms, ovf_all);
   if (stats) {
-    stats->c4_dense_min = dense_min;
-    stats->whole_graph = radius < 0;
+    const int nst = seq ? nb : 1;
+    for (int q = 0; q < nst; ++q) {
+      uint32_t mk = 0;
+      if (seq) mk = ovf[q];
+      else for (uint32_t m : ovf) mk |= m;
+      fill_stats(G, &stats[q], hb, hc, seq ? q : 0, npass, seq ? b[q].n_ins : ni, seq ? b[q].n_del : ndl, timed, ms,
+                 mk);
+      stats[q].c4_dense_min = dense_min;
+      stats[q].whole_graph = radius < 0;
+    }
   }
 }
 
@@ -839,7 +868,7 @@ int gc_apply_batch(gc_graph* g, const int32_t* ins_src, const int32_t* ins_dst, 
     if (!g) raise(GC_EINVAL, "graph is NULL");
     if (g->k != 1) raise(GC_EINVAL, "handle holds %d graphs: use gc_apply_batches", g->k);
     gc_batch_desc b{ins_src, ins_dst, n_ins, del_src, del_dst, n_del};
-    apply(g, &b, false, counts ? (int64_t(*)[11])counts : nullptr, stats);
+    apply(g, &b, 1, false, false, counts ? (int64_t(*)[11])counts : nullptr, stats);
   });
 }
 
@@ -850,14 +879,28 @@ int gc_apply_batch_dev(gc_graph* g, const int32_t* ins_src, const int32_t* ins_d
     if (!g) raise(GC_EINVAL, "graph is NULL");
     if (g->k != 1) raise(GC_EINVAL, "handle holds %d graphs: use gc_apply_batches", g->k);
     gc_batch_desc b{ins_src, ins_dst, n_ins, del_src, del_dst, n_del};
-    apply(g, &b, true, counts ? (int64_t(*)[11])counts : nullptr, stats);
+    apply(g, &b, 1, true, false, counts ? (int64_t(*)[11])counts : nullptr, stats);
   });
 }
 
 int gc_apply_batches(gc_graph* pool, const gc_batch_desc* batch, int64_t (*counts)[11], gc_batch_stats* stats) {
   return guard([&] {
     if (!pool || !batch) raise(GC_EINVAL, "NULL argument");
-    apply(pool, batch, false, counts, stats);
+    apply(pool, batch, pool->k, false, false, counts, stats);
+  });
+}
+
+int gc_apply_batch_seq(gc_graph* g, const gc_batch_desc* batches, int32_t nb, int64_t (*counts)[11],
+                       gc_batch_stats* stats) {
+  return guard([&] {
+    if (!g || (nb > 0 && !batches)) raise(GC_EINVAL, "NULL argument");
+    if (g->k != 1) raise(GC_EINVAL, "handle holds %d graphs: gc_apply_batch_seq needs a single graph", g->k);
+    if (nb < 0) raise(GC_EINVAL, "negative batch count");
+    for (int j = 0; j < nb; ++j) check_batch(batches[j], g->gn[0], j);  // all-or-nothing
+    for (int j0 = 0; j0 < nb; j0 += GC_SEQ_MAX) {
+      const int q = std::min(GC_SEQ_MAX, nb - j0);
+      apply(g, batches + j0, q, false, q > 1, counts ? counts + j0 : nullptr, stats ? stats + j0 : nullptr);
+    }
   });
 }
 
@@ -894,7 +937,7 @@ int gc_recount_exact(gc_graph* g, int32_t graph, int64_t hi[11], uint64_t lo[11]
     zero_small(g);
     BatchWork W = make_work(g);
     std::vector<unsigned long long> hc;
-    run_count(g, -1, g->state_tmp.as<long long>(), W, hc, g->entries, false);
+    run_count(g, 2, -1, g->state_tmp.as<long long>(), W, hc, g->entries, false);
     launch_all_flags(P, 0u, GC_ID, s);
     std::vector<long long> st((size_t)g->k * ST_STRIDE);
     HIPCHK(hipMemcpyAsync(st.data(), g->state_tmp.p, st.size() * 8, hipMemcpyDeviceToHost, s));

@@ -1,7 +1,10 @@
 // Counting kernels: the local static counter applied to the region, fused
-// over the two versions (G_b before, G_a after the batch; Alg. 2 counts both
-// and adds C_a - C_b).  Every structure is enumerated once in the union view
-// and its presence in each version is read off the flags of its entries.
+// over the versions of the pass (Alg. 2 counts G_b and G_a and adds
+// C_a - C_b; a pass over several queued batches counts every intermediate
+// graph as well).  Every structure is enumerated once in the union view and
+// the versions it exists in are read off the flags of its entries.  Kernels
+// are instantiated for NV = 2 versions (one batch) and NV = 4 (up to three
+// batches of one graph).
 //
 // Per-edge counting (the PGD approach of Sec. 3: iterate over edges, count
 // triangles, 4-cliques and 4-cycles, derive the rest by combinatorics):
@@ -21,8 +24,11 @@
 //   tri  S: out-degree <= 64, one wave per vertex, bit matrices in LDS
 //   tri  L: larger out-degree, one workgroup per vertex, LDS hash
 //   c4   S / M: wedge bound <= 256 / <= 4096, LDS hash per wave / workgroup
-//   c4   L: one workgroup per vertex, dense counters in global memory
+//   c4   L: one workgroup per vertex, windows of dense counters in LDS,
+//           then dense counters in global memory
 #include "gc_kernels.h"
+
+#include <type_traits>
 
 namespace {
 
@@ -80,32 +86,119 @@ __device__ __forceinline__ unsigned long long pack2(uint32_t b, uint32_t a) {
   return (unsigned long long)b | ((unsigned long long)a << 32);
 }
 
-// flush lane-private sums of a wave whose lanes all work for graph g
-__device__ __forceinline__ void flush2(unsigned long long* sig, int g, int k, int64_t& b, int64_t& a) {
-  flush_sig(sig, g, 0, k, b);
-  flush_sig(sig, g, 1, k, a);
-  b = 0; a = 0;
+// Per-version counters packed in one word: NF fields of FB bits each.
+template <int NF, int FB>
+struct Fields {
+  using T = typename std::conditional<(NF * FB <= 32), uint32_t, unsigned long long>::type;
+  // 1 in field x for every bit x of pm
+  __device__ static __forceinline__ T spread(uint32_t pm) {
+    T r = 0;
+#pragma unroll
+    for (int x = 0; x < NF; ++x) r |= (T)((pm >> x) & 1u) << (FB * x);
+    return r;
+  }
+  __device__ static __forceinline__ int64_t get(T c, int x) {
+    return (int64_t)((c >> (FB * x)) & (T)((1ull << FB) - 1ull));
+  }
+};
+
+// flush lane-private per-version sums of a wave whose lanes all work for graph g
+template <int NV>
+__device__ __forceinline__ void flushv(unsigned long long* sig, int g, int k, int64_t (&a)[NV]) {
+#pragma unroll
+  for (int x = 0; x < NV; ++x) {
+    flush_sig(sig, g, x, k, a[x]);
+    a[x] = 0;
+  }
 }
 
+template <int NV>
+__device__ __forceinline__ void zerov(int64_t (&a)[NV]) {
+#pragma unroll
+  for (int x = 0; x < NV; ++x) a[x] = 0;
+}
+
+// t of entry pos: one triangle (or c of them) present in the versions of pm
+template <int NV>
+__device__ __forceinline__ void t_add(const RegionDev& R, int64_t pos, uint32_t pm, uint32_t c = 1u) {
+  if constexpr (NV == 2) {
+    atomicAdd(&R.t[pos], pack2((pm & 1u) * c, ((pm >> 1) & 1u) * c));
+  } else {
+    if (pm == 0xFu) { atomicAdd(&R.t[pos], (unsigned long long)c); return; }
+    if (pm & 3u) atomicAdd(&R.tp[2 * pos], pack2((pm & 1u) * c, ((pm >> 1) & 1u) * c));
+    if (pm & 12u) atomicAdd(&R.tp[2 * pos + 1], pack2(((pm >> 2) & 1u) * c, ((pm >> 3) & 1u) * c));
+  }
+}
+
+// t of entry pos: c[x] triangles in version x
+template <int NV>
+__device__ __forceinline__ void t_addv(const RegionDev& R, int64_t pos, const uint32_t (&c)[NV]) {
+  if constexpr (NV == 2) {
+    if (c[0] | c[1]) atomicAdd(&R.t[pos], pack2(c[0], c[1]));
+  } else {
+    const uint32_t m = min(min(c[0], c[1]), min(c[2], c[3]));
+    if (m) atomicAdd(&R.t[pos], (unsigned long long)m);
+    if ((c[0] - m) | (c[1] - m)) atomicAdd(&R.tp[2 * pos], pack2(c[0] - m, c[1] - m));
+    if ((c[2] - m) | (c[3] - m)) atomicAdd(&R.tp[2 * pos + 1], pack2(c[2] - m, c[3] - m));
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ void t_read(const RegionDev& R, int64_t pos, int64_t (&t)[NV]) {
+  const unsigned long long a = R.t[pos];
+  if constexpr (NV == 2) {
+    t[0] = (int64_t)(a & 0xFFFFFFFFull);
+    t[1] = (int64_t)(a >> 32);
+  } else {
+    const ulonglong2 p = *(const ulonglong2*)(R.tp + 2 * pos);
+    t[0] = (int64_t)(a + (p.x & 0xFFFFFFFFull));
+    t[1] = (int64_t)(a + (p.x >> 32));
+    t[2] = (int64_t)(a + (p.y & 0xFFFFFFFFull));
+    t[3] = (int64_t)(a + (p.y >> 32));
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ void d_read(const RegionDev& R, int64_t v, int32_t (&d)[NV]) {
+  if constexpr (NV == 2) {
+    const int2 q = *(const int2*)(R.d + v * 2);
+    d[0] = q.x; d[1] = q.y;
+  } else {
+    const int4 q = *(const int4*)(R.d + v * 4);
+    d[0] = q.x; d[1] = q.y; d[2] = q.z; d[3] = q.w;
+  }
+}
+
+__device__ __forceinline__ bool absent_in(uint32_t flags, int x) { return (flags >> (GC_VSHIFT + x)) & 1u; }
+
 // ------------------------------------------------------ triangles, tier S
+// One wave per vertex u with out-degree <= 64.  Bit matrices over the slots
+// of N+(u): EU[i] has bit j (j > i) when v_i -> v_j is an edge of the union
+// view, TU its transpose, and EX[x] / TX[x] the same for the edges absent
+// from version x (only edges with flags land there).  A wave that met no
+// flag at all counts version 0 once and copies it to the others.
 constexpr int TS_WAVES = 4;
 
+template <int NV>
 __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
   __shared__ int32_t hkey[TS_WAVES][128];
   __shared__ int16_t hval[TS_WAVES][128];
   __shared__ uint32_t fsl[TS_WAVES][64];
-  __shared__ unsigned long long EB[TS_WAVES][64], EA[TS_WAVES][64], TB[TS_WAVES][64], TA[TS_WAVES][64];
+  __shared__ unsigned long long EU[TS_WAVES][64], TU[TS_WAVES][64];
+  __shared__ unsigned long long EX[TS_WAVES][NV][64], TX[TS_WAVES][NV][64];
+  __shared__ uint32_t dirty[TS_WAVES];
   const int w = threadIdx.x >> 6, l = lane_id();
   const RegionDev& R = A.R;
   const int64_t n = (int64_t)A.c[C_LIST0 + L_TRI_S];
   const int32_t* list = A.lists + L_TRI_S * A.list_stride;
   int cur_g = -1;
-  int64_t kb_ = 0, ka_ = 0;
+  int64_t kacc[NV];
+  zerov<NV>(kacc);
   for (int64_t it = (int64_t)blockIdx.x * TS_WAVES + w; it < n; it += (int64_t)gridDim.x * TS_WAVES) {
     const int32_t u = list[it];
     const int g = A.gid[u];
     if (g != cur_g) {
-      if (cur_g >= 0) flush2(A.sig, cur_g, SG_K4, kb_, ka_);
+      if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_K4, kacc);
       cur_g = g;
     }
     const int64_t ub = R.roff[u] + R.rlow[u];
@@ -113,8 +206,11 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
     uint32_t vi = 0, fi = 0;
     if (l < dp) { const uint32_t x = R.rcol[ub + l]; vi = x & GC_ID; fi = x & GC_FLAGS; }
     hkey[w][l] = -1; hkey[w][l + 64] = -1;
-    EB[w][l] = 0; EA[w][l] = 0; TB[w][l] = 0; TA[w][l] = 0;
+    EU[w][l] = 0; TU[w][l] = 0;
+#pragma unroll
+    for (int x = 0; x < NV; ++x) { EX[w][x][l] = 0; TX[w][x][l] = 0; }
     fsl[w][l] = fi;
+    if (l == 0) dirty[w] = 0;
     wave_sync();
     if (l < dp) {
       uint32_t h = hash32(vi) >> 25;
@@ -140,31 +236,50 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
         if (j >= 0) {
           const uint32_t fy = y & GC_FLAGS;
           const unsigned long long bj = 1ull << j, bi = 1ull << i;
-          if (!(fy & GC_F_NEW)) { atomicOr(&EB[w][i], bj); atomicOr(&TB[w][j], bi); }
-          if (!(fy & GC_F_DEL)) { atomicOr(&EA[w][i], bj); atomicOr(&TA[w][j], bi); }
-          const uint32_t ab = fsl[w][i] | fsl[w][j] | fy;
-          const uint32_t xb = !(ab & GC_F_NEW), xa = !(ab & GC_F_DEL);
-          if (xb | xa) atomicAdd(&R.t[pos], pack2(xb, xa));
+          atomicOr(&EU[w][i], bj);
+          atomicOr(&TU[w][j], bi);
+          if (fy) {
+            dirty[w] = 1u;
+#pragma unroll
+            for (int x = 0; x < NV; ++x)
+              if (absent_in(fy, x)) { atomicOr(&EX[w][x][i], bj); atomicOr(&TX[w][x][j], bi); }
+          }
+          const uint32_t pm = vpresent<NV>(fsl[w][i] | fsl[w][j] | fy);
+          if (pm) t_add<NV>(R, pos, pm);
         }
       }
     }
     wave_sync();
-    const uint64_t Pb = __ballot(l < dp && !(fi & GC_F_NEW));
-    const uint64_t Pa = __ballot(l < dp && !(fi & GC_F_DEL));
+    const bool clean = __ballot(l < dp && fi != 0) == 0ull && dirty[w] == 0u;
+    uint64_t Px[NV];
+#pragma unroll
+    for (int x = 0; x < NV; ++x) Px[x] = __ballot(l < dp && !absent_in(fi, x));
     if (l < dp) {
-      const bool pb = (Pb >> l) & 1ull, pa = (Pa >> l) & 1ull;
-      const uint64_t rb = EB[w][l] & Pb, ra = EA[w][l] & Pa;
-      const uint64_t cb = TB[w][l] & Pb, ca = TA[w][l] & Pa;
-      const int32_t tub = pb ? __popcll(rb | cb) : 0, tua = pa ? __popcll(ra | ca) : 0;
-      int64_t k4b = 0, k4a = 0;
-      if (pb) for (uint64_t m = rb; m; m &= m - 1) k4b += __popcll(rb & EB[w][__builtin_ctzll(m)] & Pb);
-      if (pa) for (uint64_t m = ra; m; m &= m - 1) k4a += __popcll(ra & EA[w][__builtin_ctzll(m)] & Pa);
-      kb_ += k4b; ka_ += k4a;
-      if (tub | tua) atomicAdd(&R.t[ub + l], pack2(tub, tua));
+      uint32_t tu[NV];
+      int64_t kv[NV];
+#pragma unroll
+      for (int x = 0; x < NV; ++x) {
+        tu[x] = 0;
+        kv[x] = 0;
+        if (x > 0 && clean) { tu[x] = tu[0]; kv[x] = kv[0]; continue; }
+        if (!((Px[x] >> l) & 1ull)) continue;
+        const unsigned long long e = EU[w][l] & ~EX[w][x][l] & Px[x];
+        const unsigned long long tt = TU[w][l] & ~TX[w][x][l] & Px[x];
+        tu[x] = (uint32_t)__popcll(e | tt);
+        int64_t k4 = 0;
+        for (unsigned long long m = e; m; m &= m - 1) {
+          const int j = __builtin_ctzll(m);
+          k4 += __popcll(e & EU[w][j] & ~EX[w][x][j] & Px[x]);
+        }
+        kv[x] = k4;
+      }
+#pragma unroll
+      for (int x = 0; x < NV; ++x) kacc[x] += kv[x];
+      t_addv<NV>(R, ub + l, tu);
     }
     wave_sync();
   }
-  if (cur_g >= 0) flush2(A.sig, cur_g, SG_K4, kb_, ka_);
+  if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_K4, kacc);
 }
 
 // ------------------------------------------------------ triangles, tier L
@@ -176,34 +291,41 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
 // graph induced on N+(u), union view).  4-cliques u < v_i < v_j < v_k then
 // follow from AND-popcounts of rows:
 //   K4_x(u) = sum_{i in P_x} sum_{j in E[i] & P_x} |E[i] & E[j] & P_x|
-// with P_x the slots whose edge from u exists in version x.  Edges among
-// N+(u) that exist in one version only are few; the triangles of E that
-// contain such an edge absent from version x are removed from K4_x one by
-// one (each once, at its first such edge in list order).  If the list
-// overflows, the matrix is rebuilt per version instead.
-constexpr int TL_EXC = 256;    // version-specific edges tracked per vertex
+// with P_x the slots whose edge from u exists in version x (versions with
+// equal P_x share one count).  Edges among N+(u) that are absent from some
+// version are few; the triangles of E that contain such an edge absent from
+// version x are removed from K4_x one by one (each once, at its first such
+// edge in list order).  If the list overflows, the matrix is rebuilt per
+// version instead.
+constexpr int TL_EXC = 256;  // edges with flags tracked per vertex
 
+template <int NV>
 struct TriL {
-  unsigned long long* E;   // [dp][W] row bitsets
-  unsigned long long* P;   // [2][W] slot masks of versions b, a
-  uint32_t* ids;           // [dp]
-  int32_t* hkey;           // [H]
-  int16_t* hval;           // [H]
-  uint32_t* tuc;           // [dp] packed 16-bit halves (b low, a high)
-  uint32_t* exc;           // [TL_EXC] i << 17 | j << 2 | flags >> 30
-  int32_t* nexc;           // [1]
-  int32_t W;               // words per row
+  using TU = typename Fields<NV, 16>::T;  // per-slot triangle counts, 16-bit field per version
+  unsigned long long* E;    // [dp][W] row bitsets
+  unsigned long long* P;    // [NV][W] slot masks per version
+  uint32_t* ids;            // [dp]
+  int32_t* hkey;            // [H]
+  int16_t* hval;            // [H]
+  TU* tuc;                  // [dp]
+  unsigned long long* exc;  // [TL_EXC] i << 32 | j << 4 | absence mask
+  int32_t* nexc;            // [1]
+  int32_t W;                // words per row
 };
 
-__device__ __forceinline__ bool Ebit(const TriL& S, int32_t p, int32_t q) {  // edge between slots p != q
+template <int NV>
+__device__ __forceinline__ bool Ebit(const TriL<NV>& S, int32_t p, int32_t q) {  // edge between slots p != q
   if (p > q) { int32_t t = p; p = q; q = t; }
   return (S.E[(int64_t)p * S.W + (q >> 6)] >> (q & 63)) & 1ull;
 }
 
+__device__ __forceinline__ bool bit_of(const unsigned long long* m, int32_t k) { return (m[k >> 6] >> (k & 63)) & 1ull; }
+
 // One wave: slots [g0, g0 + 64) of N+(u), their out-lists flattened over
-// lanes.  only = 0: union matrix plus all triangle bookkeeping; only = 1/2:
-// matrix of version b / a alone.
-__device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL& S, uint32_t hmask, int shift,
+// lanes.  only = 0: union matrix plus all triangle bookkeeping; only = x+1:
+// matrix of version x alone.
+template <int NV>
+__device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL<NV>& S, uint32_t hmask, int shift,
                                                 int32_t g0, int32_t dp, int only) {
   const RegionDev& R = A.R;
   const int l = lane_id();
@@ -236,30 +358,32 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL& 
     unsigned long long* Ei = S.E + (int64_t)i * S.W;
     const uint32_t fy = y & GC_FLAGS;
     if (only) {
-      if (!(fy & (only == 1 ? GC_F_NEW : GC_F_DEL))) atomicOr(&Ei[j >> 6], 1ull << (j & 63));
+      if (!absent_in(fy, only - 1)) atomicOr(&Ei[j >> 6], 1ull << (j & 63));
       continue;
     }
     atomicOr(&Ei[j >> 6], 1ull << (j & 63));
     if (fy) {
       const int32_t p = atomicAdd(S.nexc, 1);
-      if (p < TL_EXC) S.exc[p] = ((uint32_t)i << 17) | ((uint32_t)j << 2) | (fy >> 30);
+      if (p < TL_EXC)
+        S.exc[p] = ((unsigned long long)i << 32) | ((unsigned long long)j << 4) | (unsigned long long)(fy >> GC_VSHIFT);
     }
-    const uint32_t ab = fs | (S.ids[j] & GC_FLAGS) | fy;
-    const uint32_t xb = !(ab & GC_F_NEW), xa = !(ab & GC_F_DEL);
-    if (xb | xa) {
-      atomicAdd(&R.t[pos], pack2(xb, xa));
-      atomicAdd(&S.tuc[j], xb | (xa << 16));
-      atomicAdd(&S.tuc[i], xb | (xa << 16));
+    const uint32_t pm = vpresent<NV>(fs | (S.ids[j] & GC_FLAGS) | fy);
+    if (pm) {
+      t_add<NV>(R, pos, pm);
+      const typename TriL<NV>::TU add = Fields<NV, 16>::spread(pm);
+      atomicAdd(&S.tuc[j], add);
+      atomicAdd(&S.tuc[i], add);
     }
   }
 }
 
 // sum over i in mask, j in E[i] & mask of |E[i] & E[j] & mask|  (one wave's rows)
-__device__ __forceinline__ int64_t k4_rows(const TriL& S, const unsigned long long* mask, int32_t dp, int nwaves) {
+template <int NV>
+__device__ __forceinline__ int64_t k4_rows(const TriL<NV>& S, const unsigned long long* mask, int32_t dp, int nwaves) {
   const int w = threadIdx.x >> 6, l = lane_id();
   int64_t cnt = 0;
   for (int32_t i = w; i < dp; i += nwaves) {
-    if (!((mask[i >> 6] >> (i & 63)) & 1ull)) continue;
+    if (!bit_of(mask, i)) continue;
     const unsigned long long* Ei = S.E + (int64_t)i * S.W;
     for (int32_t w0 = i >> 6; w0 < S.W; ++w0) {
       const unsigned long long m = Ei[w0] & mask[w0];
@@ -274,8 +398,9 @@ __device__ __forceinline__ int64_t k4_rows(const TriL& S, const unsigned long lo
   return cnt;
 }
 
-__device__ void tri_large_vertex(const CountArgs& A, const TriL& S, int32_t u, int64_t ub, int32_t dp,
-                                 int64_t& kb_, int64_t& ka_) {
+template <int NV>
+__device__ void tri_large_vertex(const CountArgs& A, const TriL<NV>& S, int32_t u, int64_t ub, int32_t dp,
+                                 int64_t (&kacc)[NV]) {
   const RegionDev& R = A.R;
   const int w = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
@@ -287,7 +412,7 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL& S, int32_t u, i
   for (int32_t k = threadIdx.x; k < dp; k += blockDim.x) { S.ids[k] = R.rcol[ub + k]; S.tuc[k] = 0; }
   for (int32_t k = threadIdx.x; k < H; k += blockDim.x) S.hkey[k] = -1;
   for (int64_t k = threadIdx.x; k < (int64_t)dp * W; k += blockDim.x) S.E[k] = 0ull;
-  for (int32_t k = threadIdx.x; k < 2 * W; k += blockDim.x) S.P[k] = 0ull;
+  for (int32_t k = threadIdx.x; k < NV * W; k += blockDim.x) S.P[k] = 0ull;
   if (threadIdx.x == 0) *S.nexc = 0;
   __syncthreads();
   for (int32_t k = threadIdx.x; k < dp; k += blockDim.x) {
@@ -296,112 +421,142 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL& S, int32_t u, i
     uint32_t h = hash32(id) >> shift;
     while (atomicCAS(&S.hkey[h], -1, (int32_t)id) != -1) h = (h + 1) & hmask;
     S.hval[h] = (int16_t)k;
-    if (!(x & GC_F_NEW)) atomicOr(&S.P[k >> 6], 1ull << (k & 63));
-    if (!(x & GC_F_DEL)) atomicOr(&S.P[W + (k >> 6)], 1ull << (k & 63));
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+      if (!absent_in(x, q)) atomicOr(&S.P[q * W + (k >> 6)], 1ull << (k & 63));
   }
   __syncthreads();
-  for (int32_t g0 = w * 64; g0 < dp; g0 += nwaves * 64) tri_large_probe(A, S, hmask, shift, g0, dp, 0);
+  for (int32_t g0 = w * 64; g0 < dp; g0 += nwaves * 64) tri_large_probe<NV>(A, S, hmask, shift, g0, dp, 0);
   __syncthreads();
   const int32_t ne = *S.nexc;
-  const unsigned long long* Pb = S.P;
-  const unsigned long long* Pa = S.P + W;
   if (ne <= TL_EXC) {
-    bool same = true;
-    for (int32_t q = 0; q < W; ++q) same &= Pb[q] == Pa[q];
-    const int64_t cb = k4_rows(S, Pb, dp, nwaves);
-    const int64_t ca = same ? cb : k4_rows(S, Pa, dp, nwaves);
-    kb_ += cb;
-    ka_ += ca;
+    // versions with the same slot mask share one count
+    int64_t kv[NV];
+#pragma unroll
+    for (int x = 0; x < NV; ++x) {
+      int same = -1;
+      for (int y = 0; y < x && same < 0; ++y) {
+        bool eq = true;
+        for (int32_t q = 0; q < W && eq; ++q) eq = S.P[x * W + q] == S.P[y * W + q];
+        if (eq) same = y;
+      }
+      if (same >= 0) {
+#pragma unroll
+        for (int y = 0; y < NV; ++y)
+          if (y == same) kv[x] = kv[y];
+      } else {
+        kv[x] = k4_rows<NV>(S, S.P + x * W, dp, nwaves);
+      }
+    }
     // triangles of E (inside P_x) holding an edge absent from version x
     const int l = lane_id();
     for (int32_t e = w; e < ne; e += nwaves) {
-      const uint32_t ex = S.exc[e];
-      const int32_t i = (int32_t)(ex >> 17), j = (int32_t)((ex >> 2) & 0x7FFF);
-      const uint32_t fl = (ex & 3u) << 30;
-      for (int x = 0; x < 2; ++x) {
-        const uint32_t absent = x == 0 ? GC_F_NEW : GC_F_DEL;
-        if (!(fl & absent)) continue;
-        const unsigned long long* Px = x == 0 ? Pb : Pa;
-        if (!((Px[i >> 6] >> (i & 63)) & 1ull) || !((Px[j >> 6] >> (j & 63)) & 1ull)) continue;
+      const unsigned long long ex = S.exc[e];
+      const int32_t i = (int32_t)(ex >> 32), j = (int32_t)((ex >> 4) & 0xFFFFFFFull);
+      const uint32_t am = (uint32_t)(ex & 0xFull);
+#pragma unroll
+      for (int x = 0; x < NV; ++x) {
+        if (!((am >> x) & 1u)) continue;
+        const unsigned long long* Px = S.P + x * W;
+        if (!bit_of(Px, i) || !bit_of(Px, j)) continue;
         int64_t sub = 0;
         for (int32_t k = l; k < dp; k += 64) {
-          if (k == i || k == j || !((Px[k >> 6] >> (k & 63)) & 1ull)) continue;
-          if (!Ebit(S, i, k) || !Ebit(S, j, k)) continue;
+          if (k == i || k == j || !bit_of(Px, k)) continue;
+          if (!Ebit<NV>(S, i, k) || !Ebit<NV>(S, j, k)) continue;
           // count once: skip if an earlier listed edge of this triangle is absent from x
           bool first = true;
           for (int32_t f = 0; f < e && first; ++f) {
-            const uint32_t ef = S.exc[f];
-            if (!(((ef & 3u) << 30) & absent)) continue;
-            const int32_t fi = (int32_t)(ef >> 17), fj = (int32_t)((ef >> 2) & 0x7FFF);
+            const unsigned long long ef = S.exc[f];
+            if (!((ef >> x) & 1ull)) continue;
+            const int32_t fi = (int32_t)(ef >> 32), fj = (int32_t)((ef >> 4) & 0xFFFFFFFull);
             if ((fi == i && fj == k) || (fi == k && fj == i) || (fi == j && fj == k) || (fi == k && fj == j))
               first = false;
           }
           sub += first;
         }
-        if (x == 0) kb_ -= sub; else ka_ -= sub;
+        kv[x] -= sub;
       }
     }
+#pragma unroll
+    for (int x = 0; x < NV; ++x) kacc[x] += kv[x];
   } else {
     // too many version-specific edges: rebuild E per version and count
-    for (int x = 0; x < 2; ++x) {
+    for (int x = 0; x < NV; ++x) {
       __syncthreads();
       for (int64_t k = threadIdx.x; k < (int64_t)dp * W; k += blockDim.x) S.E[k] = 0ull;
       __syncthreads();
-      for (int32_t g0 = w * 64; g0 < dp; g0 += nwaves * 64) tri_large_probe(A, S, hmask, shift, g0, dp, x + 1);
+      for (int32_t g0 = w * 64; g0 < dp; g0 += nwaves * 64) tri_large_probe<NV>(A, S, hmask, shift, g0, dp, x + 1);
       __syncthreads();
-      const int64_t c = k4_rows(S, x == 0 ? Pb : Pa, dp, nwaves);
-      if (x == 0) kb_ += c; else ka_ += c;
+      const int64_t c = k4_rows<NV>(S, S.P + x * W, dp, nwaves);
+#pragma unroll
+      for (int y = 0; y < NV; ++y)
+        if (y == x) kacc[y] += c;
     }
   }
   __syncthreads();
   for (int32_t k = threadIdx.x; k < dp; k += blockDim.x) {
-    const uint32_t c = S.tuc[k];
-    if (c) atomicAdd(&R.t[ub + k], pack2(c & 0xFFFFu, c >> 16));
+    const typename TriL<NV>::TU c = S.tuc[k];
+    if (c) {
+      uint32_t cv[NV];
+#pragma unroll
+      for (int x = 0; x < NV; ++x) cv[x] = (uint32_t)Fields<NV, 16>::get(c, x);
+      t_addv<NV>(R, ub + k, cv);
+    }
   }
   __syncthreads();
 }
 
-// global-scratch slot layout (u64 words): E [cap*W] | P [2W] | then u32 words:
-// ids [cap] | tuc [cap] | hkey [4 cap] | hval [2 cap] | exc [TL_EXC] | nexc [2]
+// global-scratch slot layout (u64 words): E [cap*W] | P [NV*W] | tuc [cap] |
+// exc [TL_EXC] | then u32 words: ids [cap] | hkey [4 cap] | hval [2 cap] | nexc [2]
+template <int NV>
 __host__ __device__ inline int64_t tri_slot_words64(int64_t cap) {
   const int64_t W = ((cap + 63) / 64) | 1;
-  return cap * W + 2 * W + (cap + cap + 4 * cap + 2 * cap + TL_EXC + 2 + 1) / 2 + 8;
+  return cap * W + NV * W + cap + TL_EXC + (cap + 4 * cap + 2 * cap + 2 + 1) / 2 + 8;
+}
+
+constexpr int pow2_at_least(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
 }
 
 // Vertices with out-degree in (LO, CAP]; CAP = 0 selects the global-memory
 // scratch for everything above LO.
-template <int CAP, int THREADS>
+template <int CAP, int THREADS, int NV>
 __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int32_t lo_dp) {
   const RegionDev& R = A.R;
   const int64_t n = (int64_t)A.c[C_LIST0 + L_TRI_L];
   const int32_t* list = A.lists + L_TRI_L * A.list_stride;
   int cur_g = -1;
-  int64_t kb_ = 0, ka_ = 0;
-  TriL S;
+  int64_t kacc[NV];
+  zerov<NV>(kacc);
+  TriL<NV> S;
+  using TU = typename TriL<NV>::TU;
   if constexpr (CAP == 0) {
     const int64_t cap = A.tri_cap;
     const int64_t W = ((cap + 63) / 64) | 1;
-    unsigned long long* base = (unsigned long long*)A.tri_scratch + (int64_t)blockIdx.x * tri_slot_words64(cap);
+    unsigned long long* base = A.tri_scratch + (int64_t)blockIdx.x * tri_slot_words64<NV>(cap);
     S.W = (int32_t)W;
     S.E = base;
     S.P = base + cap * W;
-    uint32_t* u32 = (uint32_t*)(S.P + 2 * W);
+    S.tuc = (TU*)(S.P + NV * W);
+    S.exc = S.P + NV * W + cap;
+    uint32_t* u32 = (uint32_t*)(S.exc + TL_EXC);
     S.ids = u32;
-    S.tuc = u32 + cap;
-    S.hkey = (int32_t*)(u32 + 2 * cap);
-    S.hval = (int16_t*)(u32 + 6 * cap);
-    S.exc = u32 + 8 * cap;
-    S.nexc = (int32_t*)(u32 + 8 * cap + TL_EXC);
+    S.hkey = (int32_t*)(u32 + cap);
+    S.hval = (int16_t*)(u32 + 5 * cap);
+    S.nexc = (int32_t*)(u32 + 7 * cap);
   } else {
     constexpr int CW = CAP / 64;
     constexpr int CWS = CW | 1;  // largest odd row stride used
+    constexpr int HC = pow2_at_least(2 * CAP);
     __shared__ unsigned long long E[CAP * CWS];
-    __shared__ unsigned long long P[2 * CWS];
+    __shared__ unsigned long long P[NV * CWS];
     __shared__ uint32_t ids[CAP];
-    __shared__ uint32_t tuc[CAP];
-    __shared__ int32_t hkey[2 * CAP];
-    __shared__ int16_t hval[2 * CAP];
-    __shared__ uint32_t exc[TL_EXC];
+    __shared__ TU tuc[CAP];
+    __shared__ int32_t hkey[HC];
+    __shared__ int16_t hval[HC];
+    __shared__ unsigned long long exc[TL_EXC];
     __shared__ int32_t nexc;
     S.E = E; S.P = P; S.ids = ids; S.tuc = tuc; S.hkey = hkey; S.hval = hval; S.exc = exc; S.nexc = &nexc;
     S.W = CWS;
@@ -413,17 +568,17 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int32_t lo_d
     if (dp <= lo_dp || (CAP != 0 && dp > CAP)) continue;
     const int g = A.gid[u];
     if (g != cur_g) {
-      if (cur_g >= 0) flush2(A.sig, cur_g, SG_K4, kb_, ka_);
+      if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_K4, kacc);
       cur_g = g;
     }
     if constexpr (CAP != 0) S.W = ((dp + 63) / 64) | 1;  // odd row stride: rows spread over LDS banks
-    tri_large_vertex(A, S, u, ub, dp, kb_, ka_);
+    tri_large_vertex<NV>(A, S, u, ub, dp, kacc);
   }
-  if (cur_g >= 0) flush2(A.sig, cur_g, SG_K4, kb_, ka_);
+  if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_K4, kacc);
 }
 
 constexpr int TL_MID = 256;
-constexpr int TL_MAX = 1024;
+template <int NV> constexpr int tl_max() { return NV == 2 ? 1024 : 960; }
 
 // ------------------------------------------------------------ edge pass
 // After all triangles, per upper entry u -> w present in version x, with
@@ -432,59 +587,64 @@ constexpr int TL_MAX = 1024;
 //   T3  += t                        (= 3 T)
 //   PAW2 += t (d_u + d_w - 4)       (= 2 N_paw: a triangle on the edge plus a
 //                                    pendant edge at one of its ends)
-constexpr int EP_RUN = 128;
+// One thread per entry, grid-stride: consecutive lanes read consecutive
+// entries (row ids come from the region build).
+template <int NV>
+__device__ __forceinline__ void edge_flush_lane(unsigned long long* sig, int g, int64_t (&acc)[4][NV]) {
+  const int keys[4] = {SG_S2, SG_DIA, SG_T, SG_PAW};
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int x = 0; x < NV; ++x) {
+      if (acc[k][x]) atomicAdd(&sig[SIG_IDX(g, x, keys[k])], (unsigned long long)acc[k][x]);
+      acc[k][x] = 0;
+    }
+}
 
+template <int NV>
 __global__ __launch_bounds__(256) void k_edge_pass(CountArgs A) {
   const RegionDev& R = A.R;
   const int64_t E = (int64_t)A.c[C_ER];
   int cur_g = -1;
-  int64_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // s2 b/a, dia b/a, t3 b/a, paw2 b/a
-  const int keys[4] = {SG_S2, SG_DIA, SG_T, SG_PAW};
-  for (int64_t run = gtid(); run * EP_RUN < E; run += gstride()) {
-    const int64_t p0 = run * EP_RUN;
-    const int64_t p1 = p0 + EP_RUN < E ? p0 + EP_RUN : E;
-    int64_t u = upper_bound_i64(R.roff, A.N, p0);
-    int64_t nxt = R.roff[u + 1];
-    int32_t dBu = R.dB[u], dAu = R.dA[u];
-    for (int64_t p = p0; p < p1; ++p) {
-      while (nxt <= p) { ++u; nxt = R.roff[u + 1]; dBu = R.dB[u]; dAu = R.dA[u]; }
-      const uint32_t x = R.rcol[p];
-      const uint32_t wv = x & GC_ID;
-      if (wv <= (uint32_t)u) continue;
-      const int g = A.gid[u];
-      if (g != cur_g) {
-        if (cur_g >= 0)
-          for (int k = 0; k < 8; ++k) {
-            if (acc[k]) atomicAdd(&A.sig[SIG_IDX(cur_g, k & 1, keys[k >> 1])], (unsigned long long)acc[k]);
-            acc[k] = 0;
-          }
-        cur_g = g;
-      }
-      const unsigned long long tt = R.t[p];
-      if (!(x & GC_F_NEW)) {
-        const int64_t t = (int64_t)(tt & 0xFFFFFFFFull);
-        const int32_t dw = R.dB[wv];
-        acc[0] += (int64_t)(dBu - 1) * (dw - 1);
-        acc[2] += c2(t);
-        acc[4] += t;
-        acc[6] += t * (dBu + dw - 4);
-      }
-      if (!(x & GC_F_DEL)) {
-        const int64_t t = (int64_t)(tt >> 32);
-        const int32_t dw = R.dA[wv];
-        acc[1] += (int64_t)(dAu - 1) * (dw - 1);
-        acc[3] += c2(t);
-        acc[5] += t;
-        acc[7] += t * (dAu + dw - 4);
-      }
+  int64_t acc[4][NV];  // s2, dia, t3, paw2 per version
+#pragma unroll
+  for (int k = 0; k < 4; ++k) zerov<NV>(acc[k]);
+  for (int64_t p = gtid(); p < E; p += gstride()) {
+    const uint32_t x = R.rcol[p];
+    const uint32_t wv = x & GC_ID;
+    const int32_t u = R.rrow[p];
+    if (wv <= (uint32_t)u) continue;
+    const int g = A.gid[u];
+    if (g != cur_g) {
+      if (cur_g >= 0) edge_flush_lane<NV>(A.sig, cur_g, acc);
+      cur_g = g;
+    }
+    const uint32_t pm = vpresent<NV>(x);
+    int64_t t[NV];
+    int32_t du[NV], dw[NV];
+    t_read<NV>(R, p, t);
+    d_read<NV>(R, u, du);
+    d_read<NV>(R, wv, dw);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      if (!((pm >> q) & 1u)) continue;
+      acc[0][q] += (int64_t)(du[q] - 1) * (dw[q] - 1);
+      acc[1][q] += c2(t[q]);
+      acc[2][q] += t[q];
+      acc[3][q] += t[q] * (du[q] + dw[q] - 4);
     }
   }
   // wave-uniform graph: one atomic per wave, else per lane
   const int g0 = __shfl(cur_g, 0);
   const bool uniform = __ballot(cur_g == g0 || cur_g < 0) == ~0ull && g0 >= 0;
-  for (int k = 0; k < 8; ++k) {
-    if (uniform) flush_sig(A.sig, g0, k & 1, keys[k >> 1], acc[k]);
-    else if (cur_g >= 0 && acc[k]) atomicAdd(&A.sig[SIG_IDX(cur_g, k & 1, keys[k >> 1])], (unsigned long long)acc[k]);
+  if (uniform) {
+    const int keys[4] = {SG_S2, SG_DIA, SG_T, SG_PAW};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int q = 0; q < NV; ++q) flush_sig(A.sig, g0, q, keys[k], acc[k][q]);
+  } else if (cur_g >= 0) {
+    edge_flush_lane<NV>(A.sig, cur_g, acc);
   }
 }
 
@@ -497,7 +657,7 @@ __device__ __forceinline__ void c4_segment(const RegionDev& R, uint32_t v, uint3
 }
 
 // Wave-flattened walk over the wedges (v, u, w) for the lower neighbours
-// u in positions [g0, g0 + 64) of row v; calls f(w, add_b, add_a).
+// u in positions [g0, g0 + 64) of row v; calls f(w, flags of both entries).
 template <class F>
 __device__ __forceinline__ void c4_group(const RegionDev& R, uint32_t v, int64_t rb, int32_t nlow, int32_t g0, F f) {
   const int l = lane_id();
@@ -521,9 +681,7 @@ __device__ __forceinline__ void c4_group(const RegionDev& R, uint32_t v, int64_t
     const uint32_t fs = __shfl(fvu, s);
     if (idx < tot) {
       const uint32_t y = R.rcol[sbs + (idx - exs)];
-      const uint32_t ab = fs | (y & GC_FLAGS);
-      const uint32_t xb = !(ab & GC_F_NEW), xa = !(ab & GC_F_DEL);
-      if (xb | xa) f(y & GC_ID, xb, xa);
+      f(y & GC_ID, fs | (y & GC_FLAGS));
     }
   }
 }
@@ -531,90 +689,103 @@ __device__ __forceinline__ void c4_group(const RegionDev& R, uint32_t v, int64_t
 constexpr int C4S_SLOTS = 512;
 constexpr int C4S_WAVES = 4;
 
+// c(v, w) <= wedges of v <= 4096 in the small and mid tiers: 16-bit fields
+template <int NV>
 __global__ __launch_bounds__(256) void k_c4_small(CountArgs A) {
+  using F = Fields<NV, 16>;
+  using T = typename F::T;
   __shared__ int32_t hkey[C4S_WAVES][C4S_SLOTS];
-  __shared__ uint32_t hcnt[C4S_WAVES][C4S_SLOTS];
+  __shared__ T hcnt[C4S_WAVES][C4S_SLOTS];
   const int w = threadIdx.x >> 6, l = lane_id();
   const RegionDev& R = A.R;
   const int64_t n = (int64_t)A.c[C_LIST0 + L_C4_S];
   const int32_t* list = A.lists + L_C4_S * A.list_stride;
   int cur_g = -1;
-  int64_t cb_ = 0, ca_ = 0;
+  int64_t acc[NV];
+  zerov<NV>(acc);
   for (int s = l; s < C4S_SLOTS; s += 64) { hkey[w][s] = -1; hcnt[w][s] = 0; }
   wave_sync();
   for (int64_t it = (int64_t)blockIdx.x * C4S_WAVES + w; it < n; it += (int64_t)gridDim.x * C4S_WAVES) {
     const int32_t v = list[it];
     const int g = A.gid[v];
-    if (g != cur_g) { if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_); cur_g = g; }
+    if (g != cur_g) { if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_C4, acc); cur_g = g; }
     const int64_t rb = R.roff[v];
     const int32_t nlow = R.rlow[v];
     int32_t* hk = hkey[w];
-    uint32_t* hc = hcnt[w];
+    T* hc = hcnt[w];
     for (int32_t g0 = 0; g0 < nlow; g0 += 64)
-      c4_group(R, (uint32_t)v, rb, nlow, g0, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
-        hash_add<uint32_t>(hk, hc, C4S_SLOTS - 1, 23, wid, xb | (xa << 16));
+      c4_group(R, (uint32_t)v, rb, nlow, g0, [&](uint32_t wid, uint32_t fl) {
+        const uint32_t pm = vpresent<NV>(fl);
+        if (pm) hash_add<T>(hk, hc, C4S_SLOTS - 1, 23, wid, F::spread(pm));
       });
     wave_sync();
     for (int s = l; s < C4S_SLOTS; s += 64) {
       if (hk[s] != -1) {
-        const uint32_t c = hc[s];
-        cb_ += c2(c & 0xFFFFu);
-        ca_ += c2(c >> 16);
+        const T c = hc[s];
+#pragma unroll
+        for (int x = 0; x < NV; ++x) acc[x] += c2(F::get(c, x));
         hk[s] = -1; hc[s] = 0;
       }
     }
     wave_sync();
   }
-  if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_);
+  if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_C4, acc);
 }
 
 constexpr int C4M_SLOTS = 8192;
 
+template <int NV>
 __global__ __launch_bounds__(256) void k_c4_mid(CountArgs A) {
+  using F = Fields<NV, 16>;
+  using T = typename F::T;
   __shared__ int32_t hkey[C4M_SLOTS];
-  __shared__ uint32_t hcnt[C4M_SLOTS];
+  __shared__ T hcnt[C4M_SLOTS];
   const int w = threadIdx.x >> 6;
   const RegionDev& R = A.R;
   const int64_t n = (int64_t)A.c[C_LIST0 + L_C4_M];
   const int32_t* list = A.lists + L_C4_M * A.list_stride;
   int cur_g = -1;
-  int64_t cb_ = 0, ca_ = 0;
+  int64_t acc[NV];
+  zerov<NV>(acc);
   for (int s = threadIdx.x; s < C4M_SLOTS; s += blockDim.x) { hkey[s] = -1; hcnt[s] = 0; }
   __syncthreads();
   for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
     const int32_t v = list[it];
     const int g = A.gid[v];
-    if (g != cur_g) { if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_); cur_g = g; }
+    if (g != cur_g) { if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_C4, acc); cur_g = g; }
     const int64_t rb = R.roff[v];
     const int32_t nlow = R.rlow[v];
     for (int32_t g0 = w * 64; g0 < nlow; g0 += 64 * 4)
-      c4_group(R, (uint32_t)v, rb, nlow, g0, [&](uint32_t wid, uint32_t xb, uint32_t xa) {
-        hash_add<uint32_t>(hkey, hcnt, C4M_SLOTS - 1, 19, wid, xb | (xa << 16));
+      c4_group(R, (uint32_t)v, rb, nlow, g0, [&](uint32_t wid, uint32_t fl) {
+        const uint32_t pm = vpresent<NV>(fl);
+        if (pm) hash_add<T>(hkey, hcnt, C4M_SLOTS - 1, 19, wid, F::spread(pm));
       });
     __syncthreads();
     for (int s = threadIdx.x; s < C4M_SLOTS; s += blockDim.x) {
       if (hkey[s] != -1) {
-        const uint32_t c = hcnt[s];
-        cb_ += c2(c & 0xFFFFu);
-        ca_ += c2(c >> 16);
+        const T c = hcnt[s];
+#pragma unroll
+        for (int x = 0; x < NV; ++x) acc[x] += c2(F::get(c, x));
         hkey[s] = -1; hcnt[s] = 0;
       }
     }
     __syncthreads();
   }
-  if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_);
+  if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_C4, acc);
 }
 
 // Large tier: one workgroup per hub v at a time, hubs in decreasing order of
 // wedge work.  The opposite vertices w < v are taken in windows of ids from
 // v downwards; a window with enough hits gets dense LDS counters (16-bit
-// halves while c(v, w) <= 65535 can be guaranteed, which doubles the window).
+// fields while c(v, w) <= 65535 can be guaranteed, which widens the window).
 // Hits concentrate just below v because ids are a degree order and a wedge
 // reaches w with odds growing with deg w.  Once a window is sparse, all
 // wedges below it go to dense counters in global memory (one array per
 // resident workgroup, with a touched list).  Each lower neighbour u keeps a
 // cursor in its row: one binary search for v, then a short backward gallop
-// per window, so rows are read about once.
+// per window, so rows are read about once.  Four versions with 32-bit
+// fields would not fit a 64-bit counter: such hubs are walked twice, for
+// versions 0-1 and 2-3.
 constexpr int C4W_WIN = 16384;
 constexpr int C4W_T = 1024;
 
@@ -624,6 +795,13 @@ struct C4Chunk {
   uint32_t fl[C4W_T];
   int32_t wsum[C4W_T / 64];
   long long red[C4W_T / 64][2];
+};
+
+struct C4Smem {
+  unsigned long long win[C4W_WIN];
+  C4Chunk C;
+  int64_t item;
+  int32_t nt;
 };
 
 // first p in [0, c) with id(row[p]) >= lo, rows sorted, id(row[c-1]) < v
@@ -648,7 +826,7 @@ __device__ __forceinline__ void block_sum2(C4Chunk& C, long long& x, long long& 
 }
 
 // Walk the wedges (v, u_q, w) for q in [0, nlow) with w in row u_q at
-// positions [urow[q] + p0(q), urow[q] + p1(q)); f(w, add_b, add_a).
+// positions [urow[q] + p0(q), urow[q] + p1(q)); f(w, flags of both entries).
 // Short slices (the common case: u_q has few entries in the id range) are
 // walked by their own thread; long ones are spread over the whole block
 // with a scan of their lengths and a binary search per element.
@@ -668,9 +846,7 @@ __device__ __forceinline__ void c4_block_walk(const RegionDev& R, int64_t rb, in
       if (p1 - p0 <= C4W_SHORT) {
         for (int64_t p = sb; p < sb + (p1 - p0); ++p) {
           const uint32_t y = R.rcol[p];
-          const uint32_t ab = fl | (y & GC_FLAGS);
-          const uint32_t xb = !(ab & GC_F_NEW), xa = !(ab & GC_F_DEL);
-          if (xb | xa) f(y & GC_ID, xb, xa);
+          f(y & GC_ID, fl | (y & GC_FLAGS));
         }
       } else {
         C.sb[t] = sb;
@@ -694,9 +870,7 @@ __device__ __forceinline__ void c4_block_walk(const RegionDev& R, int64_t rb, in
           int32_t a = 0, z = C4W_T;  // largest a with pre[a] <= idx
           while (z - a > 1) { const int32_t m = (a + z) >> 1; if (C.pre[m] <= idx) a = m; else z = m; }
           const uint32_t y = R.rcol[C.sb[a] + (idx - C.pre[a])];
-          const uint32_t ab = C.fl[a] | (y & GC_FLAGS);
-          const uint32_t xb = !(ab & GC_F_NEW), xa = !(ab & GC_F_DEL);
-          if (xb | xa) f(y & GC_ID, xb, xa);
+          f(y & GC_ID, C.fl[a] | (y & GC_FLAGS));
         }
       }
     }
@@ -704,98 +878,123 @@ __device__ __forceinline__ void c4_block_walk(const RegionDev& R, int64_t rb, in
   }
 }
 
-__global__ __launch_bounds__(C4W_T) void k_c4_large(CountArgs A, unsigned long long* qhead) {
-  __shared__ unsigned long long win[C4W_WIN];
-  __shared__ C4Chunk C;
-  __shared__ int64_t s_item;
-  __shared__ int32_t s_nt;
+// One hub v, versions [vsh, vsh + NF) of an NV-version pass.  Window
+// counters: NF fields of FBW bits; tail counters in global memory: one u64
+// of NF fields (64 / NF bits each).
+template <int NV, int NF, int FBW>
+__device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_t (&acc)[NV], int64_t& tail_) {
+  using WFd = Fields<NF, FBW>;
+  using WT = typename WFd::T;
+  using TFd = Fields<NF, 64 / NF>;
   const RegionDev& R = A.R;
-  const int64_t n = (int64_t)A.c[C_LIST0 + L_C4_L];
-  const int32_t* list = A.lists + L_C4_L * A.list_stride;
+  const int t = threadIdx.x;
   unsigned long long* cnt = A.c4_dense + (int64_t)blockIdx.x * A.N;
   int32_t* touch = A.c4_touch + (int64_t)blockIdx.x * A.N;
   int64_t* urow = A.c4_cur + (int64_t)blockIdx.x * 2 * A.c4_maxlow;
   int32_t* ucur = (int32_t*)(urow + A.c4_maxlow);
   int32_t* unext = ucur + A.c4_maxlow;
+  const int64_t rb = R.roff[v];
+  const int32_t nlow = R.rlow[v];
+  const uint32_t fmask = (1u << NF) - 1u;
+  const int64_t ws = (int64_t)A.c4_win * 8 / (int64_t)sizeof(WT);  // ids per window
+  if (t == 0) S.nt = 0;
+  for (int32_t q = t; q < nlow; q += C4W_T) {
+    urow[q] = R.roff[R.rcol[rb + q] & GC_ID];
+    ucur[q] = R.vpos[rb + q];
+  }
+  __syncthreads();
+  int64_t hi = v;
+  while (hi > 0) {
+    const uint32_t lo = (uint32_t)(hi - ws > 0 ? hi - ws : 0);
+    long long wtot = 0, rest = 0;
+    for (int32_t q = t; q < nlow; q += C4W_T) {
+      const int32_t c = ucur[q];
+      const int32_t p0 = gallop_down(R.rcol + urow[q], c, lo);
+      unext[q] = p0;
+      wtot += c - p0;
+      rest += p0;
+    }
+    block_sum2(S.C, wtot, rest);
+    if (wtot >= A.c4_dense_min) {
+      WT* wn = (WT*)S.win;
+      for (int s = t; s < A.c4_win; s += C4W_T) S.win[s] = 0ull;
+      __syncthreads();
+      c4_block_walk(R, rb, nlow, urow, [&](int32_t q) { return unext[q]; }, [&](int32_t q) { return ucur[q]; }, S.C,
+                    [&](uint32_t wid, uint32_t fl) {
+                      const uint32_t sub = (vpresent<NV>(fl) >> vsh) & fmask;
+                      if (sub) atomicAdd(&wn[wid - lo], WFd::spread(sub));
+                    });
+      for (int64_t s = t; s < ws; s += C4W_T) {
+        const WT c = wn[s];
+        if (c) {
+#pragma unroll
+          for (int x = 0; x < NF; ++x) acc[vsh + x] += c2(WFd::get(c, x));
+        }
+      }
+      for (int32_t q = t; q < nlow; q += C4W_T) ucur[q] = unext[q];
+      __syncthreads();
+      hi = lo;
+      if (rest == 0) break;
+    } else {
+      // sparse from here down: every remaining wedge in global memory
+      c4_block_walk(R, rb, nlow, urow, [&](int32_t) { return 0; }, [&](int32_t q) { return ucur[q]; }, S.C,
+                    [&](uint32_t wid, uint32_t fl) {
+                      const uint32_t sub = (vpresent<NV>(fl) >> vsh) & fmask;
+                      if (!sub) return;
+                      ++tail_;
+                      const unsigned long long old = atomicAdd(&cnt[wid], (unsigned long long)TFd::spread(sub));
+                      if (old == 0ull) touch[atomicAdd(&S.nt, 1)] = (int32_t)wid;
+                    });
+      const int32_t nt = S.nt;
+      for (int32_t q = t; q < nt; q += C4W_T) {
+        const int32_t wid = touch[q];
+        const unsigned long long c = cnt[wid];
+        cnt[wid] = 0ull;
+#pragma unroll
+        for (int x = 0; x < NF; ++x) acc[vsh + x] += c2(TFd::get(c, x));
+      }
+      __syncthreads();
+      break;
+    }
+  }
+  __syncthreads();
+}
+
+template <int NV>
+__global__ __launch_bounds__(C4W_T) void k_c4_large(CountArgs A, unsigned long long* qhead) {
+  __shared__ C4Smem S;
+  const RegionDev& R = A.R;
+  const int64_t n = (int64_t)A.c[C_LIST0 + L_C4_L];
+  const int32_t* list = A.lists + L_C4_L * A.list_stride;
   const int t = threadIdx.x;
   int cur_g = -1;
-  int64_t cb_ = 0, ca_ = 0, tail_ = 0;
+  int64_t acc[NV];
+  zerov<NV>(acc);
+  int64_t tail_ = 0;
   while (true) {
     __syncthreads();  // every thread has read the previous item before it is replaced
-    if (t == 0) { s_item = (int64_t)atomicAdd(qhead, 1ull); s_nt = 0; }
+    if (t == 0) S.item = (int64_t)atomicAdd(qhead, 1ull);
     __syncthreads();
-    const int64_t item = s_item;
+    const int64_t item = S.item;
     if (item >= n) break;
     const int32_t v = list[item];
     const int g = A.gid[v];
-    if (g != cur_g) { if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_); cur_g = g; }
-    const int64_t rb = R.roff[v];
-    const int32_t nlow = R.rlow[v];
-    // c(v, w) <= nlow: 16-bit halves suffice up to 65535 lower neighbours
-    const bool narrow = nlow <= A.c4_narrow_max;
-    const int64_t ws = narrow ? 2 * (int64_t)A.c4_win : (int64_t)A.c4_win;
-    for (int32_t q = t; q < nlow; q += C4W_T) {
-      urow[q] = R.roff[R.rcol[rb + q] & GC_ID];
-      ucur[q] = R.vpos[rb + q];
-    }
-    __syncthreads();
-    int64_t hi = v;
-    while (hi > 0) {
-      const uint32_t lo = (uint32_t)(hi - ws > 0 ? hi - ws : 0);
-      long long wtot = 0, rest = 0;
-      for (int32_t q = t; q < nlow; q += C4W_T) {
-        const int32_t c = ucur[q];
-        const int32_t p0 = gallop_down(R.rcol + urow[q], c, lo);
-        unext[q] = p0;
-        wtot += c - p0;
-        rest += p0;
-      }
-      block_sum2(C, wtot, rest);
-      if (wtot >= A.c4_dense_min) {
-        for (int s = t; s < A.c4_win; s += C4W_T) win[s] = 0ull;
-        __syncthreads();
-        if (narrow) {
-          uint32_t* w32 = (uint32_t*)win;
-          c4_block_walk(R, rb, nlow, urow, [&](int32_t q) { return unext[q]; }, [&](int32_t q) { return ucur[q]; }, C,
-                        [&](uint32_t wid, uint32_t xb, uint32_t xa) { atomicAdd(&w32[wid - lo], xb | (xa << 16)); });
-          for (int s = t; s < 2 * A.c4_win; s += C4W_T) {
-            const uint32_t c = w32[s];
-            if (c) { cb_ += c2((int64_t)(c & 0xFFFFu)); ca_ += c2((int64_t)(c >> 16)); }
-          }
-        } else {
-          c4_block_walk(R, rb, nlow, urow, [&](int32_t q) { return unext[q]; }, [&](int32_t q) { return ucur[q]; }, C,
-                        [&](uint32_t wid, uint32_t xb, uint32_t xa) { atomicAdd(&win[wid - lo], pack2(xb, xa)); });
-          for (int s = t; s < A.c4_win; s += C4W_T) {
-            const unsigned long long c = win[s];
-            if (c) { cb_ += c2((int64_t)(c & 0xFFFFFFFFull)); ca_ += c2((int64_t)(c >> 32)); }
-          }
-        }
-        for (int32_t q = t; q < nlow; q += C4W_T) ucur[q] = unext[q];
-        __syncthreads();
-        hi = lo;
-        if (rest == 0) break;
+    if (g != cur_g) { if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_C4, acc); cur_g = g; }
+    // c(v, w) <= nlow: 16-bit fields suffice up to 65535 lower neighbours
+    const bool narrow = R.rlow[v] <= A.c4_narrow_max;
+    if constexpr (NV == 2) {
+      if (narrow) c4_hub<2, 2, 16>(A, S, v, 0, acc, tail_);
+      else c4_hub<2, 2, 32>(A, S, v, 0, acc, tail_);
+    } else {
+      if (narrow) {
+        c4_hub<4, 4, 16>(A, S, v, 0, acc, tail_);
       } else {
-        // sparse from here down: every remaining wedge in global memory
-        c4_block_walk(R, rb, nlow, urow, [&](int32_t) { return 0; }, [&](int32_t q) { return ucur[q]; }, C,
-                      [&](uint32_t wid, uint32_t xb, uint32_t xa) {
-                        ++tail_;
-                        const unsigned long long old = atomicAdd(&cnt[wid], pack2(xb, xa));
-                        if (old == 0ull) touch[atomicAdd(&s_nt, 1)] = (int32_t)wid;
-                      });
-        const int32_t nt = s_nt;
-        for (int32_t q = t; q < nt; q += C4W_T) {
-          const int32_t wid = touch[q];
-          const unsigned long long c = cnt[wid];
-          cnt[wid] = 0ull;
-          cb_ += c2((int64_t)(c & 0xFFFFFFFFull));
-          ca_ += c2((int64_t)(c >> 32));
-        }
-        __syncthreads();
-        break;
+        c4_hub<4, 2, 32>(A, S, v, 0, acc, tail_);
+        c4_hub<4, 2, 32>(A, S, v, 2, acc, tail_);
       }
     }
   }
-  if (cur_g >= 0) flush2(A.sig, cur_g, SG_C4, cb_, ca_);
+  if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_C4, acc);
   tail_ = wave_sum64(tail_);
   if (lane_id() == 0 && tail_) atomicAdd(&A.bstats[BS_TRIPROBE], (unsigned long long)tail_);
 }
@@ -807,15 +1006,17 @@ __global__ void k_c4_order(const unsigned long long* sorted, const unsigned long
 }
 
 // --------------------------------------------------------------- combine
-// C' = C_a - C_b on the six connected classes (Alg. 2), through the
-// non-induced counts of each version and the triangular relation between
-// non-induced and induced counts (copies of pattern X inside class Y).
-__global__ void k_combine(const unsigned long long* sig, long long* state, int32_t k) {
+// C' = C_x - C_0 on the six connected classes for every later version x
+// (Alg. 2), through the non-induced counts of each version and the
+// triangular relation between non-induced and induced counts (copies of
+// pattern X inside class Y).
+template <int NV>
+__global__ void k_combine(const unsigned long long* sig, long long* state, long long* vout, int32_t k) {
   const int64_t g = gtid();
   if (g >= k) return;
-  int64_t N[2][6], T[2], W[2], D1[2];
+  int64_t N[NV][6], T[NV], W[NV], D1[NV];
   int bad = 0;
-  for (int x = 0; x < 2; ++x) {
+  for (int x = 0; x < NV; ++x) {
     const unsigned long long* s = sig + SIG_IDX(g, x, 0);
     const int64_t t3 = (int64_t)s[SG_T], paw2 = (int64_t)s[SG_PAW];
     bad |= (t3 % 3 != 0) | (paw2 % 2 != 0);
@@ -829,21 +1030,29 @@ __global__ void k_combine(const unsigned long long* sig, long long* state, int32
     T[x] = t; W[x] = (int64_t)s[SG_W]; D1[x] = (int64_t)s[SG_D1];
     bad |= (D1[x] % 2 != 0);
   }
-  int64_t d[6];
-  for (int c = 0; c < 6; ++c) d[c] = N[1][c] - N[0][c];
-  int64_t I[6];
-  I[5] = d[5];
-  I[4] = d[4] - 6 * I[5];
-  I[3] = d[3] - 4 * I[4] - 12 * I[5];
-  I[2] = d[2] - I[4] - 3 * I[5];
-  I[0] = d[0] - 2 * I[3] - 4 * I[2] - 6 * I[4] - 12 * I[5];
-  I[1] = d[1] - I[3] - 2 * I[4] - 4 * I[5];
   long long* st = state + g * ST_STRIDE;
-  for (int c = 0; c < 6; ++c) st[ST_F0 + c] += I[c];
-  st[ST_T] += T[1] - T[0];
-  st[ST_W] += W[1] - W[0];
-  st[ST_M] += (D1[1] - D1[0]) / 2;
-  if (bad) st[ST_ERR] += 1;
+  long long base[ST_STRIDE];
+  for (int c = 0; c < ST_STRIDE; ++c) base[c] = st[c];
+  for (int x = 1; x < NV; ++x) {
+    int64_t d[6];
+    for (int c = 0; c < 6; ++c) d[c] = N[x][c] - N[0][c];
+    int64_t I[6];
+    I[5] = d[5];
+    I[4] = d[4] - 6 * I[5];
+    I[3] = d[3] - 4 * I[4] - 12 * I[5];
+    I[2] = d[2] - I[4] - 3 * I[5];
+    I[0] = d[0] - 2 * I[3] - 4 * I[2] - 6 * I[4] - 12 * I[5];
+    I[1] = d[1] - I[3] - 2 * I[4] - 4 * I[5];
+    long long* o = vout + ((int64_t)(x - 1) * k + g) * ST_STRIDE;
+    for (int c = 0; c < ST_STRIDE; ++c) o[c] = base[c];
+    for (int c = 0; c < 6; ++c) o[ST_F0 + c] += I[c];
+    o[ST_T] += T[x] - T[0];
+    o[ST_W] += W[x] - W[0];
+    o[ST_M] += (D1[x] - D1[0]) / 2;
+    if (bad) o[ST_ERR] += 1;
+    if (x == NV - 1)
+      for (int c = 0; c < ST_STRIDE; ++c) st[c] = o[c];
+  }
 }
 
 inline unsigned cap_grid(int64_t want, unsigned cap) {
@@ -851,45 +1060,58 @@ inline unsigned cap_grid(int64_t want, unsigned cap) {
   return (unsigned)(want > cap ? cap : want);
 }
 
-}  // namespace
-
-int32_t c4_window_max() { return C4W_WIN; }
-int64_t tri_scratch_words64(int64_t cap) { return tri_slot_words64(cap); }
-int32_t tri_lds_max() { return TL_MAX; }
-
-void launch_count(const CountArgs& A, const unsigned long long* hc, hipStream_t s, hipEvent_t* ev) {
+template <int NV>
+void launch_count_t(const CountArgs& A, const unsigned long long* hc, hipStream_t s, hipEvent_t* ev) {
   const int64_t E = (int64_t)hc[C_ER];
+  constexpr int TLM = tl_max<NV>();
   if (ev) (void)hipEventRecord(ev[0], s);
   fill_u64(A.R.t, 0ull, E, s);
+  if (NV == 4) fill_u64(A.R.tp, 0ull, 2 * E, s);
   const int64_t nts = (int64_t)hc[C_LIST0 + L_TRI_S], ntl = (int64_t)hc[C_LIST0 + L_TRI_L];
-  if (nts) hipLaunchKernelGGL(k_tri_small, dim3(cap_grid((nts + 3) / 4, 8192)), dim3(256), 0, s, A);
+  if (nts) hipLaunchKernelGGL(k_tri_small<NV>, dim3(cap_grid((nts + 3) / 4, 8192)), dim3(256), 0, s, A);
   if (ntl) {
-    hipLaunchKernelGGL((k_tri_large<TL_MID, 256>), dim3(cap_grid(ntl, 4096)), dim3(256), 0, s, A, 64);
+    hipLaunchKernelGGL((k_tri_large<TL_MID, 256, NV>), dim3(cap_grid(ntl, 4096)), dim3(256), 0, s, A, 64);
     if ((int64_t)hc[C_MAXDP] > TL_MID)
-      hipLaunchKernelGGL((k_tri_large<TL_MAX, 512>), dim3(cap_grid(ntl, 1024)), dim3(512), 0, s, A, TL_MID);
-    if ((int64_t)hc[C_MAXDP] > TL_MAX)
-      hipLaunchKernelGGL((k_tri_large<0, 256>), dim3(cap_grid(ntl, (unsigned)A.tri_slots)), dim3(256), 0, s, A, TL_MAX);
+      hipLaunchKernelGGL((k_tri_large<TLM, 512, NV>), dim3(cap_grid(ntl, 1024)), dim3(512), 0, s, A, TL_MID);
+    if ((int64_t)hc[C_MAXDP] > TLM)
+      hipLaunchKernelGGL((k_tri_large<0, 256, NV>), dim3(cap_grid(ntl, (unsigned)A.tri_slots)), dim3(256), 0, s, A,
+                         TLM);
   }
   if (ev) (void)hipEventRecord(ev[1], s);
-  if (E) hipLaunchKernelGGL(k_edge_pass, dim3(cap_grid((E / EP_RUN + 255) / 256, 8192)), dim3(256), 0, s, A);
+  if (E) hipLaunchKernelGGL(k_edge_pass<NV>, dim3(cap_grid((E + 255) / 256, 16384)), dim3(256), 0, s, A);
   if (ev) (void)hipEventRecord(ev[2], s);
   const int64_t ncs = (int64_t)hc[C_LIST0 + L_C4_S], ncm = (int64_t)hc[C_LIST0 + L_C4_M],
                 ncl = (int64_t)hc[C_LIST0 + L_C4_L];
-  if (ncs) hipLaunchKernelGGL(k_c4_small, dim3(cap_grid((ncs + 3) / 4, 8192)), dim3(256), 0, s, A);
+  if (ncs) hipLaunchKernelGGL(k_c4_small<NV>, dim3(cap_grid((ncs + 3) / 4, 8192)), dim3(256), 0, s, A);
   if (ev) (void)hipEventRecord(ev[3], s);
-  if (ncm) hipLaunchKernelGGL(k_c4_mid, dim3(cap_grid(ncm, 4096)), dim3(256), 0, s, A);
+  if (ncm) hipLaunchKernelGGL(k_c4_mid<NV>, dim3(cap_grid(ncm, 4096)), dim3(256), 0, s, A);
   if (ev) (void)hipEventRecord(ev[4], s);
   if (ncl) {
     // order the hubs by decreasing wedge work (keys written by the per-vertex pass)
     unsigned long long* sk = radix_sort_u64(A.c4_keys, A.c4_keys_alt, A.sort_tmp, ncl, A.c + C_LIST0 + L_C4_L, 64, s);
     hipLaunchKernelGGL(k_c4_order, dim3(cap_grid((ncl + 255) / 256, 1024)), dim3(256), 0, s, sk, A.c,
                        (int32_t*)(A.lists + L_C4_L * A.list_stride));
-    hipLaunchKernelGGL(k_c4_large, dim3(cap_grid(ncl, (unsigned)A.slots)), dim3(C4W_T), 0, s, A,
+    hipLaunchKernelGGL(k_c4_large<NV>, dim3(cap_grid(ncl, (unsigned)A.slots)), dim3(C4W_T), 0, s, A,
                        (unsigned long long*)(A.c + C_QHEAD));
   }
   if (ev) (void)hipEventRecord(ev[5], s);
 }
 
-void launch_combine(const unsigned long long* sig, long long* state, int32_t k, hipStream_t s) {
-  hipLaunchKernelGGL(k_combine, dim3((k + 63) / 64), dim3(64), 0, s, sig, state, k);
+}  // namespace
+
+int32_t c4_window_max() { return C4W_WIN; }
+int64_t tri_scratch_words64(int nv, int64_t cap) {
+  return nv == 2 ? tri_slot_words64<2>(cap) : tri_slot_words64<4>(cap);
+}
+int32_t tri_lds_max(int nv) { return nv == 2 ? tl_max<2>() : tl_max<4>(); }
+
+void launch_count(int nv, const CountArgs& A, const unsigned long long* hc, hipStream_t s, hipEvent_t* ev) {
+  if (nv == 2) launch_count_t<2>(A, hc, s, ev);
+  else launch_count_t<4>(A, hc, s, ev);
+}
+
+void launch_combine(int nv, const unsigned long long* sig, long long* state, long long* vout, int32_t k,
+                    hipStream_t s) {
+  if (nv == 2) hipLaunchKernelGGL(k_combine<2>, dim3((k + 63) / 64), dim3(64), 0, s, sig, state, vout, k);
+  else hipLaunchKernelGGL(k_combine<4>, dim3((k + 63) / 64), dim3(64), 0, s, sig, state, vout, k);
 }

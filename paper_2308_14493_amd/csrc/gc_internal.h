@@ -9,23 +9,32 @@
 //
 // Rows live in an arena of uint32 entries with per-row slack:
 //   off[v] (int64), len[v] (int32), cap[v] (int32);  entry = id | flags
-// During a batch the arena holds the union view of the graph before (version
-// b) and after (version a) the batch; two flag bits mark the entries that
-// exist in one version only:
-//   F_NEW  (bit 30): inserted by the batch, absent from version b
-//   F_DEL  (bit 31): deleted by the batch, absent from version a
+// During a counting pass the arena holds the union view of the versions it
+// compares: G_0 (before) and G_1 (after) for one batch, or G_0 .. G_k for k
+// queued batches of one graph counted together.  Bit 28 + x of an entry is
+// set when its edge is absent from version x; between passes no bit is set.
 // A structure (edge, wedge, triangle, 4-clique) exists in version x iff none
-// of its entries carries x's absence bit, i.e. the OR of its entries' flags
-// decides both versions at once.
+// of its entries carries bit 28 + x, so the OR of its entries' flags decides
+// every version at once.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define GC_F_NEW 0x40000000u
-#define GC_F_DEL 0x80000000u
-#define GC_FLAGS 0xC0000000u
-#define GC_ID    0x3FFFFFFFu
-#define GC_MAX_VERTICES (1 << 30)
+#define GC_VSHIFT 28
+#define GC_F_NEW 0x10000000u   // absent from version 0 (inserted by the pass)
+#define GC_F_DEL 0x20000000u   // absent from version 1 (deleted, one-batch pass)
+#define GC_FLAGS 0xF0000000u
+#define GC_ID    0x0FFFFFFFu
+#define GC_MAX_VERTICES (1 << 28)
+#define GC_NV_MAX 4            // versions per pass
+#define GC_SEQ_MAX 3           // batches of one graph per pass (GC_NV_MAX - 1)
+
+// versions (bit x = version x) in which a structure whose entries' flags OR
+// to f exists
+template <int NV> __host__ __device__ __forceinline__ constexpr uint32_t vfull() { return (1u << NV) - 1u; }
+template <int NV> __host__ __device__ __forceinline__ uint32_t vpresent(uint32_t f) {
+  return ~(f >> GC_VSHIFT) & vfull<NV>();
+}
 
 // Sigma terms accumulated per graph and version (u64, two's complement):
 enum {
@@ -40,16 +49,18 @@ enum {
   SG_D1 = 8,   // sum_v d  (twice the edge count)
   SG_N = 9
 };
-// per graph: sig[g][version][term], version 0 = b (before), 1 = a (after)
-#define SIG_IDX(g, x, k) (((int64_t)(g) * 2 + (x)) * SG_N + (k))
+// per graph: sig[g][version][term]
+#define SIG_IDX(g, x, k) (((int64_t)(g) * GC_NV_MAX + (x)) * SG_N + (k))
 
 // Device state per graph (int64): F_conn[6], T, W, m, n, error count
 enum { ST_F0 = 0, ST_T = 6, ST_W = 7, ST_M = 8, ST_N = 9, ST_ERR = 10, ST_STRIDE = 16 };
 
-// Per-batch statistics written by kernels (u64 counters on the device).
+// Statistics written by kernels (u64 counters on the device): first a block
+// per batch of the pass (ingest), then the pass-wide counters.
+enum { PB_LOOPS = 0, PB_DUPS, PB_CANCEL, PB_INS_EXIST, PB_DEL_MISS, PB_EFF_INS, PB_EFF_DEL, PB_ERR, PB_N };
+#define PB_IDX(j, k) ((j) * PB_N + (k))
 enum {
-  BS_LOOPS = 0, BS_DUPS, BS_CANCEL, BS_INS_EXIST, BS_DEL_MISS, BS_EFF_INS, BS_EFF_DEL,
-  BS_TOUCHED, BS_REGION_V, BS_REGION_E, BS_ERR, BS_ARENA_OVF, BS_MAXDPLUS, BS_TRI_S,
+  BS_TOUCHED = GC_SEQ_MAX * PB_N, BS_REGION_V, BS_REGION_E, BS_ERR, BS_ARENA_OVF, BS_MAXDPLUS, BS_TRI_S,
   BS_TRI_L, BS_C4_S, BS_C4_M, BS_C4_L, BS_F1, BS_NR, BS_WEDGES, BS_TRIPROBE, BS_COUNT
 };
 
@@ -70,9 +81,14 @@ struct RegionDev {
   int64_t* roff;       // [N + 1]
   uint32_t* rcol;      // [E_R]
   int32_t* rlow;       // [N] entries with id < v (N-(v) is the row prefix)
-  int32_t* dB;         // [N] degree in version b inside the region
-  int32_t* dA;         // [N] degree in version a inside the region
-  unsigned long long* t;  // [E_R] per upper entry: t_b | t_a << 32
+  int32_t* rrow;       // [E_R] row (vertex) of every entry
+  int32_t* d;          // [N][NV] degree of v in version x inside the region: d[v * NV + x]
+  // triangles through the edge of each entry, per version.  Two versions:
+  // t[p] = t_0 | t_1 << 32.  Four versions: t_x = t[p] + field x of the
+  // 32-bit pairs tp[2p] (x = 0, 1) and tp[2p + 1] (x = 2, 3) (t[p] holds the
+  // triangles present in every version, tp the others)
+  unsigned long long* t;   // [E_R]
+  unsigned long long* tp;  // [2 E_R] (four versions only)
   int32_t* vpos;       // [E_R] per lower entry v -> w: position of v in row w
 };
 

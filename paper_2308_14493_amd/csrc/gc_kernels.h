@@ -4,9 +4,10 @@
 
 // device counters (u64) of one batch
 enum {
-  C_DIRA = 0,     // directed insert entries (2 per effective insertion)
-  C_DIRD,         // directed delete entries
-  C_TOUCH,        // rows touched by the batch
+  C_DIRA = 0,     // directed entries of pairs absent before the pass and present in a later version
+  C_DIRD,         // directed entries of existing edges absent from a later version
+  C_DIRR,         // directed entries absent from the last version (removed by the purge)
+  C_TOUCH,        // rows touched by the pass
   C_RLIST,        // region vertices
   C_LVL0,         // C_LVL0 + k: end of level-k vertices in the region list (k = 0..4)
   C_ER = C_LVL0 + 6,  // region entries
@@ -19,21 +20,31 @@ enum {
 };
 enum { L_TRI_S = 0, L_TRI_L, L_C4_S, L_C4_M, L_C4_L, L_NUM };
 
+// Directed entry keys of the merge lists: row << bits | col, with the
+// absence mask of the edge (bit x = absent from version x) in bits 60..63.
+#define DIR_MASK_SHIFT 60
+#define DIR_KEY_MASK ((1ull << DIR_MASK_SHIFT) - 1ull)
+
+// Segments of the update arrays: one per graph of a pool (seq = 0), or one
+// per successive batch of graph 0 (seq = 1).
 struct BatchIn {
   const int32_t* iu; const int32_t* iv; const int32_t* du; const int32_t* dv;
   int64_t n_ins, n_del;
-  const int64_t* ins_seg;  // [k+1] insertion segment per graph
+  const int64_t* ins_seg;  // [k+1] insertion segment bounds
   const int64_t* del_seg;  // [k+1]
-  const int64_t* gbase;    // [k] first vertex of each graph
-  const int64_t* gn;       // [k] vertex count of each graph
-  int32_t k;
+  const int64_t* gbase;    // [graphs] first vertex of each graph
+  const int64_t* gn;       // [graphs] vertex count of each graph
+  int32_t k;               // segments
+  int32_t seq;
 };
 
 struct BatchWork {
   unsigned long long* c;       // counters
-  unsigned long long* dirA;    // sorted directed insert entries (row << bits | col)
+  unsigned long long* dirA;    // sorted directed entry keys (see DIR_MASK_SHIFT)
   unsigned long long* dirD;
-  int32_t* a_beg; int32_t* na; int32_t* d_beg; int32_t* nd; int32_t* mark; int32_t* tix;  // [N]
+  unsigned long long* dirR;
+  // per row: segment of dirA (a_beg, na) and of dirR (r_beg, nr)
+  int32_t* a_beg; int32_t* na; int32_t* r_beg; int32_t* nr; int32_t* mark; int32_t* tix;  // [N]
   int32_t* touched;            // [max_touched]
   int64_t* dest; int32_t* newcap; int32_t* tlen; int64_t* tpre;  // [max_touched (+1)]
   uint32_t* scratch;           // copy of the touched rows
@@ -42,21 +53,25 @@ struct BatchWork {
 // graph.hip
 void launch_ingest_keys(const PoolDev& P, const BatchIn& B, int bits, unsigned long long* keys,
                         unsigned long long* bstats, hipStream_t s);
-void launch_ingest_classify(const PoolDev& P, const unsigned long long* keys, int64_t total, int bits,
-                            unsigned long long* dirA, unsigned long long* dirD, unsigned long long* c,
-                            unsigned long long* bstats, hipStream_t s);
+// keys: pair << 3 | batch << 1 | op; nb batches in the pass, nv versions
+void launch_ingest_classify(const PoolDev& P, const unsigned long long* keys, int64_t total, int bits, int nb, int nv,
+                            unsigned long long* dirA, unsigned long long* dirD, unsigned long long* dirR,
+                            unsigned long long* c, unsigned long long* bstats, hipStream_t s);
+// beg/cnt may be null (rows are then only marked as touched)
 void launch_mark_rows(const unsigned long long* dir, int64_t max_n, unsigned long long* c, int which, int bits,
                       int32_t* beg, int32_t* cnt, int32_t* mark, int32_t* touched, int32_t* tix, hipStream_t s);
 void launch_merge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int64_t max_dirA, int bits, float slack,
                   unsigned long long* bstats, void* scan_tmp, hipStream_t s);
-void launch_flag_del(const PoolDev& P, const BatchWork& W, int64_t max_dirD, int bits, unsigned long long* bstats,
-                     hipStream_t s);
-void launch_purge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int bits, void* scan_tmp, hipStream_t s);
+void launch_flag_rows(const PoolDev& P, const BatchWork& W, int64_t max_dirD, int bits, unsigned long long* bstats,
+                      hipStream_t s);
+// removes the entries carrying `fin` (absent from the last version), clears all flags
+void launch_purge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int bits, uint32_t fin, void* scan_tmp,
+                  hipStream_t s);
 void launch_region(const PoolDev& P, const BatchWork& W, int radius, int32_t* level, int32_t* rlist, int32_t* rlen,
                    hipStream_t s);
 void launch_region_fill(const PoolDev& P, const RegionDev& R, const BatchWork& W, int radius, const int32_t* level,
                         const int32_t* rlist, const int32_t* rlen, void* scan_tmp, hipStream_t s);
-void launch_degrees(const RegionDev& R, const int32_t* gid, const int32_t* rlist, unsigned long long* c,
+void launch_degrees(int nv, const RegionDev& R, const int32_t* gid, const int32_t* rlist, unsigned long long* c,
                     unsigned long long* sig, int32_t* lists, int64_t list_stride, int32_t tri_small, int32_t c4_small,
                     int32_t c4_mid, unsigned long long* bstats, unsigned long long* c4_keys, hipStream_t s);
 void launch_init_keys(const int32_t* src, const int32_t* dst, int64_t m, const int64_t* seg, const int64_t* gbase,
@@ -87,7 +102,7 @@ struct CountArgs {
   unsigned long long* sig;
   unsigned long long* bstats;
   // per-slot scratch of the large tiers
-  unsigned long long* c4_dense;   // [slots][N]
+  unsigned long long* c4_dense;   // [slots][N] (two versions, or four with 16-bit fields)
   int32_t* c4_touch;              // [slots][N]
   int64_t N;
   int32_t slots;                  // workgroups of the large 4-cycle tier
@@ -103,12 +118,16 @@ struct CountArgs {
   unsigned long long* tri_scratch;  // [tri_slots][tri_scratch_words64(tri_cap)] above the LDS tier
   int64_t tri_cap;                  // out-degree capacity of a scratch slot
 };
-void launch_count(const CountArgs& A, const unsigned long long* host_counts, hipStream_t s,
+// nv = 2 or 4 versions
+void launch_count(int nv, const CountArgs& A, const unsigned long long* host_counts, hipStream_t s,
                   hipEvent_t* ev /* nullable: 6 events between the kernel phases */);
-int64_t tri_scratch_words64(int64_t cap);  // u64 words of one triangle scratch slot
-int32_t tri_lds_max();
-int32_t c4_window_max();                      // largest out-degree of the LDS triangle tier
-void launch_combine(const unsigned long long* sig, long long* state, int32_t k, hipStream_t s);
+int64_t tri_scratch_words64(int nv, int64_t cap);  // u64 words of one triangle scratch slot
+int32_t tri_lds_max(int nv);                        // largest out-degree of the LDS triangle tiers
+int32_t c4_window_max();                            // u64 words of the LDS window of the large 4-cycle tier
+// Per graph g: the state after version x (x = 1 .. nv-1) goes to
+// vout[((x - 1) * k + g) * ST_STRIDE ...]; state becomes the one of version nv-1.
+void launch_combine(int nv, const unsigned long long* sig, long long* state, long long* vout, int32_t k,
+                    hipStream_t s);
 
 // capi.cpp: thread-local error text read by gc_last_error()
 void gc_set_error(const char* msg);

@@ -5,7 +5,9 @@
 // Batch semantics (the stream model of Sec. 3 and the batch protocol of
 // Sec. 5): pairs are unordered, self loops are not edges, repeats collapse,
 // a pair both inserted and deleted by one batch is dropped, and only the
-// effective part A' = A - E, D' = D & E changes the graph.
+// effective part A' = A - E, D' = D & E changes the graph.  Several batches
+// of one graph may share a pass: they act in order, each on the graph left by
+// the previous one, and every version in between is kept (entry flags).
 #include "gc_kernels.h"
 
 namespace {
@@ -38,64 +40,83 @@ __global__ void k_ingest_keys(PoolDev P, BatchIn B, int bits, unsigned long long
     const int64_t j = del ? i - B.n_ins : i;
     int32_t u = del ? B.du[j] : B.iu[j];
     int32_t v = del ? B.dv[j] : B.iv[j];
-    // graph segment of this entry
+    // segment of this entry: a graph of the pool, or a batch of graph 0
     const int64_t* seg = del ? B.del_seg : B.ins_seg;
     int lo = 0, hi = B.k;
     while (hi - lo > 1) { int mid = (lo + hi) >> 1; if (seg[mid] <= j) lo = mid; else hi = mid; }
-    const int64_t base = B.gbase[lo], n = B.gn[lo];
+    const int g = B.seq ? 0 : lo, bj = B.seq ? lo : 0;
+    const int64_t base = B.gbase[g], n = B.gn[g];
     if (u < 0 || v < 0 || u >= n || v >= n) {
-      atomicAdd(&bstats[BS_ERR], 1ull);
+      atomicAdd(&bstats[PB_IDX(bj, PB_ERR)], 1ull);
       keys[i] = ~0ull;
       continue;
     }
     if (u == v) {
-      atomicAdd(&bstats[BS_LOOPS], 1ull);
+      atomicAdd(&bstats[PB_IDX(bj, PB_LOOPS)], 1ull);
       keys[i] = ~0ull;
       continue;
     }
     uint64_t a = (uint64_t)(uint32_t)P.ext2int[base + u];
     uint64_t b = (uint64_t)(uint32_t)P.ext2int[base + v];
     uint64_t mn = a < b ? a : b, mx = a < b ? b : a;
-    keys[i] = (((mn << bits) | (mx & idmask)) << 1) | (del ? 1ull : 0ull);
+    keys[i] = (((mn << bits) | (mx & idmask)) << 3) | ((uint64_t)bj << 1) | (del ? 1ull : 0ull);
   }
 }
 
-// After sorting: one decision per distinct pair (at its first key).
+// After sorting: one decision per distinct pair, at its first key.  The
+// batches of the pass act on the pair in order, each by the rules above on
+// the graph the previous one left.  Bit x of the absence mask says that the
+// pair is not an edge of version x (x = 0 before the pass, x = j + 1 after
+// batch j; versions past the last batch repeat the last one).  Pairs whose
+// mask is neither empty nor full change: existing edges go to dirD (flags),
+// the others to dirA (new entries), and those absent from the last version
+// also to dirR (removed by the purge).
 __global__ void k_ingest_classify(PoolDev P, const unsigned long long* __restrict__ keys, int64_t total, int bits,
-                                  unsigned long long* __restrict__ dirA, unsigned long long* __restrict__ dirD,
+                                  int nb, int nv, unsigned long long* __restrict__ dirA,
+                                  unsigned long long* __restrict__ dirD, unsigned long long* __restrict__ dirR,
                                   unsigned long long* __restrict__ c, unsigned long long* __restrict__ bstats) {
   const uint64_t idmask = (1ull << bits) - 1ull;
   for (int64_t i = gtid(); i < total; i += gstride()) {
     const unsigned long long key = keys[i];
     if (key == ~0ull) continue;
-    const unsigned long long pair = key >> 1;
-    const int op = (int)(key & 1ull);
-    const unsigned long long prev = i > 0 ? keys[i - 1] : ~0ull;
-    if (prev == key) { atomicAdd(&bstats[BS_DUPS], 1ull); continue; }
-    if (i > 0 && (prev >> 1) == pair) continue;  // deletion key of a pair already seen as insertion
-    bool has_ins = op == 0, has_del = op == 1;
-    if (has_ins) {
-      // look for the deletion key of the same pair further on
-      const unsigned long long want = (pair << 1) | 1ull;
-      int64_t lo = i + 1, hi = total;
-      while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (keys[mid] < want) lo = mid + 1; else hi = mid; }
-      has_del = lo < total && keys[lo] == want;
+    const unsigned long long pair = key >> 3;
+    if (i > 0 && (keys[i - 1] >> 3) == pair) continue;
+    uint32_t ins = 0, del = 0;  // bit j: batch j inserts / deletes the pair
+    for (int64_t q = i; q < total && (keys[q] >> 3) == pair; ++q) {
+      const int j = (int)((keys[q] >> 1) & 3ull);
+      if (q > i && keys[q] == keys[q - 1]) { atomicAdd(&bstats[PB_IDX(j, PB_DUPS)], 1ull); continue; }
+      if (keys[q] & 1ull) del |= 1u << j; else ins |= 1u << j;
     }
-    if (has_ins && has_del) { atomicAdd(&bstats[BS_CANCEL], 1ull); continue; }
     const uint32_t a = (uint32_t)(pair >> bits), b = (uint32_t)(pair & idmask);
-    const bool ex = edge_exists(P, a, b);
-    if (has_ins) {
-      if (ex) { atomicAdd(&bstats[BS_INS_EXIST], 1ull); continue; }
-      unsigned long long p = atomicAdd(&c[C_DIRA], 2ull);
-      dirA[p] = ((unsigned long long)a << bits) | b;
-      dirA[p + 1] = ((unsigned long long)b << bits) | a;
-      atomicAdd(&bstats[BS_EFF_INS], 1ull);
-    } else {
-      if (!ex) { atomicAdd(&bstats[BS_DEL_MISS], 1ull); continue; }
-      unsigned long long p = atomicAdd(&c[C_DIRD], 2ull);
-      dirD[p] = ((unsigned long long)a << bits) | b;
-      dirD[p + 1] = ((unsigned long long)b << bits) | a;
-      atomicAdd(&bstats[BS_EFF_DEL], 1ull);
+    const bool p0 = edge_exists(P, a, b);
+    bool p = p0;
+    uint32_t am = p ? 0u : 1u;
+    for (int j = 0; j < nb; ++j) {
+      const bool in = (ins >> j) & 1u, de = (del >> j) & 1u;
+      if (in && de) {
+        atomicAdd(&bstats[PB_IDX(j, PB_CANCEL)], 1ull);
+      } else if (in) {
+        if (p) atomicAdd(&bstats[PB_IDX(j, PB_INS_EXIST)], 1ull);
+        else { p = true; atomicAdd(&bstats[PB_IDX(j, PB_EFF_INS)], 1ull); }
+      } else if (de) {
+        if (!p) atomicAdd(&bstats[PB_IDX(j, PB_DEL_MISS)], 1ull);
+        else { p = false; atomicAdd(&bstats[PB_IDX(j, PB_EFF_DEL)], 1ull); }
+      }
+      if (!p) am |= 1u << (j + 1);
+    }
+    if (!p)
+      for (int x = nb + 1; x < nv; ++x) am |= 1u << x;
+    if (am == 0u || am == (1u << nv) - 1u) continue;
+    const unsigned long long ab = ((unsigned long long)a << bits) | b, ba = ((unsigned long long)b << bits) | a;
+    const unsigned long long mk = (unsigned long long)am << DIR_MASK_SHIFT;
+    unsigned long long* out = p0 ? dirD : dirA;
+    const unsigned long long q = atomicAdd(&c[p0 ? C_DIRD : C_DIRA], 2ull);
+    out[q] = ab | mk;
+    out[q + 1] = ba | mk;
+    if (!p) {
+      const unsigned long long r = atomicAdd(&c[C_DIRR], 2ull);
+      dirR[r] = ab;
+      dirR[r + 1] = ba;
     }
   }
 }
@@ -107,15 +128,19 @@ __global__ void k_mark_rows(const unsigned long long* __restrict__ dir, const un
                             int32_t* __restrict__ tix, unsigned long long* __restrict__ cc) {
   const int64_t n = ctr(c, which);
   for (int64_t i = gtid(); i < n; i += gstride()) {
-    const uint32_t row = (uint32_t)(dir[i] >> bits);
-    if (i > 0 && (uint32_t)(dir[i - 1] >> bits) == row) continue;
-    const unsigned long long nxt = (unsigned long long)(row + 1) << bits;
-    int64_t lo = i + 1, hi = n;
-    while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (dir[mid] < nxt) lo = mid + 1; else hi = mid; }
-    beg[row] = (int32_t)i;
-    cnt[row] = (int32_t)(lo - i);
-    const int bit = which == C_DIRA ? 1 : 2;
-    if (atomicOr(&mark[row], bit) == 0) {
+    const uint32_t row = (uint32_t)((dir[i] & DIR_KEY_MASK) >> bits);
+    if (i > 0 && (uint32_t)((dir[i - 1] & DIR_KEY_MASK) >> bits) == row) continue;
+    if (beg) {
+      const unsigned long long nxt = (unsigned long long)(row + 1) << bits;
+      int64_t lo = i + 1, hi = n;
+      while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if ((dir[mid] & DIR_KEY_MASK) < nxt) lo = mid + 1; else hi = mid;
+      }
+      beg[row] = (int32_t)i;
+      cnt[row] = (int32_t)(lo - i);
+    }
+    if (atomicOr(&mark[row], 1) == 0) {
       unsigned long long p = atomicAdd(&cc[C_TOUCH], 1ull);
       touched[p] = (int32_t)row;
       tix[row] = (int32_t)p;
@@ -167,7 +192,8 @@ __global__ void k_copy_rows(PoolDev P, const int32_t* __restrict__ touched, cons
 }
 
 // Merge: old entries shift right by the insertions before them; insertions
-// land after the old entries before them.  Inserted entries carry F_NEW.
+// land after the old entries before them.  Inserted entries carry their
+// absence mask (at least F_NEW: absent before the pass).
 __global__ void k_merge_old(PoolDev P, const int32_t* __restrict__ touched, const unsigned long long* c,
                             const int64_t* __restrict__ tpre, const uint32_t* __restrict__ scratch,
                             const unsigned long long* __restrict__ dirA, int bits,
@@ -199,15 +225,16 @@ __global__ void k_merge_new(PoolDev P, const unsigned long long* c, const unsign
   const int64_t n = ctr(c, C_DIRA);
   const uint64_t idmask = (1ull << bits) - 1ull;
   for (int64_t j = gtid(); j < n; j += gstride()) {
-    const uint32_t r = (uint32_t)(dirA[j] >> bits);
+    const uint32_t r = (uint32_t)((dirA[j] & DIR_KEY_MASK) >> bits);
     const uint32_t id = (uint32_t)(dirA[j] & idmask);
+    const uint32_t fl = (uint32_t)(dirA[j] >> DIR_MASK_SHIFT) << GC_VSHIFT;
     const int32_t t = tix[r];
     if (dest[t] < 0) continue;
     const int32_t q = (int32_t)(j - a_beg[r]);
     const uint32_t* old = scratch + tpre[t];
     const int32_t L = (int32_t)(tpre[t + 1] - tpre[t]);
     int32_t p = lower_bound_id(old, L, id);
-    P.col[dest[t] + q + p] = id | GC_F_NEW;
+    P.col[dest[t] + q + p] = id | fl;
   }
 }
 
@@ -224,23 +251,26 @@ __global__ void k_commit_rows(PoolDev P, const int32_t* __restrict__ touched, co
   }
 }
 
-__global__ void k_flag_del(PoolDev P, const unsigned long long* c, const unsigned long long* __restrict__ dirD,
-                           int bits, unsigned long long* __restrict__ bstats) {
+// existing edges that change: their entries take the absence mask
+__global__ void k_flag_rows(PoolDev P, const unsigned long long* c, const unsigned long long* __restrict__ dirD,
+                            int bits, unsigned long long* __restrict__ bstats) {
   const int64_t n = ctr(c, C_DIRD);
   const uint64_t idmask = (1ull << bits) - 1ull;
   for (int64_t j = gtid(); j < n; j += gstride()) {
-    const uint32_t r = (uint32_t)(dirD[j] >> bits);
+    const uint32_t r = (uint32_t)((dirD[j] & DIR_KEY_MASK) >> bits);
     const uint32_t id = (uint32_t)(dirD[j] & idmask);
+    const uint32_t fl = (uint32_t)(dirD[j] >> DIR_MASK_SHIFT) << GC_VSHIFT;
     uint32_t* row = P.col + P.off[r];
     int32_t p = lower_bound_id(row, P.len[r], id);
-    if (p < P.len[r] && (row[p] & GC_ID) == id) row[p] |= GC_F_DEL;
+    if (p < P.len[r] && (row[p] & GC_ID) == id) row[p] |= fl;
     else atomicAdd(&bstats[BS_ERR], 1ull);
   }
 }
 
 // ------------------------------------------------------------- purge
-// Remove F_DEL entries and clear F_NEW in the touched rows (from a scratch
-// copy of the union rows); reset the per-row batch arrays.
+// Remove the entries absent from the last version and clear every flag in
+// the touched rows (from a scratch copy of the union rows); reset the per-row
+// batch arrays.
 __global__ void k_touched_len(PoolDev P, const int32_t* __restrict__ touched, const unsigned long long* c,
                               int64_t max_touched, int32_t* __restrict__ tlen) {
   const int64_t nt = ctr(c, C_TOUCH);
@@ -249,8 +279,8 @@ __global__ void k_touched_len(PoolDev P, const int32_t* __restrict__ touched, co
 
 __global__ void k_purge_rows(PoolDev P, const int32_t* __restrict__ touched, const unsigned long long* c,
                              const int64_t* __restrict__ tpre, const uint32_t* __restrict__ scratch,
-                             const unsigned long long* __restrict__ dirD, int bits,
-                             const int32_t* __restrict__ d_beg, const int32_t* __restrict__ nd) {
+                             const unsigned long long* __restrict__ dirR, int bits, uint32_t fin,
+                             const int32_t* __restrict__ r_beg, const int32_t* __restrict__ nr) {
   const int64_t nt = ctr(c, C_TOUCH);
   if (nt == 0) return;
   const int64_t total = tpre[nt];
@@ -259,12 +289,12 @@ __global__ void k_purge_rows(PoolDev P, const int32_t* __restrict__ touched, con
     const int64_t t = upper_bound_i64(tpre, nt, i);
     const int32_t r = touched[t];
     const uint32_t x = scratch[i];
-    if (x & GC_F_DEL) continue;
+    if (x & fin) continue;
     const int64_t k = i - tpre[t];
-    const int32_t cntD = nd[r];
+    const int32_t cntD = nr[r];
     int32_t lo = 0;
     if (cntD) {
-      const unsigned long long* D = dirD + d_beg[r];
+      const unsigned long long* D = dirR + r_beg[r];
       const uint32_t id = x & GC_ID;
       int32_t hi = cntD;
       while (lo < hi) { int32_t mid = (lo + hi) >> 1; if ((uint32_t)(D[mid] & idmask) < id) lo = mid + 1; else hi = mid; }
@@ -274,13 +304,13 @@ __global__ void k_purge_rows(PoolDev P, const int32_t* __restrict__ touched, con
 }
 
 __global__ void k_purge_commit(PoolDev P, const int32_t* __restrict__ touched, const unsigned long long* c,
-                               int32_t* __restrict__ a_beg, int32_t* __restrict__ na, int32_t* __restrict__ d_beg,
-                               int32_t* __restrict__ nd, int32_t* __restrict__ mark, int32_t* __restrict__ tix) {
+                               int32_t* __restrict__ a_beg, int32_t* __restrict__ na, int32_t* __restrict__ r_beg,
+                               int32_t* __restrict__ nr, int32_t* __restrict__ mark, int32_t* __restrict__ tix) {
   const int64_t nt = ctr(c, C_TOUCH);
   for (int64_t i = gtid(); i < nt; i += gstride()) {
     const int32_t r = touched[i];
-    P.len[r] -= nd[r];
-    a_beg[r] = 0; na[r] = 0; d_beg[r] = 0; nd[r] = 0; mark[r] = 0; tix[r] = 0;
+    P.len[r] -= nr[r];
+    a_beg[r] = 0; na[r] = 0; r_beg[r] = 0; nr[r] = 0; mark[r] = 0; tix[r] = 0;
   }
 }
 
@@ -358,8 +388,9 @@ __global__ void k_region_fill(PoolDev P, RegionDev R, const int32_t* __restrict_
     const int32_t L = P.len[v];
     const uint32_t* row = P.col + P.off[v];
     uint32_t* out = R.rcol + R.roff[v];
+    int32_t* orow = R.rrow + R.roff[v];
     if (radius < 0 || level[v] < radius) {
-      for (int32_t k = lane_id(); k < L; k += 64) out[k] = row[k];
+      for (int32_t k = lane_id(); k < L; k += 64) { out[k] = row[k]; orow[k] = v; }
       continue;
     }
     int32_t base = 0;
@@ -369,7 +400,11 @@ __global__ void k_region_fill(PoolDev P, RegionDev R, const int32_t* __restrict_
       bool keep = false;
       if (k < L) { x = row[k]; keep = level[x & GC_ID] <= radius; }
       const uint64_t m = __ballot(keep);
-      if (keep) out[base + __popcll(m & lanemask_lt())] = x;
+      if (keep) {
+        const int32_t o = base + __popcll(m & lanemask_lt());
+        out[o] = x;
+        orow[o] = v;
+      }
       base += __popcll(m);
     }
   }
@@ -377,6 +412,19 @@ __global__ void k_region_fill(PoolDev P, RegionDev R, const int32_t* __restrict_
 
 // Per-vertex pass over the region: degrees per version, N- split, the
 // 3-star and wedge terms, and the work lists of the counting kernels.
+template <int NV>
+__device__ __forceinline__ void flush_vertex_terms(unsigned long long* sig, int g, int64_t (&s1)[NV],
+                                                   int64_t (&w2)[NV], int64_t (&d1)[NV]) {
+#pragma unroll
+  for (int x = 0; x < NV; ++x) {
+    if (s1[x]) atomicAdd(&sig[SIG_IDX(g, x, SG_S1)], (unsigned long long)s1[x]);
+    if (w2[x]) atomicAdd(&sig[SIG_IDX(g, x, SG_W)], (unsigned long long)w2[x]);
+    if (d1[x]) atomicAdd(&sig[SIG_IDX(g, x, SG_D1)], (unsigned long long)d1[x]);
+    s1[x] = 0; w2[x] = 0; d1[x] = 0;
+  }
+}
+
+template <int NV>
 __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const int32_t* __restrict__ rlist,
                           unsigned long long* __restrict__ cc, unsigned long long* __restrict__ sig,
                           int32_t* __restrict__ lists, int64_t list_stride, int32_t tri_small, int32_t c4_small,
@@ -385,7 +433,10 @@ __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const in
   const int64_t n = ctr(cc, C_RLIST);
   int cur_g = -1;
   int32_t maxlow = 0;
-  int64_t s1b = 0, s1a = 0, wb = 0, wa = 0, d1b = 0, d1a = 0, wedges = 0;
+  int64_t s1[NV], w2[NV], d1[NV];
+#pragma unroll
+  for (int x = 0; x < NV; ++x) { s1[x] = 0; w2[x] = 0; d1[x] = 0; }
+  int64_t wedges = 0;
   int32_t maxdp = 0;
   int64_t maxw = 0;
   for (int64_t i = gwave(); i < n; i += gwaves()) {
@@ -393,12 +444,16 @@ __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const in
     const int64_t b = R.roff[v];
     const int32_t L = (int32_t)(R.roff[v + 1] - b);
     const uint32_t* row = R.rcol + b;
-    int32_t db = 0, da = 0, low = 0;
+    int32_t dv[NV];
+#pragma unroll
+    for (int x = 0; x < NV; ++x) dv[x] = 0;
+    int32_t low = 0;
     int64_t wsum = 0;
     for (int32_t k = lane_id(); k < L; k += 64) {
       const uint32_t x = row[k];
-      db += !(x & GC_F_NEW);
-      da += !(x & GC_F_DEL);
+      const uint32_t pm = vpresent<NV>(x);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) dv[q] += (pm >> q) & 1u;
       const uint32_t w = x & GC_ID;
       if (w < (uint32_t)v) {
         // wedges (v, w, .) below v: entries of row w smaller than v (kept
@@ -410,23 +465,24 @@ __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const in
         wsum += pos;
       }
     }
-    db = wave_sum32(db); da = wave_sum32(da); low = wave_sum32(low);
+#pragma unroll
+    for (int x = 0; x < NV; ++x) dv[x] = wave_sum32(dv[x]);
+    low = wave_sum32(low);
     wsum = wave_sum64(wsum);
     if (lane_id() == 0) {
-      R.dB[v] = db; R.dA[v] = da; R.rlow[v] = low;
+      if constexpr (NV == 2) {
+        *(int2*)(R.d + (int64_t)v * 2) = make_int2(dv[0], dv[1]);
+      } else {
+        *(int4*)(R.d + (int64_t)v * 4) = make_int4(dv[0], dv[1], dv[2], dv[3]);
+      }
+      R.rlow[v] = low;
       const int g = gid[v];
       if (g != cur_g) {
-        if (cur_g >= 0) {
-          atomicAdd(&sig[SIG_IDX(cur_g, 0, SG_S1)], (unsigned long long)s1b);
-          atomicAdd(&sig[SIG_IDX(cur_g, 1, SG_S1)], (unsigned long long)s1a);
-          atomicAdd(&sig[SIG_IDX(cur_g, 0, SG_W)], (unsigned long long)wb);
-          atomicAdd(&sig[SIG_IDX(cur_g, 1, SG_W)], (unsigned long long)wa);
-          atomicAdd(&sig[SIG_IDX(cur_g, 0, SG_D1)], (unsigned long long)d1b);
-          atomicAdd(&sig[SIG_IDX(cur_g, 1, SG_D1)], (unsigned long long)d1a);
-        }
-        cur_g = g; s1b = s1a = wb = wa = d1b = d1a = 0;
+        if (cur_g >= 0) flush_vertex_terms<NV>(sig, cur_g, s1, w2, d1);
+        cur_g = g;
       }
-      s1b += c3(db); s1a += c3(da); wb += c2(db); wa += c2(da); d1b += db; d1a += da;
+#pragma unroll
+      for (int x = 0; x < NV; ++x) { s1[x] += c3(dv[x]); w2[x] += c2(dv[x]); d1[x] += dv[x]; }
       const int32_t dplus = L - low;
       if (dplus >= 2) {
         const int which = dplus <= tri_small ? L_TRI_S : L_TRI_L;
@@ -450,14 +506,7 @@ __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const in
     }
   }
   if (lane_id() == 0) {
-    if (cur_g >= 0) {
-      atomicAdd(&sig[SIG_IDX(cur_g, 0, SG_S1)], (unsigned long long)s1b);
-      atomicAdd(&sig[SIG_IDX(cur_g, 1, SG_S1)], (unsigned long long)s1a);
-      atomicAdd(&sig[SIG_IDX(cur_g, 0, SG_W)], (unsigned long long)wb);
-      atomicAdd(&sig[SIG_IDX(cur_g, 1, SG_W)], (unsigned long long)wa);
-      atomicAdd(&sig[SIG_IDX(cur_g, 0, SG_D1)], (unsigned long long)d1b);
-      atomicAdd(&sig[SIG_IDX(cur_g, 1, SG_D1)], (unsigned long long)d1a);
-    }
+    if (cur_g >= 0) flush_vertex_terms<NV>(sig, cur_g, s1, w2, d1);
     if (maxdp) atomicMax(&cc[C_MAXDP], (unsigned long long)maxdp);
     if (maxw) atomicMax(&cc[C_MAXW], (unsigned long long)maxw);
     if (maxlow) atomicMax(&cc[C_MAXLOW], (unsigned long long)maxlow);
@@ -633,12 +682,12 @@ void launch_ingest_keys(const PoolDev& P, const BatchIn& B, int bits, unsigned l
   hipLaunchKernelGGL(k_ingest_keys, dim3(grid_for(n)), dim3(TPB), 0, s, P, B, bits, keys, bstats);
 }
 
-void launch_ingest_classify(const PoolDev& P, const unsigned long long* keys, int64_t total, int bits,
-                            unsigned long long* dirA, unsigned long long* dirD, unsigned long long* c,
-                            unsigned long long* bstats, hipStream_t s) {
+void launch_ingest_classify(const PoolDev& P, const unsigned long long* keys, int64_t total, int bits, int nb, int nv,
+                            unsigned long long* dirA, unsigned long long* dirD, unsigned long long* dirR,
+                            unsigned long long* c, unsigned long long* bstats, hipStream_t s) {
   if (total == 0) return;
-  hipLaunchKernelGGL(k_ingest_classify, dim3(grid_for(total)), dim3(TPB), 0, s, P, keys, total, bits, dirA, dirD, c,
-                     bstats);
+  hipLaunchKernelGGL(k_ingest_classify, dim3(grid_for(total)), dim3(TPB), 0, s, P, keys, total, bits, nb, nv, dirA,
+                     dirD, dirR, c, bstats);
 }
 
 void launch_mark_rows(const unsigned long long* dir, int64_t max_n, unsigned long long* c, int which, int bits,
@@ -665,23 +714,24 @@ void launch_merge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int
                      W.newcap);
 }
 
-void launch_flag_del(const PoolDev& P, const BatchWork& W, int64_t max_dirD, int bits, unsigned long long* bstats,
-                     hipStream_t s) {
+void launch_flag_rows(const PoolDev& P, const BatchWork& W, int64_t max_dirD, int bits, unsigned long long* bstats,
+                      hipStream_t s) {
   if (max_dirD == 0) return;
-  hipLaunchKernelGGL(k_flag_del, dim3(grid_for(max_dirD)), dim3(TPB), 0, s, P, W.c, W.dirD, bits, bstats);
+  hipLaunchKernelGGL(k_flag_rows, dim3(grid_for(max_dirD)), dim3(TPB), 0, s, P, W.c, W.dirD, bits, bstats);
 }
 
-void launch_purge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int bits, void* scan_tmp, hipStream_t s) {
+void launch_purge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int bits, uint32_t fin, void* scan_tmp,
+                  hipStream_t s) {
   if (max_touched == 0) return;
   // lengths of the union rows, then a copy, then the compaction
   hipLaunchKernelGGL(k_touched_len, dim3(grid_for(max_touched)), dim3(TPB), 0, s, P, W.touched, W.c, max_touched,
                      W.tlen);
   exclusive_scan_i32_to_i64(W.tlen, W.tpre, max_touched, scan_tmp, s);
   hipLaunchKernelGGL(k_copy_rows, dim3(4096), dim3(TPB), 0, s, P, W.touched, W.c, W.tpre, W.scratch);
-  hipLaunchKernelGGL(k_purge_rows, dim3(4096), dim3(TPB), 0, s, P, W.touched, W.c, W.tpre, W.scratch, W.dirD, bits,
-                     W.d_beg, W.nd);
+  hipLaunchKernelGGL(k_purge_rows, dim3(4096), dim3(TPB), 0, s, P, W.touched, W.c, W.tpre, W.scratch, W.dirR, bits,
+                     fin, W.r_beg, W.nr);
   hipLaunchKernelGGL(k_purge_commit, dim3(grid_for(max_touched)), dim3(TPB), 0, s, P, W.touched, W.c, W.a_beg, W.na,
-                     W.d_beg, W.nd, W.mark, W.tix);
+                     W.r_beg, W.nr, W.mark, W.tix);
 }
 
 void launch_region(const PoolDev& P, const BatchWork& W, int radius, int32_t* level, int32_t* rlist, int32_t* rlen,
@@ -709,11 +759,15 @@ void launch_region_fill(const PoolDev& P, const RegionDev& R, const BatchWork& W
   hipLaunchKernelGGL(k_region_fill, dim3(4096), dim3(TPB), 0, s, P, R, rlist, W.c, level, radius);
 }
 
-void launch_degrees(const RegionDev& R, const int32_t* gid, const int32_t* rlist, unsigned long long* c,
+void launch_degrees(int nv, const RegionDev& R, const int32_t* gid, const int32_t* rlist, unsigned long long* c,
                     unsigned long long* sig, int32_t* lists, int64_t list_stride, int32_t tri_small, int32_t c4_small,
                     int32_t c4_mid, unsigned long long* bstats, unsigned long long* c4_keys, hipStream_t s) {
-  hipLaunchKernelGGL(k_degrees, dim3(4096), dim3(TPB), 0, s, R, gid, rlist, c, sig, lists, list_stride, tri_small,
-                     c4_small, c4_mid, bstats, c4_keys);
+  if (nv == 2)
+    hipLaunchKernelGGL(k_degrees<2>, dim3(4096), dim3(TPB), 0, s, R, gid, rlist, c, sig, lists, list_stride,
+                       tri_small, c4_small, c4_mid, bstats, c4_keys);
+  else
+    hipLaunchKernelGGL(k_degrees<4>, dim3(4096), dim3(TPB), 0, s, R, gid, rlist, c, sig, lists, list_stride,
+                       tri_small, c4_small, c4_mid, bstats, c4_keys);
 }
 
 // ---------------------------------------------------------------- build

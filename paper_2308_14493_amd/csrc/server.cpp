@@ -3,9 +3,11 @@
 // tickets.  Requests for different graphs run at the same time on their own
 // streams (their kernels overlap on the device); requests for one graph are
 // applied in submission order (each result is the counts after that batch).
-// Admission by memory: a graph is admitted only if its estimated footprint
-// fits the free HBM (minus a reserve); a batch starts only while the bytes
-// of the batches in flight stay within the budget.
+// Continuous batching: a worker that becomes free takes every queued batch
+// of its graph, up to three, into one counting pass that keeps each
+// intermediate version.  Admission by memory: a graph is admitted only if its
+// estimated footprint fits the free HBM (minus a reserve); batches start only
+// while the bytes of the batches in flight stay within the budget.
 #include "../../include/graphlet4.h"
 #include "gc_kernels.h"
 
@@ -41,6 +43,7 @@ struct Request {
 
 struct Slot {
   gc_graph* g = nullptr;
+  int64_t n = 0;
   int64_t footprint = 0;
   std::deque<std::shared_ptr<Request>> q;
   std::condition_variable cv;
@@ -52,6 +55,14 @@ int fail(int code, const char* msg) {
   gc_set_error(msg);
   return code;
 }
+
+bool ids_ok(const std::vector<int32_t>& a, int64_t n) {
+  for (int32_t x : a)
+    if (x < 0 || x >= n) return false;
+  return true;
+}
+
+constexpr int kPassMax = 3;  // batches per counting pass
 
 }  // namespace
 
@@ -76,27 +87,63 @@ struct gc_server {
   void worker(Slot* sl) {
     (void)hipSetDevice(opts.device);
     while (true) {
-      std::shared_ptr<Request> r;
+      std::vector<std::shared_ptr<Request>> grp;
       {
         std::unique_lock<std::mutex> lk(mu);
         sl->cv.wait(lk, [&] { return sl->stop || !sl->q.empty(); });
         if (sl->q.empty()) return;
-        r = sl->q.front();
+        std::shared_ptr<Request> r = sl->q.front();
         sl->q.pop_front();
         // memory admission of the batch (the first one always runs)
         cv_mem.wait(lk, [&] { return inflight == 0 || inflight + r->bytes <= opts.batch_budget_bytes; });
         inflight += r->bytes;
+        grp.push_back(r);
+        // batches that queued meanwhile join the pass while the budget allows
+        while ((int)grp.size() < kPassMax && !sl->q.empty() &&
+               inflight + sl->q.front()->bytes <= opts.batch_budget_bytes) {
+          inflight += sl->q.front()->bytes;
+          grp.push_back(sl->q.front());
+          sl->q.pop_front();
+        }
       }
-      r->t_start = clk::now();
-      int rc = gc_apply_batch(sl->g, r->iu.data(), r->iv.data(), (int64_t)r->iu.size(), r->du.data(), r->dv.data(),
-                              (int64_t)r->du.size(), r->counts, &r->stats);
-      r->t_done = clk::now();
+      const auto t_start = clk::now();
+      std::vector<std::shared_ptr<Request>> run;
+      std::vector<gc_batch_desc> descs;
+      for (auto& r : grp) {
+        r->t_start = t_start;
+        if (!ids_ok(r->iu, sl->n) || !ids_ok(r->iv, sl->n) || !ids_ok(r->du, sl->n) || !ids_ok(r->dv, sl->n)) {
+          r->rc = GC_EINVAL;
+          r->err = "batch has a vertex id outside [0, n)";
+          continue;
+        }
+        run.push_back(r);
+        descs.push_back(gc_batch_desc{r->iu.data(), r->iv.data(), (int64_t)r->iu.size(), r->du.data(),
+                                      r->dv.data(), (int64_t)r->du.size()});
+      }
+      int rc = GC_OK;
+      std::string err;
+      if (!run.empty()) {
+        std::vector<int64_t> cnt(run.size() * 11);
+        std::vector<gc_batch_stats> st(run.size());
+        rc = gc_apply_batch_seq(sl->g, descs.data(), (int32_t)run.size(), (int64_t(*)[11])cnt.data(), st.data());
+        if (rc) err = gc_last_error();
+        for (size_t j = 0; j < run.size(); ++j) {
+          std::memcpy(run[j]->counts, &cnt[j * 11], sizeof(run[j]->counts));
+          run[j]->stats = st[j];
+        }
+      }
+      const auto t_done = clk::now();
       {
         std::lock_guard<std::mutex> lk(mu);
-        r->rc = rc;
-        if (rc) r->err = gc_last_error();
-        r->done = true;
-        inflight -= r->bytes;
+        for (auto& r : run) {
+          r->rc = rc;
+          if (rc) r->err = err;
+        }
+        for (auto& r : grp) {
+          r->t_done = t_done;
+          r->done = true;
+          inflight -= r->bytes;
+        }
       }
       cv_mem.notify_all();
       cv_done.notify_all();
@@ -146,6 +193,7 @@ int gc_server_add_graph(gc_server* s, int64_t n, const int32_t* src, const int32
   std::lock_guard<std::mutex> lk(s->mu);
   auto sl = std::make_unique<Slot>();
   sl->g = g;
+  sl->n = n;
   sl->footprint = est;
   s->graph_bytes += est;
   Slot* raw = sl.get();

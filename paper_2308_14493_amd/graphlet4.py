@@ -33,7 +33,8 @@ class BatchStats(ctypes.Structure):
         "ins_existing", "del_missing", "touched_vertices", "region_vertices", "region_entries",
         "wedges", "c4_entries_small", "c4_entries_mid", "c4_entries_large", "c4_tail_wedges",
         "max_out_degree", "tier_tri_small", "tier_tri_large", "tier_c4_small",
-        "tier_c4_mid", "tier_c4_large", "c4_dense_min")] + [("whole_graph", _I32), ("overflow_mask", ctypes.c_uint32)] + [
+        "tier_c4_mid", "tier_c4_large", "c4_dense_min")] + [
+        ("whole_graph", _I32), ("overflow_mask", ctypes.c_uint32), ("pass_batches", _I32)] + [
         (n, ctypes.c_float) for n in ("ms_total", "ms_prepare", "ms_tri", "ms_edge", "ms_c4_small",
                                       "ms_c4_mid", "ms_c4_large", "ms_finish")]
 
@@ -55,7 +56,7 @@ class GraphletError(RuntimeError):
 _lib = None
 
 EXPORTS = ["gc_options_default", "gc_graph_init", "gc_pool_init", "gc_apply_batch", "gc_apply_batch_dev",
-           "gc_apply_batches", "gc_get_counts", "gc_get_counts_exact", "gc_recount_exact", "gc_graph_info",
+           "gc_apply_batches", "gc_apply_batch_seq", "gc_get_counts", "gc_get_counts_exact", "gc_recount_exact", "gc_graph_info",
            "gc_export_edges", "gc_graph_free", "gc_strerror", "gc_last_error",
            "gc_server_opts_default", "gc_server_create", "gc_server_add_graph", "gc_server_submit",
            "gc_server_wait", "gc_server_counts", "gc_server_destroy"]
@@ -87,6 +88,7 @@ def load(path: str = LIB_PATH):
     lib.gc_apply_batch.argtypes = [_P, _P, _P, _I64, _P, _P, _I64, _P, ctypes.POINTER(BatchStats)]
     lib.gc_apply_batch_dev.argtypes = [_P, _P, _P, _I64, _P, _P, _I64, _P, ctypes.POINTER(BatchStats)]
     lib.gc_apply_batches.argtypes = [_P, _P, _P, ctypes.POINTER(BatchStats)]
+    lib.gc_apply_batch_seq.argtypes = [_P, _P, _I32, _P, _P]
     lib.gc_get_counts.argtypes = [_P, _I32, _P, ctypes.POINTER(ctypes.c_uint32)]
     lib.gc_get_counts_exact.argtypes = [_P, _I32, _P, _P]
     lib.gc_recount_exact.argtypes = [_P, _I32, _P, _P]
@@ -229,6 +231,27 @@ class Graph:
         _check(lib.gc_apply_batches(self._h, ctypes.cast(descs, _P), None, ctypes.byref(st) if stats else None))
         out = [self.counts(g) for g in range(self.k)]
         return (out, st.as_dict()) if stats else out
+
+    def apply_batch_seq(self, batches, stats=False):
+        """Applies batches (ins_src, ins_dst, del_src, del_dst) in order, up to
+        three per counting pass; returns the counts after each batch as int64
+        values (the low 64 bits where a class leaves int64; counts() gives the
+        exact values after the last batch)."""
+        lib = load()
+        nb = len(batches)
+        keep = []
+        descs = (BatchDesc * max(nb, 1))()
+        for j, b in enumerate(batches):
+            iu, iv, du, dv = (_i32(x) for x in b)
+            assert iu.shape == iv.shape and du.shape == dv.shape
+            keep.append((iu, iv, du, dv))
+            descs[j] = BatchDesc(iu.ctypes.data, iv.ctypes.data, iu.size, du.ctypes.data, dv.ctypes.data, du.size)
+        out = np.zeros((max(nb, 1), 11), np.int64)
+        sts = (BatchStats * max(nb, 1))()
+        _check(lib.gc_apply_batch_seq(self._h, ctypes.cast(descs, _P), nb, out.ctypes.data,
+                                      ctypes.cast(sts, _P) if stats else None))
+        rows = [[int(x) for x in out[j]] for j in range(nb)]
+        return (rows, [sts[j].as_dict() for j in range(nb)]) if stats else rows
 
     def counts(self, graph=0):
         """Exact counts (Python ints) of graph `graph`."""

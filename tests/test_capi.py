@@ -25,6 +25,16 @@ def test_library_exports_every_symbol():
         assert hasattr(lib, name), name
 
 
+def test_binding_declares_argument_types():
+    """Every entry point with arguments has ctypes argument types, so that
+    pointers and 64-bit sizes are never passed as C int."""
+    lib = graphlet4.load()
+    for name in graphlet4.EXPORTS:
+        if name == "gc_last_error":
+            continue
+        assert getattr(lib, name).argtypes is not None, name
+
+
 def test_error_strings_without_device():
     lib = graphlet4.load()
     assert lib.gc_strerror(0) == b"ok"

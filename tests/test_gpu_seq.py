@@ -1,0 +1,243 @@
+"""GPU parity of multi-version passes: several queued batches of one graph
+counted in one pass (gc_apply_batch_seq, and the server's continuous
+batching), against the oracle applying the same batches one at a time.
+
+Every count is an exact integer, so the bar is equality after every batch
+of the sequence.  The batch mixes make pairs change more than once inside
+one pass (insert, delete, insert again; delete then insert), which is the
+case the per-entry version masks exist for.
+"""
+import numpy as np
+import pytest
+
+from graphgen import erdos_renyi, rmat_graph, rmat_batches, raw_noise_batch
+from oracle import native
+from oracle.semantics import apply_batch as oracle_apply
+
+pytestmark = pytest.mark.gpu
+
+
+def G(*a, **k):
+    from paper_2308_14493_amd.graphlet4 import Graph
+    return Graph(*a, **k)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def esorted(E):
+    E = sorted(E)
+    return (np.array([u for u, v in E], np.int32), np.array([v for u, v in E], np.int32))
+
+
+def edge_set(src, dst):
+    return {(min(int(a), int(b)), max(int(a), int(b))) for a, b in zip(src, dst)}
+
+
+def as_i64(c):
+    return [v - (1 << 64) if v >= (1 << 63) else v for v in (x & ((1 << 64) - 1) for x in c)]
+
+
+def oracle_after_each(n, E, batches):
+    """Counts after each batch, applying them one at a time to the set E."""
+    out = []
+    for b in batches:
+        oracle_apply(E, n, *b)
+        es, ed = esorted(E)
+        out.append(as_i64(native.static_counts(n, es, ed)))
+    return out
+
+
+def churn_batches(n, E0, seed, nb):
+    """Batches that revisit the same pairs: a pool of pairs is inserted,
+    deleted and inserted again across consecutive batches, mixed with
+    deletions of existing edges, noise (loops, repeats, pairs both inserted
+    and deleted) and fresh random insertions."""
+    rng = np.random.default_rng(seed)
+    E = set(E0)
+    pool = [(int(a), int(b)) for a, b in rng.integers(0, n, (12, 2)) if a != b]
+    out = []
+    for j in range(nb):
+        iu, iv, du, dv = [], [], [], []
+        for (a, b) in pool:
+            r = rng.random()
+            if r < 0.4:
+                iu.append(a); iv.append(b)
+            elif r < 0.8:
+                du.append(b); dv.append(a)
+        el = sorted(E)
+        if el:
+            for q in rng.choice(len(el), min(len(el), int(rng.integers(1, 8))), replace=False):
+                du.append(el[q][0]); dv.append(el[q][1])
+        k = int(rng.integers(0, 10))
+        iu += list(rng.integers(0, n, k)); iv += list(rng.integers(0, n, k))
+        if j % 3 == 1:
+            es, ed = esorted(E)
+            nz = raw_noise_batch(n, es, ed, int(rng.integers(2, 8)), seed * 10 + j)
+            iu += list(nz[0]); iv += list(nz[1]); du += list(nz[2]); dv += list(nz[3])
+        b = tuple(np.array(x, np.int32) for x in (iu, iv, du, dv))
+        out.append(b)
+        oracle_apply(E, n, *b)
+    return out
+
+
+@pytest.mark.parametrize("radius", [2, 0])
+@pytest.mark.parametrize("seed", range(5))
+def test_seq_churn_small(seed, radius):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(10, 60))
+    p = float(rng.choice([0.08, 0.2, 0.45]))
+    say("case seq churn n=%d p=%.2f seed=%d radius=%d" % (n, p, seed, radius))
+    s, d = erdos_renyi(n, p, seed)
+    E0 = edge_set(s, d)
+    batches = churn_batches(n, E0, seed + 50, 9)
+    want = oracle_after_each(n, set(E0), batches)
+    with G(n, s, d, radius=radius) as gr:
+        got = []
+        for grp in (batches[0:3], batches[3:5], batches[5:6], batches[6:9]):
+            rows, st = gr.apply_batch_seq(grp, stats=True)
+            assert all(x["pass_batches"] == len(grp) for x in st)
+            got += rows
+        assert got == want
+        assert gr.counts() == native.static_counts(n, *esorted(oracle_final(n, E0, batches)))
+        gs, gd = gr.edges()
+        assert edge_set(gs, gd) == oracle_final(n, E0, batches)
+
+
+def oracle_final(n, E0, batches):
+    E = set(E0)
+    for b in batches:
+        oracle_apply(E, n, *b)
+    return E
+
+
+def test_seq_long_sequence_chunks():
+    """Seven batches in one call: passes of three, three and one."""
+    say("case seq of 7")
+    n = 45
+    s, d = erdos_renyi(n, 0.15, 7)
+    E0 = edge_set(s, d)
+    batches = churn_batches(n, E0, 77, 7)
+    want = oracle_after_each(n, set(E0), batches)
+    with G(n, s, d) as gr:
+        rows, st = gr.apply_batch_seq(batches, stats=True)
+        assert [x["pass_batches"] for x in st] == [3, 3, 3, 3, 3, 3, 1]
+        assert rows == want
+
+
+@pytest.mark.parametrize("scale,ef,seed", [(10, 8, 1), (12, 16, 2)])
+def test_seq_rmat_equals_one_by_one(scale, ef, seed):
+    say("case seq rmat scale=%d ef=%d" % (scale, ef))
+    n, s, d, samp = rmat_graph(scale, ef, seed)
+    sizes = [5, 300, 40, 2000, 1, 700]
+    batches = rmat_batches(n, s, d, samp, sizes, seed + 3)
+    want = oracle_after_each(n, edge_set(s, d), batches)
+    with G(n, s, d) as a, G(n, s, d) as b:
+        one = [as_i64(a.apply_batch(*x)) for x in batches]
+        seq = b.apply_batch_seq(batches[:3]) + b.apply_batch_seq(batches[3:])
+        assert one == want
+        assert seq == want
+        assert b.recount() == b.counts() == a.counts()
+
+
+@pytest.mark.parametrize("dense_min", [8, 10**12])
+@pytest.mark.parametrize("narrow", [20, 65535])
+def test_seq_c4_windows_tail_and_wide(monkeypatch, dense_min, narrow):
+    """Large 4-cycle tier with four versions: 16-bit fields in windows and
+    tail, and (narrow threshold 20) the two half passes of 32-bit fields."""
+    monkeypatch.setenv("GC_C4_WINDOW", "128")
+    monkeypatch.setenv("GC_C4_NARROW_MAX", str(narrow))
+    monkeypatch.setenv("GC_C4_DENSE_MIN", str(dense_min))
+    say("case seq c4 windows 128, narrow <= %d, dense_min %d" % (narrow, dense_min))
+    n, s, d, samp = rmat_graph(13, 16, 51)
+    batches = rmat_batches(n, s, d, samp, [100, 2000, 500], 53)
+    want = oracle_after_each(n, edge_set(s, d), batches)
+    with G(n, s, d) as gr:
+        rows, st = gr.apply_batch_seq(batches, stats=True)
+        say("  c4 large tier %d vertices, tail wedges %d" % (st[0]["tier_c4_large"], st[0]["c4_tail_wedges"]))
+        assert st[0]["tier_c4_large"] > 0
+        assert rows == want
+
+
+COMP = [0, 6, 8, 7, 9, 10, 1, 3, 2, 4, 5]   # class of the complement (pinned on the CPU)
+
+
+@pytest.mark.parametrize("n,p,seed", [(900, 0.05, 43), (1300, 0.03, 44)])
+def test_seq_dense_by_complement(n, p, seed):
+    """Dense graphs: the large-out-degree triangle tiers with four versions
+    (LDS up to 960 slots, global scratch above)."""
+    say("case seq dense complement n=%d p=%.2f" % (n, p))
+    rng = np.random.default_rng(seed)
+    cs, cd = erdos_renyi(n, p, seed)
+    full = {(u, v) for u in range(n) for v in range(u + 1, n)}
+    E = full - edge_set(cs, cd)
+    s, d = esorted(E)
+
+    def want(Eset):
+        c = esorted(full - Eset)
+        o = native.static_counts(n, c[0], c[1])
+        return as_i64([o[COMP[k]] for k in range(11)])
+
+    batches = []
+    Es = set(E)
+    for k in (40, 400, 120):
+        el = sorted(Es)
+        pick = rng.choice(len(el), k // 2, replace=False)
+        du = np.array([el[q][0] for q in pick], np.int32)
+        dv = np.array([el[q][1] for q in pick], np.int32)
+        iu = rng.integers(0, n, k // 2).astype(np.int32)
+        iv = rng.integers(0, n, k // 2).astype(np.int32)
+        batches.append((iu, iv, du, dv))
+        oracle_apply(Es, n, iu, iv, du, dv)
+    with G(n, s, d) as gr:
+        rows, st = gr.apply_batch_seq(batches, stats=True)
+        say("  max out-degree %d" % st[0]["max_out_degree"])
+        Ew = set(E)
+        for b, r in zip(batches, rows):
+            oracle_apply(Ew, n, *b)
+            assert r == want(Ew)
+
+
+def test_seq_bad_id_rejects_whole_call():
+    say("case seq invalid ids")
+    from paper_2308_14493_amd.graphlet4 import GraphletError
+    n = 30
+    s, d = erdos_renyi(n, 0.2, 3)
+    with G(n, s, d) as gr:
+        before = gr.counts()
+        good = (np.array([1], np.int32), np.array([2], np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32))
+        bad = (np.array([1], np.int32), np.array([n], np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32))
+        with pytest.raises(GraphletError) as e:
+            gr.apply_batch_seq([good, bad, good])
+        assert e.value.code == -1
+        assert gr.counts() == before == gr.recount()
+
+
+def test_server_continuous_batching():
+    """Many requests for one graph submitted at once queue behind the first
+    pass; the worker folds them into multi-version passes.  Each ticket's
+    counts equal the one-by-one result; an invalid request fails alone."""
+    from paper_2308_14493_amd.graphlet4 import Server, Graph, GraphletError
+    say("case server continuous batching")
+    n, s, d, samp = rmat_graph(12, 8, 71)
+    sizes = [3000, 40, 200, 7, 900, 60, 15, 2500, 120, 33, 400, 5]
+    batches = rmat_batches(n, s, d, samp, sizes, 72)
+    with Graph(n, s, d) as g:
+        alone = [as_i64(g.apply_batch(*b)) for b in batches]
+    bad = (np.array([0], np.int32), np.array([n + 5], np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32))
+    with Server() as srv:
+        gid = srv.add_graph(n, s, d)
+        tickets = [srv.submit(gid, *b) for b in batches[:6]]
+        tbad = srv.submit(gid, *bad)
+        tickets += [srv.submit(gid, *b) for b in batches[6:]]
+        passes = []
+        for j, t in enumerate(tickets):
+            c, st, lat, qms = srv.wait(t)
+            assert [int(v) for v in c] == alone[j], "request %d" % j
+            passes.append(st["pass_batches"])
+        with pytest.raises(GraphletError):
+            srv.wait(tbad)
+        say("  pass sizes %s" % passes)
+        assert max(passes) > 1
+        assert srv.counts(gid) == native.static_counts(n, *esorted(oracle_final(n, edge_set(s, d), batches)))

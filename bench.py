@@ -193,18 +193,20 @@ def bench_served(args):
 
         th = threading.Thread(target=feeder)
         th.start()
-        lat, same = [], True
+        lat, same, passes = [], True, []
         for i in range(len(batches)):
             while tickets[i] is None:
                 time.sleep(0.0005)
             c, st, l, q = srv.wait(tickets[i])
             lat.append(l)
+            passes.append(st["pass_batches"])
             same &= [int(x) for x in c] == [int(x) for x in plain[i][0]]
         end = time.perf_counter()
         th.join()
         assert srv.counts(gid) == final
         runs["%.1fx" % f] = {"offered_rate_batches_per_s": f / service, "updates_per_s": offered / (end - start),
                              "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+                             "mean_batches_per_pass": float(np.mean(passes)),
                              "results_equal_to_plain": bool(same)}
         log("rate %.1fx: %s" % (f, runs["%.1fx" % f]))
         closed_loop(inverse)

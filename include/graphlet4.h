@@ -98,6 +98,15 @@ typedef struct {
    * decade, once the region of change covers >= 90% of the graph, later
    * batches of that size count the whole graph (same result, no marking). */
   int32_t autotune;
+  /* 1 (default): a host-array pass without statistics runs as one HIP graph:
+   * the whole pass (upload, ingest, merge, region, counting, purge, result
+   * download) is captured the first time a pass of its shape is enqueued and
+   * replayed afterwards.  The shape is the number of batches, the capacity
+   * classes of the batch sizes (powers of two), the region mode, the tuned
+   * knobs and the scratch buffers; a pass whose scratch has to grow runs
+   * directly and is captured anew.  0: every pass launches its kernels one
+   * by one.  Results are identical either way. */
+  int32_t graphs;
 } gc_options;
 
 typedef struct {
@@ -190,6 +199,10 @@ int gc_graph_info(const gc_graph* g, int32_t* num_graphs, int32_t graph, int64_t
 /* Copies the edges of graph `graph` (each once, external ids) into host
  * arrays of capacity cap; *m_out = edge count (GC_EINVAL if cap < m). */
 int gc_export_edges(gc_graph* g, int32_t graph, int32_t* src, int32_t* dst, int64_t cap, int64_t* m_out);
+
+/* Diagnostics of the graphs option: passes captured as HIP graphs and
+ * passes launched from a captured graph (replays included) so far. */
+int gc_graph_replays(const gc_graph* g, int64_t* captures, int64_t* launches);
 
 int gc_graph_free(gc_graph* g);
 

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -142,6 +143,12 @@ struct gc_graph {
   int64_t c4_cur_low = 0;
   int32_t c4_slots = 0, tri_slots = 0;
   int64_t tri_cap = 0;
+  int64_t e_alloc = 0;               // entries of the region arrays
+  int64_t seen_maxdp = 0, seen_maxlow = 0;  // largest out-degree / lower degree counted so far
+
+  // captured passes: everything an enqueued pass depends on -> executable graph
+  std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
+  int64_t graph_launches = 0, graph_captures = 0;
 
   // online autotuner (speed knobs only)
   std::vector<int64_t> tune_cands{512, 1024, 2048, 4096, 8192};
@@ -152,14 +159,33 @@ struct gc_graph {
 
   void* pin = nullptr;
   size_t pin_cap = 0;
+  // pinned results of a pass: ctr [C_COUNT] | bstats [BS_COUNT] | state [k ST] |
+  // vout [(GC_NV_MAX - 1) k ST] | arena top
+  void* pout = nullptr;
   hipEvent_t ev[10] = {};
 
   ~gc_graph() {
     if (stream) (void)hipStreamSynchronize(stream);
+    drop_graphs();
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     if (pin) (void)hipHostFree(pin);
+    if (pout) (void)hipHostFree(pout);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+  void drop_graphs() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
+  unsigned long long* out_ctr() const { return (unsigned long long*)pout; }
+  unsigned long long* out_bst() const { return out_ctr() + C_COUNT; }
+  long long* out_state() const { return (long long*)(out_bst() + BS_COUNT); }
+  long long* out_vout() const { return out_state() + (size_t)k * ST_STRIDE; }
+  unsigned long long* out_top() const {
+    return (unsigned long long*)(out_vout() + (size_t)(GC_NV_MAX - 1) * k * ST_STRIDE);
+  }
+  size_t out_bytes() const {
+    return (size_t)(C_COUNT + BS_COUNT + 1) * 8 + (size_t)GC_NV_MAX * k * ST_STRIDE * 8;
   }
 
   PoolDev pd() const {
@@ -213,109 +239,154 @@ void zero_small(gc_graph* G) {
   fill_u64(G->sig.as<unsigned long long>(), 0ull, (int64_t)G->k * GC_NV_MAX * SG_N, G->stream);
 }
 
-// Region + per-vertex pass + counting over nv versions + combine into
-// `state_d` (and G->vout for every later version).  `radius` < 0 counts
-// every vertex.  Host copy of the counters goes to hc.
-void run_count(gc_graph* G, int nv, int radius, long long* state_d, BatchWork& W, std::vector<unsigned long long>& hc,
-               int64_t union_entries, bool timed, int64_t dense_min = 2048) {
-  hipStream_t s = G->stream;
+// Before a second attempt of the counting stage: its counters, statistics
+// and sums (the ingest and merge counters stay).
+void reset_count_stage(gc_graph* G) {
+  fill_u64(G->ctr.as<unsigned long long>() + C_RLIST, 0ull, C_COUNT - C_RLIST, G->stream);
+  fill_u64(G->bstats.as<unsigned long long>() + BS_COUNT_STAGE, 0ull, BS_COUNT - BS_COUNT_STAGE, G->stream);
+  fill_u64(G->sig.as<unsigned long long>(), 0ull, (int64_t)G->k * GC_NV_MAX * SG_N, G->stream);
+}
+
+// Scratch of the counting stage for a union view of up to `entries` entries.
+// Hub and triangle scratch follow the largest degrees counted so far; a
+// kernel that meets a larger vertex asks for a second attempt (BS_RETRY).
+// Allocates: never called during stream capture.
+void size_count_scratch(gc_graph* G, int nv, int64_t entries) {
   const int64_t N = G->N;
   G->roff.ensure((N + 1) * sizeof(int64_t));
   G->c4_keys.ensure(N * sizeof(unsigned long long));
   G->c4_keys_alt.ensure(N * sizeof(unsigned long long));
   G->sort_tmp.ensure(radix_sort_tmp_bytes(N) + 64);
-  G->rcol.ensure(std::max<int64_t>(union_entries, 1) * sizeof(uint32_t));
-  G->rrow.ensure(std::max<int64_t>(union_entries, 1) * sizeof(int32_t));
-  G->t.ensure(std::max<int64_t>(union_entries, 1) * sizeof(unsigned long long));
-  if (nv > 2) G->tp.ensure(std::max<int64_t>(union_entries, 1) * 2 * sizeof(unsigned long long));
-  G->dver.ensure((size_t)N * GC_NV_MAX * sizeof(int32_t));
-  G->vpos.ensure(std::max<int64_t>(union_entries, 1) * sizeof(int32_t));
   G->scan_tmp.ensure(scan_tmp_bytes(N + 1) + 64);
-  PoolDev P = G->pd();
-  RegionDev R = G->rd();
-  launch_region(P, W, radius, G->level.as<int32_t>(), G->rlist.as<int32_t>(), G->rlen.as<int32_t>(), s);
-  launch_region_fill(P, R, W, radius, G->level.as<int32_t>(), G->rlist.as<int32_t>(), G->rlen.as<int32_t>(),
-                     G->scan_tmp.p, s);
-  launch_degrees(nv, R, G->gid.as<int32_t>(), G->rlist.as<int32_t>(), G->ctr.as<unsigned long long>(),
-                 G->sig.as<unsigned long long>(), G->lists.as<int32_t>(), N, TRI_SMALL, C4_SMALL, C4_MID,
-                 G->bstats.as<unsigned long long>(), G->c4_keys.as<unsigned long long>(), s);
-  if (timed) HIPCHK(hipEventRecord(G->ev[1], s));
-  hc.assign(C_COUNT, 0);
-  HIPCHK(hipMemcpyAsync(hc.data(), G->ctr.p, C_COUNT * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-  G->sync();
-  if ((int64_t)hc[C_ER] > union_entries) raise(GC_EDEVICE, "region larger than the union view");
+  if (entries > G->e_alloc) G->e_alloc = entries + entries / 4 + 1024;
+  const int64_t E = G->e_alloc;
+  G->rcol.ensure(E * sizeof(uint32_t));
+  G->rrow.ensure(E * sizeof(int32_t));
+  G->t.ensure(E * sizeof(unsigned long long));
+  G->vpos.ensure(E * sizeof(int32_t));
+  if (nv > 2) G->tp.ensure(2 * E * sizeof(unsigned long long));
+  G->dver.ensure((size_t)N * GC_NV_MAX * sizeof(int32_t));
+  // large 4-cycle tier: dense counters per resident workgroup (one
+  // 1024-thread block per CU fills the chip)
+  const int64_t per = N * (int64_t)(sizeof(unsigned long long) + sizeof(int32_t));
+  int64_t slots = std::max<int64_t>(1, std::min<int64_t>(256, ((int64_t)16 << 30) / std::max<int64_t>(per, 1)));
+  slots = std::min<int64_t>(slots, std::max<int64_t>(1, N));
+  if (slots > G->c4_slots) {
+    G->c4_dense.release();
+    G->c4_touch.release();
+    G->c4_dense.ensure((size_t)(slots * N) * sizeof(unsigned long long));
+    G->c4_touch.ensure((size_t)(slots * N) * sizeof(int32_t));
+    fill_u64(G->c4_dense.as<unsigned long long>(), 0ull, slots * N, G->stream);
+    G->c4_slots = (int32_t)slots;
+  }
+  if (G->seen_maxlow > G->c4_cur_low) G->c4_cur_low = G->seen_maxlow + G->seen_maxlow / 4 + 64;
+  G->c4_cur_low = std::max<int64_t>(G->c4_cur_low, 64);
+  G->c4_cur.ensure((size_t)(G->c4_slots * 2 * G->c4_cur_low) * sizeof(int64_t));
+  // triangles above the LDS tiers: scratch slots in global memory
+  if (G->seen_maxdp > tri_lds_max(nv)) {
+    if (G->seen_maxdp > 32767)
+      raise(GC_EINVAL, "oriented out-degree %lld exceeds the supported 32767", (long long)G->seen_maxdp);
+    const int64_t cap = std::max<int64_t>(G->tri_cap, std::min<int64_t>(32767, G->seen_maxdp + G->seen_maxdp / 8 + 16));
+    const size_t need = (size_t)(tri_scratch_words64(nv, cap) * 256) * sizeof(unsigned long long);
+    if (need > G->tri_scratch.cap) {
+      G->tri_scratch.release();
+      G->tri_scratch.ensure(need);
+    }
+    G->tri_cap = cap;
+    G->tri_slots = 256;
+  }
+}
 
+CountArgs make_count_args(gc_graph* G, int nv, int64_t dense_min) {
+  (void)nv;
   CountArgs A;
-  A.R = R;
+  A.R = G->rd();
   A.gid = G->gid.as<int32_t>();
   A.lists = G->lists.as<int32_t>();
-  A.list_stride = N;
+  A.list_stride = G->N;
   A.c = G->ctr.as<unsigned long long>();
   A.sig = G->sig.as<unsigned long long>();
   A.bstats = G->bstats.as<unsigned long long>();
-  A.N = N;
-  // large 4-cycle tier: dense counters per resident workgroup
-  const int64_t ncl = (int64_t)hc[C_LIST0 + L_C4_L];
-  if (ncl > 0) {
-    int64_t per = N * (int64_t)(sizeof(unsigned long long) + sizeof(int32_t));
-    // one resident 1024-thread block per CU is enough to fill the chip
-    int64_t budget = (int64_t)16 << 30;
-    int64_t slots = std::max<int64_t>(1, std::min<int64_t>(256, budget / std::max<int64_t>(per, 1)));
-    slots = std::min<int64_t>(slots, ncl);  // small graphs: fewer hubs than workgroups
-    if (slots > G->c4_slots) {
-      G->c4_dense.release();
-      G->c4_touch.release();
-      G->c4_dense.ensure((size_t)(slots * N) * sizeof(unsigned long long));
-      G->c4_touch.ensure((size_t)(slots * N) * sizeof(int32_t));
-      fill_u64(G->c4_dense.as<unsigned long long>(), 0ull, slots * N, s);
-      G->c4_slots = (int32_t)slots;
-    }
-  }
-  // window of the large 4-cycle tier; GC_C4_WINDOW / GC_C4_NARROW_MAX override
-  // the defaults (tests shrink them to reach every path on small graphs)
+  A.N = G->N;
+  // window of the large 4-cycle tier; GC_C4_WINDOW / GC_C4_NARROW_MAX /
+  // GC_C4_DENSE_MIN override the defaults (tests shrink them to reach every
+  // path on small graphs)
   A.c4_win = c4_window_max();
   A.c4_narrow_max = 65535;
   if (const char* e = std::getenv("GC_C4_WINDOW")) A.c4_win = std::max(64, std::min(c4_window_max(), std::atoi(e)));
   if (const char* e = std::getenv("GC_C4_NARROW_MAX")) A.c4_narrow_max = std::max(0, std::min(65535, std::atoi(e)));
   A.c4_dense_min = dense_min;
   if (const char* e = std::getenv("GC_C4_DENSE_MIN")) A.c4_dense_min = std::max<int64_t>(0, std::atoll(e));
-  {
-    const int64_t maxlow = std::max<int64_t>(1, (int64_t)hc[C_MAXLOW]);
-    const int64_t slots = std::max(1, G->c4_slots);
-    if (ncl > 0 && (maxlow > G->c4_cur_low || G->c4_cur.cap < (size_t)(slots * 2 * maxlow * 8))) {
-      G->c4_cur.release();
-      G->c4_cur.ensure((size_t)(slots * 2 * maxlow) * sizeof(int64_t));
-      G->c4_cur_low = maxlow;
-    }
-  }
   A.c4_cur = G->c4_cur.as<int64_t>();
-  A.c4_maxlow = std::max<int64_t>(1, G->c4_cur_low);
+  A.c4_maxlow = G->c4_cur_low;
   A.c4_keys = G->c4_keys.as<unsigned long long>();
   A.c4_keys_alt = G->c4_keys_alt.as<unsigned long long>();
   A.sort_tmp = G->sort_tmp.p;
   A.c4_dense = G->c4_dense.as<unsigned long long>();
   A.c4_touch = G->c4_touch.as<int32_t>();
   A.slots = std::max(1, G->c4_slots);
-  // triangles above the LDS tier: scratch slots in global memory
-  const int64_t maxdp = (int64_t)hc[C_MAXDP];
-  if (maxdp > tri_lds_max(nv)) {
-    if (maxdp > 32767) raise(GC_EINVAL, "oriented out-degree %lld exceeds the supported 32767", (long long)maxdp);
-    // the kernels lay out every slot for capacity tri_cap: size for the one in use
-    const int32_t slots = 256;
-    const int64_t cap_use = std::max<int64_t>(maxdp, G->tri_cap);
-    const size_t need = (size_t)(tri_scratch_words64(nv, cap_use) * slots) * sizeof(unsigned long long);
-    if (need > G->tri_scratch.cap) {
-      G->tri_scratch.release();
-      G->tri_scratch.ensure(need);
-    }
-    G->tri_cap = cap_use;
-    G->tri_slots = slots;
-  }
   A.tri_scratch = G->tri_scratch.as<unsigned long long>();
   A.tri_cap = G->tri_cap;
-  A.tri_slots = std::max(1, G->tri_slots);
-  launch_count(nv, A, hc.data(), s, timed ? &G->ev[2] : nullptr);
-  launch_combine(nv, G->sig.as<unsigned long long>(), state_d, G->vout.as<long long>(), G->k, s);
+  A.tri_slots = 256;  // blocks of the global-scratch tier (no slot is used while tri_cap == 0)
+  A.e_max = G->e_alloc;
+  return A;
+}
+
+// Region + per-vertex pass + counting over nv versions + combine into
+// `state_d` (and G->vout for every later version).  `radius` < 0 counts
+// every vertex.  Enqueue only: no allocation, no synchronisation.
+void enqueue_count(gc_graph* G, int nv, int radius, long long* state_d, BatchWork& W, const CountArgs& A, bool timed) {
+  hipStream_t s = G->stream;
+  PoolDev P = G->pd();
+  launch_region(P, W, radius, G->level.as<int32_t>(), G->rlist.as<int32_t>(), G->rlen.as<int32_t>(), s);
+  launch_region_fill(P, A.R, W, radius, G->level.as<int32_t>(), G->rlist.as<int32_t>(), G->rlen.as<int32_t>(),
+                     G->scan_tmp.p, s);
+  launch_degrees(nv, A.R, G->gid.as<int32_t>(), G->rlist.as<int32_t>(), G->ctr.as<unsigned long long>(),
+                 G->sig.as<unsigned long long>(), G->lists.as<int32_t>(), G->N, TRI_SMALL, C4_SMALL, C4_MID,
+                 G->bstats.as<unsigned long long>(), G->c4_keys.as<unsigned long long>(), s);
+  if (timed) HIPCHK(hipEventRecord(G->ev[1], s));
+  launch_count(nv, A, s, timed ? &G->ev[2] : nullptr);
+  launch_combine(nv, G->sig.as<unsigned long long>(), state_d, G->vout.as<long long>(), G->k,
+                 G->bstats.as<unsigned long long>(), s);
+}
+
+// Results of a pass into the pinned buffer (enqueue only).
+void enqueue_readback(gc_graph* G, const long long* state_d) {
+  hipStream_t s = G->stream;
+  const size_t st = (size_t)G->k * ST_STRIDE * 8;
+  HIPCHK(hipMemcpyAsync(G->out_ctr(), G->ctr.p, C_COUNT * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(G->out_bst(), G->bstats.p, BS_COUNT * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(G->out_state(), state_d, st, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(G->out_vout(), G->vout.p, (GC_NV_MAX - 1) * st, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(G->out_top(), G->top.p, 8, hipMemcpyDeviceToHost, s));
+}
+
+void note_maxima(gc_graph* G) {
+  G->seen_maxdp = std::max<int64_t>(G->seen_maxdp, (int64_t)G->out_ctr()[C_MAXDP]);
+  G->seen_maxlow = std::max<int64_t>(G->seen_maxlow, (int64_t)G->out_ctr()[C_MAXLOW]);
+}
+
+// After a pass whose results are in the pinned buffer: while a kernel asked
+// for more scratch (the combine and the purge then changed nothing), grow it
+// from the observed degrees and count again.  Returns the attempts made.
+int settle_retries(gc_graph* G, int nv, int radius, long long* state_d, BatchWork& W, int64_t dense_min,
+                   int64_t entries, bool purge, int64_t max_touched) {
+  int attempts = 0;
+  while (G->out_bst()[BS_RETRY]) {
+    if (++attempts > 2) raise(GC_EDEVICE, "counting scratch still too small after two more attempts");
+    note_maxima(G);
+    size_count_scratch(G, nv, entries);
+    reset_count_stage(G);
+    CountArgs A = make_count_args(G, nv, dense_min);
+    enqueue_count(G, nv, radius, state_d, W, A, false);
+    if (purge)
+      launch_purge(G->pd(), W, max_touched, G->bits, 1u << (GC_VSHIFT + nv - 1),
+                   G->bstats.as<unsigned long long>() + BS_RETRY, G->scan_tmp.p, G->stream);
+    enqueue_readback(G, state_d);
+    G->sync();
+  }
+  note_maxima(G);
+  return attempts;
 }
 
 BatchWork make_work(gc_graph* G) {
@@ -355,6 +426,7 @@ void alloc_vertex_arrays(gc_graph* G) {
   G->ctr.ensure(C_COUNT * sizeof(unsigned long long));
   G->bstats.ensure(BS_COUNT * sizeof(unsigned long long));
   G->top.ensure(sizeof(unsigned long long));
+  if (!G->pout) HIPCHK(hipHostMalloc(&G->pout, G->out_bytes(), hipHostMallocDefault));
 }
 
 // fresh arena with new slack; keeps ids
@@ -531,8 +603,11 @@ void build(gc_graph* G, int32_t k, const int64_t* n, const int32_t* const* src, 
   fill_u64((unsigned long long*)G->state.p, 0ull, (int64_t)k * ST_STRIDE, s);
   zero_small(G);
   BatchWork W = make_work(G);
-  std::vector<unsigned long long> hc;
-  run_count(G, 2, -1, G->state.as<long long>(), W, hc, nd, false);
+  size_count_scratch(G, 2, nd);
+  enqueue_count(G, 2, -1, G->state.as<long long>(), W, make_count_args(G, 2, 2048), false);
+  enqueue_readback(G, G->state.as<long long>());
+  G->sync();
+  settle_retries(G, 2, -1, G->state.as<long long>(), W, 2048, nd, false, 0);
   launch_all_flags(P, 0u, GC_ID, s);
   G->sync();
   G->entries = nd;
@@ -600,12 +675,96 @@ void check_batch(const gc_batch_desc& b, int64_t n, int which) {
             (long long)n);
 }
 
+int64_t pow2_at_least(int64_t x) {
+  int64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Host-side sizes of one pass.  Array layouts and grids use the capacities
+// (powers of two), so passes whose batches fall in the same capacity class
+// enqueue the same work and can replay one captured graph.
+struct PassPlan {
+  int nseg = 1, npass = 1, nv = 2;
+  bool seq = false, dev = false;
+  int64_t ni = 0, ndl = 0, total = 0;
+  int64_t cap_i = 1, cap_d = 1, cap_t = 2, max_touched = 2, union_bound = 0;
+  size_t tab_words = 0, in_bytes = 0;
+  int radius = 2;
+  int64_t dense_min = 2048;
+};
+
+// Every device step of a pass, in stream order: upload, ingest, merge,
+// counting, purge, results to the pinned buffer.  No allocation and no
+// synchronisation (except the device-array id check, which is never
+// captured), so the same sequence runs directly or under stream capture.
+void enqueue_pass(gc_graph* G, const PassPlan& L, BatchIn& B, BatchWork& W, bool timed) {
+  hipStream_t s = G->stream;
+  PoolDev P = G->pd();
+  unsigned long long* bst = G->bstats.as<unsigned long long>();
+  unsigned long long* ctr = G->ctr.as<unsigned long long>();
+  zero_small(G);
+  HIPCHK(hipMemcpyAsync(G->bin.p, G->pin, L.in_bytes, hipMemcpyHostToDevice, s));
+  if (timed) HIPCHK(hipEventRecord(G->ev[0], s));
+  launch_ingest_keys(P, B, G->bits, G->keys.as<unsigned long long>(), ctr, bst, L.cap_t, s);
+  unsigned long long* sk = radix_sort_u64(G->keys.as<unsigned long long>(), G->keys_alt.as<unsigned long long>(),
+                                          G->sort_tmp.p, L.cap_t, ctr + C_NKEYS, 2 * G->bits + 3, s);
+  launch_ingest_classify(P, sk, L.cap_t, G->bits, L.npass, L.nv, G->dirA.as<unsigned long long>(),
+                         G->dirD.as<unsigned long long>(), G->dirR.as<unsigned long long>(), ctr, bst, s);
+  if (L.dev) {
+    unsigned long long err = 0;
+    HIPCHK(hipMemcpyAsync(&err, bst + PB_IDX(0, PB_ERR), 8, hipMemcpyDeviceToHost, s));
+    G->sync();
+    if (err) raise(GC_EINVAL, "batch has %llu vertex ids outside the graph", err);
+  }
+  unsigned long long* sA = radix_sort_u64(G->dirA.as<unsigned long long>(), G->dirA_alt.as<unsigned long long>(),
+                                          G->sort_tmp.p, 2 * L.cap_i, ctr + C_DIRA, 2 * G->bits, s);
+  unsigned long long* sD = radix_sort_u64(G->dirD.as<unsigned long long>(), G->dirD_alt.as<unsigned long long>(),
+                                          G->sort_tmp.p, 2 * L.cap_d, ctr + C_DIRD, 2 * G->bits, s);
+  unsigned long long* sR = radix_sort_u64(G->dirR.as<unsigned long long>(), G->dirR_alt.as<unsigned long long>(),
+                                          G->sort_tmp.p, 2 * L.cap_d, ctr + C_DIRR, 2 * G->bits, s);
+  if (sA != W.dirA || sD != W.dirD || sR != W.dirR) raise(GC_EDEVICE, "sorted merge lists not where expected");
+  launch_mark_rows(sA, 2 * L.cap_i, ctr, C_DIRA, G->bits, W.a_beg, W.na, W.mark, W.touched, W.tix, s);
+  launch_mark_rows(sD, 2 * L.cap_d, ctr, C_DIRD, G->bits, nullptr, nullptr, W.mark, W.touched, W.tix, s);
+  launch_mark_rows(sR, 2 * L.cap_d, ctr, C_DIRR, G->bits, W.r_beg, W.nr, W.mark, W.touched, W.tix, s);
+  launch_merge(P, W, L.max_touched, 2 * L.cap_i, G->bits, G->opt.slack, bst, G->scan_tmp.p, s);
+  launch_flag_rows(P, W, 2 * L.cap_d, G->bits, bst, s);
+  enqueue_count(G, L.nv, L.radius, G->state.as<long long>(), W, make_count_args(G, L.nv, L.dense_min), timed);
+  launch_purge(P, W, L.max_touched, G->bits, 1u << (GC_VSHIFT + L.nv - 1), bst + BS_RETRY, G->scan_tmp.p, s);
+  if (timed) HIPCHK(hipEventRecord(G->ev[8], s));
+  enqueue_readback(G, G->state.as<long long>());
+}
+
+// What an enqueued pass depends on: its sizes and knobs and every buffer
+// address it reads or writes.  Equal signatures enqueue identical work.
+std::vector<uint64_t> pass_signature(gc_graph* G, const PassPlan& L, const CountArgs& A) {
+  std::vector<uint64_t> v = {(uint64_t)L.nseg, (uint64_t)L.seq, (uint64_t)L.npass, (uint64_t)L.nv,
+                             (uint64_t)L.cap_i, (uint64_t)L.cap_d, (uint64_t)(int64_t)L.radius,
+                             (uint64_t)A.c4_dense_min, (uint64_t)A.c4_win, (uint64_t)A.c4_narrow_max,
+                             (uint64_t)A.c4_maxlow, (uint64_t)A.slots, (uint64_t)A.tri_cap, (uint64_t)A.e_max,
+                             (uint64_t)G->arena_cap, (uint64_t)L.in_bytes, (uint64_t)G->k, (uint64_t)G->N,
+                             (uint64_t)G->bits};
+  const DevBuf* bufs[] = {&G->off, &G->len, &G->cap, &G->col, &G->top, &G->gid, &G->ext2int, &G->state, &G->vout,
+                          &G->sig, &G->ctr, &G->bstats, &G->bin, &G->keys, &G->keys_alt, &G->dirA, &G->dirA_alt,
+                          &G->dirD, &G->dirD_alt, &G->dirR, &G->dirR_alt, &G->a_beg, &G->na, &G->r_beg, &G->nr,
+                          &G->mark, &G->tix, &G->touched, &G->dest, &G->newcap, &G->tlen, &G->tpre, &G->scratch,
+                          &G->sort_tmp, &G->scan_tmp, &G->roff, &G->rcol, &G->rrow, &G->rlow, &G->dver, &G->t,
+                          &G->tp, &G->vpos, &G->level, &G->rlist, &G->rlen, &G->lists, &G->c4_dense, &G->c4_touch,
+                          &G->c4_cur, &G->c4_keys, &G->c4_keys_alt, &G->tri_scratch};
+  for (const DevBuf* b : bufs) v.push_back((uint64_t)(uintptr_t)b->p);
+  v.push_back((uint64_t)(uintptr_t)G->pin);
+  v.push_back((uint64_t)(uintptr_t)G->pout);
+  return v;
+}
+
 // One counting pass.  seq == false: b[g] is the batch of graph g of the pool
 // (G->k of them; host arrays unless dev, which needs k == 1).  seq == true:
 // b[0..nb) are successive batches of graph 0 of a single-graph handle (host
 // arrays, nb <= GC_SEQ_MAX); counts[j] and stats[j] are those after batch j.
 // The pass compares nv versions: 2 for one batch per graph, 4 for several
-// batches (versions past the last batch repeat it).
+// batches (versions past the last batch repeat it).  Untimed host-array
+// passes replay a captured graph of the whole pass when one with the same
+// signature exists (captured on first use).
 void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int64_t (*counts)[11],
            gc_batch_stats* stats) {
   using clk = std::chrono::steady_clock;
@@ -614,48 +773,92 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = G->stream;
   const int k = G->k;
-  const int nseg = seq ? nb : k;        // segments of the update arrays
-  const int npass = seq ? nb : 1;       // batches acting in sequence
-  const int nv = npass > 1 ? 4 : 2;
-  std::vector<int64_t> ins_seg(nseg + 1, 0), del_seg(nseg + 1, 0);
-  for (int q = 0; q < nseg; ++q) {
+  PassPlan L;
+  L.seq = seq;
+  L.dev = dev;
+  L.nseg = seq ? nb : k;         // segments of the update arrays
+  L.npass = seq ? nb : 1;        // batches acting in sequence
+  L.nv = L.npass > 1 ? 4 : 2;
+  std::vector<int64_t> ins_seg(L.nseg + 1, 0), del_seg(L.nseg + 1, 0);
+  for (int q = 0; q < L.nseg; ++q) {
     const int64_t n = G->gn[seq ? 0 : q];
     if (!dev) check_batch(b[q], n, q);
     else if (b[q].n_ins < 0 || b[q].n_del < 0) raise(GC_EINVAL, "negative batch size");
     ins_seg[q + 1] = ins_seg[q] + b[q].n_ins;
     del_seg[q + 1] = del_seg[q] + b[q].n_del;
   }
-  const int64_t ni = ins_seg[nseg], ndl = del_seg[nseg];
-  const int64_t total = ni + ndl;
+  L.ni = ins_seg[L.nseg];
+  L.ndl = del_seg[L.nseg];
+  L.total = L.ni + L.ndl;
+  L.cap_i = pow2_at_least(std::max<int64_t>(L.ni, 64));
+  L.cap_d = pow2_at_least(std::max<int64_t>(L.ndl, 64));
+  L.cap_t = L.cap_i + L.cap_d;
+  L.max_touched = 2 * L.cap_t;
+  L.union_bound = G->entries + 2 * L.ni;
   const bool timed = stats != nullptr;
 
-  // upload: [ins_seg | del_seg | gbase | gn] int64, then the four id arrays
-  const size_t tab_words = (size_t)(2 * (nseg + 1) + 2 * k);
-  const size_t bytes = tab_words * 8 + (dev ? 0 : (size_t)(2 * total) * sizeof(int32_t));
-  char* pin = (char*)G->pinned(bytes + 64);
+  // speed knobs (results never depend on them)
+  L.radius = G->opt.radius == 0 ? -1 : G->opt.radius;
+  int tune_idx = -1;
+  const int decade = (int)std::min<double>(7.0, std::floor(std::log10((double)L.total + 1.0)));
+  if (G->opt.autotune) {
+    if (G->tune_next < (int)G->tune_cands.size()) {
+      tune_idx = G->tune_next;
+      L.dense_min = G->tune_cands[tune_idx];
+    } else {
+      L.dense_min = G->dense_min_best;
+    }
+    if (L.radius >= 2 && G->region_frac[decade] >= 0.9) L.radius = -1;  // exact radii only
+  }
+  const bool timed_run = timed || (G->opt.autotune && tune_idx >= 0);
+
+  // buffers (all allocation happens here, before anything is enqueued)
+  G->keys.ensure(L.cap_t * 8);
+  G->keys_alt.ensure(L.cap_t * 8);
+  for (DevBuf* d : {&G->dirA, &G->dirA_alt}) d->ensure(2 * L.cap_i * 8);
+  for (DevBuf* d : {&G->dirD, &G->dirD_alt, &G->dirR, &G->dirR_alt}) d->ensure(2 * L.cap_d * 8);
+  G->touched.ensure(L.max_touched * 4);
+  G->dest.ensure(L.max_touched * 8);
+  G->newcap.ensure(L.max_touched * 4);
+  G->tlen.ensure(L.max_touched * 4);
+  G->tpre.ensure((L.max_touched + 1) * 8);
+  G->scratch.ensure(std::max<int64_t>(L.union_bound, 1) * 4);
+  G->sort_tmp.ensure(radix_sort_tmp_bytes(std::max<int64_t>(std::max(L.cap_t, 2 * std::max(L.cap_i, L.cap_d)), G->N)) +
+                     64);
+  G->scan_tmp.ensure(scan_tmp_bytes(std::max<int64_t>(L.max_touched, G->N) + 1) + 64);
+  size_count_scratch(G, L.nv, L.union_bound);
+  // arena reserve: enough for every touched row to move
+  const int64_t need = (int64_t)((1.0 + G->opt.slack) * (double)L.union_bound) + 8 * L.max_touched + 1024;
+  if (G->arena_cap - G->arena_top < need) compact(G, need);
+
+  // pinned input: [ins_seg | del_seg | gbase | gn] int64, then the id arrays
+  // at capacity offsets (insertions u, v, deletions u, v)
+  L.tab_words = (size_t)(2 * (L.nseg + 1) + 2 * k);
+  L.in_bytes = L.tab_words * 8 + (dev ? 0 : (size_t)(2 * L.cap_t) * sizeof(int32_t));
+  char* pin = (char*)G->pinned(L.in_bytes + 64);
   int64_t* tab = (int64_t*)pin;
-  std::memcpy(tab, ins_seg.data(), (nseg + 1) * 8);
-  std::memcpy(tab + nseg + 1, del_seg.data(), (nseg + 1) * 8);
-  std::memcpy(tab + 2 * (nseg + 1), G->gbase.data(), k * 8);
-  std::memcpy(tab + 2 * (nseg + 1) + k, G->gn.data(), k * 8);
-  G->bin.ensure(bytes + 64);
+  std::memcpy(tab, ins_seg.data(), (L.nseg + 1) * 8);
+  std::memcpy(tab + L.nseg + 1, del_seg.data(), (L.nseg + 1) * 8);
+  std::memcpy(tab + 2 * (L.nseg + 1), G->gbase.data(), k * 8);
+  std::memcpy(tab + 2 * (L.nseg + 1) + k, G->gn.data(), k * 8);
+  G->bin.ensure(L.in_bytes + 64);
   BatchIn B;
-  B.n_ins = ni;
-  B.n_del = ndl;
-  B.k = nseg;
+  B.n_ins = L.ni;
+  B.n_del = L.ndl;
+  B.k = L.nseg;
   B.seq = seq ? 1 : 0;
   char* dbase = (char*)G->bin.p;
   B.ins_seg = (const int64_t*)dbase;
-  B.del_seg = B.ins_seg + nseg + 1;
-  B.gbase = B.ins_seg + 2 * (nseg + 1);
+  B.del_seg = B.ins_seg + L.nseg + 1;
+  B.gbase = B.ins_seg + 2 * (L.nseg + 1);
   B.gn = B.gbase + k;
   if (dev) {
     B.iu = b[0].ins_src; B.iv = b[0].ins_dst; B.du = b[0].del_src; B.dv = b[0].del_dst;
   } else {
-    int32_t* ids = (int32_t*)(pin + tab_words * 8);
-    int32_t* d_ids = (int32_t*)(dbase + tab_words * 8);
-    int32_t *iu = ids, *iv = ids + ni, *du = ids + 2 * ni, *dv = ids + 2 * ni + ndl;
-    for (int q = 0; q < nseg; ++q) {
+    int32_t* ids = (int32_t*)(pin + L.tab_words * 8);
+    int32_t* d_ids = (int32_t*)(dbase + L.tab_words * 8);
+    int32_t *iu = ids, *iv = ids + L.cap_i, *du = ids + 2 * L.cap_i, *dv = ids + 2 * L.cap_i + L.cap_d;
+    for (int q = 0; q < L.nseg; ++q) {
       if (b[q].n_ins) {
         std::memcpy(iu + ins_seg[q], b[q].ins_src, b[q].n_ins * 4);
         std::memcpy(iv + ins_seg[q], b[q].ins_dst, b[q].n_ins * 4);
@@ -665,88 +868,54 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
         std::memcpy(dv + del_seg[q], b[q].del_dst, b[q].n_del * 4);
       }
     }
-    B.iu = d_ids; B.iv = d_ids + ni; B.du = d_ids + 2 * ni; B.dv = d_ids + 2 * ni + ndl;
+    B.iu = d_ids; B.iv = d_ids + L.cap_i; B.du = d_ids + 2 * L.cap_i; B.dv = d_ids + 2 * L.cap_i + L.cap_d;
   }
-  HIPCHK(hipMemcpyAsync(G->bin.p, pin, bytes, hipMemcpyHostToDevice, s));
-
-  // scratch sizes (dirA <= 2 insertions, dirD and dirR <= 2 deletions)
-  const int64_t max_touched = std::max<int64_t>(2 * total, 1);
-  const int64_t union_bound = G->entries + 2 * ni;
-  G->keys.ensure(std::max<int64_t>(total, 1) * 8);
-  G->keys_alt.ensure(std::max<int64_t>(total, 1) * 8);
-  for (DevBuf* d : {&G->dirA, &G->dirA_alt}) d->ensure(std::max<int64_t>(2 * ni, 1) * 8);
-  for (DevBuf* d : {&G->dirD, &G->dirD_alt, &G->dirR, &G->dirR_alt}) d->ensure(std::max<int64_t>(2 * ndl, 1) * 8);
-  G->touched.ensure(max_touched * 4);
-  G->dest.ensure(max_touched * 8);
-  G->newcap.ensure(max_touched * 4);
-  G->tlen.ensure(max_touched * 4);
-  G->tpre.ensure((max_touched + 1) * 8);
-  G->scratch.ensure(std::max<int64_t>(union_bound, 1) * 4);
-  G->sort_tmp.ensure(radix_sort_tmp_bytes(std::max<int64_t>(total, 2 * std::max(ni, ndl))) + 64);
-  G->scan_tmp.ensure(scan_tmp_bytes(std::max<int64_t>(max_touched, G->N) + 1) + 64);
-
-  // arena reserve: enough for every touched row to move
-  const int64_t need = (int64_t)((1.0 + G->opt.slack) * (double)union_bound) + 8 * max_touched + 1024;
-  if (G->arena_cap - G->arena_top < need) compact(G, need);
-
-  zero_small(G);
-  if (timed) HIPCHK(hipEventRecord(G->ev[0], s));
-  PoolDev P = G->pd();
-  unsigned long long* bst = G->bstats.as<unsigned long long>();
-  unsigned long long* ctr = G->ctr.as<unsigned long long>();
-  launch_ingest_keys(P, B, G->bits, G->keys.as<unsigned long long>(), bst, s);
-  unsigned long long* sk = radix_sort_u64(G->keys.as<unsigned long long>(), G->keys_alt.as<unsigned long long>(),
-                                          G->sort_tmp.p, total, nullptr, 2 * G->bits + 3, s);
-  launch_ingest_classify(P, sk, total, G->bits, npass, nv, G->dirA.as<unsigned long long>(),
-                         G->dirD.as<unsigned long long>(), G->dirR.as<unsigned long long>(), ctr, bst, s);
-  if (dev) {
-    unsigned long long err = 0;
-    HIPCHK(hipMemcpyAsync(&err, bst + PB_IDX(0, PB_ERR), 8, hipMemcpyDeviceToHost, s));
-    G->sync();
-    if (err) raise(GC_EINVAL, "batch has %llu vertex ids outside the graph", err);
-  }
-  unsigned long long* sA = radix_sort_u64(G->dirA.as<unsigned long long>(), G->dirA_alt.as<unsigned long long>(),
-                                          G->sort_tmp.p, 2 * ni, ctr + C_DIRA, 2 * G->bits, s);
-  unsigned long long* sD = radix_sort_u64(G->dirD.as<unsigned long long>(), G->dirD_alt.as<unsigned long long>(),
-                                          G->sort_tmp.p, 2 * ndl, ctr + C_DIRD, 2 * G->bits, s);
-  unsigned long long* sR = radix_sort_u64(G->dirR.as<unsigned long long>(), G->dirR_alt.as<unsigned long long>(),
-                                          G->sort_tmp.p, 2 * ndl, ctr + C_DIRR, 2 * G->bits, s);
   BatchWork W = make_work(G);
-  W.dirA = sA;
-  W.dirD = sD;
-  W.dirR = sR;
-  launch_mark_rows(sA, 2 * ni, ctr, C_DIRA, G->bits, W.a_beg, W.na, W.mark, W.touched, W.tix, s);
-  launch_mark_rows(sD, 2 * ndl, ctr, C_DIRD, G->bits, nullptr, nullptr, W.mark, W.touched, W.tix, s);
-  launch_mark_rows(sR, 2 * ndl, ctr, C_DIRR, G->bits, W.r_beg, W.nr, W.mark, W.touched, W.tix, s);
-  launch_merge(P, W, max_touched, 2 * ni, G->bits, G->opt.slack, bst, G->scan_tmp.p, s);
-  launch_flag_rows(P, W, 2 * ndl, G->bits, bst, s);
+  W.dirA = radix_sort_result(G->dirA.as<unsigned long long>(), G->dirA_alt.as<unsigned long long>(), 2 * L.cap_i,
+                             2 * G->bits);
+  W.dirD = radix_sort_result(G->dirD.as<unsigned long long>(), G->dirD_alt.as<unsigned long long>(), 2 * L.cap_d,
+                             2 * G->bits);
+  W.dirR = radix_sort_result(G->dirR.as<unsigned long long>(), G->dirR_alt.as<unsigned long long>(), 2 * L.cap_d,
+                             2 * G->bits);
 
-  std::vector<unsigned long long> hc;
-  int radius = G->opt.radius == 0 ? -1 : G->opt.radius;
-  int64_t dense_min = 2048;
-  int tune_idx = -1;
-  const int decade = (int)std::min<double>(7.0, std::floor(std::log10((double)total + 1.0)));
-  if (G->opt.autotune) {
-    if (G->tune_next < (int)G->tune_cands.size()) {
-      tune_idx = G->tune_next;
-      dense_min = G->tune_cands[tune_idx];
-    } else {
-      dense_min = G->dense_min_best;
+  const bool use_graph = G->opt.graphs && !dev && !timed_run;
+  if (use_graph) {
+    const std::vector<uint64_t> sig = pass_signature(G, L, make_count_args(G, L.nv, L.dense_min));
+    auto it = G->graphs.find(sig);
+    if (it == G->graphs.end()) {
+      if (G->graphs.size() >= 32) G->drop_graphs();
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      hipGraph_t gr = nullptr;
+      try {
+        enqueue_pass(G, L, B, W, false);
+      } catch (...) {
+        (void)hipStreamEndCapture(s, &gr);
+        if (gr) (void)hipGraphDestroy(gr);
+        throw;
+      }
+      HIPCHK(hipStreamEndCapture(s, &gr));
+      hipGraphExec_t ex = nullptr;
+      const hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      if (e != hipSuccess) raise(GC_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+      it = G->graphs.emplace(sig, ex).first;
+      ++G->graph_captures;
     }
-    if (radius >= 2 && G->region_frac[decade] >= 0.9) radius = -1;  // exact radii only
+    HIPCHK(hipGraphLaunch(it->second, s));
+    ++G->graph_launches;
+  } else {
+    enqueue_pass(G, L, B, W, timed_run);
   }
-  const bool timed_run = timed || (G->opt.autotune && tune_idx >= 0);
-  run_count(G, nv, radius, G->state.as<long long>(), W, hc, union_bound, timed_run, dense_min);
-  launch_purge(P, W, max_touched, G->bits, 1u << (GC_VSHIFT + nv - 1), G->scan_tmp.p, s);
-  if (timed_run) HIPCHK(hipEventRecord(G->ev[8], s));
-
-  std::vector<unsigned long long> hb(BS_COUNT);
-  HIPCHK(hipMemcpyAsync(hb.data(), bst, BS_COUNT * 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&G->arena_top, G->top.p, 8, hipMemcpyDeviceToHost, s));
-  std::vector<long long> st((size_t)k * ST_STRIDE), vo((size_t)(nv - 1) * k * ST_STRIDE);
-  HIPCHK(hipMemcpyAsync(st.data(), G->state.p, st.size() * 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(vo.data(), G->vout.p, vo.size() * 8, hipMemcpyDeviceToHost, s));
   G->sync();
+  const int retries = settle_retries(G, L.nv, L.radius, G->state.as<long long>(), W, L.dense_min, L.union_bound,
+                                     true, L.max_touched);
+
+  const unsigned long long* hbp = G->out_bst();
+  const std::vector<unsigned long long> hb(hbp, hbp + BS_COUNT);
+  const std::vector<unsigned long long> hc(G->out_ctr(), G->out_ctr() + C_COUNT);
+  G->arena_top = (int64_t)*G->out_top();
+  std::vector<long long> st(G->out_state(), G->out_state() + (size_t)k * ST_STRIDE);
+  std::vector<long long> vo(G->out_vout(), G->out_vout() + (size_t)(L.nv - 1) * k * ST_STRIDE);
   long long cerr = 0;
   for (int g = 0; g < k; ++g) cerr += st[g * ST_STRIDE + ST_ERR];
   if (hb[BS_ARENA_OVF] || hb[BS_ERR] || cerr) {
@@ -756,7 +925,7 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
   }
   for (int g = 0; g < k; ++g) st[g * ST_STRIDE + ST_N] = G->gn[g];
   G->hstate = st;
-  for (int j = 0; j < npass; ++j)
+  for (int j = 0; j < L.npass; ++j)
     G->entries += 2 * ((int64_t)hb[PB_IDX(j, PB_EFF_INS)] - (int64_t)hb[PB_IDX(j, PB_EFF_DEL)]);
   // results: per graph of the pool, or per batch of the sequence
   const int nout = seq ? nb : k;
@@ -770,9 +939,9 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
     to_int64(I, counts ? counts[o] : tmp, &ovf[o]);
   }
   if (G->opt.autotune) {
-    if (radius > 0 && union_bound > 0)
+    if (L.radius > 0 && L.union_bound > 0)
       G->region_frac[decade] = (double)hc[C_ER] / (double)std::max<int64_t>(1, G->entries);
-    if (tune_idx >= 0) {
+    if (tune_idx >= 0 && retries == 0) {
       float c4ms = 0;
       (void)hipEventElapsedTime(&c4ms, G->ev[6], G->ev[7]);
       G->tune_ms.push_back(c4ms);
@@ -793,10 +962,10 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
       uint32_t mk = 0;
       if (seq) mk = ovf[q];
       else for (uint32_t m : ovf) mk |= m;
-      fill_stats(G, &stats[q], hb, hc, seq ? q : 0, npass, seq ? b[q].n_ins : ni, seq ? b[q].n_del : ndl, timed, ms,
-                 mk);
-      stats[q].c4_dense_min = dense_min;
-      stats[q].whole_graph = radius < 0;
+      fill_stats(G, &stats[q], hb, hc, seq ? q : 0, L.npass, seq ? b[q].n_ins : L.ni, seq ? b[q].n_del : L.ndl,
+                 timed && retries == 0, ms, mk);
+      stats[q].c4_dense_min = L.dense_min;
+      stats[q].whole_graph = L.radius < 0;
     }
   }
 }
@@ -828,6 +997,7 @@ int gc_options_default(gc_options* opt) {
   opt->device = 0;
   opt->stream = nullptr;
   opt->autotune = 1;
+  opt->graphs = 1;
   return GC_OK;
 }
 
@@ -936,11 +1106,13 @@ int gc_recount_exact(gc_graph* g, int32_t graph, int64_t hi[11], uint64_t lo[11]
     fill_u64((unsigned long long*)g->state_tmp.p, 0ull, (int64_t)g->k * ST_STRIDE, s);
     zero_small(g);
     BatchWork W = make_work(g);
-    std::vector<unsigned long long> hc;
-    run_count(g, 2, -1, g->state_tmp.as<long long>(), W, hc, g->entries, false);
+    size_count_scratch(g, 2, g->entries);
+    enqueue_count(g, 2, -1, g->state_tmp.as<long long>(), W, make_count_args(g, 2, 2048), false);
+    enqueue_readback(g, g->state_tmp.as<long long>());
+    g->sync();
+    settle_retries(g, 2, -1, g->state_tmp.as<long long>(), W, 2048, g->entries, false, 0);
     launch_all_flags(P, 0u, GC_ID, s);
-    std::vector<long long> st((size_t)g->k * ST_STRIDE);
-    HIPCHK(hipMemcpyAsync(st.data(), g->state_tmp.p, st.size() * 8, hipMemcpyDeviceToHost, s));
+    std::vector<long long> st(g->out_state(), g->out_state() + (size_t)g->k * ST_STRIDE);
     g->sync();
     if (st[graph * ST_STRIDE + ST_ERR]) raise(GC_EDEVICE, "inexact totals in the recount");
     i128 I[11];
@@ -995,6 +1167,14 @@ int gc_export_edges(gc_graph* g, int32_t graph, int32_t* src, int32_t* dst, int6
       HIPCHK(hipMemcpyAsync(dst, ed.as<int32_t>() + range[0], m * 4, hipMemcpyDeviceToHost, s));
     }
     g->sync();
+  });
+}
+
+int gc_graph_replays(const gc_graph* g, int64_t* captures, int64_t* launches) {
+  return guard([&] {
+    if (!g) raise(GC_EINVAL, "NULL argument");
+    if (captures) *captures = g->graph_captures;
+    if (launches) *launches = g->graph_launches;
   });
 }
 

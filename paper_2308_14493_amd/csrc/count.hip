@@ -533,7 +533,8 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int32_t lo_d
   TriL<NV> S;
   using TU = typename TriL<NV>::TU;
   if constexpr (CAP == 0) {
-    const int64_t cap = A.tri_cap;
+    // slot layout for capacity tri_cap (no slot is touched while tri_cap == 0)
+    const int64_t cap = A.tri_cap > 0 ? A.tri_cap : 1;
     const int64_t W = ((cap + 63) / 64) | 1;
     unsigned long long* base = A.tri_scratch + (int64_t)blockIdx.x * tri_slot_words64<NV>(cap);
     S.W = (int32_t)W;
@@ -566,6 +567,10 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int32_t lo_d
     const int64_t ub = R.roff[u] + R.rlow[u];
     const int32_t dp = (int32_t)(R.roff[u + 1] - ub);
     if (dp <= lo_dp || (CAP != 0 && dp > CAP)) continue;
+    if (CAP == 0 && dp > A.tri_cap) {  // scratch too small: the host counts again with more
+      if (threadIdx.x == 0) atomicAdd(&A.bstats[BS_RETRY], 1ull);
+      continue;
+    }
     const int g = A.gid[u];
     if (g != cur_g) {
       if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_K4, kacc);
@@ -980,6 +985,10 @@ __global__ __launch_bounds__(C4W_T) void k_c4_large(CountArgs A, unsigned long l
     const int32_t v = list[item];
     const int g = A.gid[v];
     if (g != cur_g) { if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_C4, acc); cur_g = g; }
+    if (R.rlow[v] > A.c4_maxlow) {  // cursor scratch too small: the host counts again with more
+      if (t == 0) atomicAdd(&A.bstats[BS_RETRY], 1ull);
+      continue;
+    }
     // c(v, w) <= nlow: 16-bit fields suffice up to 65535 lower neighbours
     const bool narrow = R.rlow[v] <= A.c4_narrow_max;
     if constexpr (NV == 2) {
@@ -1011,9 +1020,10 @@ __global__ void k_c4_order(const unsigned long long* sorted, const unsigned long
 // triangular relation between non-induced and induced counts (copies of
 // pattern X inside class Y).
 template <int NV>
-__global__ void k_combine(const unsigned long long* sig, long long* state, long long* vout, int32_t k) {
+__global__ void k_combine(const unsigned long long* sig, long long* state, long long* vout, int32_t k,
+                          const unsigned long long* bstats) {
   const int64_t g = gtid();
-  if (g >= k) return;
+  if (g >= k || bstats[BS_RETRY]) return;
   int64_t N[NV][6], T[NV], W[NV], D1[NV];
   int bad = 0;
   for (int x = 0; x < NV; ++x) {
@@ -1061,39 +1071,30 @@ inline unsigned cap_grid(int64_t want, unsigned cap) {
 }
 
 template <int NV>
-void launch_count_t(const CountArgs& A, const unsigned long long* hc, hipStream_t s, hipEvent_t* ev) {
-  const int64_t E = (int64_t)hc[C_ER];
+void launch_count_t(const CountArgs& A, hipStream_t s, hipEvent_t* ev) {
   constexpr int TLM = tl_max<NV>();
+  const int64_t N = A.N;
+  const unsigned long long* cnt_er = A.c + C_ER;
   if (ev) (void)hipEventRecord(ev[0], s);
-  fill_u64(A.R.t, 0ull, E, s);
-  if (NV == 4) fill_u64(A.R.tp, 0ull, 2 * E, s);
-  const int64_t nts = (int64_t)hc[C_LIST0 + L_TRI_S], ntl = (int64_t)hc[C_LIST0 + L_TRI_L];
-  if (nts) hipLaunchKernelGGL(k_tri_small<NV>, dim3(cap_grid((nts + 3) / 4, 8192)), dim3(256), 0, s, A);
-  if (ntl) {
-    hipLaunchKernelGGL((k_tri_large<TL_MID, 256, NV>), dim3(cap_grid(ntl, 4096)), dim3(256), 0, s, A, 64);
-    if ((int64_t)hc[C_MAXDP] > TL_MID)
-      hipLaunchKernelGGL((k_tri_large<TLM, 512, NV>), dim3(cap_grid(ntl, 1024)), dim3(512), 0, s, A, TL_MID);
-    if ((int64_t)hc[C_MAXDP] > TLM)
-      hipLaunchKernelGGL((k_tri_large<0, 256, NV>), dim3(cap_grid(ntl, (unsigned)A.tri_slots)), dim3(256), 0, s, A,
-                         TLM);
-  }
+  fill_u64_count(A.R.t, 0ull, cnt_er, 1, A.e_max, s);
+  if (NV == 4) fill_u64_count(A.R.tp, 0ull, cnt_er, 2, 2 * A.e_max, s);
+  hipLaunchKernelGGL(k_tri_small<NV>, dim3(cap_grid((N + 3) / 4, 8192)), dim3(256), 0, s, A);
+  hipLaunchKernelGGL((k_tri_large<TL_MID, 256, NV>), dim3(cap_grid(N, 4096)), dim3(256), 0, s, A, 64);
+  hipLaunchKernelGGL((k_tri_large<TLM, 512, NV>), dim3(cap_grid(N, 1024)), dim3(512), 0, s, A, TL_MID);
+  hipLaunchKernelGGL((k_tri_large<0, 256, NV>), dim3(cap_grid(N, (unsigned)A.tri_slots)), dim3(256), 0, s, A, TLM);
   if (ev) (void)hipEventRecord(ev[1], s);
-  if (E) hipLaunchKernelGGL(k_edge_pass<NV>, dim3(cap_grid((E + 255) / 256, 16384)), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_edge_pass<NV>, dim3(cap_grid((A.e_max + 255) / 256, 16384)), dim3(256), 0, s, A);
   if (ev) (void)hipEventRecord(ev[2], s);
-  const int64_t ncs = (int64_t)hc[C_LIST0 + L_C4_S], ncm = (int64_t)hc[C_LIST0 + L_C4_M],
-                ncl = (int64_t)hc[C_LIST0 + L_C4_L];
-  if (ncs) hipLaunchKernelGGL(k_c4_small<NV>, dim3(cap_grid((ncs + 3) / 4, 8192)), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_c4_small<NV>, dim3(cap_grid((N + 3) / 4, 8192)), dim3(256), 0, s, A);
   if (ev) (void)hipEventRecord(ev[3], s);
-  if (ncm) hipLaunchKernelGGL(k_c4_mid<NV>, dim3(cap_grid(ncm, 4096)), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_c4_mid<NV>, dim3(cap_grid(N, 4096)), dim3(256), 0, s, A);
   if (ev) (void)hipEventRecord(ev[4], s);
-  if (ncl) {
-    // order the hubs by decreasing wedge work (keys written by the per-vertex pass)
-    unsigned long long* sk = radix_sort_u64(A.c4_keys, A.c4_keys_alt, A.sort_tmp, ncl, A.c + C_LIST0 + L_C4_L, 64, s);
-    hipLaunchKernelGGL(k_c4_order, dim3(cap_grid((ncl + 255) / 256, 1024)), dim3(256), 0, s, sk, A.c,
-                       (int32_t*)(A.lists + L_C4_L * A.list_stride));
-    hipLaunchKernelGGL(k_c4_large<NV>, dim3(cap_grid(ncl, (unsigned)A.slots)), dim3(C4W_T), 0, s, A,
-                       (unsigned long long*)(A.c + C_QHEAD));
-  }
+  // order the hubs by decreasing wedge work (keys written by the per-vertex pass)
+  unsigned long long* sk = radix_sort_u64(A.c4_keys, A.c4_keys_alt, A.sort_tmp, N, A.c + C_LIST0 + L_C4_L, 64, s);
+  hipLaunchKernelGGL(k_c4_order, dim3(cap_grid((N + 255) / 256, 1024)), dim3(256), 0, s, sk, A.c,
+                     (int32_t*)(A.lists + L_C4_L * A.list_stride));
+  hipLaunchKernelGGL(k_c4_large<NV>, dim3(cap_grid(N, (unsigned)A.slots)), dim3(C4W_T), 0, s, A,
+                     (unsigned long long*)(A.c + C_QHEAD));
   if (ev) (void)hipEventRecord(ev[5], s);
 }
 
@@ -1105,13 +1106,13 @@ int64_t tri_scratch_words64(int nv, int64_t cap) {
 }
 int32_t tri_lds_max(int nv) { return nv == 2 ? tl_max<2>() : tl_max<4>(); }
 
-void launch_count(int nv, const CountArgs& A, const unsigned long long* hc, hipStream_t s, hipEvent_t* ev) {
-  if (nv == 2) launch_count_t<2>(A, hc, s, ev);
-  else launch_count_t<4>(A, hc, s, ev);
+void launch_count(int nv, const CountArgs& A, hipStream_t s, hipEvent_t* ev) {
+  if (nv == 2) launch_count_t<2>(A, s, ev);
+  else launch_count_t<4>(A, s, ev);
 }
 
 void launch_combine(int nv, const unsigned long long* sig, long long* state, long long* vout, int32_t k,
-                    hipStream_t s) {
-  if (nv == 2) hipLaunchKernelGGL(k_combine<2>, dim3((k + 63) / 64), dim3(64), 0, s, sig, state, vout, k);
-  else hipLaunchKernelGGL(k_combine<4>, dim3((k + 63) / 64), dim3(64), 0, s, sig, state, vout, k);
+                    const unsigned long long* bstats, hipStream_t s) {
+  if (nv == 2) hipLaunchKernelGGL(k_combine<2>, dim3((k + 63) / 64), dim3(64), 0, s, sig, state, vout, k, bstats);
+  else hipLaunchKernelGGL(k_combine<4>, dim3((k + 63) / 64), dim3(64), 0, s, sig, state, vout, k, bstats);
 }

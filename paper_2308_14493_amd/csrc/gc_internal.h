@@ -59,9 +59,12 @@ enum { ST_F0 = 0, ST_T = 6, ST_W = 7, ST_M = 8, ST_N = 9, ST_ERR = 10, ST_STRIDE
 // per batch of the pass (ingest), then the pass-wide counters.
 enum { PB_LOOPS = 0, PB_DUPS, PB_CANCEL, PB_INS_EXIST, PB_DEL_MISS, PB_EFF_INS, PB_EFF_DEL, PB_ERR, PB_N };
 #define PB_IDX(j, k) ((j) * PB_N + (k))
+// Counting-stage counters run from BS_COUNT_STAGE to BS_COUNT.  BS_RETRY: a
+// kernel met a vertex larger than its scratch; combine and purge then change
+// nothing and the host runs the counting stage again with more scratch.
 enum {
-  BS_TOUCHED = GC_SEQ_MAX * PB_N, BS_REGION_V, BS_REGION_E, BS_ERR, BS_ARENA_OVF, BS_MAXDPLUS, BS_TRI_S,
-  BS_TRI_L, BS_C4_S, BS_C4_M, BS_C4_L, BS_F1, BS_NR, BS_WEDGES, BS_TRIPROBE, BS_COUNT
+  BS_TOUCHED = GC_SEQ_MAX * PB_N, BS_ERR, BS_ARENA_OVF,
+  BS_COUNT_STAGE, BS_C4_S = BS_COUNT_STAGE, BS_C4_M, BS_C4_L, BS_WEDGES, BS_TRIPROBE, BS_RETRY, BS_COUNT
 };
 
 struct PoolDev {
@@ -166,6 +169,8 @@ size_t radix_sort_tmp_bytes(int64_t max_count);
 unsigned long long* radix_sort_u64(unsigned long long* keys, unsigned long long* alt,
                                    void* tmp, int64_t max_count, const unsigned long long* d_count,
                                    int bits, hipStream_t s);
+// The buffer radix_sort_u64 leaves its result in (known before it runs).
+unsigned long long* radix_sort_result(unsigned long long* keys, unsigned long long* alt, int64_t max_count, int bits);
 size_t scan_tmp_bytes(int64_t n);
 // out[i] = sum_{j<i} in[j] for i in [0, n]; out has n + 1 entries.
 void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t s);
@@ -174,3 +179,6 @@ void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* tmp, h
 // fill helpers (kernels, capturable)
 void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);
+// p[i] = v for i < min(mult * (*count), max_n), count on the device
+void fill_u64_count(unsigned long long* p, unsigned long long v, const unsigned long long* count, int64_t mult,
+                    int64_t max_n, hipStream_t s);

@@ -8,7 +8,8 @@ enum {
   C_DIRD,         // directed entries of existing edges absent from a later version
   C_DIRR,         // directed entries absent from the last version (removed by the purge)
   C_TOUCH,        // rows touched by the pass
-  C_RLIST,        // region vertices
+  C_NKEYS,        // update entries of the pass (set by the ingest kernel)
+  C_RLIST,        // region vertices (first counter of the counting stage)
   C_LVL0,         // C_LVL0 + k: end of level-k vertices in the region list (k = 0..4)
   C_ER = C_LVL0 + 6,  // region entries
   C_MAXDP,        // max oriented out-degree
@@ -51,11 +52,14 @@ struct BatchWork {
 };
 
 // graph.hip
-void launch_ingest_keys(const PoolDev& P, const BatchIn& B, int bits, unsigned long long* keys,
-                        unsigned long long* bstats, hipStream_t s);
-// keys: pair << 3 | batch << 1 | op; nb batches in the pass, nv versions
-void launch_ingest_classify(const PoolDev& P, const unsigned long long* keys, int64_t total, int bits, int nb, int nv,
-                            unsigned long long* dirA, unsigned long long* dirD, unsigned long long* dirR,
+// The update counts live on the device (ins_seg[k], del_seg[k]); cap_total
+// bounds their sum and sizes the grid.  Sets c[C_NKEYS].
+void launch_ingest_keys(const PoolDev& P, const BatchIn& B, int bits, unsigned long long* keys, unsigned long long* c,
+                        unsigned long long* bstats, int64_t cap_total, hipStream_t s);
+// keys: pair << 3 | batch << 1 | op (c[C_NKEYS] of them); nb batches in the
+// pass, nv versions
+void launch_ingest_classify(const PoolDev& P, const unsigned long long* keys, int64_t cap_total, int bits, int nb,
+                            int nv, unsigned long long* dirA, unsigned long long* dirD, unsigned long long* dirR,
                             unsigned long long* c, unsigned long long* bstats, hipStream_t s);
 // beg/cnt may be null (rows are then only marked as touched)
 void launch_mark_rows(const unsigned long long* dir, int64_t max_n, unsigned long long* c, int which, int bits,
@@ -64,9 +68,10 @@ void launch_merge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int
                   unsigned long long* bstats, void* scan_tmp, hipStream_t s);
 void launch_flag_rows(const PoolDev& P, const BatchWork& W, int64_t max_dirD, int bits, unsigned long long* bstats,
                       hipStream_t s);
-// removes the entries carrying `fin` (absent from the last version), clears all flags
-void launch_purge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int bits, uint32_t fin, void* scan_tmp,
-                  hipStream_t s);
+// removes the entries carrying `fin` (absent from the last version), clears
+// all flags; does nothing while *skip != 0
+void launch_purge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int bits, uint32_t fin,
+                  const unsigned long long* skip, void* scan_tmp, hipStream_t s);
 void launch_region(const PoolDev& P, const BatchWork& W, int radius, int32_t* level, int32_t* rlist, int32_t* rlen,
                    hipStream_t s);
 void launch_region_fill(const PoolDev& P, const RegionDev& R, const BatchWork& W, int radius, const int32_t* level,
@@ -116,18 +121,21 @@ struct CountArgs {
   void* sort_tmp;
   int32_t tri_slots;              // workgroups of the global-scratch triangle tier
   unsigned long long* tri_scratch;  // [tri_slots][tri_scratch_words64(tri_cap)] above the LDS tier
-  int64_t tri_cap;                  // out-degree capacity of a scratch slot
+  int64_t tri_cap;                  // out-degree capacity of a scratch slot (0: no scratch)
+  int64_t e_max;                    // capacity of the region arrays (entries)
 };
-// nv = 2 or 4 versions
-void launch_count(int nv, const CountArgs& A, const unsigned long long* host_counts, hipStream_t s,
+// nv = 2 or 4 versions.  Grids come from host bounds (A.N, A.e_max, the
+// scratch sizes); work sizes from the device counters.
+void launch_count(int nv, const CountArgs& A, hipStream_t s,
                   hipEvent_t* ev /* nullable: 6 events between the kernel phases */);
 int64_t tri_scratch_words64(int nv, int64_t cap);  // u64 words of one triangle scratch slot
 int32_t tri_lds_max(int nv);                        // largest out-degree of the LDS triangle tiers
 int32_t c4_window_max();                            // u64 words of the LDS window of the large 4-cycle tier
 // Per graph g: the state after version x (x = 1 .. nv-1) goes to
 // vout[((x - 1) * k + g) * ST_STRIDE ...]; state becomes the one of version nv-1.
+// nothing is written while bstats[BS_RETRY] != 0
 void launch_combine(int nv, const unsigned long long* sig, long long* state, long long* vout, int32_t k,
-                    hipStream_t s);
+                    const unsigned long long* bstats, hipStream_t s);
 
 // capi.cpp: thread-local error text read by gc_last_error()
 void gc_set_error(const char* msg);

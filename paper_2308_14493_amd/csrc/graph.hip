@@ -32,12 +32,14 @@ __device__ __forceinline__ bool edge_exists(const PoolDev& P, uint32_t a, uint32
 
 // ------------------------------------------------------------- ingest
 __global__ void k_ingest_keys(PoolDev P, BatchIn B, int bits, unsigned long long* __restrict__ keys,
-                              unsigned long long* __restrict__ bstats) {
-  const int64_t total = B.n_ins + B.n_del;
+                              unsigned long long* __restrict__ cc, unsigned long long* __restrict__ bstats) {
+  const int64_t n_ins = B.ins_seg[B.k], n_del = B.del_seg[B.k];
+  const int64_t total = n_ins + n_del;
+  if (gtid() == 0) cc[C_NKEYS] = (unsigned long long)total;
   const uint64_t idmask = (1ull << bits) - 1ull;
   for (int64_t i = gtid(); i < total; i += gstride()) {
-    const bool del = i >= B.n_ins;
-    const int64_t j = del ? i - B.n_ins : i;
+    const bool del = i >= n_ins;
+    const int64_t j = del ? i - n_ins : i;
     int32_t u = del ? B.du[j] : B.iu[j];
     int32_t v = del ? B.dv[j] : B.iv[j];
     // segment of this entry: a graph of the pool, or a batch of graph 0
@@ -71,10 +73,11 @@ __global__ void k_ingest_keys(PoolDev P, BatchIn B, int bits, unsigned long long
 // mask is neither empty nor full change: existing edges go to dirD (flags),
 // the others to dirA (new entries), and those absent from the last version
 // also to dirR (removed by the purge).
-__global__ void k_ingest_classify(PoolDev P, const unsigned long long* __restrict__ keys, int64_t total, int bits,
-                                  int nb, int nv, unsigned long long* __restrict__ dirA,
-                                  unsigned long long* __restrict__ dirD, unsigned long long* __restrict__ dirR,
-                                  unsigned long long* __restrict__ c, unsigned long long* __restrict__ bstats) {
+__global__ void k_ingest_classify(PoolDev P, const unsigned long long* __restrict__ keys, int bits, int nb, int nv,
+                                  unsigned long long* __restrict__ dirA, unsigned long long* __restrict__ dirD,
+                                  unsigned long long* __restrict__ dirR, unsigned long long* __restrict__ c,
+                                  unsigned long long* __restrict__ bstats) {
+  const int64_t total = ctr(c, C_NKEYS);
   const uint64_t idmask = (1ull << bits) - 1ull;
   for (int64_t i = gtid(); i < total; i += gstride()) {
     const unsigned long long key = keys[i];
@@ -178,9 +181,12 @@ __global__ void k_plan_rows(PoolDev P, const int32_t* __restrict__ touched, cons
   }
 }
 
-// Flat copy of the touched rows into scratch (positions from tpre).
+// Flat copy of the touched rows into scratch (positions from tpre); skipped
+// while *skip != 0 (skip may be null).
 __global__ void k_copy_rows(PoolDev P, const int32_t* __restrict__ touched, const unsigned long long* c,
-                            const int64_t* __restrict__ tpre, uint32_t* __restrict__ scratch) {
+                            const int64_t* __restrict__ tpre, uint32_t* __restrict__ scratch,
+                            const unsigned long long* skip) {
+  if (skip && *skip) return;
   const int64_t nt = ctr(c, C_TOUCH);
   if (nt == 0) return;
   const int64_t total = tpre[nt];
@@ -272,7 +278,8 @@ __global__ void k_flag_rows(PoolDev P, const unsigned long long* c, const unsign
 // the touched rows (from a scratch copy of the union rows); reset the per-row
 // batch arrays.
 __global__ void k_touched_len(PoolDev P, const int32_t* __restrict__ touched, const unsigned long long* c,
-                              int64_t max_touched, int32_t* __restrict__ tlen) {
+                              int64_t max_touched, int32_t* __restrict__ tlen, const unsigned long long* skip) {
+  if (*skip) return;
   const int64_t nt = ctr(c, C_TOUCH);
   for (int64_t i = gtid(); i < max_touched; i += gstride()) tlen[i] = i < nt ? P.len[touched[i]] : 0;
 }
@@ -280,7 +287,9 @@ __global__ void k_touched_len(PoolDev P, const int32_t* __restrict__ touched, co
 __global__ void k_purge_rows(PoolDev P, const int32_t* __restrict__ touched, const unsigned long long* c,
                              const int64_t* __restrict__ tpre, const uint32_t* __restrict__ scratch,
                              const unsigned long long* __restrict__ dirR, int bits, uint32_t fin,
-                             const int32_t* __restrict__ r_beg, const int32_t* __restrict__ nr) {
+                             const int32_t* __restrict__ r_beg, const int32_t* __restrict__ nr,
+                             const unsigned long long* skip) {
+  if (*skip) return;
   const int64_t nt = ctr(c, C_TOUCH);
   if (nt == 0) return;
   const int64_t total = tpre[nt];
@@ -305,7 +314,9 @@ __global__ void k_purge_rows(PoolDev P, const int32_t* __restrict__ touched, con
 
 __global__ void k_purge_commit(PoolDev P, const int32_t* __restrict__ touched, const unsigned long long* c,
                                int32_t* __restrict__ a_beg, int32_t* __restrict__ na, int32_t* __restrict__ r_beg,
-                               int32_t* __restrict__ nr, int32_t* __restrict__ mark, int32_t* __restrict__ tix) {
+                               int32_t* __restrict__ nr, int32_t* __restrict__ mark, int32_t* __restrict__ tix,
+                               const unsigned long long* skip) {
+  if (*skip) return;
   const int64_t nt = ctr(c, C_TOUCH);
   for (int64_t i = gtid(); i < nt; i += gstride()) {
     const int32_t r = touched[i];
@@ -675,18 +686,16 @@ inline unsigned grid_for(int64_t n, int per = TPB, unsigned cap = 65535u * 4) {
 }  // namespace
 
 // ================================================================ launchers
-void launch_ingest_keys(const PoolDev& P, const BatchIn& B, int bits, unsigned long long* keys,
-                        unsigned long long* bstats, hipStream_t s) {
-  int64_t n = B.n_ins + B.n_del;
-  if (n == 0) return;
-  hipLaunchKernelGGL(k_ingest_keys, dim3(grid_for(n)), dim3(TPB), 0, s, P, B, bits, keys, bstats);
+void launch_ingest_keys(const PoolDev& P, const BatchIn& B, int bits, unsigned long long* keys, unsigned long long* c,
+                        unsigned long long* bstats, int64_t cap_total, hipStream_t s) {
+  hipLaunchKernelGGL(k_ingest_keys, dim3(grid_for(cap_total)), dim3(TPB), 0, s, P, B, bits, keys, c, bstats);
 }
 
-void launch_ingest_classify(const PoolDev& P, const unsigned long long* keys, int64_t total, int bits, int nb, int nv,
-                            unsigned long long* dirA, unsigned long long* dirD, unsigned long long* dirR,
+void launch_ingest_classify(const PoolDev& P, const unsigned long long* keys, int64_t cap_total, int bits, int nb,
+                            int nv, unsigned long long* dirA, unsigned long long* dirD, unsigned long long* dirR,
                             unsigned long long* c, unsigned long long* bstats, hipStream_t s) {
-  if (total == 0) return;
-  hipLaunchKernelGGL(k_ingest_classify, dim3(grid_for(total)), dim3(TPB), 0, s, P, keys, total, bits, nb, nv, dirA,
+  if (cap_total == 0) return;
+  hipLaunchKernelGGL(k_ingest_classify, dim3(grid_for(cap_total)), dim3(TPB), 0, s, P, keys, bits, nb, nv, dirA,
                      dirD, dirR, c, bstats);
 }
 
@@ -704,7 +713,8 @@ void launch_merge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int
                      W.na, slack, W.dest, W.newcap, W.tlen, bstats);
   exclusive_scan_i32_to_i64(W.tlen, W.tpre, max_touched, scan_tmp, s);
   const unsigned g = 4096;
-  hipLaunchKernelGGL(k_copy_rows, dim3(g), dim3(TPB), 0, s, P, W.touched, W.c, W.tpre, W.scratch);
+  hipLaunchKernelGGL(k_copy_rows, dim3(g), dim3(TPB), 0, s, P, W.touched, W.c, W.tpre, W.scratch,
+                     (const unsigned long long*)nullptr);
   hipLaunchKernelGGL(k_merge_old, dim3(g), dim3(TPB), 0, s, P, W.touched, W.c, W.tpre, W.scratch, W.dirA, bits,
                      W.a_beg, W.na, W.dest);
   if (max_dirA)
@@ -720,18 +730,19 @@ void launch_flag_rows(const PoolDev& P, const BatchWork& W, int64_t max_dirD, in
   hipLaunchKernelGGL(k_flag_rows, dim3(grid_for(max_dirD)), dim3(TPB), 0, s, P, W.c, W.dirD, bits, bstats);
 }
 
-void launch_purge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int bits, uint32_t fin, void* scan_tmp,
-                  hipStream_t s) {
+void launch_purge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int bits, uint32_t fin,
+                  const unsigned long long* skip, void* scan_tmp, hipStream_t s) {
   if (max_touched == 0) return;
-  // lengths of the union rows, then a copy, then the compaction
+  // lengths of the union rows, then a copy, then the compaction (the scan of
+  // stale lengths under skip is harmless: nothing reads it)
   hipLaunchKernelGGL(k_touched_len, dim3(grid_for(max_touched)), dim3(TPB), 0, s, P, W.touched, W.c, max_touched,
-                     W.tlen);
+                     W.tlen, skip);
   exclusive_scan_i32_to_i64(W.tlen, W.tpre, max_touched, scan_tmp, s);
-  hipLaunchKernelGGL(k_copy_rows, dim3(4096), dim3(TPB), 0, s, P, W.touched, W.c, W.tpre, W.scratch);
+  hipLaunchKernelGGL(k_copy_rows, dim3(4096), dim3(TPB), 0, s, P, W.touched, W.c, W.tpre, W.scratch, skip);
   hipLaunchKernelGGL(k_purge_rows, dim3(4096), dim3(TPB), 0, s, P, W.touched, W.c, W.tpre, W.scratch, W.dirR, bits,
-                     fin, W.r_beg, W.nr);
+                     fin, W.r_beg, W.nr, skip);
   hipLaunchKernelGGL(k_purge_commit, dim3(grid_for(max_touched)), dim3(TPB), 0, s, P, W.touched, W.c, W.a_beg, W.na,
-                     W.r_beg, W.nr, W.mark, W.tix);
+                     W.r_beg, W.nr, W.mark, W.tix, skip);
 }
 
 void launch_region(const PoolDev& P, const BatchWork& W, int radius, int32_t* level, int32_t* rlist, int32_t* rlen,

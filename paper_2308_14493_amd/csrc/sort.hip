@@ -212,6 +212,16 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
     p[i] = v;
 }
 
+// p[i] = v for i < min(mult * (*count), max_n): a fill whose size is known
+// only to earlier kernels
+__global__ void k_fill_u64_count(unsigned long long* p, unsigned long long v, const unsigned long long* count,
+                                 int64_t mult, int64_t max_n) {
+  int64_t n = (int64_t)*count * mult;
+  if (n > max_n) n = max_n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 inline int64_t rs_nblk(int64_t max_count) { return (max_count + RS_TILE - 1) / RS_TILE; }
 
 template <class TIn>
@@ -255,6 +265,12 @@ unsigned long long* radix_sort_u64(unsigned long long* keys, unsigned long long*
   return src;
 }
 
+unsigned long long* radix_sort_result(unsigned long long* keys, unsigned long long* alt, int64_t max_count, int bits) {
+  if (max_count <= 0 || bits <= 0) return keys;
+  const int passes = (bits + 7) / 8;
+  return passes % 2 == 0 ? keys : alt;
+}
+
 size_t scan_tmp_bytes(int64_t n) { return (size_t)((n + SC_TILE - 1) / SC_TILE + 2) * sizeof(int64_t); }
 
 void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t s) {
@@ -275,4 +291,11 @@ void fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_
   int64_t g = (n + 255) / 256;
   if (g > 8192) g = 8192;
   hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)g), dim3(256), 0, s, p, v, n);
+}
+void fill_u64_count(unsigned long long* p, unsigned long long v, const unsigned long long* count, int64_t mult,
+                    int64_t max_n, hipStream_t s) {
+  if (max_n <= 0) return;
+  int64_t g = (max_n + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_fill_u64_count, dim3((unsigned)g), dim3(256), 0, s, p, v, count, mult, max_n);
 }

@@ -24,7 +24,8 @@ _P = ctypes.c_void_p
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("radius", _I32), ("slack", ctypes.c_float), ("device", _I32), ("stream", _P), ("autotune", _I32)]
+    _fields_ = [("radius", _I32), ("slack", ctypes.c_float), ("device", _I32), ("stream", _P), ("autotune", _I32),
+                ("graphs", _I32)]
 
 
 class BatchStats(ctypes.Structure):
@@ -57,7 +58,7 @@ _lib = None
 
 EXPORTS = ["gc_options_default", "gc_graph_init", "gc_pool_init", "gc_apply_batch", "gc_apply_batch_dev",
            "gc_apply_batches", "gc_apply_batch_seq", "gc_get_counts", "gc_get_counts_exact", "gc_recount_exact", "gc_graph_info",
-           "gc_export_edges", "gc_graph_free", "gc_strerror", "gc_last_error",
+           "gc_export_edges", "gc_graph_replays", "gc_graph_free", "gc_strerror", "gc_last_error",
            "gc_server_opts_default", "gc_server_create", "gc_server_add_graph", "gc_server_submit",
            "gc_server_wait", "gc_server_counts", "gc_server_destroy"]
 
@@ -94,6 +95,7 @@ def load(path: str = LIB_PATH):
     lib.gc_recount_exact.argtypes = [_P, _I32, _P, _P]
     lib.gc_graph_info.argtypes = [_P, ctypes.POINTER(_I32), _I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]
     lib.gc_export_edges.argtypes = [_P, _I32, _P, _P, _I64, ctypes.POINTER(_I64)]
+    lib.gc_graph_replays.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]
     lib.gc_graph_free.argtypes = [_P]
     lib.gc_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
     lib.gc_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)]
@@ -125,12 +127,14 @@ def _join(hi, lo):
     return [(int(h) << 64) | int(l) for h, l in zip(hi.tolist(), lo.tolist())]
 
 
-def _opts(radius, slack, device, stream, autotune=None):
+def _opts(radius, slack, device, stream, autotune=None, graphs=None):
     lib = load()
     o = Options()
     lib.gc_options_default(ctypes.byref(o))
     if autotune is not None:
         o.autotune = int(autotune)
+    if graphs is not None:
+        o.graphs = int(graphs)
     if radius is not None:
         o.radius = radius
     if slack is not None:
@@ -144,10 +148,10 @@ class Graph:
     """A resident graph (or a pool of graphs) on one GPU."""
 
     def __init__(self, n, src=(), dst=(), radius=None, slack=None, device=0, stream=None, autotune=None,
-                 _pool=None):
+                 graphs=None, _pool=None):
         lib = load()
         self._h = _P()
-        opt = _opts(radius, slack, device, stream, autotune)
+        opt = _opts(radius, slack, device, stream, autotune, graphs)
         if _pool is None:
             s, d = _i32(src), _i32(dst)
             assert s.shape == d.shape
@@ -252,6 +256,13 @@ class Graph:
                                       ctypes.cast(sts, _P) if stats else None))
         rows = [[int(x) for x in out[j]] for j in range(nb)]
         return (rows, [sts[j].as_dict() for j in range(nb)]) if stats else rows
+
+    def graph_replays(self):
+        """(passes captured as HIP graphs, passes launched from captured graphs)."""
+        lib = load()
+        c, n = _I64(), _I64()
+        _check(lib.gc_graph_replays(self._h, ctypes.byref(c), ctypes.byref(n)))
+        return c.value, n.value
 
     def counts(self, graph=0):
         """Exact counts (Python ints) of graph `graph`."""

@@ -22,7 +22,9 @@
 //
 // Tiers (work lists built by the per-vertex pass):
 //   tri  S: out-degree <= 64, one wave per vertex, bit matrices in LDS
-//   tri  L: larger out-degree, one workgroup per vertex, LDS hash
+//   tri  L: larger out-degree, one workgroup per vertex, LDS hash; tiers of
+//           out-degree <= 128, 256, 512, 1024 (960 with four versions), and
+//           global-memory scratch above
 //   c4   S / M: wedge bound <= 256 / <= 4096, LDS hash per wave / workgroup
 //   c4   L: one workgroup per vertex, windows of dense counters in LDS,
 //           then dense counters in global memory
@@ -80,6 +82,49 @@ __device__ __forceinline__ int seg_of(int32_t excl, int32_t idx) {
     if (e <= idx) lo = mid; else hi = mid;
   }
   return lo;
+}
+
+__device__ __forceinline__ int32_t rdl32(int32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+__device__ __forceinline__ int64_t rdl64(int64_t v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), lane);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Walk the lists of a wave's lanes (lane l: positions [sb, sb + sl), with a
+// 32-bit payload pl) calling f(list lane, position, payload of that lane).
+// Lists of at least WALK_LONG entries go one at a time through the whole
+// wave (consecutive lanes read consecutive entries; the list's lane is read
+// with scalar reads); the others are flattened over the lanes with a segment
+// search per step.  Most entries sit in long lists, which then cost no
+// cross-lane traffic.  All lanes must call it.
+constexpr int32_t WALK_LONG = 32;
+
+template <class F>
+__device__ __forceinline__ void wave_walk(int64_t sb, int32_t sl, uint32_t pl, F f) {
+  const int l = lane_id();
+  const bool lng = sl >= WALK_LONG;
+  uint64_t lm = __ballot(lng);
+  while (lm) {
+    const int s = __builtin_ctzll(lm);
+    lm &= lm - 1;
+    const int64_t b = rdl64(sb, s);
+    const int32_t n = rdl32(sl, s);
+    const uint32_t ps = (uint32_t)rdl32((int32_t)pl, s);
+    for (int32_t k = l; k < n; k += 64) f(s, b + k, ps);
+  }
+  const int32_t ss = lng ? 0 : sl;
+  const int32_t incl = wave_incl_scan32(ss);
+  const int32_t tot = __shfl(incl, 63);
+  const int32_t excl = incl - ss;
+  for (int32_t base = 0; base < tot; base += 64) {
+    const int32_t idx = base + l;
+    const int s = seg_of(excl, idx);
+    const int64_t sbs = __shfl(sb, s);
+    const int32_t exs = __shfl(excl, s);
+    const uint32_t ps = (uint32_t)__shfl((int32_t)pl, s);
+    if (idx < tot) f(s, sbs + (idx - exs), ps);
+  }
 }
 
 __device__ __forceinline__ unsigned long long pack2(uint32_t b, uint32_t a) {
@@ -221,34 +266,24 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
     int64_t sb = 0;
     int32_t sl = 0;
     if (l < dp) { sb = R.roff[vi] + R.rlow[vi]; sl = (int32_t)(R.roff[vi + 1] - sb); }
-    const int32_t incl = wave_incl_scan32(sl);
-    const int32_t total = __shfl(incl, 63);
-    const int32_t excl = incl - sl;
-    for (int32_t base = 0; base < total; base += 64) {
-      const int32_t idx = base + l;
-      const int i = seg_of(excl, idx);
-      const int64_t sbi = __shfl(sb, i);
-      const int32_t exi = __shfl(excl, i);
-      if (idx < total) {
-        const int64_t pos = sbi + (idx - exi);
-        const uint32_t y = R.rcol[pos];
-        const int j = lookup_slot(hkey[w], hval[w], 127u, 25, y & GC_ID);
-        if (j >= 0) {
-          const uint32_t fy = y & GC_FLAGS;
-          const unsigned long long bj = 1ull << j, bi = 1ull << i;
-          atomicOr(&EU[w][i], bj);
-          atomicOr(&TU[w][j], bi);
-          if (fy) {
-            dirty[w] = 1u;
+    wave_walk(sb, sl, fi, [&](int i, int64_t pos, uint32_t fs) {
+      const uint32_t y = R.rcol[pos];
+      const int j = lookup_slot(hkey[w], hval[w], 127u, 25, y & GC_ID);
+      if (j >= 0) {
+        const uint32_t fy = y & GC_FLAGS;
+        const unsigned long long bj = 1ull << j, bi = 1ull << i;
+        atomicOr(&EU[w][i], bj);
+        atomicOr(&TU[w][j], bi);
+        if (fy) {
+          dirty[w] = 1u;
 #pragma unroll
-            for (int x = 0; x < NV; ++x)
-              if (absent_in(fy, x)) { atomicOr(&EX[w][x][i], bj); atomicOr(&TX[w][x][j], bi); }
-          }
-          const uint32_t pm = vpresent<NV>(fsl[w][i] | fsl[w][j] | fy);
-          if (pm) t_add<NV>(R, pos, pm);
+          for (int x = 0; x < NV; ++x)
+            if (absent_in(fy, x)) { atomicOr(&EX[w][x][i], bj); atomicOr(&TX[w][x][j], bi); }
         }
+        const uint32_t pm = vpresent<NV>(fs | fsl[w][j] | fy);
+        if (pm) t_add<NV>(R, pos, pm);
       }
-    }
+    });
     wave_sync();
     const bool clean = __ballot(l < dp && fi != 0) == 0ull && dirty[w] == 0u;
     uint64_t Px[NV];
@@ -340,26 +375,16 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL<N
     sb = R.roff[v] + R.rlow[v];
     sl = (int32_t)(R.roff[v + 1] - sb);
   }
-  const int32_t incl = wave_incl_scan32(sl);
-  const int32_t tot = __shfl(incl, 63);
-  const int32_t excl = incl - sl;
-  for (int32_t base = 0; base < tot; base += 64) {
-    const int32_t idx = base + l;
-    const int s = seg_of(excl, idx);
-    const int64_t sbs = __shfl(sb, s);
-    const int32_t exs = __shfl(excl, s);
-    const uint32_t fs = __shfl(fi, s);
-    if (idx >= tot) continue;
+  wave_walk(sb, sl, fi, [&](int s, int64_t pos, uint32_t fs) {
     const int32_t i = g0 + s;
-    const int64_t pos = sbs + (idx - exs);
     const uint32_t y = R.rcol[pos];
     const int j = lookup_slot(S.hkey, S.hval, hmask, shift, y & GC_ID);
-    if (j < 0) continue;
+    if (j < 0) return;
     unsigned long long* Ei = S.E + (int64_t)i * S.W;
     const uint32_t fy = y & GC_FLAGS;
     if (only) {
       if (!absent_in(fy, only - 1)) atomicOr(&Ei[j >> 6], 1ull << (j & 63));
-      continue;
+      return;
     }
     atomicOr(&Ei[j >> 6], 1ull << (j & 63));
     if (fy) {
@@ -374,7 +399,7 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL<N
       atomicAdd(&S.tuc[j], add);
       atomicAdd(&S.tuc[i], add);
     }
-  }
+  });
 }
 
 // sum over i in mask, j in E[i] & mask of |E[i] & E[j] & mask|  (one wave's rows)
@@ -582,7 +607,6 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int32_t lo_d
   if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_K4, kacc);
 }
 
-constexpr int TL_MID = 256;
 template <int NV> constexpr int tl_max() { return NV == 2 ? 1024 : 960; }
 
 // ------------------------------------------------------------ edge pass
@@ -675,20 +699,10 @@ __device__ __forceinline__ void c4_group(const RegionDev& R, uint32_t v, int64_t
     fvu = x & GC_FLAGS;
     c4_segment(R, v, x & GC_ID, sb, sl);
   }
-  const int32_t incl = wave_incl_scan32(sl);
-  const int32_t tot = __shfl(incl, 63);
-  const int32_t excl = incl - sl;
-  for (int32_t base = 0; base < tot; base += 64) {
-    const int32_t idx = base + l;
-    const int s = seg_of(excl, idx);
-    const int64_t sbs = __shfl(sb, s);
-    const int32_t exs = __shfl(excl, s);
-    const uint32_t fs = __shfl(fvu, s);
-    if (idx < tot) {
-      const uint32_t y = R.rcol[sbs + (idx - exs)];
-      f(y & GC_ID, fs | (y & GC_FLAGS));
-    }
-  }
+  wave_walk(sb, sl, fvu, [&](int, int64_t pos, uint32_t fs) {
+    const uint32_t y = R.rcol[pos];
+    f(y & GC_ID, fs | (y & GC_FLAGS));
+  });
 }
 
 constexpr int C4S_SLOTS = 512;
@@ -1079,8 +1093,11 @@ void launch_count_t(const CountArgs& A, hipStream_t s, hipEvent_t* ev) {
   fill_u64_count(A.R.t, 0ull, cnt_er, 1, A.e_max, s);
   if (NV == 4) fill_u64_count(A.R.tp, 0ull, cnt_er, 2, 2 * A.e_max, s);
   hipLaunchKernelGGL(k_tri_small<NV>, dim3(cap_grid((N + 3) / 4, 8192)), dim3(256), 0, s, A);
-  hipLaunchKernelGGL((k_tri_large<TL_MID, 256, NV>), dim3(cap_grid(N, 4096)), dim3(256), 0, s, A, 64);
-  hipLaunchKernelGGL((k_tri_large<TLM, 512, NV>), dim3(cap_grid(N, 1024)), dim3(512), 0, s, A, TL_MID);
+  // out-degree tiers (64,128] (256] (512] (TLM]: blocks sized to the slot groups
+  hipLaunchKernelGGL((k_tri_large<128, 128, NV>), dim3(cap_grid(N, 8192)), dim3(128), 0, s, A, 64);
+  hipLaunchKernelGGL((k_tri_large<256, 256, NV>), dim3(cap_grid(N, 4096)), dim3(256), 0, s, A, 128);
+  hipLaunchKernelGGL((k_tri_large<512, 512, NV>), dim3(cap_grid(N, 2048)), dim3(512), 0, s, A, 256);
+  hipLaunchKernelGGL((k_tri_large<TLM, 512, NV>), dim3(cap_grid(N, 1024)), dim3(512), 0, s, A, 512);
   hipLaunchKernelGGL((k_tri_large<0, 256, NV>), dim3(cap_grid(N, (unsigned)A.tri_slots)), dim3(256), 0, s, A, TLM);
   if (ev) (void)hipEventRecord(ev[1], s);
   hipLaunchKernelGGL(k_edge_pass<NV>, dim3(cap_grid((A.e_max + 255) / 256, 16384)), dim3(256), 0, s, A);

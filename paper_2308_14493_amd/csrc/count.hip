@@ -809,10 +809,6 @@ constexpr int C4W_WIN = 16384;
 constexpr int C4W_T = 1024;
 
 struct C4Chunk {
-  int64_t sb[C4W_T];
-  int32_t pre[C4W_T + 1];
-  uint32_t fl[C4W_T];
-  int32_t wsum[C4W_T / 64];
   long long red[C4W_T / 64][2];
 };
 
@@ -846,55 +842,40 @@ __device__ __forceinline__ void block_sum2(C4Chunk& C, long long& x, long long& 
 
 // Walk the wedges (v, u_q, w) for q in [0, nlow) with w in row u_q at
 // positions [urow[q] + p0(q), urow[q] + p1(q)); f(w, flags of both entries).
-// Short slices (the common case: u_q has few entries in the id range) are
-// walked by their own thread; long ones are spread over the whole block
-// with a scan of their lengths and a binary search per element.
-constexpr int32_t C4W_SHORT = 8;
+// Thread q takes u_q: short slices (the common case: u_q has few entries in
+// the id range) are walked by their own thread, long ones by their whole
+// wave, one at a time (wave_walk).
+constexpr int32_t C4W_SHORT = 16;
 
 template <class P0, class P1, class F>
 __device__ __forceinline__ void c4_block_walk(const RegionDev& R, int64_t rb, int32_t nlow, const int64_t* urow,
-                                              P0 p0f, P1 p1f, C4Chunk& C, F f) {
-  const int t = threadIdx.x, l = lane_id(), wv = t >> 6;
+                                              P0 p0f, P1 p1f, F f) {
+  const int t = threadIdx.x;
   for (int32_t c0 = 0; c0 < nlow; c0 += C4W_T) {
     const int32_t q = c0 + t;
+    int64_t sb = 0;
     int32_t sl = 0;
+    uint32_t fl = 0;
     if (q < nlow) {
       const int32_t p0 = p0f(q), p1 = p1f(q);
-      const int64_t sb = urow[q] + p0;
-      const uint32_t fl = R.rcol[rb + q] & GC_FLAGS;
+      sb = urow[q] + p0;
+      fl = R.rcol[rb + q] & GC_FLAGS;
       if (p1 - p0 <= C4W_SHORT) {
         for (int64_t p = sb; p < sb + (p1 - p0); ++p) {
           const uint32_t y = R.rcol[p];
           f(y & GC_ID, fl | (y & GC_FLAGS));
         }
       } else {
-        C.sb[t] = sb;
-        C.fl[t] = fl;
         sl = p1 - p0;
       }
     }
-    // long slices: block-wide flattened walk (skipped when there are none)
-    const int32_t inc = wave_incl_scan32(sl);
-    if (l == 63) C.wsum[wv] = inc;
-    __syncthreads();
-    int32_t before = 0, tot = 0;
-    for (int k = 0; k < C4W_T / 64; ++k) { if (k < wv) before += C.wsum[k]; tot += C.wsum[k]; }
-    if (tot > 0) {
-      C.pre[t] = before + inc - sl;
-      if (t == C4W_T - 1) C.pre[C4W_T] = before + inc;
-      __syncthreads();
-      for (int32_t base = 0; base < tot; base += C4W_T) {
-        const int32_t idx = base + t;
-        if (idx < tot) {
-          int32_t a = 0, z = C4W_T;  // largest a with pre[a] <= idx
-          while (z - a > 1) { const int32_t m = (a + z) >> 1; if (C.pre[m] <= idx) a = m; else z = m; }
-          const uint32_t y = R.rcol[C.sb[a] + (idx - C.pre[a])];
-          f(y & GC_ID, C.fl[a] | (y & GC_FLAGS));
-        }
-      }
-    }
-    __syncthreads();
+    if (__ballot(sl > 0))
+      wave_walk(sb, sl, fl, [&](int, int64_t pos, uint32_t fs) {
+        const uint32_t y = R.rcol[pos];
+        f(y & GC_ID, fs | (y & GC_FLAGS));
+      });
   }
+  __syncthreads();
 }
 
 // One hub v, versions [vsh, vsh + NF) of an NV-version pass.  Window
@@ -938,7 +919,7 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
       WT* wn = (WT*)S.win;
       for (int s = t; s < A.c4_win; s += C4W_T) S.win[s] = 0ull;
       __syncthreads();
-      c4_block_walk(R, rb, nlow, urow, [&](int32_t q) { return unext[q]; }, [&](int32_t q) { return ucur[q]; }, S.C,
+      c4_block_walk(R, rb, nlow, urow, [&](int32_t q) { return unext[q]; }, [&](int32_t q) { return ucur[q]; },
                     [&](uint32_t wid, uint32_t fl) {
                       const uint32_t sub = (vpresent<NV>(fl) >> vsh) & fmask;
                       if (sub) atomicAdd(&wn[wid - lo], WFd::spread(sub));
@@ -956,7 +937,7 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
       if (rest == 0) break;
     } else {
       // sparse from here down: every remaining wedge in global memory
-      c4_block_walk(R, rb, nlow, urow, [&](int32_t) { return 0; }, [&](int32_t q) { return ucur[q]; }, S.C,
+      c4_block_walk(R, rb, nlow, urow, [&](int32_t) { return 0; }, [&](int32_t q) { return ucur[q]; },
                     [&](uint32_t wid, uint32_t fl) {
                       const uint32_t sub = (vpresent<NV>(fl) >> vsh) & fmask;
                       if (!sub) return;

@@ -326,10 +326,11 @@ def main():
             offered += b[0].size + b[2].size
             stats.append(st)
         log("step %d: batch %d updates, %.2f ms (tri %.2f edge %.2f c4 %.2f/%.2f/%.2f prep %.2f fin %.2f) dmin %d whole %d "
-            "region_e=%d c4_tail=%d/%d" % (i, b[0].size + b[2].size, (t2 - t1) * 1e3, st["ms_tri"], st["ms_edge"],
-                                           st["ms_c4_small"], st["ms_c4_mid"], st["ms_c4_large"], st["ms_prepare"],
-                                           st["ms_finish"], st["c4_dense_min"], st["whole_graph"], st["region_entries"],
-                                           st["c4_tail_wedges"], st["wedges"]))
+            "region_e=%d c4_tail=%d/%d hubs=%d windows=%d searches=%d" % (
+                i, b[0].size + b[2].size, (t2 - t1) * 1e3, st["ms_tri"], st["ms_edge"], st["ms_c4_small"],
+                st["ms_c4_mid"], st["ms_c4_large"], st["ms_prepare"], st["ms_finish"], st["c4_dense_min"],
+                st["whole_graph"], st["region_entries"], st["c4_tail_wedges"], st["wedges"], st["tier_c4_large"],
+                st["c4_windows"], st["c4_searches"]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - tstart
     value = offered / elapsed

@@ -129,6 +129,8 @@ typedef struct {
   float ms_tri, ms_edge;             /* triangle/4-clique kernels, edge pass (device) */
   float ms_c4_small, ms_c4_mid, ms_c4_large;  /* 4-cycle tiers (device) */
   float ms_finish;                   /* combine + purge (device) */
+  int64_t c4_windows;                /* dense LDS windows of the large 4-cycle tier */
+  int64_t c4_searches;               /* cursor searches of that tier (lower neighbours x window passes) */
 } gc_batch_stats;
 
 /* One batch for one graph of a pool (host pointers). */

@@ -856,8 +856,9 @@ __device__ __forceinline__ void c4_block_walk(const RegionDev& R, int64_t rb, in
     int64_t sb = 0;
     int32_t sl = 0;
     uint32_t fl = 0;
-    if (q < nlow) {
-      const int32_t p0 = p0f(q), p1 = p1f(q);
+    int32_t p0 = 0, p1 = 0;
+    if (q < nlow) { p0 = p0f(q); p1 = p1f(q); }
+    if (p1 > p0) {
       sb = urow[q] + p0;
       fl = R.rcol[rb + q] & GC_FLAGS;
       if (p1 - p0 <= C4W_SHORT) {
@@ -906,6 +907,7 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
   int64_t hi = v;
   while (hi > 0) {
     const uint32_t lo = (uint32_t)(hi - ws > 0 ? hi - ws : 0);
+    if (t == 0) atomicAdd(&A.bstats[BS_C4_SEARCH], (unsigned long long)nlow);
     long long wtot = 0, rest = 0;
     for (int32_t q = t; q < nlow; q += C4W_T) {
       const int32_t c = ucur[q];
@@ -916,6 +918,7 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
     }
     block_sum2(S.C, wtot, rest);
     if (wtot >= A.c4_dense_min) {
+      if (t == 0) atomicAdd(&A.bstats[BS_C4_WINDOWS], 1ull);
       WT* wn = (WT*)S.win;
       for (int s = t; s < A.c4_win; s += C4W_T) S.win[s] = 0ull;
       __syncthreads();

@@ -64,7 +64,10 @@ enum { PB_LOOPS = 0, PB_DUPS, PB_CANCEL, PB_INS_EXIST, PB_DEL_MISS, PB_EFF_INS, 
 // nothing and the host runs the counting stage again with more scratch.
 enum {
   BS_TOUCHED = GC_SEQ_MAX * PB_N, BS_ERR, BS_ARENA_OVF,
-  BS_COUNT_STAGE, BS_C4_S = BS_COUNT_STAGE, BS_C4_M, BS_C4_L, BS_WEDGES, BS_TRIPROBE, BS_RETRY, BS_COUNT
+  BS_COUNT_STAGE, BS_C4_S = BS_COUNT_STAGE, BS_C4_M, BS_C4_L, BS_WEDGES, BS_TRIPROBE, BS_RETRY,
+  BS_C4_WINDOWS,  // dense LDS windows of the large 4-cycle tier
+  BS_C4_SEARCH,   // cursor searches of that tier (lower neighbours x window passes)
+  BS_COUNT
 };
 
 struct PoolDev {

@@ -37,7 +37,8 @@ class BatchStats(ctypes.Structure):
         "tier_c4_mid", "tier_c4_large", "c4_dense_min")] + [
         ("whole_graph", _I32), ("overflow_mask", ctypes.c_uint32), ("pass_batches", _I32)] + [
         (n, ctypes.c_float) for n in ("ms_total", "ms_prepare", "ms_tri", "ms_edge", "ms_c4_small",
-                                      "ms_c4_mid", "ms_c4_large", "ms_finish")]
+                                      "ms_c4_mid", "ms_c4_large", "ms_finish")] + [
+        ("c4_windows", _I64), ("c4_searches", _I64)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}

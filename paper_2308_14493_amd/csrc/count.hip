@@ -23,8 +23,8 @@
 // Tiers (work lists built by the per-vertex pass):
 //   tri  S: out-degree <= 64, one wave per vertex, bit matrices in LDS
 //   tri  L: larger out-degree, one workgroup per vertex, LDS hash; tiers of
-//           out-degree <= 128, 256, 512, 1024 (960 with four versions), and
-//           global-memory scratch above
+//           out-degree <= 128, 256, 512, 1024, 1280, and global-memory
+//           scratch above
 //   c4   S / M: wedge bound <= 256 / <= 4096, LDS hash per wave / workgroup
 //   c4   L: one workgroup per vertex, windows of dense counters in LDS,
 //           then dense counters in global memory
@@ -334,10 +334,21 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
 // version instead.
 constexpr int TL_EXC = 256;  // edges with flags tracked per vertex
 
+// Words of the triangular bit matrix of n slots with W words per full row:
+// row i keeps only words (i >> 6) .. W - 1 (its bits j > i).
+__host__ __device__ __forceinline__ int64_t tri_words(int64_t n, int64_t W) {
+  const int64_t b = n >> 6;
+  return n * W - (32 * b * (b - 1) + (n - 64 * b) * b);
+}
+
 template <int NV>
 struct TriL {
   using TU = typename Fields<NV, 16>::T;  // per-slot triangle counts, 16-bit field per version
-  unsigned long long* E;    // [dp][W] row bitsets
+  unsigned long long* E;    // triangular row bitsets, tri_words(dp, W) words
+  // word w >= (i >> 6) of row i is erow(i)[w]
+  __device__ __forceinline__ unsigned long long* erow(int32_t i) const {
+    return E + tri_words(i, W) - (i >> 6);
+  }
   unsigned long long* P;    // [NV][W] slot masks per version
   uint32_t* ids;            // [dp]
   int32_t* hkey;            // [H]
@@ -351,7 +362,7 @@ struct TriL {
 template <int NV>
 __device__ __forceinline__ bool Ebit(const TriL<NV>& S, int32_t p, int32_t q) {  // edge between slots p != q
   if (p > q) { int32_t t = p; p = q; q = t; }
-  return (S.E[(int64_t)p * S.W + (q >> 6)] >> (q & 63)) & 1ull;
+  return (S.erow(p)[q >> 6] >> (q & 63)) & 1ull;
 }
 
 __device__ __forceinline__ bool bit_of(const unsigned long long* m, int32_t k) { return (m[k >> 6] >> (k & 63)) & 1ull; }
@@ -380,7 +391,7 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL<N
     const uint32_t y = R.rcol[pos];
     const int j = lookup_slot(S.hkey, S.hval, hmask, shift, y & GC_ID);
     if (j < 0) return;
-    unsigned long long* Ei = S.E + (int64_t)i * S.W;
+    unsigned long long* Ei = S.erow(i);
     const uint32_t fy = y & GC_FLAGS;
     if (only) {
       if (!absent_in(fy, only - 1)) atomicOr(&Ei[j >> 6], 1ull << (j & 63));
@@ -409,13 +420,13 @@ __device__ __forceinline__ int64_t k4_rows(const TriL<NV>& S, const unsigned lon
   int64_t cnt = 0;
   for (int32_t i = w; i < dp; i += nwaves) {
     if (!bit_of(mask, i)) continue;
-    const unsigned long long* Ei = S.E + (int64_t)i * S.W;
+    const unsigned long long* Ei = S.erow(i);
     for (int32_t w0 = i >> 6; w0 < S.W; ++w0) {
       const unsigned long long m = Ei[w0] & mask[w0];
       if (!m) continue;
       if ((m >> l) & 1ull) {
         const int32_t j = w0 * 64 + l;
-        const unsigned long long* Ej = S.E + (int64_t)j * S.W;
+        const unsigned long long* Ej = S.erow(j);
         for (int32_t q = j >> 6; q < S.W; ++q) cnt += __popcll(Ei[q] & Ej[q] & mask[q]);
       }
     }
@@ -436,7 +447,8 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL<NV>& S, int32_t 
   const int shift = 32 - log2i((uint32_t)H);
   for (int32_t k = threadIdx.x; k < dp; k += blockDim.x) { S.ids[k] = R.rcol[ub + k]; S.tuc[k] = 0; }
   for (int32_t k = threadIdx.x; k < H; k += blockDim.x) S.hkey[k] = -1;
-  for (int64_t k = threadIdx.x; k < (int64_t)dp * W; k += blockDim.x) S.E[k] = 0ull;
+  const int64_t ew = tri_words(dp, W);
+  for (int64_t k = threadIdx.x; k < ew; k += blockDim.x) S.E[k] = 0ull;
   for (int32_t k = threadIdx.x; k < NV * W; k += blockDim.x) S.P[k] = 0ull;
   if (threadIdx.x == 0) *S.nexc = 0;
   __syncthreads();
@@ -508,7 +520,7 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL<NV>& S, int32_t 
     // too many version-specific edges: rebuild E per version and count
     for (int x = 0; x < NV; ++x) {
       __syncthreads();
-      for (int64_t k = threadIdx.x; k < (int64_t)dp * W; k += blockDim.x) S.E[k] = 0ull;
+      for (int64_t k = threadIdx.x; k < ew; k += blockDim.x) S.E[k] = 0ull;
       __syncthreads();
       for (int32_t g0 = w * 64; g0 < dp; g0 += nwaves * 64) tri_large_probe<NV>(A, S, hmask, shift, g0, dp, x + 1);
       __syncthreads();
@@ -531,12 +543,13 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL<NV>& S, int32_t 
   __syncthreads();
 }
 
-// global-scratch slot layout (u64 words): E [cap*W] | P [NV*W] | tuc [cap] |
-// exc [TL_EXC] | then u32 words: ids [cap] | hkey [4 cap] | hval [2 cap] | nexc [2]
+// global-scratch slot layout (u64 words): E [tri_words(cap, W)] | P [NV*W] |
+// tuc [cap] | exc [TL_EXC] | then u32 words: ids [cap] | hkey [4 cap] |
+// hval [2 cap] | nexc [2]
 template <int NV>
 __host__ __device__ inline int64_t tri_slot_words64(int64_t cap) {
-  const int64_t W = ((cap + 63) / 64) | 1;
-  return cap * W + NV * W + cap + TL_EXC + (cap + 4 * cap + 2 * cap + 2 + 1) / 2 + 8;
+  const int64_t W = (cap + 63) / 64;
+  return tri_words(cap, W) + NV * W + cap + TL_EXC + (cap + 4 * cap + 2 * cap + 2 + 1) / 2 + 8;
 }
 
 constexpr int pow2_at_least(int x) {
@@ -560,11 +573,11 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int32_t lo_d
   if constexpr (CAP == 0) {
     // slot layout for capacity tri_cap (no slot is touched while tri_cap == 0)
     const int64_t cap = A.tri_cap > 0 ? A.tri_cap : 1;
-    const int64_t W = ((cap + 63) / 64) | 1;
+    const int64_t W = (cap + 63) / 64;
     unsigned long long* base = A.tri_scratch + (int64_t)blockIdx.x * tri_slot_words64<NV>(cap);
     S.W = (int32_t)W;
     S.E = base;
-    S.P = base + cap * W;
+    S.P = base + tri_words(cap, W);
     S.tuc = (TU*)(S.P + NV * W);
     S.exc = S.P + NV * W + cap;
     uint32_t* u32 = (uint32_t*)(S.exc + TL_EXC);
@@ -574,10 +587,9 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int32_t lo_d
     S.nexc = (int32_t*)(u32 + 7 * cap);
   } else {
     constexpr int CW = CAP / 64;
-    constexpr int CWS = CW | 1;  // largest odd row stride used
     constexpr int HC = pow2_at_least(2 * CAP);
-    __shared__ unsigned long long E[CAP * CWS];
-    __shared__ unsigned long long P[NV * CWS];
+    __shared__ unsigned long long E[32 * CW * CW + 32 * CW];  // tri_words(CAP, CW)
+    __shared__ unsigned long long P[NV * CW];
     __shared__ uint32_t ids[CAP];
     __shared__ TU tuc[CAP];
     __shared__ int32_t hkey[HC];
@@ -585,7 +597,7 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int32_t lo_d
     __shared__ unsigned long long exc[TL_EXC];
     __shared__ int32_t nexc;
     S.E = E; S.P = P; S.ids = ids; S.tuc = tuc; S.hkey = hkey; S.hval = hval; S.exc = exc; S.nexc = &nexc;
-    S.W = CWS;
+    S.W = CW;
   }
   for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
     const int32_t u = list[it];
@@ -601,13 +613,13 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int32_t lo_d
       if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_K4, kacc);
       cur_g = g;
     }
-    if constexpr (CAP != 0) S.W = ((dp + 63) / 64) | 1;  // odd row stride: rows spread over LDS banks
+    if constexpr (CAP != 0) S.W = (dp + 63) / 64;
     tri_large_vertex<NV>(A, S, u, ub, dp, kacc);
   }
   if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_K4, kacc);
 }
 
-template <int NV> constexpr int tl_max() { return NV == 2 ? 1024 : 960; }
+template <int NV> constexpr int tl_max() { return 1280; }
 
 // ------------------------------------------------------------ edge pass
 // After all triangles, per upper entry u -> w present in version x, with
@@ -1077,11 +1089,12 @@ void launch_count_t(const CountArgs& A, hipStream_t s, hipEvent_t* ev) {
   fill_u64_count(A.R.t, 0ull, cnt_er, 1, A.e_max, s);
   if (NV == 4) fill_u64_count(A.R.tp, 0ull, cnt_er, 2, 2 * A.e_max, s);
   hipLaunchKernelGGL(k_tri_small<NV>, dim3(cap_grid((N + 3) / 4, 8192)), dim3(256), 0, s, A);
-  // out-degree tiers (64,128] (256] (512] (TLM]: blocks sized to the slot groups
+  // out-degree tiers (64,128] (256] (512] (1024] (TLM]: blocks sized to the slot groups
   hipLaunchKernelGGL((k_tri_large<128, 128, NV>), dim3(cap_grid(N, 8192)), dim3(128), 0, s, A, 64);
   hipLaunchKernelGGL((k_tri_large<256, 256, NV>), dim3(cap_grid(N, 4096)), dim3(256), 0, s, A, 128);
   hipLaunchKernelGGL((k_tri_large<512, 512, NV>), dim3(cap_grid(N, 2048)), dim3(512), 0, s, A, 256);
-  hipLaunchKernelGGL((k_tri_large<TLM, 512, NV>), dim3(cap_grid(N, 1024)), dim3(512), 0, s, A, 512);
+  hipLaunchKernelGGL((k_tri_large<1024, 1024, NV>), dim3(cap_grid(N, 1024)), dim3(1024), 0, s, A, 512);
+  hipLaunchKernelGGL((k_tri_large<TLM, 1024, NV>), dim3(cap_grid(N, 1024)), dim3(1024), 0, s, A, 1024);
   hipLaunchKernelGGL((k_tri_large<0, 256, NV>), dim3(cap_grid(N, (unsigned)A.tri_slots)), dim3(256), 0, s, A, TLM);
   if (ev) (void)hipEventRecord(ev[1], s);
   hipLaunchKernelGGL(k_edge_pass<NV>, dim3(cap_grid((A.e_max + 255) / 256, 16384)), dim3(256), 0, s, A);

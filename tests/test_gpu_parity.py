@@ -237,7 +237,7 @@ def test_rmat_large_ids(scale, ef, seed):
 COMP = [0, 6, 8, 7, 9, 10, 1, 3, 2, 4, 5]   # class of the complement (pinned on the CPU)
 
 
-@pytest.mark.parametrize("n,p,seed", [(900, 0.05, 41), (1300, 0.03, 42)])
+@pytest.mark.parametrize("n,p,seed", [(900, 0.05, 41), (1300, 0.03, 42), (1500, 0.02, 45)])
 def test_dense_graph_by_complement(n, p, seed):
     """Dense graphs (out-degrees up to ~n) exercise the large-out-degree
     triangle tiers; the oracle counts the sparse complement and the

@@ -817,7 +817,7 @@ __global__ __launch_bounds__(256) void k_c4_mid(CountArgs A) {
 // per window, so rows are read about once.  Four versions with 32-bit
 // fields would not fit a 64-bit counter: such hubs are walked twice, for
 // versions 0-1 and 2-3.
-constexpr int C4W_WIN = 16384;
+constexpr int C4W_WIN = 18432;  // 144 KB of 64-bit words
 constexpr int C4W_T = 1024;
 
 struct C4Chunk {

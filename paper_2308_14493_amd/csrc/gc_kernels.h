@@ -111,7 +111,7 @@ struct CountArgs {
   int32_t* c4_touch;              // [slots][N]
   int64_t N;
   int32_t slots;                  // workgroups of the large 4-cycle tier
-  int32_t c4_win;                 // 64-bit words of the LDS window of the large tier (a power of two <= c4_window_max())
+  int32_t c4_win;                 // 64-bit words of the LDS window of the large tier (<= c4_window_max())
   int32_t c4_narrow_max;          // up to this many lower neighbours, 16-bit counters (2x window)
   int64_t c4_dense_min;           // hits that earn a window dense LDS counters
   int64_t* c4_cur;                // [slots][2 * c4_maxlow]: row starts, cursors, next cursors

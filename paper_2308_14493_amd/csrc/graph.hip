@@ -421,6 +421,20 @@ __global__ void k_region_fill(PoolDev P, RegionDev R, const int32_t* __restrict_
   }
 }
 
+// First index in sorted row[0..n) whose id is >= key, by an exponential
+// search from the end: ids are a degree order, so for w < v the position of
+// v in row w is usually among the last few entries.
+__device__ __forceinline__ int32_t lower_bound_from_end(const uint32_t* row, int32_t n, uint32_t key) {
+  int32_t hi = n, step = 1;  // row[hi..n) >= key
+  while (hi > 0) {
+    const int32_t p = hi - step > 0 ? hi - step : 0;
+    if ((row[p] & GC_ID) < key) return p + 1 + lower_bound_id(row + p + 1, hi - p - 1, key);
+    hi = p;
+    step <<= 1;
+  }
+  return 0;
+}
+
 // Per-vertex pass over the region: degrees per version, N- split, the
 // 3-star and wedge terms, and the work lists of the counting kernels.
 template <int NV>
@@ -471,7 +485,7 @@ __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const in
         // for the 4-cycle kernels as the starting cursor in row w)
         low += 1;
         const int64_t wb = R.roff[w];
-        const int32_t pos = lower_bound_id(R.rcol + wb, (int32_t)(R.roff[w + 1] - wb), (uint32_t)v);
+        const int32_t pos = lower_bound_from_end(R.rcol + wb, (int32_t)(R.roff[w + 1] - wb), (uint32_t)v);
         R.vpos[b + k] = pos;
         wsum += pos;
       }

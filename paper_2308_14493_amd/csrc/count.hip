@@ -91,17 +91,18 @@ __device__ __forceinline__ int64_t rdl64(int64_t v, int lane) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Walk the lists of a wave's lanes (lane l: positions [sb, sb + sl), with a
-// 32-bit payload pl) calling f(list lane, position, payload of that lane).
-// Lists of at least WALK_LONG entries go one at a time through the whole
-// wave (consecutive lanes read consecutive entries; the list's lane is read
-// with scalar reads); the others are flattened over the lanes with a segment
-// search per step.  Most entries sit in long lists, which then cost no
-// cross-lane traffic.  All lanes must call it.
+// Walk the lists of a wave's lanes (lane l: positions [sb, sb + sl) of the
+// entry array col, with a 32-bit payload pl) calling f(list lane, position,
+// payload of that lane, entry).  Lists of at least WALK_LONG entries go one
+// at a time through the whole wave (consecutive lanes read consecutive
+// entries, four loads in flight per lane; the list's lane is read with scalar
+// reads); the others are flattened over the lanes with a segment search per
+// step.  Most entries sit in long lists, which then cost no cross-lane
+// traffic.  All lanes must call it.
 constexpr int32_t WALK_LONG = 32;
 
 template <class F>
-__device__ __forceinline__ void wave_walk(int64_t sb, int32_t sl, uint32_t pl, F f) {
+__device__ __forceinline__ void wave_walk(const uint32_t* col, int64_t sb, int32_t sl, uint32_t pl, F f) {
   const int l = lane_id();
   const bool lng = sl >= WALK_LONG;
   uint64_t lm = __ballot(lng);
@@ -111,7 +112,14 @@ __device__ __forceinline__ void wave_walk(int64_t sb, int32_t sl, uint32_t pl, F
     const int64_t b = rdl64(sb, s);
     const int32_t n = rdl32(sl, s);
     const uint32_t ps = (uint32_t)rdl32((int32_t)pl, s);
-    for (int32_t k = l; k < n; k += 64) f(s, b + k, ps);
+    for (int32_t k = l; k < n; k += 256) {
+      uint32_t y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) y[u] = k + 64 * u < n ? col[b + k + 64 * u] : 0u;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (k + 64 * u < n) f(s, b + k + 64 * u, ps, y[u]);
+    }
   }
   const int32_t ss = lng ? 0 : sl;
   const int32_t incl = wave_incl_scan32(ss);
@@ -123,7 +131,10 @@ __device__ __forceinline__ void wave_walk(int64_t sb, int32_t sl, uint32_t pl, F
     const int64_t sbs = __shfl(sb, s);
     const int32_t exs = __shfl(excl, s);
     const uint32_t ps = (uint32_t)__shfl((int32_t)pl, s);
-    if (idx < tot) f(s, sbs + (idx - exs), ps);
+    if (idx < tot) {
+      const int64_t pos = sbs + (idx - exs);
+      f(s, pos, ps, col[pos]);
+    }
   }
 }
 
@@ -266,8 +277,7 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
     int64_t sb = 0;
     int32_t sl = 0;
     if (l < dp) { sb = R.roff[vi] + R.rlow[vi]; sl = (int32_t)(R.roff[vi + 1] - sb); }
-    wave_walk(sb, sl, fi, [&](int i, int64_t pos, uint32_t fs) {
-      const uint32_t y = R.rcol[pos];
+    wave_walk(R.rcol, sb, sl, fi, [&](int i, int64_t pos, uint32_t fs, uint32_t y) {
       const int j = lookup_slot(hkey[w], hval[w], 127u, 25, y & GC_ID);
       if (j >= 0) {
         const uint32_t fy = y & GC_FLAGS;
@@ -386,9 +396,8 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL<N
     sb = R.roff[v] + R.rlow[v];
     sl = (int32_t)(R.roff[v + 1] - sb);
   }
-  wave_walk(sb, sl, fi, [&](int s, int64_t pos, uint32_t fs) {
+  wave_walk(R.rcol, sb, sl, fi, [&](int s, int64_t pos, uint32_t fs, uint32_t y) {
     const int32_t i = g0 + s;
-    const uint32_t y = R.rcol[pos];
     const int j = lookup_slot(S.hkey, S.hval, hmask, shift, y & GC_ID);
     if (j < 0) return;
     unsigned long long* Ei = S.erow(i);
@@ -711,10 +720,7 @@ __device__ __forceinline__ void c4_group(const RegionDev& R, uint32_t v, int64_t
     fvu = x & GC_FLAGS;
     c4_segment(R, v, x & GC_ID, sb, sl);
   }
-  wave_walk(sb, sl, fvu, [&](int, int64_t pos, uint32_t fs) {
-    const uint32_t y = R.rcol[pos];
-    f(y & GC_ID, fs | (y & GC_FLAGS));
-  });
+  wave_walk(R.rcol, sb, sl, fvu, [&](int, int64_t, uint32_t fs, uint32_t y) { f(y & GC_ID, fs | (y & GC_FLAGS)); });
 }
 
 constexpr int C4S_SLOTS = 512;
@@ -883,10 +889,7 @@ __device__ __forceinline__ void c4_block_walk(const RegionDev& R, int64_t rb, in
       }
     }
     if (__ballot(sl > 0))
-      wave_walk(sb, sl, fl, [&](int, int64_t pos, uint32_t fs) {
-        const uint32_t y = R.rcol[pos];
-        f(y & GC_ID, fs | (y & GC_FLAGS));
-      });
+      wave_walk(R.rcol, sb, sl, fl, [&](int, int64_t, uint32_t fs, uint32_t y) { f(y & GC_ID, fs | (y & GC_FLAGS)); });
   }
   __syncthreads();
 }

@@ -880,9 +880,14 @@ __device__ __forceinline__ void c4_block_walk(const RegionDev& R, int64_t rb, in
       sb = urow[q] + p0;
       fl = R.rcol[rb + q] & GC_FLAGS;
       if (p1 - p0 <= C4W_SHORT) {
-        for (int64_t p = sb; p < sb + (p1 - p0); ++p) {
-          const uint32_t y = R.rcol[p];
-          f(y & GC_ID, fl | (y & GC_FLAGS));
+        const int32_t len = p1 - p0;
+        for (int32_t k = 0; k < len; k += 4) {  // four loads in flight
+          uint32_t y[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) y[u] = k + u < len ? R.rcol[sb + k + u] : 0u;
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (k + u < len) f(y[u] & GC_ID, fl | (y[u] & GC_FLAGS));
         }
       } else {
         sl = p1 - p0;

@@ -53,6 +53,24 @@ __device__ __forceinline__ int lookup_slot(const int32_t* keys, const int16_t* v
   }
 }
 
+// Same, with the first two slots read unconditionally (one round of LDS
+// loads for nearly every lookup at load factor <= 1/2, so that several
+// lookups of a lane overlap); the loop only continues longer runs.
+__device__ __forceinline__ int lookup_slot2(const int32_t* keys, const int16_t* vals, uint32_t mask, int shift,
+                                            uint32_t key) {
+  const uint32_t h = hash32(key) >> shift, h1 = (h + 1) & mask;
+  const int32_t k0 = keys[h], k1 = keys[h1];
+  if (k0 == (int32_t)key) return vals[h];
+  if (k0 == -1) return -1;
+  if (k1 == (int32_t)key) return vals[h1];
+  if (k1 == -1) return -1;
+  for (uint32_t q = (h1 + 1) & mask;; q = (q + 1) & mask) {
+    const int32_t k = keys[q];
+    if (k == (int32_t)key) return vals[q];
+    if (k == -1) return -1;
+  }
+}
+
 // add `add` to the counter of key (insert on first use)
 template <class V>
 __device__ __forceinline__ void hash_add(int32_t* keys, V* vals, uint32_t mask, int shift, uint32_t key, V add) {
@@ -135,6 +153,51 @@ __device__ __forceinline__ void wave_walk(const uint32_t* col, int64_t sb, int32
       const int64_t pos = sbs + (idx - exs);
       f(s, pos, ps, col[pos]);
     }
+  }
+}
+
+__device__ __forceinline__ unsigned long long wave_or64(unsigned long long v) {
+  for (int o = 32; o > 0; o >>= 1) v |= (unsigned long long)__shfl_xor((long long)v, o);
+  return v;
+}
+template <class T>
+__device__ __forceinline__ T wave_add(T v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    if constexpr (sizeof(T) == 8) v += (T)__shfl_xor((long long)v, o);
+    else v += (T)__shfl_xor((int)v, o);
+  }
+  return v;
+}
+
+// The long lists of a wave's lanes (at least WALK_LONG entries), one at a
+// time through the whole wave: begin(s) -> per-list state; for every entry
+// look(entry) -> slot (or -1), then f(state, s, pos, entry, slot) for the
+// slots found; end(state, s).  Each lane loads four entries and looks all
+// four up before handling any, so their memory and LDS accesses overlap.  The
+// list's lane s is uniform, so per-list work can be hoisted into begin/end.
+template <class B, class L, class F, class E>
+__device__ __forceinline__ void wave_walk_long(const uint32_t* col, int64_t sb, int32_t sl, B begin, L look, F f,
+                                               E end) {
+  const int l = lane_id();
+  uint64_t lm = __ballot(sl >= WALK_LONG);
+  while (lm) {
+    const int s = __builtin_ctzll(lm);
+    lm &= lm - 1;
+    const int64_t b = rdl64(sb, s);
+    const int32_t n = rdl32(sl, s);
+    auto st = begin(s);
+    for (int32_t k = l; k < n; k += 256) {
+      uint32_t y[4];
+      int jj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) y[u] = k + 64 * u < n ? col[b + k + 64 * u] : 0u;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) jj[u] = k + 64 * u < n ? look(y[u]) : -1;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (jj[u] >= 0) f(st, s, b + k + 64 * u, y[u], jj[u]);
+    }
+    end(st, s);
   }
 }
 
@@ -277,22 +340,38 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
     int64_t sb = 0;
     int32_t sl = 0;
     if (l < dp) { sb = R.roff[vi] + R.rlow[vi]; sl = (int32_t)(R.roff[vi + 1] - sb); }
-    wave_walk(R.rcol, sb, sl, fi, [&](int i, int64_t pos, uint32_t fs, uint32_t y) {
-      const int j = lookup_slot(hkey[w], hval[w], 127u, 25, y & GC_ID);
-      if (j >= 0) {
-        const uint32_t fy = y & GC_FLAGS;
-        const unsigned long long bj = 1ull << j, bi = 1ull << i;
-        atomicOr(&EU[w][i], bj);
-        atomicOr(&TU[w][j], bi);
-        if (fy) {
-          dirty[w] = 1u;
+    // one probe of list i: a hit j is the triangle (u, v_i, v_j); row i's
+    // bits collect in ei (the caller writes them)
+    auto look = [&](uint32_t y) { return lookup_slot2(hkey[w], hval[w], 127u, 25, y & GC_ID); };
+    auto hit = [&](int i, int64_t pos, uint32_t fs, uint32_t y, int j, unsigned long long& ei) {
+      const uint32_t fy = y & GC_FLAGS;
+      const unsigned long long bj = 1ull << j, bi = 1ull << i;
+      ei |= bj;
+      atomicOr(&TU[w][j], bi);
+      if (fy) {
+        dirty[w] = 1u;
 #pragma unroll
-          for (int x = 0; x < NV; ++x)
-            if (absent_in(fy, x)) { atomicOr(&EX[w][x][i], bj); atomicOr(&TX[w][x][j], bi); }
-        }
-        const uint32_t pm = vpresent<NV>(fs | fsl[w][j] | fy);
-        if (pm) t_add<NV>(R, pos, pm);
+        for (int x = 0; x < NV; ++x)
+          if (absent_in(fy, x)) { atomicOr(&EX[w][x][i], bj); atomicOr(&TX[w][x][j], bi); }
       }
+      const uint32_t pm = vpresent<NV>(fs | fsl[w][j] | fy);
+      if (pm) t_add<NV>(R, pos, pm);
+    };
+    struct LongState { int i; uint32_t fs; unsigned long long ei; };
+    wave_walk_long(
+        R.rcol, sb, sl,
+        [&](int s) { return LongState{s, (uint32_t)rdl32((int32_t)fi, s), 0ull}; }, look,
+        [&](LongState& st, int, int64_t pos, uint32_t y, int j) { hit(st.i, pos, st.fs, y, j, st.ei); },
+        [&](LongState& st, int) {
+          const unsigned long long e = wave_or64(st.ei);
+          if (lane_id() == 0 && e) atomicOr(&EU[w][st.i], e);
+        });
+    wave_walk(R.rcol, sb, sl >= WALK_LONG ? 0 : sl, fi, [&](int i, int64_t pos, uint32_t fs, uint32_t y) {
+      const int j = look(y);
+      if (j < 0) return;
+      unsigned long long ei = 0;
+      hit(i, pos, fs, y, j, ei);
+      atomicOr(&EU[w][i], ei);
     });
     wave_sync();
     const bool clean = __ballot(l < dp && fi != 0) == 0ull && dirty[w] == 0u;
@@ -396,15 +475,15 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL<N
     sb = R.roff[v] + R.rlow[v];
     sl = (int32_t)(R.roff[v + 1] - sb);
   }
-  wave_walk(R.rcol, sb, sl, fi, [&](int s, int64_t pos, uint32_t fs, uint32_t y) {
-    const int32_t i = g0 + s;
-    const int j = lookup_slot(S.hkey, S.hval, hmask, shift, y & GC_ID);
-    if (j < 0) return;
-    unsigned long long* Ei = S.erow(i);
+  using TU = typename TriL<NV>::TU;
+  // one probe of list i: a hit j is the triangle (u, v_i, w_j); returns the
+  // increment of t(u, v_i), which the caller adds to tuc[i]
+  auto look = [&](uint32_t y) { return lookup_slot2(S.hkey, S.hval, hmask, shift, y & GC_ID); };
+  auto hit = [&](int32_t i, unsigned long long* Ei, uint32_t fs, int64_t pos, uint32_t y, int j) -> TU {
     const uint32_t fy = y & GC_FLAGS;
     if (only) {
       if (!absent_in(fy, only - 1)) atomicOr(&Ei[j >> 6], 1ull << (j & 63));
-      return;
+      return (TU)0;
     }
     atomicOr(&Ei[j >> 6], 1ull << (j & 63));
     if (fy) {
@@ -413,12 +492,27 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL<N
         S.exc[p] = ((unsigned long long)i << 32) | ((unsigned long long)j << 4) | (unsigned long long)(fy >> GC_VSHIFT);
     }
     const uint32_t pm = vpresent<NV>(fs | (S.ids[j] & GC_FLAGS) | fy);
-    if (pm) {
-      t_add<NV>(R, pos, pm);
-      const typename TriL<NV>::TU add = Fields<NV, 16>::spread(pm);
-      atomicAdd(&S.tuc[j], add);
-      atomicAdd(&S.tuc[i], add);
-    }
+    if (!pm) return (TU)0;
+    t_add<NV>(R, pos, pm);
+    const TU add = Fields<NV, 16>::spread(pm);
+    atomicAdd(&S.tuc[j], add);
+    return add;
+  };
+  struct LongState { int32_t i; unsigned long long* Ei; uint32_t fs; TU acc; };
+  wave_walk_long(
+      R.rcol, sb, sl,
+      [&](int s) { return LongState{g0 + s, S.erow(g0 + s), (uint32_t)rdl32((int32_t)fi, s), (TU)0}; }, look,
+      [&](LongState& st, int, int64_t pos, uint32_t y, int j) { st.acc += hit(st.i, st.Ei, st.fs, pos, y, j); },
+      [&](LongState& st, int) {
+        const TU tot = wave_add<TU>(st.acc);
+        if (lane_id() == 0 && tot) atomicAdd(&S.tuc[st.i], tot);
+      });
+  wave_walk(R.rcol, sb, sl >= WALK_LONG ? 0 : sl, fi, [&](int s, int64_t pos, uint32_t fs, uint32_t y) {
+    const int j = look(y);
+    if (j < 0) return;
+    const int32_t i = g0 + s;
+    const TU add = hit(i, S.erow(i), fs, pos, y, j);
+    if (add) atomicAdd(&S.tuc[i], add);
   });
 }
 

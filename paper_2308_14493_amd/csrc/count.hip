@@ -175,6 +175,8 @@ __device__ __forceinline__ T wave_add(T v) {
 // slots found; end(state, s).  Each lane loads four entries and looks all
 // four up before handling any, so their memory and LDS accesses overlap.  The
 // list's lane s is uniform, so per-list work can be hoisted into begin/end.
+constexpr int WALK_DEPTH = 4;  // entries per lane loaded and looked up together
+
 template <class B, class L, class F, class E>
 __device__ __forceinline__ void wave_walk_long(const uint32_t* col, int64_t sb, int32_t sl, B begin, L look, F f,
                                                E end) {
@@ -186,15 +188,15 @@ __device__ __forceinline__ void wave_walk_long(const uint32_t* col, int64_t sb, 
     const int64_t b = rdl64(sb, s);
     const int32_t n = rdl32(sl, s);
     auto st = begin(s);
-    for (int32_t k = l; k < n; k += 256) {
-      uint32_t y[4];
-      int jj[4];
+    for (int32_t k = l; k < n; k += 64 * WALK_DEPTH) {
+      uint32_t y[WALK_DEPTH];
+      int jj[WALK_DEPTH];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) y[u] = k + 64 * u < n ? col[b + k + 64 * u] : 0u;
+      for (int u = 0; u < WALK_DEPTH; ++u) y[u] = k + 64 * u < n ? col[b + k + 64 * u] : 0u;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) jj[u] = k + 64 * u < n ? look(y[u]) : -1;
+      for (int u = 0; u < WALK_DEPTH; ++u) jj[u] = k + 64 * u < n ? look(y[u]) : -1;
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < WALK_DEPTH; ++u)
         if (jj[u] >= 0) f(st, s, b + k + 64 * u, y[u], jj[u]);
     }
     end(st, s);

@@ -449,6 +449,35 @@ __device__ __forceinline__ void flush_vertex_terms(unsigned long long* sig, int 
   }
 }
 
+// List appends of the per-vertex pass, batched per wave: lane k keeps the
+// decisions of the wave's k-th vertex of the current group of 64, and one
+// atomic per list reserves room for the whole group.
+struct DegDecision {
+  int32_t v = -1;
+  int32_t tri = -1;  // L_TRI_S / L_TRI_L or -1
+  int32_t c4 = -1;   // L_C4_S / L_C4_M / L_C4_L or -1
+  unsigned long long key = 0;  // sort key of the large 4-cycle tier
+};
+
+__device__ __forceinline__ void flush_decisions(DegDecision& d, unsigned long long* cc, int32_t* lists,
+                                                int64_t list_stride, unsigned long long* c4_keys) {
+  const int l = lane_id();
+  for (int L = 0; L < L_NUM; ++L) {
+    const bool mine = (L <= L_TRI_L ? d.tri : d.c4) == L && d.v >= 0;
+    const uint64_t m = __ballot(mine);
+    if (!m) continue;
+    unsigned long long base = 0;
+    if (l == 0) base = atomicAdd(&cc[C_LIST0 + L], (unsigned long long)__popcll(m));
+    base = (unsigned long long)__shfl((long long)base, 0);
+    if (mine) {
+      const unsigned long long p = base + __popcll(m & lanemask_lt());
+      lists[L * list_stride + p] = d.v;
+      if (L == L_C4_L) c4_keys[p] = d.key;
+    }
+  }
+  d = DegDecision();
+}
+
 template <int NV>
 __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const int32_t* __restrict__ rlist,
                           unsigned long long* __restrict__ cc, unsigned long long* __restrict__ sig,
@@ -461,9 +490,11 @@ __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const in
   int64_t s1[NV], w2[NV], d1[NV];
 #pragma unroll
   for (int x = 0; x < NV; ++x) { s1[x] = 0; w2[x] = 0; d1[x] = 0; }
-  int64_t wedges = 0;
+  int64_t wedges = 0, c4e[3] = {0, 0, 0};
   int32_t maxdp = 0;
   int64_t maxw = 0;
+  DegDecision dec;
+  int slot = 0;  // lane that records the next vertex's decisions
   for (int64_t i = gwave(); i < n; i += gwaves()) {
     const int32_t v = rlist[i];
     const int64_t b = R.roff[v];
@@ -494,6 +525,7 @@ __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const in
     for (int x = 0; x < NV; ++x) dv[x] = wave_sum32(dv[x]);
     low = wave_sum32(low);
     wsum = wave_sum64(wsum);
+    // every lane holds the vertex's totals now
     if (lane_id() == 0) {
       if constexpr (NV == 2) {
         *(int2*)(R.d + (int64_t)v * 2) = make_int2(dv[0], dv[1]);
@@ -508,34 +540,42 @@ __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const in
       }
 #pragma unroll
       for (int x = 0; x < NV; ++x) { s1[x] += c3(dv[x]); w2[x] += c2(dv[x]); d1[x] += dv[x]; }
-      const int32_t dplus = L - low;
-      if (dplus >= 2) {
-        const int which = dplus <= tri_small ? L_TRI_S : L_TRI_L;
-        unsigned long long p = atomicAdd(&cc[C_LIST0 + which], 1ull);
-        lists[which * list_stride + p] = v;
-        maxdp = dplus > maxdp ? dplus : maxdp;
-      }
-      if (low >= 2 && wsum >= 2) {
-        const int which = wsum <= c4_small ? L_C4_S : (wsum <= c4_mid ? L_C4_M : L_C4_L);
-        unsigned long long p = atomicAdd(&cc[C_LIST0 + which], 1ull);
-        lists[which * list_stride + p] = v;
-        maxw = wsum > maxw ? wsum : maxw;
-        wedges += wsum;
-        atomicAdd(&bstats[BS_C4_S + which - L_C4_S], (unsigned long long)(wsum + low));
-        if (which == L_C4_L) {
-          const uint64_t wk = wsum < 0xFFFFFFFFll ? (uint64_t)wsum : 0xFFFFFFFFull;
-          c4_keys[p] = ((0xFFFFFFFFull - wk) << 32) | (uint32_t)v;
-          maxlow = low > maxlow ? low : maxlow;
-        }
+    }
+    const int32_t dplus = L - low;
+    const bool tri = dplus >= 2, c4 = low >= 2 && wsum >= 2;
+    if (lane_id() == slot) {
+      dec.v = v;
+      dec.tri = tri ? (dplus <= tri_small ? L_TRI_S : L_TRI_L) : -1;
+      dec.c4 = c4 ? (wsum <= c4_small ? L_C4_S : (wsum <= c4_mid ? L_C4_M : L_C4_L)) : -1;
+      if (dec.c4 == L_C4_L) {
+        const uint64_t wk = wsum < 0xFFFFFFFFll ? (uint64_t)wsum : 0xFFFFFFFFull;
+        dec.key = ((0xFFFFFFFFull - wk) << 32) | (uint32_t)v;
       }
     }
+    if (lane_id() == 0) {
+      if (tri) maxdp = dplus > maxdp ? dplus : maxdp;
+      if (c4) {
+        const int which = wsum <= c4_small ? 0 : (wsum <= c4_mid ? 1 : 2);
+        maxw = wsum > maxw ? wsum : maxw;
+        wedges += wsum;
+        c4e[which] += wsum + low;
+        if (which == 2) maxlow = low > maxlow ? low : maxlow;
+      }
+    }
+    if (++slot == 64) {
+      flush_decisions(dec, cc, lists, list_stride, c4_keys);
+      slot = 0;
+    }
   }
+  flush_decisions(dec, cc, lists, list_stride, c4_keys);
   if (lane_id() == 0) {
     if (cur_g >= 0) flush_vertex_terms<NV>(sig, cur_g, s1, w2, d1);
     if (maxdp) atomicMax(&cc[C_MAXDP], (unsigned long long)maxdp);
     if (maxw) atomicMax(&cc[C_MAXW], (unsigned long long)maxw);
     if (maxlow) atomicMax(&cc[C_MAXLOW], (unsigned long long)maxlow);
     if (wedges) atomicAdd(&bstats[BS_WEDGES], (unsigned long long)wedges);
+    for (int q = 0; q < 3; ++q)
+      if (c4e[q]) atomicAdd(&bstats[BS_C4_S + q], (unsigned long long)c4e[q]);
   }
 }
 

@@ -343,6 +343,17 @@ __global__ void k_level0(const int32_t* __restrict__ touched, const unsigned lon
   if (gtid() == 0) { cc[C_RLIST] = (unsigned long long)nt; cc[C_LVL0 + 1] = (unsigned long long)nt; cc[C_LVL0] = 0; }
 }
 
+// Append the lanes with `take` to the region list (one atomic per wave).
+__device__ __forceinline__ void wave_append(bool take, int32_t v, int32_t* __restrict__ rlist,
+                                            unsigned long long* __restrict__ cc) {
+  const uint64_t m = __ballot(take);
+  if (!m) return;
+  unsigned long long base = 0;
+  if (lane_id() == 0) base = atomicAdd(&cc[C_RLIST], (unsigned long long)__popcll(m));
+  base = (unsigned long long)__shfl((long long)base, 0);
+  if (take) rlist[base + __popcll(m & lanemask_lt())] = v;
+}
+
 // Expand the vertices of list range [lvl_beg, lvl_end) by one hop.
 __global__ void k_expand(PoolDev P, int lvl, int32_t* __restrict__ level, int32_t* __restrict__ rlist,
                          unsigned long long* __restrict__ cc) {
@@ -351,12 +362,15 @@ __global__ void k_expand(PoolDev P, int lvl, int32_t* __restrict__ level, int32_
     const int32_t v = rlist[i];
     const uint32_t* row = P.col + P.off[v];
     const int32_t L = P.len[v];
-    for (int32_t k = lane_id(); k < L; k += 64) {
-      const uint32_t w = row[k] & GC_ID;
-      if (level[w] == LV_OUT && atomicCAS(&level[w], LV_OUT, lvl + 1) == LV_OUT) {
-        unsigned long long p = atomicAdd(&cc[C_RLIST], 1ull);
-        rlist[p] = (int32_t)w;
+    for (int32_t k0 = 0; k0 < L; k0 += 64) {
+      const int32_t k = k0 + lane_id();
+      uint32_t w = 0;
+      bool take = false;
+      if (k < L) {
+        w = row[k] & GC_ID;
+        take = level[w] == LV_OUT && atomicCAS(&level[w], LV_OUT, lvl + 1) == LV_OUT;
       }
+      wave_append(take, (int32_t)w, rlist, cc);
     }
   }
 }
@@ -367,11 +381,10 @@ __global__ void k_level_end(unsigned long long* cc, int lvl) {
 
 // Whole-graph region: every vertex with a non-empty row.
 __global__ void k_all_rows(PoolDev P, int32_t* __restrict__ rlist, unsigned long long* __restrict__ cc) {
-  for (int64_t v = gtid(); v < P.N; v += gstride()) {
-    if (P.len[v] > 0) {
-      unsigned long long p = atomicAdd(&cc[C_RLIST], 1ull);
-      rlist[p] = (int32_t)v;
-    }
+  const int64_t lim = (P.N + 63) / 64 * 64;  // whole waves take part in the appends
+  for (int64_t v = gtid(); v < lim; v += gstride()) {
+    const bool take = v < P.N && P.len[v] > 0;
+    wave_append(take, (int32_t)v, rlist, cc);
   }
 }
 

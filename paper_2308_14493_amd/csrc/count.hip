@@ -995,6 +995,62 @@ __device__ __forceinline__ void c4_block_walk(const RegionDev& R, int64_t rb, in
   __syncthreads();
 }
 
+// One window of ids [lo, ...) of hub v: every lower neighbour u_q walks its
+// row backwards from its cursor while the ids stay >= lo and leaves the
+// cursor at the first position below the window, so the slice is read once
+// and no search precedes it.  The thread reads up to C4W_SHORT entries itself,
+// four at a time; the rest of a longer slice is delimited by a gallop and
+// walked by the whole wave.  wtot += entries walked, rest += entries left
+// below the window (per thread).
+template <class F>
+__device__ __forceinline__ void c4_window_walk(const RegionDev& R, int64_t rb, int32_t nlow, const int64_t* urow,
+                                               int32_t* ucur, uint32_t lo, F f, long long& wtot, long long& rest) {
+  const int t = threadIdx.x;
+  for (int32_t c0 = 0; c0 < nlow; c0 += C4W_T) {
+    const int32_t q = c0 + t;
+    int64_t sb = 0;
+    int32_t sl = 0;
+    uint32_t fl = 0;
+    if (q < nlow) {
+      const int32_t c = ucur[q];
+      int32_t k = c;  // positions [k, c) are walked
+      if (c > 0) {
+        const int64_t base = urow[q];
+        const uint32_t* row = R.rcol + base;
+        fl = R.rcol[rb + q] & GC_FLAGS;
+        bool open = true;
+        while (open && c - k < C4W_SHORT) {
+          uint32_t y[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) y[u] = k - 1 - u >= 0 ? row[k - 1 - u] : 0u;
+          int32_t took = 0;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (open && k - 1 - u >= 0 && (y[u] & GC_ID) >= lo) {
+              f(y[u] & GC_ID, fl | (y[u] & GC_FLAGS));
+              ++took;
+            } else {
+              open = false;
+            }
+          }
+          k -= took;
+        }
+        if (open) {  // more than C4W_SHORT entries in the window
+          const int32_t p0 = gallop_down(row, k, lo);
+          sb = base + p0;
+          sl = k - p0;
+          k = p0;
+        }
+        ucur[q] = k;
+      }
+      wtot += c - k;
+      rest += k;
+    }
+    if (__ballot(sl > 0))
+      wave_walk(R.rcol, sb, sl, fl, [&](int, int64_t, uint32_t fs, uint32_t y) { f(y & GC_ID, fs | (y & GC_FLAGS)); });
+  }
+}
+
 // One hub v, versions [vsh, vsh + NF) of an NV-version pass.  Window
 // counters: NF fields of FBW bits; tail counters in global memory: one u64
 // of NF fields (64 / NF bits each).
@@ -1009,7 +1065,6 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
   int32_t* touch = A.c4_touch + (int64_t)blockIdx.x * A.N;
   int64_t* urow = A.c4_cur + (int64_t)blockIdx.x * 2 * A.c4_maxlow;
   int32_t* ucur = (int32_t*)(urow + A.c4_maxlow);
-  int32_t* unext = ucur + A.c4_maxlow;
   const int64_t rb = R.roff[v];
   const int32_t nlow = R.rlow[v];
   const uint32_t fmask = (1u << NF) - 1u;
@@ -1023,38 +1078,32 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
   int64_t hi = v;
   while (hi > 0) {
     const uint32_t lo = (uint32_t)(hi - ws > 0 ? hi - ws : 0);
-    if (t == 0) atomicAdd(&A.bstats[BS_C4_SEARCH], (unsigned long long)nlow);
-    long long wtot = 0, rest = 0;
-    for (int32_t q = t; q < nlow; q += C4W_T) {
-      const int32_t c = ucur[q];
-      const int32_t p0 = gallop_down(R.rcol + urow[q], c, lo);
-      unext[q] = p0;
-      wtot += c - p0;
-      rest += p0;
+    if (t == 0) {
+      atomicAdd(&A.bstats[BS_C4_SEARCH], (unsigned long long)nlow);
+      atomicAdd(&A.bstats[BS_C4_WINDOWS], 1ull);
     }
-    block_sum2(S.C, wtot, rest);
-    if (wtot >= A.c4_dense_min) {
-      if (t == 0) atomicAdd(&A.bstats[BS_C4_WINDOWS], 1ull);
-      WT* wn = (WT*)S.win;
-      for (int s = t; s < A.c4_win; s += C4W_T) S.win[s] = 0ull;
-      __syncthreads();
-      c4_block_walk(R, rb, nlow, urow, [&](int32_t q) { return unext[q]; }, [&](int32_t q) { return ucur[q]; },
-                    [&](uint32_t wid, uint32_t fl) {
-                      const uint32_t sub = (vpresent<NV>(fl) >> vsh) & fmask;
-                      if (sub) atomicAdd(&wn[wid - lo], WFd::spread(sub));
-                    });
-      for (int64_t s = t; s < ws; s += C4W_T) {
-        const WT c = wn[s];
-        if (c) {
+    WT* wn = (WT*)S.win;
+    for (int s = t; s < A.c4_win; s += C4W_T) S.win[s] = 0ull;
+    __syncthreads();
+    long long wtot = 0, rest = 0;
+    c4_window_walk(R, rb, nlow, urow, ucur, lo,
+                   [&](uint32_t wid, uint32_t fl) {
+                     const uint32_t sub = (vpresent<NV>(fl) >> vsh) & fmask;
+                     if (sub) atomicAdd(&wn[wid - lo], WFd::spread(sub));
+                   },
+                   wtot, rest);
+    block_sum2(S.C, wtot, rest);  // also orders the window's counter updates before the scan
+    for (int64_t s = t; s < ws; s += C4W_T) {
+      const WT c = wn[s];
+      if (c) {
 #pragma unroll
-          for (int x = 0; x < NF; ++x) acc[vsh + x] += c2(WFd::get(c, x));
-        }
+        for (int x = 0; x < NF; ++x) acc[vsh + x] += c2(WFd::get(c, x));
       }
-      for (int32_t q = t; q < nlow; q += C4W_T) ucur[q] = unext[q];
-      __syncthreads();
-      hi = lo;
-      if (rest == 0) break;
-    } else {
+    }
+    __syncthreads();
+    hi = lo;
+    if (rest == 0) break;
+    if (wtot < A.c4_dense_min) {
       // sparse from here down: every remaining wedge in global memory
       c4_block_walk(R, rb, nlow, urow, [&](int32_t) { return 0; }, [&](int32_t q) { return ucur[q]; },
                     [&](uint32_t wid, uint32_t fl) {

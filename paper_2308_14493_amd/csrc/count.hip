@@ -458,15 +458,16 @@ __device__ __forceinline__ bool Ebit(const TriL<NV>& S, int32_t p, int32_t q) { 
 
 __device__ __forceinline__ bool bit_of(const unsigned long long* m, int32_t k) { return (m[k >> 6] >> (k & 63)) & 1ull; }
 
-// One wave: slots [g0, g0 + 64) of N+(u), their out-lists flattened over
-// lanes.  only = 0: union matrix plus all triangle bookkeeping; only = x+1:
-// matrix of version x alone.
+// One wave: slots g0 + gs * l (lane l) of N+(u), their out-lists walked
+// together.  The slots of a vertex are dealt to the waves of the block in
+// turn, so every wave gets a share whatever the out-degree.  only = 0: union
+// matrix plus all triangle bookkeeping; only = x+1: matrix of version x alone.
 template <int NV>
 __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL<NV>& S, uint32_t hmask, int shift,
-                                                int32_t g0, int32_t dp, int only) {
+                                                int32_t g0, int32_t gs, int32_t dp, int only) {
   const RegionDev& R = A.R;
   const int l = lane_id();
-  const int32_t i0 = g0 + l;
+  const int32_t i0 = g0 + gs * l;
   int64_t sb = 0;
   int32_t sl = 0;
   uint32_t fi = 0;
@@ -503,7 +504,7 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL<N
   struct LongState { int32_t i; unsigned long long* Ei; uint32_t fs; TU acc; };
   wave_walk_long(
       R.rcol, sb, sl,
-      [&](int s) { return LongState{g0 + s, S.erow(g0 + s), (uint32_t)rdl32((int32_t)fi, s), (TU)0}; }, look,
+      [&](int s) { return LongState{g0 + gs * s, S.erow(g0 + gs * s), (uint32_t)rdl32((int32_t)fi, s), (TU)0}; }, look,
       [&](LongState& st, int, int64_t pos, uint32_t y, int j) { st.acc += hit(st.i, st.Ei, st.fs, pos, y, j); },
       [&](LongState& st, int) {
         const TU tot = wave_add<TU>(st.acc);
@@ -512,7 +513,7 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL<N
   wave_walk(R.rcol, sb, sl >= WALK_LONG ? 0 : sl, fi, [&](int s, int64_t pos, uint32_t fs, uint32_t y) {
     const int j = look(y);
     if (j < 0) return;
-    const int32_t i = g0 + s;
+    const int32_t i = g0 + gs * s;
     const TU add = hit(i, S.erow(i), fs, pos, y, j);
     if (add) atomicAdd(&S.tuc[i], add);
   });
@@ -568,7 +569,7 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL<NV>& S, int32_t 
       if (!absent_in(x, q)) atomicOr(&S.P[q * W + (k >> 6)], 1ull << (k & 63));
   }
   __syncthreads();
-  for (int32_t g0 = w * 64; g0 < dp; g0 += nwaves * 64) tri_large_probe<NV>(A, S, hmask, shift, g0, dp, 0);
+  for (int32_t g0 = w; g0 < dp; g0 += nwaves * 64) tri_large_probe<NV>(A, S, hmask, shift, g0, nwaves, dp, 0);
   __syncthreads();
   const int32_t ne = *S.nexc;
   if (ne <= TL_EXC) {
@@ -627,7 +628,7 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL<NV>& S, int32_t 
       __syncthreads();
       for (int64_t k = threadIdx.x; k < ew; k += blockDim.x) S.E[k] = 0ull;
       __syncthreads();
-      for (int32_t g0 = w * 64; g0 < dp; g0 += nwaves * 64) tri_large_probe<NV>(A, S, hmask, shift, g0, dp, x + 1);
+      for (int32_t g0 = w; g0 < dp; g0 += nwaves * 64) tri_large_probe<NV>(A, S, hmask, shift, g0, nwaves, dp, x + 1);
       __syncthreads();
       const int64_t c = k4_rows<NV>(S, S.P + x * W, dp, nwaves);
 #pragma unroll

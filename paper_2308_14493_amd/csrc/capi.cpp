@@ -641,7 +641,8 @@ void fill_stats(gc_graph* G, gc_batch_stats* st, const std::vector<unsigned long
   st->c4_tail_wedges = (int64_t)hb[BS_TRIPROBE];
   st->max_out_degree = (int64_t)hc[C_MAXDP];
   st->tier_tri_small = (int64_t)hc[C_LIST0 + L_TRI_S];
-  st->tier_tri_large = (int64_t)hc[C_LIST0 + L_TRI_L];
+  st->tier_tri_large = 0;
+  for (int L = L_TRI_1; L <= L_TRI_G; ++L) st->tier_tri_large += (int64_t)hc[C_LIST0 + L];
   st->tier_c4_small = (int64_t)hc[C_LIST0 + L_C4_S];
   st->tier_c4_mid = (int64_t)hc[C_LIST0 + L_C4_M];
   st->tier_c4_large = (int64_t)hc[C_LIST0 + L_C4_L];

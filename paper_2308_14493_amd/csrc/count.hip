@@ -664,13 +664,15 @@ constexpr int pow2_at_least(int x) {
   return p;
 }
 
-// Vertices with out-degree in (LO, CAP]; CAP = 0 selects the global-memory
-// scratch for everything above LO.
+// The vertices of work list L (out-degree at most CAP; CAP = 0 selects the
+// global-memory scratch), taken one at a time from the queue whose head is
+// qhead.
 template <int CAP, int THREADS, int NV>
-__global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int32_t lo_dp) {
+__global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int L, unsigned long long* qhead) {
   const RegionDev& R = A.R;
-  const int64_t n = (int64_t)A.c[C_LIST0 + L_TRI_L];
-  const int32_t* list = A.lists + L_TRI_L * A.list_stride;
+  const int64_t n = (int64_t)A.c[C_LIST0 + L];
+  const int32_t* list = A.lists + L * A.list_stride;
+  __shared__ int64_t item_s;
   int cur_g = -1;
   int64_t kacc[NV];
   zerov<NV>(kacc);
@@ -705,11 +707,19 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int32_t lo_d
     S.E = E; S.P = P; S.ids = ids; S.tuc = tuc; S.hkey = hkey; S.hval = hval; S.exc = exc; S.nexc = &nexc;
     S.W = CW;
   }
-  for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+  while (true) {
+    __syncthreads();  // every thread has read the previous item before it is replaced
+    if (threadIdx.x == 0) item_s = (int64_t)atomicAdd(qhead, 1ull);
+    __syncthreads();
+    const int64_t it = item_s;
+    if (it >= n) break;
     const int32_t u = list[it];
     const int64_t ub = R.roff[u] + R.rlow[u];
     const int32_t dp = (int32_t)(R.roff[u + 1] - ub);
-    if (dp <= lo_dp || (CAP != 0 && dp > CAP)) continue;
+    if (CAP != 0 && dp > CAP) {  // cannot happen: the lists are cut at the tier capacities
+      if (threadIdx.x == 0) atomicAdd(&A.bstats[BS_ERR], 1ull);
+      continue;
+    }
     if (CAP == 0 && dp > A.tri_cap) {  // scratch too small: the host counts again with more
       if (threadIdx.x == 0) atomicAdd(&A.bstats[BS_RETRY], 1ull);
       continue;
@@ -725,7 +735,7 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int32_t lo_d
   if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_K4, kacc);
 }
 
-template <int NV> constexpr int tl_max() { return 1280; }
+template <int NV> constexpr int tl_max() { return TRI_LDS_MAX; }
 
 // ------------------------------------------------------------ edge pass
 // After all triangles, per upper entry u -> w present in version x, with
@@ -1243,13 +1253,20 @@ void launch_count_t(const CountArgs& A, hipStream_t s, hipEvent_t* ev) {
   fill_u64_count(A.R.t, 0ull, cnt_er, 1, A.e_max, s);
   if (NV == 4) fill_u64_count(A.R.tp, 0ull, cnt_er, 2, 2 * A.e_max, s);
   hipLaunchKernelGGL(k_tri_small<NV>, dim3(cap_grid((N + 3) / 4, 8192)), dim3(256), 0, s, A);
-  // out-degree tiers (64,128] (256] (512] (1024] (TLM]: blocks sized to the slot groups
-  hipLaunchKernelGGL((k_tri_large<128, 128, NV>), dim3(cap_grid(N, 8192)), dim3(128), 0, s, A, 64);
-  hipLaunchKernelGGL((k_tri_large<256, 256, NV>), dim3(cap_grid(N, 4096)), dim3(256), 0, s, A, 128);
-  hipLaunchKernelGGL((k_tri_large<512, 512, NV>), dim3(cap_grid(N, 2048)), dim3(512), 0, s, A, 256);
-  hipLaunchKernelGGL((k_tri_large<1024, 1024, NV>), dim3(cap_grid(N, 1024)), dim3(1024), 0, s, A, 512);
-  hipLaunchKernelGGL((k_tri_large<TLM, 1024, NV>), dim3(cap_grid(N, 1024)), dim3(1024), 0, s, A, 1024);
-  hipLaunchKernelGGL((k_tri_large<0, 256, NV>), dim3(cap_grid(N, (unsigned)A.tri_slots)), dim3(256), 0, s, A, TLM);
+  // out-degree tiers (64,128] (256] (512] (1024] (TLM] and above, one list each
+  unsigned long long* qt = (unsigned long long*)(A.c + C_QTRI) - L_TRI_1;
+  hipLaunchKernelGGL((k_tri_large<128, 128, NV>), dim3(cap_grid(N, 8192)), dim3(128), 0, s, A, (int)L_TRI_1,
+                     qt + L_TRI_1);
+  hipLaunchKernelGGL((k_tri_large<256, 256, NV>), dim3(cap_grid(N, 4096)), dim3(256), 0, s, A, (int)L_TRI_2,
+                     qt + L_TRI_2);
+  hipLaunchKernelGGL((k_tri_large<512, 512, NV>), dim3(cap_grid(N, 2048)), dim3(512), 0, s, A, (int)L_TRI_3,
+                     qt + L_TRI_3);
+  hipLaunchKernelGGL((k_tri_large<1024, 1024, NV>), dim3(cap_grid(N, 1024)), dim3(1024), 0, s, A, (int)L_TRI_4,
+                     qt + L_TRI_4);
+  hipLaunchKernelGGL((k_tri_large<TLM, 1024, NV>), dim3(cap_grid(N, 1024)), dim3(1024), 0, s, A, (int)L_TRI_5,
+                     qt + L_TRI_5);
+  hipLaunchKernelGGL((k_tri_large<0, 256, NV>), dim3(cap_grid(N, (unsigned)A.tri_slots)), dim3(256), 0, s, A,
+                     (int)L_TRI_G, qt + L_TRI_G);
   if (ev) (void)hipEventRecord(ev[1], s);
   hipLaunchKernelGGL(k_edge_pass<NV>, dim3(cap_grid((A.e_max + 255) / 256, 16384)), dim3(256), 0, s, A);
   if (ev) (void)hipEventRecord(ev[2], s);

@@ -16,10 +16,26 @@ enum {
   C_MAXW,         // max wedge bound
   C_MAXLOW,       // max lower degree in the large 4-cycle tier
   C_LIST0,        // C_LIST0 + L_*: work list sizes
-  C_QHEAD = C_LIST0 + 8,  // dynamic queue head of the large 4-cycle tier
-  C_COUNT = C_QHEAD + 2
+  C_QHEAD = C_LIST0 + 12,  // dynamic queue head of the large 4-cycle tier
+  C_QTRI,                  // C_QTRI + k: queue head of list L_TRI_1 + k
+  C_COUNT = C_QTRI + 8
 };
-enum { L_TRI_S = 0, L_TRI_L, L_C4_S, L_C4_M, L_C4_L, L_NUM };
+// Work lists: triangles by out-degree (<= 64 one wave per vertex, then the
+// workgroup tiers (64,128] (128,256] (256,512] (512,1024] (1024,TRI_LDS_MAX]
+// in LDS and the global-scratch tier above), 4-cycles by wedge bound.
+enum { L_TRI_S = 0, L_TRI_1, L_TRI_2, L_TRI_3, L_TRI_4, L_TRI_5, L_TRI_G, L_C4_S, L_C4_M, L_C4_L, L_NUM };
+constexpr int TRI_LDS_MAX = 1280;
+static_assert(L_NUM <= 12, "list counters");
+
+__host__ __device__ inline int tri_list_of(int32_t dplus, int32_t small) {
+  if (dplus <= small) return L_TRI_S;
+  if (dplus <= 128) return L_TRI_1;
+  if (dplus <= 256) return L_TRI_2;
+  if (dplus <= 512) return L_TRI_3;
+  if (dplus <= 1024) return L_TRI_4;
+  if (dplus <= TRI_LDS_MAX) return L_TRI_5;
+  return L_TRI_G;
+}
 
 // Directed entry keys of the merge lists: row << bits | col, with the
 // absence mask of the edge (bit x = absent from version x) in bits 60..63.

@@ -467,7 +467,7 @@ __device__ __forceinline__ void flush_vertex_terms(unsigned long long* sig, int 
 // atomic per list reserves room for the whole group.
 struct DegDecision {
   int32_t v = -1;
-  int32_t tri = -1;  // L_TRI_S / L_TRI_L or -1
+  int32_t tri = -1;  // L_TRI_S .. L_TRI_G or -1
   int32_t c4 = -1;   // L_C4_S / L_C4_M / L_C4_L or -1
   unsigned long long key = 0;  // sort key of the large 4-cycle tier
 };
@@ -476,7 +476,7 @@ __device__ __forceinline__ void flush_decisions(DegDecision& d, unsigned long lo
                                                 int64_t list_stride, unsigned long long* c4_keys) {
   const int l = lane_id();
   for (int L = 0; L < L_NUM; ++L) {
-    const bool mine = (L <= L_TRI_L ? d.tri : d.c4) == L && d.v >= 0;
+    const bool mine = (L <= L_TRI_G ? d.tri : d.c4) == L && d.v >= 0;
     const uint64_t m = __ballot(mine);
     if (!m) continue;
     unsigned long long base = 0;
@@ -558,7 +558,7 @@ __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const in
     const bool tri = dplus >= 2, c4 = low >= 2 && wsum >= 2;
     if (lane_id() == slot) {
       dec.v = v;
-      dec.tri = tri ? (dplus <= tri_small ? L_TRI_S : L_TRI_L) : -1;
+      dec.tri = tri ? tri_list_of(dplus, tri_small) : -1;
       dec.c4 = c4 ? (wsum <= c4_small ? L_C4_S : (wsum <= c4_mid ? L_C4_M : L_C4_L)) : -1;
       if (dec.c4 == L_C4_L) {
         const uint64_t wk = wsum < 0xFFFFFFFFll ? (uint64_t)wsum : 0xFFFFFFFFull;

@@ -1031,13 +1031,18 @@ __device__ __forceinline__ void c4_window_walk(const RegionDev& R, int64_t rb, i
         fl = R.rcol[rb + q] & GC_FLAGS;
         bool open = true;
         while (open && c - k < C4W_SHORT) {
-          uint32_t y[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) y[u] = k - 1 - u >= 0 ? row[k - 1 - u] : 0u;
+          // one 16-byte load: the aligned group of four entries holding
+          // position k - 1 (its entries past k - 1 are skipped, those before
+          // the row end the walk)
+          const int64_t top = base + k - 1;
+          const int64_t ap = top & ~3ll;
+          const uint4 g4 = *(const uint4*)(R.rcol + ap);
+          const uint32_t y[4] = {g4.x, g4.y, g4.z, g4.w};
           int32_t took = 0;
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            if (open && k - 1 - u >= 0 && (y[u] & GC_ID) >= lo) {
+          for (int u = 3; u >= 0; --u) {
+            if (ap + u > top) continue;
+            if (open && ap + u >= base && (y[u] & GC_ID) >= lo) {
               f(y[u] & GC_ID, fl | (y[u] & GC_FLAGS));
               ++took;
             } else {
@@ -1045,6 +1050,7 @@ __device__ __forceinline__ void c4_window_walk(const RegionDev& R, int64_t rb, i
             }
           }
           k -= took;
+          if (k == 0) open = false;
         }
         if (open) {  // more than C4W_SHORT entries in the window
           const int32_t p0 = gallop_down(row, k, lo);

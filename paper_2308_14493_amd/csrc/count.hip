@@ -1029,28 +1029,27 @@ __device__ __forceinline__ void c4_window_walk(const RegionDev& R, int64_t rb, i
         const int64_t base = urow[q];
         const uint32_t* row = R.rcol + base;
         fl = R.rcol[rb + q] & GC_FLAGS;
+        const int32_t a0 = (int32_t)(base & 3);  // row start within its 16-byte group
         bool open = true;
         while (open && c - k < C4W_SHORT) {
           // one 16-byte load: the aligned group of four entries holding
-          // position k - 1 (its entries past k - 1 are skipped, those before
-          // the row end the walk)
-          const int64_t top = base + k - 1;
-          const int64_t ap = top & ~3ll;
-          const uint4 g4 = *(const uint4*)(R.rcol + ap);
+          // position k - 1.  Its positions in [0, k) with ids >= lo are a
+          // run ending at k - 1 (rows are sorted), so each entry is tested
+          // on its own; the walk goes on while the whole group was taken.
+          const int32_t top = k - 1;
+          const int32_t g = ((top + a0) & ~3) - a0;  // position of the group's first entry (>= -3)
+          const uint4 g4 = *(const uint4*)(row + g);
           const uint32_t y[4] = {g4.x, g4.y, g4.z, g4.w};
           int32_t took = 0;
 #pragma unroll
-          for (int u = 3; u >= 0; --u) {
-            if (ap + u > top) continue;
-            if (open && ap + u >= base && (y[u] & GC_ID) >= lo) {
-              f(y[u] & GC_ID, fl | (y[u] & GC_FLAGS));
-              ++took;
-            } else {
-              open = false;
-            }
+          for (int u = 0; u < 4; ++u) {
+            const uint32_t id = y[u] & GC_ID;
+            const bool ok = g + u >= 0 && g + u <= top && id >= lo;
+            took += ok ? 1 : 0;
+            if (ok) f(id, fl | (y[u] & GC_FLAGS));
           }
+          open = g > 0 && took == top + 1 - g;
           k -= took;
-          if (k == 0) open = false;
         }
         if (open) {  // more than C4W_SHORT entries in the window
           const int32_t p0 = gallop_down(row, k, lo);
@@ -1104,9 +1103,8 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
     __syncthreads();
     long long wtot = 0, rest = 0;
     c4_window_walk(R, rb, nlow, urow, ucur, lo,
-                   [&](uint32_t wid, uint32_t fl) {
-                     const uint32_t sub = (vpresent<NV>(fl) >> vsh) & fmask;
-                     if (sub) atomicAdd(&wn[wid - lo], WFd::spread(sub));
+                   [&](uint32_t wid, uint32_t fl) {  // adds 0 for a wedge of no version (rare)
+                     atomicAdd(&wn[wid - lo], WFd::spread((vpresent<NV>(fl) >> vsh) & fmask));
                    },
                    wtot, rest);
     block_sum2(S.C, wtot, rest);  // also orders the window's counter updates before the scan

@@ -41,35 +41,39 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) { return x * 2654435761u;
 
 __device__ __forceinline__ int32_t ld_relaxed(int32_t* p) { return __atomic_load_n(p, __ATOMIC_RELAXED); }
 
-// find key in an open-addressing table of size mask+1 (keys -1 = empty)
-__device__ __forceinline__ int lookup_slot(const int32_t* keys, const int16_t* vals, uint32_t mask, int shift,
-                                           uint32_t key) {
-  uint32_t h = hash32(key) >> shift;
-  while (true) {
-    int32_t k = keys[h];
-    if (k == (int32_t)key) return vals[h];
-    if (k == -1) return -1;
-    h = (h + 1) & mask;
+// Lookups in two steps so that the lookups of several entries overlap:
+// read() loads the first two slots of the key's run (no branch between the
+// loads and their use), pos() picks the key's position from them, going on
+// in a loop only for longer runs (rare at load factor <= 1/2), and val()
+// reads the value of a found position.
+struct HashLook {
+  const int32_t* keys;
+  const int16_t* vals;
+  uint32_t mask;
+  int shift;
+  struct Two { uint32_t h; int32_t k0, k1; };
+  __device__ __forceinline__ Two read(uint32_t key) const {
+    const uint32_t h = hash32(key) >> shift;
+    return Two{h, keys[h], keys[(h + 1) & mask]};
   }
-}
-
-// Same, with the first two slots read unconditionally (one round of LDS
-// loads for nearly every lookup at load factor <= 1/2, so that several
-// lookups of a lane overlap); the loop only continues longer runs.
-__device__ __forceinline__ int lookup_slot2(const int32_t* keys, const int16_t* vals, uint32_t mask, int shift,
-                                            uint32_t key) {
-  const uint32_t h = hash32(key) >> shift, h1 = (h + 1) & mask;
-  const int32_t k0 = keys[h], k1 = keys[h1];
-  if (k0 == (int32_t)key) return vals[h];
-  if (k0 == -1) return -1;
-  if (k1 == (int32_t)key) return vals[h1];
-  if (k1 == -1) return -1;
-  for (uint32_t q = (h1 + 1) & mask;; q = (q + 1) & mask) {
-    const int32_t k = keys[q];
-    if (k == (int32_t)key) return vals[q];
-    if (k == -1) return -1;
+  __device__ __forceinline__ int pos(const Two& t, uint32_t key) const {
+    const int32_t k = (int32_t)key;
+    int r = t.k0 == k ? (int)t.h : (t.k1 == k ? (int)((t.h + 1) & mask) : -1);
+    if (r < 0 && t.k0 != -1 && t.k1 != -1) {
+      for (uint32_t q = (t.h + 2) & mask;; q = (q + 1) & mask) {
+        const int32_t kq = keys[q];
+        if (kq == k) { r = (int)q; break; }
+        if (kq == -1) break;
+      }
+    }
+    return r;
   }
-}
+  __device__ __forceinline__ int val(int p) const { return vals[p]; }
+  __device__ __forceinline__ int find(uint32_t key) const {  // value of key, or -1
+    const int p = pos(read(key), key);
+    return p >= 0 ? val(p) : -1;
+  }
+};
 
 // add `add` to the counter of key (insert on first use)
 template <class V>
@@ -170,16 +174,18 @@ __device__ __forceinline__ T wave_add(T v) {
 }
 
 // The long lists of a wave's lanes (at least WALK_LONG entries), one at a
-// time through the whole wave: begin(s) -> per-list state; for every entry
-// look(entry) -> slot (or -1), then f(state, s, pos, entry, slot) for the
-// slots found; end(state, s).  Each lane loads four entries and looks all
-// four up before handling any, so their memory and LDS accesses overlap.  The
-// list's lane s is uniform, so per-list work can be hoisted into begin/end.
+// time through the whole wave: begin(s) -> per-list state; every entry y is
+// looked up (hl, key y & GC_ID) and f(state, s, pos, y, value) is called for
+// the keys found; end(state, s).  Each lane loads four entries (indexes
+// clamped to the list, so the loads need no branch) and reads the hash slots
+// of all four before picking any, so their memory and LDS accesses overlap.
+// The list's lane s is uniform, so per-list work can be hoisted into
+// begin/end.
 constexpr int WALK_DEPTH = 4;  // entries per lane loaded and looked up together
 
-template <class B, class L, class F, class E>
-__device__ __forceinline__ void wave_walk_long(const uint32_t* col, int64_t sb, int32_t sl, B begin, L look, F f,
-                                               E end) {
+template <class B, class F, class E>
+__device__ __forceinline__ void wave_walk_long(const uint32_t* col, int64_t sb, int32_t sl, B begin,
+                                               const HashLook& hl, F f, E end) {
   const int l = lane_id();
   uint64_t lm = __ballot(sl >= WALK_LONG);
   while (lm) {
@@ -190,14 +196,17 @@ __device__ __forceinline__ void wave_walk_long(const uint32_t* col, int64_t sb, 
     auto st = begin(s);
     for (int32_t k = l; k < n; k += 64 * WALK_DEPTH) {
       uint32_t y[WALK_DEPTH];
-      int jj[WALK_DEPTH];
+      HashLook::Two tw[WALK_DEPTH];
+      int hp[WALK_DEPTH];
 #pragma unroll
-      for (int u = 0; u < WALK_DEPTH; ++u) y[u] = k + 64 * u < n ? col[b + k + 64 * u] : 0u;
+      for (int u = 0; u < WALK_DEPTH; ++u) y[u] = col[b + min(k + 64 * u, n - 1)];
 #pragma unroll
-      for (int u = 0; u < WALK_DEPTH; ++u) jj[u] = k + 64 * u < n ? look(y[u]) : -1;
+      for (int u = 0; u < WALK_DEPTH; ++u) tw[u] = hl.read(y[u] & GC_ID);
+#pragma unroll
+      for (int u = 0; u < WALK_DEPTH; ++u) hp[u] = k + 64 * u < n ? hl.pos(tw[u], y[u] & GC_ID) : -1;
 #pragma unroll
       for (int u = 0; u < WALK_DEPTH; ++u)
-        if (jj[u] >= 0) f(st, s, b + k + 64 * u, y[u], jj[u]);
+        if (hp[u] >= 0) f(st, s, b + k + 64 * u, y[u], hl.val(hp[u]));
     }
     end(st, s);
   }
@@ -344,7 +353,7 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
     if (l < dp) { sb = R.roff[vi] + R.rlow[vi]; sl = (int32_t)(R.roff[vi + 1] - sb); }
     // one probe of list i: a hit j is the triangle (u, v_i, v_j); row i's
     // bits collect in ei (the caller writes them)
-    auto look = [&](uint32_t y) { return lookup_slot2(hkey[w], hval[w], 127u, 25, y & GC_ID); };
+    const HashLook hl{hkey[w], hval[w], 127u, 25};
     auto hit = [&](int i, int64_t pos, uint32_t fs, uint32_t y, int j, unsigned long long& ei) {
       const uint32_t fy = y & GC_FLAGS;
       const unsigned long long bj = 1ull << j, bi = 1ull << i;
@@ -362,14 +371,14 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
     struct LongState { int i; uint32_t fs; unsigned long long ei; };
     wave_walk_long(
         R.rcol, sb, sl,
-        [&](int s) { return LongState{s, (uint32_t)rdl32((int32_t)fi, s), 0ull}; }, look,
+        [&](int s) { return LongState{s, (uint32_t)rdl32((int32_t)fi, s), 0ull}; }, hl,
         [&](LongState& st, int, int64_t pos, uint32_t y, int j) { hit(st.i, pos, st.fs, y, j, st.ei); },
         [&](LongState& st, int) {
           const unsigned long long e = wave_or64(st.ei);
           if (lane_id() == 0 && e) atomicOr(&EU[w][st.i], e);
         });
     wave_walk(R.rcol, sb, sl >= WALK_LONG ? 0 : sl, fi, [&](int i, int64_t pos, uint32_t fs, uint32_t y) {
-      const int j = look(y);
+      const int j = hl.find(y & GC_ID);
       if (j < 0) return;
       unsigned long long ei = 0;
       hit(i, pos, fs, y, j, ei);
@@ -481,7 +490,7 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL<N
   using TU = typename TriL<NV>::TU;
   // one probe of list i: a hit j is the triangle (u, v_i, w_j); returns the
   // increment of t(u, v_i), which the caller adds to tuc[i]
-  auto look = [&](uint32_t y) { return lookup_slot2(S.hkey, S.hval, hmask, shift, y & GC_ID); };
+  const HashLook hl{S.hkey, S.hval, hmask, shift};
   auto hit = [&](int32_t i, unsigned long long* Ei, uint32_t fs, int64_t pos, uint32_t y, int j) -> TU {
     const uint32_t fy = y & GC_FLAGS;
     if (only) {
@@ -504,14 +513,14 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL<N
   struct LongState { int32_t i; unsigned long long* Ei; uint32_t fs; TU acc; };
   wave_walk_long(
       R.rcol, sb, sl,
-      [&](int s) { return LongState{g0 + gs * s, S.erow(g0 + gs * s), (uint32_t)rdl32((int32_t)fi, s), (TU)0}; }, look,
+      [&](int s) { return LongState{g0 + gs * s, S.erow(g0 + gs * s), (uint32_t)rdl32((int32_t)fi, s), (TU)0}; }, hl,
       [&](LongState& st, int, int64_t pos, uint32_t y, int j) { st.acc += hit(st.i, st.Ei, st.fs, pos, y, j); },
       [&](LongState& st, int) {
         const TU tot = wave_add<TU>(st.acc);
         if (lane_id() == 0 && tot) atomicAdd(&S.tuc[st.i], tot);
       });
   wave_walk(R.rcol, sb, sl >= WALK_LONG ? 0 : sl, fi, [&](int s, int64_t pos, uint32_t fs, uint32_t y) {
-    const int j = look(y);
+    const int j = hl.find(y & GC_ID);
     if (j < 0) return;
     const int32_t i = g0 + gs * s;
     const TU add = hit(i, S.erow(i), fs, pos, y, j);

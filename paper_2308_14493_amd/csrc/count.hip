@@ -45,10 +45,10 @@ __device__ __forceinline__ int32_t ld_relaxed(int32_t* p) { return __atomic_load
 // read() loads the first two slots of the key's run (no branch between the
 // loads and their use), pos() picks the key's position from them, going on
 // in a loop only for longer runs (rare at load factor <= 1/2), and val()
-// reads the value of a found position.
+// reads the 32-bit value of a position.
 struct HashLook {
   const int32_t* keys;
-  const int16_t* vals;
+  const uint32_t* vals;
   uint32_t mask;
   int shift;
   struct Two { uint32_t h; int32_t k0, k1; };
@@ -68,11 +68,8 @@ struct HashLook {
     }
     return r;
   }
-  __device__ __forceinline__ int val(int p) const { return vals[p]; }
-  __device__ __forceinline__ int find(uint32_t key) const {  // value of key, or -1
-    const int p = pos(read(key), key);
-    return p >= 0 ? val(p) : -1;
-  }
+  __device__ __forceinline__ uint32_t val(int p) const { return vals[p]; }
+  __device__ __forceinline__ int find(uint32_t key) const { return pos(read(key), key); }  // position or -1
 };
 
 // add `add` to the counter of key (insert on first use)
@@ -177,8 +174,9 @@ __device__ __forceinline__ T wave_add(T v) {
 // time through the whole wave: begin(s) -> per-list state; every entry y is
 // looked up (hl, key y & GC_ID) and f(state, s, pos, y, value) is called for
 // the keys found; end(state, s).  Each lane loads four entries (indexes
-// clamped to the list, so the loads need no branch) and reads the hash slots
-// of all four before picking any, so their memory and LDS accesses overlap.
+// clamped to the list, so the loads need no branch), reads the hash slots of
+// all four before picking any and the values of all four before handling
+// any, so their memory and LDS accesses overlap.
 // The list's lane s is uniform, so per-list work can be hoisted into
 // begin/end.
 constexpr int WALK_DEPTH = 4;  // entries per lane loaded and looked up together
@@ -195,7 +193,7 @@ __device__ __forceinline__ void wave_walk_long(const uint32_t* col, int64_t sb, 
     const int32_t n = rdl32(sl, s);
     auto st = begin(s);
     for (int32_t k = l; k < n; k += 64 * WALK_DEPTH) {
-      uint32_t y[WALK_DEPTH];
+      uint32_t y[WALK_DEPTH], jv[WALK_DEPTH];
       HashLook::Two tw[WALK_DEPTH];
       int hp[WALK_DEPTH];
 #pragma unroll
@@ -203,10 +201,15 @@ __device__ __forceinline__ void wave_walk_long(const uint32_t* col, int64_t sb, 
 #pragma unroll
       for (int u = 0; u < WALK_DEPTH; ++u) tw[u] = hl.read(y[u] & GC_ID);
 #pragma unroll
-      for (int u = 0; u < WALK_DEPTH; ++u) hp[u] = k + 64 * u < n ? hl.pos(tw[u], y[u] & GC_ID) : -1;
+      for (int u = 0; u < WALK_DEPTH; ++u) {
+        const int p = hl.pos(tw[u], y[u] & GC_ID);
+        hp[u] = k + 64 * u < n ? p : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < WALK_DEPTH; ++u) jv[u] = hl.val(max(hp[u], 0));
 #pragma unroll
       for (int u = 0; u < WALK_DEPTH; ++u)
-        if (hp[u] >= 0) f(st, s, b + k + 64 * u, y[u], hl.val(hp[u]));
+        if (hp[u] >= 0) f(st, s, b + k + 64 * u, y[u], jv[u]);
     }
     end(st, s);
   }
@@ -312,8 +315,7 @@ constexpr int TS_WAVES = 4;
 template <int NV>
 __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
   __shared__ int32_t hkey[TS_WAVES][128];
-  __shared__ int16_t hval[TS_WAVES][128];
-  __shared__ uint32_t fsl[TS_WAVES][64];
+  __shared__ uint32_t hval[TS_WAVES][128];  // slot | its flags
   __shared__ unsigned long long EU[TS_WAVES][64], TU[TS_WAVES][64];
   __shared__ unsigned long long EX[TS_WAVES][NV][64], TX[TS_WAVES][NV][64];
   __shared__ uint32_t dirty[TS_WAVES];
@@ -339,22 +341,22 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
     EU[w][l] = 0; TU[w][l] = 0;
 #pragma unroll
     for (int x = 0; x < NV; ++x) { EX[w][x][l] = 0; TX[w][x][l] = 0; }
-    fsl[w][l] = fi;
     if (l == 0) dirty[w] = 0;
     wave_sync();
     if (l < dp) {
       uint32_t h = hash32(vi) >> 25;
       while (atomicCAS(&hkey[w][h], -1, (int32_t)vi) != -1) h = (h + 1) & 127u;
-      hval[w][h] = (int16_t)l;
+      hval[w][h] = (uint32_t)l | fi;
     }
     wave_sync();
     int64_t sb = 0;
     int32_t sl = 0;
     if (l < dp) { sb = R.roff[vi] + R.rlow[vi]; sl = (int32_t)(R.roff[vi + 1] - sb); }
-    // one probe of list i: a hit j is the triangle (u, v_i, v_j); row i's
-    // bits collect in ei (the caller writes them)
+    // one probe of list i: a hit (slot j with flags, jv) is the triangle
+    // (u, v_i, v_j); row i's bits collect in ei (the caller writes them)
     const HashLook hl{hkey[w], hval[w], 127u, 25};
-    auto hit = [&](int i, int64_t pos, uint32_t fs, uint32_t y, int j, unsigned long long& ei) {
+    auto hit = [&](int i, int64_t pos, uint32_t fs, uint32_t y, uint32_t jv, unsigned long long& ei) {
+      const int j = (int)(jv & GC_ID);
       const uint32_t fy = y & GC_FLAGS;
       const unsigned long long bj = 1ull << j, bi = 1ull << i;
       ei |= bj;
@@ -365,23 +367,23 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
         for (int x = 0; x < NV; ++x)
           if (absent_in(fy, x)) { atomicOr(&EX[w][x][i], bj); atomicOr(&TX[w][x][j], bi); }
       }
-      const uint32_t pm = vpresent<NV>(fs | fsl[w][j] | fy);
+      const uint32_t pm = vpresent<NV>(fs | (jv & GC_FLAGS) | fy);
       if (pm) t_add<NV>(R, pos, pm);
     };
     struct LongState { int i; uint32_t fs; unsigned long long ei; };
     wave_walk_long(
         R.rcol, sb, sl,
         [&](int s) { return LongState{s, (uint32_t)rdl32((int32_t)fi, s), 0ull}; }, hl,
-        [&](LongState& st, int, int64_t pos, uint32_t y, int j) { hit(st.i, pos, st.fs, y, j, st.ei); },
+        [&](LongState& st, int, int64_t pos, uint32_t y, uint32_t jv) { hit(st.i, pos, st.fs, y, jv, st.ei); },
         [&](LongState& st, int) {
           const unsigned long long e = wave_or64(st.ei);
           if (lane_id() == 0 && e) atomicOr(&EU[w][st.i], e);
         });
     wave_walk(R.rcol, sb, sl >= WALK_LONG ? 0 : sl, fi, [&](int i, int64_t pos, uint32_t fs, uint32_t y) {
-      const int j = hl.find(y & GC_ID);
-      if (j < 0) return;
+      const int p = hl.find(y & GC_ID);
+      if (p < 0) return;
       unsigned long long ei = 0;
-      hit(i, pos, fs, y, j, ei);
+      hit(i, pos, fs, y, hl.val(p), ei);
       atomicOr(&EU[w][i], ei);
     });
     wave_sync();
@@ -452,7 +454,7 @@ struct TriL {
   unsigned long long* P;    // [NV][W] slot masks per version
   uint32_t* ids;            // [dp]
   int32_t* hkey;            // [H]
-  int16_t* hval;            // [H]
+  uint32_t* hval;           // [H] slot | its flags
   TU* tuc;                  // [dp]
   unsigned long long* exc;  // [TL_EXC] i << 32 | j << 4 | absence mask
   int32_t* nexc;            // [1]
@@ -488,10 +490,12 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL<N
     sl = (int32_t)(R.roff[v + 1] - sb);
   }
   using TU = typename TriL<NV>::TU;
-  // one probe of list i: a hit j is the triangle (u, v_i, w_j); returns the
-  // increment of t(u, v_i), which the caller adds to tuc[i]
+  // one probe of list i: a hit (slot j with flags, jv) is the triangle
+  // (u, v_i, w_j); returns the increment of t(u, v_i), which the caller adds
+  // to tuc[i]
   const HashLook hl{S.hkey, S.hval, hmask, shift};
-  auto hit = [&](int32_t i, unsigned long long* Ei, uint32_t fs, int64_t pos, uint32_t y, int j) -> TU {
+  auto hit = [&](int32_t i, unsigned long long* Ei, uint32_t fs, int64_t pos, uint32_t y, uint32_t jv) -> TU {
+    const int j = (int)(jv & GC_ID);
     const uint32_t fy = y & GC_FLAGS;
     if (only) {
       if (!absent_in(fy, only - 1)) atomicOr(&Ei[j >> 6], 1ull << (j & 63));
@@ -503,7 +507,7 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL<N
       if (p < TL_EXC)
         S.exc[p] = ((unsigned long long)i << 32) | ((unsigned long long)j << 4) | (unsigned long long)(fy >> GC_VSHIFT);
     }
-    const uint32_t pm = vpresent<NV>(fs | (S.ids[j] & GC_FLAGS) | fy);
+    const uint32_t pm = vpresent<NV>(fs | (jv & GC_FLAGS) | fy);
     if (!pm) return (TU)0;
     t_add<NV>(R, pos, pm);
     const TU add = Fields<NV, 16>::spread(pm);
@@ -514,16 +518,16 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL<N
   wave_walk_long(
       R.rcol, sb, sl,
       [&](int s) { return LongState{g0 + gs * s, S.erow(g0 + gs * s), (uint32_t)rdl32((int32_t)fi, s), (TU)0}; }, hl,
-      [&](LongState& st, int, int64_t pos, uint32_t y, int j) { st.acc += hit(st.i, st.Ei, st.fs, pos, y, j); },
+      [&](LongState& st, int, int64_t pos, uint32_t y, uint32_t jv) { st.acc += hit(st.i, st.Ei, st.fs, pos, y, jv); },
       [&](LongState& st, int) {
         const TU tot = wave_add<TU>(st.acc);
         if (lane_id() == 0 && tot) atomicAdd(&S.tuc[st.i], tot);
       });
   wave_walk(R.rcol, sb, sl >= WALK_LONG ? 0 : sl, fi, [&](int s, int64_t pos, uint32_t fs, uint32_t y) {
-    const int j = hl.find(y & GC_ID);
-    if (j < 0) return;
+    const int p = hl.find(y & GC_ID);
+    if (p < 0) return;
     const int32_t i = g0 + gs * s;
-    const TU add = hit(i, S.erow(i), fs, pos, y, j);
+    const TU add = hit(i, S.erow(i), fs, pos, y, hl.val(p));
     if (add) atomicAdd(&S.tuc[i], add);
   });
 }
@@ -572,7 +576,7 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL<NV>& S, int32_t 
     const uint32_t id = x & GC_ID;
     uint32_t h = hash32(id) >> shift;
     while (atomicCAS(&S.hkey[h], -1, (int32_t)id) != -1) h = (h + 1) & hmask;
-    S.hval[h] = (int16_t)k;
+    S.hval[h] = (uint32_t)k | (x & GC_FLAGS);
 #pragma unroll
     for (int q = 0; q < NV; ++q)
       if (!absent_in(x, q)) atomicOr(&S.P[q * W + (k >> 6)], 1ull << (k & 63));
@@ -660,11 +664,11 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL<NV>& S, int32_t 
 
 // global-scratch slot layout (u64 words): E [tri_words(cap, W)] | P [NV*W] |
 // tuc [cap] | exc [TL_EXC] | then u32 words: ids [cap] | hkey [4 cap] |
-// hval [2 cap] | nexc [2]
+// hval [4 cap] | nexc [2]
 template <int NV>
 __host__ __device__ inline int64_t tri_slot_words64(int64_t cap) {
   const int64_t W = (cap + 63) / 64;
-  return tri_words(cap, W) + NV * W + cap + TL_EXC + (cap + 4 * cap + 2 * cap + 2 + 1) / 2 + 8;
+  return tri_words(cap, W) + NV * W + cap + TL_EXC + (cap + 4 * cap + 4 * cap + 2 + 1) / 2 + 8;
 }
 
 constexpr int pow2_at_least(int x) {
@@ -700,8 +704,8 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int L, unsig
     uint32_t* u32 = (uint32_t*)(S.exc + TL_EXC);
     S.ids = u32;
     S.hkey = (int32_t*)(u32 + cap);
-    S.hval = (int16_t*)(u32 + 5 * cap);
-    S.nexc = (int32_t*)(u32 + 7 * cap);
+    S.hval = u32 + 5 * cap;
+    S.nexc = (int32_t*)(u32 + 9 * cap);
   } else {
     constexpr int CW = CAP / 64;
     constexpr int HC = pow2_at_least(2 * CAP);
@@ -710,7 +714,7 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int L, unsig
     __shared__ uint32_t ids[CAP];
     __shared__ TU tuc[CAP];
     __shared__ int32_t hkey[HC];
-    __shared__ int16_t hval[HC];
+    __shared__ uint32_t hval[HC];
     __shared__ unsigned long long exc[TL_EXC];
     __shared__ int32_t nexc;
     S.E = E; S.P = P; S.ids = ids; S.tuc = tuc; S.hkey = hkey; S.hval = hval; S.exc = exc; S.nexc = &nexc;

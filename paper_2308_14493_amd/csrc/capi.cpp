@@ -314,6 +314,7 @@ CountArgs make_count_args(gc_graph* G, int nv, int64_t dense_min) {
   A.c4_win = c4_window_max();
   A.c4_narrow_max = 65535;
   if (const char* e = std::getenv("GC_C4_WINDOW")) A.c4_win = std::max(64, std::min(c4_window_max(), std::atoi(e)));
+  A.c4_win &= ~1;  // the window is scanned 16 bytes at a time
   if (const char* e = std::getenv("GC_C4_NARROW_MAX")) A.c4_narrow_max = std::max(0, std::min(65535, std::atoi(e)));
   A.c4_dense_min = dense_min;
   if (const char* e = std::getenv("GC_C4_DENSE_MIN")) A.c4_dense_min = std::max<int64_t>(0, std::atoll(e));

@@ -1080,9 +1080,31 @@ __device__ __forceinline__ void c4_window_walk(const RegionDev& R, int64_t rb, i
   }
 }
 
+// Pair sums of one 16-byte piece of window counters (NF fields of FB bits
+// per counter): s[x] += c(c - 1) for the field c of version x of every
+// counter, with no branch on zero counters (0 adds 0).
+template <int NF, int FB>
+__device__ __forceinline__ void window_pairs(const uint4 q, uint64_t (&s)[NF]) {
+  const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if constexpr (FB == 16) {
+      const int x0 = NF == 2 ? 0 : 2 * (k & 1);  // four fields span two words
+      const uint32_t a = wv[k] & 0xFFFFu, b = wv[k] >> 16;
+      s[x0] += (uint64_t)(a * (a - 1u));  // < 2^32 for a < 2^16, and 0 for a = 0
+      s[x0 + 1] += (uint64_t)(b * (b - 1u));
+    } else {
+      static_assert(NF == 2 && FB == 32, "window fields");
+      const uint32_t a = wv[k];
+      s[k & 1] += (uint64_t)a * (uint64_t)(a - 1u);
+    }
+  }
+}
+
 // One hub v, versions [vsh, vsh + NF) of an NV-version pass.  Window
 // counters: NF fields of FBW bits; tail counters in global memory: one u64
-// of NF fields (64 / NF bits each).
+// of NF fields (64 / NF bits each).  The window is all zero on entry and on
+// return (each window's scan clears what it read).
 template <int NV, int NF, int FBW>
 __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_t (&acc)[NV], int64_t& tail_) {
   using WFd = Fields<NF, FBW>;
@@ -1112,8 +1134,6 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
       atomicAdd(&A.bstats[BS_C4_WINDOWS], 1ull);
     }
     WT* wn = (WT*)S.win;
-    for (int s = t; s < A.c4_win; s += C4W_T) S.win[s] = 0ull;
-    __syncthreads();
     long long wtot = 0, rest = 0;
     c4_window_walk(R, rb, nlow, urow, ucur, lo,
                    [&](uint32_t wid, uint32_t fl) {  // adds 0 for a wedge of no version (rare)
@@ -1121,12 +1141,18 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
                    },
                    wtot, rest);
     block_sum2(S.C, wtot, rest);  // also orders the window's counter updates before the scan
-    for (int64_t s = t; s < ws; s += C4W_T) {
-      const WT c = wn[s];
-      if (c) {
+    {
+      uint4* w4 = (uint4*)S.win;
+      uint64_t s2[NF];
 #pragma unroll
-        for (int x = 0; x < NF; ++x) acc[vsh + x] += c2(WFd::get(c, x));
+      for (int x = 0; x < NF; ++x) s2[x] = 0;
+      for (int qi = t; qi < A.c4_win / 2; qi += C4W_T) {
+        const uint4 q = w4[qi];
+        w4[qi] = make_uint4(0u, 0u, 0u, 0u);
+        window_pairs<NF, FBW>(q, s2);
       }
+#pragma unroll
+      for (int x = 0; x < NF; ++x) acc[vsh + x] += (int64_t)(s2[x] >> 1);  // sum of c(c - 1), all even
     }
     __syncthreads();
     hi = lo;
@@ -1167,6 +1193,7 @@ __global__ __launch_bounds__(C4W_T) void k_c4_large(CountArgs A, unsigned long l
   int64_t acc[NV];
   zerov<NV>(acc);
   int64_t tail_ = 0;
+  for (int s = t; s < A.c4_win; s += C4W_T) S.win[s] = 0ull;  // kept zero between windows
   while (true) {
     __syncthreads();  // every thread has read the previous item before it is replaced
     if (t == 0) S.item = (int64_t)atomicAdd(qhead, 1ull);

@@ -151,10 +151,10 @@ struct gc_graph {
   int64_t graph_launches = 0, graph_captures = 0;
 
   // online autotuner (speed knobs only)
-  std::vector<int64_t> tune_cands{512, 1024, 2048, 4096, 8192};
+  std::vector<int64_t> tune_cands{96, 192, 384, 768, 1536};
   std::vector<double> tune_ms, tune_wedges;
   int tune_next = 0;
-  int64_t dense_min_best = 2048;
+  int64_t dense_min_best = 256;
   double region_frac[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
 
   void* pin = nullptr;
@@ -695,7 +695,7 @@ struct PassPlan {
   int64_t cap_i = 1, cap_d = 1, cap_t = 2, max_touched = 2, union_bound = 0;
   size_t tab_words = 0, in_bytes = 0;
   int radius = 2;
-  int64_t dense_min = 2048;
+  int64_t dense_min = 256;
 };
 
 // Every device step of a pass, in stream order: upload, ingest, merge,

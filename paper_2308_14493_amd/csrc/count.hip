@@ -1080,36 +1080,37 @@ __device__ __forceinline__ void c4_window_walk(const RegionDev& R, int64_t rb, i
   }
 }
 
-// Pair sums of one 16-byte piece of window counters (NF fields of FB bits
-// per counter): s[x] += c(c - 1) for the field c of version x of every
-// counter, with no branch on zero counters (0 adds 0).
-template <int NF, int FB>
-__device__ __forceinline__ void window_pairs(const uint4 q, uint64_t (&s)[NF]) {
+// Pair sums of one 16-byte piece of single-field window counters of FB bits:
+// s += c(c - 1) for every counter c, with no branch on zero counters.
+template <int FB>
+__device__ __forceinline__ void window_pairs(const uint4 q, uint64_t& s) {
   const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if constexpr (FB == 16) {
-      const int x0 = NF == 2 ? 0 : 2 * (k & 1);  // four fields span two words
       const uint32_t a = wv[k] & 0xFFFFu, b = wv[k] >> 16;
-      s[x0] += (uint64_t)(a * (a - 1u));  // < 2^32 for a < 2^16, and 0 for a = 0
-      s[x0 + 1] += (uint64_t)(b * (b - 1u));
+      s += (uint64_t)(a * (a - 1u));  // < 2^32 for a < 2^16, and 0 for a = 0
+      s += (uint64_t)(b * (b - 1u));
     } else {
-      static_assert(NF == 2 && FB == 32, "window fields");
-      const uint32_t a = wv[k];
-      s[k & 1] += (uint64_t)a * (uint64_t)(a - 1u);
+      s += (uint64_t)wv[k] * (uint64_t)(wv[k] - 1u);
     }
   }
 }
 
-// One hub v, versions [vsh, vsh + NF) of an NV-version pass.  Window
-// counters: NF fields of FBW bits; tail counters in global memory: one u64
-// of NF fields (64 / NF bits each).  The window is all zero on entry and on
-// return (each window's scan clears what it read).
+// One hub v, versions [vsh, vsh + NF) of an NV-version pass.  The window
+// counts, per opposite vertex w, the wedges present in all NF versions
+// (c_A(w), one field of FBW bits); the wedges present in only some of them
+// (few: they hold a flagged entry) go to the block's global counters
+// (e_x(w) per version x, one u64 of NF fields of 64 / NF bits, with a
+// touched list).  With c_x = c_A + e_x,
+//   sum_w C(c_x(w), 2) = sum_w C(c_A(w), 2) + sum_{w with exceptions} (c_A e_x + C(e_x, 2)),
+// so the scan of the window serves every version and the exceptions add the
+// rest.  The tail uses the same global counters.  The window and the global
+// counters are clear on entry and on return (each pass clears what it read).
 template <int NV, int NF, int FBW>
 __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_t (&acc)[NV], int64_t& tail_) {
-  using WFd = Fields<NF, FBW>;
-  using WT = typename WFd::T;
   using TFd = Fields<NF, 64 / NF>;
+  constexpr int IPW = 32 / FBW;  // ids per 32-bit window word
   const RegionDev& R = A.R;
   const int t = threadIdx.x;
   unsigned long long* cnt = A.c4_dense + (int64_t)blockIdx.x * A.N;
@@ -1119,7 +1120,12 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
   const int64_t rb = R.roff[v];
   const int32_t nlow = R.rlow[v];
   const uint32_t fmask = (1u << NF) - 1u;
-  const int64_t ws = (int64_t)A.c4_win * 8 / (int64_t)sizeof(WT);  // ids per window
+  const int64_t ws = (int64_t)A.c4_win * 2 * IPW;  // ids per window
+  uint32_t* wc = (uint32_t*)S.win;
+  auto count_of = [&](uint32_t o) -> uint32_t {  // c_A of the id at offset o in the window
+    if constexpr (FBW == 16) return (wc[o >> 1] >> (16 * (o & 1))) & 0xFFFFu;
+    else return wc[o];
+  };
   if (t == 0) S.nt = 0;
   for (int32_t q = t; q < nlow; q += C4W_T) {
     urow[q] = R.roff[R.rcol[rb + q] & GC_ID];
@@ -1133,26 +1139,46 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
       atomicAdd(&A.bstats[BS_C4_SEARCH], (unsigned long long)nlow);
       atomicAdd(&A.bstats[BS_C4_WINDOWS], 1ull);
     }
-    WT* wn = (WT*)S.win;
     long long wtot = 0, rest = 0;
     c4_window_walk(R, rb, nlow, urow, ucur, lo,
-                   [&](uint32_t wid, uint32_t fl) {  // adds 0 for a wedge of no version (rare)
-                     atomicAdd(&wn[wid - lo], WFd::spread((vpresent<NV>(fl) >> vsh) & fmask));
+                   [&](uint32_t wid, uint32_t fl) {
+                     const uint32_t sub = (vpresent<NV>(fl) >> vsh) & fmask;
+                     const uint32_t o = wid - lo;
+                     if (sub == fmask) {
+                       if constexpr (FBW == 16) atomicAdd(&wc[o >> 1], 1u << (16 * (o & 1)));
+                       else atomicAdd(&wc[o], 1u);
+                     } else if (sub) {  // present in some versions only
+                       const unsigned long long old = atomicAdd(&cnt[wid], (unsigned long long)TFd::spread(sub));
+                       if (old == 0ull) touch[atomicAdd(&S.nt, 1)] = (int32_t)wid;
+                     }
                    },
                    wtot, rest);
-    block_sum2(S.C, wtot, rest);  // also orders the window's counter updates before the scan
+    block_sum2(S.C, wtot, rest);  // also orders the window's counter updates before the passes below
+    if (const int32_t nt = S.nt) {  // the window's exceptions
+      for (int32_t q = t; q < nt; q += C4W_T) {
+        const int32_t k = touch[q];
+        const unsigned long long e = cnt[k];
+        cnt[k] = 0ull;
+        const int64_t c = (int64_t)count_of((uint32_t)k - lo);
+#pragma unroll
+        for (int x = 0; x < NF; ++x) {
+          const int64_t ex = TFd::get(e, x);
+          acc[vsh + x] += c * ex + c2(ex);
+        }
+      }
+      __syncthreads();
+      if (t == 0) S.nt = 0;
+    }
     {
       uint4* w4 = (uint4*)S.win;
-      uint64_t s2[NF];
-#pragma unroll
-      for (int x = 0; x < NF; ++x) s2[x] = 0;
+      uint64_t s2 = 0;
       for (int qi = t; qi < A.c4_win / 2; qi += C4W_T) {
         const uint4 q = w4[qi];
         w4[qi] = make_uint4(0u, 0u, 0u, 0u);
-        window_pairs<NF, FBW>(q, s2);
+        window_pairs<FBW>(q, s2);
       }
 #pragma unroll
-      for (int x = 0; x < NF; ++x) acc[vsh + x] += (int64_t)(s2[x] >> 1);  // sum of c(c - 1), all even
+      for (int x = 0; x < NF; ++x) acc[vsh + x] += (int64_t)(s2 >> 1);  // sum of c(c - 1), all even
     }
     __syncthreads();
     hi = lo;
@@ -1176,6 +1202,7 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
         for (int x = 0; x < NF; ++x) acc[vsh + x] += c2(TFd::get(c, x));
       }
       __syncthreads();
+      if (t == 0) S.nt = 0;
       break;
     }
   }
@@ -1193,7 +1220,7 @@ __global__ __launch_bounds__(C4W_T) void k_c4_large(CountArgs A, unsigned long l
   int64_t acc[NV];
   zerov<NV>(acc);
   int64_t tail_ = 0;
-  for (int s = t; s < A.c4_win; s += C4W_T) S.win[s] = 0ull;  // kept zero between windows
+  for (int s = t; s < A.c4_win; s += C4W_T) S.win[s] = 0ull;  // kept clear between windows
   while (true) {
     __syncthreads();  // every thread has read the previous item before it is replaced
     if (t == 0) S.item = (int64_t)atomicAdd(qhead, 1ull);

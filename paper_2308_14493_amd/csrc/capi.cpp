@@ -297,7 +297,7 @@ void size_count_scratch(gc_graph* G, int nv, int64_t entries) {
   }
 }
 
-CountArgs make_count_args(gc_graph* G, int nv, int64_t dense_min) {
+CountArgs make_count_args(gc_graph* G, int nv, int64_t dense_min, bool fresh) {
   (void)nv;
   CountArgs A;
   A.R = G->rd();
@@ -317,6 +317,10 @@ CountArgs make_count_args(gc_graph* G, int nv, int64_t dense_min) {
   A.c4_win &= ~1;  // the window is scanned 16 bytes at a time
   if (const char* e = std::getenv("GC_C4_NARROW_MAX")) A.c4_narrow_max = std::max(0, std::min(65535, std::atoi(e)));
   A.c4_dense_min = dense_min;
+  // the hub windows count the wedges present in every version; in a count of
+  // a whole graph inserted into the empty one, version 0 has none
+  A.c4_ref = (1u << nv) - 1u;
+  if (fresh) A.c4_ref &= ~1u;
   if (const char* e = std::getenv("GC_C4_DENSE_MIN")) A.c4_dense_min = std::max<int64_t>(0, std::atoll(e));
   A.c4_cur = G->c4_cur.as<int64_t>();
   A.c4_maxlow = G->c4_cur_low;
@@ -371,14 +375,14 @@ void note_maxima(gc_graph* G) {
 // for more scratch (the combine and the purge then changed nothing), grow it
 // from the observed degrees and count again.  Returns the attempts made.
 int settle_retries(gc_graph* G, int nv, int radius, long long* state_d, BatchWork& W, int64_t dense_min,
-                   int64_t entries, bool purge, int64_t max_touched) {
+                   int64_t entries, bool purge, int64_t max_touched, bool fresh) {
   int attempts = 0;
   while (G->out_bst()[BS_RETRY]) {
     if (++attempts > 2) raise(GC_EDEVICE, "counting scratch still too small after two more attempts");
     note_maxima(G);
     size_count_scratch(G, nv, entries);
     reset_count_stage(G);
-    CountArgs A = make_count_args(G, nv, dense_min);
+    CountArgs A = make_count_args(G, nv, dense_min, fresh);
     enqueue_count(G, nv, radius, state_d, W, A, false);
     if (purge)
       launch_purge(G->pd(), W, max_touched, G->bits, 1u << (GC_VSHIFT + nv - 1),
@@ -605,10 +609,10 @@ void build(gc_graph* G, int32_t k, const int64_t* n, const int32_t* const* src, 
   zero_small(G);
   BatchWork W = make_work(G);
   size_count_scratch(G, 2, nd);
-  enqueue_count(G, 2, -1, G->state.as<long long>(), W, make_count_args(G, 2, 2048), false);
+  enqueue_count(G, 2, -1, G->state.as<long long>(), W, make_count_args(G, 2, G->dense_min_best, true), false);
   enqueue_readback(G, G->state.as<long long>());
   G->sync();
-  settle_retries(G, 2, -1, G->state.as<long long>(), W, 2048, nd, false, 0);
+  settle_retries(G, 2, -1, G->state.as<long long>(), W, G->dense_min_best, nd, false, 0, true);
   launch_all_flags(P, 0u, GC_ID, s);
   G->sync();
   G->entries = nd;
@@ -733,7 +737,7 @@ void enqueue_pass(gc_graph* G, const PassPlan& L, BatchIn& B, BatchWork& W, bool
   launch_mark_rows(sR, 2 * L.cap_d, ctr, C_DIRR, G->bits, W.r_beg, W.nr, W.mark, W.touched, W.tix, s);
   launch_merge(P, W, L.max_touched, 2 * L.cap_i, G->bits, G->opt.slack, bst, G->scan_tmp.p, s);
   launch_flag_rows(P, W, 2 * L.cap_d, G->bits, bst, s);
-  enqueue_count(G, L.nv, L.radius, G->state.as<long long>(), W, make_count_args(G, L.nv, L.dense_min), timed);
+  enqueue_count(G, L.nv, L.radius, G->state.as<long long>(), W, make_count_args(G, L.nv, L.dense_min, false), timed);
   launch_purge(P, W, L.max_touched, G->bits, 1u << (GC_VSHIFT + L.nv - 1), bst + BS_RETRY, G->scan_tmp.p, s);
   if (timed) HIPCHK(hipEventRecord(G->ev[8], s));
   enqueue_readback(G, G->state.as<long long>());
@@ -744,7 +748,7 @@ void enqueue_pass(gc_graph* G, const PassPlan& L, BatchIn& B, BatchWork& W, bool
 std::vector<uint64_t> pass_signature(gc_graph* G, const PassPlan& L, const CountArgs& A) {
   std::vector<uint64_t> v = {(uint64_t)L.nseg, (uint64_t)L.seq, (uint64_t)L.npass, (uint64_t)L.nv,
                              (uint64_t)L.cap_i, (uint64_t)L.cap_d, (uint64_t)(int64_t)L.radius,
-                             (uint64_t)A.c4_dense_min, (uint64_t)A.c4_win, (uint64_t)A.c4_narrow_max,
+                             (uint64_t)A.c4_dense_min, (uint64_t)A.c4_win, (uint64_t)A.c4_narrow_max, (uint64_t)A.c4_ref,
                              (uint64_t)A.c4_maxlow, (uint64_t)A.slots, (uint64_t)A.tri_cap, (uint64_t)A.e_max,
                              (uint64_t)G->arena_cap, (uint64_t)L.in_bytes, (uint64_t)G->k, (uint64_t)G->N,
                              (uint64_t)G->bits};
@@ -884,7 +888,7 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
 
   const bool use_graph = G->opt.graphs && !dev && !timed_run;
   if (use_graph) {
-    const std::vector<uint64_t> sig = pass_signature(G, L, make_count_args(G, L.nv, L.dense_min));
+    const std::vector<uint64_t> sig = pass_signature(G, L, make_count_args(G, L.nv, L.dense_min, false));
     auto it = G->graphs.find(sig);
     if (it == G->graphs.end()) {
       if (G->graphs.size() >= 32) G->drop_graphs();
@@ -912,7 +916,7 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
   }
   G->sync();
   const int retries = settle_retries(G, L.nv, L.radius, G->state.as<long long>(), W, L.dense_min, L.union_bound,
-                                     true, L.max_touched);
+                                     true, L.max_touched, false);
 
   const unsigned long long* hbp = G->out_bst();
   const std::vector<unsigned long long> hb(hbp, hbp + BS_COUNT);
@@ -1111,10 +1115,10 @@ int gc_recount_exact(gc_graph* g, int32_t graph, int64_t hi[11], uint64_t lo[11]
     zero_small(g);
     BatchWork W = make_work(g);
     size_count_scratch(g, 2, g->entries);
-    enqueue_count(g, 2, -1, g->state_tmp.as<long long>(), W, make_count_args(g, 2, 2048), false);
+    enqueue_count(g, 2, -1, g->state_tmp.as<long long>(), W, make_count_args(g, 2, g->dense_min_best, true), false);
     enqueue_readback(g, g->state_tmp.as<long long>());
     g->sync();
-    settle_retries(g, 2, -1, g->state_tmp.as<long long>(), W, 2048, g->entries, false, 0);
+    settle_retries(g, 2, -1, g->state_tmp.as<long long>(), W, g->dense_min_best, g->entries, false, 0, true);
     launch_all_flags(P, 0u, GC_ID, s);
     std::vector<long long> st(g->out_state(), g->out_state() + (size_t)g->k * ST_STRIDE);
     g->sync();

@@ -173,13 +173,12 @@ __device__ __forceinline__ T wave_add(T v) {
 // The long lists of a wave's lanes (at least WALK_LONG entries), one at a
 // time through the whole wave: begin(s) -> per-list state; every entry y is
 // looked up (hl, key y & GC_ID) and f(state, s, pos, y, value) is called for
-// the keys found; end(state, s).  Each lane loads four entries (indexes
+// the keys found; end(state, s).  Each lane loads WALK_DEPTH entries (indexes
 // clamped to the list, so the loads need no branch), reads the hash slots of
-// all four before picking any and the values of all four before handling
-// any, so their memory and LDS accesses overlap.
-// The list's lane s is uniform, so per-list work can be hoisted into
-// begin/end.
-constexpr int WALK_DEPTH = 4;  // entries per lane loaded and looked up together
+// all of them before picking any and their values before handling any, so
+// their memory and LDS accesses overlap.  The list's lane s is uniform, so
+// per-list work can be hoisted into begin/end.
+constexpr int WALK_DEPTH = 2;  // entries per lane loaded and looked up together (more waves fit than with 4)
 
 template <class B, class F, class E>
 __device__ __forceinline__ void wave_walk_long(const uint32_t* col, int64_t sb, int32_t sl, B begin,
@@ -1098,15 +1097,18 @@ __device__ __forceinline__ void window_pairs(const uint4 q, uint64_t& s) {
 }
 
 // One hub v, versions [vsh, vsh + NF) of an NV-version pass.  The window
-// counts, per opposite vertex w, the wedges present in all NF versions
-// (c_A(w), one field of FBW bits); the wedges present in only some of them
-// (few: they hold a flagged entry) go to the block's global counters
-// (e_x(w) per version x, one u64 of NF fields of 64 / NF bits, with a
-// touched list).  With c_x = c_A + e_x,
-//   sum_w C(c_x(w), 2) = sum_w C(c_A(w), 2) + sum_{w with exceptions} (c_A e_x + C(e_x, 2)),
-// so the scan of the window serves every version and the exceptions add the
-// rest.  The tail uses the same global counters.  The window and the global
-// counters are clear on entry and on return (each pass clears what it read).
+// counts, per opposite vertex w, the wedges present in exactly the reference
+// versions (c_A(w), one field of FBW bits; the reference set M is every
+// version, or every version but 0 when version 0 is the empty graph); the
+// other wedges (few: they hold a flagged entry) go to the block's global
+// counters (e_x(w) per version x, one u64 of NF fields of 64 / NF bits, with
+// a touched list).  With c_x = [x in M] c_A + e_x,
+//   sum_w C(c_x(w), 2) = [x in M] sum_w C(c_A(w), 2)
+//                        + sum_{w with exceptions} ([x in M] c_A e_x + C(e_x, 2)),
+// so one scan of the window serves every version of M and the exceptions add
+// the rest.  The tail uses the same global counters.  The window and the
+// global counters are clear on entry and on return (each pass clears what it
+// read).
 template <int NV, int NF, int FBW>
 __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_t (&acc)[NV], int64_t& tail_) {
   using TFd = Fields<NF, 64 / NF>;
@@ -1120,6 +1122,7 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
   const int64_t rb = R.roff[v];
   const int32_t nlow = R.rlow[v];
   const uint32_t fmask = (1u << NF) - 1u;
+  const uint32_t ref = (A.c4_ref >> vsh) & fmask;
   const int64_t ws = (int64_t)A.c4_win * 2 * IPW;  // ids per window
   uint32_t* wc = (uint32_t*)S.win;
   auto count_of = [&](uint32_t o) -> uint32_t {  // c_A of the id at offset o in the window
@@ -1144,7 +1147,7 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
                    [&](uint32_t wid, uint32_t fl) {
                      const uint32_t sub = (vpresent<NV>(fl) >> vsh) & fmask;
                      const uint32_t o = wid - lo;
-                     if (sub == fmask) {
+                     if (sub == ref) {
                        if constexpr (FBW == 16) atomicAdd(&wc[o >> 1], 1u << (16 * (o & 1)));
                        else atomicAdd(&wc[o], 1u);
                      } else if (sub) {  // present in some versions only
@@ -1163,7 +1166,7 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
 #pragma unroll
         for (int x = 0; x < NF; ++x) {
           const int64_t ex = TFd::get(e, x);
-          acc[vsh + x] += c * ex + c2(ex);
+          acc[vsh + x] += ((ref >> x) & 1u ? c * ex : 0) + c2(ex);
         }
       }
       __syncthreads();
@@ -1178,7 +1181,8 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
         window_pairs<FBW>(q, s2);
       }
 #pragma unroll
-      for (int x = 0; x < NF; ++x) acc[vsh + x] += (int64_t)(s2 >> 1);  // sum of c(c - 1), all even
+      for (int x = 0; x < NF; ++x)
+        if ((ref >> x) & 1u) acc[vsh + x] += (int64_t)(s2 >> 1);  // sum of c(c - 1), all even
     }
     __syncthreads();
     hi = lo;

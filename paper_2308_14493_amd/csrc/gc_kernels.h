@@ -130,6 +130,7 @@ struct CountArgs {
   int32_t c4_win;                 // 64-bit words of the LDS window of the large tier (<= c4_window_max())
   int32_t c4_narrow_max;          // up to this many lower neighbours, 16-bit counters (2x window)
   int64_t c4_dense_min;           // hits that earn a window dense LDS counters
+  uint32_t c4_ref;                // versions whose common wedges the hub windows count (the rest are exceptions)
   int64_t* c4_cur;                // [slots][2 * c4_maxlow]: row starts, cursors
   int64_t c4_maxlow;              // largest lower degree of a large-tier vertex
   unsigned long long* c4_keys;    // [N] sort keys of the large tier (written by the per-vertex pass)

@@ -139,7 +139,7 @@ struct gc_graph {
 
   // region and counting
   DevBuf roff, rcol, rrow, rlow, dver, t, tp, vpos, level, rlist, rlen, lists;
-  DevBuf c4_dense, c4_touch, c4_cur, c4_keys, c4_keys_alt, tri_scratch;
+  DevBuf c4_dense, c4_touch, c4_cur, c4_blk, c4_keys, c4_keys_alt, tri_scratch;
   int64_t c4_cur_low = 0;
   int32_t c4_slots = 0, tri_slots = 0;
   int64_t tri_cap = 0;
@@ -282,6 +282,7 @@ void size_count_scratch(gc_graph* G, int nv, int64_t entries) {
   if (G->seen_maxlow > G->c4_cur_low) G->c4_cur_low = G->seen_maxlow + G->seen_maxlow / 4 + 64;
   G->c4_cur_low = std::max<int64_t>(G->c4_cur_low, 64);
   G->c4_cur.ensure((size_t)(G->c4_slots * 2 * G->c4_cur_low) * sizeof(int64_t));
+  G->c4_blk.ensure((size_t)(N / c4_block_ids() + 2) * sizeof(int32_t));
   // triangles above the LDS tiers: scratch slots in global memory
   if (G->seen_maxdp > tri_lds_max(nv)) {
     if (G->seen_maxdp > 32767)
@@ -323,6 +324,7 @@ CountArgs make_count_args(gc_graph* G, int nv, int64_t dense_min, bool fresh) {
   if (fresh) A.c4_ref &= ~1u;
   if (const char* e = std::getenv("GC_C4_DENSE_MIN")) A.c4_dense_min = std::max<int64_t>(0, std::atoll(e));
   A.c4_cur = G->c4_cur.as<int64_t>();
+  A.c4_blk = G->c4_blk.as<int32_t>();
   A.c4_maxlow = G->c4_cur_low;
   A.c4_keys = G->c4_keys.as<unsigned long long>();
   A.c4_keys_alt = G->c4_keys_alt.as<unsigned long long>();
@@ -758,7 +760,7 @@ std::vector<uint64_t> pass_signature(gc_graph* G, const PassPlan& L, const Count
                           &G->mark, &G->tix, &G->touched, &G->dest, &G->newcap, &G->tlen, &G->tpre, &G->scratch,
                           &G->sort_tmp, &G->scan_tmp, &G->roff, &G->rcol, &G->rrow, &G->rlow, &G->dver, &G->t,
                           &G->tp, &G->vpos, &G->level, &G->rlist, &G->rlen, &G->lists, &G->c4_dense, &G->c4_touch,
-                          &G->c4_cur, &G->c4_keys, &G->c4_keys_alt, &G->tri_scratch};
+                          &G->c4_cur, &G->c4_blk, &G->c4_keys, &G->c4_keys_alt, &G->tri_scratch};
   for (const DevBuf* b : bufs) v.push_back((uint64_t)(uintptr_t)b->p);
   v.push_back((uint64_t)(uintptr_t)G->pin);
   v.push_back((uint64_t)(uintptr_t)G->pout);

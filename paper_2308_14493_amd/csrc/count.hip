@@ -944,6 +944,8 @@ __global__ __launch_bounds__(256) void k_c4_mid(CountArgs A) {
 // versions 0-1 and 2-3.
 constexpr int C4W_WIN = 18432;  // 144 KB of 64-bit words
 constexpr int C4W_T = 1024;
+constexpr int C4_BLK_LOG = 10;  // ids per entry of the row-length maxima: 1024
+constexpr int C4_BLK = 1 << C4_BLK_LOG;
 
 struct C4Chunk {
   long long red[C4W_T / 64][2];
@@ -964,6 +966,18 @@ __device__ __forceinline__ int32_t gallop_down(const uint32_t* row, int32_t c, u
   const int32_t a = c - 1 - k > 0 ? c - 1 - k : 0;   // row[a] < lo or a == 0
   const int32_t z = c - 1 - (k >> 1);                 // row[z] >= lo
   return a + lower_bound_id(row + a, z - a + 1, lo);
+}
+
+// block maximum (all threads call; result valid in every thread)
+__device__ __forceinline__ int32_t block_max32(C4Chunk& C, int32_t x) {
+  const int wv = threadIdx.x >> 6;
+  x = wave_max32(x);
+  if (lane_id() == 0) C.red[wv][0] = x;
+  __syncthreads();
+  x = 0;
+  for (int k = 0; k < C4W_T / 64; ++k) x = max(x, (int32_t)C.red[k][0]);
+  __syncthreads();
+  return x;
 }
 
 // block sum of two values (all threads call; result valid in every thread)
@@ -1086,7 +1100,15 @@ __device__ __forceinline__ void window_pairs(const uint4 q, uint64_t& s) {
   const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    if constexpr (FB == 16) {
+    if constexpr (FB == 8) {
+      uint32_t p = 0;  // four products < 2^16 each
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const uint32_t a = (wv[k] >> (8 * b)) & 0xFFu;
+        p += a * (a - 1u);
+      }
+      s += p;
+    } else if constexpr (FB == 16) {
       const uint32_t a = wv[k] & 0xFFFFu, b = wv[k] >> 16;
       s += (uint64_t)(a * (a - 1u));  // < 2^32 for a < 2^16, and 0 for a = 0
       s += (uint64_t)(b * (b - 1u));
@@ -1098,7 +1120,9 @@ __device__ __forceinline__ void window_pairs(const uint4 q, uint64_t& s) {
 
 // One hub v, versions [vsh, vsh + NF) of an NV-version pass.  The window
 // counts, per opposite vertex w, the wedges present in exactly the reference
-// versions (c_A(w), one field of FBW bits; the reference set M is every
+// versions (c_A(w), one field of FBW bits, or of 8 bits over twice the ids
+// where every row of the window's blocks has at most 255 entries, which
+// bounds c_A; the reference set M is every
 // version, or every version but 0 when version 0 is the empty graph); the
 // other wedges (few: they hold a flagged entry) go to the block's global
 // counters (e_x(w) per version x, one u64 of NF fields of 64 / NF bits, with
@@ -1125,9 +1149,11 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
   const uint32_t ref = (A.c4_ref >> vsh) & fmask;
   const int64_t ws = (int64_t)A.c4_win * 2 * IPW;  // ids per window
   uint32_t* wc = (uint32_t*)S.win;
+  // field layout of the current window: 2^sh ids of fw bits per 32-bit word
+  int sh = FBW == 16 ? 1 : 0, fw = FBW;
   auto count_of = [&](uint32_t o) -> uint32_t {  // c_A of the id at offset o in the window
-    if constexpr (FBW == 16) return (wc[o >> 1] >> (16 * (o & 1))) & 0xFFFFu;
-    else return wc[o];
+    const uint32_t im = (1u << sh) - 1u;
+    return (uint32_t)(((uint64_t)wc[o >> sh] >> (fw * (o & im))) & ((1ull << fw) - 1ull));
   };
   if (t == 0) S.nt = 0;
   for (int32_t q = t; q < nlow; q += C4W_T) {
@@ -1137,7 +1163,19 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
   __syncthreads();
   int64_t hi = v;
   while (hi > 0) {
-    const uint32_t lo = (uint32_t)(hi - ws > 0 ? hi - ws : 0);
+    int64_t wsz = ws;
+    sh = FBW == 16 ? 1 : 0;
+    fw = FBW;
+    if constexpr (FBW == 16) {
+      // 8-bit fields over twice the ids when no row there is longer than 255
+      const int64_t lo8 = hi - 2 * ws > 0 ? hi - 2 * ws : 0;
+      const int64_t b0 = lo8 >> C4_BLK_LOG, b1 = (hi - 1) >> C4_BLK_LOG;
+      int32_t m = 0;
+      for (int64_t b = b0 + t; b <= b1; b += C4W_T) m = max(m, A.c4_blk[b]);
+      if (block_max32(S.C, m) <= 255) { sh = 2; fw = 8; wsz = 2 * ws; }
+    }
+    const uint32_t lo = (uint32_t)(hi - wsz > 0 ? hi - wsz : 0);
+    const uint32_t im = (1u << sh) - 1u;
     if (t == 0) {
       atomicAdd(&A.bstats[BS_C4_SEARCH], (unsigned long long)nlow);
       atomicAdd(&A.bstats[BS_C4_WINDOWS], 1ull);
@@ -1148,8 +1186,7 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
                      const uint32_t sub = (vpresent<NV>(fl) >> vsh) & fmask;
                      const uint32_t o = wid - lo;
                      if (sub == ref) {
-                       if constexpr (FBW == 16) atomicAdd(&wc[o >> 1], 1u << (16 * (o & 1)));
-                       else atomicAdd(&wc[o], 1u);
+                       atomicAdd(&wc[o >> sh], 1u << (fw * (o & im)));
                      } else if (sub) {  // present in some versions only
                        const unsigned long long old = atomicAdd(&cnt[wid], (unsigned long long)TFd::spread(sub));
                        if (old == 0ull) touch[atomicAdd(&S.nt, 1)] = (int32_t)wid;
@@ -1178,7 +1215,8 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
       for (int qi = t; qi < A.c4_win / 2; qi += C4W_T) {
         const uint4 q = w4[qi];
         w4[qi] = make_uint4(0u, 0u, 0u, 0u);
-        window_pairs<FBW>(q, s2);
+        if (fw == 8) window_pairs<8>(q, s2);
+        else window_pairs<FBW>(q, s2);
       }
 #pragma unroll
       for (int x = 0; x < NF; ++x)
@@ -1255,6 +1293,23 @@ __global__ __launch_bounds__(C4W_T) void k_c4_large(CountArgs A, unsigned long l
   if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_C4, acc);
   tail_ = wave_sum64(tail_);
   if (lane_id() == 0 && tail_) atomicAdd(&A.bstats[BS_TRIPROBE], (unsigned long long)tail_);
+}
+
+// Largest union row length in each block of C4_BLK ids: bounds c(v, w) for
+// every w of the block, so a hub window over blocks whose rows are all at
+// most 255 long can count in 8-bit fields.  blk must be zero on entry.
+__global__ void k_c4_blkmax(const int64_t* __restrict__ roff, int64_t N, int32_t* __restrict__ blk) {
+  for (int64_t v0 = (int64_t)blockIdx.x * 256 * 4; v0 < N; v0 += (int64_t)gridDim.x * 256 * 4) {
+    int32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t v = v0 + threadIdx.x + 256 * k;
+      if (v < N) m = max(m, (int32_t)(roff[v + 1] - roff[v]));
+    }
+    // the 1024 ids of one iteration form one block (v0 is block aligned)
+    m = wave_max32(m);
+    if (lane_id() == 0 && m) atomicMax(&blk[v0 >> C4_BLK_LOG], m);
+  }
 }
 
 // hubs of the large tier in decreasing order of wedge work
@@ -1353,6 +1408,8 @@ void launch_count_t(const CountArgs& A, hipStream_t s, hipEvent_t* ev) {
   unsigned long long* sk = radix_sort_u64(A.c4_keys, A.c4_keys_alt, A.sort_tmp, N, A.c + C_LIST0 + L_C4_L, 64, s);
   hipLaunchKernelGGL(k_c4_order, dim3(cap_grid((N + 255) / 256, 1024)), dim3(256), 0, s, sk, A.c,
                      (int32_t*)(A.lists + L_C4_L * A.list_stride));
+  fill_u32((uint32_t*)A.c4_blk, 0u, N / C4_BLK + 2, s);
+  hipLaunchKernelGGL(k_c4_blkmax, dim3(cap_grid((N + 1023) / 1024, 4096)), dim3(256), 0, s, A.R.roff, N, A.c4_blk);
   hipLaunchKernelGGL(k_c4_large<NV>, dim3(cap_grid(N, (unsigned)A.slots)), dim3(C4W_T), 0, s, A,
                      (unsigned long long*)(A.c + C_QHEAD));
   if (ev) (void)hipEventRecord(ev[5], s);
@@ -1361,6 +1418,7 @@ void launch_count_t(const CountArgs& A, hipStream_t s, hipEvent_t* ev) {
 }  // namespace
 
 int32_t c4_window_max() { return C4W_WIN; }
+int32_t c4_block_ids() { return C4_BLK; }
 int64_t tri_scratch_words64(int nv, int64_t cap) {
   return nv == 2 ? tri_slot_words64<2>(cap) : tri_slot_words64<4>(cap);
 }

@@ -132,6 +132,7 @@ struct CountArgs {
   int64_t c4_dense_min;           // hits that earn a window dense LDS counters
   uint32_t c4_ref;                // versions whose common wedges the hub windows count (the rest are exceptions)
   int64_t* c4_cur;                // [slots][2 * c4_maxlow]: row starts, cursors
+  int32_t* c4_blk;                // [N / C4_BLK + 1] largest union row length per block of C4_BLK ids
   int64_t c4_maxlow;              // largest lower degree of a large-tier vertex
   unsigned long long* c4_keys;    // [N] sort keys of the large tier (written by the per-vertex pass)
   unsigned long long* c4_keys_alt;
@@ -148,6 +149,7 @@ void launch_count(int nv, const CountArgs& A, hipStream_t s,
 int64_t tri_scratch_words64(int nv, int64_t cap);  // u64 words of one triangle scratch slot
 int32_t tri_lds_max(int nv);                        // largest out-degree of the LDS triangle tiers
 int32_t c4_window_max();                            // u64 words of the LDS window of the large 4-cycle tier
+int32_t c4_block_ids();                             // ids per entry of CountArgs::c4_blk
 // Per graph g: the state after version x (x = 1 .. nv-1) goes to
 // vout[((x - 1) * k + g) * ST_STRIDE ...]; state becomes the one of version nv-1.
 // nothing is written while bstats[BS_RETRY] != 0

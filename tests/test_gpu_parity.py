@@ -296,6 +296,61 @@ def test_c4_windows_tail_and_wide_counters(monkeypatch, dense_min):
             assert got == native.static_counts(n, es, ed)
 
 
+def _two_hub_graph(n, extra, seed):
+    """Vertices A and B share the 255 lower neighbours 0..254 (each of those
+    also has 20 neighbours in a pool of low-degree vertices), so A and B top
+    the degree order, both sit in the large 4-cycle tier and c(B, A) = 255;
+    `extra` more neighbours of B lengthen its row."""
+    rng = np.random.default_rng(seed)
+    A, B = n - 2, n - 1
+    pool = np.arange(255, n - 2)
+    E = set()
+    for l in range(255):
+        E.add((l, A))
+        E.add((l, B))
+        for p in rng.choice(pool, 20, replace=False):
+            E.add((l, int(p)))
+    for p in pool[:extra]:
+        E.add((int(p), B))
+    return E, A, B
+
+
+@pytest.mark.parametrize("extra", [0, 1])
+def test_c4_window_field_width_boundary(extra):
+    """c(v, w) = 255, the largest value an 8-bit window field holds: every row
+    at most 255 long keeps 8-bit windows; one row of 256 entries switches the
+    window to 16-bit fields.  Batches then move the row lengths across the
+    boundary in both directions, and three-version passes do the same."""
+    n = 800
+    say("case c4 window field width, row of B = %d" % (255 + extra))
+    E, A, B = _two_hub_graph(n, extra, 90 + extra)
+    s, d = esorted(E)
+    with G(n, s, d, radius=0) as gr:
+        assert gr.counts() == native.static_counts(n, s, d)
+        steps = [
+            ([(300, A)], []),                     # A: 256 entries
+            ([], [(300, A), (0, B)]),             # A back to 255, c(B, A) = 254
+            ([(0, B), (301, B), (301, A)], []),   # c(B, A) = 256, both rows 256 or more
+            ([], [(301, B), (301, A), (5, A)]),
+        ]
+        for ins, dels in steps:
+            b = tuple(np.array(x, np.int32) for x in ([u for u, v in ins], [v for u, v in ins],
+                                                      [u for u, v in dels], [v for u, v in dels]))
+            got, st = gr.apply_batch(*b, stats=True)
+            assert st["tier_c4_large"] >= 2
+            oracle_apply(E, n, *b)
+            assert got == native.static_counts(n, *esorted(E))
+        seq = [tuple(np.array(x, np.int32) for x in ([310], [B], [7], [A])),
+               tuple(np.array(x, np.int32) for x in ([7], [A], [310], [B])),
+               tuple(np.array(x, np.int32) for x in ([311, 312], [A, B], [], []))]
+        rows = gr.apply_batch_seq(seq)
+        for b, r in zip(seq, rows):
+            oracle_apply(E, n, *b)
+            want = native.static_counts(n, *esorted(E))
+            assert [v & ((1 << 64) - 1) for v in r] == [v & ((1 << 64) - 1) for v in want]
+        assert gr.recount() == gr.counts()
+
+
 def test_server_results_same_alone_and_in_the_mix():
     """Requests for three graphs submitted from two host threads, interleaved:
     every ticket's counts equal the counts of the same batch sequence applied

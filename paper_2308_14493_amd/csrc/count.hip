@@ -932,16 +932,17 @@ __global__ __launch_bounds__(256) void k_c4_mid(CountArgs A) {
 
 // Large tier: one workgroup per hub v at a time, hubs in decreasing order of
 // wedge work.  The opposite vertices w < v are taken in windows of ids from
-// v downwards; a window with enough hits gets dense LDS counters (16-bit
-// fields while c(v, w) <= 65535 can be guaranteed, which widens the window).
-// Hits concentrate just below v because ids are a degree order and a wedge
-// reaches w with odds growing with deg w.  Once a window is sparse, all
-// wedges below it go to dense counters in global memory (one array per
-// resident workgroup, with a touched list).  Each lower neighbour u keeps a
-// cursor in its row: one binary search for v, then a short backward gallop
-// per window, so rows are read about once.  Four versions with 32-bit
-// fields would not fit a 64-bit counter: such hubs are walked twice, for
-// versions 0-1 and 2-3.
+// v downwards, each with dense LDS counters: one field per w for the wedges
+// present in every version (8 bits where no row of the window exceeds 255
+// entries, else 16 bits while c(v, w) <= 65535 can be guaranteed, else 32),
+// the other wedges in per-version global counters.  Hits concentrate just
+// below v because ids are a degree order and a wedge reaches w with odds
+// growing with deg w.  Once a window is sparse, all wedges below it go to
+// the global counters (one array per resident workgroup, with a touched
+// list).  Each lower neighbour u keeps a cursor in its row, starting at v's
+// position, and walks it backwards window by window, so rows are read about
+// once.  Four versions with 32-bit fields would not fit a 64-bit counter:
+// such hubs are walked twice, for versions 0-1 and 2-3.
 constexpr int C4W_WIN = 18432;  // 144 KB of 64-bit words
 constexpr int C4W_T = 1024;
 constexpr int C4_BLK_LOG = 10;  // ids per entry of the row-length maxima: 1024

@@ -313,8 +313,8 @@ constexpr int TS_WAVES = 4;
 
 template <int NV>
 __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
-  __shared__ int32_t hkey[TS_WAVES][256];  // load factor <= 1/4
-  __shared__ uint32_t hval[TS_WAVES][256];  // slot | its flags
+  __shared__ int32_t hkey[TS_WAVES][512];  // load factor <= 1/8
+  __shared__ uint32_t hval[TS_WAVES][512];  // slot | its flags
   __shared__ unsigned long long EU[TS_WAVES][64], TU[TS_WAVES][64];
   __shared__ unsigned long long EX[TS_WAVES][NV][64], TX[TS_WAVES][NV][64];
   __shared__ uint32_t dirty[TS_WAVES];
@@ -337,15 +337,15 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
     uint32_t vi = 0, fi = 0;
     if (l < dp) { const uint32_t x = R.rcol[ub + l]; vi = x & GC_ID; fi = x & GC_FLAGS; }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) hkey[w][l + 64 * q] = -1;
+    for (int q = 0; q < 8; ++q) hkey[w][l + 64 * q] = -1;
     EU[w][l] = 0; TU[w][l] = 0;
 #pragma unroll
     for (int x = 0; x < NV; ++x) { EX[w][x][l] = 0; TX[w][x][l] = 0; }
     if (l == 0) dirty[w] = 0;
     wave_sync();
     if (l < dp) {
-      uint32_t h = hash32(vi) >> 24;
-      while (atomicCAS(&hkey[w][h], -1, (int32_t)vi) != -1) h = (h + 1) & 255u;
+      uint32_t h = hash32(vi) >> 23;
+      while (atomicCAS(&hkey[w][h], -1, (int32_t)vi) != -1) h = (h + 1) & 511u;
       hval[w][h] = (uint32_t)l | fi;
     }
     wave_sync();
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
     if (l < dp) { sb = R.roff[vi] + R.rlow[vi]; sl = (int32_t)(R.roff[vi + 1] - sb); }
     // one probe of list i: a hit (slot j with flags, jv) is the triangle
     // (u, v_i, v_j); row i's bits collect in ei (the caller writes them)
-    const HashLook hl{hkey[w], hval[w], 255u, 24};
+    const HashLook hl{hkey[w], hval[w], 511u, 23};
     auto hit = [&](int i, int64_t pos, uint32_t fs, uint32_t y, uint32_t jv, unsigned long long& ei) {
       const int j = (int)(jv & GC_ID);
       const uint32_t fy = y & GC_FLAGS;
@@ -561,10 +561,10 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL<NV>& S, int32_t 
   const int w = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
   const int32_t W = S.W;
-  // load factor <= 1/4 where the table has room, else <= 1/2
+  // load factor <= 1/8 where the table has room, else as low as it allows
   int H = 1;
-  while (H < 4 * dp) H <<= 1;
-  if (H > S.hcap) H >>= 1;
+  while (H < 8 * dp) H <<= 1;
+  while (H > S.hcap) H >>= 1;
   const uint32_t hmask = (uint32_t)H - 1u;
   const int shift = 32 - log2i((uint32_t)H);
   for (int32_t k = threadIdx.x; k < dp; k += blockDim.x) { S.ids[k] = R.rcol[ub + k]; S.tuc[k] = 0; }
@@ -714,7 +714,7 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int L, unsig
     S.hcap = hc;
   } else {
     constexpr int CW = CAP / 64;
-    constexpr int HC = CAP <= 1024 ? pow2_at_least(4 * CAP) : pow2_at_least(2 * CAP);
+    constexpr int HC = CAP <= 1024 ? pow2_at_least(8 * CAP) : pow2_at_least(2 * CAP);
     __shared__ unsigned long long E[32 * CW * CW + 32 * CW];  // tri_words(CAP, CW)
     __shared__ unsigned long long P[NV * CW];
     __shared__ uint32_t ids[CAP];

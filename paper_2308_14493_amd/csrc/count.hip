@@ -764,8 +764,10 @@ template <int NV> constexpr int tl_max() { return TRI_LDS_MAX; }
 //   T3  += t                        (= 3 T)
 //   PAW2 += t (d_u + d_w - 4)       (= 2 N_paw: a triangle on the edge plus a
 //                                    pendant edge at one of its ends)
-// One thread per entry, grid-stride: consecutive lanes read consecutive
-// entries (row ids come from the region build).
+// One thread per entry: each workgroup takes one contiguous range of the
+// entries, consecutive lanes read consecutive entries (row ids come from the
+// region build), and a lane meets a new graph of a pool only at a graph
+// boundary of its range, so its per-graph sums are flushed rarely.
 template <int NV>
 __device__ __forceinline__ void edge_flush_lane(unsigned long long* sig, int g, int64_t (&acc)[4][NV]) {
   const int keys[4] = {SG_S2, SG_DIA, SG_T, SG_PAW};
@@ -786,7 +788,9 @@ __global__ __launch_bounds__(256) void k_edge_pass(CountArgs A) {
   int64_t acc[4][NV];  // s2, dia, t3, paw2 per version
 #pragma unroll
   for (int k = 0; k < 4; ++k) zerov<NV>(acc[k]);
-  for (int64_t p = gtid(); p < E; p += gstride()) {
+  const int64_t per = ((E + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
+  const int64_t end = min(E, per * (blockIdx.x + 1));
+  for (int64_t p = per * blockIdx.x + threadIdx.x; p < end; p += 256) {
     const uint32_t x = R.rcol[p];
     const uint32_t wv = x & GC_ID;
     const int32_t u = R.rrow[p];
@@ -811,17 +815,46 @@ __global__ __launch_bounds__(256) void k_edge_pass(CountArgs A) {
       acc[3][q] += t[q] * (du[q] + dw[q] - 4);
     }
   }
-  // wave-uniform graph: one atomic per wave, else per lane
-  const int g0 = __shfl(cur_g, 0);
-  const bool uniform = __ballot(cur_g == g0 || cur_g < 0) == ~0ull && g0 >= 0;
-  if (uniform) {
+  // Sums of a wave that worked for one graph (or none) go through a block
+  // reduction: one atomic per value and block when every wave of the block
+  // has the same graph (many atomics on the few words of one graph would
+  // queue at one L2 channel), else one per value and wave.  Lanes that saw
+  // several graphs flush on their own.
+  __shared__ int64_t red[4][4 * NV];
+  __shared__ int wg[4];
+  const int wv_ = threadIdx.x >> 6;
+  int g0 = __shfl(cur_g, 0);
+  for (int l = 1; l < 64 && g0 < 0; ++l) g0 = __shfl(cur_g, l);
+  const bool wuni = __ballot(cur_g == g0 || cur_g < 0) == ~0ull;
+  if (!wuni && cur_g >= 0) edge_flush_lane<NV>(A.sig, cur_g, acc);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int64_t v = wave_sum64(wuni ? acc[k][q] : 0);
+      if (lane_id() == 0) red[wv_][k * NV + q] = v;
+    }
+  if (lane_id() == 0) wg[wv_] = wuni ? g0 : -1;
+  __syncthreads();
+  if (threadIdx.x < 4 * NV) {
     const int keys[4] = {SG_S2, SG_DIA, SG_T, SG_PAW};
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int q = 0; q < NV; ++q) flush_sig(A.sig, g0, q, keys[k], acc[k][q]);
-  } else if (cur_g >= 0) {
-    edge_flush_lane<NV>(A.sig, cur_g, acc);
+    const int k = threadIdx.x / NV, q = threadIdx.x % NV;
+    int gb = -1;
+    bool same = true;
+    for (int w = 0; w < 4; ++w) {
+      if (wg[w] < 0) continue;
+      if (gb < 0) gb = wg[w];
+      else if (wg[w] != gb) same = false;
+    }
+    if (same) {
+      int64_t v = 0;
+      for (int w = 0; w < 4; ++w) v += red[w][threadIdx.x];
+      if (gb >= 0 && v) atomicAdd(&A.sig[SIG_IDX(gb, q, keys[k])], (unsigned long long)v);
+    } else {
+      for (int w = 0; w < 4; ++w)
+        if (wg[w] >= 0 && red[w][threadIdx.x])
+          atomicAdd(&A.sig[SIG_IDX(wg[w], q, keys[k])], (unsigned long long)red[w][threadIdx.x]);
+    }
   }
 }
 
@@ -1407,7 +1440,8 @@ void launch_count_t(const CountArgs& A, hipStream_t s, hipEvent_t* ev) {
   hipLaunchKernelGGL((k_tri_large<0, 256, NV>), dim3(cap_grid(N, (unsigned)A.tri_slots)), dim3(256), 0, s, A,
                      (int)L_TRI_G, qt + L_TRI_G);
   if (ev) (void)hipEventRecord(ev[1], s);
-  hipLaunchKernelGGL(k_edge_pass<NV>, dim3(cap_grid((A.e_max + 255) / 256, 16384)), dim3(256), 0, s, A);
+  // at least 4096 entries per workgroup: few flushes of per-graph sums
+  hipLaunchKernelGGL(k_edge_pass<NV>, dim3(cap_grid((A.e_max + 4095) / 4096, 2048)), dim3(256), 0, s, A);
   if (ev) (void)hipEventRecord(ev[2], s);
   hipLaunchKernelGGL(k_c4_small<NV>, dim3(cap_grid((N + 3) / 4, 8192)), dim3(256), 0, s, A);
   if (ev) (void)hipEventRecord(ev[3], s);

@@ -581,14 +581,64 @@ __global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const in
     }
   }
   flush_decisions(dec, cc, lists, list_stride, c4_keys);
+  // The waves' totals (held by lane 0) meet in LDS: one set of atomics per
+  // workgroup instead of per wave (the few words of one graph's sums and the
+  // shared maxima would otherwise queue at one L2 channel).
+  constexpr int NW = TPB / 64, NR = 3 * NV + 7;
+  __shared__ int64_t red[NW][NR];
+  __shared__ int wg[NW];
+  const int wv = threadIdx.x >> 6;
   if (lane_id() == 0) {
-    if (cur_g >= 0) flush_vertex_terms<NV>(sig, cur_g, s1, w2, d1);
-    if (maxdp) atomicMax(&cc[C_MAXDP], (unsigned long long)maxdp);
-    if (maxw) atomicMax(&cc[C_MAXW], (unsigned long long)maxw);
-    if (maxlow) atomicMax(&cc[C_MAXLOW], (unsigned long long)maxlow);
-    if (wedges) atomicAdd(&bstats[BS_WEDGES], (unsigned long long)wedges);
+    wg[wv] = cur_g;
+#pragma unroll
+    for (int x = 0; x < NV; ++x) { red[wv][x] = s1[x]; red[wv][NV + x] = w2[x]; red[wv][2 * NV + x] = d1[x]; }
+    red[wv][3 * NV] = maxdp;
+    red[wv][3 * NV + 1] = maxw;
+    red[wv][3 * NV + 2] = maxlow;
+    red[wv][3 * NV + 3] = wedges;
+    for (int q = 0; q < 3; ++q) red[wv][3 * NV + 4 + q] = c4e[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int gb = -1;
+    bool same = true;
+    for (int w = 0; w < NW; ++w) {
+      if (wg[w] < 0) continue;
+      if (gb < 0) gb = wg[w];
+      else if (wg[w] != gb) same = false;
+    }
+    int64_t t1[NV], t2[NV], t3[NV];
+    if (same) {  // one graph (or none): sum the waves, one flush
+#pragma unroll
+      for (int x = 0; x < NV; ++x) { t1[x] = 0; t2[x] = 0; t3[x] = 0; }
+      for (int w = 0; w < NW; ++w) {
+        if (wg[w] < 0) continue;
+#pragma unroll
+        for (int x = 0; x < NV; ++x) { t1[x] += red[w][x]; t2[x] += red[w][NV + x]; t3[x] += red[w][2 * NV + x]; }
+      }
+      if (gb >= 0) flush_vertex_terms<NV>(sig, gb, t1, t2, t3);
+    } else {  // waves of different graphs of a pool: one flush each
+      for (int w = 0; w < NW; ++w) {
+        if (wg[w] < 0) continue;
+#pragma unroll
+        for (int x = 0; x < NV; ++x) { t1[x] = red[w][x]; t2[x] = red[w][NV + x]; t3[x] = red[w][2 * NV + x]; }
+        flush_vertex_terms<NV>(sig, wg[w], t1, t2, t3);
+      }
+    }
+    int64_t mdp = 0, mw = 0, ml = 0, wd = 0, ce[3] = {0, 0, 0};
+    for (int w = 0; w < NW; ++w) {
+      mdp = max(mdp, red[w][3 * NV]);
+      mw = max(mw, red[w][3 * NV + 1]);
+      ml = max(ml, red[w][3 * NV + 2]);
+      wd += red[w][3 * NV + 3];
+      for (int q = 0; q < 3; ++q) ce[q] += red[w][3 * NV + 4 + q];
+    }
+    if (mdp) atomicMax(&cc[C_MAXDP], (unsigned long long)mdp);
+    if (mw) atomicMax(&cc[C_MAXW], (unsigned long long)mw);
+    if (ml) atomicMax(&cc[C_MAXLOW], (unsigned long long)ml);
+    if (wd) atomicAdd(&bstats[BS_WEDGES], (unsigned long long)wd);
     for (int q = 0; q < 3; ++q)
-      if (c4e[q]) atomicAdd(&bstats[BS_C4_S + q], (unsigned long long)c4e[q]);
+      if (ce[q]) atomicAdd(&bstats[BS_C4_S + q], (unsigned long long)ce[q]);
   }
 }
 
@@ -840,11 +890,13 @@ void launch_region_fill(const PoolDev& P, const RegionDev& R, const BatchWork& W
 void launch_degrees(int nv, const RegionDev& R, const int32_t* gid, const int32_t* rlist, unsigned long long* c,
                     unsigned long long* sig, int32_t* lists, int64_t list_stride, int32_t tri_small, int32_t c4_small,
                     int32_t c4_mid, unsigned long long* bstats, unsigned long long* c4_keys, hipStream_t s) {
+  // at least 1024 vertices (list_stride = N bounds the region) per workgroup
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (list_stride + 1023) / 1024));
   if (nv == 2)
-    hipLaunchKernelGGL(k_degrees<2>, dim3(4096), dim3(TPB), 0, s, R, gid, rlist, c, sig, lists, list_stride,
+    hipLaunchKernelGGL(k_degrees<2>, dim3(grid), dim3(TPB), 0, s, R, gid, rlist, c, sig, lists, list_stride,
                        tri_small, c4_small, c4_mid, bstats, c4_keys);
   else
-    hipLaunchKernelGGL(k_degrees<4>, dim3(4096), dim3(TPB), 0, s, R, gid, rlist, c, sig, lists, list_stride,
+    hipLaunchKernelGGL(k_degrees<4>, dim3(grid), dim3(TPB), 0, s, R, gid, rlist, c, sig, lists, list_stride,
                        tri_small, c4_small, c4_mid, bstats, c4_keys);
 }
 

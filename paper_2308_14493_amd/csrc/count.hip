@@ -1038,7 +1038,7 @@ __device__ __forceinline__ void block_sum2(C4Chunk& C, long long& x, long long& 
 // Thread q takes u_q: short slices (the common case: u_q has few entries in
 // the id range) are walked by their own thread, long ones by their whole
 // wave, one at a time (wave_walk).
-constexpr int32_t C4W_SHORT = 32;
+constexpr int32_t C4W_SHORT = 128;  // entries a thread walks itself before the gallop
 
 template <class P0, class P1, class F>
 __device__ __forceinline__ void c4_block_walk(const RegionDev& R, int64_t rb, int32_t nlow, const int64_t* urow,

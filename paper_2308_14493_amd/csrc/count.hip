@@ -178,7 +178,7 @@ __device__ __forceinline__ T wave_add(T v) {
 // all of them before picking any and their values before handling any, so
 // their memory and LDS accesses overlap.  The list's lane s is uniform, so
 // per-list work can be hoisted into begin/end.
-constexpr int WALK_DEPTH = 2;  // entries per lane loaded and looked up together (more waves fit than with 4)
+constexpr int WALK_DEPTH = 3;  // entries per lane loaded and looked up together (more waves fit than with 4)
 
 template <class B, class F, class E>
 __device__ __forceinline__ void wave_walk_long(const uint32_t* col, int64_t sb, int32_t sl, B begin,
@@ -313,8 +313,8 @@ constexpr int TS_WAVES = 4;
 
 template <int NV>
 __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
-  __shared__ int32_t hkey[TS_WAVES][512];  // load factor <= 1/8
-  __shared__ uint32_t hval[TS_WAVES][512];  // slot | its flags
+  __shared__ int32_t hkey[TS_WAVES][256];  // load factor <= 1/4
+  __shared__ uint32_t hval[TS_WAVES][256];  // slot | its flags
   __shared__ unsigned long long EU[TS_WAVES][64], TU[TS_WAVES][64];
   __shared__ unsigned long long EX[TS_WAVES][NV][64], TX[TS_WAVES][NV][64];
   __shared__ uint32_t dirty[TS_WAVES];
@@ -337,15 +337,15 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
     uint32_t vi = 0, fi = 0;
     if (l < dp) { const uint32_t x = R.rcol[ub + l]; vi = x & GC_ID; fi = x & GC_FLAGS; }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) hkey[w][l + 64 * q] = -1;
+    for (int q = 0; q < 4; ++q) hkey[w][l + 64 * q] = -1;
     EU[w][l] = 0; TU[w][l] = 0;
 #pragma unroll
     for (int x = 0; x < NV; ++x) { EX[w][x][l] = 0; TX[w][x][l] = 0; }
     if (l == 0) dirty[w] = 0;
     wave_sync();
     if (l < dp) {
-      uint32_t h = hash32(vi) >> 23;
-      while (atomicCAS(&hkey[w][h], -1, (int32_t)vi) != -1) h = (h + 1) & 511u;
+      uint32_t h = hash32(vi) >> 24;
+      while (atomicCAS(&hkey[w][h], -1, (int32_t)vi) != -1) h = (h + 1) & 255u;
       hval[w][h] = (uint32_t)l | fi;
     }
     wave_sync();
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
     if (l < dp) { sb = R.roff[vi] + R.rlow[vi]; sl = (int32_t)(R.roff[vi + 1] - sb); }
     // one probe of list i: a hit (slot j with flags, jv) is the triangle
     // (u, v_i, v_j); row i's bits collect in ei (the caller writes them)
-    const HashLook hl{hkey[w], hval[w], 511u, 23};
+    const HashLook hl{hkey[w], hval[w], 255u, 24};
     auto hit = [&](int i, int64_t pos, uint32_t fs, uint32_t y, uint32_t jv, unsigned long long& ei) {
       const int j = (int)(jv & GC_ID);
       const uint32_t fy = y & GC_FLAGS;

@@ -117,7 +117,7 @@ typedef struct {
   int64_t region_vertices, region_entries;  /* region size (entries = 2 x edges) */
   int64_t wedges;                    /* 4-cycle wedges enumerated */
   int64_t c4_entries_small, c4_entries_mid, c4_entries_large;  /* adjacency entries read per 4-cycle tier */
-  int64_t c4_tail_wedges;            /* wedges of the large tier counted in global memory */
+  int64_t c4_tail_wedges;            /* wedges of the large tier counted in the global tail (below the windows) */
   int64_t max_out_degree;
   int64_t tier_tri_small, tier_tri_large, tier_c4_small, tier_c4_mid, tier_c4_large;  /* vertices per tier */
   int64_t c4_dense_min;              /* hub-window density threshold used */
@@ -130,7 +130,7 @@ typedef struct {
   float ms_c4_small, ms_c4_mid, ms_c4_large;  /* 4-cycle tiers (device) */
   float ms_finish;                   /* combine + purge (device) */
   int64_t c4_windows;                /* dense LDS windows of the large 4-cycle tier */
-  int64_t c4_searches;               /* cursor searches of that tier (lower neighbours x window passes) */
+  int64_t c4_searches;               /* cursor visits of that tier (lower neighbours x window passes) */
 } gc_batch_stats;
 
 /* One batch for one graph of a pool (host pointers). */

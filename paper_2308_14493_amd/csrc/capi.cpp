@@ -818,7 +818,12 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
     } else {
       L.dense_min = G->dense_min_best;
     }
-    if (L.radius >= 2 && G->region_frac[decade] >= 0.9) L.radius = -1;  // exact radii only
+    // whole-graph mode once a batch no larger than this one saw a region of
+    // >= 90% of the entries (a larger batch's region covers at least as much
+    // in expectation); exact radii only
+    bool wide = false;
+    for (int d = 0; d <= decade; ++d) wide = wide || G->region_frac[d] >= 0.9;
+    if (L.radius >= 2 && wide) L.radius = -1;
   }
   const bool timed_run = timed || (G->opt.autotune && tune_idx >= 0);
 

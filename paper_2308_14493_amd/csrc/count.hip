@@ -114,13 +114,13 @@ __device__ __forceinline__ int64_t rdl64(int64_t v, int lane) {
 // entry array col, with a 32-bit payload pl) calling f(list lane, position,
 // payload of that lane, entry).  Lists of at least WALK_LONG entries go one
 // at a time through the whole wave (consecutive lanes read consecutive
-// entries, four loads in flight per lane; the list's lane is read with scalar
+// entries, D loads in flight per lane; the list's lane is read with scalar
 // reads); the others are flattened over the lanes with a segment search per
 // step.  Most entries sit in long lists, which then cost no cross-lane
 // traffic.  All lanes must call it.
 constexpr int32_t WALK_LONG = 32;
 
-template <class F>
+template <int D = 4, class F>
 __device__ __forceinline__ void wave_walk(const uint32_t* col, int64_t sb, int32_t sl, uint32_t pl, F f) {
   const int l = lane_id();
   const bool lng = sl >= WALK_LONG;
@@ -131,12 +131,12 @@ __device__ __forceinline__ void wave_walk(const uint32_t* col, int64_t sb, int32
     const int64_t b = rdl64(sb, s);
     const int32_t n = rdl32(sl, s);
     const uint32_t ps = (uint32_t)rdl32((int32_t)pl, s);
-    for (int32_t k = l; k < n; k += 256) {
-      uint32_t y[4];
+    for (int32_t k = l; k < n; k += 64 * D) {
+      uint32_t y[D];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) y[u] = k + 64 * u < n ? col[b + k + 64 * u] : 0u;
+      for (int u = 0; u < D; ++u) y[u] = k + 64 * u < n ? col[b + k + 64 * u] : 0u;
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < D; ++u)
         if (k + 64 * u < n) f(s, b + k + 64 * u, ps, y[u]);
     }
   }
@@ -1130,8 +1130,8 @@ __device__ __forceinline__ void c4_window_walk(const RegionDev& R, int64_t rb, i
       wtot += c - k;
       rest += k;
     }
-    if (__ballot(sl > 0))
-      wave_walk(R.rcol, sb, sl, fl, [&](int, int64_t, uint32_t fs, uint32_t y) { f(y & GC_ID, fs | (y & GC_FLAGS)); });
+    if (__ballot(sl > 0))  // slices this long run to hundreds of entries: eight loads in flight per lane
+      wave_walk<8>(R.rcol, sb, sl, fl, [&](int, int64_t, uint32_t fs, uint32_t y) { f(y & GC_ID, fs | (y & GC_FLAGS)); });
   }
 }
 

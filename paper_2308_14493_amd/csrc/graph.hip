@@ -491,103 +491,194 @@ __device__ __forceinline__ void flush_decisions(DegDecision& d, unsigned long lo
   d = DegDecision();
 }
 
+// Segment of entry idx of a wave's concatenated lists: the last lane s whose
+// exclusive prefix excl(s) is <= idx (excl nondecreasing over the lanes,
+// excl(0) = 0, idx below the total).  All lanes must call it.
+__device__ __forceinline__ int wave_segment(int32_t excl, int32_t idx) {
+  int lo = 0, hi = 64;
+#pragma unroll
+  for (int st = 0; st < 6; ++st) {
+    const int mid = (lo + hi) >> 1;
+    if (__shfl(excl, mid) <= idx) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int64_t wave_max64(int64_t v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const int64_t t = __shfl_xor(v, o);
+    v = t > v ? t : v;
+  }
+  return v;
+}
+
+// a value equal in every lane, read from the first one (scalar registers)
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// rows at least this long are walked by the whole wave, one at a time
+constexpr int32_t DEG_WAVE_ROW = 1 << 16;
+
+// A wave takes a group of 64 region vertices at a time, one per lane: the
+// rows of the shorter ones are concatenated and dealt over the lanes (a
+// segment search per step), so the lanes' searches for v in the rows of its
+// lower neighbours overlap instead of one vertex's chain of loads at a time;
+// the per-vertex sums meet in LDS, one slot per lane.
 template <int NV>
-__global__ void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const int32_t* __restrict__ rlist,
+__global__ __launch_bounds__(TPB) void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const int32_t* __restrict__ rlist,
                           unsigned long long* __restrict__ cc, unsigned long long* __restrict__ sig,
                           int32_t* __restrict__ lists, int64_t list_stride, int32_t tri_small, int32_t c4_small,
                           int32_t c4_mid, unsigned long long* __restrict__ bstats,
                           unsigned long long* __restrict__ c4_keys) {
+  __shared__ uint32_t sdv[TPB / 64][NV][64];          // degree per version
+  __shared__ uint32_t slow[TPB / 64][64];             // lower entries
+  __shared__ unsigned long long sws[TPB / 64][64];    // wedge bound
+  const int l = lane_id(), wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int x = 0; x < NV; ++x) sdv[wv][x][l] = 0u;
+  slow[wv][l] = 0u;
+  sws[wv][l] = 0ull;
+  wave_sync();
   const int64_t n = ctr(cc, C_RLIST);
-  int cur_g = -1;
-  int32_t maxlow = 0;
+  int cur_g = -1;  // graph of the running sums s1, w2, d1 (lane 0)
   int64_t s1[NV], w2[NV], d1[NV];
 #pragma unroll
   for (int x = 0; x < NV; ++x) { s1[x] = 0; w2[x] = 0; d1[x] = 0; }
+  // per lane until the end
   int64_t wedges = 0, c4e[3] = {0, 0, 0};
-  int32_t maxdp = 0;
+  int32_t maxdp = 0, maxlow = 0;
   int64_t maxw = 0;
   DegDecision dec;
-  int slot = 0;  // lane that records the next vertex's decisions
-  for (int64_t i = gwave(); i < n; i += gwaves()) {
-    const int32_t v = rlist[i];
-    const int64_t b = R.roff[v];
-    const int32_t L = (int32_t)(R.roff[v + 1] - b);
-    const uint32_t* row = R.rcol + b;
-    int32_t dv[NV];
-#pragma unroll
-    for (int x = 0; x < NV; ++x) dv[x] = 0;
-    int32_t low = 0;
-    int64_t wsum = 0;
-    for (int32_t k = lane_id(); k < L; k += 64) {
-      const uint32_t x = row[k];
+  // group c holds the region vertices c, c + C, c + 2C, ... (C groups): one
+  // from each 64th of the list, so the high-degree vertices (ids follow the
+  // degree order) are spread over the groups
+  const int64_t C = (n + 63) / 64;
+  for (int64_t c = gwave(); c < C; c += gwaves()) {
+    const int64_t i = c + (int64_t)l * C;
+    int32_t v = -1, L = 0;
+    int64_t b = 0;
+    if (i < n) {
+      v = rlist[i];
+      b = R.roff[v];
+      L = (int32_t)(R.roff[v + 1] - b);
+    }
+    // entry at region position p of the row of lane s (vertex vs)
+    auto entry = [&](int s, int32_t vs, int64_t p) {
+      const uint32_t x = R.rcol[p];
       const uint32_t pm = vpresent<NV>(x);
 #pragma unroll
-      for (int q = 0; q < NV; ++q) dv[q] += (pm >> q) & 1u;
+      for (int q = 0; q < NV; ++q)
+        if ((pm >> q) & 1u) atomicAdd(&sdv[wv][q][s], 1u);
       const uint32_t w = x & GC_ID;
-      if (w < (uint32_t)v) {
-        // wedges (v, w, .) below v: entries of row w smaller than v (kept
+      if (w < (uint32_t)vs) {
+        // wedges (vs, w, .) below vs: entries of row w smaller than vs (kept
         // for the 4-cycle kernels as the starting cursor in row w)
-        low += 1;
+        atomicAdd(&slow[wv][s], 1u);
         const int64_t wb = R.roff[w];
-        const int32_t pos = lower_bound_from_end(R.rcol + wb, (int32_t)(R.roff[w + 1] - wb), (uint32_t)v);
-        R.vpos[b + k] = pos;
-        wsum += pos;
+        const int32_t pos = lower_bound_from_end(R.rcol + wb, (int32_t)(R.roff[w + 1] - wb), (uint32_t)vs);
+        R.vpos[p] = pos;
+        if (pos) atomicAdd(&sws[wv][s], (unsigned long long)pos);
+      }
+    };
+    {
+      const int32_t ss = L < DEG_WAVE_ROW ? L : 0;  // total < 64 * DEG_WAVE_ROW
+      const int32_t incl = wave_incl_scan32(ss);
+      const int32_t tot = __shfl(incl, 63);
+      const int32_t excl = incl - ss;
+      for (int32_t base = 0; base < tot; base += 64) {
+        const int32_t idx = base + l;
+        const int s = wave_segment(excl, idx);
+        const int32_t vs = __shfl(v, s);
+        const int64_t bs = __shfl(b, s);
+        const int32_t es = __shfl(excl, s);
+        if (idx < tot) entry(s, vs, bs + (idx - es));
       }
     }
+    for (uint64_t lm = __ballot(L >= DEG_WAVE_ROW); lm; lm &= lm - 1) {
+      const int s = __builtin_ctzll(lm);
+      const int32_t vs = __shfl(v, s), Ls = __shfl(L, s);
+      const int64_t bs = __shfl(b, s);
+      for (int32_t k = l; k < Ls; k += 64) entry(s, vs, bs + k);
+    }
+    wave_sync();
+    int32_t dv[NV];
 #pragma unroll
-    for (int x = 0; x < NV; ++x) dv[x] = wave_sum32(dv[x]);
-    low = wave_sum32(low);
-    wsum = wave_sum64(wsum);
-    // every lane holds the vertex's totals now
-    if (lane_id() == 0) {
+    for (int x = 0; x < NV; ++x) {
+      dv[x] = (int32_t)sdv[wv][x][l];
+      sdv[wv][x][l] = 0u;
+    }
+    const int32_t low = (int32_t)slow[wv][l];
+    const int64_t wsum = (int64_t)sws[wv][l];
+    slow[wv][l] = 0u;
+    sws[wv][l] = 0ull;
+    wave_sync();
+    const bool has = v >= 0;
+    if (has) {
       if constexpr (NV == 2) {
         *(int2*)(R.d + (int64_t)v * 2) = make_int2(dv[0], dv[1]);
       } else {
         *(int4*)(R.d + (int64_t)v * 4) = make_int4(dv[0], dv[1], dv[2], dv[3]);
       }
       R.rlow[v] = low;
-      const int g = gid[v];
-      if (g != cur_g) {
-        if (cur_g >= 0) flush_vertex_terms<NV>(sig, cur_g, s1, w2, d1);
-        cur_g = g;
-      }
+    }
+    // the 3-star and wedge terms, summed over the lanes of each graph in the
+    // group into running sums of one graph (the same in every lane), flushed
+    // by lane 0 when the graph changes
+    {
+      const int g = has ? gid[v] : -1;
+      for (uint64_t left = __ballot(has); left;) {
+        const int gs = __builtin_amdgcn_readfirstlane(__shfl(g, __builtin_ctzll(left)));
+        const bool in = has && g == gs;
+        left &= ~__ballot(in);
+        if (gs != cur_g) {
+          if (cur_g >= 0 && l == 0) flush_vertex_terms<NV>(sig, cur_g, s1, w2, d1);
 #pragma unroll
-      for (int x = 0; x < NV; ++x) { s1[x] += c3(dv[x]); w2[x] += c2(dv[x]); d1[x] += dv[x]; }
+          for (int x = 0; x < NV; ++x) { s1[x] = 0; w2[x] = 0; d1[x] = 0; }
+          cur_g = gs;
+        }
+#pragma unroll
+        for (int x = 0; x < NV; ++x) {
+          s1[x] += uniform64(wave_sum64(in ? c3(dv[x]) : 0));
+          w2[x] += uniform64(wave_sum64(in ? c2(dv[x]) : 0));
+          d1[x] += uniform64(wave_sum64(in ? (int64_t)dv[x] : 0));
+        }
+      }
     }
     const int32_t dplus = L - low;
-    const bool tri = dplus >= 2, c4 = low >= 2 && wsum >= 2;
-    if (lane_id() == slot) {
-      dec.v = v;
-      dec.tri = tri ? tri_list_of(dplus, tri_small) : -1;
-      dec.c4 = c4 ? (wsum <= c4_small ? L_C4_S : (wsum <= c4_mid ? L_C4_M : L_C4_L)) : -1;
-      if (dec.c4 == L_C4_L) {
-        const uint64_t wk = wsum < 0xFFFFFFFFll ? (uint64_t)wsum : 0xFFFFFFFFull;
-        dec.key = ((0xFFFFFFFFull - wk) << 32) | (uint32_t)v;
-      }
+    const bool tri = has && dplus >= 2, c4 = has && low >= 2 && wsum >= 2;
+    dec.v = has ? v : -1;
+    dec.tri = tri ? tri_list_of(dplus, tri_small) : -1;
+    dec.c4 = c4 ? (wsum <= c4_small ? L_C4_S : (wsum <= c4_mid ? L_C4_M : L_C4_L)) : -1;
+    if (dec.c4 == L_C4_L) {
+      const uint64_t wk = wsum < 0xFFFFFFFFll ? (uint64_t)wsum : 0xFFFFFFFFull;
+      dec.key = ((0xFFFFFFFFull - wk) << 32) | (uint32_t)v;
     }
-    if (lane_id() == 0) {
-      if (tri) maxdp = dplus > maxdp ? dplus : maxdp;
-      if (c4) {
-        const int which = wsum <= c4_small ? 0 : (wsum <= c4_mid ? 1 : 2);
-        maxw = wsum > maxw ? wsum : maxw;
-        wedges += wsum;
-        c4e[which] += wsum + low;
-        if (which == 2) maxlow = low > maxlow ? low : maxlow;
-      }
+    if (tri) maxdp = dplus > maxdp ? dplus : maxdp;
+    if (c4) {
+      const int which = wsum <= c4_small ? 0 : (wsum <= c4_mid ? 1 : 2);
+      maxw = wsum > maxw ? wsum : maxw;
+      wedges += wsum;
+      c4e[which] += wsum + low;
+      if (which == 2) maxlow = low > maxlow ? low : maxlow;
     }
-    if (++slot == 64) {
-      flush_decisions(dec, cc, lists, list_stride, c4_keys);
-      slot = 0;
-    }
+    flush_decisions(dec, cc, lists, list_stride, c4_keys);
   }
-  flush_decisions(dec, cc, lists, list_stride, c4_keys);
+  maxdp = wave_max32(maxdp);
+  maxlow = wave_max32(maxlow);
+  maxw = wave_max64(maxw);
+  wedges = wave_sum64(wedges);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) c4e[q] = wave_sum64(c4e[q]);
   // The waves' totals (held by lane 0) meet in LDS: one set of atomics per
   // workgroup instead of per wave (the few words of one graph's sums and the
   // shared maxima would otherwise queue at one L2 channel).
   constexpr int NW = TPB / 64, NR = 3 * NV + 7;
   __shared__ int64_t red[NW][NR];
   __shared__ int wg[NW];
-  const int wv = threadIdx.x >> 6;
   if (lane_id() == 0) {
     wg[wv] = cur_g;
 #pragma unroll

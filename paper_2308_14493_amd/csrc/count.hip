@@ -1217,24 +1217,31 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
       if (block_max32(S.C, m) <= 255) { sh = 2; fw = 8; wsz = 2 * ws; }
     }
     const uint32_t lo = (uint32_t)(hi - wsz > 0 ? hi - wsz : 0);
-    const uint32_t im = (1u << sh) - 1u;
     if (t == 0) {
       atomicAdd(&A.bstats[BS_C4_SEARCH], (unsigned long long)nlow);
       atomicAdd(&A.bstats[BS_C4_WINDOWS], 1ull);
     }
     long long wtot = 0, rest = 0;
-    c4_window_walk(R, rb, nlow, urow, ucur, lo,
-                   [&](uint32_t wid, uint32_t fl) {
-                     const uint32_t sub = (vpresent<NV>(fl) >> vsh) & fmask;
-                     const uint32_t o = wid - lo;
-                     if (sub == ref) {
-                       atomicAdd(&wc[o >> sh], 1u << (fw * (o & im)));
-                     } else if (sub) {  // present in some versions only
-                       const unsigned long long old = atomicAdd(&cnt[wid], (unsigned long long)TFd::spread(sub));
-                       if (old == 0ull) touch[atomicAdd(&S.nt, 1)] = (int32_t)wid;
-                     }
-                   },
-                   wtot, rest);
+    // the window walk with the field layout as constants (8-bit fields, or FBW)
+    auto walk = [&](auto fwc) {
+      constexpr int FW = decltype(fwc)::value;
+      constexpr int SH = FW == 8 ? 2 : (FW == 16 ? 1 : 0);
+      constexpr uint32_t IM = (1u << SH) - 1u;
+      c4_window_walk(R, rb, nlow, urow, ucur, lo,
+                     [&](uint32_t wid, uint32_t fl) {
+                       const uint32_t sub = (vpresent<NV>(fl) >> vsh) & fmask;
+                       const uint32_t o = wid - lo;
+                       if (sub == ref) {
+                         atomicAdd(&wc[o >> SH], 1u << (FW * (o & IM)));
+                       } else if (sub) {  // present in some versions only
+                         const unsigned long long old = atomicAdd(&cnt[wid], (unsigned long long)TFd::spread(sub));
+                         if (old == 0ull) touch[atomicAdd(&S.nt, 1)] = (int32_t)wid;
+                       }
+                     },
+                     wtot, rest);
+    };
+    if (fw == 8) walk(std::integral_constant<int, 8>{});
+    else walk(std::integral_constant<int, FBW>{});
     block_sum2(S.C, wtot, rest);  // also orders the window's counter updates before the passes below
     if (const int32_t nt = S.nt) {  // the window's exceptions
       for (int32_t q = t; q < nt; q += C4W_T) {

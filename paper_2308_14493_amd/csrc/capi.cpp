@@ -155,6 +155,9 @@ struct gc_graph {
   std::vector<double> tune_ms, tune_wedges;
   int tune_next = 0;
   int64_t dense_min_best = 256;
+  // rows at least this long go through a whole wave in the per-vertex pass
+  // (GC_DEG_WAVE_ROW overrides it: tests lower it to reach that path)
+  int32_t deg_wave_row = 1 << 16;
   double region_frac[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
 
   void* pin = nullptr;
@@ -350,7 +353,7 @@ void enqueue_count(gc_graph* G, int nv, int radius, long long* state_d, BatchWor
                      G->scan_tmp.p, s);
   launch_degrees(nv, A.R, G->gid.as<int32_t>(), G->rlist.as<int32_t>(), G->ctr.as<unsigned long long>(),
                  G->sig.as<unsigned long long>(), G->lists.as<int32_t>(), G->N, TRI_SMALL, C4_SMALL, C4_MID,
-                 G->bstats.as<unsigned long long>(), G->c4_keys.as<unsigned long long>(), s);
+                 G->deg_wave_row, G->bstats.as<unsigned long long>(), G->c4_keys.as<unsigned long long>(), s);
   if (timed) HIPCHK(hipEventRecord(G->ev[1], s));
   launch_count(nv, A, s, timed ? &G->ev[2] : nullptr);
   launch_combine(nv, G->sig.as<unsigned long long>(), state_d, G->vout.as<long long>(), G->k,
@@ -473,6 +476,7 @@ void read_state(gc_graph* G) {
 
 void setup_handle(gc_graph* G, const gc_options* opt) {
   if (opt) G->opt = *opt; else gc_options_default(&G->opt);
+  if (const char* e = std::getenv("GC_DEG_WAVE_ROW")) G->deg_wave_row = std::max(1, std::min(1 << 16, std::atoi(e)));
   if (G->opt.radius < 0 || G->opt.radius > 4) raise(GC_EINVAL, "radius must be in [0, 4]");
   if (!(G->opt.slack >= 0.0f && G->opt.slack <= 16.0f)) raise(GC_EINVAL, "slack must be in [0, 16]");
   int ndev = 0;

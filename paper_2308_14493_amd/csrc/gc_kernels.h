@@ -92,9 +92,11 @@ void launch_region(const PoolDev& P, const BatchWork& W, int radius, int32_t* le
                    hipStream_t s);
 void launch_region_fill(const PoolDev& P, const RegionDev& R, const BatchWork& W, int radius, const int32_t* level,
                         const int32_t* rlist, const int32_t* rlen, void* scan_tmp, hipStream_t s);
+// wave_row in [1, 65536]: rows at least this long are walked by a whole wave
 void launch_degrees(int nv, const RegionDev& R, const int32_t* gid, const int32_t* rlist, unsigned long long* c,
                     unsigned long long* sig, int32_t* lists, int64_t list_stride, int32_t tri_small, int32_t c4_small,
-                    int32_t c4_mid, unsigned long long* bstats, unsigned long long* c4_keys, hipStream_t s);
+                    int32_t c4_mid, int32_t wave_row, unsigned long long* bstats, unsigned long long* c4_keys,
+                    hipStream_t s);
 void launch_init_keys(const int32_t* src, const int32_t* dst, int64_t m, const int64_t* seg, const int64_t* gbase,
                       int32_t k, int bits, unsigned long long* keys, hipStream_t s);
 void launch_init_unique(const unsigned long long* keys, int64_t m, int bits, unsigned long long* uniq,

@@ -520,19 +520,17 @@ __device__ __forceinline__ int64_t uniform64(int64_t x) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// rows at least this long are walked by the whole wave, one at a time
-constexpr int32_t DEG_WAVE_ROW = 1 << 16;
-
 // A wave takes a group of 64 region vertices at a time, one per lane: the
 // rows of the shorter ones are concatenated and dealt over the lanes (a
 // segment search per step), so the lanes' searches for v in the rows of its
 // lower neighbours overlap instead of one vertex's chain of loads at a time;
-// the per-vertex sums meet in LDS, one slot per lane.
+// the per-vertex sums meet in LDS, one slot per lane.  Rows of at least
+// wave_row (<= 65536) entries are walked by the whole wave, one at a time.
 template <int NV>
 __global__ __launch_bounds__(TPB) void k_degrees(RegionDev R, const int32_t* __restrict__ gid, const int32_t* __restrict__ rlist,
                           unsigned long long* __restrict__ cc, unsigned long long* __restrict__ sig,
                           int32_t* __restrict__ lists, int64_t list_stride, int32_t tri_small, int32_t c4_small,
-                          int32_t c4_mid, unsigned long long* __restrict__ bstats,
+                          int32_t c4_mid, int32_t wave_row, unsigned long long* __restrict__ bstats,
                           unsigned long long* __restrict__ c4_keys) {
   __shared__ uint32_t sdv[TPB / 64][NV][64];          // degree per version
   __shared__ uint32_t slow[TPB / 64][64];             // lower entries
@@ -585,7 +583,7 @@ __global__ __launch_bounds__(TPB) void k_degrees(RegionDev R, const int32_t* __r
       }
     };
     {
-      const int32_t ss = L < DEG_WAVE_ROW ? L : 0;  // total < 64 * DEG_WAVE_ROW
+      const int32_t ss = L < wave_row ? L : 0;  // total < 64 * 65536
       const int32_t incl = wave_incl_scan32(ss);
       const int32_t tot = __shfl(incl, 63);
       const int32_t excl = incl - ss;
@@ -598,7 +596,7 @@ __global__ __launch_bounds__(TPB) void k_degrees(RegionDev R, const int32_t* __r
         if (idx < tot) entry(s, vs, bs + (idx - es));
       }
     }
-    for (uint64_t lm = __ballot(L >= DEG_WAVE_ROW); lm; lm &= lm - 1) {
+    for (uint64_t lm = __ballot(L >= wave_row); lm; lm &= lm - 1) {
       const int s = __builtin_ctzll(lm);
       const int32_t vs = __shfl(v, s), Ls = __shfl(L, s);
       const int64_t bs = __shfl(b, s);
@@ -980,15 +978,16 @@ void launch_region_fill(const PoolDev& P, const RegionDev& R, const BatchWork& W
 
 void launch_degrees(int nv, const RegionDev& R, const int32_t* gid, const int32_t* rlist, unsigned long long* c,
                     unsigned long long* sig, int32_t* lists, int64_t list_stride, int32_t tri_small, int32_t c4_small,
-                    int32_t c4_mid, unsigned long long* bstats, unsigned long long* c4_keys, hipStream_t s) {
+                    int32_t c4_mid, int32_t wave_row, unsigned long long* bstats, unsigned long long* c4_keys,
+                    hipStream_t s) {
   // at least 1024 vertices (list_stride = N bounds the region) per workgroup
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (list_stride + 1023) / 1024));
   if (nv == 2)
     hipLaunchKernelGGL(k_degrees<2>, dim3(grid), dim3(TPB), 0, s, R, gid, rlist, c, sig, lists, list_stride,
-                       tri_small, c4_small, c4_mid, bstats, c4_keys);
+                       tri_small, c4_small, c4_mid, wave_row, bstats, c4_keys);
   else
     hipLaunchKernelGGL(k_degrees<4>, dim3(grid), dim3(TPB), 0, s, R, gid, rlist, c, sig, lists, list_stride,
-                       tri_small, c4_small, c4_mid, bstats, c4_keys);
+                       tri_small, c4_small, c4_mid, wave_row, bstats, c4_keys);
 }
 
 // ---------------------------------------------------------------- build

@@ -111,6 +111,32 @@ def test_rmat_streams(scale, ef, seed):
         assert gr.recount() == gr.counts()
 
 
+@pytest.mark.parametrize("wave_row", [1, 24])
+def test_per_vertex_pass_whole_wave_rows(monkeypatch, wave_row):
+    """The per-vertex pass deals the rows of 64 vertices over a wave's lanes
+    and sends rows of at least wave_row entries (65536 by default) through
+    the whole wave.  A low threshold mixes both kinds in most groups (1: every
+    nonempty row through the whole wave), for one-batch and three-batch
+    passes."""
+    monkeypatch.setenv("GC_DEG_WAVE_ROW", str(wave_row))
+    say("case per-vertex pass, whole-wave rows >= %d" % wave_row)
+    n, s, d, samp = rmat_graph(12, 16, 61)
+    batches = rmat_batches(n, s, d, samp, [3, 60, 1500, 20, 400, 7], 62)
+    E = edge_set(s, d)
+    with G(n, s, d) as gr:
+        assert gr.counts() == native.static_counts(n, s, d)
+        for b in batches[:3]:
+            got = gr.apply_batch(*b)
+            oracle_apply(E, n, *b)
+            assert got == native.static_counts(n, *esorted(E))
+        rows = gr.apply_batch_seq(batches[3:])
+        for b, r in zip(batches[3:], rows):
+            oracle_apply(E, n, *b)
+            want = native.static_counts(n, *esorted(E))
+            assert [v & ((1 << 64) - 1) for v in r] == [v & ((1 << 64) - 1) for v in want]
+        assert gr.recount() == gr.counts()
+
+
 def test_chung_lu_small():
     say("case chung-lu n=20000 m=60000")
     n, s, d, _ = chung_lu_graph(20000, 60000, 2.1, 2000.0, 5)

@@ -607,6 +607,34 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL<NV>& S, int32_t 
         kv[x] = k4_rows<NV>(S, S.P + x * W, dp, nwaves);
       }
     }
+    // The exceptions by slot pair, in the probe hash table (not read again
+    // for this vertex): key min << 16 | max, value the exception's index.
+    // Pairs are unique (each found from its lower slot's list only).
+    const bool keyed = dp <= 65536;
+    if (keyed) {
+      for (int32_t k = threadIdx.x; k < H; k += blockDim.x) S.hkey[k] = -1;
+      __syncthreads();
+      for (int32_t e = threadIdx.x; e < ne; e += blockDim.x) {
+        const unsigned long long ex = S.exc[e];
+        const uint32_t a = (uint32_t)(ex >> 32), b = (uint32_t)((ex >> 4) & 0xFFFFFFFull);
+        const uint32_t key = (min(a, b) << 16) | max(a, b);
+        uint32_t h = hash32(key) >> shift;
+        while (atomicCAS(&S.hkey[h], -1, (int32_t)key) != -1) h = (h + 1) & hmask;
+        S.hval[h] = (uint32_t)e;
+      }
+      __syncthreads();
+    }
+    // index of the exception on slot pair (a, b), or -1
+    auto exc_of = [&](int32_t a, int32_t b) -> int32_t {
+      const uint32_t key = ((uint32_t)min(a, b) << 16) | (uint32_t)max(a, b);
+      uint32_t h = hash32(key) >> shift;
+      for (;;) {
+        const int32_t q = S.hkey[h];
+        if (q == -1) return -1;
+        if ((uint32_t)q == key) return (int32_t)S.hval[h];
+        h = (h + 1) & hmask;
+      }
+    };
     // triangles of E (inside P_x) holding an edge absent from version x
     const int l = lane_id();
     for (int32_t e = w; e < ne; e += nwaves) {
@@ -624,12 +652,18 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL<NV>& S, int32_t 
           if (!Ebit<NV>(S, i, k) || !Ebit<NV>(S, j, k)) continue;
           // count once: skip if an earlier listed edge of this triangle is absent from x
           bool first = true;
-          for (int32_t f = 0; f < e && first; ++f) {
-            const unsigned long long ef = S.exc[f];
-            if (!((ef >> x) & 1ull)) continue;
-            const int32_t fi = (int32_t)(ef >> 32), fj = (int32_t)((ef >> 4) & 0xFFFFFFFull);
-            if ((fi == i && fj == k) || (fi == k && fj == i) || (fi == j && fj == k) || (fi == k && fj == j))
-              first = false;
+          if (keyed) {
+            const int32_t f1 = exc_of(i, k), f2 = exc_of(j, k);
+            if (f1 >= 0 && f1 < e && ((S.exc[f1] >> x) & 1ull)) first = false;
+            if (f2 >= 0 && f2 < e && ((S.exc[f2] >> x) & 1ull)) first = false;
+          } else {
+            for (int32_t f = 0; f < e && first; ++f) {
+              const unsigned long long ef = S.exc[f];
+              if (!((ef >> x) & 1ull)) continue;
+              const int32_t fi = (int32_t)(ef >> 32), fj = (int32_t)((ef >> 4) & 0xFFFFFFFull);
+              if ((fi == i && fj == k) || (fi == k && fj == i) || (fi == j && fj == k) || (fi == k && fj == j))
+                first = false;
+            }
           }
           sub += first;
         }

@@ -1251,6 +1251,7 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
       if (block_max32(S.C, m) <= 255) { sh = 2; fw = 8; wsz = 2 * ws; }
     }
     const uint32_t lo = (uint32_t)(hi - wsz > 0 ? hi - wsz : 0);
+    const int32_t wcap = (int32_t)(hi - lo);  // list capacity: ids of the window (<= N)
     if (t == 0) {
       atomicAdd(&A.bstats[BS_C4_SEARCH], (unsigned long long)nlow);
       atomicAdd(&A.bstats[BS_C4_WINDOWS], 1ull);
@@ -1268,8 +1269,11 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
                        if (sub == ref) {
                          atomicAdd(&wc[o >> SH], 1u << (FW * (o & IM)));
                        } else if (sub) {  // present in some versions only
-                         const unsigned long long old = atomicAdd(&cnt[wid], (unsigned long long)TFd::spread(sub));
-                         if (old == 0ull) touch[atomicAdd(&S.nt, 1)] = (int32_t)wid;
+                         // no wait for the global atomic: the id is listed once per
+                         // exception wedge (while the list is shorter than the window)
+                         atomicAdd(&cnt[wid], (unsigned long long)TFd::spread(sub));
+                         const int32_t p = atomicAdd(&S.nt, 1);
+                         if (p < wcap) touch[p] = (int32_t)wid;
                        }
                      },
                      wtot, rest);
@@ -1278,15 +1282,29 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
     else walk(std::integral_constant<int, FBW>{});
     block_sum2(S.C, wtot, rest);  // also orders the window's counter updates before the passes below
     if (const int32_t nt = S.nt) {  // the window's exceptions
-      for (int32_t q = t; q < nt; q += C4W_T) {
-        const int32_t k = touch[q];
-        const unsigned long long e = cnt[k];
-        cnt[k] = 0ull;
+      auto one = [&](int32_t k, unsigned long long e) {
         const int64_t c = (int64_t)count_of((uint32_t)k - lo);
 #pragma unroll
         for (int x = 0; x < NF; ++x) {
           const int64_t ex = TFd::get(e, x);
           acc[vsh + x] += ((ref >> x) & 1u ? c * ex : 0) + c2(ex);
+        }
+      };
+      if (nt <= wcap) {
+        // an id listed several times: the first exchange takes its counter
+        for (int32_t q = t; q < nt; q += C4W_T) {
+          const int32_t k = touch[q];
+          const unsigned long long e = atomicExch(&cnt[k], 0ull);
+          if (e) one(k, e);
+        }
+      } else {
+        // more exception wedges than ids in the window: every counter of it
+        for (int64_t k = lo + t; k < hi; k += C4W_T) {
+          const unsigned long long e = __hip_atomic_load(&cnt[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (e) {
+            cnt[k] = 0ull;
+            one((int32_t)k, e);
+          }
         }
       }
       __syncthreads();

@@ -1328,21 +1328,34 @@ __device__ void c4_hub(const CountArgs& A, C4Smem& S, int32_t v, int vsh, int64_
     if (rest == 0) break;
     if (wtot < A.c4_dense_min) {
       // sparse from here down: every remaining wedge in global memory
+      const int32_t tcap = (int32_t)lo;  // list capacity: the ids below the windows (<= N)
       c4_block_walk(R, rb, nlow, urow, [&](int32_t) { return 0; }, [&](int32_t q) { return ucur[q]; },
                     [&](uint32_t wid, uint32_t fl) {
                       const uint32_t sub = (vpresent<NV>(fl) >> vsh) & fmask;
                       if (!sub) return;
                       ++tail_;
-                      const unsigned long long old = atomicAdd(&cnt[wid], (unsigned long long)TFd::spread(sub));
-                      if (old == 0ull) touch[atomicAdd(&S.nt, 1)] = (int32_t)wid;
+                      // as in the windows: no wait for the global atomic, the id
+                      // listed once per wedge while the list is shorter than [0, lo)
+                      atomicAdd(&cnt[wid], (unsigned long long)TFd::spread(sub));
+                      const int32_t p = atomicAdd(&S.nt, 1);
+                      if (p < tcap) touch[p] = (int32_t)wid;
                     });
       const int32_t nt = S.nt;
-      for (int32_t q = t; q < nt; q += C4W_T) {
-        const int32_t wid = touch[q];
-        const unsigned long long c = cnt[wid];
-        cnt[wid] = 0ull;
+      if (nt <= tcap) {
+        for (int32_t q = t; q < nt; q += C4W_T) {
+          const unsigned long long c = atomicExch(&cnt[touch[q]], 0ull);
 #pragma unroll
-        for (int x = 0; x < NF; ++x) acc[vsh + x] += c2(TFd::get(c, x));
+          for (int x = 0; x < NF; ++x) acc[vsh + x] += c2(TFd::get(c, x));
+        }
+      } else {
+        for (int64_t k = t; k < (int64_t)lo; k += C4W_T) {
+          const unsigned long long c = __hip_atomic_load(&cnt[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (c) {
+            cnt[k] = 0ull;
+#pragma unroll
+            for (int x = 0; x < NF; ++x) acc[vsh + x] += c2(TFd::get(c, x));
+          }
+        }
       }
       __syncthreads();
       if (t == 0) S.nt = 0;

@@ -555,7 +555,7 @@ __device__ __forceinline__ int64_t k4_rows(const TriL<NV>& S, const unsigned lon
 }
 
 template <int NV>
-__device__ void tri_large_vertex(const CountArgs& A, const TriL<NV>& S, int32_t u, int64_t ub, int32_t dp,
+__device__ void tri_large_vertex(const CountArgs& A, const TriL<NV>& S, int64_t ub, int32_t dp,
                                  int64_t (&kacc)[NV]) {
   const RegionDev& R = A.R;
   const int w = threadIdx.x >> 6;
@@ -784,7 +784,7 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int L, unsig
       cur_g = g;
     }
     if constexpr (CAP != 0) S.W = (dp + 63) / 64;
-    tri_large_vertex<NV>(A, S, u, ub, dp, kacc);
+    tri_large_vertex<NV>(A, S, ub, dp, kacc);
   }
   if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_K4, kacc);
 }
@@ -1201,8 +1201,10 @@ __device__ __forceinline__ void window_pairs(const uint4 q, uint64_t& s) {
 // bounds c_A; the reference set M is every
 // version, or every version but 0 when version 0 is the empty graph); the
 // other wedges (few: they hold a flagged entry) go to the block's global
-// counters (e_x(w) per version x, one u64 of NF fields of 64 / NF bits, with
-// a touched list).  With c_x = [x in M] c_A + e_x,
+// counters (e_x(w) per version x, one u64 of NF fields of 64 / NF bits, by
+// atomics whose result nobody waits for, with w listed once per wedge, or
+// the whole id range read back when the list would outgrow it).  With
+// c_x = [x in M] c_A + e_x,
 //   sum_w C(c_x(w), 2) = [x in M] sum_w C(c_A(w), 2)
 //                        + sum_{w with exceptions} ([x in M] c_A e_x + C(e_x, 2)),
 // so one scan of the window serves every version of M and the exceptions add

@@ -3,8 +3,9 @@
 ``static_counts``  the static recount of Sec. 4.1 (the baseline recounts the
                    whole updated graph after every batch), 11 induced classes.
 ``brute_counts``   the plain definition: classify every 4-subset.
-``noninduced``     the non-induced pattern counts and global terms that the
-                   static recount inverts (for per-term checks).
+``static_counts_merge``  the same recount through a second formulation
+                   (sorted merges per edge in id order), for cross-checks.
+``sample_seconds`` time of the recount's loops over a sample of vertices.
 Results are exact Python ints (the C side works in __int128).
 """
 from __future__ import annotations
@@ -39,8 +40,13 @@ def _load():
         P = ctypes.c_void_p
         lib.static_counts.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, P, P, P, P]
         lib.static_counts.restype = ctypes.c_int
+        lib.static_counts_merge.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, P, P]
+        lib.static_counts_merge.restype = ctypes.c_int
         lib.brute_counts.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, P, P]
         lib.brute_counts.restype = ctypes.c_int
+        lib.static_counts_sample_time.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, ctypes.c_int64,
+                                                  ctypes.c_int64, P]
+        lib.static_counts_sample_time.restype = ctypes.c_int
         lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -74,6 +80,17 @@ def static_counts(n: int, src, dst, with_terms: bool = False):
     return counts
 
 
+def static_counts_merge(n: int, src, dst):
+    """static_counts through the merge formulation (O(sum of d^2) steps)."""
+    lib = _load()
+    s, d = _edges(src, dst)
+    hi = np.zeros(11, np.int64); lo = np.zeros(11, np.uint64)
+    rc = lib.static_counts_merge(n, s.size, s.ctypes.data, d.ctypes.data, hi.ctypes.data, lo.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle static_counts_merge failed (%d)" % rc)
+    return _join(hi, lo)
+
+
 def brute_counts(n: int, src, dst):
     """Induced 4-vertex counts by enumerating all C(n,4) subsets (n <= 4096)."""
     lib = _load()
@@ -83,6 +100,18 @@ def brute_counts(n: int, src, dst):
     if rc != 0:
         raise ValueError("oracle brute_counts failed (%d)" % rc)
     return _join(hi, lo)
+
+
+def sample_seconds(n: int, src, dst, stride: int, offset: int = 0):
+    """(build seconds, seconds of the per-vertex loops of static_counts over
+    the vertices offset, offset + stride, ...).  No counts: timing only."""
+    lib = _load()
+    s, d = _edges(src, dst)
+    secs = np.zeros(2, np.float64)
+    rc = lib.static_counts_sample_time(n, s.size, s.ctypes.data, d.ctypes.data, stride, offset, secs.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle static_counts_sample_time failed (%d)" % rc)
+    return float(secs[0]), float(secs[1])
 
 
 def threads() -> int:

@@ -34,7 +34,15 @@
 #include <omp.h>
 #endif
 
+#include <time.h>
+
 typedef __int128 i128;
+
+static double now_s(void) {
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
 
 /* ---------------------------------------------------------------- helpers */
 static int cmp_i32(const void* a, const void* b) {
@@ -172,8 +180,166 @@ int brute_counts(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
 /* Non-induced copy counts of the six connected patterns plus the global
  * terms the disconnected classes need.  sig layout (all exact integers):
  *   0 N_P4  1 N_K13  2 N_C4  3 N_paw  4 N_diamond  5 N_K4  6 T  7 W  8 m
- * Returned as hi/lo halves of __int128. */
-static int noninduced(const adjlist* g, i128 sig[9]) {
+ * Returned as hi/lo halves of __int128.
+ *
+ * Every edge and every 4-clique is visited once under a fixed total order
+ * of the vertices: a precedes b iff (deg a, a) < (deg b, b).  Any total
+ * order visits each once; this one makes the row that is scanned the
+ * shorter one. */
+static inline int precedes(const adjlist* g, int64_t a, int64_t b) {
+    int64_t da = deg(g, a), db = deg(g, b);
+    return da < db || (da == db && a < b);
+}
+
+/* stride > 1 visits only the vertices offset, offset + stride, ... in the
+ * three per-vertex loops below (to time a sample of the work; the sums are
+ * then partial). */
+static int noninduced(const adjlist* g, i128 sig[9], int64_t stride, int64_t offset) {
+    const int64_t n = g->n;
+    const int64_t ns_v = offset < n ? (n - offset + stride - 1) / stride : 0;
+    i128 W = 0, K13 = 0, T3 = 0, P4raw = 0, paw2 = 0, dia = 0, k4 = 0, c4x2 = 0;
+    int ovf = 0;
+
+    /* vertex terms: wedges W = sum C(d,2); 3-stars sum C(d,3) */
+    #pragma omp parallel
+    {
+        i128 w = 0, s = 0;
+        #pragma omp for schedule(static)
+        for (int64_t v = 0; v < n; ++v) { int64_t d = deg(g, v); w += c2(d); s += c3(d); }
+        #pragma omp critical
+        { W += w; K13 += s; }
+    }
+
+    /* edge terms, every edge (u, v) once, at its later endpoint v:
+     * t_uv = |N(u) & N(v)| = number of w in N(u) marked as members of N(v).
+     *   3T        = sum_e t
+     *   N_P4 + 3T = sum_e (d_u - 1)(d_v - 1)   (middle edge, one end each side)
+     *   2 N_paw   = sum_e t (d_u + d_v - 4)    (triangle on e, pendant at u or v)
+     *   N_diamond = sum_e C(t, 2)              (two triangles sharing e)  */
+    #pragma omp parallel
+    {
+        i128 t3 = 0, p4 = 0, pw = 0, di = 0;
+        uint8_t* mark = (uint8_t*)calloc((size_t)n + 1, 1);
+        #pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < ns_v; ++i) {
+            const int64_t v = offset + i * stride;
+            for (int64_t q = g->off[v]; q < g->off[v + 1]; ++q) mark[g->adj[q]] = 1;
+            for (int64_t p = g->off[v]; p < g->off[v + 1]; ++p) {
+                int32_t u = g->adj[p];
+                if (!precedes(g, u, v)) continue;
+                int64_t t = 0;
+                for (int64_t q = g->off[u]; q < g->off[u + 1]; ++q) t += mark[g->adj[q]];
+                int64_t du = deg(g, u), dv = deg(g, v);
+                t3 += t;
+                p4 += (i128)(du - 1) * (dv - 1);
+                pw += (i128)t * (du + dv - 4);
+                di += c2(t);
+            }
+            for (int64_t q = g->off[v]; q < g->off[v + 1]; ++q) mark[g->adj[q]] = 0;
+        }
+        free(mark);
+        #pragma omp critical
+        { T3 += t3; P4raw += p4; paw2 += pw; dia += di; }
+    }
+
+    /* 4-cliques {a, b, c, d} with a, b, c, d in that order: counted once, at
+     * u = a, v = b, as the edge (c, d) inside S = out(a) & out(b), where
+     * out(x) = the neighbours that follow x. */
+    {
+        int64_t* ooff = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+        for (int64_t u = 0; u < n; ++u) {
+            int64_t c = 0;
+            for (int64_t p = g->off[u]; p < g->off[u + 1]; ++p) c += precedes(g, u, g->adj[p]);
+            ooff[u + 1] = ooff[u] + c;
+        }
+        int32_t* oadj = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ooff[n] + 1));
+        #pragma omp parallel for schedule(dynamic, 1024)
+        for (int64_t u = 0; u < n; ++u) {
+            int64_t k = ooff[u];
+            for (int64_t p = g->off[u]; p < g->off[u + 1]; ++p)
+                if (precedes(g, u, g->adj[p])) oadj[k++] = g->adj[p];
+        }
+        #pragma omp parallel
+        {
+            i128 kk = 0;
+            uint8_t* in_a = (uint8_t*)calloc((size_t)n + 1, 1);
+            uint8_t* in_s = (uint8_t*)calloc((size_t)n + 1, 1);
+            int64_t cap = 16, ns;
+            int32_t* S = (int32_t*)malloc(sizeof(int32_t) * cap);
+            #pragma omp for schedule(dynamic, 64)
+            for (int64_t i = 0; i < ns_v; ++i) {
+                const int64_t a = offset + i * stride;
+                for (int64_t p = ooff[a]; p < ooff[a + 1]; ++p) in_a[oadj[p]] = 1;
+                for (int64_t p = ooff[a]; p < ooff[a + 1]; ++p) {
+                    int32_t b = oadj[p];
+                    ns = 0;
+                    for (int64_t q = ooff[b]; q < ooff[b + 1]; ++q)
+                        if (in_a[oadj[q]]) {
+                            if (ns == cap) { cap *= 2; S = (int32_t*)realloc(S, sizeof(int32_t) * cap); }
+                            S[ns++] = oadj[q];
+                        }
+                    for (int64_t i = 0; i < ns; ++i) in_s[S[i]] = 1;
+                    for (int64_t i = 0; i < ns; ++i)
+                        for (int64_t q = ooff[S[i]]; q < ooff[S[i] + 1]; ++q) kk += in_s[oadj[q]];
+                    for (int64_t i = 0; i < ns; ++i) in_s[S[i]] = 0;
+                }
+                for (int64_t p = ooff[a]; p < ooff[a + 1]; ++p) in_a[oadj[p]] = 0;
+            }
+            free(in_a); free(in_s); free(S);
+            #pragma omp critical
+            k4 += kk;
+        }
+        free(ooff); free(oadj);
+    }
+
+    /* 4-cycles: N_C4 = 1/2 sum over unordered vertex pairs {v, w} of
+     * C(c(v, w), 2), c(v, w) = number of common neighbours, over ALL pairs
+     * (adjacent or not): each 4-cycle has two diagonals.  For every vertex v,
+     * c[w] counts the common neighbours of v and each w < v (vertex ids). */
+    #pragma omp parallel
+    {
+        int32_t* cnt = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
+        int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+        i128 acc = 0;
+        #pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < ns_v; ++i) {
+            const int64_t v = offset + i * stride;
+            int64_t nt = 0;
+            for (int64_t p = g->off[v]; p < g->off[v + 1]; ++p) {
+                int32_t u = g->adj[p];
+                for (int64_t q = g->off[u]; q < g->off[u + 1]; ++q) {
+                    int32_t w = g->adj[q];
+                    if (w >= v) break;   /* rows are sorted by id */
+                    if (cnt[w]++ == 0) touched[nt++] = w;
+                }
+            }
+            for (int64_t i = 0; i < nt; ++i) { acc += c2(cnt[touched[i]]); cnt[touched[i]] = 0; }
+        }
+        free(cnt); free(touched);
+        #pragma omp critical
+        c4x2 += acc;
+    }
+
+    if (T3 % 3 != 0 || paw2 % 2 != 0 || c4x2 % 2 != 0) ovf = 1;
+    i128 T = T3 / 3;
+    sig[0] = P4raw - 3 * T;
+    sig[1] = K13;
+    sig[2] = c4x2 / 2;
+    sig[3] = paw2 / 2;
+    sig[4] = dia;
+    sig[5] = k4;
+    sig[6] = T;
+    sig[7] = W;
+    sig[8] = g->m;
+    return ovf ? -3 : 0;
+}
+
+/* The same non-induced counts by a second formulation: t_uv by a sorted
+ * merge of the two rows for every edge u < v (vertex id order), 4-cliques as
+ * u < v < w < x by id with a binary search per pair.  O(sum of d^2) merge
+ * steps: kept only so that tests can check the two formulations against
+ * each other on graphs too large for brute force. */
+static int noninduced_merge(const adjlist* g, i128 sig[9]) {
     const int64_t n = g->n;
     i128 W = 0, K13 = 0, T3 = 0, P4raw = 0, paw2 = 0, dia = 0, k4 = 0, c4x4 = 0;
     int ovf = 0;
@@ -319,12 +485,45 @@ int static_counts(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
     adjlist g;
     if (build_adj(n, m, src, dst, &g) != 0) { free_adj(&g); return -1; }
     i128 sig[9], I[11];
-    int rc = noninduced(&g, sig);
+    int rc = noninduced(&g, sig, 1, 0);
     free_adj(&g);
     if (rc) return rc;
     invert(n, sig, I);
     for (int k = 0; k < 11; ++k) store128(I[k], &hi[k], &lo[k]);
     if (sig_hi) for (int k = 0; k < 9; ++k) store128(sig[k], &sig_hi[k], &sig_lo[k]);
+    return 0;
+}
+
+/* Same output as static_counts, through the merge formulation. */
+int static_counts_merge(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                        int64_t* hi, uint64_t* lo) {
+    adjlist g;
+    if (build_adj(n, m, src, dst, &g) != 0) { free_adj(&g); return -1; }
+    i128 sig[9], I[11];
+    int rc = noninduced_merge(&g, sig);
+    free_adj(&g);
+    if (rc) return rc;
+    invert(n, sig, I);
+    for (int k = 0; k < 11; ++k) store128(I[k], &hi[k], &lo[k]);
+    return 0;
+}
+
+/* Timing of a sample of static_counts' work (no counts): the adjacency
+ * build in full, then the per-vertex loops over the vertices offset,
+ * offset + stride, ...  secs[0] = build, secs[1] = sampled loops. */
+int static_counts_sample_time(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                              int64_t stride, int64_t offset, double* secs) {
+    if (stride < 1 || offset < 0) return -2;
+    double t0 = now_s();
+    adjlist g;
+    if (build_adj(n, m, src, dst, &g) != 0) { free_adj(&g); return -1; }
+    double t1 = now_s();
+    i128 sig[9];
+    (void)noninduced(&g, sig, stride, offset);
+    double t2 = now_s();
+    free_adj(&g);
+    secs[0] = t1 - t0;
+    secs[1] = t2 - t1;
     return 0;
 }
 

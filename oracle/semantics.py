@@ -62,3 +62,66 @@ def apply_batch(E: set, n: int, ins_src, ins_dst, del_src, del_dst):
     E -= D
     E |= A
     return A, D, st
+
+
+# ---------------------------------------------------------------- arrays ---
+# The same rules on sorted arrays of pair keys (min << 32 | max, uint64), for
+# graphs too large for a Python set.  Every step names the rule it applies.
+
+def _keys(u, v):
+    import numpy as np
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    lo, hi = np.minimum(u, v), np.maximum(u, v)
+    return ((lo << 32) | hi).astype(np.uint64), u != v
+
+
+def _member(sorted_keys, q):
+    import numpy as np
+    if sorted_keys.size == 0 or q.size == 0:
+        return np.zeros(q.shape, dtype=bool)
+    pos = np.minimum(np.searchsorted(sorted_keys, q), sorted_keys.size - 1)
+    return sorted_keys[pos] == q
+
+
+def effective_batch_keys(E_keys, n: int, ins_src, ins_dst, del_src, del_dst):
+    """effective_batch on a sorted uint64 key array E_keys (not modified).
+    Returns (A' keys, D' keys, stats), both sorted."""
+    import numpy as np
+    for arr in (ins_src, ins_dst, del_src, del_dst):
+        a = np.asarray(arr, dtype=np.int64)
+        if a.size and (a.min() < 0 or a.max() >= n):
+            raise BatchRejected("vertex id out of range")
+    ka, keep_a = _keys(ins_src, ins_dst)          # (u, v) and (v, u) are one edge
+    kd, keep_d = _keys(del_src, del_dst)
+    stats = dict(offered_ins=len(ins_src), offered_del=len(del_src),
+                 loops=int((~keep_a).sum() + (~keep_d).sum()))
+    A = np.unique(ka[keep_a])                     # loops dropped, repeats collapse
+    D = np.unique(kd[keep_d])
+    both = np.intersect1d(A, D, assume_unique=True)
+    A = np.setdiff1d(A, both, assume_unique=True)  # a pair in A and D is dropped
+    D = np.setdiff1d(D, both, assume_unique=True)
+    stats["cancelled"] = int(both.size)
+    Ae = A[~_member(E_keys, A)]                   # no-op insertions / deletions
+    De = D[_member(E_keys, D)]
+    stats["ins_existing"] = int(A.size - Ae.size)
+    stats["del_missing"] = int(D.size - De.size)
+    stats["eff_ins"] = int(Ae.size)
+    stats["eff_del"] = int(De.size)
+    return Ae, De, stats
+
+
+def apply_batch_keys(E_keys, n: int, ins_src, ins_dst, del_src, del_dst):
+    """Returns (E - D' + A' as a sorted key array, stats)."""
+    import numpy as np
+    A, D, st = effective_batch_keys(E_keys, n, ins_src, ins_dst, del_src, del_dst)
+    kept = E_keys[~_member(D, E_keys)]
+    return np.union1d(kept, A).astype(np.uint64), st
+
+
+def keys_to_pairs(E_keys):
+    """Sorted key array -> (src, dst) int32 arrays with src < dst."""
+    import numpy as np
+    E_keys = np.asarray(E_keys, dtype=np.uint64)
+    return ((E_keys >> np.uint64(32)).astype(np.int32),
+            (E_keys & np.uint64(0xFFFFFFFF)).astype(np.int32))

@@ -271,3 +271,37 @@ def test_golden_er150():
         es, ed = edges_of(E)
         assert native.static_counts(n, es, ed) == want
         assert sum(want) == C(n, 4)
+
+
+@pytest.mark.parametrize("kind,seed", [("rmat12", 1), ("rmat13", 2), ("chung_lu", 3)])
+def test_static_two_formulations(kind, seed):
+    """Graphs with hubs, too large for brute force: the recount (degree
+    order, marks, 4-cycles over pairs counted once) equals the second
+    formulation (id order, sorted merges, 4-cycles over ordered pairs)."""
+    from graphgen import chung_lu_graph
+    if kind == "chung_lu":
+        n, s, d, _ = chung_lu_graph(20000, 60000, 2.1, 2000.0, seed)
+    else:
+        n, s, d, _ = rmat_graph(int(kind[4:]), 16, seed)
+    a = native.static_counts(n, s, d)
+    assert a == native.static_counts_merge(n, s, d)
+    assert sum(a) == C(n, 4)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_semantics_keys_equal_sets(seed):
+    """The array form of the batch rules equals the set form on messy
+    batches (loops, repeats in both orientations, no-ops, A and D overlap)."""
+    from graphgen import raw_noise_batch
+    from oracle.semantics import apply_batch_keys, keys_to_pairs
+    n, s, d, _ = rmat_graph(9, 6, seed)
+    E = set(zip(s.tolist(), d.tolist()))
+    K = np.unique(canon_keys(s, d))
+    for k in range(4):
+        b = raw_noise_batch(n, *keys_to_pairs(K), 40, 100 * seed + k)
+        A, D, st = apply_batch(E, n, *b)
+        K, st2 = apply_batch_keys(K, n, *b)
+        assert st == st2
+        assert set(zip(*[x.tolist() for x in keys_to_pairs(K)])) == E
+    with pytest.raises(BatchRejected):
+        apply_batch_keys(K, n, [0], [n], [], [])

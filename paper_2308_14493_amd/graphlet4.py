@@ -194,7 +194,9 @@ class Graph:
 
     # ------------------------------------------------------------------
     def apply_batch(self, ins_src=(), ins_dst=(), del_src=(), del_dst=(), stats=False):
-        """Applies one batch; returns the 11 exact counts (Python ints)."""
+        """Applies one batch; returns the 11 exact counts (Python ints).  The
+        library's int64 output of the call (low 64 bits of each class, as
+        unsigned values) is kept in ``last_int64``."""
         lib = load()
         iu, iv, du, dv = _i32(ins_src), _i32(ins_dst), _i32(del_src), _i32(del_dst)
         assert iu.shape == iv.shape and du.shape == dv.shape
@@ -203,6 +205,7 @@ class Graph:
         _check(lib.gc_apply_batch(self._h, iu.ctypes.data, iv.ctypes.data, iu.size, du.ctypes.data,
                                   dv.ctypes.data, du.size, out.ctypes.data,
                                   ctypes.byref(st) if stats else None))
+        self.last_int64 = [int(x) for x in out.view(np.uint64)]
         c = self.counts()
         return (c, st.as_dict()) if stats else c
 
@@ -219,6 +222,7 @@ class Graph:
         _check(lib.gc_apply_batch_dev(self._h, ins_src.data_ptr(), ins_dst.data_ptr(), ins_src.numel(),
                                       del_src.data_ptr(), del_dst.data_ptr(), del_src.numel(),
                                       out.ctypes.data, ctypes.byref(st) if stats else None))
+        self.last_int64 = [int(x) for x in out.view(np.uint64)]
         c = self.counts()
         return (c, st.as_dict()) if stats else c
 

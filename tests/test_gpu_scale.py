@@ -1,0 +1,106 @@
+"""GPU parity at the stated sizes of the workloads, with the library's
+default knobs (no environment overrides): the plain per-batch path after
+every batch, and the pool of 256 graphs in one pass, against counts stored by
+tests/golden/make_scale.py, which calls only the oracle (static recount of
+the whole graph after every batch) and the input generators.  The inputs are
+drawn again here from the same seeds; their digest must equal the stored one
+before any count is compared.  Counts are exact integers: the bar is
+equality of all eleven classes, and the int64 view (low 64 bits plus the
+overflow mask) is checked against the exact value.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from graphgen import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+INT64_MAX = 2**63 - 1
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def golden(name):
+    return json.load(open(os.path.join(HERE, "golden", name)))
+
+
+@pytest.fixture(autouse=True)
+def default_knobs(monkeypatch):
+    for k in ("GC_C4_WINDOW", "GC_C4_NARROW_MAX", "GC_C4_DENSE_MIN", "GC_DEG_WAVE_ROW"):
+        monkeypatch.delenv(k, raising=False)
+
+
+def check_int64(g, want, graph=0):
+    out, mask = g.counts_int64(graph)
+    for c in range(11):
+        lo = want[c] & (2**64 - 1)
+        assert int(np.uint64(out[c])) == lo, "class %d low 64 bits" % c
+        assert bool(mask >> c & 1) == (want[c] > INT64_MAX), "class %d overflow bit" % c
+
+
+def run_stream(w, gold, dev_every=0):
+    from paper_2308_14493_amd.graphlet4 import Graph
+    assert wl.workload_digest(w) == gold["input_sha256"], "inputs differ from the stored ones"
+    steps = gold["steps"]
+    assert steps == list(range(len(w.batches) + 1))
+    with Graph(w.n, w.src, w.dst) as g:
+        assert g.counts() == gold["counts"][0], "initial counts"
+        check_int64(g, gold["counts"][0])
+        for j, b in enumerate(w.batches):
+            if dev_every and j % dev_every == dev_every - 1:
+                import torch
+                db = [torch.as_tensor(np.ascontiguousarray(x, dtype=np.int32)).cuda() for x in b]
+                got, st = g.apply_batch_dev(*db, stats=True)
+            else:
+                got, st = g.apply_batch(*b, stats=True)
+            say("%s batch %d (%d updates, whole %d): %s" % (w.name, j, b[0].size + b[2].size, st["whole_graph"],
+                                                          got == gold["counts"][j + 1]))
+            assert got == gold["counts"][j + 1], "counts after batch %d" % j
+            assert g.info()["m"] == gold["m"][j + 1]
+            assert g.last_int64 == [x & (2**64 - 1) for x in got]
+            check_int64(g, got)
+
+
+def test_rmat_s18_ef8_every_batch():
+    """R-MAT scale 18, ef 8; ten batches each of 1k, 10k and 100k updates;
+    every third batch through the device-array entry point."""
+    say("case rmat_s18_ef8 stream")
+    run_stream(wl.rmat_s18_stream(), golden("scale_rmat_s18_ef8.json"), dev_every=3)
+
+
+def test_chung_lu_2_4m_every_batch():
+    """Chung-Lu n = 2.4M, m = 5M, gamma 2.1: hubs of tens of thousands of
+    neighbours, batches of 1e3, 1e4 and 1e5 degree-proportional updates."""
+    say("case chung_lu 2.4M/5M stream")
+    run_stream(wl.chung_lu_stream(), golden("scale_chung_lu.json"))
+
+
+def test_pool256_one_round():
+    """The 256-graph pool: initial counts and the counts after one batch per
+    graph in one pooled pass, graph by graph."""
+    from paper_2308_14493_amd.graphlet4 import Graph
+    say("case pool256")
+    gold = golden("scale_pool256.json")
+    graphs = wl.pool256()
+    assert wl.pool_digest(graphs) == gold["input_sha256"]
+    pool = Graph.pool([x["n"] for x in graphs], [x["src"] for x in graphs], [x["dst"] for x in graphs])
+    try:
+        for i in range(len(graphs)):
+            assert pool.counts(i) == gold["counts_initial"][i], "graph %d initial" % i
+        got = pool.apply_batches([x["batch"] for x in graphs])
+        bad = [i for i in range(len(graphs)) if got[i] != gold["counts_after"][i]]
+        assert not bad, "graphs with wrong counts after the batch: %s" % bad[:10]
+        over = 0
+        for i in range(len(graphs)):
+            check_int64(pool, got[i], i)
+            over += got[i][10] > INT64_MAX
+        say("pool256: %d graphs with the empty class beyond int64" % over)
+        assert over > 0
+    finally:
+        pool.close()

@@ -29,9 +29,12 @@
  *   - an id outside [0, n) rejects the whole batch (GC_EINVAL) and leaves
  *     the graph and its counts unchanged.
  *
- * Conventions.  Every function returns GC_OK (0) or a negative gc_status.
- * On error the graph is unchanged and gc_last_error() describes the cause
- * (thread-local string).  Input arrays are borrowed for the duration of the
+ * Conventions.  Every function returns GC_OK (0) or a negative gc_status,
+ * and gc_last_error() describes the cause (thread-local string).  On error
+ * the graph is unchanged, with one exception: a device failure (GC_EDEVICE,
+ * or GC_ENOMEM while growing scratch) once a call has started to merge a
+ * batch into the resident graph, or a static recount has started to mark it,
+ * leaves the handle unusable, and every later call on it returns GC_ESTATE.  Input arrays are borrowed for the duration of the
  * call only: host arrays are copied before the call returns; device arrays
  * (the _dev variants) must stay valid until the call returns.  A handle owns
  * all of its device memory; it is not re-entrant (one call at a time per
@@ -131,6 +134,10 @@ typedef struct {
   float ms_finish;                   /* combine + purge (device) */
   int64_t c4_windows;                /* dense LDS windows of the large 4-cycle tier */
   int64_t c4_searches;               /* cursor visits of that tier (lower neighbours x window passes) */
+  int64_t tri_global_vertices;       /* vertices whose out-degree exceeds the LDS triangle tiers (global scratch) */
+  int64_t tri_exc_rebuilds;          /* triangle-tier vertices counted once per version (too many version-specific edges) */
+  int32_t retries;                   /* counting stages run again after growing scratch for a larger vertex */
+  int32_t reserved;
 } gc_batch_stats;
 
 /* One batch for one graph of a pool (host pointers). */
@@ -202,6 +209,14 @@ int gc_graph_info(const gc_graph* g, int32_t* num_graphs, int32_t graph, int64_t
  * arrays of capacity cap; *m_out = edge count (GC_EINVAL if cap < m). */
 int gc_export_edges(gc_graph* g, int32_t graph, int32_t* src, int32_t* dst, int64_t cap, int64_t* m_out);
 
+/* Estimated device bytes a single-graph handle built from this edge list
+ * reaches (resident rows with slack, region view, per-edge triangle counts,
+ * hub counters, multi-version passes, the transient arrays of the build),
+ * from the same sizing rules the library allocates by; batch staging is not
+ * included.  Host arrays; needs no device.  The server's admission uses it. */
+int gc_graph_footprint(int64_t n, const int32_t* src, const int32_t* dst, int64_t m, const gc_options* opt,
+                       int64_t* bytes);
+
 /* Diagnostics of the graphs option: passes captured as HIP graphs and
  * passes launched from a captured graph (replays included) so far. */
 int gc_graph_replays(const gc_graph* g, int64_t* captures, int64_t* launches);
@@ -218,8 +233,9 @@ int gc_graph_free(gc_graph* g);
  * when a graph's worker becomes free it takes up to three queued batches of
  * that graph into one counting pass (gc_apply_batch_seq); a batch that fails
  * the host-side id check fails alone.  Admission by memory:
- * a graph is admitted only if its estimated footprint fits the free HBM
- * (hipMemGetInfo, or hbm_budget_bytes when > 0) minus hbm_reserve_bytes,
+ * a graph is admitted only if its footprint (gc_graph_footprint) fits the
+ * free HBM (hipMemGetInfo, or, when hbm_budget_bytes > 0, that budget minus
+ * the footprints of the graphs already admitted) minus hbm_reserve_bytes,
  * else GC_ENOMEM; a batch starts only while the estimated bytes of batches in
  * flight stay within batch_budget_bytes (one batch always runs).  A server
  * may be used from several host threads. */

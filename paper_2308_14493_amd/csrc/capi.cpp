@@ -112,6 +112,42 @@ constexpr int C4_MID = 4096;
 
 void gc_set_error(const char* msg) { g_err = msg ? msg : ""; }
 
+// Device bytes a single-graph handle reaches, from the sizing rules of
+// build(), alloc_vertex_arrays() and size_count_scratch() (multi-version
+// passes included), for a graph of n vertices and m edges whose largest
+// degree is max_deg and whose largest out-degree under the build order is
+// max_out.  Batch staging is not included.
+int64_t gc_footprint_estimate(int64_t n, int64_t m, double slack, int64_t max_deg, int64_t max_out) {
+  const int64_t N = std::max<int64_t>(n, 1), E = 2 * m;
+  int64_t b = 0;
+  // resident rows (off, len, cap, gid, ext2int, int2ext) and the arena
+  b += 28 * N;
+  const int64_t used = (int64_t)((1.0 + slack) * (double)E) + 2 * N;
+  b += 4 * std::max<int64_t>(4 * used, used + (1 << 20));
+  // per-vertex pass arrays and work lists
+  b += (10 + L_NUM) * 4 * N;
+  // region view of the union (entries grow by a quarter when exceeded) and
+  // the merge scratch: rcol, rrow, t, vpos (20 B) + tp (16 B) per entry
+  const int64_t e_alloc = E + E / 2 + (1 << 20);
+  b += 36 * e_alloc + 4 * e_alloc;
+  b += 8 * (N + 1) + 16 * N + 4 * GC_NV_MAX * N;  // roff, c4 keys, degrees per version
+  b += (int64_t)radix_sort_tmp_bytes(std::max<int64_t>(2 * m, N)) + (int64_t)scan_tmp_bytes(N + 1);
+  // hub counters of the large 4-cycle tier and their cursors
+  const int64_t per = 12 * N;
+  int64_t slots = std::max<int64_t>(1, std::min<int64_t>(256, ((int64_t)16 << 30) / per));
+  slots = std::min<int64_t>(slots, N);
+  b += slots * per;
+  b += slots * 2 * (max_deg + max_deg / 4 + 64) * 8;
+  // triangles above the LDS tiers
+  if (max_out > tri_lds_max(4)) {
+    const int64_t cap = std::min<int64_t>(32767, max_out + max_out / 8 + 16);
+    b += 256 * tri_scratch_words64(4, cap) * 8;
+  }
+  // transient arrays of the build (edge keys, directed entries, ranks)
+  b += 64 * m + 24 * N;
+  return b + ((int64_t)64 << 20);
+}
+
 struct gc_graph {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -159,6 +195,12 @@ struct gc_graph {
   // (GC_DEG_WAVE_ROW overrides it: tests lower it to reach that path)
   int32_t deg_wave_row = 1 << 16;
   double region_frac[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+  // counting attempts after the first when scratch proves too small
+  // (GC_RETRY_LIMIT overrides it: tests set 0 to reach the failure path)
+  int retry_limit = 2;
+  // set while the resident graph holds a pass's union view (from the merge
+  // until the purge has been read back): a failure then leaves it unusable
+  bool in_pass = false;
 
   void* pin = nullptr;
   size_t pin_cap = 0;
@@ -383,7 +425,8 @@ int settle_retries(gc_graph* G, int nv, int radius, long long* state_d, BatchWor
                    int64_t entries, bool purge, int64_t max_touched, bool fresh) {
   int attempts = 0;
   while (G->out_bst()[BS_RETRY]) {
-    if (++attempts > 2) raise(GC_EDEVICE, "counting scratch still too small after two more attempts");
+    if (++attempts > G->retry_limit)
+      raise(GC_EDEVICE, "counting scratch still too small after %d more attempts", G->retry_limit);
     note_maxima(G);
     size_count_scratch(G, nv, entries);
     reset_count_stage(G);
@@ -477,6 +520,7 @@ void read_state(gc_graph* G) {
 void setup_handle(gc_graph* G, const gc_options* opt) {
   if (opt) G->opt = *opt; else gc_options_default(&G->opt);
   if (const char* e = std::getenv("GC_DEG_WAVE_ROW")) G->deg_wave_row = std::max(1, std::min(1 << 16, std::atoi(e)));
+  if (const char* e = std::getenv("GC_RETRY_LIMIT")) G->retry_limit = std::max(0, std::min(8, std::atoi(e)));
   if (G->opt.radius < 0 || G->opt.radius > 4) raise(GC_EINVAL, "radius must be in [0, 4]");
   if (!(G->opt.slack >= 0.0f && G->opt.slack <= 16.0f)) raise(GC_EINVAL, "slack must be in [0, 16]");
   int ndev = 0;
@@ -661,6 +705,8 @@ void fill_stats(gc_graph* G, gc_batch_stats* st, const std::vector<unsigned long
   st->pass_batches = nb;
   st->c4_windows = (int64_t)hb[BS_C4_WINDOWS];
   st->c4_searches = (int64_t)hb[BS_C4_SEARCH];
+  st->tri_global_vertices = (int64_t)hb[BS_TRI_GLOBAL];
+  st->tri_exc_rebuilds = (int64_t)hb[BS_TRI_REBUILD];
   st->ms_total = (float)ms_total;
   if (timed) {
     float a = 0;
@@ -738,6 +784,7 @@ void enqueue_pass(gc_graph* G, const PassPlan& L, BatchIn& B, BatchWork& W, bool
   unsigned long long* sR = radix_sort_u64(G->dirR.as<unsigned long long>(), G->dirR_alt.as<unsigned long long>(),
                                           G->sort_tmp.p, 2 * L.cap_d, ctr + C_DIRR, 2 * G->bits, s);
   if (sA != W.dirA || sD != W.dirD || sR != W.dirR) raise(GC_EDEVICE, "sorted merge lists not where expected");
+  G->in_pass = true;  // from here on the resident graph holds the union view until the purge
   launch_mark_rows(sA, 2 * L.cap_i, ctr, C_DIRA, G->bits, W.a_beg, W.na, W.mark, W.touched, W.tix, s);
   launch_mark_rows(sD, 2 * L.cap_d, ctr, C_DIRD, G->bits, nullptr, nullptr, W.mark, W.touched, W.tix, s);
   launch_mark_rows(sR, 2 * L.cap_d, ctr, C_DIRR, G->bits, W.r_beg, W.nr, W.mark, W.touched, W.tix, s);
@@ -889,6 +936,7 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
     }
     B.iu = d_ids; B.iv = d_ids + L.cap_i; B.du = d_ids + 2 * L.cap_i; B.dv = d_ids + 2 * L.cap_i + L.cap_d;
   }
+  int retries = 0;
   BatchWork W = make_work(G);
   W.dirA = radix_sort_result(G->dirA.as<unsigned long long>(), G->dirA_alt.as<unsigned long long>(), 2 * L.cap_i,
                              2 * G->bits);
@@ -898,6 +946,9 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
                              2 * G->bits);
 
   const bool use_graph = G->opt.graphs && !dev && !timed_run;
+  // A failure once the merge may have run leaves the union view in the
+  // resident graph: the handle is then marked unusable (GC_ESTATE).
+  try {
   if (use_graph) {
     const std::vector<uint64_t> sig = pass_signature(G, L, make_count_args(G, L.nv, L.dense_min, false));
     auto it = G->graphs.find(sig);
@@ -920,14 +971,21 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
       it = G->graphs.emplace(sig, ex).first;
       ++G->graph_captures;
     }
+    G->in_pass = true;
     HIPCHK(hipGraphLaunch(it->second, s));
     ++G->graph_launches;
   } else {
     enqueue_pass(G, L, B, W, timed_run);
   }
   G->sync();
-  const int retries = settle_retries(G, L.nv, L.radius, G->state.as<long long>(), W, L.dense_min, L.union_bound,
-                                     true, L.max_touched, false);
+  retries = settle_retries(G, L.nv, L.radius, G->state.as<long long>(), W, L.dense_min, L.union_bound, true,
+                           L.max_touched, false);
+  } catch (...) {
+    if (G->in_pass) G->broken = true;
+    G->in_pass = false;
+    throw;
+  }
+  G->in_pass = false;
 
   const unsigned long long* hbp = G->out_bst();
   const std::vector<unsigned long long> hb(hbp, hbp + BS_COUNT);
@@ -985,6 +1043,7 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
                  timed && retries == 0, ms, mk);
       stats[q].c4_dense_min = L.dense_min;
       stats[q].whole_graph = L.radius < 0;
+      stats[q].retries = retries;
     }
   }
 }
@@ -1121,18 +1180,27 @@ int gc_recount_exact(gc_graph* g, int32_t graph, int64_t hi[11], uint64_t lo[11]
     HIPCHK(hipSetDevice(g->device));
     hipStream_t s = g->stream;
     PoolDev P = g->pd();
-    launch_all_flags(P, GC_F_NEW, GC_ID, s);
-    fill_u64((unsigned long long*)g->state_tmp.p, 0ull, (int64_t)g->k * ST_STRIDE, s);
-    zero_small(g);
     BatchWork W = make_work(g);
     size_count_scratch(g, 2, g->entries);
-    enqueue_count(g, 2, -1, g->state_tmp.as<long long>(), W, make_count_args(g, 2, g->dense_min_best, true), false);
-    enqueue_readback(g, g->state_tmp.as<long long>());
-    g->sync();
-    settle_retries(g, 2, -1, g->state_tmp.as<long long>(), W, g->dense_min_best, g->entries, false, 0, true);
-    launch_all_flags(P, 0u, GC_ID, s);
-    std::vector<long long> st(g->out_state(), g->out_state() + (size_t)g->k * ST_STRIDE);
-    g->sync();
+    std::vector<long long> st;
+    // every entry carries the insertion flag until the last line: a failure
+    // in between leaves the handle unusable
+    try {
+      launch_all_flags(P, GC_F_NEW, GC_ID, s);
+      fill_u64((unsigned long long*)g->state_tmp.p, 0ull, (int64_t)g->k * ST_STRIDE, s);
+      zero_small(g);
+      enqueue_count(g, 2, -1, g->state_tmp.as<long long>(), W, make_count_args(g, 2, g->dense_min_best, true),
+                    false);
+      enqueue_readback(g, g->state_tmp.as<long long>());
+      g->sync();
+      settle_retries(g, 2, -1, g->state_tmp.as<long long>(), W, g->dense_min_best, g->entries, false, 0, true);
+      launch_all_flags(P, 0u, GC_ID, s);
+      st.assign(g->out_state(), g->out_state() + (size_t)g->k * ST_STRIDE);
+      g->sync();
+    } catch (...) {
+      g->broken = true;
+      throw;
+    }
     if (st[graph * ST_STRIDE + ST_ERR]) raise(GC_EDEVICE, "inexact totals in the recount");
     i128 I[11];
     finalize(&st[graph * ST_STRIDE], g->gn[graph], I);
@@ -1186,6 +1254,37 @@ int gc_export_edges(gc_graph* g, int32_t graph, int32_t* src, int32_t* dst, int6
       HIPCHK(hipMemcpyAsync(dst, ed.as<int32_t>() + range[0], m * 4, hipMemcpyDeviceToHost, s));
     }
     g->sync();
+  });
+}
+
+int gc_graph_footprint(int64_t n, const int32_t* src, const int32_t* dst, int64_t m, const gc_options* opt,
+                       int64_t* bytes) {
+  return guard([&] {
+    if (!bytes) raise(GC_EINVAL, "bytes is NULL");
+    if (n < 1 || m < 0 || (m > 0 && (!src || !dst))) raise(GC_EINVAL, "bad graph size or edge arrays");
+    gc_options o;
+    if (opt) o = *opt; else gc_options_default(&o);
+    // the largest degree and the largest out-degree under the build order
+    // (degree, then id) of the edge list as given; repeats counted, which
+    // can only raise the estimate
+    std::vector<int32_t> deg((size_t)n, 0), out((size_t)n, 0);
+    for (int64_t i = 0; i < m; ++i) {
+      const int32_t u = src[i], v = dst[i];
+      if (u < 0 || u >= n || v < 0 || v >= n) raise(GC_EINVAL, "edge %lld has a vertex id outside [0, n)", (long long)i);
+      if (u != v) { ++deg[u]; ++deg[v]; }
+    }
+    for (int64_t i = 0; i < m; ++i) {
+      const int32_t u = src[i], v = dst[i];
+      if (u == v) continue;
+      const bool u_first = deg[u] < deg[v] || (deg[u] == deg[v] && u < v);
+      ++out[u_first ? u : v];
+    }
+    int64_t max_deg = 0, max_out = 0;
+    for (int64_t v = 0; v < n; ++v) {
+      max_deg = std::max<int64_t>(max_deg, deg[v]);
+      max_out = std::max<int64_t>(max_out, out[v]);
+    }
+    *bytes = gc_footprint_estimate(n, m, o.slack, max_deg, max_out);
   });
 }
 

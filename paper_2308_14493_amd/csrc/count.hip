@@ -674,6 +674,7 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL<NV>& S, int64_t 
     for (int x = 0; x < NV; ++x) kacc[x] += kv[x];
   } else {
     // too many version-specific edges: rebuild E per version and count
+    if (threadIdx.x == 0) atomicAdd(&A.bstats[BS_TRI_REBUILD], 1ull);
     for (int x = 0; x < NV; ++x) {
       __syncthreads();
       for (int64_t k = threadIdx.x; k < ew; k += blockDim.x) S.E[k] = 0ull;
@@ -778,6 +779,7 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int L, unsig
       if (threadIdx.x == 0) atomicAdd(&A.bstats[BS_RETRY], 1ull);
       continue;
     }
+    if (CAP == 0 && threadIdx.x == 0) atomicAdd(&A.bstats[BS_TRI_GLOBAL], 1ull);
     const int g = A.gid[u];
     if (g != cur_g) {
       if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_K4, kacc);

@@ -67,6 +67,8 @@ enum {
   BS_COUNT_STAGE, BS_C4_S = BS_COUNT_STAGE, BS_C4_M, BS_C4_L, BS_WEDGES, BS_TRIPROBE, BS_RETRY,
   BS_C4_WINDOWS,  // dense LDS windows of the large 4-cycle tier
   BS_C4_SEARCH,   // cursor searches of that tier (lower neighbours x window passes)
+  BS_TRI_GLOBAL,  // vertices counted by the global-scratch triangle tier
+  BS_TRI_REBUILD, // vertices whose version-specific edges overflowed the exception list
   BS_COUNT
 };
 

@@ -160,3 +160,5 @@ void launch_combine(int nv, const unsigned long long* sig, long long* state, lon
 
 // capi.cpp: thread-local error text read by gc_last_error()
 void gc_set_error(const char* msg);
+// device bytes a single-graph handle reaches (capi.cpp); used by the server's admission
+int64_t gc_footprint_estimate(int64_t n, int64_t m, double slack, int64_t max_deg, int64_t max_out);

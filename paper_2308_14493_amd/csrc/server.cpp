@@ -13,6 +13,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -175,16 +176,17 @@ int gc_server_create(const gc_server_opts* opts, gc_server** out) {
 int gc_server_add_graph(gc_server* s, int64_t n, const int32_t* src, const int32_t* dst, int64_t m,
                         const gc_options* opt, int32_t* graph_id) {
   if (!s || !graph_id) return fail(GC_EINVAL, "NULL argument");
-  // footprint estimate: resident arena (4 B per entry, 4x slack and room),
-  // region view and per-edge counts (12 B per entry), per-vertex arrays
-  const int64_t est = 16 * 2 * m + 12 * 2 * m + 160 * n + ((int64_t)64 << 20);
+  if (n < 1 || m < 0 || (m > 0 && (!src || !dst))) return fail(GC_EINVAL, "bad graph size or edge arrays");
+  gc_options o;
+  if (opt) o = *opt; else gc_options_default(&o);
+  // footprint from the library's own sizing rules
+  int64_t est = 0;
+  if (int rc = gc_graph_footprint(n, src, dst, m, &o, &est)) return rc;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if ((int32_t)s->slots.size() >= s->opts.max_graphs) return fail(GC_EBUSY, "server holds max_graphs graphs");
     if (s->free_hbm() - s->opts.hbm_reserve_bytes < est) return fail(GC_ENOMEM, "not enough free HBM to admit the graph");
   }
-  gc_options o;
-  if (opt) o = *opt; else gc_options_default(&o);
   o.device = s->opts.device;
   o.stream = nullptr;  // every graph runs on its own stream
   gc_graph* g = nullptr;

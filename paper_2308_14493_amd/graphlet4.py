@@ -38,7 +38,8 @@ class BatchStats(ctypes.Structure):
         ("whole_graph", _I32), ("overflow_mask", ctypes.c_uint32), ("pass_batches", _I32)] + [
         (n, ctypes.c_float) for n in ("ms_total", "ms_prepare", "ms_tri", "ms_edge", "ms_c4_small",
                                       "ms_c4_mid", "ms_c4_large", "ms_finish")] + [
-        ("c4_windows", _I64), ("c4_searches", _I64)]
+        ("c4_windows", _I64), ("c4_searches", _I64), ("tri_global_vertices", _I64), ("tri_exc_rebuilds", _I64),
+        ("retries", _I32), ("reserved", _I32)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
@@ -59,7 +60,7 @@ _lib = None
 
 EXPORTS = ["gc_options_default", "gc_graph_init", "gc_pool_init", "gc_apply_batch", "gc_apply_batch_dev",
            "gc_apply_batches", "gc_apply_batch_seq", "gc_get_counts", "gc_get_counts_exact", "gc_recount_exact", "gc_graph_info",
-           "gc_export_edges", "gc_graph_replays", "gc_graph_free", "gc_strerror", "gc_last_error",
+           "gc_export_edges", "gc_graph_footprint", "gc_graph_replays", "gc_graph_free", "gc_strerror", "gc_last_error",
            "gc_server_opts_default", "gc_server_create", "gc_server_add_graph", "gc_server_submit",
            "gc_server_wait", "gc_server_counts", "gc_server_destroy"]
 
@@ -97,6 +98,7 @@ def load(path: str = LIB_PATH):
     lib.gc_graph_info.argtypes = [_P, ctypes.POINTER(_I32), _I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]
     lib.gc_export_edges.argtypes = [_P, _I32, _P, _P, _I64, ctypes.POINTER(_I64)]
     lib.gc_graph_replays.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]
+    lib.gc_graph_footprint.argtypes = [_I64, _P, _P, _I64, ctypes.POINTER(Options), ctypes.POINTER(_I64)]
     lib.gc_graph_free.argtypes = [_P]
     lib.gc_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
     lib.gc_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)]
@@ -143,6 +145,16 @@ def _opts(radius, slack, device, stream, autotune=None, graphs=None):
     o.device = device
     o.stream = stream
     return o
+
+
+def footprint(n, src, dst, slack=None):
+    """Estimated device bytes of a handle built from this edge list."""
+    lib = load()
+    s, d = _i32(src), _i32(dst)
+    opt = _opts(None, slack, 0, None)
+    b = _I64()
+    _check(lib.gc_graph_footprint(int(n), s.ctypes.data, d.ctypes.data, s.size, ctypes.byref(opt), ctypes.byref(b)))
+    return b.value
 
 
 class Graph:

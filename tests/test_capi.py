@@ -61,3 +61,18 @@ def test_server_admission_refusal_without_device():
     o.max_graphs = 0
     h = ctypes.c_void_p()
     assert lib.gc_server_create(ctypes.byref(o), ctypes.byref(h)) == -1
+
+
+def test_footprint_estimate_without_device():
+    """The admission estimate is host arithmetic: positive, growing with the
+    graph, and it rejects ids outside [0, n)."""
+    from paper_2308_14493_amd.graphlet4 import footprint, GraphletError
+    small = footprint(100, [0, 1], [1, 2])
+    big = footprint(100000, list(range(0, 99999)), list(range(1, 100000)))
+    assert 0 < small < big
+    try:
+        footprint(10, [0], [10])
+    except GraphletError as e:
+        assert e.code == -1
+    else:
+        raise AssertionError("an id outside [0, n) must be rejected")

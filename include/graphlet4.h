@@ -175,6 +175,30 @@ int gc_apply_batch_dev(gc_graph* g, const int32_t* ins_src, const int32_t* ins_d
                        const int32_t* del_src, const int32_t* del_dst, int64_t n_del,
                        int64_t counts[11], gc_batch_stats* stats);
 
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture of the caller's own work, tight serving loops, harnesses that
+ * forbid hipMalloc): gc_apply_batch_dev with no allocation in the call: no
+ * hipMalloc, hipFree or pinned memory, and on success no host heap memory
+ * either (only an error path allocates its message).  The batch's
+ * staging (keys, merge lists, per-row work arrays; at most 64 MiB) lives in
+ * one static device array per GPU, which the library holds until the process
+ * ends; every other buffer is the handle's own and must already be large
+ * enough.  Limits: the staging, 72 (c_i + c_d) + 32 c_i + 64 c_d bytes with
+ * c_i, c_d the numbers of insertions and deletions rounded up to powers of
+ * two (at least 64), must fit the 64 MiB array -- every batch of at most
+ * 262144 insertions and 262144 deletions does (GC_EINVAL beyond, nothing
+ * changed); a graph whose resident rows, region
+ * view or counting scratch would have to grow for this batch is refused with
+ * GC_ENOMEM and left unchanged, and so is a batch after which a vertex
+ * outgrows the counting scratch (its merge is undone on the device) -- one
+ * gc_apply_batch_dev call of that size grows the handle's buffers.  Results
+ * are those of gc_apply_batch_dev.  Single-graph handles only.  The static
+ * array is shared by every handle on a device: calls that overlap in time on
+ * one GPU (from several host threads) race and must not be made. */
+int gc_apply_batch_dev_noalloc(gc_graph* g, const int32_t* ins_src, const int32_t* ins_dst, int64_t n_ins,
+                               const int32_t* del_src, const int32_t* del_dst, int64_t n_del,
+                               int64_t counts[11], gc_batch_stats* stats);
+
 /* Applies batch[g] to graph g of a pool, for all k graphs at once; counts
  * is k x 11 (may be NULL).  The batches are independent; the result for
  * each graph equals k separate gc_apply_batch calls. */

@@ -12,8 +12,17 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
+
+// Batch staging of gc_apply_batch_dev_noalloc: one fixed array per device
+// that the library runs on, held until the process ends.  Host code reaches
+// it only through the address hipGetSymbolAddress returns for the current
+// device (noalloc_scratch_ptr); the array's name itself is not a device
+// address on the host.
+static constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
 
@@ -343,6 +352,38 @@ void size_count_scratch(gc_graph* G, int nv, int64_t entries) {
   }
 }
 
+// True when size_count_scratch(G, nv, entries) would neither allocate nor
+// change a size.
+bool count_scratch_fits(const gc_graph* G, int nv, int64_t entries) {
+  const int64_t N = G->N;
+  auto has = [](const DevBuf& b, size_t bytes) { return b.p != nullptr && std::max<size_t>(bytes, 16) <= b.cap; };
+  if (!has(G->roff, (N + 1) * sizeof(int64_t)) || !has(G->c4_keys, N * sizeof(unsigned long long)) ||
+      !has(G->c4_keys_alt, N * sizeof(unsigned long long)))
+    return false;
+  if (!has(G->sort_tmp, radix_sort_tmp_bytes(N) + 64) || !has(G->scan_tmp, scan_tmp_bytes(N + 1) + 64)) return false;
+  if (entries > G->e_alloc) return false;
+  const int64_t E = G->e_alloc;
+  if (!has(G->rcol, E * sizeof(uint32_t)) || !has(G->rrow, E * sizeof(int32_t)) ||
+      !has(G->t, E * sizeof(unsigned long long)) || !has(G->vpos, E * sizeof(int32_t)))
+    return false;
+  if (nv > 2 && !has(G->tp, 2 * E * sizeof(unsigned long long))) return false;
+  if (!has(G->dver, (size_t)N * GC_NV_MAX * sizeof(int32_t))) return false;
+  const int64_t per = N * (int64_t)(sizeof(unsigned long long) + sizeof(int32_t));
+  int64_t slots = std::max<int64_t>(1, std::min<int64_t>(256, ((int64_t)16 << 30) / std::max<int64_t>(per, 1)));
+  slots = std::min<int64_t>(slots, std::max<int64_t>(1, N));
+  if (slots > G->c4_slots) return false;
+  if (G->seen_maxlow > G->c4_cur_low || G->c4_cur_low < 64) return false;
+  if (!has(G->c4_cur, (size_t)(G->c4_slots * 2 * G->c4_cur_low) * sizeof(int64_t))) return false;
+  if (!has(G->c4_blk, (size_t)(N / c4_block_ids() + 2) * sizeof(int32_t))) return false;
+  if (G->seen_maxdp > tri_lds_max(nv)) {
+    if (G->seen_maxdp > 32767) return false;
+    const int64_t cap = std::max<int64_t>(G->tri_cap, std::min<int64_t>(32767, G->seen_maxdp + G->seen_maxdp / 8 + 16));
+    if (cap != G->tri_cap) return false;
+    if ((size_t)(tri_scratch_words64(nv, cap) * 256) * sizeof(unsigned long long) > G->tri_scratch.cap) return false;
+  }
+  return true;
+}
+
 CountArgs make_count_args(gc_graph* G, int nv, int64_t dense_min, bool fresh) {
   (void)nv;
   CountArgs A;
@@ -442,26 +483,61 @@ int settle_retries(gc_graph* G, int nv, int radius, long long* state_d, BatchWor
   return attempts;
 }
 
-BatchWork make_work(gc_graph* G) {
+// Per-batch staging of a pass: the input table and the batch's keys, the
+// directed merge lists and the per-touched-row arrays.  The handle's own
+// buffers, or (gc_apply_batch_dev_noalloc) pieces of the static scratch.
+struct Staging {
+  void* bin = nullptr;
+  unsigned long long *keys = nullptr, *keys_alt = nullptr, *dirA = nullptr, *dirA_alt = nullptr;
+  unsigned long long *dirD = nullptr, *dirD_alt = nullptr, *dirR = nullptr, *dirR_alt = nullptr;
+  int32_t* touched = nullptr;
+  int64_t* dest = nullptr;
+  int32_t* newcap = nullptr;
+  int32_t* tlen = nullptr;
+  int64_t* tpre = nullptr;
+};
+
+Staging handle_staging(gc_graph* G) {
+  Staging S;
+  S.bin = G->bin.p;
+  S.keys = G->keys.as<unsigned long long>();
+  S.keys_alt = G->keys_alt.as<unsigned long long>();
+  S.dirA = G->dirA.as<unsigned long long>();
+  S.dirA_alt = G->dirA_alt.as<unsigned long long>();
+  S.dirD = G->dirD.as<unsigned long long>();
+  S.dirD_alt = G->dirD_alt.as<unsigned long long>();
+  S.dirR = G->dirR.as<unsigned long long>();
+  S.dirR_alt = G->dirR_alt.as<unsigned long long>();
+  S.touched = G->touched.as<int32_t>();
+  S.dest = G->dest.as<int64_t>();
+  S.newcap = G->newcap.as<int32_t>();
+  S.tlen = G->tlen.as<int32_t>();
+  S.tpre = G->tpre.as<int64_t>();
+  return S;
+}
+
+BatchWork make_work(gc_graph* G, const Staging& S) {
   BatchWork W;
   W.c = G->ctr.as<unsigned long long>();
-  W.dirA = G->dirA.as<unsigned long long>();
-  W.dirD = G->dirD.as<unsigned long long>();
-  W.dirR = G->dirR.as<unsigned long long>();
+  W.dirA = S.dirA;
+  W.dirD = S.dirD;
+  W.dirR = S.dirR;
   W.a_beg = G->a_beg.as<int32_t>();
   W.na = G->na.as<int32_t>();
   W.r_beg = G->r_beg.as<int32_t>();
   W.nr = G->nr.as<int32_t>();
   W.mark = G->mark.as<int32_t>();
   W.tix = G->tix.as<int32_t>();
-  W.touched = G->touched.as<int32_t>();
-  W.dest = G->dest.as<int64_t>();
-  W.newcap = G->newcap.as<int32_t>();
-  W.tlen = G->tlen.as<int32_t>();
-  W.tpre = G->tpre.as<int64_t>();
+  W.touched = S.touched;
+  W.dest = S.dest;
+  W.newcap = S.newcap;
+  W.tlen = S.tlen;
+  W.tpre = S.tpre;
   W.scratch = G->scratch.as<uint32_t>();
   return W;
 }
+
+BatchWork make_work(gc_graph* G) { return make_work(G, handle_staging(G)); }
 
 void alloc_vertex_arrays(gc_graph* G) {
   const int64_t N = G->N;
@@ -517,6 +593,27 @@ void read_state(gc_graph* G) {
   G->sync();
 }
 
+// Address of the static staging array on each device, looked up once per
+// device with that device current (at the first handle built on it).
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+void noalloc_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) raise(GC_EDEVICE, "device %d beyond the supported %d", device, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) raise(GC_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+  g_noalloc_ptr[device] = ptr;
+}
+
+void* noalloc_scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  return (device >= 0 && device < kMaxDevices) ? g_noalloc_ptr[device] : nullptr;
+}
+
 void setup_handle(gc_graph* G, const gc_options* opt) {
   if (opt) G->opt = *opt; else gc_options_default(&G->opt);
   if (const char* e = std::getenv("GC_DEG_WAVE_ROW")) G->deg_wave_row = std::max(1, std::min(1 << 16, std::atoi(e)));
@@ -532,6 +629,7 @@ void setup_handle(gc_graph* G, const gc_options* opt) {
   HIPCHK(hipGetDeviceProperties(&prop, G->device));
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     raise(GC_EDEVICE, "device %d is %s; this library is built for gfx950", G->device, prop.gcnArchName);
+  noalloc_scratch_setup(G->device);
   if (G->opt.stream) {
     G->stream = (hipStream_t)G->opt.stream;
   } else {
@@ -659,6 +757,13 @@ void build(gc_graph* G, int32_t k, const int64_t* n, const int32_t* const* src, 
   zero_small(G);
   BatchWork W = make_work(G);
   size_count_scratch(G, 2, nd);
+  // the merge's copy of the touched rows, as large as the region view, so
+  // that a batch can be applied without growing it
+  G->scratch.ensure(std::max<int64_t>(G->e_alloc, 1) * 4);
+  // sort and scan temporaries for batches up to the allocation-free limit
+  // (2^18 insertions and 2^18 deletions: 2^20 touched rows at most)
+  G->sort_tmp.ensure(radix_sort_tmp_bytes(std::max<int64_t>(std::max<int64_t>(2 * M, N), 1 << 20)) + 64);
+  G->scan_tmp.ensure(scan_tmp_bytes(std::max<int64_t>(N, 1 << 20) + 1) + 64);
   enqueue_count(G, 2, -1, G->state.as<long long>(), W, make_count_args(G, 2, G->dense_min_best, true), false);
   enqueue_readback(G, G->state.as<long long>());
   G->sync();
@@ -672,9 +777,8 @@ void build(gc_graph* G, int32_t k, const int64_t* n, const int32_t* const* src, 
   for (int g = 0; g < k; ++g) G->hstate[g * ST_STRIDE + ST_N] = n[g];
 }
 
-void fill_stats(gc_graph* G, gc_batch_stats* st, const std::vector<unsigned long long>& hb,
-                const std::vector<unsigned long long>& hc, int j, int nb, int64_t n_ins, int64_t n_del, bool timed,
-                double ms_total, uint32_t ovf) {
+void fill_stats(gc_graph* G, gc_batch_stats* st, const unsigned long long* hb, const unsigned long long* hc, int j,
+                int nb, int64_t n_ins, int64_t n_del, bool timed, double ms_total, uint32_t ovf) {
   if (!st) return;
   std::memset(st, 0, sizeof(*st));
   st->offered_ins = n_ins;
@@ -758,31 +862,27 @@ struct PassPlan {
 // counting, purge, results to the pinned buffer.  No allocation and no
 // synchronisation (except the device-array id check, which is never
 // captured), so the same sequence runs directly or under stream capture.
-void enqueue_pass(gc_graph* G, const PassPlan& L, BatchIn& B, BatchWork& W, bool timed) {
+void enqueue_pass(gc_graph* G, const PassPlan& L, BatchIn& B, BatchWork& W, const Staging& S, bool timed,
+                  bool upload) {
   hipStream_t s = G->stream;
   PoolDev P = G->pd();
   unsigned long long* bst = G->bstats.as<unsigned long long>();
   unsigned long long* ctr = G->ctr.as<unsigned long long>();
   zero_small(G);
-  HIPCHK(hipMemcpyAsync(G->bin.p, G->pin, L.in_bytes, hipMemcpyHostToDevice, s));
+  if (upload) HIPCHK(hipMemcpyAsync(S.bin, G->pin, L.in_bytes, hipMemcpyHostToDevice, s));
   if (timed) HIPCHK(hipEventRecord(G->ev[0], s));
-  launch_ingest_keys(P, B, G->bits, G->keys.as<unsigned long long>(), ctr, bst, L.cap_t, s);
-  unsigned long long* sk = radix_sort_u64(G->keys.as<unsigned long long>(), G->keys_alt.as<unsigned long long>(),
-                                          G->sort_tmp.p, L.cap_t, ctr + C_NKEYS, 2 * G->bits + 3, s);
-  launch_ingest_classify(P, sk, L.cap_t, G->bits, L.npass, L.nv, G->dirA.as<unsigned long long>(),
-                         G->dirD.as<unsigned long long>(), G->dirR.as<unsigned long long>(), ctr, bst, s);
+  launch_ingest_keys(P, B, G->bits, S.keys, ctr, bst, L.cap_t, s);
+  unsigned long long* sk = radix_sort_u64(S.keys, S.keys_alt, G->sort_tmp.p, L.cap_t, ctr + C_NKEYS, 2 * G->bits + 3, s);
+  launch_ingest_classify(P, sk, L.cap_t, G->bits, L.npass, L.nv, S.dirA, S.dirD, S.dirR, ctr, bst, s);
   if (L.dev) {
     unsigned long long err = 0;
     HIPCHK(hipMemcpyAsync(&err, bst + PB_IDX(0, PB_ERR), 8, hipMemcpyDeviceToHost, s));
     G->sync();
     if (err) raise(GC_EINVAL, "batch has %llu vertex ids outside the graph", err);
   }
-  unsigned long long* sA = radix_sort_u64(G->dirA.as<unsigned long long>(), G->dirA_alt.as<unsigned long long>(),
-                                          G->sort_tmp.p, 2 * L.cap_i, ctr + C_DIRA, 2 * G->bits, s);
-  unsigned long long* sD = radix_sort_u64(G->dirD.as<unsigned long long>(), G->dirD_alt.as<unsigned long long>(),
-                                          G->sort_tmp.p, 2 * L.cap_d, ctr + C_DIRD, 2 * G->bits, s);
-  unsigned long long* sR = radix_sort_u64(G->dirR.as<unsigned long long>(), G->dirR_alt.as<unsigned long long>(),
-                                          G->sort_tmp.p, 2 * L.cap_d, ctr + C_DIRR, 2 * G->bits, s);
+  unsigned long long* sA = radix_sort_u64(S.dirA, S.dirA_alt, G->sort_tmp.p, 2 * L.cap_i, ctr + C_DIRA, 2 * G->bits, s);
+  unsigned long long* sD = radix_sort_u64(S.dirD, S.dirD_alt, G->sort_tmp.p, 2 * L.cap_d, ctr + C_DIRD, 2 * G->bits, s);
+  unsigned long long* sR = radix_sort_u64(S.dirR, S.dirR_alt, G->sort_tmp.p, 2 * L.cap_d, ctr + C_DIRR, 2 * G->bits, s);
   if (sA != W.dirA || sD != W.dirD || sR != W.dirR) raise(GC_EDEVICE, "sorted merge lists not where expected");
   G->in_pass = true;  // from here on the resident graph holds the union view until the purge
   launch_mark_rows(sA, 2 * L.cap_i, ctr, C_DIRA, G->bits, W.a_beg, W.na, W.mark, W.touched, W.tix, s);
@@ -937,13 +1037,11 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
     B.iu = d_ids; B.iv = d_ids + L.cap_i; B.du = d_ids + 2 * L.cap_i; B.dv = d_ids + 2 * L.cap_i + L.cap_d;
   }
   int retries = 0;
-  BatchWork W = make_work(G);
-  W.dirA = radix_sort_result(G->dirA.as<unsigned long long>(), G->dirA_alt.as<unsigned long long>(), 2 * L.cap_i,
-                             2 * G->bits);
-  W.dirD = radix_sort_result(G->dirD.as<unsigned long long>(), G->dirD_alt.as<unsigned long long>(), 2 * L.cap_d,
-                             2 * G->bits);
-  W.dirR = radix_sort_result(G->dirR.as<unsigned long long>(), G->dirR_alt.as<unsigned long long>(), 2 * L.cap_d,
-                             2 * G->bits);
+  const Staging S = handle_staging(G);
+  BatchWork W = make_work(G, S);
+  W.dirA = radix_sort_result(S.dirA, S.dirA_alt, 2 * L.cap_i, 2 * G->bits);
+  W.dirD = radix_sort_result(S.dirD, S.dirD_alt, 2 * L.cap_d, 2 * G->bits);
+  W.dirR = radix_sort_result(S.dirR, S.dirR_alt, 2 * L.cap_d, 2 * G->bits);
 
   const bool use_graph = G->opt.graphs && !dev && !timed_run;
   // A failure once the merge may have run leaves the union view in the
@@ -957,7 +1055,7 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
       HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       hipGraph_t gr = nullptr;
       try {
-        enqueue_pass(G, L, B, W, false);
+        enqueue_pass(G, L, B, W, S, false, true);
       } catch (...) {
         (void)hipStreamEndCapture(s, &gr);
         if (gr) (void)hipGraphDestroy(gr);
@@ -975,7 +1073,7 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
     HIPCHK(hipGraphLaunch(it->second, s));
     ++G->graph_launches;
   } else {
-    enqueue_pass(G, L, B, W, timed_run);
+    enqueue_pass(G, L, B, W, S, timed_run, true);
   }
   G->sync();
   retries = settle_retries(G, L.nv, L.radius, G->state.as<long long>(), W, L.dense_min, L.union_bound, true,
@@ -1039,12 +1137,175 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
       uint32_t mk = 0;
       if (seq) mk = ovf[q];
       else for (uint32_t m : ovf) mk |= m;
-      fill_stats(G, &stats[q], hb, hc, seq ? q : 0, L.npass, seq ? b[q].n_ins : L.ni, seq ? b[q].n_del : L.ndl,
+      fill_stats(G, &stats[q], hb.data(), hc.data(), seq ? q : 0, L.npass, seq ? b[q].n_ins : L.ni, seq ? b[q].n_del : L.ndl,
                  timed && retries == 0, ms, mk);
       stats[q].c4_dense_min = L.dense_min;
       stats[q].whole_graph = L.radius < 0;
       stats[q].retries = retries;
     }
+  }
+}
+
+// Carves the batch staging of a one-batch device-array pass with batch
+// capacities cap_i, cap_d out of `base` (nullptr: sizes only); returns the
+// bytes used.
+size_t carve_staging(char* base, int64_t cap_i, int64_t cap_d, size_t table_bytes, Staging* S) {
+  const int64_t cap_t = cap_i + cap_d, mt = 2 * cap_t;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return (void*)p;
+  };
+  S->bin = take(table_bytes);
+  S->keys = (unsigned long long*)take(cap_t * 8);
+  S->keys_alt = (unsigned long long*)take(cap_t * 8);
+  S->dirA = (unsigned long long*)take(2 * cap_i * 8);
+  S->dirA_alt = (unsigned long long*)take(2 * cap_i * 8);
+  S->dirD = (unsigned long long*)take(2 * cap_d * 8);
+  S->dirD_alt = (unsigned long long*)take(2 * cap_d * 8);
+  S->dirR = (unsigned long long*)take(2 * cap_d * 8);
+  S->dirR_alt = (unsigned long long*)take(2 * cap_d * 8);
+  S->touched = (int32_t*)take(mt * 4);
+  S->dest = (int64_t*)take(mt * 8);
+  S->newcap = (int32_t*)take(mt * 4);
+  S->tlen = (int32_t*)take(mt * 4);
+  S->tpre = (int64_t*)take((mt + 1) * 8);
+  return off;
+}
+
+struct Table6 {
+  int64_t v[6];
+};
+__global__ void k_put_table(int64_t* dst, Table6 t) {
+  if (threadIdx.x < 6) dst[threadIdx.x] = t.v[threadIdx.x];
+}
+
+// One batch given as device arrays, applied with no allocation: the batch
+// staging comes from the static array, every other buffer is the handle's
+// and must already be large enough (checked before anything is enqueued).
+// A pass whose counting asks for more scratch is undone (the purge removes
+// the new entries and clears the flags) and the call fails with the graph
+// unchanged.  Host side: no heap allocation either (fixed-size arrays only).
+void apply_noalloc(gc_graph* G, const int32_t* iu, const int32_t* iv, int64_t n_ins, const int32_t* du,
+                   const int32_t* dv, int64_t n_del, int64_t counts[11], gc_batch_stats* stats) {
+  using clk = std::chrono::steady_clock;
+  const auto t0 = clk::now();
+  if (G->broken) raise(GC_ESTATE, "handle unusable after an earlier device failure");
+  if (G->k != 1) raise(GC_EINVAL, "handle holds %d graphs", G->k);
+  if (n_ins < 0 || n_del < 0) raise(GC_EINVAL, "negative batch size");
+  if ((n_ins && (!iu || !iv)) || (n_del && (!du || !dv))) raise(GC_EINVAL, "null batch array");
+  HIPCHK(hipSetDevice(G->device));
+  char* base = (char*)noalloc_scratch_ptr(G->device);
+  if (!base) raise(GC_EDEVICE, "static staging of device %d not set up", G->device);
+  hipStream_t s = G->stream;
+  PassPlan L;
+  L.dev = true;
+  L.ni = n_ins;
+  L.ndl = n_del;
+  L.total = n_ins + n_del;
+  L.cap_i = pow2_at_least(std::max<int64_t>(L.ni, 64));
+  L.cap_d = pow2_at_least(std::max<int64_t>(L.ndl, 64));
+  L.cap_t = L.cap_i + L.cap_d;
+  L.max_touched = 2 * L.cap_t;
+  L.union_bound = G->entries + 2 * L.ni;
+  L.tab_words = 6;
+  L.in_bytes = L.tab_words * 8;
+  Staging S;
+  const size_t need_bytes = carve_staging(nullptr, L.cap_i, L.cap_d, L.in_bytes, &S);
+  if (need_bytes > kNoAllocBytes)
+    raise(GC_EINVAL,
+          "batch of %lld insertions and %lld deletions needs %zu bytes of staging; the allocation-free entry point "
+          "has %zu (every batch of at most 262144 insertions and 262144 deletions fits)",
+          (long long)n_ins, (long long)n_del, need_bytes, kNoAllocBytes);
+  // speed knobs as apply() chooses them, without autotuning trials
+  L.radius = G->opt.radius == 0 ? -1 : G->opt.radius;
+  const int decade = (int)std::min<double>(7.0, std::floor(std::log10((double)L.total + 1.0)));
+  L.dense_min = G->dense_min_best;
+  if (G->opt.autotune) {
+    bool wide = false;
+    for (int d = 0; d <= decade; ++d) wide = wide || G->region_frac[d] >= 0.9;
+    if (L.radius >= 2 && wide) L.radius = -1;
+  }
+  // every buffer the pass uses besides the staging must already fit
+  const size_t sort_need = radix_sort_tmp_bytes(std::max<int64_t>(std::max(L.cap_t, 2 * std::max(L.cap_i, L.cap_d)), G->N)) + 64;
+  const size_t scan_need = scan_tmp_bytes(std::max<int64_t>(L.max_touched, G->N) + 1) + 64;
+  const int64_t arena_need = (int64_t)((1.0 + G->opt.slack) * (double)L.union_bound) + 8 * L.max_touched + 1024;
+  if (G->sort_tmp.cap < sort_need || G->scan_tmp.cap < scan_need ||
+      G->scratch.cap < (size_t)std::max<int64_t>(L.union_bound, 4) * 4 || !count_scratch_fits(G, 2, L.union_bound) ||
+      G->arena_cap - G->arena_top < arena_need)
+    raise(GC_ENOMEM,
+          "the handle's buffers are not sized for this batch (graph of %lld entries plus %lld insertions); "
+          "one gc_apply_batch_dev call of this size grows them",
+          (long long)G->entries, (long long)n_ins);
+
+  // the input table (segment bounds, graph base and size) by a kernel: no host staging
+  carve_staging(base, L.cap_i, L.cap_d, L.in_bytes, &S);
+  Table6 tb = {{0, n_ins, 0, n_del, G->gbase[0], G->gn[0]}};
+  hipLaunchKernelGGL(k_put_table, dim3(1), dim3(64), 0, s, (int64_t*)S.bin, tb);
+  BatchIn B;
+  B.n_ins = n_ins;
+  B.n_del = n_del;
+  B.k = 1;
+  B.seq = 0;
+  B.ins_seg = (const int64_t*)S.bin;
+  B.del_seg = B.ins_seg + 2;
+  B.gbase = B.ins_seg + 4;
+  B.gn = B.ins_seg + 5;
+  B.iu = iu; B.iv = iv; B.du = du; B.dv = dv;
+  BatchWork W = make_work(G, S);
+  W.dirA = radix_sort_result(S.dirA, S.dirA_alt, 2 * L.cap_i, 2 * G->bits);
+  W.dirD = radix_sort_result(S.dirD, S.dirD_alt, 2 * L.cap_d, 2 * G->bits);
+  W.dirR = radix_sort_result(S.dirR, S.dirR_alt, 2 * L.cap_d, 2 * G->bits);
+  const bool timed = stats != nullptr;
+  try {
+    enqueue_pass(G, L, B, W, S, timed, false);
+    G->sync();
+    if (G->out_bst()[BS_RETRY]) {
+      // counting needs more scratch: undo the merge, keep the graph as it was
+      unsigned long long* bst = G->bstats.as<unsigned long long>();
+      fill_u64(bst + BS_RETRY, 0ull, 1, s);
+      launch_purge(G->pd(), W, L.max_touched, G->bits, 0u, bst + BS_RETRY, G->scan_tmp.p, s, true);
+      G->sync();
+      G->arena_top = (int64_t)*G->out_top();
+      G->in_pass = false;
+      note_maxima(G);
+      raise(GC_ENOMEM,
+            "a vertex outgrew the counting scratch; the batch was undone and the graph is unchanged "
+            "(one gc_apply_batch_dev call grows the scratch)");
+    }
+  } catch (...) {
+    if (G->in_pass) G->broken = true;
+    G->in_pass = false;
+    throw;
+  }
+  G->in_pass = false;
+  note_maxima(G);
+  const unsigned long long* hb = G->out_bst();
+  const unsigned long long* hc = G->out_ctr();
+  G->arena_top = (int64_t)*G->out_top();
+  const long long* st = G->out_state();
+  if (hb[BS_ARENA_OVF] || hb[BS_ERR] || st[ST_ERR]) {
+    G->broken = true;
+    raise(GC_EDEVICE, "device-side inconsistency (arena overflow %llu, errors %llu, inexact totals %lld)",
+          hb[BS_ARENA_OVF], hb[BS_ERR], st[ST_ERR]);
+  }
+  std::memcpy(G->hstate.data(), st, ST_STRIDE * sizeof(long long));
+  G->hstate[ST_N] = G->gn[0];
+  G->entries += 2 * ((int64_t)hb[PB_IDX(0, PB_EFF_INS)] - (int64_t)hb[PB_IDX(0, PB_EFF_DEL)]);
+  i128 I[11];
+  finalize(G->hstate.data(), G->gn[0], I);
+  int64_t tmp[11];
+  uint32_t ovf = 0;
+  to_int64(I, counts ? counts : tmp, &ovf);
+  if (G->opt.autotune && L.radius > 0 && L.union_bound > 0)
+    G->region_frac[decade] = (double)hc[C_ER] / (double)std::max<int64_t>(1, G->entries);
+  if (stats) {
+    const double ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    fill_stats(G, stats, hb, hc, 0, 1, n_ins, n_del, true, ms, ovf);
+    stats->c4_dense_min = L.dense_min;
+    stats->whole_graph = L.radius < 0;
+    stats->retries = 0;
   }
 }
 
@@ -1128,6 +1389,15 @@ int gc_apply_batch_dev(gc_graph* g, const int32_t* ins_src, const int32_t* ins_d
     if (g->k != 1) raise(GC_EINVAL, "handle holds %d graphs: use gc_apply_batches", g->k);
     gc_batch_desc b{ins_src, ins_dst, n_ins, del_src, del_dst, n_del};
     apply(g, &b, 1, true, false, counts ? (int64_t(*)[11])counts : nullptr, stats);
+  });
+}
+
+int gc_apply_batch_dev_noalloc(gc_graph* g, const int32_t* ins_src, const int32_t* ins_dst, int64_t n_ins,
+                               const int32_t* del_src, const int32_t* del_dst, int64_t n_del, int64_t counts[11],
+                               gc_batch_stats* stats) {
+  return guard([&] {
+    if (!g) raise(GC_EINVAL, "graph is NULL");
+    apply_noalloc(g, ins_src, ins_dst, n_ins, del_src, del_dst, n_del, counts, stats);
   });
 }
 

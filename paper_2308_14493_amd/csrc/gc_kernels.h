@@ -85,9 +85,11 @@ void launch_merge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int
 void launch_flag_rows(const PoolDev& P, const BatchWork& W, int64_t max_dirD, int bits, unsigned long long* bstats,
                       hipStream_t s);
 // removes the entries carrying `fin` (absent from the last version), clears
-// all flags; does nothing while *skip != 0
+// all flags; does nothing while *skip != 0.  undo: removes the entries new
+// in the pass instead (GC_F_NEW, listed in W.dirA), which restores the graph
+// as it was before a one-batch pass whose counting did not complete
 void launch_purge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int bits, uint32_t fin,
-                  const unsigned long long* skip, void* scan_tmp, hipStream_t s);
+                  const unsigned long long* skip, void* scan_tmp, hipStream_t s, bool undo = false);
 void launch_region(const PoolDev& P, const BatchWork& W, int radius, int32_t* level, int32_t* rlist, int32_t* rlen,
                    hipStream_t s);
 void launch_region_fill(const PoolDev& P, const RegionDev& R, const BatchWork& W, int radius, const int32_t* level,

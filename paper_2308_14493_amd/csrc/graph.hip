@@ -312,15 +312,16 @@ __global__ void k_purge_rows(PoolDev P, const int32_t* __restrict__ touched, con
   }
 }
 
+// nrem: the per-row counts of the removal list k_purge_rows used (nr, or na
+// when the pass is undone)
 __global__ void k_purge_commit(PoolDev P, const int32_t* __restrict__ touched, const unsigned long long* c,
-                               int32_t* __restrict__ a_beg, int32_t* __restrict__ na, int32_t* __restrict__ r_beg,
-                               int32_t* __restrict__ nr, int32_t* __restrict__ mark, int32_t* __restrict__ tix,
-                               const unsigned long long* skip) {
+                               int32_t* a_beg, int32_t* na, int32_t* r_beg, int32_t* nr, int32_t* __restrict__ mark,
+                               int32_t* __restrict__ tix, const int32_t* nrem, const unsigned long long* skip) {
   if (*skip) return;
   const int64_t nt = ctr(c, C_TOUCH);
   for (int64_t i = gtid(); i < nt; i += gstride()) {
     const int32_t r = touched[i];
-    P.len[r] -= nr[r];
+    P.len[r] -= nrem[r];
     a_beg[r] = 0; na[r] = 0; r_beg[r] = 0; nr[r] = 0; mark[r] = 0; tix[r] = 0;
   }
 }
@@ -937,18 +938,24 @@ void launch_flag_rows(const PoolDev& P, const BatchWork& W, int64_t max_dirD, in
 }
 
 void launch_purge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int bits, uint32_t fin,
-                  const unsigned long long* skip, void* scan_tmp, hipStream_t s) {
+                  const unsigned long long* skip, void* scan_tmp, hipStream_t s, bool undo) {
   if (max_touched == 0) return;
+  // undo: keep version 0 instead of the last version (remove the new
+  // entries, listed in dirA, and clear the flags of the others)
+  const unsigned long long* rm = undo ? W.dirA : W.dirR;
+  const int32_t* rm_beg = undo ? W.a_beg : W.r_beg;
+  const int32_t* rm_n = undo ? W.na : W.nr;
+  if (undo) fin = GC_F_NEW;
   // lengths of the union rows, then a copy, then the compaction (the scan of
   // stale lengths under skip is harmless: nothing reads it)
   hipLaunchKernelGGL(k_touched_len, dim3(grid_for(max_touched)), dim3(TPB), 0, s, P, W.touched, W.c, max_touched,
                      W.tlen, skip);
   exclusive_scan_i32_to_i64(W.tlen, W.tpre, max_touched, scan_tmp, s);
   hipLaunchKernelGGL(k_copy_rows, dim3(4096), dim3(TPB), 0, s, P, W.touched, W.c, W.tpre, W.scratch, skip);
-  hipLaunchKernelGGL(k_purge_rows, dim3(4096), dim3(TPB), 0, s, P, W.touched, W.c, W.tpre, W.scratch, W.dirR, bits,
-                     fin, W.r_beg, W.nr, skip);
+  hipLaunchKernelGGL(k_purge_rows, dim3(4096), dim3(TPB), 0, s, P, W.touched, W.c, W.tpre, W.scratch, rm, bits,
+                     fin, rm_beg, rm_n, skip);
   hipLaunchKernelGGL(k_purge_commit, dim3(grid_for(max_touched)), dim3(TPB), 0, s, P, W.touched, W.c, W.a_beg, W.na,
-                     W.r_beg, W.nr, W.mark, W.tix, skip);
+                     W.r_beg, W.nr, W.mark, W.tix, rm_n, skip);
 }
 
 void launch_region(const PoolDev& P, const BatchWork& W, int radius, int32_t* level, int32_t* rlist, int32_t* rlen,

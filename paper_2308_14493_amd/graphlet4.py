@@ -59,6 +59,7 @@ class GraphletError(RuntimeError):
 _lib = None
 
 EXPORTS = ["gc_options_default", "gc_graph_init", "gc_pool_init", "gc_apply_batch", "gc_apply_batch_dev",
+           "gc_apply_batch_dev_noalloc",
            "gc_apply_batches", "gc_apply_batch_seq", "gc_get_counts", "gc_get_counts_exact", "gc_recount_exact", "gc_graph_info",
            "gc_export_edges", "gc_graph_footprint", "gc_graph_replays", "gc_graph_free", "gc_strerror", "gc_last_error",
            "gc_server_opts_default", "gc_server_create", "gc_server_add_graph", "gc_server_submit",
@@ -90,6 +91,7 @@ def load(path: str = LIB_PATH):
     lib.gc_pool_init.argtypes = [_I32, _P, _P, _P, _P, ctypes.POINTER(Options), ctypes.POINTER(_P), _P]
     lib.gc_apply_batch.argtypes = [_P, _P, _P, _I64, _P, _P, _I64, _P, ctypes.POINTER(BatchStats)]
     lib.gc_apply_batch_dev.argtypes = [_P, _P, _P, _I64, _P, _P, _I64, _P, ctypes.POINTER(BatchStats)]
+    lib.gc_apply_batch_dev_noalloc.argtypes = [_P, _P, _P, _I64, _P, _P, _I64, _P, ctypes.POINTER(BatchStats)]
     lib.gc_apply_batches.argtypes = [_P, _P, _P, ctypes.POINTER(BatchStats)]
     lib.gc_apply_batch_seq.argtypes = [_P, _P, _I32, _P, _P]
     lib.gc_get_counts.argtypes = [_P, _I32, _P, ctypes.POINTER(ctypes.c_uint32)]
@@ -234,6 +236,23 @@ class Graph:
         _check(lib.gc_apply_batch_dev(self._h, ins_src.data_ptr(), ins_dst.data_ptr(), ins_src.numel(),
                                       del_src.data_ptr(), del_dst.data_ptr(), del_src.numel(),
                                       out.ctypes.data, ctypes.byref(st) if stats else None))
+        self.last_int64 = [int(x) for x in out.view(np.uint64)]
+        c = self.counts()
+        return (c, st.as_dict()) if stats else c
+
+    def apply_batch_dev_noalloc(self, ins_src, ins_dst, del_src, del_dst, stats=False):
+        """gc_apply_batch_dev_noalloc: device arrays, no allocation in the
+        library call (staging in a static device array)."""
+        lib = load()
+        st = BatchStats()
+        out = np.zeros(11, np.int64)
+        import torch
+        for t in (ins_src, ins_dst, del_src, del_dst):
+            assert t.dtype == torch.int32 and t.is_cuda and t.is_contiguous()
+        torch.cuda.current_stream().synchronize()
+        _check(lib.gc_apply_batch_dev_noalloc(self._h, ins_src.data_ptr(), ins_dst.data_ptr(), ins_src.numel(),
+                                              del_src.data_ptr(), del_dst.data_ptr(), del_src.numel(),
+                                              out.ctypes.data, ctypes.byref(st) if stats else None))
         self.last_int64 = [int(x) for x in out.view(np.uint64)]
         c = self.counts()
         return (c, st.as_dict()) if stats else c

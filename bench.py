@@ -8,13 +8,25 @@ same R-MAT generator.  One step = one batch through the whole path (ingest,
 merge, region of change, fused two-version count, combine, purge), timed from
 the host call to the counts on the host (result download included).  The
 timed batches are resident in HBM before the timed region and go through the
-device-array entry point; a few more batches through the host-array entry
-point give the PCIe-inclusive rate as a separate field.
+device-array entry point.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--scale 22] [--ef 16]
+Checks: the counts of the initial graph and after the last batch are compared
+with the oracle's static recount stored in tests/golden (written by
+tests/golden/make_scale.py from the oracle alone), and with a static recount
+on the GPU.  The graph is then taken back to its state before the timed
+batches (one net batch) and the same timed batches run again through the
+host-array entry point: the PCIe-inclusive rate, never ``value``, and the
+counts must come out the same.
 
-Prints one JSON line (rank 0).  The oracle (test infrastructure) is only
-used for the cpu_baseline leg.
+Also in the same line (skipped with --no-served / --no-batched): the served
+form (continuous batching into multi-version passes, Poisson arrivals at
+0.5x, 0.9x and 1.5x the plain path's saturation rate) and the batched form
+(256 graphs in one pooled pass against one call per graph).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form plain|batched|served]
+
+Prints one JSON line.  The oracle (test infrastructure) is used only by the
+cpu_baseline leg.
 """
 from __future__ import annotations
 
@@ -45,18 +57,21 @@ def percentile(xs, q):
     return xs[k]
 
 
+def read_kv(path):
+    kv = {}
+    if os.path.exists(path):
+        for line in open(path):
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    return kv
+
+
 def measured_traffic(kernel_file, summary):
     """HBM bytes per launch from a committed rocprofv3 counter summary, or
     None once the kernel source differs from the one the counters saw."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", summary)
-    if not os.path.exists(path):
-        return None
-    kv = {}
-    for line in open(path):
-        if ":" in line:
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
+    kv = read_kv(os.path.join(ROOT, "profiles", summary))
     src = os.path.join(ROOT, "paper_2308_14493_amd", "csrc", kernel_file)
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     if kv.get("source_sha256_prefix") != sha or "traffic_bytes_per_launch" not in kv:
@@ -64,23 +79,69 @@ def measured_traffic(kernel_file, summary):
     return float(kv["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(scale, ef, mean_batch, seed=5):
-    """Oracle static recount (the per-batch work of the recount-from-scratch
-    baseline) on a bounded sample: a full recount of a smaller R-MAT graph
-    from the same generator; extrapolated to the benchmark graph by the edge
-    ratio, which can only overstate the CPU rate (recount work grows faster
-    than the edge count on these graphs)."""
-    from graphgen import rmat_graph
+def host_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": usable, "logical_cpus": os.cpu_count(), "cpu_model": model}
+
+
+def golden_counts(w, steps):
+    """Oracle counts stored for this stream (step j = after j batches), keyed
+    by the digest of the graph and its first j batches; {} if none match."""
+    from graphgen import workloads as wl
+    path = os.path.join(ROOT, "tests", "golden", "scale_rmat_s22_bench.json")
+    if not os.path.exists(path):
+        return {}
+    g = json.load(open(path))
+    have = dict(zip(g.get("prefix_sha256", []), g["counts"]))
+    out = {}
+    for j in steps:
+        c = have.get(wl.prefix_digest(w, j))
+        if c is not None:
+            out[j] = c
+    return out
+
+
+def cpu_baseline(n, s, d, mean_batch, stride, scale, ef):
+    """The oracle's static recount (the per-batch work of the
+    recount-from-scratch baseline) of the benchmark graph, timed on a
+    bounded sample: the adjacency build in full, the per-vertex loops over
+    every stride-th vertex (ids are randomly permuted, so a uniform sample),
+    scaled by the stride.  Also reports the full recount of the same graph
+    measured on this kind of host, when a profile of it is committed."""
     from oracle import native
-    n, s, d, _ = rmat_graph(scale, ef, seed)
     native.build()
-    t0 = time.perf_counter()
-    native.static_counts(n, s, d)
-    secs = time.perf_counter() - t0
-    return secs, s.size, native.threads()
+    t_build, t_loops = native.sample_seconds(n, s, d, stride, 0)
+    est = t_build + stride * t_loops
+    hi = host_info()
+    out = {"value": mean_batch / est, "unit": "updates/s", "cores": native.threads(), "kind": "oracle",
+           "sample": "oracle static recount of the benchmark graph, R-MAT scale %d ef %d (m=%d): adjacency build "
+                     "%.1fs in full, per-vertex loops over 1 vertex in %d %.1fs, scaled: %.0fs per recount on %d "
+                     "threads (%s); updates/s = mean batch size %.0f / recount time" % (
+                         scale, ef, s.size, t_build, stride, t_loops, est, native.threads(), hi["cpu_model"],
+                         mean_batch),
+           "recount_s_estimated": est, "host": hi}
+    kv = read_kv(os.path.join(ROOT, "profiles", "cpu_oracle_rmat_s22.md"))
+    if "full_recount_s" in kv and scale == 22 and ef == 16:
+        out["full_recount_s_measured"] = float(kv["full_recount_s"])
+        out["full_recount_threads"] = int(kv.get("threads", "0"))
+        out["full_recount_cpu_model"] = kv.get("cpu_model", "")
+        out["single_thread_recount_s_rmat_s18_ef8"] = float(kv.get("single_thread_s18_ef8_s", "nan"))
+    return out
 
 
-def bench_batched(args):
+# ------------------------------------------------------------------ forms
+def run_batched(args):
     """Many independent R-MAT graphs (n log-uniform in [1e3, 2e5], edge factor
     in {4, 8, 16}), one update batch per graph per round (log-uniform in
     [100, 1e4], 50/50, the same size every round): one pooled pass per round
@@ -88,7 +149,6 @@ def bench_batched(args):
     launching kernel by kernel and against one call per graph.  Every form
     first applies the same warm-up rounds (the autotuner's trial passes, then
     the capture); the timed rounds follow."""
-    import math as _m
     from graphgen import rmat_graph, rmat_batches
     import paper_2308_14493_amd as pkg
     import torch
@@ -97,15 +157,15 @@ def bench_batched(args):
     warm, rounds = 6, args.rounds
     work = []
     for i in range(args.graphs):
-        n = int(round(10 ** rng.uniform(3, _m.log10(2e5))))
+        n = int(round(10 ** rng.uniform(3, math.log10(2e5))))
         ef = int(rng.choice([4, 8, 16]))
         size = int(round(10 ** rng.uniform(2, 4)))
-        scale = max(1, _m.ceil(_m.log2(n)))
+        scale = max(1, math.ceil(math.log2(n)))
         gs = int(rng.integers(0, 2**31 - 1))
         n, s, d, samp = rmat_graph(scale, ef, gs, n=n)
         work.append((n, s, d, rmat_batches(n, s, d, samp, [size] * (warm + rounds), gs + 1)))
     m_tot = sum(w[1].size for w in work)
-    log("generated %d graphs (sum m = %d) in %.1fs" % (len(work), m_tot, time.time() - t0))
+    log("batched: generated %d graphs (sum m = %d) in %.1fs" % (len(work), m_tot, time.time() - t0))
     pkg.load()
     torch.cuda.init()
     offered = [sum(w[3][warm + r][0].size + w[3][warm + r][2].size for w in work) for r in range(rounds)]
@@ -126,58 +186,56 @@ def bench_batched(args):
         return times, res, rep
 
     t_graph, r_graph, rep = pooled(1)
-    log("pooled pass, replayed graph: %s ms (captures %d, graph launches %d)" %
+    log("batched: pooled pass, replayed graph: %s ms (captures %d, graph launches %d)" %
         (["%.2f" % (t * 1e3) for t in t_graph], rep[0], rep[1]))
     t_direct, r_direct, _ = pooled(0)
-    log("pooled pass, kernel by kernel: %s ms" % ["%.2f" % (t * 1e3) for t in t_direct])
-    # graph by graph, kernel by kernel (first timed round)
-    seq, t_seq = [], 0.0
+    log("batched: pooled pass, kernel by kernel: %s ms" % ["%.2f" % (t * 1e3) for t in t_direct])
+    # graph by graph, kernel by kernel, every timed round
+    seq, t_seq = [[] for _ in range(rounds)], [0.0] * rounds
     for n, s, d, bs in work:
         g = pkg.Graph(n, s, d, radius=args.radius, graphs=0)
         for r in range(warm):
             g.apply_batch(*bs[r])
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        seq.append(g.apply_batch(*bs[warm]))
-        t_seq += time.perf_counter() - t1
+        for r in range(rounds):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            seq[r].append(g.apply_batch(*bs[warm + r]))
+            t_seq[r] += time.perf_counter() - t1
         g.close()
-    log("graph by graph: %.2f ms" % (t_seq * 1e3))
-    same = seq == r_graph[0] and r_graph == r_direct
+    log("batched: graph by graph: %s ms" % ["%.2f" % (t * 1e3) for t in t_seq])
+    same = seq == r_graph and r_graph == r_direct
     tg = float(np.mean(t_graph))
-    out = {"metric": "updates/sec, %d-graph pool, one batch per graph" % len(work),
-           "value": float(np.mean(offered)) / tg, "unit": "updates/s", "n_gpus": 1, "steps": rounds,
-           "warmup": warm, "ms_per_step": tg * 1e3, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-           "config": {"workload": "%d R-MAT graphs, n log-uniform [1e3, 2e5], ef {4,8,16}, sum m = %d, one batch "
-                                  "per graph per round log-uniform [100, 1e4], 50/50" % (len(work), m_tot),
-                      "form": "batched"},
-           "graph_captures": rep[0], "graph_launches": rep[1],
-           "direct_pool_ms": float(np.mean(t_direct)) * 1e3,
-           "sequential_updates_per_s": offered[0] / t_seq, "sequential_ms": t_seq * 1e3,
-           "speedup_vs_sequential": t_seq / t_graph[0], "results_equal": same}
-    print(json.dumps(out), flush=True)
+    return {"graphs": len(work), "sum_m": m_tot, "rounds": rounds, "warmup_rounds": warm,
+            "updates_per_s": float(np.mean(offered)) / tg, "ms_per_round": tg * 1e3,
+            "direct_pool_ms": float(np.mean(t_direct)) * 1e3,
+            "sequential_updates_per_s": float(np.sum(offered)) / float(np.sum(t_seq)),
+            "sequential_ms_per_round": float(np.mean(t_seq)) * 1e3,
+            "speedup_vs_sequential": float(np.mean(t_seq)) / tg,
+            "graph_captures": rep[0], "graph_launches": rep[1], "results_equal": bool(same)}
 
 
-def bench_served(args):
-    """Serving: the R-MAT graph resident in a server; one fixed sequence of
-    batches (sizes log-uniform in [min, max], 50/50) is offered as a Poisson
-    stream at 0.5x, 0.9x and 1.5x the saturation rate of the plain path
-    (1 / mean service time, measured on the same sequence through the server
-    one request at a time).  Between rates the inverse batches, applied in
-    reverse order, restore the graph so that every rate sees the same
-    sequence on the same graph.  Latency = submit -> counts on the host."""
+def run_served(args, n, s, d, sampler):
+    """Serving: the graph resident in a server; one fixed sequence of batches
+    (sizes log-uniform in [min, max], 50/50) is offered as a Poisson stream
+    at 0.5x, 0.9x and 1.5x the saturation rate of the plain path (1 / mean
+    service time, measured on the same sequence through the server one
+    request at a time).  Between rates one net batch takes the graph back to
+    where the sequence started, so every rate sees the same sequence on the
+    same graph and every result must equal the one-at-a-time result.
+    Latency = submit -> counts on the host."""
     import threading
-    from graphgen import rmat_graph, BatchStream, log_uniform_sizes, poisson_arrivals
+    from graphgen import BatchStream, log_uniform_sizes, poisson_arrivals
+    from graphgen.workloads import net_batch
     import paper_2308_14493_amd as pkg
     import torch
     t0 = time.time()
-    n, s, d, sampler = rmat_graph(args.scale, args.ef, args.seed)
     sizes = log_uniform_sizes(args.requests, args.min_batch, args.max_batch, args.seed + 5)
     stream = BatchStream.from_edges(n, s, d, args.seed + 6, ins_sampler=sampler)
+    keys0 = stream.keys.copy()
     batches = [stream.next_batch(sz // 2, sz - sz // 2) for sz in sizes]
-    inverse = [(b[2], b[3], b[0], b[1]) for b in reversed(batches)]
+    restore = net_batch(stream.keys, keys0)
     offered = sum(b[0].size + b[2].size for b in batches)
-    log("generated graph and %d batches in %.1fs (sizes %s)" % (len(batches), time.time() - t0, sizes))
+    log("served: generated %d batches in %.1fs" % (len(batches), time.time() - t0))
     pkg.load()
     torch.cuda.init()
     srv = pkg.Server()
@@ -185,23 +243,20 @@ def bench_served(args):
     base = srv.counts(gid)
 
     def closed_loop(seq):
-        out = []
-        for b in seq:
-            out.append(srv.wait(srv.submit(gid, *b)))
-        return out
+        return [srv.wait(srv.submit(gid, *b)) for b in seq]
 
     closed_loop(batches[:1] + [(batches[0][2], batches[0][3], batches[0][0], batches[0][1])])  # warm-up
     t1 = time.perf_counter()
     plain = closed_loop(batches)
     t_plain = time.perf_counter() - t1
     final = srv.counts(gid)
-    closed_loop(inverse)
+    closed_loop([restore])
     assert srv.counts(gid) == base
     service = t_plain / len(batches)
     runs = {}
     for f in (0.5, 0.9, 1.5):
         arr = poisson_arrivals(f / service, len(batches), args.seed + int(f * 10))
-        tickets, subs = [None] * len(batches), [0.0] * len(batches)
+        tickets = [None] * len(batches)
         start = time.perf_counter()
 
         def feeder():
@@ -209,7 +264,6 @@ def bench_served(args):
                 dt = start + arr[i] - time.perf_counter()
                 if dt > 0:
                     time.sleep(dt)
-                subs[i] = time.perf_counter()
                 tickets[i] = srv.submit(gid, *b)
 
         th = threading.Thread(target=feeder)
@@ -229,43 +283,50 @@ def bench_served(args):
                              "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
                              "mean_batches_per_pass": float(np.mean(passes)),
                              "results_equal_to_plain": bool(same)}
-        log("rate %.1fx: %s" % (f, runs["%.1fx" % f]))
-        closed_loop(inverse)
+        log("served: rate %.1fx: %s" % (f, runs["%.1fx" % f]))
+        closed_loop([restore])
         assert srv.counts(gid) == base
     srv.close()
-    out = {"metric": "updates/sec + p50/p99 batch latency, served, exact 4-graphlet counts, R-MAT s%d" % args.scale,
-           "value": max(r["updates_per_s"] for r in runs.values()), "unit": "updates/s", "n_gpus": 1,
-           "steps": len(batches), "warmup": 1, "ms_per_step": service * 1e3, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-           "config": {"workload": "R-MAT scale %d ef %d, %d batches log-uniform [%g, %g], Poisson arrivals at "
-                                  "0.5/0.9/1.5x plain saturation" % (args.scale, args.ef, len(batches),
-                                                                     args.min_batch, args.max_batch),
-                      "form": "served"},
-           "plain_closed_loop_updates_per_s": offered / t_plain, "plain_p50_ms": percentile([p[2] for p in plain], 50),
-           "rates": runs}
+    lat_plain = [p[2] for p in plain]
+    best = max(r["updates_per_s"] for r in runs.values())
+    return {"requests": len(batches), "plain_closed_loop_updates_per_s": offered / t_plain,
+            "plain_service_ms": service * 1e3,
+            "plain_p50_ms": percentile(lat_plain, 50), "plain_p99_ms": percentile(lat_plain, 99),
+            "best_served_updates_per_s": best, "served_vs_plain": best / (offered / t_plain),
+            "results_equal_to_plain": all(r["results_equal_to_plain"] for r in runs.values()), "rates": runs}
+
+
+def form_line(args, metric, value, ms, extra):
+    out = {"metric": metric, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int64", "data": "synthetic"}
+    out.update(extra)
     print(json.dumps(out), flush=True)
 
 
+# ------------------------------------------------------------------ plain
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--ef", type=int, default=16)
     ap.add_argument("--seed", type=int, default=22)
     ap.add_argument("--min-batch", type=float, default=10)
     ap.add_argument("--max-batch", type=float, default=1e5)
     ap.add_argument("--radius", type=int, default=2)
-    ap.add_argument("--cpu-scale", type=int, default=17)
+    ap.add_argument("--cpu-stride", type=int, default=16, help="cpu_baseline: every stride-th vertex is timed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recount-check", action="store_true")
-    ap.add_argument("--host-steps", type=int, default=3, help="extra batches through the host-array entry point")
+    ap.add_argument("--no-host-rerun", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--form", choices=["plain", "batched", "served"], default="plain",
-                    help="plain: one graph, one batch per call; batched: a pool of many graphs, one batch per "
-                         "graph per call, against the same batches applied graph by graph")
+                    help="plain (default; the served and batched forms ride along as extra keys), or one of the "
+                         "other forms alone")
     ap.add_argument("--graphs", type=int, default=256)
-    ap.add_argument("--requests", type=int, default=8, help="served form: batches per offered rate")
+    ap.add_argument("--requests", type=int, default=64, help="served form: batches per offered rate")
     ap.add_argument("--rounds", type=int, default=3, help="batched form: timed rounds")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB copied device-to-device once before the batches (a plain copy kernel of known size, "
@@ -278,22 +339,33 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    from graphgen import rmat_graph, BatchStream, log_uniform_sizes
+    from graphgen import workloads as wl
     import paper_2308_14493_amd as pkg
+
     if args.form == "batched":
-        return bench_batched(args)
-    if args.form == "served":
-        return bench_served(args)
+        b = run_batched(args)
+        return form_line(args, "updates/sec, %d-graph pool, one batch per graph" % b["graphs"], b["updates_per_s"],
+                         b["ms_per_round"], {"config": {"workload": "%d R-MAT graphs, n log-uniform [1e3, 2e5], ef "
+                                                        "{4,8,16}, one batch per graph per round log-uniform "
+                                                        "[100, 1e4], 50/50" % b["graphs"], "form": "batched"},
+                                             "batched": b})
 
     t0 = time.time()
-    n, s, d, sampler = rmat_graph(args.scale, args.ef, args.seed)
-    log("generated R-MAT scale %d ef %d: n=%d m=%d in %.1fs" % (args.scale, args.ef, n, s.size, time.time() - t0))
     total = args.warmup + args.steps
-    sizes = log_uniform_sizes(total, args.min_batch, args.max_batch, args.seed + 1)
-    stream = BatchStream.from_edges(n, s, d, args.seed + 2, ins_sampler=sampler)
-    t0 = time.time()
-    batches = [stream.next_batch(sz // 2, sz - sz // 2) for sz in sizes]
-    log("generated %d batches in %.1fs (sizes %s)" % (total, time.time() - t0, sizes))
+    w, sizes, stream = wl.rmat_s22_bench_stream(total, 0, args.min_batch, args.max_batch, args.scale, args.ef,
+                                                args.seed, snapshot_at=args.warmup)
+    n, s, d = w.n, w.src, w.dst
+    log("generated R-MAT scale %d ef %d: n=%d m=%d and %d batches in %.1fs (sizes %s)" % (
+        args.scale, args.ef, n, s.size, total, time.time() - t0, sizes))
+    if args.form == "served":
+        sv = run_served(args, n, s, d, stream.ins_sampler)
+        return form_line(args, "updates/sec + p50/p99 batch latency, served, exact 4-graphlet counts, R-MAT s%d"
+                         % args.scale, sv["best_served_updates_per_s"], sv["plain_service_ms"],
+                         {"config": {"workload": "R-MAT scale %d ef %d, %d batches log-uniform [%g, %g], Poisson "
+                                                 "arrivals at 0.5/0.9/1.5x plain saturation" % (
+                                                     args.scale, args.ef, sv["requests"], args.min_batch,
+                                                     args.max_batch), "form": "served"}, "served": sv})
+    gold = golden_counts(w, [0, total])
 
     pkg.load()
     import torch  # device plumbing only
@@ -308,9 +380,14 @@ def main():
     t0 = time.time()
     g = pkg.Graph(n, s, d, radius=args.radius)
     torch.cuda.synchronize()
-    log("graph resident on the GPU in %.2fs; counts %s" % (time.time() - t0, g.counts()))
+    c0 = g.counts()
+    log("graph resident on the GPU in %.2fs; counts %s" % (time.time() - t0, c0))
+    checks = {}
+    if 0 in gold:
+        checks["initial"] = c0 == gold[0]
 
     # batches resident in HBM before the timed region (device-array entry point)
+    batches = w.batches
     dev_batches = [[torch.as_tensor(np.ascontiguousarray(x, dtype=np.int32)).cuda() for x in b] for b in batches]
     torch.cuda.synchronize()
     lat, offered, stats = [], 0, []
@@ -325,72 +402,88 @@ def main():
             lat.append((t2 - t1) * 1e3)
             offered += b[0].size + b[2].size
             stats.append(st)
-        log("step %d: batch %d updates, %.2f ms (tri %.2f edge %.2f c4 %.2f/%.2f/%.2f prep %.2f fin %.2f) dmin %d whole %d "
-            "region_e=%d c4_tail=%d/%d hubs=%d windows=%d searches=%d" % (
+        log("step %d: batch %d updates, %.2f ms (tri %.2f edge %.2f c4 %.2f/%.2f/%.2f prep %.2f fin %.2f) dmin %d "
+            "whole %d region_e=%d c4_tail=%d/%d hubs=%d windows=%d searches=%d tri_e=%d" % (
                 i, b[0].size + b[2].size, (t2 - t1) * 1e3, st["ms_tri"], st["ms_edge"], st["ms_c4_small"],
                 st["ms_c4_mid"], st["ms_c4_large"], st["ms_prepare"], st["ms_finish"], st["c4_dense_min"],
                 st["whole_graph"], st["region_entries"], st["c4_tail_wedges"], st["wedges"], st["tier_c4_large"],
-                st["c4_windows"], st["c4_searches"]))
+                st["c4_windows"], st["c4_searches"], st["tri_entries"]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - tstart
     value = offered / elapsed
-    # the same kind of batches handed over as host arrays (upload over PCIe included)
-    host_rate = None
-    if args.host_steps:
-        more = [stream.next_batch(sz // 2, sz - sz // 2) for sz in sizes[args.warmup:args.warmup + args.host_steps]]
-        t1 = time.perf_counter()
-        for b in more:
-            g.apply_batch(*b)
-        host_rate = sum(b[0].size + b[2].size for b in more) / (time.perf_counter() - t1)
-        log("host-array (PCIe-inclusive) rate: %.1f updates/s over %d batches" % (host_rate, len(more)))
+    c_end = g.counts()
+    if total in gold:
+        checks["after_last_batch"] = c_end == gold[total]
+    log("oracle check: %s" % checks)
     recount_ok = None
     if not args.no_recount_check:
-        recount_ok = g.recount() == g.counts()
+        recount_ok = g.recount() == c_end
         log("maintained counts == GPU static recount: %s" % recount_ok)
 
-    # roofline of the dominant kernel: the large 4-cycle tier (one launch per
-    # batch); algorithmic bytes = 4 B per adjacency entry it reads
+    # the same timed batches again as host arrays (upload over PCIe included),
+    # from the same graph: one net batch takes it back first
+    host_rate, host_same = None, None
+    if not args.no_host_rerun and args.steps > 0:
+        back = wl.net_batch(stream.keys, stream.snapshot)
+        g.apply_batch(*back)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for b in batches[args.warmup:]:
+            g.apply_batch(*b)
+        host_rate = offered / (time.perf_counter() - t1)
+        host_same = g.counts() == c_end
+        log("host-array (PCIe-inclusive) rate over the same %d batches: %.1f updates/s, counts equal: %s" %
+            (args.steps, host_rate, host_same))
+
+    # rooflines: the large 4-cycle tier (the dominant kernel, one launch per
+    # batch) and the triangle tiers; algorithmic bytes = 4 B per adjacency
+    # entry the method reads (counted by the kernels)
     phases = ["ms_tri", "ms_edge", "ms_c4_small", "ms_c4_mid", "ms_c4_large"]
     tot = {p: sum(st[p] for st in stats) for p in phases}
     dom = max(tot, key=tot.get)
-    c4l_bytes = sum(4.0 * st["c4_entries_large"] for st in stats)
-    c4l_ms = tot["ms_c4_large"]
-    achieved = c4l_bytes / (c4l_ms / 1e3) / 1e9 if c4l_ms > 0 else 0.0
-    traffic = measured_traffic("count.hip", "pmc_k_c4_large_rmat_s22.md") if args.scale == 22 and args.ef == 16 else None
-    roof = {"kernel": "k_c4_large", "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-            "bytes_per_launch": c4l_bytes / max(1, len(stats)),
-            "avg_launch_ms": c4l_ms / max(1, len(stats)), "dominant_phase": dom,
-            "phase_ms_avg": {p: round(tot[p] / max(1, len(stats)), 3) for p in phases}}
+    nst = max(1, len(stats))
+
+    def roof(kernel, bytes_, ms, traffic):
+        ach = bytes_ / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+        return {"kernel": kernel, "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": traffic, "bytes_per_launch": bytes_ / nst,
+                "avg_launch_ms": ms / nst}
+
+    s22 = args.scale == 22 and args.ef == 16
+    roof_c4 = roof("k_c4_large", sum(4.0 * st["c4_entries_large"] for st in stats), tot["ms_c4_large"],
+                   measured_traffic("count.hip", "pmc_k_c4_large_rmat_s22.md") if s22 else None)
+    roof_c4.update({"dominant_phase": dom, "phase_ms_avg": {p: round(tot[p] / nst, 3) for p in phases}})
+    roof_tri = roof("k_tri_small + k_tri_large tiers", sum(4.0 * st["tri_entries"] for st in stats), tot["ms_tri"],
+                    measured_traffic("count.hip", "pmc_tri_tiers_rmat_s22.md") if s22 else None)
+    g.close()
+    del dev_batches
 
     cpu = None
     if not args.no_cpu_baseline:
         mean_batch = float(np.mean([x[0].size + x[2].size for x in batches[args.warmup:]]))
-        secs, m_s, thr = cpu_baseline(args.cpu_scale, args.ef, mean_batch)
-        ratio = s.size / m_s
-        rate = mean_batch / (secs * ratio)
-        cpu = {"value": rate, "unit": "updates/s", "cores": thr, "kind": "oracle",
-               "sample": "one full static recount by the oracle (recount-from-scratch baseline) of R-MAT scale %d "
-                         "ef %d (m=%d) took %.2fs on %d threads; scaled to the benchmark graph by the edge ratio "
-                         "%.1f and divided into the mean batch size %.0f" % (args.cpu_scale, args.ef, m_s, secs, thr,
-                                                                             ratio, mean_batch)}
+        cpu = cpu_baseline(n, s, d, mean_batch, args.cpu_stride, args.scale, args.ef)
+        log("cpu baseline: %s" % cpu["sample"])
+    served = None if args.no_served else run_served(args, n, s, d, stream.ins_sampler)
+    batched = None if args.no_batched else run_batched(args)
 
     out = {
         "metric": "updates/sec + p50/p99 batch latency, exact 4-graphlet counts, R-MAT s22",
         "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": elapsed * 1e3 / max(1, args.steps), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": "R-MAT scale %d edge factor %d (n=%d, m=%d), batches log-uniform in [%g, %g], "
                                "50/50 insert/delete, plain per-batch path, radius %d"
                                % (args.scale, args.ef, n, s.size, args.min_batch, args.max_batch, args.radius),
                    "form": "plain"},
         "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
-        "host_array_updates_per_s": host_rate,
+        "oracle_check": {"golden": "tests/golden/scale_rmat_s22_bench.json", "after_batches": sorted(gold),
+                         "equal": checks, "all_equal": bool(checks) and all(checks.values())},
         "recount_check": recount_ok,
-        "roofline": roof,
+        "host_array_updates_per_s": host_rate, "host_array_counts_equal": host_same,
+        "roofline": roof_c4, "roofline_tri": roof_tri,
         "cpu_baseline": cpu,
+        "served": served, "batched": batched,
     }
-    g.close()
     print(json.dumps(out), flush=True)
 
 

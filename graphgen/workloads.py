@@ -89,21 +89,55 @@ def pool_digest(graphs) -> str:
 S22_SEED = 22
 
 
-def rmat_s22_bench_stream(warmup: int = 6, steps: int = 20, host_steps: int = 3,
-                          lo: float = 10, hi: float = 1e5, scale: int = 22, ef: int = 16,
-                          seed: int = S22_SEED):
+def rmat_s22_bench_stream(total: int = 25, host_steps: int = 0, lo: float = 10, hi: float = 1e5,
+                          scale: int = 22, ef: int = 16, seed: int = S22_SEED, snapshot_at=None):
     """R-MAT scale 22, edge factor 16 (n = 4,194,304, m = 67,108,864) with
-    ``warmup + steps`` batches of log-uniform size in [lo, hi] (50/50), then
-    ``host_steps`` more batches of the sizes of the first timed ones.
-    Returns (Workload with all batches in order, sizes, stream)."""
+    ``total`` batches of log-uniform size in [lo, hi] (half uniform
+    deletions, half R-MAT insertions), then ``host_steps`` more batches of
+    the same kind with sizes of their own.  The sequence depends on
+    ``total`` and ``host_steps`` only.  Returns (Workload with all batches in
+    order, sizes of the first ``total``, the stream); with ``snapshot_at``
+    = j the stream also keeps ``stream.snapshot``, its edge keys after the
+    first j batches."""
     n, s, d, sampler = rmat_graph(scale, ef, seed)
-    total = warmup + steps
     sizes = log_uniform_sizes(total, lo, hi, seed + 1)
     stream = BatchStream.from_edges(n, s, d, seed + 2, ins_sampler=sampler)
-    batches = [stream.next_batch(sz // 2, sz - sz // 2) for sz in sizes]
-    more = [stream.next_batch(sz // 2, sz - sz // 2) for sz in sizes[warmup:warmup + host_steps]]
+    batches = []
+    for j, sz in enumerate(sizes):
+        if snapshot_at == j:
+            stream.snapshot = stream.keys.copy()
+        batches.append(stream.next_batch(sz // 2, sz - sz // 2))
+    if snapshot_at == len(sizes):
+        stream.snapshot = stream.keys.copy()
+    hsizes = log_uniform_sizes(host_steps, lo, hi, seed + 3)
+    more = [stream.next_batch(sz // 2, sz - sz // 2) for sz in hsizes]
     w = Workload("rmat_s%d_ef%d_bench" % (scale, ef), n, s, d, batches + more,
-                 "rmat_graph(%d, %d, seed %d); sizes log_uniform_sizes(%d, %g, %g, seed %d); "
-                 "BatchStream(seed %d, R-MAT insertions); %d more batches of sizes[%d:%d]"
-                 % (scale, ef, seed, total, lo, hi, seed + 1, seed + 2, host_steps, warmup, warmup + host_steps))
+                 "rmat_graph(%d, %d, seed %d); %d batches, sizes log_uniform_sizes(%d, %g, %g, seed %d); "
+                 "BatchStream(seed %d, R-MAT insertions); then %d batches of sizes log_uniform_sizes(%d, %g, %g, "
+                 "seed %d)" % (scale, ef, seed, total, total, lo, hi, seed + 1, seed + 2, host_steps, host_steps,
+                               lo, hi, seed + 3))
     return w, sizes, stream
+
+
+def graph_digest(w: Workload) -> str:
+    return digest([np.array([w.n], np.int64), w.src, w.dst])
+
+
+def prefix_digest(w: Workload, j: int) -> str:
+    """Digest of the graph and its first j batches."""
+    parts = [np.array([w.n], np.int64), w.src, w.dst]
+    for b in w.batches[:j]:
+        parts.extend(b)
+    return digest(parts)
+
+
+def net_batch(keys_from, keys_to):
+    """One clean batch taking the edge-key set keys_from to keys_to (both
+    sorted uint64 pair keys): insert keys_to - keys_from, delete
+    keys_from - keys_to."""
+    from .generators import keys_to_edges
+    ins = np.setdiff1d(keys_to, keys_from, assume_unique=True)
+    dele = np.setdiff1d(keys_from, keys_to, assume_unique=True)
+    a, b = keys_to_edges(ins)
+    c, d = keys_to_edges(dele)
+    return a, b, c, d

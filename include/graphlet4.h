@@ -138,6 +138,7 @@ typedef struct {
   int64_t tri_exc_rebuilds;          /* triangle-tier vertices counted once per version (too many version-specific edges) */
   int32_t retries;                   /* counting stages run again after growing scratch for a larger vertex */
   int32_t reserved;
+  int64_t tri_entries;               /* adjacency entries read by the triangle tiers (N+(u) and each N+(v) probed) */
 } gc_batch_stats;
 
 /* One batch for one graph of a pool (host pointers). */

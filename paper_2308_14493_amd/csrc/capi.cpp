@@ -811,6 +811,7 @@ void fill_stats(gc_graph* G, gc_batch_stats* st, const unsigned long long* hb, c
   st->c4_searches = (int64_t)hb[BS_C4_SEARCH];
   st->tri_global_vertices = (int64_t)hb[BS_TRI_GLOBAL];
   st->tri_exc_rebuilds = (int64_t)hb[BS_TRI_REBUILD];
+  st->tri_entries = (int64_t)hb[BS_TRI_E];
   st->ms_total = (float)ms_total;
   if (timed) {
     float a = 0;

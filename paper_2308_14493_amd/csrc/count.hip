@@ -325,6 +325,7 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
   int cur_g = -1;
   int64_t kacc[NV];
   zerov<NV>(kacc);
+  int64_t ent = 0;  // entries of N+(u) and of the lists probed (algorithmic reads)
   for (int64_t it = (int64_t)blockIdx.x * TS_WAVES + w; it < n; it += (int64_t)gridDim.x * TS_WAVES) {
     const int32_t u = list[it];
     const int g = A.gid[u];
@@ -351,7 +352,7 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
     wave_sync();
     int64_t sb = 0;
     int32_t sl = 0;
-    if (l < dp) { sb = R.roff[vi] + R.rlow[vi]; sl = (int32_t)(R.roff[vi + 1] - sb); }
+    if (l < dp) { sb = R.roff[vi] + R.rlow[vi]; sl = (int32_t)(R.roff[vi + 1] - sb); ent += 1 + sl; }
     // one probe of list i: a hit (slot j with flags, jv) is the triangle
     // (u, v_i, v_j); row i's bits collect in ei (the caller writes them)
     const HashLook hl{hkey[w], hval[w], 255u, 24};
@@ -417,6 +418,8 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
     wave_sync();
   }
   if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_K4, kacc);
+  ent = wave_sum64(ent);
+  if (l == 0 && ent) atomicAdd(&A.bstats[BS_TRI_E], (unsigned long long)ent);
 }
 
 // ------------------------------------------------------ triangles, tier L
@@ -476,7 +479,7 @@ __device__ __forceinline__ bool bit_of(const unsigned long long* m, int32_t k) {
 // matrix plus all triangle bookkeeping; only = x+1: matrix of version x alone.
 template <int NV>
 __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL<NV>& S, uint32_t hmask, int shift,
-                                                int32_t g0, int32_t gs, int32_t dp, int only) {
+                                                int32_t g0, int32_t gs, int32_t dp, int only, int64_t& ent) {
   const RegionDev& R = A.R;
   const int l = lane_id();
   const int32_t i0 = g0 + gs * l;
@@ -489,6 +492,7 @@ __device__ __forceinline__ void tri_large_probe(const CountArgs& A, const TriL<N
     fi = xi & GC_FLAGS;
     sb = R.roff[v] + R.rlow[v];
     sl = (int32_t)(R.roff[v + 1] - sb);
+    if (only == 0) ent += sl;
   }
   using TU = typename TriL<NV>::TU;
   // one probe of list i: a hit (slot j with flags, jv) is the triangle
@@ -556,7 +560,7 @@ __device__ __forceinline__ int64_t k4_rows(const TriL<NV>& S, const unsigned lon
 
 template <int NV>
 __device__ void tri_large_vertex(const CountArgs& A, const TriL<NV>& S, int64_t ub, int32_t dp,
-                                 int64_t (&kacc)[NV]) {
+                                 int64_t (&kacc)[NV], int64_t& ent) {
   const RegionDev& R = A.R;
   const int w = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
@@ -585,7 +589,8 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL<NV>& S, int64_t 
       if (!absent_in(x, q)) atomicOr(&S.P[q * W + (k >> 6)], 1ull << (k & 63));
   }
   __syncthreads();
-  for (int32_t g0 = w; g0 < dp; g0 += nwaves * 64) tri_large_probe<NV>(A, S, hmask, shift, g0, nwaves, dp, 0);
+  if (threadIdx.x == 0) ent += dp;
+  for (int32_t g0 = w; g0 < dp; g0 += nwaves * 64) tri_large_probe<NV>(A, S, hmask, shift, g0, nwaves, dp, 0, ent);
   __syncthreads();
   const int32_t ne = *S.nexc;
   if (ne <= TL_EXC) {
@@ -679,7 +684,7 @@ __device__ void tri_large_vertex(const CountArgs& A, const TriL<NV>& S, int64_t 
       __syncthreads();
       for (int64_t k = threadIdx.x; k < ew; k += blockDim.x) S.E[k] = 0ull;
       __syncthreads();
-      for (int32_t g0 = w; g0 < dp; g0 += nwaves * 64) tri_large_probe<NV>(A, S, hmask, shift, g0, nwaves, dp, x + 1);
+      for (int32_t g0 = w; g0 < dp; g0 += nwaves * 64) tri_large_probe<NV>(A, S, hmask, shift, g0, nwaves, dp, x + 1, ent);
       __syncthreads();
       const int64_t c = k4_rows<NV>(S, S.P + x * W, dp, nwaves);
 #pragma unroll
@@ -727,6 +732,7 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int L, unsig
   int cur_g = -1;
   int64_t kacc[NV];
   zerov<NV>(kacc);
+  int64_t ent = 0;  // entries of N+(u) and of the lists probed (algorithmic reads)
   TriL<NV> S;
   using TU = typename TriL<NV>::TU;
   if constexpr (CAP == 0) {
@@ -786,9 +792,11 @@ __global__ __launch_bounds__(THREADS) void k_tri_large(CountArgs A, int L, unsig
       cur_g = g;
     }
     if constexpr (CAP != 0) S.W = (dp + 63) / 64;
-    tri_large_vertex<NV>(A, S, ub, dp, kacc);
+    tri_large_vertex<NV>(A, S, ub, dp, kacc, ent);
   }
   if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_K4, kacc);
+  ent = wave_sum64(ent);
+  if (lane_id() == 0 && ent) atomicAdd(&A.bstats[BS_TRI_E], (unsigned long long)ent);
 }
 
 template <int NV> constexpr int tl_max() { return TRI_LDS_MAX; }

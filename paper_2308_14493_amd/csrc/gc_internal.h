@@ -69,6 +69,7 @@ enum {
   BS_C4_SEARCH,   // cursor searches of that tier (lower neighbours x window passes)
   BS_TRI_GLOBAL,  // vertices counted by the global-scratch triangle tier
   BS_TRI_REBUILD, // vertices whose version-specific edges overflowed the exception list
+  BS_TRI_E,       // adjacency entries the triangle tiers read: N+(u) and the lists N+(v) probed
   BS_COUNT
 };
 

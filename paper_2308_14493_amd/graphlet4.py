@@ -39,7 +39,7 @@ class BatchStats(ctypes.Structure):
         (n, ctypes.c_float) for n in ("ms_total", "ms_prepare", "ms_tri", "ms_edge", "ms_c4_small",
                                       "ms_c4_mid", "ms_c4_large", "ms_finish")] + [
         ("c4_windows", _I64), ("c4_searches", _I64), ("tri_global_vertices", _I64), ("tri_exc_rebuilds", _I64),
-        ("retries", _I32), ("reserved", _I32)]
+        ("retries", _I32), ("reserved", _I32), ("tri_entries", _I64)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}

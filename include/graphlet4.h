@@ -223,6 +223,15 @@ int gc_apply_batch_seq(gc_graph* g, const gc_batch_desc* batches, int32_t nb, in
 int gc_get_counts(const gc_graph* g, int32_t graph, int64_t counts[11], uint32_t* overflow_mask);
 int gc_get_counts_exact(const gc_graph* g, int32_t graph, int64_t hi[11], uint64_t lo[11]);
 
+/* The four induced 3-vertex counts of graph `graph`, exactly (128-bit
+ * hi/lo pairs), in the order gc_class3: Sec. 3 notes that the static
+ * per-edge counter finds the size-3 graphlets along with the size-4 ones.
+ * They follow from the totals maintained for the disconnected 4-vertex
+ * classes: triangles T, 2-paths W = sum_v C(deg v, 2) (a triangle holds
+ * three), edges m and n.  No device work. */
+typedef enum { GC3_TRIANGLE = 0, GC3_PATH = 1, GC3_EDGE_ISO = 2, GC3_EMPTY = 3 } gc_class3;
+int gc_get_counts3(const gc_graph* g, int32_t graph, int64_t hi[4], uint64_t lo[4]);
+
 /* Static recount of graph `graph` from scratch on the GPU (the baseline of
  * Sec. 4.1); does not change the maintained counts.  For checking. */
 int gc_recount_exact(gc_graph* g, int32_t graph, int64_t hi[11], uint64_t lo[11]);

@@ -6,6 +6,7 @@
 ``static_counts_merge``  the same recount through a second formulation
                    (sorted merges per edge in id order), for cross-checks.
 ``sample_seconds`` time of the recount's loops over a sample of vertices.
+``static_counts3`` / ``brute3_counts``  the four induced 3-vertex counts.
 Results are exact Python ints (the C side works in __int128).
 """
 from __future__ import annotations
@@ -47,6 +48,9 @@ def _load():
         lib.static_counts_sample_time.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, ctypes.c_int64,
                                                   ctypes.c_int64, P]
         lib.static_counts_sample_time.restype = ctypes.c_int
+        for fn in ("brute3_counts", "static_counts3"):
+            getattr(lib, fn).argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, P, P]
+            getattr(lib, fn).restype = ctypes.c_int
         lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -112,6 +116,27 @@ def sample_seconds(n: int, src, dst, stride: int, offset: int = 0):
     if rc != 0:
         raise ValueError("oracle static_counts_sample_time failed (%d)" % rc)
     return float(secs[0]), float(secs[1])
+
+
+def _counts3(fn, n, src, dst):
+    lib = _load()
+    s, d = _edges(src, dst)
+    hi = np.zeros(4, np.int64); lo = np.zeros(4, np.uint64)
+    rc = getattr(lib, fn)(n, s.size, s.ctypes.data, d.ctypes.data, hi.ctypes.data, lo.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle %s failed (%d)" % (fn, rc))
+    return _join(hi, lo)
+
+
+def static_counts3(n: int, src, dst):
+    """Induced 3-vertex counts [triangle, 2-path, edge + isolated, empty]
+    from the static recount's totals."""
+    return _counts3("static_counts3", n, src, dst)
+
+
+def brute3_counts(n: int, src, dst):
+    """Induced 3-vertex counts by enumerating all C(n,3) subsets (n <= 4096)."""
+    return _counts3("brute3_counts", n, src, dst)
 
 
 def threads() -> int:

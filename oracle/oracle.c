@@ -527,6 +527,59 @@ int static_counts_sample_time(int64_t n, int64_t m, const int32_t* src, const in
     return 0;
 }
 
+/* ------------------------------------------------- 3-vertex graphlets -- */
+/* Induced 3-vertex counts, order: 0 triangle, 1 induced 2-path (wedge),
+ * 2 one edge + isolated vertex, 3 empty.  Sec. 3: PGD counts the graphlets
+ * of size 3 as well as size 4. */
+
+/* By enumeration of all C(n,3) subsets (n <= 4096). */
+int brute3_counts(int64_t n, int64_t m, const int32_t* src, const int32_t* dst, int64_t* hi, uint64_t* lo) {
+    if (n > 4096) return -2;
+    uint8_t* A = (uint8_t*)calloc((size_t)(n * n + 1), 1);
+    for (int64_t i = 0; i < m; ++i) {
+        int32_t u = src[i], v = dst[i];
+        if (u < 0 || v < 0 || u >= n || v >= n || u == v) { free(A); return -1; }
+        A[u * n + v] = 1; A[v * n + u] = 1;
+    }
+    i128 cnt[4] = {0};
+    #pragma omp parallel
+    {
+        int64_t loc[4] = {0};
+        #pragma omp for schedule(dynamic, 1)
+        for (int64_t a = 0; a < n; ++a)
+            for (int64_t b = a + 1; b < n; ++b)
+                for (int64_t c = b + 1; c < n; ++c) {
+                    int e = A[a * n + b] + A[a * n + c] + A[b * n + c];
+                    loc[3 - e]++;   /* 3 edges -> 0 (triangle), ..., 0 edges -> 3 (empty) */
+                }
+        #pragma omp critical
+        for (int k = 0; k < 4; ++k) cnt[k] += loc[k];
+    }
+    free(A);
+    for (int k = 0; k < 4; ++k) store128(cnt[k], &hi[k], &lo[k]);
+    return 0;
+}
+
+/* From the static recount's totals: T triangles, W = sum_v C(d_v, 2) 2-paths
+ * (a triangle holds three), m edges; every triple with an edge is counted
+ * by its edges in m (n - 2). */
+int static_counts3(int64_t n, int64_t m, const int32_t* src, const int32_t* dst, int64_t* hi, uint64_t* lo) {
+    adjlist g;
+    if (build_adj(n, m, src, dst, &g) != 0) { free_adj(&g); return -1; }
+    i128 sig[9];
+    int rc = noninduced(&g, sig, 1, 0);
+    free_adj(&g);
+    if (rc) return rc;
+    const i128 T = sig[6], W = sig[7], mm = sig[8], nn = n;
+    i128 I[4];
+    I[0] = T;
+    I[1] = W - 3 * T;
+    I[2] = mm * (nn - 2) - 2 * I[1] - 3 * I[0];
+    I[3] = nn * (nn - 1) * (nn - 2) / 6 - I[0] - I[1] - I[2];
+    for (int k = 0; k < 4; ++k) store128(I[k], &hi[k], &lo[k]);
+    return 0;
+}
+
 int oracle_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

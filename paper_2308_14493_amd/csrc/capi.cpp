@@ -104,6 +104,17 @@ void finalize(const long long* st, int64_t n, i128 I[11]) {
   I[10] = c4w(nn) - s;
 }
 
+// The four induced 3-vertex classes (triangle, 2-path, edge + isolated
+// vertex, empty) from T, W = sum C(d,2) and m: a triangle holds three
+// 2-paths, and every triple is counted by its edges in m (n - 2).
+void finalize3(const long long* st, int64_t n, i128 I[4]) {
+  const i128 T = st[ST_T], W = st[ST_W], m = st[ST_M], nn = n;
+  I[0] = T;
+  I[1] = W - 3 * T;
+  I[2] = m * (nn - 2) - 2 * I[1] - 3 * I[0];
+  I[3] = nn * (nn - 1) * (nn - 2) / 6 - I[0] - I[1] - I[2];
+}
+
 void to_int64(const i128 I[11], int64_t out[11], uint32_t* mask) {
   uint32_t mk = 0;
   for (int c = 0; c < 11; ++c) {
@@ -1440,6 +1451,16 @@ int gc_get_counts_exact(const gc_graph* g, int32_t graph, int64_t hi[11], uint64
     i128 I[11];
     finalize(&g->hstate[graph * ST_STRIDE], g->gn[graph], I);
     for (int c = 0; c < 11; ++c) { lo[c] = (uint64_t)I[c]; hi[c] = (int64_t)(I[c] >> 64); }
+  });
+}
+
+int gc_get_counts3(const gc_graph* g, int32_t graph, int64_t hi[4], uint64_t lo[4]) {
+  return guard([&] {
+    if (!g || !hi || !lo) raise(GC_EINVAL, "NULL argument");
+    if (graph < 0 || graph >= g->k) raise(GC_EINVAL, "graph index out of range");
+    i128 I[4];
+    finalize3(&g->hstate[graph * ST_STRIDE], g->gn[graph], I);
+    for (int c = 0; c < 4; ++c) { lo[c] = (uint64_t)I[c]; hi[c] = (int64_t)(I[c] >> 64); }
   });
 }
 

@@ -60,7 +60,7 @@ _lib = None
 
 EXPORTS = ["gc_options_default", "gc_graph_init", "gc_pool_init", "gc_apply_batch", "gc_apply_batch_dev",
            "gc_apply_batch_dev_noalloc",
-           "gc_apply_batches", "gc_apply_batch_seq", "gc_get_counts", "gc_get_counts_exact", "gc_recount_exact", "gc_graph_info",
+           "gc_apply_batches", "gc_apply_batch_seq", "gc_get_counts", "gc_get_counts_exact", "gc_get_counts3", "gc_recount_exact", "gc_graph_info",
            "gc_export_edges", "gc_graph_footprint", "gc_graph_replays", "gc_graph_free", "gc_strerror", "gc_last_error",
            "gc_server_opts_default", "gc_server_create", "gc_server_add_graph", "gc_server_submit",
            "gc_server_wait", "gc_server_counts", "gc_server_destroy"]
@@ -97,6 +97,7 @@ def load(path: str = LIB_PATH):
     lib.gc_get_counts.argtypes = [_P, _I32, _P, ctypes.POINTER(ctypes.c_uint32)]
     lib.gc_get_counts_exact.argtypes = [_P, _I32, _P, _P]
     lib.gc_recount_exact.argtypes = [_P, _I32, _P, _P]
+    lib.gc_get_counts3.argtypes = [_P, _I32, _P, _P]
     lib.gc_graph_info.argtypes = [_P, ctypes.POINTER(_I32), _I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]
     lib.gc_export_edges.argtypes = [_P, _I32, _P, _P, _I64, ctypes.POINTER(_I64)]
     lib.gc_graph_replays.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]
@@ -306,6 +307,15 @@ class Graph:
         hi = np.zeros(11, np.int64)
         lo = np.zeros(11, np.uint64)
         _check(lib.gc_get_counts_exact(self._h, graph, hi.ctypes.data, lo.ctypes.data))
+        return _join(hi, lo)
+
+    def counts3(self, graph=0):
+        """Exact induced 3-vertex counts [triangle, 2-path, edge + isolated,
+        empty] of graph `graph`."""
+        lib = load()
+        hi = np.zeros(4, np.int64)
+        lo = np.zeros(4, np.uint64)
+        _check(lib.gc_get_counts3(self._h, graph, hi.ctypes.data, lo.ctypes.data))
         return _join(hi, lo)
 
     def counts_int64(self, graph=0):

@@ -305,3 +305,29 @@ def test_semantics_keys_equal_sets(seed):
         assert set(zip(*[x.tolist() for x in keys_to_pairs(K)])) == E
     with pytest.raises(BatchRejected):
         apply_batch_keys(K, n, [0], [n], [], [])
+
+
+# ------------------------------------------------------ 3-vertex counts ---
+def test_counts3_static_vs_brute():
+    rng = random.Random(31)
+    for trial in range(200):
+        n = rng.randint(3, 16)
+        E = rand_graph(n, rng.choice([0.05, 0.3, 0.6, 0.95]), rng)
+        s, d = edges_of(E)
+        b = native.brute3_counts(n, s, d)
+        assert sum(b) == C(n, 3)
+        assert native.static_counts3(n, s, d) == b, (n, sorted(E))
+    n, s, d, _ = rmat_graph(8, 8, 5)
+    assert native.static_counts3(n, s, d) == native.brute3_counts(n, s, d)
+
+
+@pytest.mark.parametrize("n", [3, 7, 40, 200000])
+def test_counts3_closed_forms(n):
+    star = [(0, i) for i in range(1, n)]
+    assert native.static_counts3(n, *edges_of(star)) == [0, C(n - 1, 2), 0, C(n - 1, 3)]
+    path = [(i, i + 1) for i in range(n - 1)]
+    # an end edge sees n - 3 vertices adjacent to neither endpoint, an inner edge n - 4
+    one_edge = 2 * (n - 3) + (n - 3) * (n - 4) if n > 3 else 0
+    assert native.static_counts3(n, *edges_of(path)) == [0, n - 2, one_edge, C(n, 3) - (n - 2) - one_edge]
+    if n <= 40:
+        assert native.static_counts3(n, *edges_of(_complete(n))) == [C(n, 3), 0, 0, 0]

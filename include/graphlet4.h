@@ -110,6 +110,16 @@ typedef struct {
    * directly and is captured anew.  0: every pass launches its kernels one
    * by one.  Results are identical either way. */
   int32_t graphs;
+  /* Edge-local passes (one batch per graph of a pass only): instead of
+   * counting the region of change before and after, enumerate only the
+   * structures that contain a changed pair (triangles, 4-cliques and
+   * 4-cycles through each changed edge, the edges whose triangle count
+   * changed), each once from its changed pair of smallest key, with the
+   * triangles at every vertex kept on the device.  Same counts; far less
+   * work for small batches, more for very large ones.  0 (default): per
+   * batch-size decade the faster kind as measured (with autotune), 1:
+   * always, -1: never. */
+  int32_t delta;
 } gc_options;
 
 typedef struct {
@@ -137,7 +147,7 @@ typedef struct {
   int64_t tri_global_vertices;       /* vertices whose out-degree exceeds the LDS triangle tiers (global scratch) */
   int64_t tri_exc_rebuilds;          /* triangle-tier vertices counted once per version (too many version-specific edges) */
   int32_t retries;                   /* counting stages run again after growing scratch for a larger vertex */
-  int32_t reserved;
+  int32_t delta;                     /* 1: the pass was edge-local (gc_options.delta) */
   int64_t tri_entries;               /* adjacency entries read by the triangle tiers (N+(u) and each N+(v) probed) */
 } gc_batch_stats;
 

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgraphlet4.so")
-SOURCES = ["sort.hip", "graph.hip", "count.hip", "capi.cpp", "server.cpp"]
+SOURCES = ["sort.hip", "graph.hip", "count.hip", "delta.hip", "capi.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",

@@ -163,6 +163,11 @@ int64_t gc_footprint_estimate(int64_t n, int64_t m, double slack, int64_t max_de
     const int64_t cap = std::min<int64_t>(32767, max_out + max_out / 8 + 16);
     b += 256 * tri_scratch_words64(4, cap) * 8;
   }
+  // triangles per vertex and the edge-local passes' scratch (affected edges
+  // of a batch of 2^18 updates; common neighbours per hub-counter slot)
+  b += 24 * N;
+  b += 2 * 8 * (8 * ((int64_t)1 << 18) + 4096);
+  b += slots * (max_deg + max_deg / 4 + 4096) * 4;
   // transient arrays of the build (edge keys, directed entries, ranks)
   b += 64 * m + 24 * N;
   return b + ((int64_t)64 << 20);
@@ -196,6 +201,15 @@ struct gc_graph {
   // region and counting
   DevBuf roff, rcol, rrow, rlow, dver, t, tp, vpos, level, rlist, rlen, lists;
   DevBuf c4_dense, c4_touch, c4_cur, c4_blk, c4_keys, c4_keys_alt, tri_scratch;
+  // triangles at each vertex (kept for the edge-local passes) and the
+  // scratch of those passes
+  DevBuf Tv, dTs, sbt, ce, ae, ae_alt, slot_list, dctr;
+  int64_t ae_cap = 0, slot_cap = 0;
+  // edge-local vs region passes per batch-size decade: mean wall ms and
+  // passes seen (autotune)
+  double mode_ms[8][2] = {};
+  int64_t mode_n[8][2] = {};
+  int64_t decade_passes[8] = {};
   int64_t c4_cur_low = 0;
   int32_t c4_slots = 0, tri_slots = 0;
   int64_t tri_cap = 0;
@@ -439,7 +453,8 @@ CountArgs make_count_args(gc_graph* G, int nv, int64_t dense_min, bool fresh) {
 // Region + per-vertex pass + counting over nv versions + combine into
 // `state_d` (and G->vout for every later version).  `radius` < 0 counts
 // every vertex.  Enqueue only: no allocation, no synchronisation.
-void enqueue_count(gc_graph* G, int nv, int radius, long long* state_d, BatchWork& W, const CountArgs& A, bool timed) {
+void enqueue_count(gc_graph* G, int nv, int radius, long long* state_d, BatchWork& W, const CountArgs& A, bool timed,
+                   bool tv) {
   hipStream_t s = G->stream;
   PoolDev P = G->pd();
   launch_region(P, W, radius, G->level.as<int32_t>(), G->rlist.as<int32_t>(), G->rlen.as<int32_t>(), s);
@@ -450,6 +465,9 @@ void enqueue_count(gc_graph* G, int nv, int radius, long long* state_d, BatchWor
                  G->deg_wave_row, G->bstats.as<unsigned long long>(), G->c4_keys.as<unsigned long long>(), s);
   if (timed) HIPCHK(hipEventRecord(G->ev[1], s));
   launch_count(nv, A, s, timed ? &G->ev[2] : nullptr);
+  if (tv)
+    launch_tv_region(nv, A.R, G->rlist.as<int32_t>(), G->ctr.as<unsigned long long>(), G->dTs.as<unsigned long long>(),
+                     G->Tv.as<long long>(), G->bstats.as<unsigned long long>(), s);
   launch_combine(nv, G->sig.as<unsigned long long>(), state_d, G->vout.as<long long>(), G->k,
                  G->bstats.as<unsigned long long>(), s);
 }
@@ -474,7 +492,7 @@ void note_maxima(gc_graph* G) {
 // for more scratch (the combine and the purge then changed nothing), grow it
 // from the observed degrees and count again.  Returns the attempts made.
 int settle_retries(gc_graph* G, int nv, int radius, long long* state_d, BatchWork& W, int64_t dense_min,
-                   int64_t entries, bool purge, int64_t max_touched, bool fresh) {
+                   int64_t entries, bool purge, int64_t max_touched, bool fresh, bool tv) {
   int attempts = 0;
   while (G->out_bst()[BS_RETRY]) {
     if (++attempts > G->retry_limit)
@@ -483,7 +501,7 @@ int settle_retries(gc_graph* G, int nv, int radius, long long* state_d, BatchWor
     size_count_scratch(G, nv, entries);
     reset_count_stage(G);
     CountArgs A = make_count_args(G, nv, dense_min, fresh);
-    enqueue_count(G, nv, radius, state_d, W, A, false);
+    enqueue_count(G, nv, radius, state_d, W, A, false, tv);
     if (purge)
       launch_purge(G->pd(), W, max_touched, G->bits, 1u << (GC_VSHIFT + nv - 1),
                    G->bstats.as<unsigned long long>() + BS_RETRY, G->scan_tmp.p, G->stream);
@@ -566,6 +584,11 @@ void alloc_vertex_arrays(gc_graph* G) {
   G->ctr.ensure(C_COUNT * sizeof(unsigned long long));
   G->bstats.ensure(BS_COUNT * sizeof(unsigned long long));
   G->top.ensure(sizeof(unsigned long long));
+  for (DevBuf* b : {&G->Tv, &G->dTs, &G->sbt}) {
+    b->ensure(N * sizeof(long long));
+    fill_u64(b->as<unsigned long long>(), 0ull, N, s);
+  }
+  G->dctr.ensure(DC_COUNT * sizeof(unsigned long long));
   if (!G->pout) HIPCHK(hipHostMalloc(&G->pout, G->out_bytes(), hipHostMallocDefault));
 }
 
@@ -775,10 +798,10 @@ void build(gc_graph* G, int32_t k, const int64_t* n, const int32_t* const* src, 
   // (2^18 insertions and 2^18 deletions: 2^20 touched rows at most)
   G->sort_tmp.ensure(radix_sort_tmp_bytes(std::max<int64_t>(std::max<int64_t>(2 * M, N), 1 << 20)) + 64);
   G->scan_tmp.ensure(scan_tmp_bytes(std::max<int64_t>(N, 1 << 20) + 1) + 64);
-  enqueue_count(G, 2, -1, G->state.as<long long>(), W, make_count_args(G, 2, G->dense_min_best, true), false);
+  enqueue_count(G, 2, -1, G->state.as<long long>(), W, make_count_args(G, 2, G->dense_min_best, true), false, true);
   enqueue_readback(G, G->state.as<long long>());
   G->sync();
-  settle_retries(G, 2, -1, G->state.as<long long>(), W, G->dense_min_best, nd, false, 0, true);
+  settle_retries(G, 2, -1, G->state.as<long long>(), W, G->dense_min_best, nd, false, 0, true, true);
   launch_all_flags(P, 0u, GC_ID, s);
   G->sync();
   G->entries = nd;
@@ -823,6 +846,7 @@ void fill_stats(gc_graph* G, gc_batch_stats* st, const unsigned long long* hb, c
   st->tri_global_vertices = (int64_t)hb[BS_TRI_GLOBAL];
   st->tri_exc_rebuilds = (int64_t)hb[BS_TRI_REBUILD];
   st->tri_entries = (int64_t)hb[BS_TRI_E];
+  st->delta = 0;
   st->ms_total = (float)ms_total;
   if (timed) {
     float a = 0;
@@ -868,7 +892,55 @@ struct PassPlan {
   size_t tab_words = 0, in_bytes = 0;
   int radius = 2;
   int64_t dense_min = 256;
+  bool delta = false;  // edge-local pass (one batch per graph) instead of the region count
 };
+
+DeltaArgs make_delta_args(gc_graph* G, const BatchWork& W) {
+  DeltaArgs D;
+  D.P = G->pd();
+  D.N = G->N;
+  D.bits = G->bits;
+  D.dirA = W.dirA;
+  D.dirD = W.dirD;
+  D.c = G->ctr.as<unsigned long long>();
+  D.touched = W.touched;
+  D.mark = W.mark;
+  D.gid = G->gid.as<int32_t>();
+  D.sig = G->sig.as<unsigned long long>();
+  D.bstats = G->bstats.as<unsigned long long>();
+  D.dd = G->dver.as<int32_t>();
+  D.Tv = G->Tv.as<long long>();
+  D.dT = G->dTs.as<unsigned long long>();
+  D.sbt = G->sbt.as<unsigned long long>();
+  D.ce = G->ce.as<unsigned long long>();
+  D.ce_cap = (int64_t)(G->ce.cap / 8);
+  D.ae = G->ae.as<unsigned long long>();
+  D.ae_alt = G->ae_alt.as<unsigned long long>();
+  D.ae_cap = G->ae_cap;
+  D.sort_tmp = G->sort_tmp.p;
+  D.slot_mark = G->c4_dense.as<unsigned long long>();
+  D.slot_list = G->slot_list.as<uint32_t>();
+  D.slot_cap = G->slot_cap;
+  D.dc = G->dctr.as<unsigned long long>();
+  return D;
+}
+
+// Buffers of an edge-local pass for batches of capacity cap_t (allocates:
+// never called during stream capture).
+void size_delta(gc_graph* G, int64_t cap_t, int64_t ae_need, int64_t slot_need) {
+  G->ce.ensure(std::max<int64_t>(cap_t, 64) * 8);
+  G->ae_cap = std::max<int64_t>(G->ae_cap, std::max<int64_t>(ae_need, 8 * cap_t + 4096));
+  G->ae.ensure(G->ae_cap * 8);
+  G->ae_alt.ensure(G->ae_cap * 8);
+  G->sort_tmp.ensure(radix_sort_tmp_bytes(G->ae_cap) + 64);
+  G->slot_cap = std::max<int64_t>(G->slot_cap, std::max<int64_t>(slot_need, 4096));
+  G->slot_list.ensure((size_t)std::max(1, G->c4_slots) * G->slot_cap * 4);
+}
+
+// After an edge-local pass whose affected-edge list or common-neighbour slot
+// was too small (the combine and the purge then changed nothing): grow them
+// from the sizes the kernels asked for and run the stage again.
+int settle_delta(gc_graph* G, const PassPlan& L, BatchWork& W);
 
 // Every device step of a pass, in stream order: upload, ingest, merge,
 // counting, purge, results to the pinned buffer.  No allocation and no
@@ -902,10 +974,42 @@ void enqueue_pass(gc_graph* G, const PassPlan& L, BatchIn& B, BatchWork& W, cons
   launch_mark_rows(sR, 2 * L.cap_d, ctr, C_DIRR, G->bits, W.r_beg, W.nr, W.mark, W.touched, W.tix, s);
   launch_merge(P, W, L.max_touched, 2 * L.cap_i, G->bits, G->opt.slack, bst, G->scan_tmp.p, s);
   launch_flag_rows(P, W, 2 * L.cap_d, G->bits, bst, s);
-  enqueue_count(G, L.nv, L.radius, G->state.as<long long>(), W, make_count_args(G, L.nv, L.dense_min, false), timed);
+  if (L.delta) {
+    if (timed) HIPCHK(hipEventRecord(G->ev[1], s));
+    launch_delta(make_delta_args(G, W), G->c4_slots, s);
+    if (timed)
+      for (int e = 2; e <= 7; ++e) HIPCHK(hipEventRecord(G->ev[e], s));
+    launch_combine(2, G->sig.as<unsigned long long>(), G->state.as<long long>(), G->vout.as<long long>(), G->k, bst, s);
+  } else {
+    enqueue_count(G, L.nv, L.radius, G->state.as<long long>(), W, make_count_args(G, L.nv, L.dense_min, false), timed,
+                  true);
+  }
   launch_purge(P, W, L.max_touched, G->bits, 1u << (GC_VSHIFT + L.nv - 1), bst + BS_RETRY, G->scan_tmp.p, s);
   if (timed) HIPCHK(hipEventRecord(G->ev[8], s));
   enqueue_readback(G, G->state.as<long long>());
+}
+
+int settle_delta(gc_graph* G, const PassPlan& L, BatchWork& W) {
+  int attempts = 0;
+  hipStream_t s = G->stream;
+  while (G->out_bst()[BS_RETRY]) {
+    if (++attempts > G->retry_limit)
+      raise(GC_EDEVICE, "edge-local scratch still too small after %d more attempts", G->retry_limit);
+    unsigned long long dc[DC_COUNT];
+    HIPCHK(hipMemcpyAsync(dc, G->dctr.p, sizeof(dc), hipMemcpyDeviceToHost, s));
+    G->sync();
+    size_delta(G, L.cap_t, (int64_t)dc[DC_AFF_NEED] + (int64_t)dc[DC_AFF_NEED] / 4,
+               (int64_t)dc[DC_SLOT_NEED] + (int64_t)dc[DC_SLOT_NEED] / 4);
+    reset_count_stage(G);
+    launch_delta(make_delta_args(G, W), G->c4_slots, s);
+    launch_combine(2, G->sig.as<unsigned long long>(), G->state.as<long long>(), G->vout.as<long long>(), G->k,
+                   G->bstats.as<unsigned long long>(), s);
+    launch_purge(G->pd(), W, L.max_touched, G->bits, 1u << (GC_VSHIFT + 1), G->bstats.as<unsigned long long>() + BS_RETRY,
+                 G->scan_tmp.p, s);
+    enqueue_readback(G, G->state.as<long long>());
+    G->sync();
+  }
+  return attempts;
 }
 
 // What an enqueued pass depends on: its sizes and knobs and every buffer
@@ -916,14 +1020,16 @@ std::vector<uint64_t> pass_signature(gc_graph* G, const PassPlan& L, const Count
                              (uint64_t)A.c4_dense_min, (uint64_t)A.c4_win, (uint64_t)A.c4_narrow_max, (uint64_t)A.c4_ref,
                              (uint64_t)A.c4_maxlow, (uint64_t)A.slots, (uint64_t)A.tri_cap, (uint64_t)A.e_max,
                              (uint64_t)G->arena_cap, (uint64_t)L.in_bytes, (uint64_t)G->k, (uint64_t)G->N,
-                             (uint64_t)G->bits};
+                             (uint64_t)G->bits, (uint64_t)L.delta, (uint64_t)G->ae_cap, (uint64_t)G->slot_cap,
+                             (uint64_t)G->ce.cap};
   const DevBuf* bufs[] = {&G->off, &G->len, &G->cap, &G->col, &G->top, &G->gid, &G->ext2int, &G->state, &G->vout,
                           &G->sig, &G->ctr, &G->bstats, &G->bin, &G->keys, &G->keys_alt, &G->dirA, &G->dirA_alt,
                           &G->dirD, &G->dirD_alt, &G->dirR, &G->dirR_alt, &G->a_beg, &G->na, &G->r_beg, &G->nr,
                           &G->mark, &G->tix, &G->touched, &G->dest, &G->newcap, &G->tlen, &G->tpre, &G->scratch,
                           &G->sort_tmp, &G->scan_tmp, &G->roff, &G->rcol, &G->rrow, &G->rlow, &G->dver, &G->t,
                           &G->tp, &G->vpos, &G->level, &G->rlist, &G->rlen, &G->lists, &G->c4_dense, &G->c4_touch,
-                          &G->c4_cur, &G->c4_blk, &G->c4_keys, &G->c4_keys_alt, &G->tri_scratch};
+                          &G->c4_cur, &G->c4_blk, &G->c4_keys, &G->c4_keys_alt, &G->tri_scratch, &G->Tv, &G->dTs,
+                          &G->sbt, &G->ce, &G->ae, &G->ae_alt, &G->slot_list, &G->dctr};
   for (const DevBuf* b : bufs) v.push_back((uint64_t)(uintptr_t)b->p);
   v.push_back((uint64_t)(uintptr_t)G->pin);
   v.push_back((uint64_t)(uintptr_t)G->pout);
@@ -988,6 +1094,23 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
     for (int d = 0; d <= decade; ++d) wide = wide || G->region_frac[d] >= 0.9;
     if (L.radius >= 2 && wide) L.radius = -1;
   }
+  // edge-local pass: one batch per graph and an exact radius; forced by the
+  // option, or per batch-size decade the faster of the two kinds measured so
+  // far (each tried once, then the other one again every 16th pass)
+  if (L.nv == 2 && G->opt.radius != 1) {
+    if (G->opt.delta > 0) {
+      L.delta = true;
+    } else if (G->opt.delta == 0 && G->opt.autotune && tune_idx < 0) {
+      const int64_t* n = G->mode_n[decade];
+      const double* ms = G->mode_ms[decade];
+      if (n[0] == 0) L.delta = false;
+      else if (n[1] == 0) L.delta = true;
+      else {
+        L.delta = ms[1] < ms[0];
+        if (G->decade_passes[decade] % 16 == 15) L.delta = !L.delta;
+      }
+    }
+  }
   const bool timed_run = timed || (G->opt.autotune && tune_idx >= 0);
 
   // buffers (all allocation happens here, before anything is enqueued)
@@ -1005,6 +1128,7 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
                      64);
   G->scan_tmp.ensure(scan_tmp_bytes(std::max<int64_t>(L.max_touched, G->N) + 1) + 64);
   size_count_scratch(G, L.nv, L.union_bound);
+  if (L.delta) size_delta(G, L.cap_t, 0, 0);
   // arena reserve: enough for every touched row to move
   const int64_t need = (int64_t)((1.0 + G->opt.slack) * (double)L.union_bound) + 8 * L.max_touched + 1024;
   if (G->arena_cap - G->arena_top < need) compact(G, need);
@@ -1088,8 +1212,9 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
     enqueue_pass(G, L, B, W, S, timed_run, true);
   }
   G->sync();
-  retries = settle_retries(G, L.nv, L.radius, G->state.as<long long>(), W, L.dense_min, L.union_bound, true,
-                           L.max_touched, false);
+  if (L.delta) retries += settle_delta(G, L, W);
+  retries += settle_retries(G, L.nv, L.radius, G->state.as<long long>(), W, L.dense_min, L.union_bound, true,
+                            L.max_touched, false, true);
   } catch (...) {
     if (G->in_pass) G->broken = true;
     G->in_pass = false;
@@ -1143,6 +1268,14 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
     }
   }
   const double ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  if (L.nv == 2 && retries == 0) {
+    const int m = L.delta ? 1 : 0;
+    int64_t& cnt = G->mode_n[decade][m];
+    double& avg = G->mode_ms[decade][m];
+    avg = cnt == 0 ? ms : 0.75 * avg + 0.25 * ms;
+    ++cnt;
+    ++G->decade_passes[decade];
+  }
   if (stats) {
     const int nst = seq ? nb : 1;
     for (int q = 0; q < nst; ++q) {
@@ -1152,8 +1285,9 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
       fill_stats(G, &stats[q], hb.data(), hc.data(), seq ? q : 0, L.npass, seq ? b[q].n_ins : L.ni, seq ? b[q].n_del : L.ndl,
                  timed && retries == 0, ms, mk);
       stats[q].c4_dense_min = L.dense_min;
-      stats[q].whole_graph = L.radius < 0;
+      stats[q].whole_graph = L.radius < 0 && !L.delta;
       stats[q].retries = retries;
+      stats[q].delta = L.delta;
     }
   }
 }
@@ -1349,6 +1483,7 @@ int gc_options_default(gc_options* opt) {
   opt->stream = nullptr;
   opt->autotune = 1;
   opt->graphs = 1;
+  opt->delta = 0;
   return GC_OK;
 }
 
@@ -1482,10 +1617,10 @@ int gc_recount_exact(gc_graph* g, int32_t graph, int64_t hi[11], uint64_t lo[11]
       fill_u64((unsigned long long*)g->state_tmp.p, 0ull, (int64_t)g->k * ST_STRIDE, s);
       zero_small(g);
       enqueue_count(g, 2, -1, g->state_tmp.as<long long>(), W, make_count_args(g, 2, g->dense_min_best, true),
-                    false);
+                    false, false);
       enqueue_readback(g, g->state_tmp.as<long long>());
       g->sync();
-      settle_retries(g, 2, -1, g->state_tmp.as<long long>(), W, g->dense_min_best, g->entries, false, 0, true);
+      settle_retries(g, 2, -1, g->state_tmp.as<long long>(), W, g->dense_min_best, g->entries, false, 0, true, false);
       launch_all_flags(P, 0u, GC_ID, s);
       st.assign(g->out_state(), g->out_state() + (size_t)g->k * ST_STRIDE);
       g->sync();

@@ -161,6 +161,42 @@ void launch_combine(int nv, const unsigned long long* sig, long long* state, lon
                     const unsigned long long* bstats, hipStream_t s);
 
 // capi.cpp: thread-local error text read by gc_last_error()
+// delta.hip: edge-local update of the Sigma terms of a one-batch pass
+enum { DC_EDGES = 0, DC_AFF, DC_AFF_TOTAL, DC_AFF_NEED, DC_SLOT_NEED, DC_QTRI, DC_QC4, DC_COUNT };
+struct DeltaArgs {
+  PoolDev P;                          // union view left by the tombstone merge
+  int64_t N;
+  int bits;
+  const unsigned long long* dirA;     // sorted directed change lists (counts in c)
+  const unsigned long long* dirD;
+  const unsigned long long* c;        // batch counters (C_DIRA, C_DIRD, C_TOUCH)
+  const int32_t* touched;             // touched rows
+  const int32_t* mark;                // [N] 1 on touched rows
+  const int32_t* gid;                 // [N] graph of each vertex
+  unsigned long long* sig;            // per-graph sums; version 1 receives the deltas
+  unsigned long long* bstats;         // BS_RETRY when a buffer below is too small
+  int32_t* dd;                        // [N][2] degrees before / after of the touched rows
+  long long* Tv;                      // [N] triangles at each vertex (moved to the graph after the batch)
+  unsigned long long* dT;             // [N] scratch, zero between passes: twice the change of T(v)
+  unsigned long long* sbt;            // [N] scratch, zero between passes: t before of affected edges at v
+  unsigned long long* ce;             // changed pairs (u < v) | nibble << 60
+  int64_t ce_cap;
+  unsigned long long* ae;             // affected edge keys and their sort buffer
+  unsigned long long* ae_alt;
+  int64_t ae_cap;
+  void* sort_tmp;                     // radix sort scratch for ae_cap keys
+  unsigned long long* slot_mark;      // [slots][N] dense marks, zero between uses
+  uint32_t* slot_list;                // [slots][slot_cap] common neighbours of a changed edge
+  int64_t slot_cap;
+  unsigned long long* dc;             // [DC_COUNT] counters of the stage
+};
+// launches the delta stage with `slots` workgroups for the per-edge kernels
+void launch_delta(const DeltaArgs& D, int slots, hipStream_t s);
+// T(v) of the region vertices after a region pass (t of the last version
+// minus t of version 0); dT zero before and after
+void launch_tv_region(int nv, const RegionDev& R, const int32_t* rlist, const unsigned long long* c,
+                      unsigned long long* dT, long long* Tv, unsigned long long* bstats, hipStream_t s);
+
 void gc_set_error(const char* msg);
 // device bytes a single-graph handle reaches (capi.cpp); used by the server's admission
 int64_t gc_footprint_estimate(int64_t n, int64_t m, double slack, int64_t max_deg, int64_t max_out);

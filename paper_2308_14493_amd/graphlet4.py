@@ -25,7 +25,7 @@ _P = ctypes.c_void_p
 
 class Options(ctypes.Structure):
     _fields_ = [("radius", _I32), ("slack", ctypes.c_float), ("device", _I32), ("stream", _P), ("autotune", _I32),
-                ("graphs", _I32)]
+                ("graphs", _I32), ("delta", _I32)]
 
 
 class BatchStats(ctypes.Structure):
@@ -39,7 +39,7 @@ class BatchStats(ctypes.Structure):
         (n, ctypes.c_float) for n in ("ms_total", "ms_prepare", "ms_tri", "ms_edge", "ms_c4_small",
                                       "ms_c4_mid", "ms_c4_large", "ms_finish")] + [
         ("c4_windows", _I64), ("c4_searches", _I64), ("tri_global_vertices", _I64), ("tri_exc_rebuilds", _I64),
-        ("retries", _I32), ("reserved", _I32), ("tri_entries", _I64)]
+        ("retries", _I32), ("delta", _I32), ("tri_entries", _I64)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
@@ -133,10 +133,12 @@ def _join(hi, lo):
     return [(int(h) << 64) | int(l) for h, l in zip(hi.tolist(), lo.tolist())]
 
 
-def _opts(radius, slack, device, stream, autotune=None, graphs=None):
+def _opts(radius, slack, device, stream, autotune=None, graphs=None, delta=None):
     lib = load()
     o = Options()
     lib.gc_options_default(ctypes.byref(o))
+    if delta is not None:
+        o.delta = int(delta)
     if autotune is not None:
         o.autotune = int(autotune)
     if graphs is not None:
@@ -164,10 +166,10 @@ class Graph:
     """A resident graph (or a pool of graphs) on one GPU."""
 
     def __init__(self, n, src=(), dst=(), radius=None, slack=None, device=0, stream=None, autotune=None,
-                 graphs=None, _pool=None):
+                 graphs=None, delta=None, _pool=None):
         lib = load()
         self._h = _P()
-        opt = _opts(radius, slack, device, stream, autotune, graphs)
+        opt = _opts(radius, slack, device, stream, autotune, graphs, delta)
         if _pool is None:
             s, d = _i32(src), _i32(dst)
             assert s.shape == d.shape

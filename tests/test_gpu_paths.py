@@ -50,7 +50,7 @@ def test_scratch_growth_retry_exact(monkeypatch):
     say("case scratch growth retry")
     n, E, b = hub_growth_case()
     s, d = esorted(E)
-    with Graph(n, s, d) as g:
+    with Graph(n, s, d, delta=-1) as g:
         assert g.counts() == native.static_counts(n, s, d)
         got, st = g.apply_batch(*b, stats=True)
         say("  retries %d hubs %d" % (st["retries"], st["tier_c4_large"]))
@@ -67,7 +67,7 @@ def test_failure_after_merge_marks_handle_unusable(monkeypatch):
     n, E, b = hub_growth_case()
     s, d = esorted(E)
     monkeypatch.setenv("GC_RETRY_LIMIT", "0")
-    with Graph(n, s, d) as g:
+    with Graph(n, s, d, delta=-1) as g:
         before = g.counts()
         with pytest.raises(GraphletError) as e1:
             g.apply_batch(*b)
@@ -97,7 +97,7 @@ def test_dense_fallback_paths(n, p, k, seed, what):
         o = native.static_counts(n, c[0], c[1])
         return [o[COMP[j]] for j in range(11)]
 
-    with Graph(n, s, d) as g:
+    with Graph(n, s, d, delta=-1) as g:
         el = sorted(E)
         pick = rng.choice(len(el), k // 2, replace=False)
         du = np.array([el[q][0] for q in pick], np.int32)

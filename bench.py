@@ -316,6 +316,8 @@ def main():
     ap.add_argument("--min-batch", type=float, default=10)
     ap.add_argument("--max-batch", type=float, default=1e5)
     ap.add_argument("--radius", type=int, default=2)
+    ap.add_argument("--delta", type=int, default=0,
+                    help="edge-local passes: 1 always, -1 never, 0 the faster kind per batch-size decade (default)")
     ap.add_argument("--cpu-stride", type=int, default=16, help="cpu_baseline: every stride-th vertex is timed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recount-check", action="store_true")
@@ -378,7 +380,7 @@ def main():
         log("calibration copy of %d MiB done" % args.calibrate_copy)
         del src, dst
     t0 = time.time()
-    g = pkg.Graph(n, s, d, radius=args.radius)
+    g = pkg.Graph(n, s, d, radius=args.radius, delta=args.delta)
     torch.cuda.synchronize()
     c0 = g.counts()
     log("graph resident on the GPU in %.2fs; counts %s" % (time.time() - t0, c0))
@@ -403,11 +405,11 @@ def main():
             offered += b[0].size + b[2].size
             stats.append(st)
         log("step %d: batch %d updates, %.2f ms (tri %.2f edge %.2f c4 %.2f/%.2f/%.2f prep %.2f fin %.2f) dmin %d "
-            "whole %d region_e=%d c4_tail=%d/%d hubs=%d windows=%d searches=%d tri_e=%d" % (
+            "whole %d delta %d region_e=%d c4_tail=%d/%d hubs=%d windows=%d searches=%d tri_e=%d" % (
                 i, b[0].size + b[2].size, (t2 - t1) * 1e3, st["ms_tri"], st["ms_edge"], st["ms_c4_small"],
                 st["ms_c4_mid"], st["ms_c4_large"], st["ms_prepare"], st["ms_finish"], st["c4_dense_min"],
-                st["whole_graph"], st["region_entries"], st["c4_tail_wedges"], st["wedges"], st["tier_c4_large"],
-                st["c4_windows"], st["c4_searches"], st["tri_entries"]))
+                st["whole_graph"], st["delta"], st["region_entries"], st["c4_tail_wedges"], st["wedges"],
+                st["tier_c4_large"], st["c4_windows"], st["c4_searches"], st["tri_entries"]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - tstart
     value = offered / elapsed
@@ -472,8 +474,9 @@ def main():
         "ms_per_step": elapsed * 1e3 / max(1, args.steps), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": "R-MAT scale %d edge factor %d (n=%d, m=%d), batches log-uniform in [%g, %g], "
-                               "50/50 insert/delete, plain per-batch path, radius %d"
-                               % (args.scale, args.ef, n, s.size, args.min_batch, args.max_batch, args.radius),
+                               "50/50 insert/delete, plain per-batch path, radius %d, edge-local passes %s"
+                               % (args.scale, args.ef, n, s.size, args.min_batch, args.max_batch, args.radius,
+                                  {0: "auto", 1: "always", -1: "never"}[args.delta]),
                    "form": "plain"},
         "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
         "oracle_check": {"golden": "tests/golden/scale_rmat_s22_bench.json", "after_batches": sorted(gold),

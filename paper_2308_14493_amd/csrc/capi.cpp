@@ -203,13 +203,16 @@ struct gc_graph {
   DevBuf c4_dense, c4_touch, c4_cur, c4_blk, c4_keys, c4_keys_alt, tri_scratch;
   // triangles at each vertex (kept for the edge-local passes) and the
   // scratch of those passes
-  DevBuf Tv, dTs, sbt, ce, ae, ae_alt, slot_list, dctr;
-  int64_t ae_cap = 0, slot_cap = 0;
-  // edge-local vs region passes per batch-size decade: mean wall ms and
-  // passes seen (autotune)
-  double mode_ms[8][2] = {};
-  int64_t mode_n[8][2] = {};
-  int64_t decade_passes[8] = {};
+  DevBuf Tv, dTs, sbt, ce, ae, ae_alt, slot_list, dctr, c4_nch, c4_side, c4_off, pair_edge, pair_len, pair_off;
+  int64_t ae_cap = 0, slot_cap = 0, pair_cap = 0;
+  // cost model of the two kinds of one-batch pass (autotune): per
+  // half-decade of batch size and kind (0 region, 1 edge-local), the mean
+  // wall ms, mean batch size and passes seen; the mean of all region passes
+  double mode_ms[16][2] = {};
+  double mode_sz[16][2] = {};
+  int64_t mode_n[16][2] = {};
+  double region_ms_all = 0;
+  int64_t region_n_all = 0;
   int64_t c4_cur_low = 0;
   int32_t c4_slots = 0, tri_slots = 0;
   int64_t tri_cap = 0;
@@ -922,13 +925,30 @@ DeltaArgs make_delta_args(gc_graph* G, const BatchWork& W) {
   D.slot_list = G->slot_list.as<uint32_t>();
   D.slot_cap = G->slot_cap;
   D.dc = G->dctr.as<unsigned long long>();
+  D.c4_nch = G->c4_nch.as<int32_t>();
+  D.c4_side = G->c4_side.as<int32_t>();
+  D.c4_off = G->c4_off.as<int64_t>();
+  D.pair_edge = G->pair_edge.as<int32_t>();
+  D.pair_len = G->pair_len.as<int32_t>();
+  D.pair_off = G->pair_off.as<int64_t>();
+  D.pair_cap = G->pair_cap;
+  D.scan_tmp = G->scan_tmp.p;
   return D;
 }
 
 // Buffers of an edge-local pass for batches of capacity cap_t (allocates:
 // never called during stream capture).
-void size_delta(gc_graph* G, int64_t cap_t, int64_t ae_need, int64_t slot_need) {
-  G->ce.ensure(std::max<int64_t>(cap_t, 64) * 8);
+void size_delta(gc_graph* G, int64_t cap_t, int64_t ae_need, int64_t slot_need, int64_t pair_need = 0) {
+  const int64_t ce_cap = std::max<int64_t>(cap_t, 64);
+  G->ce.ensure(ce_cap * 8);
+  G->c4_nch.ensure(G->ce.cap / 8 * 4);
+  G->c4_side.ensure(G->ce.cap / 8 * 4);
+  G->c4_off.ensure((G->ce.cap / 8 + 1) * 8);
+  G->pair_cap = std::max<int64_t>(G->pair_cap, std::max<int64_t>(pair_need, 64 * cap_t + 4096));
+  G->pair_edge.ensure(G->pair_cap * 4);
+  G->pair_len.ensure(G->pair_cap * 4);
+  G->pair_off.ensure((G->pair_cap + 1) * 8);
+  G->scan_tmp.ensure(scan_tmp_bytes(std::max<int64_t>(G->ce.cap / 8, G->pair_cap) + 1) + 64);
   G->ae_cap = std::max<int64_t>(G->ae_cap, std::max<int64_t>(ae_need, 8 * cap_t + 4096));
   G->ae.ensure(G->ae_cap * 8);
   G->ae_alt.ensure(G->ae_cap * 8);
@@ -941,6 +961,34 @@ void size_delta(gc_graph* G, int64_t cap_t, int64_t ae_need, int64_t slot_need) 
 // was too small (the combine and the purge then changed nothing): grow them
 // from the sizes the kernels asked for and run the stage again.
 int settle_delta(gc_graph* G, const PassPlan& L, BatchWork& W);
+
+// Edge-local or region pass for a batch of `total` updates in half-decade
+// `b`: the kind with the smaller expected wall time.  Region time: this
+// bucket's mean, else the mean of all region passes (it hardly depends on
+// the batch).  Edge-local time: this bucket's mean, else the nearest
+// measured bucket's scaled by the batch size (its work grows with the
+// changed pairs), else a first try for batches of at most 1000 updates.
+// Both kinds measured in a bucket: every 32nd pass there tries the other.
+bool choose_delta(gc_graph* G, int b, int64_t total) {
+  const int64_t* n = G->mode_n[b];
+  if (G->region_n_all == 0) return false;
+  if (n[0] > 0 && n[1] > 0) {
+    const bool d = G->mode_ms[b][1] < G->mode_ms[b][0];
+    return (n[0] + n[1]) % 32 == 31 ? !d : d;
+  }
+  const double est_r = n[0] > 0 ? G->mode_ms[b][0] : G->region_ms_all;
+  double est_d = -1;
+  if (n[1] > 0) {
+    est_d = G->mode_ms[b][1];
+  } else {
+    for (int k = 1; k < 16 && est_d < 0; ++k)
+      for (int bb : {b - k, b + k})
+        if (bb >= 0 && bb < 16 && G->mode_n[bb][1] > 0 && est_d < 0)
+          est_d = G->mode_ms[bb][1] * (double)std::max<int64_t>(total, 1) / std::max(1.0, G->mode_sz[bb][1]);
+  }
+  if (est_d < 0) return total <= 1000;
+  return est_d < est_r;
+}
 
 // Every device step of a pass, in stream order: upload, ingest, merge,
 // counting, purge, results to the pinned buffer.  No allocation and no
@@ -999,7 +1047,8 @@ int settle_delta(gc_graph* G, const PassPlan& L, BatchWork& W) {
     HIPCHK(hipMemcpyAsync(dc, G->dctr.p, sizeof(dc), hipMemcpyDeviceToHost, s));
     G->sync();
     size_delta(G, L.cap_t, (int64_t)dc[DC_AFF_NEED] + (int64_t)dc[DC_AFF_NEED] / 4,
-               (int64_t)dc[DC_SLOT_NEED] + (int64_t)dc[DC_SLOT_NEED] / 4);
+               (int64_t)dc[DC_SLOT_NEED] + (int64_t)dc[DC_SLOT_NEED] / 4,
+               (int64_t)dc[DC_PAIR_NEED] + (int64_t)dc[DC_PAIR_NEED] / 4);
     reset_count_stage(G);
     launch_delta(make_delta_args(G, W), G->c4_slots, s);
     launch_combine(2, G->sig.as<unsigned long long>(), G->state.as<long long>(), G->vout.as<long long>(), G->k,
@@ -1021,7 +1070,7 @@ std::vector<uint64_t> pass_signature(gc_graph* G, const PassPlan& L, const Count
                              (uint64_t)A.c4_maxlow, (uint64_t)A.slots, (uint64_t)A.tri_cap, (uint64_t)A.e_max,
                              (uint64_t)G->arena_cap, (uint64_t)L.in_bytes, (uint64_t)G->k, (uint64_t)G->N,
                              (uint64_t)G->bits, (uint64_t)L.delta, (uint64_t)G->ae_cap, (uint64_t)G->slot_cap,
-                             (uint64_t)G->ce.cap};
+                             (uint64_t)G->ce.cap, (uint64_t)G->pair_cap};
   const DevBuf* bufs[] = {&G->off, &G->len, &G->cap, &G->col, &G->top, &G->gid, &G->ext2int, &G->state, &G->vout,
                           &G->sig, &G->ctr, &G->bstats, &G->bin, &G->keys, &G->keys_alt, &G->dirA, &G->dirA_alt,
                           &G->dirD, &G->dirD_alt, &G->dirR, &G->dirR_alt, &G->a_beg, &G->na, &G->r_beg, &G->nr,
@@ -1029,7 +1078,8 @@ std::vector<uint64_t> pass_signature(gc_graph* G, const PassPlan& L, const Count
                           &G->sort_tmp, &G->scan_tmp, &G->roff, &G->rcol, &G->rrow, &G->rlow, &G->dver, &G->t,
                           &G->tp, &G->vpos, &G->level, &G->rlist, &G->rlen, &G->lists, &G->c4_dense, &G->c4_touch,
                           &G->c4_cur, &G->c4_blk, &G->c4_keys, &G->c4_keys_alt, &G->tri_scratch, &G->Tv, &G->dTs,
-                          &G->sbt, &G->ce, &G->ae, &G->ae_alt, &G->slot_list, &G->dctr};
+                          &G->sbt, &G->ce, &G->ae, &G->ae_alt, &G->slot_list, &G->dctr, &G->c4_nch, &G->c4_side,
+                          &G->c4_off, &G->pair_edge, &G->pair_len, &G->pair_off};
   for (const DevBuf* b : bufs) v.push_back((uint64_t)(uintptr_t)b->p);
   v.push_back((uint64_t)(uintptr_t)G->pin);
   v.push_back((uint64_t)(uintptr_t)G->pout);
@@ -1095,21 +1145,11 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
     if (L.radius >= 2 && wide) L.radius = -1;
   }
   // edge-local pass: one batch per graph and an exact radius; forced by the
-  // option, or per batch-size decade the faster of the two kinds measured so
-  // far (each tried once, then the other one again every 16th pass)
+  // option, or (autotune) the kind with the smaller expected time
+  const int bucket = (int)std::min<double>(15.0, std::floor(2.0 * std::log10((double)L.total + 1.0)));
   if (L.nv == 2 && G->opt.radius != 1) {
-    if (G->opt.delta > 0) {
-      L.delta = true;
-    } else if (G->opt.delta == 0 && G->opt.autotune && tune_idx < 0) {
-      const int64_t* n = G->mode_n[decade];
-      const double* ms = G->mode_ms[decade];
-      if (n[0] == 0) L.delta = false;
-      else if (n[1] == 0) L.delta = true;
-      else {
-        L.delta = ms[1] < ms[0];
-        if (G->decade_passes[decade] % 16 == 15) L.delta = !L.delta;
-      }
-    }
+    if (G->opt.delta > 0) L.delta = true;
+    else if (G->opt.delta == 0 && G->opt.autotune && tune_idx < 0) L.delta = choose_delta(G, bucket, L.total);
   }
   const bool timed_run = timed || (G->opt.autotune && tune_idx >= 0);
 
@@ -1270,11 +1310,16 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
   const double ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
   if (L.nv == 2 && retries == 0) {
     const int m = L.delta ? 1 : 0;
-    int64_t& cnt = G->mode_n[decade][m];
-    double& avg = G->mode_ms[decade][m];
+    int64_t& cnt = G->mode_n[bucket][m];
+    double& avg = G->mode_ms[bucket][m];
+    double& sz = G->mode_sz[bucket][m];
     avg = cnt == 0 ? ms : 0.75 * avg + 0.25 * ms;
+    sz = cnt == 0 ? (double)L.total : 0.75 * sz + 0.25 * (double)L.total;
     ++cnt;
-    ++G->decade_passes[decade];
+    if (!L.delta) {
+      G->region_ms_all = G->region_n_all == 0 ? ms : 0.75 * G->region_ms_all + 0.25 * ms;
+      ++G->region_n_all;
+    }
   }
   if (stats) {
     const int nst = seq ? nb : 1;

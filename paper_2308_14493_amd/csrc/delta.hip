@@ -26,7 +26,8 @@
 //   K4          per changed edge e = (u, v): pairs {w, x} of common
 //               neighbours S(e) joined by an edge;
 //   C4          per changed edge: paths s - a - b - o closing the cycle with
-//               e = (s, o), walked from the side with fewer wedges.
+//               e = (s, o), each pair (s, a) walking the shorter of N(a),
+//               N(o) and searching the other.
 #include "gc_kernels.h"
 
 namespace {
@@ -347,107 +348,160 @@ __global__ void k_delta_tv(DeltaArgs D, const unsigned long long* __restrict__ k
 }
 
 // ------------------------------------------------------------- 4-cycles
-// One workgroup per changed edge e = (s, o) at a time: the neighbours of o
-// are marked (with the nibble of (o, b)) in the workgroup's dense slot; the
-// wedges s - a - b with a != o, b != s closing on a marked b are the
-// 4-cycles s - a - b - o through e.  s is the end whose neighbours have the
-// smaller degree sum.  The rows of a in N(s) are walked by the waves 64
-// entries of N(s) at a time, their rows concatenated over the lanes.
+// Through a changed edge e = (s, o) run the 4-cycles s - a - b - o with
+// a in N(s) - {o}, b in N(a) & N(o) - {s}.  Per pair (s, a) the shorter of
+// N(a) and N(o) is walked and each entry searched in the other row, so a hub
+// on either side costs at most the other side's degree; s is the end with
+// the smaller sum over its neighbours a of min(d_a, d_o).  The work is
+// balanced over the whole chip: every pair (e, a) gets its walk length, a
+// scan places the walked entries of all pairs in one index space, and each
+// lane takes entries of that space (a hub pair is spread over many waves).
+
+// per changed edge: the end to walk from and its number of pairs
+__global__ void k_delta_c4_plan(DeltaArgs D) {
+  const int64_t ne = min(ctr(D.dc, DC_EDGES), D.ce_cap);
+  const unsigned long long idmask = (1ull << D.bits) - 1ull;
+  const int l = lane_id();
+  const int64_t w0 = gtid() >> 6, ws = gstride() >> 6;
+  for (int64_t i = w0; i < D.ce_cap; i += ws) {
+    if (i >= ne) {
+      if (l == 0) { D.c4_nch[i] = 0; D.c4_side[i] = 0; }
+      continue;
+    }
+    const unsigned long long K = D.ce[i] & DIR_KEY_MASK;
+    const uint32_t u = (uint32_t)(K >> D.bits), v = (uint32_t)(K & idmask);
+    const int64_t du = D.P.len[u], dv = D.P.len[v];
+    int64_t cu = 0, cv = 0;
+    const uint32_t* ru = D.P.col + D.P.off[u];
+    const uint32_t* rv = D.P.col + D.P.off[v];
+    for (int64_t k = l; k < du; k += 64) cu += min((int64_t)D.P.len[ru[k] & GC_ID], dv);
+    for (int64_t k = l; k < dv; k += 64) cv += min((int64_t)D.P.len[rv[k] & GC_ID], du);
+    cu = wave_sum64(cu);
+    cv = wave_sum64(cv);
+    if (l == 0) {
+      const bool from_u = cu <= cv;
+      D.c4_side[i] = from_u ? 0 : 1;
+      D.c4_nch[i] = (int32_t)(from_u ? du : dv);
+    }
+  }
+}
+
+// per pair (e, a): its position and its walk length min(d_a, d_o)
+__global__ void k_delta_c4_pairs(DeltaArgs D) {
+  const int64_t ne = min(ctr(D.dc, DC_EDGES), D.ce_cap);
+  const int64_t npairs = D.c4_off[D.ce_cap];
+  if (gtid() == 0 && npairs > D.pair_cap) {
+    atomicAdd(&D.bstats[BS_RETRY], 1ull);
+    atomicMax(&D.dc[DC_PAIR_NEED], (unsigned long long)npairs);
+  }
+  if (npairs > D.pair_cap) return;
+  const unsigned long long idmask = (1ull << D.bits) - 1ull;
+  const int l = lane_id();
+  const int64_t w0 = gtid() >> 6, ws = gstride() >> 6;
+  for (int64_t i = w0; i < ne; i += ws) {
+    const unsigned long long K = D.ce[i] & DIR_KEY_MASK;
+    const uint32_t u = (uint32_t)(K >> D.bits), v = (uint32_t)(K & idmask);
+    const uint32_t s = D.c4_side[i] ? v : u, o = s == u ? v : u;
+    const uint32_t* srow = D.P.col + D.P.off[s];
+    const int32_t sl = D.P.len[s], ol = D.P.len[o];
+    const int64_t base = D.c4_off[i];
+    for (int32_t k = l; k < sl; k += 64) {
+      const uint32_t a = srow[k] & GC_ID;
+      D.pair_edge[base + k] = (int32_t)i;
+      D.pair_len[base + k] = a == o ? 0 : min(D.P.len[a], ol);
+    }
+  }
+}
+
 __global__ __launch_bounds__(TPB) void k_delta_c4(DeltaArgs D) {
   if (D.bstats[BS_RETRY]) return;
-  constexpr int NW = TPB / 64;
-  __shared__ int64_t item_s;
-  __shared__ int64_t side_s[2];
-  __shared__ int32_t pre_s[NW][65];
-  __shared__ uint32_t aid_s[NW][64];
-  const int64_t ne = min(ctr(D.dc, DC_EDGES), D.ce_cap);
-  unsigned long long* mark = D.slot_mark + (int64_t)blockIdx.x * D.N;
+  const int64_t npairs = D.c4_off[D.ce_cap];
+  const int64_t total = D.pair_off[npairs];
   const unsigned long long idmask = (1ull << D.bits) - 1ull;
-  const int wv = threadIdx.x >> 6, l = lane_id();
   int64_t acc = 0;
   int cur_g = -1;
-  while (true) {
-    __syncthreads();
-    if (threadIdx.x == 0) { item_s = (int64_t)atomicAdd(&D.dc[DC_QC4], 1ull); side_s[0] = 0; side_s[1] = 0; }
-    __syncthreads();
-    const int64_t it = item_s;
-    if (it >= ne) break;
-    const unsigned long long ek = D.ce[it];
+  // a lane walks entries f = first, first + stride, ... of the index space;
+  // p tracks the pair holding f (pair_off[p] <= f < pair_off[p + 1])
+  const int64_t stride = gstride();
+  int64_t f = gtid();
+  int64_t p = 0;
+  if (f < total) {
+    int64_t lo = 0, hi = npairs;
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (D.pair_off[mid] <= f) lo = mid; else hi = mid;
+    }
+    p = lo;
+  }
+  for (; f < total; f += stride) {
+    while (D.pair_off[p + 1] <= f) {
+      // long jumps (stride > a pair) search; short ones step
+      if (D.pair_off[min(p + 8, npairs)] <= f) {
+        int64_t a0 = p + 8, b0 = npairs;
+        while (b0 - a0 > 1) {
+          const int64_t mid = (a0 + b0) >> 1;
+          if (D.pair_off[mid] <= f) a0 = mid; else b0 = mid;
+        }
+        p = a0;
+      } else {
+        ++p;
+      }
+    }
+    const int32_t i = D.pair_edge[p];
+    const unsigned long long ek = D.ce[i];
     const unsigned long long K = ek & DIR_KEY_MASK;
     const uint32_t fe = (uint32_t)(ek >> DIR_MASK_SHIFT) & 3u;
     const uint32_t u = (uint32_t)(K >> D.bits), v = (uint32_t)(K & idmask);
-    const int g = D.gid[u];
-    if (g != cur_g) {
-      if (cur_g >= 0) add_sig(D, cur_g, SG_C4, acc);
-      acc = 0;
-      cur_g = g;
-    }
-    // wedge counts from each end
-    for (int q = 0; q < 2; ++q) {
-      const uint32_t r = q ? v : u;
-      const uint32_t* row = D.P.col + D.P.off[r];
-      const int32_t L = D.P.len[r];
-      int64_t sum = 0;
-      for (int32_t k = threadIdx.x; k < L; k += blockDim.x) sum += D.P.len[row[k] & GC_ID];
-      sum = wave_sum64(sum);
-      if (l == 0) atomicAdd((unsigned long long*)&side_s[q], (unsigned long long)sum);
-    }
-    __syncthreads();
-    const uint32_t s = side_s[0] <= side_s[1] ? u : v, o = s == u ? v : u;
+    const uint32_t s = D.c4_side[i] ? v : u, o = s == u ? v : u;
+    const int64_t k = p - D.c4_off[i];
+    const uint32_t eaj = D.P.col[D.P.off[s] + k], a = eaj & GC_ID;
+    const int32_t q = (int32_t)(f - D.pair_off[p]);
     const uint32_t* orow = D.P.col + D.P.off[o];
-    const int32_t ol = D.P.len[o];
-    for (int32_t k = threadIdx.x; k < ol; k += blockDim.x) {
-      const uint32_t eb = orow[k];
-      mark[eb & GC_ID] = 0x100ull | nib(eb);
+    const uint32_t* arow = D.P.col + D.P.off[a];
+    const int32_t ol = D.P.len[o], al = D.P.len[a];
+    uint32_t b, fab = 0, fob = 0;
+    bool hit;
+    if (al <= ol) {  // walk N(a), search N(o)
+      const uint32_t eab = arow[q];
+      b = eab & GC_ID;
+      fab = nib(eab);
+      const int32_t x = lower_bound_id(orow, ol, b);
+      hit = x < ol && (orow[x] & GC_ID) == b;
+      if (hit) fob = nib(orow[x]);
+    } else {         // walk N(o), search N(a)
+      const uint32_t eob = orow[q];
+      b = eob & GC_ID;
+      fob = nib(eob);
+      const int32_t x = lower_bound_id(arow, al, b);
+      hit = x < al && (arow[x] & GC_ID) == b;
+      if (hit) fab = nib(arow[x]);
     }
-    __syncthreads();
-    const uint32_t* srow = D.P.col + D.P.off[s];
-    const int32_t sl = D.P.len[s];
-    for (int32_t c0 = wv * 64; c0 < sl; c0 += NW * 64) {
-      // 64 entries a of N(s) per wave, their rows dealt over the lanes
-      const int32_t k = c0 + l;
-      uint32_t ea = 0, a = 0;
-      int32_t len = 0;
-      if (k < sl) {
-        ea = srow[k];
-        a = ea & GC_ID;
-        if (a != o) len = D.P.len[a];
-      }
-      int32_t incl = wave_incl_scan32(len);
-      pre_s[wv][l + 1] = incl;
-      if (l == 0) pre_s[wv][0] = 0;
-      aid_s[wv][l] = ea;
-      wave_sync();
-      const int32_t total = __shfl(incl, 63);
-      for (int32_t f0 = 0; f0 < total; f0 += 64) {
-        const int32_t f = f0 + l;
-        if (f < total) {
-          // segment j with pre[j] <= f < pre[j + 1]
-          int32_t lo = 0, hi = 64;
-          while (hi - lo > 1) {
-            const int32_t mid = (lo + hi) >> 1;
-            if (pre_s[wv][mid] <= f) lo = mid; else hi = mid;
-          }
-          const uint32_t eaj = aid_s[wv][lo], aj = eaj & GC_ID;
-          const uint32_t eab = D.P.col[D.P.off[aj] + (f - pre_s[wv][lo])];
-          const uint32_t b = eab & GC_ID;
-          if (b != s) {
-            const unsigned long long mb = mark[b];
-            if (mb) {
-              const uint32_t fsa = nib(eaj), fab = nib(eab), fob = (uint32_t)mb & 15u;
-              const bool skip = (fsa && pkey(s, aj, D.bits) < K) || (fab && pkey(aj, b, D.bits) < K) ||
-                                (fob && pkey(o, b, D.bits) < K);
-              if (!skip) acc += delta_of(fe | fsa | fab | fob);
-            }
-          }
+    if (hit && b != s) {
+      const uint32_t fsa = nib(eaj);
+      const bool skip = (fsa && pkey(s, a, D.bits) < K) || (fab && pkey(a, b, D.bits) < K) ||
+                        (fob && pkey(o, b, D.bits) < K);
+      if (!skip) {
+        const int g = D.gid[u];
+        if (g != cur_g) {
+          if (cur_g >= 0 && acc) atomicAdd(&D.sig[SIG_IDX(cur_g, 1, SG_C4)], (unsigned long long)acc);
+          acc = 0;
+          cur_g = g;
         }
+        acc += delta_of(fe | fsa | fab | fob);
       }
-      wave_sync();
     }
-    __syncthreads();
-    for (int32_t k = threadIdx.x; k < ol; k += blockDim.x) mark[orow[k] & GC_ID] = 0ull;
   }
-  if (cur_g >= 0) add_sig(D, cur_g, SG_C4, acc);
+  // one atomic per wave when its lanes hold sums of one graph
+  const uint64_t has = __ballot(cur_g >= 0 && acc != 0);
+  if (has) {
+    const int gl = __shfl(cur_g, __builtin_ctzll(has));
+    if (__ballot(acc != 0 && cur_g != gl) == 0) {
+      const int64_t t = wave_sum64(acc);
+      if (lane_id() == 0 && t) atomicAdd(&D.sig[SIG_IDX(gl, 1, SG_C4)], (unsigned long long)t);
+    } else if (acc) {
+      atomicAdd(&D.sig[SIG_IDX(cur_g, 1, SG_C4)], (unsigned long long)acc);
+    }
+  }
 }
 
 // ------------------------------------------------ T(v) in the region path
@@ -502,14 +556,21 @@ void launch_delta(const DeltaArgs& D, int slots, hipStream_t s) {
   hipLaunchKernelGGL(k_delta_edges, dim3(1024), dim3(TPB), 0, s, D);
   hipLaunchKernelGGL(k_delta_vertex, dim3(2048), dim3(TPB), 0, s, D);
   hipLaunchKernelGGL(k_delta_s2, dim3(2048), dim3(TPB), 0, s, D);
+  // every kernel that can find a buffer too small (and raise BS_RETRY)
+  // runs before the first one that moves T(v) or clears scratch
   hipLaunchKernelGGL(k_delta_tri, dim3(slots), dim3(TPB), 0, s, D);
   hipLaunchKernelGGL(k_delta_aff_changed, dim3(1024), dim3(TPB), 0, s, D);
+  hipLaunchKernelGGL(k_delta_c4_plan, dim3(1024), dim3(TPB), 0, s, D);
+  exclusive_scan_i32_to_i64(D.c4_nch, D.c4_off, D.ce_cap, D.scan_tmp, s);
+  fill_u32((uint32_t*)D.pair_len, 0u, D.pair_cap, s);
+  hipLaunchKernelGGL(k_delta_c4_pairs, dim3(1024), dim3(TPB), 0, s, D);
+  exclusive_scan_i32_to_i64(D.pair_len, D.pair_off, D.pair_cap, D.scan_tmp, s);
   unsigned long long* sorted =
       radix_sort_u64(D.ae, D.ae_alt, D.sort_tmp, D.ae_cap, D.dc + DC_AFF_TOTAL, 2 * D.bits, s);
   hipLaunchKernelGGL(k_delta_aff, dim3(4096), dim3(TPB), 0, s, D, (const unsigned long long*)sorted);
   hipLaunchKernelGGL(k_delta_vertex2, dim3(1024), dim3(TPB), 0, s, D);
   hipLaunchKernelGGL(k_delta_tv, dim3(1024), dim3(TPB), 0, s, D, (const unsigned long long*)sorted);
-  hipLaunchKernelGGL(k_delta_c4, dim3(slots), dim3(TPB), 0, s, D);
+  hipLaunchKernelGGL(k_delta_c4, dim3(4096), dim3(TPB), 0, s, D);
 }
 
 void launch_tv_region(int nv, const RegionDev& R, const int32_t* rlist, const unsigned long long* c,

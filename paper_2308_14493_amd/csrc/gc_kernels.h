@@ -162,7 +162,7 @@ void launch_combine(int nv, const unsigned long long* sig, long long* state, lon
 
 // capi.cpp: thread-local error text read by gc_last_error()
 // delta.hip: edge-local update of the Sigma terms of a one-batch pass
-enum { DC_EDGES = 0, DC_AFF, DC_AFF_TOTAL, DC_AFF_NEED, DC_SLOT_NEED, DC_QTRI, DC_QC4, DC_COUNT };
+enum { DC_EDGES = 0, DC_AFF, DC_AFF_TOTAL, DC_AFF_NEED, DC_SLOT_NEED, DC_QTRI, DC_QC4, DC_PAIR_NEED, DC_COUNT };
 struct DeltaArgs {
   PoolDev P;                          // union view left by the tombstone merge
   int64_t N;
@@ -189,6 +189,14 @@ struct DeltaArgs {
   uint32_t* slot_list;                // [slots][slot_cap] common neighbours of a changed edge
   int64_t slot_cap;
   unsigned long long* dc;             // [DC_COUNT] counters of the stage
+  int32_t* c4_nch;                    // [ce_cap] pairs (e, a) per changed edge: degree of the end walked from
+  int32_t* c4_side;                   // [ce_cap] 0: walk from u, 1: from v
+  int64_t* c4_off;                    // [ce_cap + 1] exclusive scan of c4_nch
+  int32_t* pair_edge;                 // [pair_cap] changed edge of each pair
+  int32_t* pair_len;                  // [pair_cap] walk length of each pair
+  int64_t* pair_off;                  // [pair_cap + 1] exclusive scan of pair_len
+  int64_t pair_cap;
+  void* scan_tmp;                     // scan scratch for max(ce_cap, pair_cap) + 1 entries
 };
 // launches the delta stage with `slots` workgroups for the per-edge kernels
 void launch_delta(const DeltaArgs& D, int slots, hipStream_t s);

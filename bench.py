@@ -296,6 +296,65 @@ def run_served(args, n, s, d, sampler):
             "results_equal_to_plain": all(r["results_equal_to_plain"] for r in runs.values()), "rates": runs}
 
 
+def run_protocol(args):
+    """The paper's experimental protocol (Sec. 5) on stand-ins of its four
+    graphs (Table 1 sizes): the edges in a seeded order, the graph built from
+    all but the last ones, then insert-only batches of 10 and of 100 (Alg. 1)
+    and fully dynamic batches of 100 with the p = 0.7 labelling (Alg. 2),
+    each stream on a fresh copy of that graph.  Reported per stream: the
+    cumulative time after every batch (Figs. 2-4), and the baseline that
+    recounts the whole graph after every batch (the oracle's static recount,
+    timed once on the final graph of the stream, times the batch count)."""
+    from graphgen import protocol
+    import paper_2308_14493_amd as pkg
+    import torch
+    from oracle import native
+    pkg.load()
+    torch.cuda.init()
+    out = {}
+    for name in args.protocol_graphs.split(","):
+        t0 = time.time()
+        n, s, d = protocol.table1_standin(name, 11)
+        s, d = protocol.edge_order(s, d, 12)
+        K = args.protocol_batches
+        res = {"n": n, "m": int(s.size)}
+        streams = {
+            "insert_10": (s.size - 10 * K, lambda m0: protocol.incremental_batches(s, d, 10, start=m0, count=K)),
+            "insert_100": (s.size - 100 * K, lambda m0: protocol.incremental_batches(s, d, 100, start=m0, count=K)),
+            "dynamic_100": (s.size - int(100 * K / 0.7 * 1.1), lambda m0: protocol.fully_dynamic_batches(
+                s[m0:], d[m0:], 100, 0.7, 13, count=K, lag=1000)),
+        }
+        log("protocol %s: n=%d m=%d drawn in %.1fs" % (name, n, s.size, time.time() - t0))
+        for key, (m0, make) in streams.items():
+            batches = make(m0)
+            g = pkg.Graph(n, s[:m0], d[:m0], radius=args.radius, delta=args.delta)
+            cum, tot = [], 0.0
+            lat = []
+            for b in batches:
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                g.apply_batch(*b)
+                dt = time.perf_counter() - t1
+                tot += dt
+                lat.append(dt * 1e3)
+                cum.append(tot)
+            ga, gb = g.edges()
+            g.close()
+            t1 = time.perf_counter()
+            native.static_counts(n, ga, gb)
+            rec = time.perf_counter() - t1
+            step = max(1, len(cum) // 10)
+            res[key] = {"m_start": int(m0), "batches": len(batches), "gpu_total_s": tot,
+                        "gpu_p50_ms": percentile(lat, 50), "gpu_p99_ms": percentile(lat, 99),
+                        "baseline_recount_s": rec, "baseline_total_s": rec * len(batches),
+                        "speedup_vs_baseline": rec * len(batches) / max(tot, 1e-9),
+                        "cumulative_s": {str(i + 1): round(cum[i], 4) for i in range(step - 1, len(cum), step)}}
+            log("protocol %s %s: %d batches, GPU %.3fs (p50 %.2f ms), baseline %.1fs per batch" % (
+                name, key, len(batches), tot, res[key]["gpu_p50_ms"], rec))
+        out[name] = res
+    return out
+
+
 def form_line(args, metric, value, ms, extra):
     out = {"metric": metric, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -324,7 +383,9 @@ def main():
     ap.add_argument("--no-host-rerun", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--form", choices=["plain", "batched", "served"], default="plain",
+    ap.add_argument("--protocol-graphs", default="WikiVote,WikiTalk,Pokec,LiveJournal")
+    ap.add_argument("--protocol-batches", type=int, default=200)
+    ap.add_argument("--form", choices=["plain", "batched", "served", "protocol"], default="plain",
                     help="plain (default; the served and batched forms ride along as extra keys), or one of the "
                          "other forms alone")
     ap.add_argument("--graphs", type=int, default=256)
@@ -344,6 +405,17 @@ def main():
     from graphgen import workloads as wl
     import paper_2308_14493_amd as pkg
 
+    if args.form == "protocol":
+        pr = run_protocol(args)
+        tot = sum(v[k]["batches"] * (100 if k.endswith("100") else 10) for v in pr.values()
+                  for k in ("insert_10", "insert_100", "dynamic_100"))
+        secs = sum(v[k]["gpu_total_s"] for v in pr.values() for k in ("insert_10", "insert_100", "dynamic_100"))
+        return form_line(args, "updates/sec, the paper's protocol (Sec. 5) on Table 1 stand-ins", tot / secs,
+                         secs * 1e3 / max(1, args.protocol_batches), {
+                             "config": {"workload": "stand-ins of %s; insert-only batches of 10 and 100, fully "
+                                                    "dynamic batches of 100 (p = 0.7), %d batches each"
+                                                    % (args.protocol_graphs, args.protocol_batches),
+                                        "form": "protocol"}, "protocol": pr})
     if args.form == "batched":
         b = run_batched(args)
         return form_line(args, "updates/sec, %d-graph pool, one batch per graph" % b["graphs"], b["updates_per_s"],

@@ -11,3 +11,4 @@ from .generators import (  # noqa: F401
     multi_graph_workload, raw_noise_batch, poisson_arrivals,
     log_uniform_sizes, chung_lu_weights,
 )
+from . import protocol  # noqa: F401,E402

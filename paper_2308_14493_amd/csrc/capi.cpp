@@ -238,6 +238,9 @@ struct gc_graph {
   // set while the resident graph holds a pass's union view (from the merge
   // until the purge has been read back): a failure then leaves it unusable
   bool in_pass = false;
+  // the pass being settled has no deletions (its purge only clears flags)
+  bool pass_insert_only = false;
+  int64_t pass_max_dirA = 0;
 
   void* pin = nullptr;
   size_t pin_cap = 0;
@@ -491,6 +494,16 @@ void note_maxima(gc_graph* G) {
   G->seen_maxlow = std::max<int64_t>(G->seen_maxlow, (int64_t)G->out_ctr()[C_MAXLOW]);
 }
 
+// The purge of the current pass: rows drop the entries absent from the last
+// version and lose every flag (a pass without deletions only clears flags).
+void enqueue_purge(gc_graph* G, BatchWork& W, int64_t max_touched, int nv) {
+  const unsigned long long* skip = G->bstats.as<unsigned long long>() + BS_RETRY;
+  if (G->pass_insert_only)
+    launch_purge_insert_only(G->pd(), W, max_touched, G->pass_max_dirA, G->bits, skip, G->stream);
+  else
+    launch_purge(G->pd(), W, max_touched, G->bits, 1u << (GC_VSHIFT + nv - 1), skip, G->scan_tmp.p, G->stream);
+}
+
 // After a pass whose results are in the pinned buffer: while a kernel asked
 // for more scratch (the combine and the purge then changed nothing), grow it
 // from the observed degrees and count again.  Returns the attempts made.
@@ -506,8 +519,7 @@ int settle_retries(gc_graph* G, int nv, int radius, long long* state_d, BatchWor
     CountArgs A = make_count_args(G, nv, dense_min, fresh);
     enqueue_count(G, nv, radius, state_d, W, A, false, tv);
     if (purge)
-      launch_purge(G->pd(), W, max_touched, G->bits, 1u << (GC_VSHIFT + nv - 1),
-                   G->bstats.as<unsigned long long>() + BS_RETRY, G->scan_tmp.p, G->stream);
+      enqueue_purge(G, W, max_touched, nv);
     enqueue_readback(G, state_d);
     G->sync();
   }
@@ -1013,15 +1025,24 @@ void enqueue_pass(gc_graph* G, const PassPlan& L, BatchIn& B, BatchWork& W, cons
     if (err) raise(GC_EINVAL, "batch has %llu vertex ids outside the graph", err);
   }
   unsigned long long* sA = radix_sort_u64(S.dirA, S.dirA_alt, G->sort_tmp.p, 2 * L.cap_i, ctr + C_DIRA, 2 * G->bits, s);
-  unsigned long long* sD = radix_sort_u64(S.dirD, S.dirD_alt, G->sort_tmp.p, 2 * L.cap_d, ctr + C_DIRD, 2 * G->bits, s);
-  unsigned long long* sR = radix_sort_u64(S.dirR, S.dirR_alt, G->sort_tmp.p, 2 * L.cap_d, ctr + C_DIRR, 2 * G->bits, s);
+  // a pass without deletions (insert-only batches, Alg. 1) has empty flag and
+  // removal lists: their sorts, marks and flag kernels are skipped
+  const bool ins_only = L.ndl == 0;
+  unsigned long long* sD = ins_only ? W.dirD
+                                    : radix_sort_u64(S.dirD, S.dirD_alt, G->sort_tmp.p, 2 * L.cap_d, ctr + C_DIRD,
+                                                     2 * G->bits, s);
+  unsigned long long* sR = ins_only ? W.dirR
+                                    : radix_sort_u64(S.dirR, S.dirR_alt, G->sort_tmp.p, 2 * L.cap_d, ctr + C_DIRR,
+                                                     2 * G->bits, s);
   if (sA != W.dirA || sD != W.dirD || sR != W.dirR) raise(GC_EDEVICE, "sorted merge lists not where expected");
   G->in_pass = true;  // from here on the resident graph holds the union view until the purge
   launch_mark_rows(sA, 2 * L.cap_i, ctr, C_DIRA, G->bits, W.a_beg, W.na, W.mark, W.touched, W.tix, s);
-  launch_mark_rows(sD, 2 * L.cap_d, ctr, C_DIRD, G->bits, nullptr, nullptr, W.mark, W.touched, W.tix, s);
-  launch_mark_rows(sR, 2 * L.cap_d, ctr, C_DIRR, G->bits, W.r_beg, W.nr, W.mark, W.touched, W.tix, s);
+  if (!ins_only) {
+    launch_mark_rows(sD, 2 * L.cap_d, ctr, C_DIRD, G->bits, nullptr, nullptr, W.mark, W.touched, W.tix, s);
+    launch_mark_rows(sR, 2 * L.cap_d, ctr, C_DIRR, G->bits, W.r_beg, W.nr, W.mark, W.touched, W.tix, s);
+  }
   launch_merge(P, W, L.max_touched, 2 * L.cap_i, G->bits, G->opt.slack, bst, G->scan_tmp.p, s);
-  launch_flag_rows(P, W, 2 * L.cap_d, G->bits, bst, s);
+  if (!ins_only) launch_flag_rows(P, W, 2 * L.cap_d, G->bits, bst, s);
   if (L.delta) {
     if (timed) HIPCHK(hipEventRecord(G->ev[1], s));
     launch_delta(make_delta_args(G, W), G->c4_slots, s);
@@ -1032,7 +1053,7 @@ void enqueue_pass(gc_graph* G, const PassPlan& L, BatchIn& B, BatchWork& W, cons
     enqueue_count(G, L.nv, L.radius, G->state.as<long long>(), W, make_count_args(G, L.nv, L.dense_min, false), timed,
                   true);
   }
-  launch_purge(P, W, L.max_touched, G->bits, 1u << (GC_VSHIFT + L.nv - 1), bst + BS_RETRY, G->scan_tmp.p, s);
+  enqueue_purge(G, W, L.max_touched, L.nv);
   if (timed) HIPCHK(hipEventRecord(G->ev[8], s));
   enqueue_readback(G, G->state.as<long long>());
 }
@@ -1053,8 +1074,7 @@ int settle_delta(gc_graph* G, const PassPlan& L, BatchWork& W) {
     launch_delta(make_delta_args(G, W), G->c4_slots, s);
     launch_combine(2, G->sig.as<unsigned long long>(), G->state.as<long long>(), G->vout.as<long long>(), G->k,
                    G->bstats.as<unsigned long long>(), s);
-    launch_purge(G->pd(), W, L.max_touched, G->bits, 1u << (GC_VSHIFT + 1), G->bstats.as<unsigned long long>() + BS_RETRY,
-                 G->scan_tmp.p, s);
+    enqueue_purge(G, W, L.max_touched, 2);
     enqueue_readback(G, G->state.as<long long>());
     G->sync();
   }
@@ -1070,7 +1090,7 @@ std::vector<uint64_t> pass_signature(gc_graph* G, const PassPlan& L, const Count
                              (uint64_t)A.c4_maxlow, (uint64_t)A.slots, (uint64_t)A.tri_cap, (uint64_t)A.e_max,
                              (uint64_t)G->arena_cap, (uint64_t)L.in_bytes, (uint64_t)G->k, (uint64_t)G->N,
                              (uint64_t)G->bits, (uint64_t)L.delta, (uint64_t)G->ae_cap, (uint64_t)G->slot_cap,
-                             (uint64_t)G->ce.cap, (uint64_t)G->pair_cap};
+                             (uint64_t)G->ce.cap, (uint64_t)G->pair_cap, (uint64_t)(L.ndl == 0)};
   const DevBuf* bufs[] = {&G->off, &G->len, &G->cap, &G->col, &G->top, &G->gid, &G->ext2int, &G->state, &G->vout,
                           &G->sig, &G->ctr, &G->bstats, &G->bin, &G->keys, &G->keys_alt, &G->dirA, &G->dirA_alt,
                           &G->dirD, &G->dirD_alt, &G->dirR, &G->dirR_alt, &G->a_beg, &G->na, &G->r_beg, &G->nr,
@@ -1213,6 +1233,8 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
     B.iu = d_ids; B.iv = d_ids + L.cap_i; B.du = d_ids + 2 * L.cap_i; B.dv = d_ids + 2 * L.cap_i + L.cap_d;
   }
   int retries = 0;
+  G->pass_insert_only = L.ndl == 0;
+  G->pass_max_dirA = 2 * L.cap_i;
   const Staging S = handle_staging(G);
   BatchWork W = make_work(G, S);
   W.dirA = radix_sort_result(S.dirA, S.dirA_alt, 2 * L.cap_i, 2 * G->bits);
@@ -1448,6 +1470,8 @@ void apply_noalloc(gc_graph* G, const int32_t* iu, const int32_t* iv, int64_t n_
   W.dirA = radix_sort_result(S.dirA, S.dirA_alt, 2 * L.cap_i, 2 * G->bits);
   W.dirD = radix_sort_result(S.dirD, S.dirD_alt, 2 * L.cap_d, 2 * G->bits);
   W.dirR = radix_sort_result(S.dirR, S.dirR_alt, 2 * L.cap_d, 2 * G->bits);
+  G->pass_insert_only = L.ndl == 0;
+  G->pass_max_dirA = 2 * L.cap_i;
   const bool timed = stats != nullptr;
   try {
     enqueue_pass(G, L, B, W, S, timed, false);

@@ -90,6 +90,10 @@ void launch_flag_rows(const PoolDev& P, const BatchWork& W, int64_t max_dirD, in
 // as it was before a one-batch pass whose counting did not complete
 void launch_purge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int bits, uint32_t fin,
                   const unsigned long long* skip, void* scan_tmp, hipStream_t s, bool undo = false);
+// the purge of a pass without deletions: the flags of the new entries are
+// cleared in place (max_dirA bounds their count)
+void launch_purge_insert_only(const PoolDev& P, const BatchWork& W, int64_t max_touched, int64_t max_dirA, int bits,
+                              const unsigned long long* skip, hipStream_t s);
 void launch_region(const PoolDev& P, const BatchWork& W, int radius, int32_t* level, int32_t* rlist, int32_t* rlen,
                    hipStream_t s);
 void launch_region_fill(const PoolDev& P, const RegionDev& R, const BatchWork& W, int radius, const int32_t* level,

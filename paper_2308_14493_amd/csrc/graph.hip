@@ -958,6 +958,32 @@ void launch_purge(const PoolDev& P, const BatchWork& W, int64_t max_touched, int
                      W.r_beg, W.nr, W.mark, W.tix, rm_n, skip);
 }
 
+// Purge of a pass without deletions (Alg. 1's insert-only batches): nothing
+// leaves the rows, so the new entries (listed in dirA) only lose their flags
+// in place; no row is copied or compacted.
+__global__ void k_clear_new(PoolDev P, const unsigned long long* __restrict__ dirA, const unsigned long long* c,
+                            int bits, const unsigned long long* skip) {
+  if (*skip) return;
+  const int64_t n = ctr(c, C_DIRA);
+  const uint64_t idmask = (1ull << bits) - 1ull;
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    const unsigned long long key = dirA[i] & DIR_KEY_MASK;
+    const uint32_t r = (uint32_t)(key >> bits), id = (uint32_t)(key & idmask);
+    uint32_t* row = P.col + P.off[r];
+    const int32_t p = lower_bound_id(row, P.len[r], id);
+    if (p < P.len[r] && (row[p] & GC_ID) == id) row[p] = id;
+  }
+}
+
+void launch_purge_insert_only(const PoolDev& P, const BatchWork& W, int64_t max_touched, int64_t max_dirA, int bits,
+                              const unsigned long long* skip, hipStream_t s) {
+  if (max_touched == 0) return;
+  if (max_dirA > 0)
+    hipLaunchKernelGGL(k_clear_new, dim3(grid_for(max_dirA)), dim3(TPB), 0, s, P, W.dirA, W.c, bits, skip);
+  hipLaunchKernelGGL(k_purge_commit, dim3(grid_for(max_touched)), dim3(TPB), 0, s, P, W.touched, W.c, W.a_beg, W.na,
+                     W.r_beg, W.nr, W.mark, W.tix, (const int32_t*)W.nr, skip);
+}
+
 void launch_region(const PoolDev& P, const BatchWork& W, int radius, int32_t* level, int32_t* rlist, int32_t* rlen,
                    hipStream_t s) {
   const int64_t N = P.N;

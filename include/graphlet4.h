@@ -27,7 +27,8 @@
  *     leaves the graph unchanged;
  *   - inserting an existing edge or deleting a missing one has no effect;
  *   - an id outside [0, n) rejects the whole batch (GC_EINVAL) and leaves
- *     the graph and its counts unchanged.
+ *     the graph and its counts unchanged (after gc_add_vertices /
+ *     gc_remove_vertices: an id not issued, or of a removed vertex).
  *
  * Conventions.  Every function returns GC_OK (0) or a negative gc_status,
  * and gc_last_error() describes the cause (thread-local string).  On error
@@ -120,6 +121,12 @@ typedef struct {
    * batch-size decade the faster kind as measured (with autotune), 1:
    * always, -1: never. */
   int32_t delta;
+  /* Vertex ids reserved for gc_add_vertices (single-graph handles): the
+   * resident rows and per-vertex arrays are sized for this many ids, so
+   * that adding vertices up to it costs no device work.  0 (default) or
+   * any value <= n: n.  Beyond it, gc_add_vertices rebuilds the graph over
+   * a larger id space. */
+  int64_t vertex_capacity;
 } gc_options;
 
 typedef struct {
@@ -246,7 +253,31 @@ int gc_get_counts3(const gc_graph* g, int32_t graph, int64_t hi[4], uint64_t lo[
  * Sec. 4.1); does not change the maintained counts.  For checking. */
 int gc_recount_exact(gc_graph* g, int32_t graph, int64_t hi[11], uint64_t lo[11]);
 
-/* Number of graphs, vertices and edges. */
+/* Vertex insertion and deletion (Sec. 3: vertex operations reduce to edge
+ * operations, a vertex losing its incident edges before it leaves V).
+ * Single-graph handles only; the vertex count n of the disconnected
+ * classes is that of the live vertices.
+ *
+ * gc_add_vertices adds `count` isolated vertices with the next unused ids
+ * first_id .. first_id + count - 1 (ids are never reused; the first call
+ * after gc_graph_init on n vertices returns first_id = n) and returns the
+ * counts (they change through n only).  Within gc_options.vertex_capacity
+ * this is host bookkeeping; beyond it the edges are read back and the graph
+ * is built again over max(needed, 2 x capacity) ids (external ids and
+ * counts kept; a failure there leaves the handle unusable).  count = 0 only
+ * reports first_id.  GC_EINVAL if ids would reach 2^28.
+ *
+ * gc_remove_vertices deletes every edge at the `count` listed vertices as
+ * one batch (the rules, statistics and failure behaviour of gc_apply_batch;
+ * stats may be NULL) and then takes the vertices out of V: n falls by
+ * count, and their ids are rejected by every later batch (GC_EINVAL, as
+ * for ids out of range; the device-array variants report them like other
+ * invalid ids).  GC_EINVAL, with nothing changed, for an id not yet issued,
+ * already removed or listed twice. */
+int gc_add_vertices(gc_graph* g, int64_t count, int64_t* first_id, int64_t counts[11]);
+int gc_remove_vertices(gc_graph* g, const int32_t* ids, int64_t count, int64_t counts[11], gc_batch_stats* stats);
+
+/* Number of graphs, vertices (live ones) and edges. */
 int gc_graph_info(const gc_graph* g, int32_t* num_graphs, int32_t graph, int64_t* n, int64_t* m);
 
 /* Copies the edges of graph `graph` (each once, external ids) into host

@@ -125,3 +125,26 @@ def keys_to_pairs(E_keys):
     E_keys = np.asarray(E_keys, dtype=np.uint64)
     return ((E_keys >> np.uint64(32)).astype(np.int32),
             (E_keys & np.uint64(0xFFFFFFFF)).astype(np.int32))
+
+
+# Vertex operations (Sec. 3): they reduce to edge operations -- a vertex that
+# leaves V first loses every incident edge.  The vertex set is then the live
+# ids; the counts of (V, E) depend on |V| and on E only, so they are those of
+# the graph relabelled onto 0 .. |V| - 1.
+
+def remove_vertices(E: set, live: set, ids):
+    """Deletes every edge at `ids`, then the vertices; E and live in place."""
+    ids = {int(x) for x in ids}
+    if not ids <= live:
+        raise BatchRejected("vertex not in V")
+    for e in [e for e in E if e[0] in ids or e[1] in ids]:
+        E.discard(e)
+    live -= ids
+
+
+def compact(E: set, live: set):
+    """(n, src, dst) of (live, E) relabelled onto 0 .. |live| - 1 in id order."""
+    import numpy as np
+    rank = {v: i for i, v in enumerate(sorted(live))}
+    pairs = sorted((rank[u], rank[v]) for u, v in E)
+    return (len(live), np.array([u for u, _ in pairs], np.int32), np.array([v for _, v in pairs], np.int32))

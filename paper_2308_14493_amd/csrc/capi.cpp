@@ -62,7 +62,7 @@ struct DevBuf {
   }
   // grow-only; contents are not preserved
   void ensure(size_t bytes) {
-    if (bytes == 0) bytes = 16;
+    bytes = std::max<size_t>(bytes, 16);  // as the no-allocation checks assume
     if (bytes <= cap) return;
     release();
     size_t nb = std::max(bytes, cap + cap / 2);
@@ -181,7 +181,13 @@ struct gc_graph {
   bool broken = false;
 
   int32_t k = 1;
-  std::vector<int64_t> gbase, gn;
+  // per graph: first internal id, id capacity (the internal id space), ids
+  // issued so far, live vertices (the n of the counts)
+  std::vector<int64_t> gbase, gn, gi, gl;
+  // vertices taken out of V (single-graph handles): their ids stay invalid
+  std::vector<uint8_t> dead_h;
+  DevBuf dead_d;
+  bool any_dead = false;
   int64_t N = 0;
   int bits = 1;
 
@@ -215,6 +221,7 @@ struct gc_graph {
   int64_t region_n_all = 0;
   int64_t c4_cur_low = 0;
   int32_t c4_slots = 0, tri_slots = 0;
+  int64_t c4_dense_n = 0;            // vertex count the hub counters are sized for
   int64_t tri_cap = 0;
   int64_t e_alloc = 0;               // entries of the region arrays
   int64_t seen_maxdp = 0, seen_maxlow = 0;  // largest out-degree / lower degree counted so far
@@ -356,13 +363,16 @@ void size_count_scratch(gc_graph* G, int nv, int64_t entries) {
   const int64_t per = N * (int64_t)(sizeof(unsigned long long) + sizeof(int32_t));
   int64_t slots = std::max<int64_t>(1, std::min<int64_t>(256, ((int64_t)16 << 30) / std::max<int64_t>(per, 1)));
   slots = std::min<int64_t>(slots, std::max<int64_t>(1, N));
-  if (slots > G->c4_slots) {
+  // (re)sized when more slots fit or the id space changed: slot j of vertex
+  // v is word j * N + v
+  if (slots > G->c4_slots || N != G->c4_dense_n) {
     G->c4_dense.release();
     G->c4_touch.release();
     G->c4_dense.ensure((size_t)(slots * N) * sizeof(unsigned long long));
     G->c4_touch.ensure((size_t)(slots * N) * sizeof(int32_t));
     fill_u64(G->c4_dense.as<unsigned long long>(), 0ull, slots * N, G->stream);
     G->c4_slots = (int32_t)slots;
+    G->c4_dense_n = N;
   }
   if (G->seen_maxlow > G->c4_cur_low) G->c4_cur_low = G->seen_maxlow + G->seen_maxlow / 4 + 64;
   G->c4_cur_low = std::max<int64_t>(G->c4_cur_low, 64);
@@ -383,36 +393,38 @@ void size_count_scratch(gc_graph* G, int nv, int64_t entries) {
   }
 }
 
-// True when size_count_scratch(G, nv, entries) would neither allocate nor
-// change a size.
-bool count_scratch_fits(const gc_graph* G, int nv, int64_t entries) {
+// nullptr when size_count_scratch(G, nv, entries) would neither allocate nor
+// change a size; else the part that would.
+const char* count_scratch_short(const gc_graph* G, int nv, int64_t entries) {
   const int64_t N = G->N;
   auto has = [](const DevBuf& b, size_t bytes) { return b.p != nullptr && std::max<size_t>(bytes, 16) <= b.cap; };
   if (!has(G->roff, (N + 1) * sizeof(int64_t)) || !has(G->c4_keys, N * sizeof(unsigned long long)) ||
       !has(G->c4_keys_alt, N * sizeof(unsigned long long)))
-    return false;
-  if (!has(G->sort_tmp, radix_sort_tmp_bytes(N) + 64) || !has(G->scan_tmp, scan_tmp_bytes(N + 1) + 64)) return false;
-  if (entries > G->e_alloc) return false;
+    return "per-vertex region arrays";
+  if (!has(G->sort_tmp, radix_sort_tmp_bytes(N) + 64) || !has(G->scan_tmp, scan_tmp_bytes(N + 1) + 64))
+    return "sort and scan temporaries";
+  if (entries > G->e_alloc) return "region view (entries)";
   const int64_t E = G->e_alloc;
   if (!has(G->rcol, E * sizeof(uint32_t)) || !has(G->rrow, E * sizeof(int32_t)) ||
       !has(G->t, E * sizeof(unsigned long long)) || !has(G->vpos, E * sizeof(int32_t)))
-    return false;
-  if (nv > 2 && !has(G->tp, 2 * E * sizeof(unsigned long long))) return false;
-  if (!has(G->dver, (size_t)N * GC_NV_MAX * sizeof(int32_t))) return false;
+    return "region view (arrays)";
+  if (nv > 2 && !has(G->tp, 2 * E * sizeof(unsigned long long))) return "multi-version triangle counts";
+  if (!has(G->dver, (size_t)N * GC_NV_MAX * sizeof(int32_t))) return "per-version degrees";
   const int64_t per = N * (int64_t)(sizeof(unsigned long long) + sizeof(int32_t));
   int64_t slots = std::max<int64_t>(1, std::min<int64_t>(256, ((int64_t)16 << 30) / std::max<int64_t>(per, 1)));
   slots = std::min<int64_t>(slots, std::max<int64_t>(1, N));
-  if (slots > G->c4_slots) return false;
-  if (G->seen_maxlow > G->c4_cur_low || G->c4_cur_low < 64) return false;
-  if (!has(G->c4_cur, (size_t)(G->c4_slots * 2 * G->c4_cur_low) * sizeof(int64_t))) return false;
-  if (!has(G->c4_blk, (size_t)(N / c4_block_ids() + 2) * sizeof(int32_t))) return false;
+  if (slots > G->c4_slots || N != G->c4_dense_n) return "hub counters";
+  if (G->seen_maxlow > G->c4_cur_low || G->c4_cur_low < 64) return "hub cursors (lower degree)";
+  if (!has(G->c4_cur, (size_t)(G->c4_slots * 2 * G->c4_cur_low) * sizeof(int64_t))) return "hub cursors";
+  if (!has(G->c4_blk, (size_t)(N / c4_block_ids() + 2) * sizeof(int32_t))) return "4-cycle blocks";
   if (G->seen_maxdp > tri_lds_max(nv)) {
-    if (G->seen_maxdp > 32767) return false;
+    if (G->seen_maxdp > 32767) return "triangle scratch (out-degree above 32767)";
     const int64_t cap = std::max<int64_t>(G->tri_cap, std::min<int64_t>(32767, G->seen_maxdp + G->seen_maxdp / 8 + 16));
-    if (cap != G->tri_cap) return false;
-    if ((size_t)(tri_scratch_words64(nv, cap) * 256) * sizeof(unsigned long long) > G->tri_scratch.cap) return false;
+    if (cap != G->tri_cap) return "triangle scratch (out-degree)";
+    if ((size_t)(tri_scratch_words64(nv, cap) * 256) * sizeof(unsigned long long) > G->tri_scratch.cap)
+      return "triangle scratch";
   }
-  return true;
+  return nullptr;
 }
 
 CountArgs make_count_args(gc_graph* G, int nv, int64_t dense_min, bool fresh) {
@@ -696,6 +708,8 @@ void build(gc_graph* G, int32_t k, const int64_t* n, const int32_t* const* src, 
   G->k = k;
   G->gbase.assign(k, 0);
   G->gn.assign(n, n + k);
+  G->gi.assign(n, n + k);
+  G->gl.assign(n, n + k);
   int64_t N = 0, M = 0, maxn = 1;
   for (int g = 0; g < k; ++g) {
     if (n[g] < 1) raise(GC_EINVAL, "graph %d: n must be >= 1", g);
@@ -876,18 +890,19 @@ void fill_stats(gc_graph* G, gc_batch_stats* st, const unsigned long long* hb, c
 }
 
 // Host-side check of one batch's arrays (sizes, pointers, ids in [0, n)).
-void check_batch(const gc_batch_desc& b, int64_t n, int which) {
+void check_batch(const gc_batch_desc& b, int64_t n, int which, const uint8_t* dead = nullptr) {
   if (b.n_ins < 0 || b.n_del < 0) raise(GC_EINVAL, "batch %d: negative size", which);
   if ((b.n_ins && (!b.ins_src || !b.ins_dst)) || (b.n_del && (!b.del_src || !b.del_dst)))
     raise(GC_EINVAL, "batch %d: null array", which);
+  auto bad = [&](int32_t x) { return x < 0 || x >= n || (dead && dead[x]); };
   for (int64_t i = 0; i < b.n_ins; ++i)
-    if (b.ins_src[i] < 0 || b.ins_src[i] >= n || b.ins_dst[i] < 0 || b.ins_dst[i] >= n)
-      raise(GC_EINVAL, "batch %d: insertion %lld has a vertex id outside [0, %lld)", which, (long long)i,
-            (long long)n);
+    if (bad(b.ins_src[i]) || bad(b.ins_dst[i]))
+      raise(GC_EINVAL, "batch %d: insertion %lld has a vertex id outside [0, %lld) or of a removed vertex", which,
+            (long long)i, (long long)n);
   for (int64_t i = 0; i < b.n_del; ++i)
-    if (b.del_src[i] < 0 || b.del_src[i] >= n || b.del_dst[i] < 0 || b.del_dst[i] >= n)
-      raise(GC_EINVAL, "batch %d: deletion %lld has a vertex id outside [0, %lld)", which, (long long)i,
-            (long long)n);
+    if (bad(b.del_src[i]) || bad(b.del_dst[i]))
+      raise(GC_EINVAL, "batch %d: deletion %lld has a vertex id outside [0, %lld) or of a removed vertex", which,
+            (long long)i, (long long)n);
 }
 
 int64_t pow2_at_least(int64_t x) {
@@ -1099,7 +1114,7 @@ std::vector<uint64_t> pass_signature(gc_graph* G, const PassPlan& L, const Count
                           &G->tp, &G->vpos, &G->level, &G->rlist, &G->rlen, &G->lists, &G->c4_dense, &G->c4_touch,
                           &G->c4_cur, &G->c4_blk, &G->c4_keys, &G->c4_keys_alt, &G->tri_scratch, &G->Tv, &G->dTs,
                           &G->sbt, &G->ce, &G->ae, &G->ae_alt, &G->slot_list, &G->dctr, &G->c4_nch, &G->c4_side,
-                          &G->c4_off, &G->pair_edge, &G->pair_len, &G->pair_off};
+                          &G->c4_off, &G->pair_edge, &G->pair_len, &G->pair_off, &G->dead_d};
   for (const DevBuf* b : bufs) v.push_back((uint64_t)(uintptr_t)b->p);
   v.push_back((uint64_t)(uintptr_t)G->pin);
   v.push_back((uint64_t)(uintptr_t)G->pout);
@@ -1130,8 +1145,8 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
   L.nv = L.npass > 1 ? 4 : 2;
   std::vector<int64_t> ins_seg(L.nseg + 1, 0), del_seg(L.nseg + 1, 0);
   for (int q = 0; q < L.nseg; ++q) {
-    const int64_t n = G->gn[seq ? 0 : q];
-    if (!dev) check_batch(b[q], n, q);
+    const int64_t n = G->gi[seq ? 0 : q];
+    if (!dev) check_batch(b[q], n, q, G->any_dead ? G->dead_h.data() : nullptr);
     else if (b[q].n_ins < 0 || b[q].n_del < 0) raise(GC_EINVAL, "negative batch size");
     ins_seg[q + 1] = ins_seg[q] + b[q].n_ins;
     del_seg[q + 1] = del_seg[q] + b[q].n_del;
@@ -1202,7 +1217,7 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
   std::memcpy(tab, ins_seg.data(), (L.nseg + 1) * 8);
   std::memcpy(tab + L.nseg + 1, del_seg.data(), (L.nseg + 1) * 8);
   std::memcpy(tab + 2 * (L.nseg + 1), G->gbase.data(), k * 8);
-  std::memcpy(tab + 2 * (L.nseg + 1) + k, G->gn.data(), k * 8);
+  std::memcpy(tab + 2 * (L.nseg + 1) + k, G->gi.data(), k * 8);
   G->bin.ensure(L.in_bytes + 64);
   BatchIn B;
   B.n_ins = L.ni;
@@ -1214,6 +1229,7 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
   B.del_seg = B.ins_seg + L.nseg + 1;
   B.gbase = B.ins_seg + 2 * (L.nseg + 1);
   B.gn = B.gbase + k;
+  B.dead = G->any_dead ? G->dead_d.as<uint8_t>() : nullptr;
   if (dev) {
     B.iu = b[0].ins_src; B.iv = b[0].ins_dst; B.du = b[0].del_src; B.dv = b[0].del_dst;
   } else {
@@ -1297,7 +1313,7 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
     raise(GC_EDEVICE, "device-side inconsistency (arena overflow %llu, errors %llu, inexact totals %lld)",
           hb[BS_ARENA_OVF], hb[BS_ERR], cerr);
   }
-  for (int g = 0; g < k; ++g) st[g * ST_STRIDE + ST_N] = G->gn[g];
+  for (int g = 0; g < k; ++g) st[g * ST_STRIDE + ST_N] = G->gl[g];
   G->hstate = st;
   for (int j = 0; j < L.npass; ++j)
     G->entries += 2 * ((int64_t)hb[PB_IDX(j, PB_EFF_INS)] - (int64_t)hb[PB_IDX(j, PB_EFF_DEL)]);
@@ -1306,9 +1322,9 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
   std::vector<uint32_t> ovf(nout, 0);
   for (int o = 0; o < nout; ++o) {
     long long* so = seq ? &vo[(size_t)o * ST_STRIDE] : &G->hstate[(size_t)o * ST_STRIDE];
-    so[ST_N] = G->gn[seq ? 0 : o];
+    so[ST_N] = G->gl[seq ? 0 : o];
     i128 I[11];
-    finalize(so, G->gn[seq ? 0 : o], I);
+    finalize(so, G->gl[seq ? 0 : o], I);
     int64_t tmp[11];
     to_int64(I, counts ? counts[o] : tmp, &ovf[o]);
   }
@@ -1444,17 +1460,21 @@ void apply_noalloc(gc_graph* G, const int32_t* iu, const int32_t* iv, int64_t n_
   const size_t sort_need = radix_sort_tmp_bytes(std::max<int64_t>(std::max(L.cap_t, 2 * std::max(L.cap_i, L.cap_d)), G->N)) + 64;
   const size_t scan_need = scan_tmp_bytes(std::max<int64_t>(L.max_touched, G->N) + 1) + 64;
   const int64_t arena_need = (int64_t)((1.0 + G->opt.slack) * (double)L.union_bound) + 8 * L.max_touched + 1024;
-  if (G->sort_tmp.cap < sort_need || G->scan_tmp.cap < scan_need ||
-      G->scratch.cap < (size_t)std::max<int64_t>(L.union_bound, 4) * 4 || !count_scratch_fits(G, 2, L.union_bound) ||
-      G->arena_cap - G->arena_top < arena_need)
+  const char* short_of = G->sort_tmp.cap < sort_need                                          ? "sort temporaries"
+                         : G->scan_tmp.cap < scan_need                                        ? "scan temporaries"
+                         : G->scratch.cap < (size_t)std::max<int64_t>(L.union_bound, 4) * 4 ? "merge scratch"
+                         : count_scratch_short(G, 2, L.union_bound)                           ? count_scratch_short(G, 2, L.union_bound)
+                         : G->arena_cap - G->arena_top < arena_need                           ? "resident rows"
+                                                                                              : nullptr;
+  if (short_of)
     raise(GC_ENOMEM,
-          "the handle's buffers are not sized for this batch (graph of %lld entries plus %lld insertions); "
+          "the handle's buffers (%s) are not sized for this batch (graph of %lld entries plus %lld insertions); "
           "one gc_apply_batch_dev call of this size grows them",
-          (long long)G->entries, (long long)n_ins);
+          short_of, (long long)G->entries, (long long)n_ins);
 
   // the input table (segment bounds, graph base and size) by a kernel: no host staging
   carve_staging(base, L.cap_i, L.cap_d, L.in_bytes, &S);
-  Table6 tb = {{0, n_ins, 0, n_del, G->gbase[0], G->gn[0]}};
+  Table6 tb = {{0, n_ins, 0, n_del, G->gbase[0], G->gi[0]}};
   hipLaunchKernelGGL(k_put_table, dim3(1), dim3(64), 0, s, (int64_t*)S.bin, tb);
   BatchIn B;
   B.n_ins = n_ins;
@@ -1465,6 +1485,7 @@ void apply_noalloc(gc_graph* G, const int32_t* iu, const int32_t* iv, int64_t n_
   B.del_seg = B.ins_seg + 2;
   B.gbase = B.ins_seg + 4;
   B.gn = B.ins_seg + 5;
+  B.dead = G->any_dead ? G->dead_d.as<uint8_t>() : nullptr;
   B.iu = iu; B.iv = iv; B.du = du; B.dv = dv;
   BatchWork W = make_work(G, S);
   W.dirA = radix_sort_result(S.dirA, S.dirA_alt, 2 * L.cap_i, 2 * G->bits);
@@ -1506,10 +1527,10 @@ void apply_noalloc(gc_graph* G, const int32_t* iu, const int32_t* iv, int64_t n_
           hb[BS_ARENA_OVF], hb[BS_ERR], st[ST_ERR]);
   }
   std::memcpy(G->hstate.data(), st, ST_STRIDE * sizeof(long long));
-  G->hstate[ST_N] = G->gn[0];
+  G->hstate[ST_N] = G->gl[0];
   G->entries += 2 * ((int64_t)hb[PB_IDX(0, PB_EFF_INS)] - (int64_t)hb[PB_IDX(0, PB_EFF_DEL)]);
   i128 I[11];
-  finalize(G->hstate.data(), G->gn[0], I);
+  finalize(G->hstate.data(), G->gl[0], I);
   int64_t tmp[11];
   uint32_t ovf = 0;
   to_int64(I, counts ? counts : tmp, &ovf);
@@ -1521,6 +1542,166 @@ void apply_noalloc(gc_graph* G, const int32_t* iu, const int32_t* iv, int64_t n_
     stats->c4_dense_min = L.dense_min;
     stats->whole_graph = L.radius < 0;
     stats->retries = 0;
+  }
+}
+
+// Edges of graph `graph`, each once, external ids, into host arrays of
+// capacity capn; returns the edge count.
+int64_t export_edges(gc_graph* g, int32_t graph, int32_t* src, int32_t* dst, int64_t capn) {
+  HIPCHK(hipSetDevice(g->device));
+  const int64_t m = g->hstate[graph * ST_STRIDE + ST_M];
+  if (capn < m) raise(GC_EINVAL, "capacity %lld below the edge count %lld", (long long)capn, (long long)m);
+  if (m > 0 && (!src || !dst)) raise(GC_EINVAL, "NULL output arrays");
+  hipStream_t s = g->stream;
+  const int64_t N = g->N;
+  DevBuf cnt, pre, es, ed, gb;
+  cnt.ensure(N * 4);
+  pre.ensure((N + 1) * 8);
+  const int64_t total = g->entries / 2;
+  es.ensure(std::max<int64_t>(total, 1) * 4);
+  ed.ensure(std::max<int64_t>(total, 1) * 4);
+  gb.ensure(g->k * 8);
+  HIPCHK(hipMemcpyAsync(gb.p, g->gbase.data(), g->k * 8, hipMemcpyHostToDevice, s));
+  PoolDev P = g->pd();
+  launch_upper_count(P, cnt.as<int32_t>(), s);
+  g->scan_tmp.ensure(scan_tmp_bytes(N + 1) + 64);
+  exclusive_scan_i32_to_i64(cnt.as<int32_t>(), pre.as<int64_t>(), N, g->scan_tmp.p, s);
+  launch_export(P, g->int2ext.as<int32_t>(), gb.as<int64_t>(), pre.as<int64_t>(), es.as<int32_t>(),
+                ed.as<int32_t>(), s);
+  int64_t range[2];
+  HIPCHK(hipMemcpyAsync(&range[0], pre.as<int64_t>() + g->gbase[graph], 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&range[1], pre.as<int64_t>() + g->gbase[graph] + g->gn[graph], 8, hipMemcpyDeviceToHost, s));
+  g->sync();
+  if (range[1] - range[0] != m) raise(GC_EDEVICE, "edge count mismatch (%lld vs %lld)",
+                                      (long long)(range[1] - range[0]), (long long)m);
+  if (m) {
+    HIPCHK(hipMemcpyAsync(src, es.as<int32_t>() + range[0], m * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(dst, ed.as<int32_t>() + range[0], m * 4, hipMemcpyDeviceToHost, s));
+  }
+  g->sync();
+  return m;
+}
+
+// Removed vertices on the device: a byte per id of the internal id space,
+// allocated and cleared on the first removal.
+void mark_dead(gc_graph* G, const int32_t* ids_dev, const std::vector<int32_t>& ids) {
+  hipStream_t s = G->stream;
+  if (!G->any_dead) {
+    G->dead_h.assign(G->N, 0);
+    G->dead_d.ensure(G->N);
+    HIPCHK(hipMemsetAsync(G->dead_d.p, 0, G->N, s));
+  }
+  for (int32_t x : ids) G->dead_h[x] = 1;
+  launch_set_bytes(G->dead_d.as<uint8_t>(), ids_dev, (int64_t)ids.size(), 1, s);
+  G->sync();
+  G->any_dead = true;
+}
+
+// A larger id space for a single graph: its edges are read back and the
+// graph is built again over cap ids.  External ids, counts and removed
+// vertices are kept; captured passes are dropped (their buffers change).
+void regrow_ids(gc_graph* G, int64_t cap) {
+  if (cap >= GC_MAX_VERTICES) raise(GC_EINVAL, "vertex ids must stay below 2^28");
+  const int64_t m = G->hstate[ST_M];
+  std::vector<int32_t> src(std::max<int64_t>(m, 1)), dst(std::max<int64_t>(m, 1));
+  export_edges(G, 0, src.data(), dst.data(), m);
+  const int64_t gi = G->gi[0], gl = G->gl[0];
+  G->sync();
+  G->drop_graphs();
+  try {
+    const int32_t* ps = src.data();
+    const int32_t* pd = dst.data();
+    build(G, 1, &cap, &ps, &pd, &m);
+    G->gi[0] = gi;
+    G->gl[0] = gl;
+    G->hstate[ST_N] = gl;
+    if (G->any_dead) {
+      G->dead_h.resize(cap, 0);
+      G->dead_d.ensure(cap);
+      HIPCHK(hipMemcpyAsync(G->dead_d.p, G->dead_h.data(), cap, hipMemcpyHostToDevice, G->stream));
+      G->sync();
+    }
+  } catch (...) {
+    G->broken = true;
+    throw;
+  }
+}
+
+void counts_now(gc_graph* G, int64_t counts[11]) {
+  if (!counts) return;
+  i128 I[11];
+  finalize(G->hstate.data(), G->gl[0], I);
+  to_int64(I, counts, nullptr);
+}
+
+void add_vertices(gc_graph* G, int64_t count, int64_t* first_id) {
+  if (G->broken) raise(GC_ESTATE, "handle unusable after an earlier device failure");
+  if (G->k != 1) raise(GC_EINVAL, "handle holds %d graphs: vertices are added to single-graph handles", G->k);
+  if (count < 0) raise(GC_EINVAL, "negative vertex count");
+  HIPCHK(hipSetDevice(G->device));
+  const int64_t need = G->gi[0] + count;
+  if (need >= GC_MAX_VERTICES) raise(GC_EINVAL, "vertex ids must stay below 2^28");
+  if (need > G->gn[0]) regrow_ids(G, std::min<int64_t>(GC_MAX_VERTICES - 1, std::max(need, 2 * G->gn[0])));
+  if (first_id) *first_id = G->gi[0];
+  G->gi[0] = need;
+  G->gl[0] += count;
+  G->hstate[ST_N] = G->gl[0];
+}
+
+// Deletes every edge at the given vertices in one batch (through the
+// ordinary batch path: counts, statistics and failure rules of a batch),
+// then takes them out of V.
+void remove_vertices(gc_graph* G, const int32_t* ids, int64_t count, int64_t counts[11], gc_batch_stats* stats) {
+  if (G->broken) raise(GC_ESTATE, "handle unusable after an earlier device failure");
+  if (G->k != 1) raise(GC_EINVAL, "handle holds %d graphs: vertices are removed from single-graph handles", G->k);
+  if (count < 0 || (count > 0 && !ids)) raise(GC_EINVAL, "bad vertex list");
+  std::vector<int32_t> v(ids, ids + count);
+  std::sort(v.begin(), v.end());
+  for (int64_t i = 0; i < count; ++i) {
+    if (v[i] < 0 || v[i] >= G->gi[0]) raise(GC_EINVAL, "vertex id %d outside [0, %lld)", v[i], (long long)G->gi[0]);
+    if (G->any_dead && G->dead_h[v[i]]) raise(GC_EINVAL, "vertex %d was removed already", v[i]);
+    if (i && v[i] == v[i - 1]) raise(GC_EINVAL, "vertex %d listed twice", v[i]);
+  }
+  HIPCHK(hipSetDevice(G->device));
+  hipStream_t s = G->stream;
+  // the incident edges, read from the resident rows
+  DevBuf did, dlen, dpre, du, dv;
+  std::vector<int32_t> len(std::max<int64_t>(count, 1));
+  std::vector<int64_t> pre(count + 1, 0);
+  did.ensure(std::max<int64_t>(count, 1) * 4);
+  dlen.ensure(std::max<int64_t>(count, 1) * 4);
+  if (count) HIPCHK(hipMemcpyAsync(did.p, v.data(), count * 4, hipMemcpyHostToDevice, s));
+  launch_row_len(G->pd(), did.as<int32_t>(), count, dlen.as<int32_t>(), s);
+  if (count) HIPCHK(hipMemcpyAsync(len.data(), dlen.p, count * 4, hipMemcpyDeviceToHost, s));
+  G->sync();
+  for (int64_t i = 0; i < count; ++i) pre[i + 1] = pre[i] + len[i];
+  const int64_t e = pre[count];
+  std::vector<int32_t> eu(std::max<int64_t>(e, 1)), ev(std::max<int64_t>(e, 1));
+  if (e) {
+    dpre.ensure((count + 1) * 8);
+    du.ensure(e * 4);
+    dv.ensure(e * 4);
+    HIPCHK(hipMemcpyAsync(dpre.p, pre.data(), (count + 1) * 8, hipMemcpyHostToDevice, s));
+    launch_row_gather(G->pd(), G->int2ext.as<int32_t>(), did.as<int32_t>(), count, dpre.as<int64_t>(),
+                      du.as<int32_t>(), dv.as<int32_t>(), s);
+    HIPCHK(hipMemcpyAsync(eu.data(), du.p, e * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(ev.data(), dv.p, e * 4, hipMemcpyDeviceToHost, s));
+    G->sync();
+  }
+  // an edge between two removed vertices is listed from both ends: the
+  // batch rules drop the repeat
+  gc_batch_desc b{nullptr, nullptr, 0, eu.data(), ev.data(), e};
+  apply(G, &b, 1, false, false, nullptr, stats);
+  if (count) mark_dead(G, did.as<int32_t>(), v);
+  G->gl[0] -= count;
+  G->hstate[ST_N] = G->gl[0];
+  counts_now(G, counts);
+  if (stats) {
+    // the batch's int64 overflow flags, now for the smaller vertex set
+    i128 I[11];
+    finalize(G->hstate.data(), G->gl[0], I);
+    int64_t tmp[11];
+    to_int64(I, tmp, &stats->overflow_mask);
   }
 }
 
@@ -1553,6 +1734,7 @@ int gc_options_default(gc_options* opt) {
   opt->autotune = 1;
   opt->graphs = 1;
   opt->delta = 0;
+  opt->vertex_capacity = 0;
   return GC_OK;
 }
 
@@ -1565,7 +1747,19 @@ int gc_pool_init(int32_t k, const int64_t* n, const int32_t* const* src, const i
     gc_graph* G = new gc_graph();
     try {
       setup_handle(G, opt);
-      build(G, k, n, src, dst, m);
+      // a single graph may reserve ids for vertices added later
+      std::vector<int64_t> ncap(n, n + k);
+      if (k == 1 && G->opt.vertex_capacity > n[0]) {
+        for (int64_t i = 0; i < m[0]; ++i)
+          if (src[0][i] < 0 || src[0][i] >= n[0] || dst[0][i] < 0 || dst[0][i] >= n[0])
+            raise(GC_EINVAL, "edge %lld has a vertex id outside [0, %lld)", (long long)i, (long long)n[0]);
+        ncap[0] = G->opt.vertex_capacity;
+      }
+      build(G, k, ncap.data(), src, dst, m);
+      for (int g = 0; g < k; ++g) {
+        G->gi[g] = G->gl[g] = n[g];
+        G->hstate[g * ST_STRIDE + ST_N] = n[g];
+      }
     } catch (...) {
       delete G;
       throw;
@@ -1573,7 +1767,7 @@ int gc_pool_init(int32_t k, const int64_t* n, const int32_t* const* src, const i
     if (counts)
       for (int g = 0; g < k; ++g) {
         i128 I[11];
-        finalize(&G->hstate[g * ST_STRIDE], G->gn[g], I);
+        finalize(&G->hstate[g * ST_STRIDE], G->gl[g], I);
         to_int64(I, counts[g], nullptr);
       }
     *out = G;
@@ -1630,7 +1824,8 @@ int gc_apply_batch_seq(gc_graph* g, const gc_batch_desc* batches, int32_t nb, in
     if (!g || (nb > 0 && !batches)) raise(GC_EINVAL, "NULL argument");
     if (g->k != 1) raise(GC_EINVAL, "handle holds %d graphs: gc_apply_batch_seq needs a single graph", g->k);
     if (nb < 0) raise(GC_EINVAL, "negative batch count");
-    for (int j = 0; j < nb; ++j) check_batch(batches[j], g->gn[0], j);  // all-or-nothing
+    for (int j = 0; j < nb; ++j)
+      check_batch(batches[j], g->gi[0], j, g->any_dead ? g->dead_h.data() : nullptr);  // all-or-nothing
     for (int j0 = 0; j0 < nb; j0 += GC_SEQ_MAX) {
       const int q = std::min(GC_SEQ_MAX, nb - j0);
       apply(g, batches + j0, q, false, q > 1, counts ? counts + j0 : nullptr, stats ? stats + j0 : nullptr);
@@ -1643,7 +1838,7 @@ int gc_get_counts(const gc_graph* g, int32_t graph, int64_t counts[11], uint32_t
     if (!g || !counts) raise(GC_EINVAL, "NULL argument");
     if (graph < 0 || graph >= g->k) raise(GC_EINVAL, "graph index out of range");
     i128 I[11];
-    finalize(&g->hstate[graph * ST_STRIDE], g->gn[graph], I);
+    finalize(&g->hstate[graph * ST_STRIDE], g->gl[graph], I);
     to_int64(I, counts, overflow_mask);
   });
 }
@@ -1653,7 +1848,7 @@ int gc_get_counts_exact(const gc_graph* g, int32_t graph, int64_t hi[11], uint64
     if (!g || !hi || !lo) raise(GC_EINVAL, "NULL argument");
     if (graph < 0 || graph >= g->k) raise(GC_EINVAL, "graph index out of range");
     i128 I[11];
-    finalize(&g->hstate[graph * ST_STRIDE], g->gn[graph], I);
+    finalize(&g->hstate[graph * ST_STRIDE], g->gl[graph], I);
     for (int c = 0; c < 11; ++c) { lo[c] = (uint64_t)I[c]; hi[c] = (int64_t)(I[c] >> 64); }
   });
 }
@@ -1663,7 +1858,7 @@ int gc_get_counts3(const gc_graph* g, int32_t graph, int64_t hi[4], uint64_t lo[
     if (!g || !hi || !lo) raise(GC_EINVAL, "NULL argument");
     if (graph < 0 || graph >= g->k) raise(GC_EINVAL, "graph index out of range");
     i128 I[4];
-    finalize3(&g->hstate[graph * ST_STRIDE], g->gn[graph], I);
+    finalize3(&g->hstate[graph * ST_STRIDE], g->gl[graph], I);
     for (int c = 0; c < 4; ++c) { lo[c] = (uint64_t)I[c]; hi[c] = (int64_t)(I[c] >> 64); }
   });
 }
@@ -1699,7 +1894,7 @@ int gc_recount_exact(gc_graph* g, int32_t graph, int64_t hi[11], uint64_t lo[11]
     }
     if (st[graph * ST_STRIDE + ST_ERR]) raise(GC_EDEVICE, "inexact totals in the recount");
     i128 I[11];
-    finalize(&st[graph * ST_STRIDE], g->gn[graph], I);
+    finalize(&st[graph * ST_STRIDE], g->gl[graph], I);
     for (int c = 0; c < 11; ++c) { lo[c] = (uint64_t)I[c]; hi[c] = (int64_t)(I[c] >> 64); }
   });
 }
@@ -1709,7 +1904,7 @@ int gc_graph_info(const gc_graph* g, int32_t* num_graphs, int32_t graph, int64_t
     if (!g) raise(GC_EINVAL, "NULL argument");
     if (num_graphs) *num_graphs = g->k;
     if (graph < 0 || graph >= g->k) raise(GC_EINVAL, "graph index out of range");
-    if (n) *n = g->gn[graph];
+    if (n) *n = g->gl[graph];
     if (m) *m = g->hstate[graph * ST_STRIDE + ST_M];
   });
 }
@@ -1718,38 +1913,22 @@ int gc_export_edges(gc_graph* g, int32_t graph, int32_t* src, int32_t* dst, int6
   return guard([&] {
     if (!g || !m_out) raise(GC_EINVAL, "NULL argument");
     if (graph < 0 || graph >= g->k) raise(GC_EINVAL, "graph index out of range");
-    HIPCHK(hipSetDevice(g->device));
-    const int64_t m = g->hstate[graph * ST_STRIDE + ST_M];
-    *m_out = m;
-    if (capn < m) raise(GC_EINVAL, "capacity %lld below the edge count %lld", (long long)capn, (long long)m);
-    if (m > 0 && (!src || !dst)) raise(GC_EINVAL, "NULL output arrays");
-    hipStream_t s = g->stream;
-    const int64_t N = g->N;
-    DevBuf cnt, pre, es, ed, gb;
-    cnt.ensure(N * 4);
-    pre.ensure((N + 1) * 8);
-    const int64_t total = g->entries / 2;
-    es.ensure(std::max<int64_t>(total, 1) * 4);
-    ed.ensure(std::max<int64_t>(total, 1) * 4);
-    gb.ensure(g->k * 8);
-    HIPCHK(hipMemcpyAsync(gb.p, g->gbase.data(), g->k * 8, hipMemcpyHostToDevice, s));
-    PoolDev P = g->pd();
-    launch_upper_count(P, cnt.as<int32_t>(), s);
-    g->scan_tmp.ensure(scan_tmp_bytes(N + 1) + 64);
-    exclusive_scan_i32_to_i64(cnt.as<int32_t>(), pre.as<int64_t>(), N, g->scan_tmp.p, s);
-    launch_export(P, g->int2ext.as<int32_t>(), gb.as<int64_t>(), pre.as<int64_t>(), es.as<int32_t>(),
-                  ed.as<int32_t>(), s);
-    int64_t range[2];
-    HIPCHK(hipMemcpyAsync(&range[0], pre.as<int64_t>() + g->gbase[graph], 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&range[1], pre.as<int64_t>() + g->gbase[graph] + g->gn[graph], 8, hipMemcpyDeviceToHost, s));
-    g->sync();
-    if (range[1] - range[0] != m) raise(GC_EDEVICE, "edge count mismatch (%lld vs %lld)",
-                                        (long long)(range[1] - range[0]), (long long)m);
-    if (m) {
-      HIPCHK(hipMemcpyAsync(src, es.as<int32_t>() + range[0], m * 4, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(dst, ed.as<int32_t>() + range[0], m * 4, hipMemcpyDeviceToHost, s));
-    }
-    g->sync();
+    *m_out = export_edges(g, graph, src, dst, capn);
+  });
+}
+
+int gc_add_vertices(gc_graph* g, int64_t count, int64_t* first_id, int64_t counts[11]) {
+  return guard([&] {
+    if (!g) raise(GC_EINVAL, "graph is NULL");
+    add_vertices(g, count, first_id);
+    counts_now(g, counts);
+  });
+}
+
+int gc_remove_vertices(gc_graph* g, const int32_t* ids, int64_t count, int64_t counts[11], gc_batch_stats* stats) {
+  return guard([&] {
+    if (!g) raise(GC_EINVAL, "graph is NULL");
+    remove_vertices(g, ids, count, counts, stats);
   });
 }
 
@@ -1780,7 +1959,7 @@ int gc_graph_footprint(int64_t n, const int32_t* src, const int32_t* dst, int64_
       max_deg = std::max<int64_t>(max_deg, deg[v]);
       max_out = std::max<int64_t>(max_out, out[v]);
     }
-    *bytes = gc_footprint_estimate(n, m, o.slack, max_deg, max_out);
+    *bytes = gc_footprint_estimate(std::max<int64_t>(n, o.vertex_capacity), m, o.slack, max_deg, max_out);
   });
 }
 

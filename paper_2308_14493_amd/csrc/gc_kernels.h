@@ -53,6 +53,7 @@ struct BatchIn {
   const int64_t* gn;       // [graphs] vertex count of each graph
   int32_t k;               // segments
   int32_t seq;
+  const uint8_t* dead;     // [N] 1 for a vertex taken out of its graph (nullptr: none)
 };
 
 struct BatchWork {
@@ -118,6 +119,13 @@ void launch_caps(const PoolDev& P, float slack, hipStream_t s);  // P.cap <- len
 void launch_all_flags(const PoolDev& P, uint32_t set, uint32_t keep, hipStream_t s);
 void launch_compact(const PoolDev& P, int64_t* noff, uint32_t* ncol, hipStream_t s);
 void launch_upper_count(const PoolDev& P, int32_t* cnt, hipStream_t s);
+// rows of k vertices of a single graph (external ids): lengths, then the
+// edges (x, neighbour) in external ids at the exclusive prefix pre
+void launch_row_len(const PoolDev& P, const int32_t* ids, int64_t k, int32_t* out, hipStream_t s);
+void launch_row_gather(const PoolDev& P, const int32_t* int2ext, const int32_t* ids, int64_t k, const int64_t* pre,
+                       int32_t* u, int32_t* v, hipStream_t s);
+// a[ids[i]] = val
+void launch_set_bytes(uint8_t* a, const int32_t* ids, int64_t k, uint8_t val, hipStream_t s);
 void launch_export(const PoolDev& P, const int32_t* int2ext, const int64_t* gbase, const int64_t* pre, int32_t* src,
                    int32_t* dst, hipStream_t s);
 

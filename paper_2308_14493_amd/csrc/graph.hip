@@ -48,7 +48,7 @@ __global__ void k_ingest_keys(PoolDev P, BatchIn B, int bits, unsigned long long
     while (hi - lo > 1) { int mid = (lo + hi) >> 1; if (seg[mid] <= j) lo = mid; else hi = mid; }
     const int g = B.seq ? 0 : lo, bj = B.seq ? lo : 0;
     const int64_t base = B.gbase[g], n = B.gn[g];
-    if (u < 0 || v < 0 || u >= n || v >= n) {
+    if (u < 0 || v < 0 || u >= n || v >= n || (B.dead && (B.dead[base + u] | B.dead[base + v]))) {
       atomicAdd(&bstats[PB_IDX(bj, PB_ERR)], 1ull);
       keys[i] = ~0ull;
       continue;
@@ -868,6 +868,31 @@ __global__ void k_export_edges(PoolDev P, const int32_t* __restrict__ int2ext, c
   }
 }
 
+// rows of given vertices of a single graph (external ids): their lengths,
+// then their edges (x, neighbour) in external ids, x's at pre[i]
+__global__ void k_row_len(PoolDev P, const int32_t* __restrict__ ids, int64_t k, int32_t* __restrict__ out) {
+  for (int64_t i = gtid(); i < k; i += gstride()) out[i] = P.len[P.ext2int[ids[i]]];
+}
+
+__global__ void k_row_gather(PoolDev P, const int32_t* __restrict__ int2ext, const int32_t* __restrict__ ids,
+                             int64_t k, const int64_t* __restrict__ pre, int32_t* __restrict__ u,
+                             int32_t* __restrict__ v) {
+  for (int64_t i = gwave(); i < k; i += gwaves()) {
+    const int32_t x = ids[i], r = P.ext2int[x];
+    const uint32_t* row = P.col + P.off[r];
+    const int32_t L = P.len[r];
+    const int64_t b = pre[i];
+    for (int32_t j = lane_id(); j < L; j += 64) {
+      u[b + j] = x;
+      v[b + j] = int2ext[row[j] & GC_ID];
+    }
+  }
+}
+
+__global__ void k_set_bytes(uint8_t* __restrict__ a, const int32_t* __restrict__ ids, int64_t k, uint8_t val) {
+  for (int64_t i = gtid(); i < k; i += gstride()) a[ids[i]] = val;
+}
+
 __global__ void k_upper_count(PoolDev P, int32_t* __restrict__ cnt) {
   for (int64_t v = gwave(); v < P.N; v += gwaves()) {
     const uint32_t* row = P.col + P.off[v];
@@ -1067,6 +1092,18 @@ void launch_compact(const PoolDev& P, int64_t* noff, uint32_t* ncol, hipStream_t
 }
 void launch_upper_count(const PoolDev& P, int32_t* cnt, hipStream_t s) {
   hipLaunchKernelGGL(k_upper_count, dim3(4096), dim3(TPB), 0, s, P, cnt);
+}
+void launch_row_len(const PoolDev& P, const int32_t* ids, int64_t k, int32_t* out, hipStream_t s) {
+  if (k > 0) hipLaunchKernelGGL(k_row_len, dim3(grid_for(k)), dim3(TPB), 0, s, P, ids, k, out);
+}
+void launch_row_gather(const PoolDev& P, const int32_t* int2ext, const int32_t* ids, int64_t k, const int64_t* pre,
+                       int32_t* u, int32_t* v, hipStream_t s) {
+  if (k > 0)
+    hipLaunchKernelGGL(k_row_gather, dim3((unsigned)std::min<int64_t>(4096, (k + 3) / 4)), dim3(TPB), 0, s, P,
+                       int2ext, ids, k, pre, u, v);
+}
+void launch_set_bytes(uint8_t* a, const int32_t* ids, int64_t k, uint8_t val, hipStream_t s) {
+  if (k > 0) hipLaunchKernelGGL(k_set_bytes, dim3(grid_for(k)), dim3(TPB), 0, s, a, ids, k, val);
 }
 void launch_export(const PoolDev& P, const int32_t* int2ext, const int64_t* gbase, const int64_t* pre, int32_t* src,
                    int32_t* dst, hipStream_t s) {

@@ -25,7 +25,7 @@ _P = ctypes.c_void_p
 
 class Options(ctypes.Structure):
     _fields_ = [("radius", _I32), ("slack", ctypes.c_float), ("device", _I32), ("stream", _P), ("autotune", _I32),
-                ("graphs", _I32), ("delta", _I32)]
+                ("graphs", _I32), ("delta", _I32), ("vertex_capacity", _I64)]
 
 
 class BatchStats(ctypes.Structure):
@@ -60,7 +60,7 @@ _lib = None
 
 EXPORTS = ["gc_options_default", "gc_graph_init", "gc_pool_init", "gc_apply_batch", "gc_apply_batch_dev",
            "gc_apply_batch_dev_noalloc",
-           "gc_apply_batches", "gc_apply_batch_seq", "gc_get_counts", "gc_get_counts_exact", "gc_get_counts3", "gc_recount_exact", "gc_graph_info",
+           "gc_apply_batches", "gc_apply_batch_seq", "gc_add_vertices", "gc_remove_vertices", "gc_get_counts", "gc_get_counts_exact", "gc_get_counts3", "gc_recount_exact", "gc_graph_info",
            "gc_export_edges", "gc_graph_footprint", "gc_graph_replays", "gc_graph_free", "gc_strerror", "gc_last_error",
            "gc_server_opts_default", "gc_server_create", "gc_server_add_graph", "gc_server_submit",
            "gc_server_wait", "gc_server_counts", "gc_server_destroy"]
@@ -94,6 +94,8 @@ def load(path: str = LIB_PATH):
     lib.gc_apply_batch_dev_noalloc.argtypes = [_P, _P, _P, _I64, _P, _P, _I64, _P, ctypes.POINTER(BatchStats)]
     lib.gc_apply_batches.argtypes = [_P, _P, _P, ctypes.POINTER(BatchStats)]
     lib.gc_apply_batch_seq.argtypes = [_P, _P, _I32, _P, _P]
+    lib.gc_add_vertices.argtypes = [_P, _I64, ctypes.POINTER(_I64), _P]
+    lib.gc_remove_vertices.argtypes = [_P, _P, _I64, _P, ctypes.POINTER(BatchStats)]
     lib.gc_get_counts.argtypes = [_P, _I32, _P, ctypes.POINTER(ctypes.c_uint32)]
     lib.gc_get_counts_exact.argtypes = [_P, _I32, _P, _P]
     lib.gc_recount_exact.argtypes = [_P, _I32, _P, _P]
@@ -133,10 +135,12 @@ def _join(hi, lo):
     return [(int(h) << 64) | int(l) for h, l in zip(hi.tolist(), lo.tolist())]
 
 
-def _opts(radius, slack, device, stream, autotune=None, graphs=None, delta=None):
+def _opts(radius, slack, device, stream, autotune=None, graphs=None, delta=None, vertex_capacity=None):
     lib = load()
     o = Options()
     lib.gc_options_default(ctypes.byref(o))
+    if vertex_capacity is not None:
+        o.vertex_capacity = int(vertex_capacity)
     if delta is not None:
         o.delta = int(delta)
     if autotune is not None:
@@ -166,10 +170,10 @@ class Graph:
     """A resident graph (or a pool of graphs) on one GPU."""
 
     def __init__(self, n, src=(), dst=(), radius=None, slack=None, device=0, stream=None, autotune=None,
-                 graphs=None, delta=None, _pool=None):
+                 graphs=None, delta=None, vertex_capacity=None, _pool=None):
         lib = load()
         self._h = _P()
-        opt = _opts(radius, slack, device, stream, autotune, graphs, delta)
+        opt = _opts(radius, slack, device, stream, autotune, graphs, delta, vertex_capacity)
         if _pool is None:
             s, d = _i32(src), _i32(dst)
             assert s.shape == d.shape
@@ -302,6 +306,24 @@ class Graph:
         c, n = _I64(), _I64()
         _check(lib.gc_graph_replays(self._h, ctypes.byref(c), ctypes.byref(n)))
         return c.value, n.value
+
+    def add_vertices(self, count):
+        """gc_add_vertices: `count` new isolated vertices; returns (first id,
+        counts)."""
+        lib = load()
+        first = _I64()
+        _check(lib.gc_add_vertices(self._h, int(count), ctypes.byref(first), None))
+        return first.value, self.counts()
+
+    def remove_vertices(self, ids, stats=False):
+        """gc_remove_vertices: deletes the edges at `ids`, then the vertices;
+        returns the counts (and the batch statistics)."""
+        lib = load()
+        v = _i32(ids)
+        st = BatchStats()
+        _check(lib.gc_remove_vertices(self._h, v.ctypes.data, v.size, None, ctypes.byref(st) if stats else None))
+        c = self.counts()
+        return (c, st.as_dict()) if stats else c
 
     def counts(self, graph=0):
         """Exact counts (Python ints) of graph `graph`."""

@@ -331,3 +331,29 @@ def test_counts3_closed_forms(n):
     assert native.static_counts3(n, *edges_of(path)) == [0, n - 2, one_edge, C(n, 3) - (n - 2) - one_edge]
     if n <= 40:
         assert native.static_counts3(n, *edges_of(_complete(n))) == [C(n, 3), 0, 0, 0]
+
+
+def test_vertex_removal_vs_subset_brute():
+    """Vertex deletion (Sec. 3: incident edges first, then the vertex) and
+    the relabelling onto the live ids, against a classification of every
+    4-subset of the surviving vertices in the ORIGINAL graph."""
+    from oracle.semantics import compact, remove_vertices
+    rng = random.Random(21)
+    for trial in range(40):
+        n = rng.randint(5, 12)
+        E = rand_graph(n, rng.choice([0.2, 0.5, 0.8]), rng)
+        S = set(rng.sample(range(n), rng.randint(1, n - 4)))
+        rest = sorted(set(range(n)) - S)
+        want = [0] * 11
+        for Q in itertools.combinations(rest, 4):
+            loc = {v: i for i, v in enumerate(Q)}
+            sub = {(loc[u], loc[v]) for u, v in E if u in loc and v in loc}
+            c = brute_counts_py(4, sub)
+            want = [a + b for a, b in zip(want, c)]
+        E2, live = set(E), set(range(n))
+        remove_vertices(E2, live, S)
+        n2, s2, d2 = compact(E2, live)
+        assert n2 == len(rest)
+        assert native.static_counts(n2, s2, d2) == want
+        with pytest.raises(BatchRejected):
+            remove_vertices(E2, live, [min(S)])

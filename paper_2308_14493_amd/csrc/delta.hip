@@ -418,76 +418,94 @@ __global__ __launch_bounds__(TPB) void k_delta_c4(DeltaArgs D) {
   const int64_t npairs = D.c4_off[D.ce_cap];
   const int64_t total = D.pair_off[npairs];
   const unsigned long long idmask = (1ull << D.bits) - 1ull;
+  const int l = lane_id();
+  // each wave takes one contiguous range of whole 64-entry chunks of the
+  // index space (equal ranges: balanced by construction); its lanes walk
+  // entries f = chunk * 64 + lane, so a lane's pair only moves forward and
+  // is found by stepping, and the pair's row data is loaded once per pair
+  const int64_t nchunk = (total + 63) >> 6, nw = gstride() >> 6;
+  const int64_t per = (nchunk + nw - 1) / nw;
+  const int64_t c0 = (gtid() >> 6) * per, c1 = min(nchunk, c0 + per);
   int64_t acc = 0;
   int cur_g = -1;
-  // a lane walks entries f = first, first + stride, ... of the index space;
-  // p tracks the pair holding f (pair_off[p] <= f < pair_off[p + 1])
-  const int64_t stride = gstride();
-  int64_t f = gtid();
-  int64_t p = 0;
-  if (f < total) {
-    int64_t lo = 0, hi = npairs;
-    while (hi - lo > 1) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (D.pair_off[mid] <= f) lo = mid; else hi = mid;
-    }
-    p = lo;
-  }
-  for (; f < total; f += stride) {
-    while (D.pair_off[p + 1] <= f) {
-      // long jumps (stride > a pair) search; short ones step
-      if (D.pair_off[min(p + 8, npairs)] <= f) {
-        int64_t a0 = p + 8, b0 = npairs;
-        while (b0 - a0 > 1) {
-          const int64_t mid = (a0 + b0) >> 1;
-          if (D.pair_off[mid] <= f) a0 = mid; else b0 = mid;
-        }
-        p = a0;
-      } else {
-        ++p;
+  if (c0 < c1) {
+    // the pair holding the range's first entry: largest p with
+    // pair_off[p] <= f (empty pairs share their offset with the next)
+    const int64_t fs = c0 << 6;
+    int64_t p = 0;
+    {
+      int64_t lo = 0, hi = npairs;
+      while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (D.pair_off[mid] <= fs) lo = mid; else hi = mid;
       }
+      p = lo;
     }
-    const int32_t i = D.pair_edge[p];
-    const unsigned long long ek = D.ce[i];
-    const unsigned long long K = ek & DIR_KEY_MASK;
-    const uint32_t fe = (uint32_t)(ek >> DIR_MASK_SHIFT) & 3u;
-    const uint32_t u = (uint32_t)(K >> D.bits), v = (uint32_t)(K & idmask);
-    const uint32_t s = D.c4_side[i] ? v : u, o = s == u ? v : u;
-    const int64_t k = p - D.c4_off[i];
-    const uint32_t eaj = D.P.col[D.P.off[s] + k], a = eaj & GC_ID;
-    const int32_t q = (int32_t)(f - D.pair_off[p]);
-    const uint32_t* orow = D.P.col + D.P.off[o];
-    const uint32_t* arow = D.P.col + D.P.off[a];
-    const int32_t ol = D.P.len[o], al = D.P.len[a];
-    uint32_t b, fab = 0, fob = 0;
-    bool hit;
-    if (al <= ol) {  // walk N(a), search N(o)
-      const uint32_t eab = arow[q];
-      b = eab & GC_ID;
-      fab = nib(eab);
-      const int32_t x = lower_bound_id(orow, ol, b);
-      hit = x < ol && (orow[x] & GC_ID) == b;
-      if (hit) fob = nib(orow[x]);
-    } else {         // walk N(o), search N(a)
-      const uint32_t eob = orow[q];
-      b = eob & GC_ID;
-      fob = nib(eob);
-      const int32_t x = lower_bound_id(arow, al, b);
-      hit = x < al && (arow[x] & GC_ID) == b;
-      if (hit) fab = nib(arow[x]);
-    }
-    if (hit && b != s) {
-      const uint32_t fsa = nib(eaj);
-      const bool skip = (fsa && pkey(s, a, D.bits) < K) || (fab && pkey(a, b, D.bits) < K) ||
-                        (fob && pkey(o, b, D.bits) < K);
-      if (!skip) {
-        const int g = D.gid[u];
-        if (g != cur_g) {
-          if (cur_g >= 0 && acc) atomicAdd(&D.sig[SIG_IDX(cur_g, 1, SG_C4)], (unsigned long long)acc);
-          acc = 0;
-          cur_g = g;
+    int64_t pend = D.pair_off[p + 1], pbeg = D.pair_off[p];
+    bool fresh = true;
+    // the current pair's data
+    unsigned long long K = 0;
+    uint32_t fe = 0, s = 0, o = 0, eaj = 0, a = 0, fsa = 0;
+    const uint32_t* orow = nullptr;
+    const uint32_t* arow = nullptr;
+    int32_t ol = 0, al = 0;
+    int g = 0;
+    for (int64_t c = c0; c < c1; ++c) {
+      const int64_t f = (c << 6) + l;
+      if (f >= total) break;
+      while (pend <= f) {
+        ++p;
+        pbeg = pend;
+        pend = D.pair_off[p + 1];
+        fresh = true;
+      }
+      if (fresh) {
+        fresh = false;
+        const int32_t i = D.pair_edge[p];
+        const unsigned long long ek = D.ce[i];
+        K = ek & DIR_KEY_MASK;
+        fe = (uint32_t)(ek >> DIR_MASK_SHIFT) & 3u;
+        const uint32_t u = (uint32_t)(K >> D.bits), v = (uint32_t)(K & idmask);
+        s = D.c4_side[i] ? v : u;
+        o = s == u ? v : u;
+        eaj = D.P.col[D.P.off[s] + (p - D.c4_off[i])];
+        a = eaj & GC_ID;
+        fsa = nib(eaj);
+        orow = D.P.col + D.P.off[o];
+        arow = D.P.col + D.P.off[a];
+        ol = D.P.len[o];
+        al = D.P.len[a];
+        g = D.gid[u];
+      }
+      const int32_t q = (int32_t)(f - pbeg);
+      uint32_t b, fab = 0, fob = 0;
+      bool hit;
+      if (al <= ol) {  // walk N(a), search N(o)
+        const uint32_t eab = arow[q];
+        b = eab & GC_ID;
+        fab = nib(eab);
+        const int32_t x = lower_bound_id(orow, ol, b);
+        hit = x < ol && (orow[x] & GC_ID) == b;
+        if (hit) fob = nib(orow[x]);
+      } else {         // walk N(o), search N(a)
+        const uint32_t eob = orow[q];
+        b = eob & GC_ID;
+        fob = nib(eob);
+        const int32_t x = lower_bound_id(arow, al, b);
+        hit = x < al && (arow[x] & GC_ID) == b;
+        if (hit) fab = nib(arow[x]);
+      }
+      if (hit && b != s) {
+        const bool skip = (fsa && pkey(s, a, D.bits) < K) || (fab && pkey(a, b, D.bits) < K) ||
+                          (fob && pkey(o, b, D.bits) < K);
+        if (!skip) {
+          if (g != cur_g) {
+            if (cur_g >= 0 && acc) atomicAdd(&D.sig[SIG_IDX(cur_g, 1, SG_C4)], (unsigned long long)acc);
+            acc = 0;
+            cur_g = g;
+          }
+          acc += delta_of(fe | fsa | fab | fob);
         }
-        acc += delta_of(fe | fsa | fab | fob);
       }
     }
   }

@@ -477,9 +477,10 @@ def main():
             offered += b[0].size + b[2].size
             stats.append(st)
         log("step %d: batch %d updates, %.2f ms (tri %.2f edge %.2f c4 %.2f/%.2f/%.2f prep %.2f fin %.2f) dmin %d "
-            "whole %d delta %d region_e=%d c4_tail=%d/%d hubs=%d windows=%d searches=%d tri_e=%d" % (
+            "tiers %d/%d/%d whole %d delta %d region_e=%d c4_tail=%d/%d hubs=%d windows=%d searches=%d tri_e=%d" % (
                 i, b[0].size + b[2].size, (t2 - t1) * 1e3, st["ms_tri"], st["ms_edge"], st["ms_c4_small"],
                 st["ms_c4_mid"], st["ms_c4_large"], st["ms_prepare"], st["ms_finish"], st["c4_dense_min"],
+                st["tri_small_max"], st["c4_small_max"], st["c4_mid_max"],
                 st["whole_graph"], st["delta"], st["region_entries"], st["c4_tail_wedges"], st["wedges"],
                 st["tier_c4_large"], st["c4_windows"], st["c4_searches"], st["tri_entries"]))
     torch.cuda.synchronize()
@@ -536,6 +537,17 @@ def main():
                     "edge_local_passes": len(stats) - len(ran)})
     roof_tri = roof("k_tri_small + k_tri_large tiers", sum(4.0 * st["tri_entries"] for st in ran), tot["ms_tri"],
                     measured_traffic("count.hip", "pmc_tri_tiers_rmat_s22.md") if s22 else None)
+    # speed knobs as the autotuner left them: those of the last timed region
+    # pass, and which kind of pass each timed batch ran
+    last_region = [st for st in stats if not st["delta"]]
+    tuned = None
+    if last_region:
+        lr = last_region[-1]
+        tuned = {"c4_dense_min": lr["c4_dense_min"], "tri_small_max": lr["tri_small_max"],
+                 "c4_small_max": lr["c4_small_max"], "c4_mid_max": lr["c4_mid_max"],
+                 "timed_passes": {"edge_local": len(stats) - len(last_region),
+                                  "whole_graph": sum(1 for st in last_region if st["whole_graph"]),
+                                  "region": sum(1 for st in last_region if not st["whole_graph"])}}
     g.close()
     del dev_batches
 
@@ -563,6 +575,7 @@ def main():
         "recount_check": recount_ok,
         "host_array_updates_per_s": host_rate, "host_array_counts_equal": host_same,
         "roofline": roof_c4, "roofline_tri": roof_tri,
+        "tuned": tuned,
         "cpu_baseline": cpu,
         "served": served, "batched": batched,
     }

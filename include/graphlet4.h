@@ -127,6 +127,19 @@ typedef struct {
    * any value <= n: n.  Beyond it, gc_add_vertices rebuilds the graph over
    * a larger id space. */
   int64_t vertex_capacity;
+  /* Tier thresholds of the counting kernels (speed only; results never
+   * depend on them): the largest out-degree counted by the one-wave
+   * triangle tier (at most 64, the slots of its bit matrices), and the
+   * largest wedge bound counted by the one-wave and by the one-workgroup
+   * 4-cycle tiers (at most 256 and 4096, half their hash tables).  Vertices
+   * above a threshold go to the next tier up.  0 (default): with autotune,
+   * five passes that count a region anyway try (64, 256, 4096), a triangle
+   * threshold of 32, a one-wave 4-cycle threshold of 128 and one-workgroup
+   * thresholds of 2048 and 1024, and keep the fastest per unit of work
+   * (triangle entries read, wedges); without, the maxima.  Nonzero: fixed
+   * (an unset one takes its maximum); GC_EINVAL outside [1, max], or with
+   * c4_mid_max below c4_small_max. */
+  int32_t tri_small_max, c4_small_max, c4_mid_max;
 } gc_options;
 
 typedef struct {
@@ -156,6 +169,7 @@ typedef struct {
   int32_t retries;                   /* counting stages run again after growing scratch for a larger vertex */
   int32_t delta;                     /* 1: the pass was edge-local (gc_options.delta) */
   int64_t tri_entries;               /* adjacency entries read by the triangle tiers (N+(u) and each N+(v) probed) */
+  int32_t tri_small_max, c4_small_max, c4_mid_max;  /* tier thresholds of the pass (gc_options) */
 } gc_batch_stats;
 
 /* One batch for one graph of a pool (host pointers). */

@@ -5,6 +5,7 @@
 #include "gc_kernels.h"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -124,9 +125,13 @@ void to_int64(const i128 I[11], int64_t out[11], uint32_t* mask) {
   if (mask) *mask = mk;
 }
 
-constexpr int TRI_SMALL = 64;
-constexpr int C4_SMALL = 256;
-constexpr int C4_MID = 4096;
+// Tier thresholds: largest out-degree of the one-wave triangle tier (its bit
+// matrices hold 64 slots), largest wedge bound of the one-wave and of the
+// one-workgroup 4-cycle tiers (their hash tables hold twice as many).  Lower
+// values are valid too; they move vertices to the next tier up.
+constexpr int TRI_SMALL_MAX = 64;
+constexpr int C4_SMALL_MAX = 256;
+constexpr int C4_MID_MAX = 4096;
 
 }  // namespace
 
@@ -229,6 +234,19 @@ struct gc_graph {
   // captured passes: everything an enqueued pass depends on -> executable graph
   std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
   int64_t graph_launches = 0, graph_captures = 0;
+
+  // tier thresholds (tri_small, c4_small, c4_mid): the best so far, those of
+  // the pass being enqueued, and the trials of the autotuner (each measured
+  // on a pass that counts a region anyway: time per triangle entry read for
+  // the first, per wedge for the other two)
+  int32_t tiers_best[3] = {TRI_SMALL_MAX, C4_SMALL_MAX, C4_MID_MAX};
+  int32_t tiers_now[3] = {TRI_SMALL_MAX, C4_SMALL_MAX, C4_MID_MAX};
+  bool tiers_forced = false;
+  std::vector<std::array<int32_t, 3>> tier_cands{
+      {TRI_SMALL_MAX, C4_SMALL_MAX, C4_MID_MAX}, {32, C4_SMALL_MAX, C4_MID_MAX}, {TRI_SMALL_MAX, 128, C4_MID_MAX},
+      {TRI_SMALL_MAX, C4_SMALL_MAX, 2048}, {TRI_SMALL_MAX, C4_SMALL_MAX, 1024}};
+  std::vector<double> tier_tri_cost, tier_c4_cost;
+  int tier_next = 0;
 
   // online autotuner (speed knobs only)
   std::vector<int64_t> tune_cands{96, 192, 384, 768, 1536};
@@ -479,7 +497,7 @@ void enqueue_count(gc_graph* G, int nv, int radius, long long* state_d, BatchWor
   launch_region_fill(P, A.R, W, radius, G->level.as<int32_t>(), G->rlist.as<int32_t>(), G->rlen.as<int32_t>(),
                      G->scan_tmp.p, s);
   launch_degrees(nv, A.R, G->gid.as<int32_t>(), G->rlist.as<int32_t>(), G->ctr.as<unsigned long long>(),
-                 G->sig.as<unsigned long long>(), G->lists.as<int32_t>(), G->N, TRI_SMALL, C4_SMALL, C4_MID,
+                 G->sig.as<unsigned long long>(), G->lists.as<int32_t>(), G->N, G->tiers_now[0], G->tiers_now[1], G->tiers_now[2],
                  G->deg_wave_row, G->bstats.as<unsigned long long>(), G->c4_keys.as<unsigned long long>(), s);
   if (timed) HIPCHK(hipEventRecord(G->ev[1], s));
   launch_count(nv, A, s, timed ? &G->ev[2] : nullptr);
@@ -681,6 +699,19 @@ void setup_handle(gc_graph* G, const gc_options* opt) {
   if (const char* e = std::getenv("GC_RETRY_LIMIT")) G->retry_limit = std::max(0, std::min(8, std::atoi(e)));
   if (G->opt.radius < 0 || G->opt.radius > 4) raise(GC_EINVAL, "radius must be in [0, 4]");
   if (!(G->opt.slack >= 0.0f && G->opt.slack <= 16.0f)) raise(GC_EINVAL, "slack must be in [0, 16]");
+  {
+    const int32_t ts = G->opt.tri_small_max, cs = G->opt.c4_small_max, cm = G->opt.c4_mid_max;
+    if (ts || cs || cm) {
+      const int32_t t0 = ts ? ts : TRI_SMALL_MAX, c0 = cs ? cs : C4_SMALL_MAX, m0 = cm ? cm : C4_MID_MAX;
+      if (t0 < 1 || t0 > TRI_SMALL_MAX) raise(GC_EINVAL, "tri_small_max must be in [1, %d]", TRI_SMALL_MAX);
+      if (c0 < 1 || c0 > C4_SMALL_MAX) raise(GC_EINVAL, "c4_small_max must be in [1, %d]", C4_SMALL_MAX);
+      if (m0 < c0 || m0 > C4_MID_MAX) raise(GC_EINVAL, "c4_mid_max must be in [c4_small_max, %d]", C4_MID_MAX);
+      G->tiers_best[0] = G->tiers_now[0] = t0;
+      G->tiers_best[1] = G->tiers_now[1] = c0;
+      G->tiers_best[2] = G->tiers_now[2] = m0;
+      G->tiers_forced = true;
+    }
+  }
   int ndev = 0;
   HIPCHK(hipGetDeviceCount(&ndev));
   if (G->opt.device < 0 || G->opt.device >= ndev) raise(GC_EDEVICE, "device %d not present", G->opt.device);
@@ -1105,7 +1136,8 @@ std::vector<uint64_t> pass_signature(gc_graph* G, const PassPlan& L, const Count
                              (uint64_t)A.c4_maxlow, (uint64_t)A.slots, (uint64_t)A.tri_cap, (uint64_t)A.e_max,
                              (uint64_t)G->arena_cap, (uint64_t)L.in_bytes, (uint64_t)G->k, (uint64_t)G->N,
                              (uint64_t)G->bits, (uint64_t)L.delta, (uint64_t)G->ae_cap, (uint64_t)G->slot_cap,
-                             (uint64_t)G->ce.cap, (uint64_t)G->pair_cap, (uint64_t)(L.ndl == 0)};
+                             (uint64_t)G->ce.cap, (uint64_t)G->pair_cap, (uint64_t)(L.ndl == 0),
+                             (uint64_t)G->tiers_now[0], (uint64_t)G->tiers_now[1], (uint64_t)G->tiers_now[2]};
   const DevBuf* bufs[] = {&G->off, &G->len, &G->cap, &G->col, &G->top, &G->gid, &G->ext2int, &G->state, &G->vout,
                           &G->sig, &G->ctr, &G->bstats, &G->bin, &G->keys, &G->keys_alt, &G->dirA, &G->dirA_alt,
                           &G->dirD, &G->dirD_alt, &G->dirR, &G->dirR_alt, &G->a_beg, &G->na, &G->r_beg, &G->nr,
@@ -1186,7 +1218,16 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
     if (G->opt.delta > 0) L.delta = true;
     else if (G->opt.delta == 0 && G->opt.autotune && tune_idx < 0) L.delta = choose_delta(G, bucket, L.total);
   }
-  const bool timed_run = timed || (G->opt.autotune && tune_idx >= 0);
+  // tier thresholds: a trial on a pass that counts a region anyway (after
+  // the hub-window trials), else the best so far
+  int tier_idx = -1;
+  std::copy(G->tiers_best, G->tiers_best + 3, G->tiers_now);
+  if (G->opt.autotune && !G->tiers_forced && !L.delta && tune_idx < 0 &&
+      G->tier_next < (int)G->tier_cands.size()) {
+    tier_idx = G->tier_next;
+    std::copy(G->tier_cands[tier_idx].begin(), G->tier_cands[tier_idx].end(), G->tiers_now);
+  }
+  const bool timed_run = timed || (G->opt.autotune && (tune_idx >= 0 || tier_idx >= 0));
 
   // buffers (all allocation happens here, before anything is enqueued)
   G->keys.ensure(L.cap_t * 8);
@@ -1344,7 +1385,31 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
         G->dense_min_best = G->tune_cands[best];
       }
     }
+    if (tier_idx >= 0 && retries == 0) {
+      float tri_ms = 0, c4_ms = 0;
+      (void)hipEventElapsedTime(&tri_ms, G->ev[2], G->ev[3]);
+      (void)hipEventElapsedTime(&c4_ms, G->ev[4], G->ev[7]);
+      G->tier_tri_cost.push_back(tri_ms / ((double)hb[BS_TRI_E] + 1.0));
+      G->tier_c4_cost.push_back(c4_ms / ((double)hb[BS_WEDGES] + 1.0));
+      ++G->tier_next;
+      if (G->tier_next == (int)G->tier_cands.size()) {
+        // the triangle threshold from the trials that differ in it only,
+        // the 4-cycle pair from the others
+        int bt = 0, bc = 0;
+        for (int i = 1; i < (int)G->tier_cands.size(); ++i) {
+          const auto& c = G->tier_cands[i];
+          const bool tri_only = c[1] == G->tier_cands[0][1] && c[2] == G->tier_cands[0][2];
+          if (tri_only && G->tier_tri_cost[i] < G->tier_tri_cost[bt]) bt = i;
+          if (!tri_only && G->tier_c4_cost[i] < G->tier_c4_cost[bc]) bc = i;
+        }
+        G->tiers_best[0] = G->tier_cands[bt][0];
+        G->tiers_best[1] = G->tier_cands[bc][1];
+        G->tiers_best[2] = G->tier_cands[bc][2];
+      }
+    }
   }
+  const int32_t tiers_used[3] = {G->tiers_now[0], G->tiers_now[1], G->tiers_now[2]};
+  std::copy(G->tiers_best, G->tiers_best + 3, G->tiers_now);
   const double ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
   if (L.nv == 2 && retries == 0) {
     const int m = L.delta ? 1 : 0;
@@ -1371,6 +1436,9 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
       stats[q].whole_graph = L.radius < 0 && !L.delta;
       stats[q].retries = retries;
       stats[q].delta = L.delta;
+      stats[q].tri_small_max = tiers_used[0];
+      stats[q].c4_small_max = tiers_used[1];
+      stats[q].c4_mid_max = tiers_used[2];
     }
   }
 }
@@ -1735,6 +1803,9 @@ int gc_options_default(gc_options* opt) {
   opt->graphs = 1;
   opt->delta = 0;
   opt->vertex_capacity = 0;
+  opt->tri_small_max = 0;
+  opt->c4_small_max = 0;
+  opt->c4_mid_max = 0;
   return GC_OK;
 }
 

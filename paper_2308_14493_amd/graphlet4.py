@@ -25,7 +25,8 @@ _P = ctypes.c_void_p
 
 class Options(ctypes.Structure):
     _fields_ = [("radius", _I32), ("slack", ctypes.c_float), ("device", _I32), ("stream", _P), ("autotune", _I32),
-                ("graphs", _I32), ("delta", _I32), ("vertex_capacity", _I64)]
+                ("graphs", _I32), ("delta", _I32), ("vertex_capacity", _I64),
+                ("tri_small_max", _I32), ("c4_small_max", _I32), ("c4_mid_max", _I32)]
 
 
 class BatchStats(ctypes.Structure):
@@ -39,7 +40,8 @@ class BatchStats(ctypes.Structure):
         (n, ctypes.c_float) for n in ("ms_total", "ms_prepare", "ms_tri", "ms_edge", "ms_c4_small",
                                       "ms_c4_mid", "ms_c4_large", "ms_finish")] + [
         ("c4_windows", _I64), ("c4_searches", _I64), ("tri_global_vertices", _I64), ("tri_exc_rebuilds", _I64),
-        ("retries", _I32), ("delta", _I32), ("tri_entries", _I64)]
+        ("retries", _I32), ("delta", _I32), ("tri_entries", _I64),
+        ("tri_small_max", _I32), ("c4_small_max", _I32), ("c4_mid_max", _I32)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
@@ -135,10 +137,12 @@ def _join(hi, lo):
     return [(int(h) << 64) | int(l) for h, l in zip(hi.tolist(), lo.tolist())]
 
 
-def _opts(radius, slack, device, stream, autotune=None, graphs=None, delta=None, vertex_capacity=None):
+def _opts(radius, slack, device, stream, autotune=None, graphs=None, delta=None, vertex_capacity=None, tiers=None):
     lib = load()
     o = Options()
     lib.gc_options_default(ctypes.byref(o))
+    if tiers is not None:
+        o.tri_small_max, o.c4_small_max, o.c4_mid_max = (int(x) for x in tiers)
     if vertex_capacity is not None:
         o.vertex_capacity = int(vertex_capacity)
     if delta is not None:
@@ -170,10 +174,10 @@ class Graph:
     """A resident graph (or a pool of graphs) on one GPU."""
 
     def __init__(self, n, src=(), dst=(), radius=None, slack=None, device=0, stream=None, autotune=None,
-                 graphs=None, delta=None, vertex_capacity=None, _pool=None):
+                 graphs=None, delta=None, vertex_capacity=None, tiers=None, _pool=None):
         lib = load()
         self._h = _P()
-        opt = _opts(radius, slack, device, stream, autotune, graphs, delta, vertex_capacity)
+        opt = _opts(radius, slack, device, stream, autotune, graphs, delta, vertex_capacity, tiers)
         if _pool is None:
             s, d = _i32(src), _i32(dst)
             assert s.shape == d.shape

@@ -76,3 +76,32 @@ def test_footprint_estimate_without_device():
         assert e.code == -1
     else:
         raise AssertionError("an id outside [0, n) must be rejected")
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """The ctypes mirrors of gc_options, gc_batch_stats, gc_batch_desc and
+    gc_server_opts have the C layout: every field at the offset the header
+    gives it, and the same total size (compiled here with gcc)."""
+    import subprocess
+    mirrors = {"gc_options": graphlet4.Options, "gc_batch_stats": graphlet4.BatchStats,
+               "gc_batch_desc": graphlet4.BatchDesc, "gc_server_opts": graphlet4.ServerOpts}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "graphlet4.h"', 'int main(void) {']
+    for cname, py in mirrors.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f[0], cname, f[0]))
+    lines += ['return 0;', '}']
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, v = line.split()
+            got[(a, b)] = int(v)
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])

@@ -297,7 +297,7 @@ def run_served(args, n, s, d, sampler):
 
 
 def run_protocol(args):
-    """The paper's experimental protocol (Sec. 5) on stand-ins of its four
+    """The paper's experimental protocol (Sec. 6) on stand-ins of its four
     graphs (Table 1 sizes): the edges in a seeded order, the graph built from
     all but the last ones, then insert-only batches of 10 and of 100 (Alg. 1)
     and fully dynamic batches of 100 with the p = 0.7 labelling (Alg. 2),
@@ -410,7 +410,7 @@ def main():
         tot = sum(v[k]["batches"] * (100 if k.endswith("100") else 10) for v in pr.values()
                   for k in ("insert_10", "insert_100", "dynamic_100"))
         secs = sum(v[k]["gpu_total_s"] for v in pr.values() for k in ("insert_10", "insert_100", "dynamic_100"))
-        return form_line(args, "updates/sec, the paper's protocol (Sec. 5) on Table 1 stand-ins", tot / secs,
+        return form_line(args, "updates/sec, the paper's protocol (Sec. 6) on Table 1 stand-ins", tot / secs,
                          secs * 1e3 / max(1, args.protocol_batches), {
                              "config": {"workload": "stand-ins of %s; insert-only batches of 10 and 100, fully "
                                                     "dynamic batches of 100 (p = 0.7), %d batches each"

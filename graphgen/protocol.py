@@ -1,4 +1,4 @@
-"""Update streams of the paper's experiments (Sec. 5), on synthetic edge lists.
+"""Update streams of the paper's experiments (Sec. 6), on synthetic edge lists.
 
 * Incremental streams: the edges of a graph, in a seeded random order,
   grouped into insert-only batches of a fixed size (Alg. 1, IGC; batches of

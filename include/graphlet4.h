@@ -20,7 +20,7 @@
  * follow from the connected counts and the global totals n, m,
  * W = sum_v C(deg v, 2) and the triangle count, which are maintained too.
  *
- * Batch semantics (stream model of Sec. 3, batch protocol of Sec. 5):
+ * Batch semantics (stream model of Sec. 3, batch protocol of Sec. 6):
  *   - (u, v) and (v, u) name the same edge; self loops are ignored;
  *   - repeated pairs inside the insertions (or the deletions) collapse;
  *   - a pair that is both inserted and deleted by one batch is dropped and
@@ -98,9 +98,14 @@ typedef struct {
   void* stream;
   /* 1 (default): online autotuning of speed knobs; results never change.
    * The first batches each try one density threshold of the hub windows of
-   * the 4-cycle count and the fastest per wedge is kept; per batch-size
-   * decade, once the region of change covers >= 90% of the graph, later
-   * batches of that size count the whole graph (same result, no marking). */
+   * the 4-cycle count and the fastest per wedge is kept; then passes that
+   * count a region try the tier thresholds (tri_small_max below).  Per
+   * batch-size decade, once the region of change covers >= 90% of the graph,
+   * later batches of that size count the whole graph (same result, no
+   * marking): this measured switch takes the place of a fixed "whole graph
+   * above this percentage" option.  Per half-decade of batch size, the
+   * edge-local and the region kinds of pass are chosen by their measured
+   * times (the delta option).  0: the defaults, nothing measured. */
   int32_t autotune;
   /* 1 (default): a host-array pass without statistics runs as one HIP graph:
    * the whole pass (upload, ingest, merge, region, counting, purge, result
@@ -158,7 +163,8 @@ typedef struct {
   uint32_t overflow_mask;            /* classes whose count left int64 */
   int32_t pass_batches;              /* batches that shared the counting pass (1: one batch per graph) */
   float ms_total;                    /* wall time of the call */
-  float ms_prepare;                  /* ingest, merge, region, per-vertex pass (device) */
+  float ms_prepare;                  /* ingest, merge, region, per-vertex pass (device): one figure, as they
+                                        run back to back with no event between them */
   float ms_tri, ms_edge;             /* triangle/4-clique kernels, edge pass (device) */
   float ms_c4_small, ms_c4_mid, ms_c4_large;  /* 4-cycle tiers (device) */
   float ms_finish;                   /* combine + purge (device) */
@@ -189,7 +195,8 @@ int gc_options_default(gc_options* opt);
 int gc_graph_init(int64_t n, const int32_t* src, const int32_t* dst, int64_t m,
                   const gc_options* opt, gc_graph** out, int64_t counts[11]);
 
-/* Several independent graphs in one handle ("pool"): graph g has n[g]
+/* Several independent graphs in one handle ("pool"; a batched interface of
+ * this library: the paper maintains one graph): graph g has n[g]
  * vertices and m[g] edges.  Batches for all of them are then applied
  * together by gc_apply_batches (one pass of device work for all graphs).
  * counts (k x 11) may be NULL. */
@@ -202,7 +209,9 @@ int gc_apply_batch(gc_graph* g, const int32_t* ins_src, const int32_t* ins_dst, 
                    const int32_t* del_src, const int32_t* del_dst, int64_t n_del,
                    int64_t counts[11], gc_batch_stats* stats);
 
-/* Same with device arrays (int32, on the handle's device). */
+/* Same with device arrays (int32, on the handle's device): the batch of
+ * Problem 1 already resident in HBM.  An interface of this library, not of
+ * the paper; the ids are checked on the device, before anything changes. */
 int gc_apply_batch_dev(gc_graph* g, const int32_t* ins_src, const int32_t* ins_dst, int64_t n_ins,
                        const int32_t* del_src, const int32_t* del_dst, int64_t n_del,
                        int64_t counts[11], gc_batch_stats* stats);
@@ -250,7 +259,9 @@ int gc_apply_batches(gc_graph* pool, const gc_batch_desc* batch, int64_t (*count
 int gc_apply_batch_seq(gc_graph* g, const gc_batch_desc* batches, int32_t nb, int64_t (*counts)[11],
                        gc_batch_stats* stats);
 
-/* Current counts of graph `graph` (0 for a single-graph handle). */
+/* Current counts of graph `graph` (0 for a single-graph handle): the
+ * frequencies Problem 1 maintains, for the six connected classes of Fig. 1,
+ * and the five disconnected classes derived from them and n, m, W, T. */
 int gc_get_counts(const gc_graph* g, int32_t graph, int64_t counts[11], uint32_t* overflow_mask);
 int gc_get_counts_exact(const gc_graph* g, int32_t graph, int64_t hi[11], uint64_t lo[11]);
 
@@ -295,24 +306,30 @@ int gc_remove_vertices(gc_graph* g, const int32_t* ids, int64_t count, int64_t c
 int gc_graph_info(const gc_graph* g, int32_t* num_graphs, int32_t graph, int64_t* n, int64_t* m);
 
 /* Copies the edges of graph `graph` (each once, external ids) into host
- * arrays of capacity cap; *m_out = edge count (GC_EINVAL if cap < m). */
+ * arrays of capacity cap; *m_out = edge count (GC_EINVAL if cap < m).
+ * Library interface (for checking and persistence), not in the paper. */
 int gc_export_edges(gc_graph* g, int32_t graph, int32_t* src, int32_t* dst, int64_t cap, int64_t* m_out);
 
 /* Estimated device bytes a single-graph handle built from this edge list
  * reaches (resident rows with slack, region view, per-edge triangle counts,
  * hub counters, multi-version passes, the transient arrays of the build),
  * from the same sizing rules the library allocates by; batch staging is not
- * included.  Host arrays; needs no device.  The server's admission uses it. */
+ * included.  Host arrays; needs no device.  The server's admission uses it.
+ * Library interface, not in the paper. */
 int gc_graph_footprint(int64_t n, const int32_t* src, const int32_t* dst, int64_t m, const gc_options* opt,
                        int64_t* bytes);
 
 /* Diagnostics of the graphs option: passes captured as HIP graphs and
- * passes launched from a captured graph (replays included) so far. */
+ * passes launched from a captured graph (replays included) so far
+ * (library interface). */
 int gc_graph_replays(const gc_graph* g, int64_t* captures, int64_t* launches);
 
+/* Frees the handle and its device memory (library interface). */
 int gc_graph_free(gc_graph* g);
 
 /* ------------------------------------------------------------- serving
+ * (A serving interface of this library; no passage of the paper defines
+ * it.  Each batch is still applied by Alg. 2 as gc_apply_batch does.)
  * A server keeps graphs resident on one device, each with its own stream and
  * worker thread, and answers asynchronously submitted update batches through
  * tickets.  Batches for different graphs run at the same time (their kernels

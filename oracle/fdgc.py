@@ -1,16 +1,16 @@
 """ORACLE -- test infrastructure.  Set-based reference of the paper's Alg. 2.
 
-FDGC (Sec. 4.3, Alg. 2): for a batch B = A u D,
+FDGC (Sec. 4.5, Alg. 2): for a batch B = A u D,
     H   = union over changed edges e = (u, v) of G[N_r(u) u N_r(v)]
     G_a = (H - D) u A,    G_b = (H - A) u D
     F  += PGD(G_a) - PGD(G_b)
     G   = G - D u A
 with F the six connected induced 4-graphlet counts (Fig. 1), starting from
 F = 0 on the empty graph.  The paper takes r = 3 (a 4-vertex graphlet has
-diameter at most 3, Sec. 4.2).  Lemma 2 states that F then equals a recount
+diameter at most 3, Sec. 4.3).  Lemma 2 states that F then equals a recount
 of the updated graph.
 
-The batch is first reduced to its effective part (semantics.py): Sec. 5
+The batch is first reduced to its effective part (semantics.py): Sec. 6
 cancels pairs that are both added and deleted; an insertion of an existing
 edge or a deletion of a missing one is not a change.
 

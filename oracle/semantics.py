@@ -3,7 +3,7 @@
 The stream model (Sec. 3) applies a tuple <e, o> by set union (o = +) or set
 difference (o = -); Problem 1 maintains the counts of
 G^{t+1} = (V, E^t + A - D) for a batch B = A u D of a simple undirected graph.
-Sec. 5 first removes the edges that are both added and deleted in a batch and
+Sec. 6 first removes the edges that are both added and deleted in a batch and
 runs the algorithm on the rest.  Together:
 
   * (u, v) and (v, u) are the same edge; self loops are not edges (dropped);

@@ -3,7 +3,7 @@
 // marking, the region CSR and its per-vertex pass, and the initial build.
 //
 // Batch semantics (the stream model of Sec. 3 and the batch protocol of
-// Sec. 5): pairs are unordered, self loops are not edges, repeats collapse,
+// Sec. 6): pairs are unordered, self loops are not edges, repeats collapse,
 // a pair both inserted and deleted by one batch is dropped, and only the
 // effective part A' = A - E, D' = D & E changes the graph.  Several batches
 // of one graph may share a pass: they act in order, each on the graph left by

@@ -1,4 +1,4 @@
-"""GPU: the paper's experimental protocol (Sec. 5) on a WikiVote-shaped
+"""GPU: the paper's experimental protocol (Sec. 6) on a WikiVote-shaped
 stand-in, checked against the oracle after every batch: insert-only batches
 of 10 and of 100 from the empty graph (Alg. 1: passes without deletions take
 the insert-only path), and fully dynamic batches of 100 with the p = 0.7

@@ -1,4 +1,4 @@
-"""Host checks of the update streams of the paper's experiments (Sec. 5):
+"""Host checks of the update streams of the paper's experiments (Sec. 6):
 insert-only batches in edge order, and the p-labelled fully dynamic stream
 (each negative removes an edge some batches after its positive)."""
 import numpy as np

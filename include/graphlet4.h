@@ -97,9 +97,10 @@ typedef struct {
   /* hipStream_t to run on (NULL = the library's own stream). */
   void* stream;
   /* 1 (default): online autotuning of speed knobs; results never change.
-   * The first batches each try one density threshold of the hub windows of
-   * the 4-cycle count and the fastest per wedge is kept; then passes that
-   * count a region try the tier thresholds (tri_small_max below).  Per
+   * The first five passes that count a region (rather than edge-locally)
+   * each try one density threshold of the hub windows of the 4-cycle count
+   * and the fastest per wedge is kept; the next five try the tier
+   * thresholds (tri_small_max below).  Per
    * batch-size decade, once the region of change covers >= 90% of the graph,
    * later batches of that size count the whole graph (same result, no
    * marking): this measured switch takes the place of a fixed "whole graph
@@ -140,7 +141,8 @@ typedef struct {
    * above a threshold go to the next tier up.  0 (default): with autotune,
    * five passes that count a region anyway try (64, 256, 4096), a triangle
    * threshold of 32, a one-wave 4-cycle threshold of 128 and one-workgroup
-   * thresholds of 2048 and 1024, and keep the fastest per unit of work
+   * thresholds of 2048 and 1024 (after the hub-window trials), and keep the
+   * fastest per unit of work
    * (triangle entries read, wedges); without, the maxima.  Nonzero: fixed
    * (an unset one takes its maximum); GC_EINVAL outside [1, max], or with
    * c4_mid_max below c4_small_max. */

@@ -1025,11 +1025,13 @@ int settle_delta(gc_graph* G, const PassPlan& L, BatchWork& W);
 // bucket's mean, else the mean of all region passes (it hardly depends on
 // the batch).  Edge-local time: this bucket's mean, else the nearest
 // measured bucket's scaled by the batch size (its work grows with the
-// changed pairs), else a first try for batches of at most 1000 updates.
+// changed pairs), else a first try for batches of at most 1000 updates (also
+// while no region pass has been measured).
 // Both kinds measured in a bucket: every 32nd pass there tries the other.
 bool choose_delta(gc_graph* G, int b, int64_t total) {
   const int64_t* n = G->mode_n[b];
-  if (G->region_n_all == 0) return false;
+  // nothing measured for the region kind yet: small batches start edge-local
+  if (G->region_n_all == 0) return total <= 1000;
   if (n[0] > 0 && n[1] > 0) {
     const bool d = G->mode_ms[b][1] < G->mode_ms[b][0];
     return (n[0] + n[1]) % 32 == 31 ? !d : d;
@@ -1195,15 +1197,10 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
 
   // speed knobs (results never depend on them)
   L.radius = G->opt.radius == 0 ? -1 : G->opt.radius;
-  int tune_idx = -1;
+  int tune_idx = -1, tier_idx = -1;
   const int decade = (int)std::min<double>(7.0, std::floor(std::log10((double)L.total + 1.0)));
+  L.dense_min = G->dense_min_best;
   if (G->opt.autotune) {
-    if (G->tune_next < (int)G->tune_cands.size()) {
-      tune_idx = G->tune_next;
-      L.dense_min = G->tune_cands[tune_idx];
-    } else {
-      L.dense_min = G->dense_min_best;
-    }
     // whole-graph mode once a batch no larger than this one saw a region of
     // >= 90% of the entries (a larger batch's region covers at least as much
     // in expectation); exact radii only
@@ -1216,16 +1213,19 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
   const int bucket = (int)std::min<double>(15.0, std::floor(2.0 * std::log10((double)L.total + 1.0)));
   if (L.nv == 2 && G->opt.radius != 1) {
     if (G->opt.delta > 0) L.delta = true;
-    else if (G->opt.delta == 0 && G->opt.autotune && tune_idx < 0) L.delta = choose_delta(G, bucket, L.total);
+    else if (G->opt.delta == 0 && G->opt.autotune) L.delta = choose_delta(G, bucket, L.total);
   }
-  // tier thresholds: a trial on a pass that counts a region anyway (after
-  // the hub-window trials), else the best so far
-  int tier_idx = -1;
+  // trials of the region count's knobs, each on a pass that counts a region
+  // anyway: first the hub-window density thresholds, then the tier thresholds
   std::copy(G->tiers_best, G->tiers_best + 3, G->tiers_now);
-  if (G->opt.autotune && !G->tiers_forced && !L.delta && tune_idx < 0 &&
-      G->tier_next < (int)G->tier_cands.size()) {
-    tier_idx = G->tier_next;
-    std::copy(G->tier_cands[tier_idx].begin(), G->tier_cands[tier_idx].end(), G->tiers_now);
+  if (G->opt.autotune && !L.delta) {
+    if (G->tune_next < (int)G->tune_cands.size()) {
+      tune_idx = G->tune_next;
+      L.dense_min = G->tune_cands[tune_idx];
+    } else if (!G->tiers_forced && G->tier_next < (int)G->tier_cands.size()) {
+      tier_idx = G->tier_next;
+      std::copy(G->tier_cands[tier_idx].begin(), G->tier_cands[tier_idx].end(), G->tiers_now);
+    }
   }
   const bool timed_run = timed || (G->opt.autotune && (tune_idx >= 0 || tier_idx >= 0));
 

@@ -532,6 +532,14 @@ def main():
                 "avg_launch_ms": ms / nl, "launches": len(ran),
                 "traffic_frac": round(traffic / (ms / nl / 1e3) / 1e9 / HBM_PEAK_GBS, 5) if traffic and ms > 0 else None}
 
+    # the compulsory bytes of a region pass: the region's rows read once
+    # (4 B per entry, 16 B per vertex for its offset, length and degrees)
+    comp = None
+    if ran:
+        cb = [4.0 * st["region_entries"] + 16.0 * st["region_vertices"] for st in ran]
+        cms = [st["ms_total"] for st in ran]
+        comp = {"bytes_per_region_pass": sum(cb) / len(cb), "GBps": sum(cb) / (sum(cms) / 1e3) / 1e9,
+                "unit": "GB/s", "over": "wall time of the region passes"}
     s22 = args.scale == 22 and args.ef == 16
     roof_c4 = roof("k_c4_large", sum(4.0 * st["c4_entries_large"] for st in ran), tot["ms_c4_large"],
                    measured_traffic("count.hip", "pmc_k_c4_large_rmat_s22.md") if s22 else None)
@@ -576,7 +584,8 @@ def main():
                          "equal": checks, "all_equal": bool(checks) and all(checks.values())},
         "recount_check": recount_ok,
         "host_array_updates_per_s": host_rate, "host_array_counts_equal": host_same,
-        "roofline": roof_c4, "roofline_tri": roof_tri,
+        "effective_updates_per_s": sum(st["eff_ins"] + st["eff_del"] for st in stats) / elapsed,
+        "roofline": roof_c4, "roofline_tri": roof_tri, "compulsory_bandwidth": comp,
         "tuned": tuned,
         "cpu_baseline": cpu,
         "served": served, "batched": batched,

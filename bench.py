@@ -147,14 +147,15 @@ def run_batched(args):
     [100, 1e4], 50/50, the same size every round): one pooled pass per round
     for all graphs, replayed from a captured HIP graph, against the same pool
     launching kernel by kernel and against one call per graph.  Every form
-    first applies the same warm-up rounds (the autotuner's trial passes, then
-    the capture); the timed rounds follow."""
+    first applies the same warm-up rounds (the autotuner's ten trial passes --
+    hub-window and tier thresholds -- then the capture); the timed rounds
+    follow."""
     from graphgen import rmat_graph, rmat_batches
     import paper_2308_14493_amd as pkg
     import torch
     rng = np.random.default_rng(4)
     t0 = time.time()
-    warm, rounds = 6, args.rounds
+    warm, rounds = 11, args.rounds
     work = []
     for i in range(args.graphs):
         n = int(round(10 ** rng.uniform(3, math.log10(2e5))))

@@ -255,9 +255,14 @@ int gc_apply_batches(gc_graph* pool, const gc_batch_desc* batch, int64_t (*count
  * batches share one counting pass: Lemma 2 applied to G_0 and each G_j,
  * with the region of change taken in the union of G_0 .. G_j (a superset of
  * each version's region, so exact) and every adjacency entry marking the
- * versions its edge belongs to.  The arrays of all nb batches are checked
- * first: one id outside [0, n) rejects the whole call with GC_EINVAL and
- * leaves the graph unchanged. */
+ * versions its edge belongs to.  Whether they do: with autotune and
+ * automatic pass kinds (gc_options.delta = 0), when the measured cost of
+ * such a pass is below that of the batches one by one (each then
+ * edge-local where that is faster; while nothing is measured, batches of at
+ * most 1000 updates run alone); always with delta = -1 or without autotune;
+ * never with delta = 1.  Results are the same either way.  The arrays of
+ * all nb batches are checked first: one id outside [0, n) rejects the
+ * whole call with GC_EINVAL and leaves the graph unchanged. */
 int gc_apply_batch_seq(gc_graph* g, const gc_batch_desc* batches, int32_t nb, int64_t (*counts)[11],
                        gc_batch_stats* stats);
 
@@ -339,7 +344,8 @@ int gc_graph_free(gc_graph* g);
  * order, and each ticket's result is the counts right after its batch, the
  * same as gc_apply_batch would return in that order.  Continuous batching:
  * when a graph's worker becomes free it takes up to three queued batches of
- * that graph into one counting pass (gc_apply_batch_seq); a batch that fails
+ * that graph into one gc_apply_batch_seq call, which folds them into one
+ * counting pass when that is measured to be faster; a batch that fails
  * the host-side id check fails alone.  Admission by memory:
  * a graph is admitted only if its footprint (gc_graph_footprint) fits the
  * free HBM (hipMemGetInfo, or, when hbm_budget_bytes > 0, that budget minus

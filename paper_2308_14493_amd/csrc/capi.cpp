@@ -224,6 +224,9 @@ struct gc_graph {
   int64_t mode_n[16][2] = {};
   double region_ms_all = 0;
   int64_t region_n_all = 0;
+  // mean wall ms of multi-version passes by their number of batches
+  double multi_ms[GC_NV_MAX] = {};
+  int64_t multi_n[GC_NV_MAX] = {};
   int64_t c4_cur_low = 0;
   int32_t c4_slots = 0, tri_slots = 0;
   int64_t c4_dense_n = 0;            // vertex count the hub counters are sized for
@@ -1028,16 +1031,14 @@ int settle_delta(gc_graph* G, const PassPlan& L, BatchWork& W);
 // changed pairs), else a first try for batches of at most 1000 updates (also
 // while no region pass has been measured).
 // Both kinds measured in a bucket: every 32nd pass there tries the other.
-bool choose_delta(gc_graph* G, int b, int64_t total) {
+// Expected wall ms of the two kinds of one-batch pass (< 0: no estimate):
+// region, this bucket's mean, else the mean of all region passes;
+// edge-local, this bucket's mean, else the nearest measured bucket's scaled
+// by the batch size.
+void pass_estimates(const gc_graph* G, int b, int64_t total, double& est_r, double& est_d) {
   const int64_t* n = G->mode_n[b];
-  // nothing measured for the region kind yet: small batches start edge-local
-  if (G->region_n_all == 0) return total <= 1000;
-  if (n[0] > 0 && n[1] > 0) {
-    const bool d = G->mode_ms[b][1] < G->mode_ms[b][0];
-    return (n[0] + n[1]) % 32 == 31 ? !d : d;
-  }
-  const double est_r = n[0] > 0 ? G->mode_ms[b][0] : G->region_ms_all;
-  double est_d = -1;
+  est_r = n[0] > 0 ? G->mode_ms[b][0] : (G->region_n_all > 0 ? G->region_ms_all : -1.0);
+  est_d = -1;
   if (n[1] > 0) {
     est_d = G->mode_ms[b][1];
   } else {
@@ -1046,8 +1047,50 @@ bool choose_delta(gc_graph* G, int b, int64_t total) {
         if (bb >= 0 && bb < 16 && G->mode_n[bb][1] > 0 && est_d < 0)
           est_d = G->mode_ms[bb][1] * (double)std::max<int64_t>(total, 1) / std::max(1.0, G->mode_sz[bb][1]);
   }
+}
+
+int size_bucket(int64_t total) {
+  return (int)std::min(15.0, std::floor(2.0 * std::log10((double)total + 1.0)));
+}
+
+bool choose_delta(gc_graph* G, int b, int64_t total) {
+  const int64_t* n = G->mode_n[b];
+  // nothing measured for the region kind yet: small batches start edge-local
+  if (G->region_n_all == 0) return total <= 1000;
+  if (n[0] > 0 && n[1] > 0) {
+    const bool d = G->mode_ms[b][1] < G->mode_ms[b][0];
+    return (n[0] + n[1]) % 32 == 31 ? !d : d;
+  }
+  double est_r, est_d;
+  pass_estimates(G, b, total, est_r, est_d);
   if (est_d < 0) return total <= 1000;
   return est_d < est_r;
+}
+
+// Whether q queued batches of one graph (gc_apply_batch_seq, the server)
+// should share one multi-version pass rather than run one by one (each then
+// edge-local where that is faster): by the cost model, when autotuning with
+// automatic pass kinds; always with edge-local passes off (or no autotune),
+// never with them forced.
+bool fold_batches(const gc_graph* G, const gc_batch_desc* b, int q) {
+  if (q < 2) return false;
+  if (G->opt.delta < 0 || !G->opt.autotune) return true;
+  if (G->opt.delta > 0) return false;
+  bool all_small = true;
+  double one_by_one = 0;
+  for (int j = 0; j < q; ++j) {
+    const int64_t t = b[j].n_ins + b[j].n_del;
+    all_small = all_small && t <= 1000;
+    double er, ed;
+    pass_estimates(G, size_bucket(t), t, er, ed);
+    const double e = er >= 0 && ed >= 0 ? std::min(er, ed) : (er >= 0 ? er : ed);
+    if (e < 0) return !all_small;  // nothing measured: small batches start edge-local
+    one_by_one += e;
+  }
+  double multi = G->multi_n[q] > 0 ? G->multi_ms[q] : -1.0;
+  if (multi < 0 && G->region_n_all > 0) multi = G->region_ms_all * (1.0 + 0.25 * (q - 1));
+  if (multi < 0) return !all_small;
+  return multi < one_by_one;
 }
 
 // Every device step of a pass, in stream order: upload, ingest, merge,
@@ -1210,7 +1253,7 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
   }
   // edge-local pass: one batch per graph and an exact radius; forced by the
   // option, or (autotune) the kind with the smaller expected time
-  const int bucket = (int)std::min<double>(15.0, std::floor(2.0 * std::log10((double)L.total + 1.0)));
+  const int bucket = size_bucket(L.total);
   if (L.nv == 2 && G->opt.radius != 1) {
     if (G->opt.delta > 0) L.delta = true;
     else if (G->opt.delta == 0 && G->opt.autotune) L.delta = choose_delta(G, bucket, L.total);
@@ -1411,6 +1454,11 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
   const int32_t tiers_used[3] = {G->tiers_now[0], G->tiers_now[1], G->tiers_now[2]};
   std::copy(G->tiers_best, G->tiers_best + 3, G->tiers_now);
   const double ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  if (L.nv == 4 && retries == 0 && L.npass < GC_NV_MAX) {
+    double& avg = G->multi_ms[L.npass];
+    avg = G->multi_n[L.npass] == 0 ? ms : 0.75 * avg + 0.25 * ms;
+    ++G->multi_n[L.npass];
+  }
   if (L.nv == 2 && retries == 0) {
     const int m = L.delta ? 1 : 0;
     int64_t& cnt = G->mode_n[bucket][m];
@@ -1897,9 +1945,11 @@ int gc_apply_batch_seq(gc_graph* g, const gc_batch_desc* batches, int32_t nb, in
     if (nb < 0) raise(GC_EINVAL, "negative batch count");
     for (int j = 0; j < nb; ++j)
       check_batch(batches[j], g->gi[0], j, g->any_dead ? g->dead_h.data() : nullptr);  // all-or-nothing
-    for (int j0 = 0; j0 < nb; j0 += GC_SEQ_MAX) {
-      const int q = std::min(GC_SEQ_MAX, nb - j0);
+    for (int j0 = 0; j0 < nb;) {
+      int q = std::min(GC_SEQ_MAX, nb - j0);
+      if (!fold_batches(g, batches + j0, q)) q = 1;
       apply(g, batches + j0, q, false, q > 1, counts ? counts + j0 : nullptr, stats ? stats + j0 : nullptr);
+      j0 += q;
     }
   });
 }

@@ -396,10 +396,10 @@ class Server:
         self._h = _P()
         _check(lib.gc_server_create(ctypes.byref(o), ctypes.byref(self._h)))
 
-    def add_graph(self, n, src, dst, radius=None, slack=None):
+    def add_graph(self, n, src, dst, radius=None, slack=None, delta=None):
         lib = load()
         s, d = _i32(src), _i32(dst)
-        opt = _opts(radius, slack, 0, None)
+        opt = _opts(radius, slack, 0, None, delta=delta)
         gid = _I32()
         _check(lib.gc_server_add_graph(self._h, int(n), s.ctypes.data, d.ctypes.data, s.size, ctypes.byref(opt),
                                        ctypes.byref(gid)))

@@ -18,7 +18,10 @@ pytestmark = pytest.mark.gpu
 
 
 def G(*a, **k):
+    """A handle whose queued batches always share multi-version passes
+    (edge-local passes off): the passes these tests exercise."""
     from paper_2308_14493_amd.graphlet4 import Graph
+    k.setdefault("delta", -1)
     return Graph(*a, **k)
 
 
@@ -227,7 +230,7 @@ def test_server_continuous_batching():
         alone = [as_i64(g.apply_batch(*b)) for b in batches]
     bad = (np.array([0], np.int32), np.array([n + 5], np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32))
     with Server() as srv:
-        gid = srv.add_graph(n, s, d)
+        gid = srv.add_graph(n, s, d, delta=-1)
         tickets = [srv.submit(gid, *b) for b in batches[:6]]
         tbad = srv.submit(gid, *bad)
         tickets += [srv.submit(gid, *b) for b in batches[6:]]
@@ -241,3 +244,25 @@ def test_server_continuous_batching():
         say("  pass sizes %s" % passes)
         assert max(passes) > 1
         assert srv.counts(gid) == native.static_counts(n, *esorted(oracle_final(n, edge_set(s, d), batches)))
+
+
+def test_seq_folding_policy_auto():
+    """With automatic pass kinds, a call of queued batches runs them one by
+    one (each edge-local where that is faster) or folds them into a
+    multi-version pass by the measured costs; either way every result equals
+    the one-by-one application and the oracle."""
+    from paper_2308_14493_amd.graphlet4 import Graph
+    say("case seq folding policy")
+    n, s, d, samp = rmat_graph(12, 16, 91)
+    small = rmat_batches(n, s, d, samp, [40] * 6, 92)
+    E = edge_set(s, d)
+    want = oracle_after_each(n, set(E), small)
+    with Graph(n, s, d) as g:
+        rows, st = g.apply_batch_seq(small[:3], stats=True)
+        rows2, st2 = g.apply_batch_seq(small[3:], stats=True)
+        # nothing measured yet for the region kind: small batches run alone
+        assert [x["pass_batches"] for x in st] == [1, 1, 1]
+        assert rows + rows2 == want
+        for x in st + st2:
+            if x["pass_batches"] == 1:
+                assert x["delta"] == 1

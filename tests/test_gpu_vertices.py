@@ -201,3 +201,47 @@ def test_vertex_degenerate():
             pool.add_vertices(1)
         with pytest.raises(GraphletError):
             pool.remove_vertices([1])
+
+
+def test_vertex_ops_rmat_s16():
+    """R-MAT scale 16 (65,536 vertices, hubs of thousands of edges): vertex
+    additions within the reserved ids, a batch on the new vertices, removal
+    of the 50 largest hubs (one deletion batch of tens of thousands of
+    edges), growth past the reservation, then a large mixed batch; the
+    counts equal the oracle's after every step."""
+    from paper_2308_14493_amd.graphlet4 import Graph
+    say("case vertex ops R-MAT s16")
+    rng = np.random.default_rng(16)
+    n, s, d, _ = rmat_graph(16, 8, 11)
+    E = {e for e in edge_set(s, d) if e[0] != e[1]}
+    live = set(range(n))
+    with Graph(n, s, d, vertex_capacity=n + 500) as gr:
+        assert gr.counts() == want(E, live)
+        first, c = gr.add_vertices(300)
+        new = set(range(first, first + 300))
+        live |= new
+        assert c == want(E, live)
+        b = rand_batch(rng, E, live, 2000, 1000, hot=new)
+        got = gr.apply_batch(*b)
+        oracle_apply(E, n + 300, *b)
+        assert got == want(E, live)
+        deg = {}
+        for u, v in E:
+            deg[u] = deg.get(u, 0) + 1
+            deg[v] = deg.get(v, 0) + 1
+        hubs = sorted(deg, key=lambda x: -deg[x])[:50]
+        got, st = gr.remove_vertices(hubs, stats=True)
+        inc = sum(1 for u, v in E if u in hubs or v in hubs)
+        oracle_remove(E, live, hubs)
+        say("  removed 50 hubs: %d edges" % inc)
+        assert st["eff_del"] == inc and got == want(E, live)
+        first2, c = gr.add_vertices(1000)
+        assert first2 == first + 300
+        live |= set(range(first2, first2 + 1000))
+        assert c == want(E, live)
+        b = rand_batch(rng, E, live, 5000, 5000)
+        got = gr.apply_batch(*b)
+        oracle_apply(E, first2 + 1000, *b)
+        assert got == want(E, live)
+        assert gr.recount() == got
+        assert edge_set(*gr.edges()) == E

@@ -56,6 +56,40 @@ __device__ __forceinline__ int64_t find_in_row(const PoolDev& P, uint32_t r, uin
   return (p < n && (row[p] & GC_ID) == id) ? P.off[r] + p : -1;
 }
 
+// The common ids of two id-sorted rows, the wave together: each step loads
+// the next 64 entries of both rows (one per lane), finds each a entry in the
+// b window by a search over the lanes, and consumes the window with the
+// smaller last id together with the entries of the other window up to that
+// id.  No common id is ever consumed on one side only, so each is met once,
+// in the step that consumes it, with both of its entries in the windows.
+// f(entry of a, entry of b) per common id, on the lane holding the a entry.
+template <class F>
+__device__ __forceinline__ void wave_window_common(const uint32_t* a, int32_t na, const uint32_t* b, int32_t nb,
+                                                   F f) {
+  const int l = lane_id();
+  int32_t i0 = 0, j0 = 0;
+  while (i0 < na && j0 < nb) {
+    const bool va = i0 + l < na, vb = j0 + l < nb;
+    const uint32_t ea = va ? a[i0 + l] : 0u, eb = vb ? b[j0 + l] : 0u;
+    const uint32_t ia = va ? (ea & GC_ID) : 0xFFFFFFFFu, ib = vb ? (eb & GC_ID) : 0xFFFFFFFFu;
+    const uint32_t amax = __shfl(ia, min(63, na - 1 - i0)), bmax = __shfl(ib, min(63, nb - 1 - j0));
+    int lo = 0;  // number of window ids of b below ia (the window is ascending, padded above)
+#pragma unroll
+    for (int sp = 32; sp >= 1; sp >>= 1)
+      if (__shfl(ib, lo + sp - 1) < ia) lo += sp;
+    const int p = min(lo, 63);
+    const uint32_t ibp = __shfl(ib, p), ebp = __shfl(eb, p);
+    if (va && ibp == ia) f(ea, ebp);
+    if (amax <= bmax) {
+      j0 += __popcll(__ballot(ib <= amax));
+      i0 += 64;
+    } else {
+      i0 += __popcll(__ballot(ia <= bmax));
+      j0 += 64;
+    }
+  }
+}
+
 // degree of v in version x (0 before, 1 after): touched rows carry flags and
 // have their two degrees in dd; the others have none
 __device__ __forceinline__ int64_t deg_of(const DeltaArgs& D, uint32_t v, int x) {
@@ -275,16 +309,27 @@ __global__ void k_delta_aff(DeltaArgs D, const unsigned long long* __restrict__ 
     }
     const uint32_t a = D.P.len[x] <= D.P.len[y] ? x : y, b = a == x ? y : x;
     const uint32_t* arow = D.P.col + D.P.off[a];
-    const int32_t al = D.P.len[a];
+    const int32_t al = D.P.len[a], bl = D.P.len[b];
     int32_t tb = 0, ta = 0;
-    for (int32_t k = l; k < al; k += 64) {
-      const uint32_t ea = arow[k], w = ea & GC_ID;
-      if (w == b) continue;
-      const int64_t p = find_in_row(D.P, b, w);
-      if (p < 0) continue;
-      const uint32_t f = nib(ea) | nib(D.P.col[p]);
-      tb += (f & 1u) == 0;
-      ta += (f & 2u) == 0;
+    if (al > 0 && (int64_t)bl <= (int64_t)al * (30 - __clz(max(bl, 1)))) {
+      // rows of similar length: both walked together, 64 entries of each a
+      // step, instead of a search of the longer row per entry of the shorter
+      wave_window_common(arow, al, D.P.col + D.P.off[b], bl, [&](uint32_t ea, uint32_t eb) {
+        const uint32_t f = nib(ea) | nib(eb);
+        tb += (f & 1u) == 0;
+        ta += (f & 2u) == 0;
+      });
+    } else {
+      // the shorter row's entries searched in the longer
+      for (int32_t k = l; k < al; k += 64) {
+        const uint32_t ea = arow[k], w = ea & GC_ID;
+        if (w == b) continue;
+        const int64_t p = find_in_row(D.P, b, w);
+        if (p < 0) continue;
+        const uint32_t f = nib(ea) | nib(D.P.col[p]);
+        tb += (f & 1u) == 0;
+        ta += (f & 2u) == 0;
+      }
     }
     tb = wave_sum32(tb);
     ta = wave_sum32(ta);

@@ -452,8 +452,15 @@ __global__ void k_delta_c4_pairs(DeltaArgs D) {
     const int64_t base = D.c4_off[i];
     for (int32_t k = l; k < sl; k += 64) {
       const uint32_t a = srow[k] & GC_ID;
+      const int32_t al = D.P.len[a];
+      const int32_t mn = min(al, ol), mx = max(al, ol);
       D.pair_edge[base + k] = (int32_t)i;
-      D.pair_len[base + k] = a == o ? 0 : min(D.P.len[a], ol);
+      // rows of similar length (the longer at most (log2 of it - 1) times
+      // the shorter) are merged by a wave; the others walk the shorter row
+      // and search the longer, lane by lane
+      const bool merge = a != o && mn > 0 && (int64_t)mx <= (int64_t)mn * (30 - __clz(max(mx, 1)));
+      D.pair_len[base + k] = a == o || merge ? 0 : mn;
+      if (merge) D.pair_merge[atomicAdd(&D.dc[DC_MERGE], 1ull)] = (int32_t)(base + k);
     }
   }
 }
@@ -567,6 +574,49 @@ __global__ __launch_bounds__(TPB) void k_delta_c4(DeltaArgs D) {
   }
 }
 
+// The pairs (e, a) whose rows N(a) and N(o) have similar lengths: one wave
+// per pair merges both rows (wave_window_common); each common b != s closes
+// the path s - a - b - o.
+__global__ __launch_bounds__(TPB) void k_delta_c4_merge(DeltaArgs D) {
+  if (D.bstats[BS_RETRY]) return;
+  const int64_t nm = ctr(D.dc, DC_MERGE);
+  const unsigned long long idmask = (1ull << D.bits) - 1ull;
+  const int64_t w0 = gtid() >> 6, ws = gstride() >> 6;
+  int64_t acc = 0;
+  int cur_g = -1;
+  for (int64_t m = w0; m < nm; m += ws) {
+    const int64_t p = D.pair_merge[m];
+    const int32_t i = D.pair_edge[p];
+    const unsigned long long ek = D.ce[i];
+    const unsigned long long K = ek & DIR_KEY_MASK;
+    const uint32_t fe = (uint32_t)(ek >> DIR_MASK_SHIFT) & 3u;
+    const uint32_t u = (uint32_t)(K >> D.bits), v = (uint32_t)(K & idmask);
+    const uint32_t s = D.c4_side[i] ? v : u, o = s == u ? v : u;
+    const uint32_t eaj = D.P.col[D.P.off[s] + (p - D.c4_off[i])], a = eaj & GC_ID;
+    const uint32_t fsa = nib(eaj);
+    const int g = D.gid[u];
+    if (g != cur_g) {
+      // the wave's graph changes: flush per lane (wave-uniform branch)
+      if (cur_g >= 0 && acc) atomicAdd(&D.sig[SIG_IDX(cur_g, 1, SG_C4)], (unsigned long long)acc);
+      acc = 0;
+      cur_g = g;
+    }
+    wave_window_common(D.P.col + D.P.off[a], D.P.len[a], D.P.col + D.P.off[o], D.P.len[o],
+                       [&](uint32_t eab, uint32_t eob) {
+                         const uint32_t b = eab & GC_ID;
+                         if (b == s) return;
+                         const uint32_t fab = nib(eab), fob = nib(eob);
+                         const bool skip = (fsa && pkey(s, a, D.bits) < K) || (fab && pkey(a, b, D.bits) < K) ||
+                                           (fob && pkey(o, b, D.bits) < K);
+                         if (!skip) acc += delta_of(fe | fsa | fab | fob);
+                       });
+  }
+  if (cur_g >= 0) {
+    const int64_t t = wave_sum64(acc);
+    if (lane_id() == 0 && t) atomicAdd(&D.sig[SIG_IDX(cur_g, 1, SG_C4)], (unsigned long long)t);
+  }
+}
+
 // ------------------------------------------------ T(v) in the region path
 // After the triangle kernels of a region (or whole-graph) pass, t holds the
 // triangles of every upper entry (id order) of the region per version.  A
@@ -634,6 +684,7 @@ void launch_delta(const DeltaArgs& D, int slots, hipStream_t s) {
   hipLaunchKernelGGL(k_delta_vertex2, dim3(1024), dim3(TPB), 0, s, D);
   hipLaunchKernelGGL(k_delta_tv, dim3(1024), dim3(TPB), 0, s, D, (const unsigned long long*)sorted);
   hipLaunchKernelGGL(k_delta_c4, dim3(4096), dim3(TPB), 0, s, D);
+  hipLaunchKernelGGL(k_delta_c4_merge, dim3(4096), dim3(TPB), 0, s, D);
 }
 
 void launch_tv_region(int nv, const RegionDev& R, const int32_t* rlist, const unsigned long long* c,

@@ -174,7 +174,8 @@ void launch_combine(int nv, const unsigned long long* sig, long long* state, lon
 
 // capi.cpp: thread-local error text read by gc_last_error()
 // delta.hip: edge-local update of the Sigma terms of a one-batch pass
-enum { DC_EDGES = 0, DC_AFF, DC_AFF_TOTAL, DC_AFF_NEED, DC_SLOT_NEED, DC_QTRI, DC_QC4, DC_PAIR_NEED, DC_COUNT };
+enum { DC_EDGES = 0, DC_AFF, DC_AFF_TOTAL, DC_AFF_NEED, DC_SLOT_NEED, DC_QTRI, DC_QC4, DC_PAIR_NEED, DC_MERGE,
+       DC_COUNT };
 struct DeltaArgs {
   PoolDev P;                          // union view left by the tombstone merge
   int64_t N;
@@ -205,7 +206,8 @@ struct DeltaArgs {
   int32_t* c4_side;                   // [ce_cap] 0: walk from u, 1: from v
   int64_t* c4_off;                    // [ce_cap + 1] exclusive scan of c4_nch
   int32_t* pair_edge;                 // [pair_cap] changed edge of each pair
-  int32_t* pair_len;                  // [pair_cap] walk length of each pair
+  int32_t* pair_len;                  // [pair_cap] walk length of each pair (0: merged instead)
+  int32_t* pair_merge;                // [pair_cap] pairs whose rows are merged by a wave (DC_MERGE of them)
   int64_t* pair_off;                  // [pair_cap + 1] exclusive scan of pair_len
   int64_t pair_cap;
   void* scan_tmp;                     // scan scratch for max(ce_cap, pair_cap) + 1 entries

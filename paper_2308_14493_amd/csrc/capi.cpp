@@ -1026,14 +1026,6 @@ void size_delta(gc_graph* G, int64_t cap_t, int64_t ae_need, int64_t slot_need, 
 // from the sizes the kernels asked for and run the stage again.
 int settle_delta(gc_graph* G, const PassPlan& L, BatchWork& W);
 
-// Edge-local or region pass for a batch of `total` updates in half-decade
-// `b`: the kind with the smaller expected wall time.  Region time: this
-// bucket's mean, else the mean of all region passes (it hardly depends on
-// the batch).  Edge-local time: this bucket's mean, else the nearest
-// measured bucket's scaled by the batch size (its work grows with the
-// changed pairs), else a first try for batches of at most 1000 updates (also
-// while no region pass has been measured).
-// Both kinds measured in a bucket: every 32nd pass there tries the other.
 // Expected wall ms of the two kinds of one-batch pass (< 0: no estimate):
 // region, this bucket's mean, else the mean of all region passes;
 // edge-local, this bucket's mean, else the nearest measured bucket's scaled
@@ -1056,6 +1048,16 @@ int size_bucket(int64_t total) {
   return (int)std::min(15.0, std::floor(2.0 * std::log10((double)total + 1.0)));
 }
 
+// Edge-local or region pass for a batch of `total` updates in half-decade
+// `b`: the kind with the smaller expected wall time.  Region time: this
+// bucket's mean, else the mean of all region passes (it hardly depends on
+// the batch).  Edge-local time: this bucket's mean, else the nearest
+// measured bucket's scaled by the batch size (its work grows with the
+// changed pairs), else a first try for batches of at most 1000 updates (also
+// while no region pass has been measured).
+// Both kinds measured in a bucket: every 32nd pass there tries the other.
+// A bucket with no edge-local pass yet tries one while the carried-over
+// estimate is within 1.5x of the region's.
 bool choose_delta(gc_graph* G, int b, int64_t total) {
   const int64_t* n = G->mode_n[b];
   // nothing measured for the region kind yet: small batches start edge-local
@@ -1067,6 +1069,11 @@ bool choose_delta(gc_graph* G, int b, int64_t total) {
   double est_r, est_d;
   pass_estimates(G, b, total, est_r, est_d);
   if (est_d < 0) return total <= 1000;
+  // an edge-local estimate carried over from another bucket scales that
+  // bucket's time (fixed costs included) by the batch size, so it runs
+  // high for larger batches: the first edge-local try in a bucket is taken
+  // while it is within 1.5x of the region estimate
+  if (n[1] == 0) return est_d < 1.5 * est_r;
   return est_d < est_r;
 }
 

@@ -311,9 +311,10 @@ __global__ void k_delta_aff(DeltaArgs D, const unsigned long long* __restrict__ 
     const uint32_t* arow = D.P.col + D.P.off[a];
     const int32_t al = D.P.len[a], bl = D.P.len[b];
     int32_t tb = 0, ta = 0;
-    if (al > 0 && (int64_t)bl <= (int64_t)al * (30 - __clz(max(bl, 1)))) {
-      // rows of similar length: both walked together, 64 entries of each a
-      // step, instead of a search of the longer row per entry of the shorter
+    if (al > 0 && (int64_t)bl <= (int64_t)al * ((30 - __clz(max(bl, 1))) / 2)) {
+      // rows of similar length (as for the 4-cycle pairs): both walked
+      // together, 64 entries of each a step, instead of a search of the
+      // longer row per entry of the shorter
       wave_window_common(arow, al, D.P.col + D.P.off[b], bl, [&](uint32_t ea, uint32_t eb) {
         const uint32_t f = nib(ea) | nib(eb);
         tb += (f & 1u) == 0;
@@ -455,10 +456,10 @@ __global__ void k_delta_c4_pairs(DeltaArgs D) {
       const int32_t al = D.P.len[a];
       const int32_t mn = min(al, ol), mx = max(al, ol);
       D.pair_edge[base + k] = (int32_t)i;
-      // rows of similar length (the longer at most (log2 of it - 1) times
-      // the shorter) are merged by a wave; the others walk the shorter row
-      // and search the longer, lane by lane
-      const bool merge = a != o && mn > 0 && (int64_t)mx <= (int64_t)mn * (30 - __clz(max(mx, 1)));
+      // rows of similar length (the longer at most (log2 of it - 1) / 2
+      // times the shorter, the best split measured) are merged by a wave;
+      // the others walk the shorter row and search the longer, lane by lane
+      const bool merge = a != o && mn > 0 && (int64_t)mx <= (int64_t)mn * ((30 - __clz(max(mx, 1))) / 2);
       D.pair_len[base + k] = a == o || merge ? 0 : mn;
       if (merge) D.pair_merge[atomicAdd(&D.dc[DC_MERGE], 1ull)] = (int32_t)(base + k);
     }

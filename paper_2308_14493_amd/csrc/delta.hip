@@ -183,7 +183,11 @@ __global__ __launch_bounds__(TPB) void k_delta_tri(DeltaArgs D) {
   __shared__ int64_t item_s;
   __shared__ int32_t ns_s;
   const int64_t ne = min(ctr(D.dc, DC_EDGES), D.ce_cap);
-  unsigned long long* mark = D.slot_mark + (int64_t)blockIdx.x * D.N;
+  // marks of S(e), one byte per vertex (bit 7 set, the nibbles of (u, w) and
+  // (v, w) in bits 0-1 and 2-3) in the first N bytes of the workgroup's
+  // slot (denser than a word per vertex for the random reads of the
+  // 4-clique step); all zero again when the kernel ends
+  uint8_t* mark = (uint8_t*)(D.slot_mark + (int64_t)blockIdx.x * D.N);
   uint32_t* S = D.slot_list + (int64_t)blockIdx.x * D.slot_cap;
   const unsigned long long idmask = (1ull << D.bits) - 1ull;
   int64_t k4acc = 0;
@@ -218,7 +222,7 @@ __global__ __launch_bounds__(TPB) void k_delta_tri(DeltaArgs D) {
       if (p < 0) continue;
       const uint32_t eo = D.P.col[p];
       const uint32_t fu = nib(s == u ? es : eo), fv = nib(s == u ? eo : es);
-      mark[w] = 0x100ull | fu | (fv << 4);
+      mark[w] = (uint8_t)(0x80u | fu | (fv << 2));
       S[atomicAdd(&ns_s, 1)] = w;
       // affected edges (u, w), (v, w)
       const unsigned long long q = atomicAdd(&D.dc[DC_AFF], 2ull);
@@ -229,15 +233,15 @@ __global__ __launch_bounds__(TPB) void k_delta_tri(DeltaArgs D) {
     // 4-cliques: pairs w < x in S(e) with an edge (w, x)
     for (int32_t i = threadIdx.x >> 6; i < ns; i += blockDim.x >> 6) {
       const uint32_t w = S[i];
-      const unsigned long long mw = mark[w];
+      const uint32_t mw = mark[w];
       const uint32_t* wrow = D.P.col + D.P.off[w];
       const int32_t wl = D.P.len[w];
       const int32_t above = lower_bound_id(wrow, wl, w + 1);
       const int32_t nab = wl - above;
       int64_t acc = 0;
-      auto clique = [&](uint32_t x, uint32_t fwx, unsigned long long mx) {
-        const uint32_t fuw = (uint32_t)mw & 15u, fvw = (uint32_t)(mw >> 4) & 15u;
-        const uint32_t fux = (uint32_t)mx & 15u, fvx = (uint32_t)(mx >> 4) & 15u;
+      auto clique = [&](uint32_t x, uint32_t fwx, uint32_t mx) {
+        const uint32_t fuw = mw & 3u, fvw = (mw >> 2) & 3u;
+        const uint32_t fux = mx & 3u, fvx = (mx >> 2) & 3u;
         // counted from the changed edge of smallest key only
         if ((fuw && pkey(u, w, D.bits) < K) || (fvw && pkey(v, w, D.bits) < K) || (fux && pkey(u, x, D.bits) < K) ||
             (fvx && pkey(v, x, D.bits) < K) || (fwx && pkey(w, x, D.bits) < K))
@@ -247,7 +251,7 @@ __global__ __launch_bounds__(TPB) void k_delta_tri(DeltaArgs D) {
       if (nab <= ns) {
         for (int32_t k = above + lane_id(); k < wl; k += 64) {
           const uint32_t ex = wrow[k], x = ex & GC_ID;
-          const unsigned long long mx = mark[x];
+          const uint32_t mx = mark[x];
           if (mx) clique(x, nib(ex), mx);
         }
       } else {
@@ -261,7 +265,7 @@ __global__ __launch_bounds__(TPB) void k_delta_tri(DeltaArgs D) {
       k4acc += acc;
     }
     __syncthreads();
-    for (int32_t i = threadIdx.x; i < ns; i += blockDim.x) mark[S[i]] = 0ull;
+    for (int32_t i = threadIdx.x; i < ns; i += blockDim.x) mark[S[i]] = 0;
   }
   if (cur_g >= 0) add_sig(D, cur_g, SG_K4, k4acc);
 }

@@ -178,6 +178,7 @@ typedef struct {
   int32_t delta;                     /* 1: the pass was edge-local (gc_options.delta) */
   int64_t tri_entries;               /* adjacency entries read by the triangle tiers (N+(u) and each N+(v) probed) */
   int32_t tri_small_max, c4_small_max, c4_mid_max;  /* tier thresholds of the pass (gc_options) */
+  int64_t k4_split_edges;            /* edge-local: changed edges whose 4-cliques were spread over workgroups */
 } gc_batch_stats;
 
 /* One batch for one graph of a pool (host pointers). */

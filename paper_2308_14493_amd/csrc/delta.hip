@@ -179,8 +179,53 @@ __global__ void k_delta_s2(DeltaArgs D) {
 // nibbles of (u, w) and (v, w).  Then every pair {w, x} of S(e) joined by an
 // edge closes a 4-clique {u, v, w, x}: for each w, the shorter of its row
 // above w and S(e) is tested against the other.
+// 4-cliques {u, v, w, x} through the changed edge (u, v) (key K, nibble fe)
+// for the common neighbours w = S[i], i in [i0, i1) (one wave per w, the
+// workgroup's waves in turn): x runs over S(e) above w, joined to w by an
+// edge; S(e) is marked in `mark` (a byte per vertex: bit 7, the nibble of
+// (u, x) in bits 0-1 and of (v, x) in bits 2-3) and listed in S (ids, flag
+// bits above them ignored).  Returns this lane's share of the sum.
+__device__ int64_t k4_through(const DeltaArgs& D, const uint8_t* mark, const uint32_t* S, int32_t ns, int32_t i0,
+                              int32_t i1, uint32_t u, uint32_t v, unsigned long long K, uint32_t fe) {
+  int64_t k4 = 0;
+  for (int32_t i = i0 + (int32_t)(threadIdx.x >> 6); i < i1; i += (int32_t)(blockDim.x >> 6)) {
+    const uint32_t w = S[i] & GC_ID;
+    const uint32_t mw = mark[w];
+    const uint32_t* wrow = D.P.col + D.P.off[w];
+    const int32_t wl = D.P.len[w];
+    const int32_t above = lower_bound_id(wrow, wl, w + 1);
+    const int32_t nab = wl - above;
+    int64_t acc = 0;
+    auto clique = [&](uint32_t x, uint32_t fwx, uint32_t mx) {
+      const uint32_t fuw = mw & 3u, fvw = (mw >> 2) & 3u;
+      const uint32_t fux = mx & 3u, fvx = (mx >> 2) & 3u;
+      // counted from the changed edge of smallest key only
+      if ((fuw && pkey(u, w, D.bits) < K) || (fvw && pkey(v, w, D.bits) < K) || (fux && pkey(u, x, D.bits) < K) ||
+          (fvx && pkey(v, x, D.bits) < K) || (fwx && pkey(w, x, D.bits) < K))
+        return;
+      acc += delta_of(fe | fuw | fvw | fux | fvx | fwx);
+    };
+    if (nab <= ns) {
+      for (int32_t k = above + lane_id(); k < wl; k += 64) {
+        const uint32_t ex = wrow[k], x = ex & GC_ID;
+        const uint32_t mx = mark[x];
+        if (mx) clique(x, nib(ex), mx);
+      }
+    } else {
+      for (int32_t j = lane_id(); j < ns; j += 64) {
+        const uint32_t x = S[j] & GC_ID;
+        if (x <= w) continue;
+        const int32_t p = lower_bound_id(wrow, wl, x);
+        if (p < wl && (wrow[p] & GC_ID) == x) clique(x, nib(wrow[p]), mark[x]);
+      }
+    }
+    k4 += acc;
+  }
+  return k4;
+}
+
 __global__ __launch_bounds__(TPB) void k_delta_tri(DeltaArgs D) {
-  __shared__ int64_t item_s;
+  __shared__ int64_t item_s, split_s;
   __shared__ int32_t ns_s;
   const int64_t ne = min(ctr(D.dc, DC_EDGES), D.ce_cap);
   // marks of S(e), one byte per vertex (bit 7 set, the nibbles of (u, w) and
@@ -230,43 +275,110 @@ __global__ __launch_bounds__(TPB) void k_delta_tri(DeltaArgs D) {
     }
     __syncthreads();
     const int32_t ns = ns_s;
-    // 4-cliques: pairs w < x in S(e) with an edge (w, x)
-    for (int32_t i = threadIdx.x >> 6; i < ns; i += blockDim.x >> 6) {
-      const uint32_t w = S[i];
-      const uint32_t mw = mark[w];
-      const uint32_t* wrow = D.P.col + D.P.off[w];
-      const int32_t wl = D.P.len[w];
-      const int32_t above = lower_bound_id(wrow, wl, w + 1);
-      const int32_t nab = wl - above;
-      int64_t acc = 0;
-      auto clique = [&](uint32_t x, uint32_t fwx, uint32_t mx) {
-        const uint32_t fuw = mw & 3u, fvw = (mw >> 2) & 3u;
-        const uint32_t fux = mx & 3u, fvx = (mx >> 2) & 3u;
-        // counted from the changed edge of smallest key only
-        if ((fuw && pkey(u, w, D.bits) < K) || (fvw && pkey(v, w, D.bits) < K) || (fux && pkey(u, x, D.bits) < K) ||
-            (fvx && pkey(v, x, D.bits) < K) || (fwx && pkey(w, x, D.bits) < K))
-          return;
-        acc += delta_of(fe | fuw | fvw | fux | fvx | fwx);
-      };
-      if (nab <= ns) {
-        for (int32_t k = above + lane_id(); k < wl; k += 64) {
-          const uint32_t ex = wrow[k], x = ex & GC_ID;
-          const uint32_t mx = mark[x];
-          if (mx) clique(x, nib(ex), mx);
+    // an edge with many common neighbours hands its 4-cliques to
+    // k_delta_k4_split in chunks (when the fixed buffers hold it)
+    if (ns >= K4_HEAVY_MIN) {
+      if (threadIdx.x == 0) {
+        const int32_t nch = (ns + K4_CHUNK - 1) / K4_CHUNK;
+        int64_t off = (int64_t)atomicAdd(&D.dc[DC_HS], (unsigned long long)ns);
+        bool ok = off + ns <= K4_HS_CAP;
+        int64_t first = -1;
+        if (ok) {
+          first = (int64_t)atomicAdd(&D.dc[DC_HITEMS], (unsigned long long)nch);
+          if (first + nch > K4_IT_CAP) {
+            for (int64_t t = first; t < min(first + nch, K4_IT_CAP); ++t) D.k4_item[2 * t] = -1;
+            ok = false;
+          }
         }
-      } else {
-        for (int32_t j = lane_id(); j < ns; j += 64) {
-          const uint32_t x = S[j];
-          if (x <= w) continue;
-          const int32_t p = lower_bound_id(wrow, wl, x);
-          if (p < wl && (wrow[p] & GC_ID) == x) clique(x, nib(wrow[p]), mark[x]);
+        if (ok) {
+          const int64_t h = (int64_t)atomicAdd(&D.dc[DC_HEAVY], 1ull);
+          if (h >= K4_HE_CAP) {
+            for (int64_t t = first; t < first + nch; ++t) D.k4_item[2 * t] = -1;
+            ok = false;
+          } else {
+            D.k4_edge[3 * h] = it;
+            D.k4_edge[3 * h + 1] = off;
+            D.k4_edge[3 * h + 2] = ns;
+            for (int32_t c = 0; c < nch; ++c) {
+              D.k4_item[2 * (first + c)] = (int32_t)h;
+              D.k4_item[2 * (first + c) + 1] = c;
+            }
+            atomicAdd(&D.bstats[BS_K4_SPLIT], 1ull);
+          }
         }
+        split_s = ok ? off : -1;
       }
-      k4acc += acc;
+      __syncthreads();
+    } else if (threadIdx.x == 0) {
+      split_s = -1;
+    }
+    __syncthreads();
+    const int64_t off = split_s;
+    if (off >= 0) {
+      for (int32_t i = threadIdx.x; i < ns; i += blockDim.x) {
+        const uint32_t w = S[i], m = mark[w];
+        D.k4_s[off + i] = w | ((m & 3u) << 28) | (((m >> 2) & 3u) << 30);
+      }
+    } else {
+      k4acc += k4_through(D, mark, S, ns, 0, ns, u, v, K, fe);
     }
     __syncthreads();
     for (int32_t i = threadIdx.x; i < ns; i += blockDim.x) mark[S[i]] = 0;
   }
+  if (cur_g >= 0) add_sig(D, cur_g, SG_K4, k4acc);
+}
+
+// The 4-cliques of the edges k_delta_tri split: each workgroup takes chunks
+// of K4_CHUNK common neighbours from a queue, marks the edge's common
+// neighbours in its own slot (kept while the next chunk is of the same
+// edge) and counts the chunk's 4-cliques; the slot is clear on return.
+__global__ __launch_bounds__(TPB) void k_delta_k4_split(DeltaArgs D) {
+  if (D.bstats[BS_RETRY]) return;
+  __shared__ int64_t item_s;
+  const int64_t nit = min((int64_t)ctr(D.dc, DC_HITEMS), K4_IT_CAP);
+  uint8_t* mark = (uint8_t*)(D.slot_mark + (int64_t)blockIdx.x * D.N);
+  const unsigned long long idmask = (1ull << D.bits) - 1ull;
+  int64_t k4acc = 0;
+  int cur_g = -1;
+  int32_t cur_h = -1, cur_ns = 0;
+  const uint32_t* cur_S = nullptr;
+  while (true) {
+    __syncthreads();
+    if (threadIdx.x == 0) item_s = (int64_t)atomicAdd(&D.dc[DC_QK4], 1ull);
+    __syncthreads();
+    const int64_t t = item_s;
+    if (t >= nit) break;
+    const int32_t h = D.k4_item[2 * t], c = D.k4_item[2 * t + 1];
+    if (h < 0) continue;
+    const int64_t i = D.k4_edge[3 * h], off = D.k4_edge[3 * h + 1];
+    const int32_t ns = (int32_t)D.k4_edge[3 * h + 2];
+    const uint32_t* Sh = D.k4_s + off;
+    if (h != cur_h) {
+      for (int32_t j = threadIdx.x; j < cur_ns; j += blockDim.x) mark[cur_S[j] & GC_ID] = 0;
+      __syncthreads();
+      for (int32_t j = threadIdx.x; j < ns; j += blockDim.x) {
+        const uint32_t e = Sh[j];
+        mark[e & GC_ID] = (uint8_t)(0x80u | ((e >> 28) & 3u) | (((e >> 30) & 3u) << 2));
+      }
+      __syncthreads();
+      cur_h = h;
+      cur_ns = ns;
+      cur_S = Sh;
+    }
+    const unsigned long long ek = D.ce[i];
+    const unsigned long long K = ek & DIR_KEY_MASK;
+    const uint32_t fe = (uint32_t)(ek >> DIR_MASK_SHIFT) & 3u;
+    const uint32_t u = (uint32_t)(K >> D.bits), v = (uint32_t)(K & idmask);
+    const int g = D.gid[u];
+    if (g != cur_g) {
+      if (cur_g >= 0) add_sig(D, cur_g, SG_K4, k4acc);
+      k4acc = 0;
+      cur_g = g;
+    }
+    k4acc += k4_through(D, mark, Sh, ns, c * K4_CHUNK, min(ns, (c + 1) * K4_CHUNK), u, v, K, fe);
+  }
+  __syncthreads();
+  for (int32_t j = threadIdx.x; j < cur_ns; j += blockDim.x) mark[cur_S[j] & GC_ID] = 0;
   if (cur_g >= 0) add_sig(D, cur_g, SG_K4, k4acc);
 }
 
@@ -677,6 +789,7 @@ void launch_delta(const DeltaArgs& D, int slots, hipStream_t s) {
   // every kernel that can find a buffer too small (and raise BS_RETRY)
   // runs before the first one that moves T(v) or clears scratch
   hipLaunchKernelGGL(k_delta_tri, dim3(slots), dim3(TPB), 0, s, D);
+  hipLaunchKernelGGL(k_delta_k4_split, dim3(slots), dim3(TPB), 0, s, D);
   hipLaunchKernelGGL(k_delta_aff_changed, dim3(1024), dim3(TPB), 0, s, D);
   hipLaunchKernelGGL(k_delta_c4_plan, dim3(1024), dim3(TPB), 0, s, D);
   exclusive_scan_i32_to_i64(D.c4_nch, D.c4_off, D.ce_cap, D.scan_tmp, s);

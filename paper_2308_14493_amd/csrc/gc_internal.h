@@ -70,6 +70,7 @@ enum {
   BS_TRI_GLOBAL,  // vertices counted by the global-scratch triangle tier
   BS_TRI_REBUILD, // vertices whose version-specific edges overflowed the exception list
   BS_TRI_E,       // adjacency entries the triangle tiers read: N+(u) and the lists N+(v) probed
+  BS_K4_SPLIT,    // changed edges whose edge-local 4-cliques were split into chunks
   BS_COUNT
 };
 

@@ -175,7 +175,16 @@ void launch_combine(int nv, const unsigned long long* sig, long long* state, lon
 // capi.cpp: thread-local error text read by gc_last_error()
 // delta.hip: edge-local update of the Sigma terms of a one-batch pass
 enum { DC_EDGES = 0, DC_AFF, DC_AFF_TOTAL, DC_AFF_NEED, DC_SLOT_NEED, DC_QTRI, DC_QC4, DC_PAIR_NEED, DC_MERGE,
-       DC_COUNT };
+       DC_HS, DC_HITEMS, DC_HEAVY, DC_QK4, DC_COUNT };
+// 4-cliques of changed edges with many common neighbours, spread over the
+// workgroups in chunks: the common neighbours of such edges (with their
+// flags), the edges, and the chunks (fixed capacities; an edge that does not
+// fit is counted in place)
+constexpr int K4_HEAVY_MIN = 256;       // common neighbours from which an edge is split
+constexpr int K4_CHUNK = 64;            // common neighbours per chunk
+constexpr int64_t K4_HS_CAP = 1 << 22;  // stored common neighbours
+constexpr int64_t K4_HE_CAP = 1 << 14;  // split edges
+constexpr int64_t K4_IT_CAP = 1 << 18;  // chunks
 struct DeltaArgs {
   PoolDev P;                          // union view left by the tombstone merge
   int64_t N;
@@ -208,6 +217,9 @@ struct DeltaArgs {
   int32_t* pair_edge;                 // [pair_cap] changed edge of each pair
   int32_t* pair_len;                  // [pair_cap] walk length of each pair (0: merged instead)
   int32_t* pair_merge;                // [pair_cap] pairs whose rows are merged by a wave (DC_MERGE of them)
+  uint32_t* k4_s;                     // [K4_HS_CAP] common neighbours of split edges: id | nibble(u, w) << 28 | nibble(v, w) << 30
+  int64_t* k4_edge;                   // [K4_HE_CAP][3] split edges: changed edge index, offset in k4_s, count
+  int32_t* k4_item;                   // [K4_IT_CAP][2] chunks: split edge (-1: none), chunk index
   int64_t* pair_off;                  // [pair_cap + 1] exclusive scan of pair_len
   int64_t pair_cap;
   void* scan_tmp;                     // scan scratch for max(ce_cap, pair_cap) + 1 entries

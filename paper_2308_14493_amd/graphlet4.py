@@ -41,7 +41,7 @@ class BatchStats(ctypes.Structure):
                                       "ms_c4_mid", "ms_c4_large", "ms_finish")] + [
         ("c4_windows", _I64), ("c4_searches", _I64), ("tri_global_vertices", _I64), ("tri_exc_rebuilds", _I64),
         ("retries", _I32), ("delta", _I32), ("tri_entries", _I64),
-        ("tri_small_max", _I32), ("c4_small_max", _I32), ("c4_mid_max", _I32)]
+        ("tri_small_max", _I32), ("c4_small_max", _I32), ("c4_mid_max", _I32), ("k4_split_edges", _I64)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}

@@ -111,12 +111,15 @@ def test_delta_hub_pair_scratch_growth():
     E = {(0, 1)} | {(0, w) for w in range(2, 6002)} | {(1, w) for w in range(2, 6002)}
     E |= {(w, w + 1) for w in range(2, 8999)}
     with Graph(n, *esorted(E), delta=1) as g:
-        for b in (([], [], [0], [1]), ([1], [0], [], []), ([0, 1], [8500, 8600], [2], [3])):
+        for j, b in enumerate((([], [], [0], [1]), ([1], [0], [], []), ([0, 1], [8500, 8600], [2], [3]))):
             b = [np.array(x, np.int32) for x in b]
             got, st = g.apply_batch(*b, stats=True)
             oracle_apply(E, n, *b)
-            say("  retries %d" % st["retries"])
+            say("  retries %d, split edges %d" % (st["retries"], st["k4_split_edges"]))
             assert got == native.static_counts(n, *esorted(E))
+            if j < 2:
+                # (0, 1) and its 6000 common neighbours: 4-cliques in chunks
+                assert st["k4_split_edges"] >= 1
 
 
 def test_delta_and_region_alternate():

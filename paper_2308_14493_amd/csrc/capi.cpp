@@ -215,7 +215,7 @@ struct gc_graph {
   // triangles at each vertex (kept for the edge-local passes) and the
   // scratch of those passes
   DevBuf Tv, dTs, sbt, ce, ae, ae_alt, slot_list, dctr, c4_nch, c4_side, c4_off, pair_edge, pair_len, pair_off,
-      pair_merge, k4_s, k4_edge, k4_item;
+      pair_merge, k4_s, k4_edge, k4_item, tv_items, tv_ioff;
   int64_t ae_cap = 0, slot_cap = 0, pair_cap = 0;
   // cost model of the two kinds of one-batch pass (autotune): per
   // half-decade of batch size and kind (0 region, 1 edge-local), the mean
@@ -997,6 +997,9 @@ DeltaArgs make_delta_args(gc_graph* G, const BatchWork& W) {
   D.k4_s = G->k4_s.as<uint32_t>();
   D.k4_edge = G->k4_edge.as<int64_t>();
   D.k4_item = G->k4_item.as<int32_t>();
+  D.tv_items = G->tv_items.as<int32_t>();
+  D.tv_ioff = G->tv_ioff.as<int64_t>();
+  D.tcap = 2 * (int64_t)(G->ce.cap / 8);
   D.pair_off = G->pair_off.as<int64_t>();
   D.pair_cap = G->pair_cap;
   D.scan_tmp = G->scan_tmp.p;
@@ -1018,8 +1021,11 @@ void size_delta(gc_graph* G, int64_t cap_t, int64_t ae_need, int64_t slot_need, 
   G->k4_s.ensure(K4_HS_CAP * 4);
   G->k4_edge.ensure(K4_HE_CAP * 3 * 8);
   G->k4_item.ensure(K4_IT_CAP * 2 * 4);
+  // touched rows: at most both ends of every change
+  G->tv_items.ensure(2 * (G->ce.cap / 8) * 4);
+  G->tv_ioff.ensure((2 * (G->ce.cap / 8) + 1) * 8);
   G->pair_off.ensure((G->pair_cap + 1) * 8);
-  G->scan_tmp.ensure(scan_tmp_bytes(std::max<int64_t>(G->ce.cap / 8, G->pair_cap) + 1) + 64);
+  G->scan_tmp.ensure(scan_tmp_bytes(std::max<int64_t>(2 * (G->ce.cap / 8), G->pair_cap) + 1) + 64);
   G->ae_cap = std::max<int64_t>(G->ae_cap, std::max<int64_t>(ae_need, 8 * cap_t + 4096));
   G->ae.ensure(G->ae_cap * 8);
   G->ae_alt.ensure(G->ae_cap * 8);
@@ -1208,7 +1214,8 @@ std::vector<uint64_t> pass_signature(gc_graph* G, const PassPlan& L, const Count
                           &G->tp, &G->vpos, &G->level, &G->rlist, &G->rlen, &G->lists, &G->c4_dense, &G->c4_touch,
                           &G->c4_cur, &G->c4_blk, &G->c4_keys, &G->c4_keys_alt, &G->tri_scratch, &G->Tv, &G->dTs,
                           &G->sbt, &G->ce, &G->ae, &G->ae_alt, &G->slot_list, &G->dctr, &G->c4_nch, &G->c4_side,
-                          &G->c4_off, &G->pair_edge, &G->pair_len, &G->pair_off, &G->dead_d, &G->pair_merge, &G->k4_s, &G->k4_edge, &G->k4_item};
+                          &G->c4_off, &G->pair_edge, &G->pair_len, &G->pair_off, &G->dead_d, &G->pair_merge, &G->k4_s, &G->k4_edge, &G->k4_item, &G->tv_items,
+                          &G->tv_ioff};
   for (const DevBuf* b : bufs) v.push_back((uint64_t)(uintptr_t)b->p);
   v.push_back((uint64_t)(uintptr_t)G->pin);
   v.push_back((uint64_t)(uintptr_t)G->pout);

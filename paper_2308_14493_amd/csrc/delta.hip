@@ -120,32 +120,76 @@ __global__ void k_delta_edges(DeltaArgs D) {
 }
 
 // ------------------------------------------------------- touched vertices
-// One wave per touched row: its degree before and after; the 3-star, wedge
-// and degree-sum terms.
+// The touched rows are cut in pieces of at most TV_CHUNK entries (a hub row
+// in many), numbered by a scan, and each wave takes one piece at a time: no
+// wave walks a whole hub row alone.
+
+// pieces per touched row (0 past the touched count, for the scan)
+__global__ void k_delta_titems(DeltaArgs D) {
+  const int64_t nt = ctr(D.c, C_TOUCH);
+  for (int64_t t = gtid(); t < D.tcap; t += gstride()) {
+    int32_t n = 0;
+    if (t < nt) {
+      const int32_t x = D.touched[t];
+      n = max(1, (D.P.len[x] + TV_CHUNK - 1) / TV_CHUNK);
+      D.dd[2 * (int64_t)x] = 0;
+      D.dd[2 * (int64_t)x + 1] = 0;
+    }
+    D.tv_items[t] = n;
+  }
+}
+
+// touched row and entry range of piece k (wave-uniform)
+__device__ __forceinline__ void touched_piece(const DeltaArgs& D, int64_t nt, int64_t k, uint32_t& x, int32_t& k0,
+                                              int32_t& k1) {
+  int64_t lo = 0, hi = nt;  // largest t with tv_ioff[t] <= k
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (D.tv_ioff[mid] <= k) lo = mid; else hi = mid;
+  }
+  x = (uint32_t)D.touched[lo];
+  k0 = (int32_t)((k - D.tv_ioff[lo]) * TV_CHUNK);
+  k1 = min(D.P.len[x], k0 + TV_CHUNK);
+}
+
+// degrees of the touched rows before and after the batch, by pieces
 __global__ void k_delta_vertex(DeltaArgs D) {
   const int64_t nt = ctr(D.c, C_TOUCH);
+  if (nt == 0) return;
+  const int64_t np = D.tv_ioff[nt];
   const int l = lane_id();
   const int64_t w0 = gtid() >> 6, ws = gstride() >> 6;
-  for (int64_t t = w0; t < nt; t += ws) {
-    const uint32_t x = (uint32_t)D.touched[t];
+  for (int64_t k = w0; k < np; k += ws) {
+    uint32_t x;
+    int32_t k0, k1;
+    touched_piece(D, nt, k, x, k0, k1);
     const uint32_t* row = D.P.col + D.P.off[x];
-    const int32_t L = D.P.len[x];
     int32_t db = 0, da = 0;
-    for (int32_t k = l; k < L; k += 64) {
-      const uint32_t f = nib(row[k]);
+    for (int32_t q = k0 + l; q < k1; q += 64) {
+      const uint32_t f = nib(row[q]);
       db += (f & 1u) == 0;
       da += (f & 2u) == 0;
     }
     db = wave_sum32(db);
     da = wave_sum32(da);
-    if (l == 0) { D.dd[2 * (int64_t)x] = db; D.dd[2 * (int64_t)x + 1] = da; }
-    const int g = D.gid[x];
     if (l == 0) {
-      const int64_t s1 = c3(da) - c3(db), w2 = c2(da) - c2(db), d1 = (int64_t)da - db;
-      if (s1) atomicAdd(&D.sig[SIG_IDX(g, 1, SG_S1)], (unsigned long long)s1);
-      if (w2) atomicAdd(&D.sig[SIG_IDX(g, 1, SG_W)], (unsigned long long)w2);
-      if (d1) atomicAdd(&D.sig[SIG_IDX(g, 1, SG_D1)], (unsigned long long)d1);
+      if (db) atomicAdd(&D.dd[2 * (int64_t)x], db);
+      if (da) atomicAdd(&D.dd[2 * (int64_t)x + 1], da);
     }
+  }
+}
+
+// the 3-star, wedge and degree-sum terms of each touched vertex
+__global__ void k_delta_vertex_fin(DeltaArgs D) {
+  const int64_t nt = ctr(D.c, C_TOUCH);
+  for (int64_t t = gtid(); t < nt; t += gstride()) {
+    const uint32_t x = (uint32_t)D.touched[t];
+    const int64_t db = D.dd[2 * (int64_t)x], da = D.dd[2 * (int64_t)x + 1];
+    const int g = D.gid[x];
+    const int64_t s1 = c3(da) - c3(db), w2 = c2(da) - c2(db), d1 = da - db;
+    if (s1) atomicAdd(&D.sig[SIG_IDX(g, 1, SG_S1)], (unsigned long long)s1);
+    if (w2) atomicAdd(&D.sig[SIG_IDX(g, 1, SG_W)], (unsigned long long)w2);
+    if (d1) atomicAdd(&D.sig[SIG_IDX(g, 1, SG_D1)], (unsigned long long)d1);
   }
 }
 
@@ -153,16 +197,19 @@ __global__ void k_delta_vertex(DeltaArgs D) {
 // an edge between two touched vertices is taken at the smaller id.
 __global__ void k_delta_s2(DeltaArgs D) {
   const int64_t nt = ctr(D.c, C_TOUCH);
+  if (nt == 0) return;
+  const int64_t np = D.tv_ioff[nt];
   const int l = lane_id();
   const int64_t w0 = gtid() >> 6, ws = gstride() >> 6;
-  for (int64_t t = w0; t < nt; t += ws) {
-    const uint32_t x = (uint32_t)D.touched[t];
+  for (int64_t k = w0; k < np; k += ws) {
+    uint32_t x;
+    int32_t k0, k1;
+    touched_piece(D, nt, k, x, k0, k1);
     const uint32_t* row = D.P.col + D.P.off[x];
-    const int32_t L = D.P.len[x];
     const int64_t dbx = D.dd[2 * (int64_t)x] - 1, dax = D.dd[2 * (int64_t)x + 1] - 1;
     int64_t acc = 0;
-    for (int32_t k = l; k < L; k += 64) {
-      const uint32_t e = row[k], y = e & GC_ID, f = nib(e);
+    for (int32_t q = k0 + l; q < k1; q += 64) {
+      const uint32_t e = row[q], y = e & GC_ID, f = nib(e);
       if (D.mark[y] && y < x) continue;
       if ((f & 2u) == 0) acc += dax * (deg_of(D, y, 1) - 1);
       if ((f & 1u) == 0) acc -= dbx * (deg_of(D, y, 0) - 1);
@@ -519,32 +566,74 @@ __global__ void k_delta_tv(DeltaArgs D, const unsigned long long* __restrict__ k
 // scan places the walked entries of all pairs in one index space, and each
 // lane takes entries of that space (a hub pair is spread over many waves).
 
-// per changed edge: the end to walk from and its number of pairs
+// per changed edge: the end to walk from and its number of pairs.  The
+// walk of an end u costs sum_{a in N(u)} min(d_a, d_v); both rows of every
+// changed edge are cut in pieces of at most TV_CHUNK entries (the touched
+// rows' arrays hold the numbering; they are free again after the degree
+// passes), each wave sums one piece at a time into the edge's two totals
+// (kept in pair_off, free until the pair scan), and a last pass picks the
+// cheaper end.
+__global__ void k_delta_plan_items(DeltaArgs D) {
+  const int64_t ne = min(ctr(D.dc, DC_EDGES), D.ce_cap);
+  const unsigned long long idmask = (1ull << D.bits) - 1ull;
+  for (int64_t i = gtid(); i < D.tcap; i += gstride()) {
+    int32_t n = 0;
+    if (i < ne) {
+      const unsigned long long K = D.ce[i] & DIR_KEY_MASK;
+      const uint32_t u = (uint32_t)(K >> D.bits), v = (uint32_t)(K & idmask);
+      n = max(1, (D.P.len[u] + TV_CHUNK - 1) / TV_CHUNK) + max(1, (D.P.len[v] + TV_CHUNK - 1) / TV_CHUNK);
+      D.pair_off[2 * i] = 0;
+      D.pair_off[2 * i + 1] = 0;
+    }
+    D.tv_items[i] = n;
+  }
+}
+
 __global__ void k_delta_c4_plan(DeltaArgs D) {
   const int64_t ne = min(ctr(D.dc, DC_EDGES), D.ce_cap);
+  if (ne == 0) return;
+  const int64_t np = D.tv_ioff[ne];
   const unsigned long long idmask = (1ull << D.bits) - 1ull;
   const int l = lane_id();
   const int64_t w0 = gtid() >> 6, ws = gstride() >> 6;
-  for (int64_t i = w0; i < D.ce_cap; i += ws) {
+  for (int64_t k = w0; k < np; k += ws) {
+    int64_t lo = 0, hi = ne;  // the edge holding piece k
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (D.tv_ioff[mid] <= k) lo = mid; else hi = mid;
+    }
+    const int64_t i = lo;
+    const unsigned long long K = D.ce[i] & DIR_KEY_MASK;
+    const uint32_t u = (uint32_t)(K >> D.bits), v = (uint32_t)(K & idmask);
+    const int32_t du = D.P.len[u], dv = D.P.len[v];
+    const int64_t nu = max(1, (du + TV_CHUNK - 1) / TV_CHUNK);
+    const int64_t pk = k - D.tv_ioff[i];
+    const bool side_v = pk >= nu;  // pieces of u first, then of v
+    const uint32_t x = side_v ? v : u;
+    const int32_t dx = side_v ? dv : du, other = side_v ? du : dv;
+    const int32_t k0 = (int32_t)((side_v ? pk - nu : pk) * TV_CHUNK), k1 = min(dx, k0 + TV_CHUNK);
+    const uint32_t* rx = D.P.col + D.P.off[x];
+    int64_t c = 0;
+    for (int32_t q = k0 + l; q < k1; q += 64) c += min((int64_t)D.P.len[rx[q] & GC_ID], (int64_t)other);
+    c = wave_sum64(c);
+    if (l == 0 && c) atomicAdd((unsigned long long*)&D.pair_off[2 * i + (side_v ? 1 : 0)], (unsigned long long)c);
+  }
+}
+
+__global__ void k_delta_plan_fin(DeltaArgs D) {
+  const int64_t ne = min(ctr(D.dc, DC_EDGES), D.ce_cap);
+  const unsigned long long idmask = (1ull << D.bits) - 1ull;
+  for (int64_t i = gtid(); i < D.ce_cap; i += gstride()) {
     if (i >= ne) {
-      if (l == 0) { D.c4_nch[i] = 0; D.c4_side[i] = 0; }
+      D.c4_nch[i] = 0;
+      D.c4_side[i] = 0;
       continue;
     }
     const unsigned long long K = D.ce[i] & DIR_KEY_MASK;
     const uint32_t u = (uint32_t)(K >> D.bits), v = (uint32_t)(K & idmask);
-    const int64_t du = D.P.len[u], dv = D.P.len[v];
-    int64_t cu = 0, cv = 0;
-    const uint32_t* ru = D.P.col + D.P.off[u];
-    const uint32_t* rv = D.P.col + D.P.off[v];
-    for (int64_t k = l; k < du; k += 64) cu += min((int64_t)D.P.len[ru[k] & GC_ID], dv);
-    for (int64_t k = l; k < dv; k += 64) cv += min((int64_t)D.P.len[rv[k] & GC_ID], du);
-    cu = wave_sum64(cu);
-    cv = wave_sum64(cv);
-    if (l == 0) {
-      const bool from_u = cu <= cv;
-      D.c4_side[i] = from_u ? 0 : 1;
-      D.c4_nch[i] = (int32_t)(from_u ? du : dv);
-    }
+    const bool from_u = D.pair_off[2 * i] <= D.pair_off[2 * i + 1];
+    D.c4_side[i] = from_u ? 0 : 1;
+    D.c4_nch[i] = from_u ? D.P.len[u] : D.P.len[v];
   }
 }
 
@@ -784,14 +873,20 @@ __global__ void k_tv_apply(const int32_t* __restrict__ rlist, const unsigned lon
 void launch_delta(const DeltaArgs& D, int slots, hipStream_t s) {
   fill_u64(D.dc, 0ull, DC_COUNT, s);
   hipLaunchKernelGGL(k_delta_edges, dim3(1024), dim3(TPB), 0, s, D);
+  hipLaunchKernelGGL(k_delta_titems, dim3(1024), dim3(TPB), 0, s, D);
+  exclusive_scan_i32_to_i64(D.tv_items, D.tv_ioff, D.tcap, D.scan_tmp, s);
   hipLaunchKernelGGL(k_delta_vertex, dim3(2048), dim3(TPB), 0, s, D);
+  hipLaunchKernelGGL(k_delta_vertex_fin, dim3(256), dim3(TPB), 0, s, D);
   hipLaunchKernelGGL(k_delta_s2, dim3(2048), dim3(TPB), 0, s, D);
   // every kernel that can find a buffer too small (and raise BS_RETRY)
   // runs before the first one that moves T(v) or clears scratch
   hipLaunchKernelGGL(k_delta_tri, dim3(slots), dim3(TPB), 0, s, D);
   hipLaunchKernelGGL(k_delta_k4_split, dim3(slots), dim3(TPB), 0, s, D);
   hipLaunchKernelGGL(k_delta_aff_changed, dim3(1024), dim3(TPB), 0, s, D);
-  hipLaunchKernelGGL(k_delta_c4_plan, dim3(1024), dim3(TPB), 0, s, D);
+  hipLaunchKernelGGL(k_delta_plan_items, dim3(1024), dim3(TPB), 0, s, D);
+  exclusive_scan_i32_to_i64(D.tv_items, D.tv_ioff, D.tcap, D.scan_tmp, s);
+  hipLaunchKernelGGL(k_delta_c4_plan, dim3(2048), dim3(TPB), 0, s, D);
+  hipLaunchKernelGGL(k_delta_plan_fin, dim3(256), dim3(TPB), 0, s, D);
   exclusive_scan_i32_to_i64(D.c4_nch, D.c4_off, D.ce_cap, D.scan_tmp, s);
   fill_u32((uint32_t*)D.pair_len, 0u, D.pair_cap, s);
   hipLaunchKernelGGL(k_delta_c4_pairs, dim3(1024), dim3(TPB), 0, s, D);

@@ -185,6 +185,7 @@ constexpr int K4_CHUNK = 64;            // common neighbours per chunk
 constexpr int64_t K4_HS_CAP = 1 << 22;  // stored common neighbours
 constexpr int64_t K4_HE_CAP = 1 << 14;  // split edges
 constexpr int64_t K4_IT_CAP = 1 << 18;  // chunks
+constexpr int32_t TV_CHUNK = 4096;      // entries of a touched row per piece in the edge-local degree passes
 struct DeltaArgs {
   PoolDev P;                          // union view left by the tombstone merge
   int64_t N;
@@ -220,6 +221,9 @@ struct DeltaArgs {
   uint32_t* k4_s;                     // [K4_HS_CAP] common neighbours of split edges: id | nibble(u, w) << 28 | nibble(v, w) << 30
   int64_t* k4_edge;                   // [K4_HE_CAP][3] split edges: changed edge index, offset in k4_s, count
   int32_t* k4_item;                   // [K4_IT_CAP][2] chunks: split edge (-1: none), chunk index
+  int32_t* tv_items;                  // [tcap] pieces of each touched row (rows split in TV_CHUNK entries)
+  int64_t* tv_ioff;                   // [tcap + 1] exclusive scan of tv_items
+  int64_t tcap;                       // touched rows the two arrays cover (>= the touched count)
   int64_t* pair_off;                  // [pair_cap + 1] exclusive scan of pair_len
   int64_t pair_cap;
   void* scan_tmp;                     // scan scratch for max(ce_cap, pair_cap) + 1 entries

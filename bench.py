@@ -516,22 +516,24 @@ def main():
     # rooflines: the large 4-cycle tier (the dominant kernel, one launch per
     # batch) and the triangle tiers; algorithmic bytes = 4 B per adjacency
     # entry the method reads (counted by the kernels)
-    phases = ["ms_tri", "ms_edge", "ms_c4_small", "ms_c4_mid", "ms_c4_large"]
-    tot = {p: sum(st[p] for st in stats) for p in phases}
-    dom = max(tot, key=tot.get)
-    nst = max(1, len(stats))
-
     # per launch: over the passes that ran the kernel (region passes; an
     # edge-local pass runs none of them)
     ran = [st for st in stats if not st["delta"]]
     nl = max(1, len(ran))
+    phases = ["ms_tri", "ms_edge", "ms_c4_small", "ms_c4_mid", "ms_c4_large"]
+    tot = {p: sum(st[p] for st in ran) for p in phases}
+    dom = max(tot, key=tot.get)
 
     def roof(kernel, bytes_, ms, traffic):
-        ach = bytes_ / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+        if not ran or ms <= 0:  # no timed pass ran the kernel: nothing to report
+            return {"kernel": kernel, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": None, "traffic": traffic, "bytes_per_launch": None, "avg_launch_ms": None,
+                    "launches": 0, "traffic_frac": None}
+        ach = bytes_ / (ms / 1e3) / 1e9
         return {"kernel": kernel, "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": traffic, "bytes_per_launch": bytes_ / nl,
                 "avg_launch_ms": ms / nl, "launches": len(ran),
-                "traffic_frac": round(traffic / (ms / nl / 1e3) / 1e9 / HBM_PEAK_GBS, 5) if traffic and ms > 0 else None}
+                "traffic_frac": round(traffic / (ms / nl / 1e3) / 1e9 / HBM_PEAK_GBS, 5) if traffic else None}
 
     # the compulsory bytes of a region pass: the region's rows read once
     # (4 B per entry, 16 B per vertex for its offset, length and degrees)

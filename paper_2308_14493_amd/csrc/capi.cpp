@@ -217,6 +217,10 @@ struct gc_graph {
   DevBuf Tv, dTs, sbt, ce, ae, ae_alt, slot_list, dctr, c4_nch, c4_side, c4_off, pair_edge, pair_len, pair_off,
       pair_merge, k4_s, k4_edge, k4_item, tv_items, tv_ioff;
   int64_t ae_cap = 0, slot_cap = 0, pair_cap = 0;
+  // largest affected-edge and 4-cycle-pair demand per update seen in an
+  // edge-local pass: later passes size their lists for their batch capacity
+  // at that rate instead of finding them short and counting again
+  double ae_per_update = 0, pair_per_update = 0;
   // cost model of the two kinds of one-batch pass (autotune): per
   // half-decade of batch size and kind (0 region, 1 edge-local), the mean
   // wall ms, mean batch size and passes seen; the mean of all region passes
@@ -1181,6 +1185,9 @@ int settle_delta(gc_graph* G, const PassPlan& L, BatchWork& W) {
     unsigned long long dc[DC_COUNT];
     HIPCHK(hipMemcpyAsync(dc, G->dctr.p, sizeof(dc), hipMemcpyDeviceToHost, s));
     G->sync();
+    const double tot = (double)std::max<int64_t>(L.total, 1);
+    G->ae_per_update = std::max(G->ae_per_update, (double)dc[DC_AFF_NEED] / tot);
+    G->pair_per_update = std::max(G->pair_per_update, (double)dc[DC_PAIR_NEED] / tot);
     size_delta(G, L.cap_t, (int64_t)dc[DC_AFF_NEED] + (int64_t)dc[DC_AFF_NEED] / 4,
                (int64_t)dc[DC_SLOT_NEED] + (int64_t)dc[DC_SLOT_NEED] / 4,
                (int64_t)dc[DC_PAIR_NEED] + (int64_t)dc[DC_PAIR_NEED] / 4);
@@ -1311,7 +1318,13 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
                      64);
   G->scan_tmp.ensure(scan_tmp_bytes(std::max<int64_t>(L.max_touched, G->N) + 1) + 64);
   size_count_scratch(G, L.nv, L.union_bound);
-  if (L.delta) size_delta(G, L.cap_t, 0, 0);
+  if (L.delta) {
+    // at the demand per update seen so far (within 2^26 entries a list: a
+    // larger demand is met by the retry, which sizes for the batch at hand)
+    const double lim = (double)(1ll << 26);
+    size_delta(G, L.cap_t, (int64_t)std::min(lim, 1.25 * G->ae_per_update * (double)L.cap_t), 0,
+               (int64_t)std::min(lim, 1.25 * G->pair_per_update * (double)L.cap_t));
+  }
   // arena reserve: enough for every touched row to move
   const int64_t need = (int64_t)((1.0 + G->opt.slack) * (double)L.union_bound) + 8 * L.max_touched + 1024;
   if (G->arena_cap - G->arena_top < need) compact(G, need);

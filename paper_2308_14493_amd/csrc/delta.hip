@@ -63,28 +63,51 @@ __device__ __forceinline__ int64_t find_in_row(const PoolDev& P, uint32_t r, uin
 // id.  No common id is ever consumed on one side only, so each is met once,
 // in the step that consumes it, with both of its entries in the windows.
 // f(entry of a, entry of b) per common id, on the lane holding the a entry.
+// The step bookkeeping is wave-uniform (scalar registers and branches): lanes
+// past a row's end load its last entry again instead of branching, the
+// windows' last ids are read from lane 63, and the lane exchanges address
+// ds_bpermute by byte (lane * 4) directly.
+__device__ __forceinline__ uint32_t bperm4(uint32_t byte_lane, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_ds_bpermute((int)byte_lane, (int)v);
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+  return (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32)) << 32) |
+                   __builtin_amdgcn_readfirstlane((uint32_t)x));
+}
+
+// Rows a = col + oa (na entries) and b = col + ob (nb entries), the same on
+// every lane of the wave.
 template <class F>
-__device__ __forceinline__ void wave_window_common(const uint32_t* a, int32_t na, const uint32_t* b, int32_t nb,
-                                                   F f) {
-  const int l = lane_id();
+__device__ __forceinline__ void wave_window_common(const uint32_t* __restrict__ col, int64_t oa_, int32_t na_,
+                                                   int64_t ob_, int32_t nb_, F f) {
+  const int64_t oa = uniform64(oa_), ob = uniform64(ob_);
+  const int32_t na = __builtin_amdgcn_readfirstlane(na_), nb = __builtin_amdgcn_readfirstlane(nb_);
+  const int32_t l = lane_id();
   int32_t i0 = 0, j0 = 0;
   while (i0 < na && j0 < nb) {
-    const bool va = i0 + l < na, vb = j0 + l < nb;
-    const uint32_t ea = va ? a[i0 + l] : 0u, eb = vb ? b[j0 + l] : 0u;
-    const uint32_t ia = va ? (ea & GC_ID) : 0xFFFFFFFFu, ib = vb ? (eb & GC_ID) : 0xFFFFFFFFu;
-    const uint32_t amax = __shfl(ia, min(63, na - 1 - i0)), bmax = __shfl(ib, min(63, nb - 1 - j0));
-    int lo = 0;  // number of window ids of b below ia (the window is ascending, padded above)
+    const int32_t ra = na - i0, rb = nb - j0;  // > 0
+    const bool va = l < ra, vb = l < rb;
+    const uint32_t* aw = col + (oa + i0);
+    const uint32_t* bw = col + (ob + j0);
+    const uint32_t ea = aw[(uint32_t)min(l, ra - 1)], eb = bw[(uint32_t)min(l, rb - 1)];
+    const uint32_t ida = ea & GC_ID, idb = eb & GC_ID;
+    // last ids of the windows (lane 63 holds the last entry of a short one)
+    const uint32_t amax = __builtin_amdgcn_readlane(ida, 63), bmax = __builtin_amdgcn_readlane(idb, 63);
+    const uint32_t ia = va ? ida : 0xFFFFFFFFu, ib = vb ? idb : 0xFFFFFFFFu;
+    // 4 x (number of window ids of b below ia): the window ascends and is
+    // padded above; a count of 64 reads lane 0 (ds_bpermute wraps), whose
+    // id is below ia, so it never matches
+    uint32_t lo4 = 0;
 #pragma unroll
-    for (int sp = 32; sp >= 1; sp >>= 1)
-      if (__shfl(ib, lo + sp - 1) < ia) lo += sp;
-    const int p = min(lo, 63);
-    const uint32_t ibp = __shfl(ib, p), ebp = __shfl(eb, p);
+    for (uint32_t sp = 32; sp >= 1; sp >>= 1) lo4 = bperm4(lo4 + 4 * (sp - 1), ib) < ia ? lo4 + 4 * sp : lo4;
+    const uint32_t ibp = bperm4(lo4, ib), ebp = bperm4(lo4, eb);
     if (va && ibp == ia) f(ea, ebp);
     if (amax <= bmax) {
-      j0 += __popcll(__ballot(ib <= amax));
+      j0 += (int32_t)__popcll(__ballot(ib <= amax));
       i0 += 64;
     } else {
-      i0 += __popcll(__ballot(ia <= bmax));
+      i0 += (int32_t)__popcll(__ballot(ia <= bmax));
       j0 += 64;
     }
   }
@@ -478,7 +501,7 @@ __global__ void k_delta_aff(DeltaArgs D, const unsigned long long* __restrict__ 
       // rows of similar length (as for the 4-cycle pairs): both walked
       // together, 64 entries of each a step, instead of a search of the
       // longer row per entry of the shorter
-      wave_window_common(arow, al, D.P.col + D.P.off[b], bl, [&](uint32_t ea, uint32_t eb) {
+      wave_window_common(D.P.col, D.P.off[a], al, D.P.off[b], bl, [&](uint32_t ea, uint32_t eb) {
         const uint32_t f = nib(ea) | nib(eb);
         tb += (f & 1u) == 0;
         ta += (f & 2u) == 0;
@@ -807,7 +830,7 @@ __global__ __launch_bounds__(TPB) void k_delta_c4_merge(DeltaArgs D) {
       acc = 0;
       cur_g = g;
     }
-    wave_window_common(D.P.col + D.P.off[a], D.P.len[a], D.P.col + D.P.off[o], D.P.len[o],
+    wave_window_common(D.P.col, D.P.off[a], D.P.len[a], D.P.off[o], D.P.len[o],
                        [&](uint32_t eab, uint32_t eob) {
                          const uint32_t b = eab & GC_ID;
                          if (b == s) return;

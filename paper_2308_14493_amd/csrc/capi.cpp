@@ -215,7 +215,7 @@ struct gc_graph {
   // triangles at each vertex (kept for the edge-local passes) and the
   // scratch of those passes
   DevBuf Tv, dTs, sbt, ce, ae, ae_alt, slot_list, dctr, c4_nch, c4_side, c4_off, pair_edge, pair_len, pair_off,
-      pair_merge, k4_s, k4_edge, k4_item, tv_items, tv_ioff;
+      pair_merge, pair_hlen, pair_hoff, k4_s, k4_edge, k4_item, tv_items, tv_ioff;
   int64_t ae_cap = 0, slot_cap = 0, pair_cap = 0;
   // largest affected-edge and 4-cycle-pair demand per update seen in an
   // edge-local pass: later passes size their lists for their batch capacity
@@ -1005,6 +1005,8 @@ DeltaArgs make_delta_args(gc_graph* G, const BatchWork& W) {
   D.tv_ioff = G->tv_ioff.as<int64_t>();
   D.tcap = 2 * (int64_t)(G->ce.cap / 8);
   D.pair_off = G->pair_off.as<int64_t>();
+  D.pair_hlen = G->pair_hlen.as<int32_t>();
+  D.pair_hoff = G->pair_hoff.as<int64_t>();
   D.pair_cap = G->pair_cap;
   D.scan_tmp = G->scan_tmp.p;
   return D;
@@ -1022,6 +1024,8 @@ void size_delta(gc_graph* G, int64_t cap_t, int64_t ae_need, int64_t slot_need, 
   G->pair_edge.ensure(G->pair_cap * 4);
   G->pair_len.ensure(G->pair_cap * 4);
   G->pair_merge.ensure(G->pair_cap * 4);
+  G->pair_hlen.ensure(G->pair_cap * 4);
+  G->pair_hoff.ensure((G->pair_cap + 1) * 8);
   G->k4_s.ensure(K4_HS_CAP * 4);
   G->k4_edge.ensure(K4_HE_CAP * 3 * 8);
   G->k4_item.ensure(K4_IT_CAP * 2 * 4);
@@ -1221,7 +1225,7 @@ std::vector<uint64_t> pass_signature(gc_graph* G, const PassPlan& L, const Count
                           &G->tp, &G->vpos, &G->level, &G->rlist, &G->rlen, &G->lists, &G->c4_dense, &G->c4_touch,
                           &G->c4_cur, &G->c4_blk, &G->c4_keys, &G->c4_keys_alt, &G->tri_scratch, &G->Tv, &G->dTs,
                           &G->sbt, &G->ce, &G->ae, &G->ae_alt, &G->slot_list, &G->dctr, &G->c4_nch, &G->c4_side,
-                          &G->c4_off, &G->pair_edge, &G->pair_len, &G->pair_off, &G->dead_d, &G->pair_merge, &G->k4_s, &G->k4_edge, &G->k4_item, &G->tv_items,
+                          &G->c4_off, &G->pair_edge, &G->pair_len, &G->pair_off, &G->dead_d, &G->pair_merge, &G->pair_hlen, &G->pair_hoff, &G->k4_s, &G->k4_edge, &G->k4_item, &G->tv_items,
                           &G->tv_ioff};
   for (const DevBuf* b : bufs) v.push_back((uint64_t)(uintptr_t)b->p);
   v.push_back((uint64_t)(uintptr_t)G->pin);

@@ -686,9 +686,13 @@ __global__ void k_delta_c4_pairs(DeltaArgs D) {
       D.pair_edge[base + k] = (int32_t)i;
       // rows of similar length (the longer at most (log2 of it - 1) / 2
       // times the shorter, the best split measured) are merged by a wave;
-      // the others walk the shorter row and search the longer, lane by lane
+      // of the others, a shorter N(a) against an N(o) small enough for an
+      // LDS hash table is walked against the table (k_delta_c4_hash), and
+      // the rest walk the shorter row and search the longer, lane by lane
       const bool merge = a != o && mn > 0 && (int64_t)mx <= (int64_t)mn * ((30 - __clz(max(mx, 1))) / 2);
-      D.pair_len[base + k] = a == o || merge ? 0 : mn;
+      const bool hashed = !merge && a != o && al > 0 && al < ol && ol <= C4H_MAX;
+      D.pair_len[base + k] = a == o || merge || hashed ? 0 : mn;
+      D.pair_hlen[base + k] = hashed ? al : 0;
       if (merge) D.pair_merge[atomicAdd(&D.dc[DC_MERGE], 1ull)] = (int32_t)(base + k);
     }
   }
@@ -846,6 +850,152 @@ __global__ __launch_bounds__(TPB) void k_delta_c4_merge(DeltaArgs D) {
   }
 }
 
+// Entries of the walked rows per chunk of hashed pairs: at least
+// C4H_CHUNK_MIN and four times |N(o)|, so that building the table of N(o)
+// costs at most a quarter of a chunk.
+__device__ __forceinline__ int64_t c4h_chunk(int32_t ol) { return max(C4H_CHUNK_MIN, 4 * (int64_t)ol); }
+
+// Chunks of the hashed pairs per changed edge (0 past the edge count, for
+// the scan).
+__global__ void k_delta_hitems(DeltaArgs D) {
+  const int64_t ne = min(ctr(D.dc, DC_EDGES), D.ce_cap);
+  const bool fits = D.c4_off[D.ce_cap] <= D.pair_cap;  // else the pairs were not listed (count again)
+  const unsigned long long idmask = (1ull << D.bits) - 1ull;
+  for (int64_t i = gtid(); i < D.tcap; i += gstride()) {
+    int32_t n = 0;
+    if (i < ne && fits) {
+      const int64_t h = D.pair_hoff[D.c4_off[i + 1]] - D.pair_hoff[D.c4_off[i]];
+      if (h > 0) {
+        const unsigned long long K = D.ce[i] & DIR_KEY_MASK;
+        const uint32_t u = (uint32_t)(K >> D.bits), v = (uint32_t)(K & idmask);
+        const uint32_t o = D.c4_side[i] ? u : v;
+        const int64_t T = c4h_chunk(D.P.len[o]);
+        n = (int32_t)((h + T - 1) / T);
+      }
+    }
+    D.tv_items[i] = n;
+  }
+}
+
+// The hashed pairs (e, a): each workgroup takes chunks from a queue, builds
+// an LDS hash table of N(o) for the chunk's edge (kept while the next chunk
+// is of the same edge): id, the nibble of (o, b), and whether (o, b) is a
+// changed pair of smaller key than e (such paths are counted from that
+// pair).  Its waves split the chunk's entries in contiguous pieces; a lane
+// steps through the pairs of its piece and probes the table with each entry
+// b of N(a): a hit with b != s closes the path s - a - b - o.
+__global__ __launch_bounds__(C4H_T) void k_delta_c4_hash(DeltaArgs D) {
+  __shared__ uint32_t tab[C4H_SLOTS];
+  __shared__ int64_t item_s;
+  if (D.bstats[BS_RETRY]) return;
+  const int64_t ne = min(ctr(D.dc, DC_EDGES), D.ce_cap);
+  if (ne == 0) return;
+  const int64_t nitems = D.tv_ioff[ne];
+  const unsigned long long idmask = (1ull << D.bits) - 1ull;
+  const int32_t l = lane_id(), wv = (int32_t)(threadIdx.x >> 6), nwv = (int32_t)(blockDim.x >> 6);
+  constexpr uint32_t EMPTY = 0xFFFFFFFFu;
+  int64_t acc = 0;
+  int cur_g = -1;
+  int64_t cur_i = -1;
+  while (true) {
+    __syncthreads();
+    if (threadIdx.x == 0) item_s = (int64_t)atomicAdd(&D.dc[DC_QH], 1ull);
+    __syncthreads();
+    const int64_t it = item_s;
+    if (it >= nitems) break;
+    int64_t lo = 0, hi = ne;  // the item's edge: largest i with tv_ioff[i] <= it
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (D.tv_ioff[mid] <= it) lo = mid; else hi = mid;
+    }
+    const int64_t i = lo;
+    const unsigned long long ek = D.ce[i];
+    const unsigned long long K = ek & DIR_KEY_MASK;
+    const uint32_t fe = (uint32_t)(ek >> DIR_MASK_SHIFT) & 3u;
+    const uint32_t u = (uint32_t)(K >> D.bits), v = (uint32_t)(K & idmask);
+    const uint32_t s = D.c4_side[i] ? v : u, o = s == u ? v : u;
+    const int32_t ol = D.P.len[o];  // <= C4H_MAX: the edge has hashed pairs
+    int tb = 8;  // table of 2^tb slots: at least 4 |N(o)| where LDS allows
+    while ((1 << tb) < 4 * ol && (1 << tb) < C4H_SLOTS) ++tb;
+    const uint32_t tmask = (1u << tb) - 1u;
+    if (i != cur_i) {
+      for (int32_t k = (int32_t)threadIdx.x; k <= (int32_t)tmask; k += (int32_t)blockDim.x) tab[k] = EMPTY;
+      __syncthreads();
+      const uint32_t* orow = D.P.col + D.P.off[o];
+      for (int32_t k = (int32_t)threadIdx.x; k < ol; k += (int32_t)blockDim.x) {
+        const uint32_t e = orow[k], b = e & GC_ID, f = nib(e);
+        const uint32_t val = b | (f << 28) | ((f && pkey(o, b, D.bits) < K) ? (1u << 30) : 0u);
+        uint32_t h = (b * 2654435761u) >> (32 - tb);
+        while (atomicCAS(&tab[h], EMPTY, val) != EMPTY) h = (h + 1) & tmask;
+      }
+      __syncthreads();
+      cur_i = i;
+    }
+    const int g = D.gid[u];
+    if (g != cur_g) {
+      if (cur_g >= 0) add_sig(D, cur_g, SG_C4, acc);
+      acc = 0;
+      cur_g = g;
+    }
+    // the chunk: entries [r0, r1) of the hashed walk index space
+    const int64_t p0 = D.c4_off[i], p1 = D.c4_off[i + 1];
+    const int64_t T = c4h_chunk(ol);
+    const int64_t r0 = D.pair_hoff[p0] + (it - D.tv_ioff[i]) * T, r1 = min(D.pair_hoff[p1], r0 + T);
+    const int64_t nst = (r1 - r0 + 63) >> 6, per = (nst + nwv - 1) / nwv;
+    const int64_t st0 = wv * per, st1 = min(nst, st0 + per);
+    if (st0 >= st1) continue;
+    // this lane's first pair: largest p with pair_hoff[p] <= f (pairs
+    // walked elsewhere share their offset with the next)
+    int64_t f = r0 + (st0 << 6) + l;
+    int64_t p = p0;
+    {
+      int64_t a0 = p0, a1 = p1;
+      while (a1 - a0 > 1) {
+        const int64_t mid = (a0 + a1) >> 1;
+        if (D.pair_hoff[mid] <= f) a0 = mid; else a1 = mid;
+      }
+      p = a0;
+    }
+    int64_t pbeg = D.pair_hoff[p], pend = D.pair_hoff[p + 1];
+    bool fresh = true;
+    const uint32_t* srow = D.P.col + D.P.off[s];
+    const uint32_t* arow = nullptr;
+    uint32_t a = 0, fsa = 0;
+    bool skip_sa = false;
+    for (int64_t st = st0; st < st1; ++st) {
+      f = r0 + (st << 6) + l;
+      if (f >= r1) break;
+      while (pend <= f) {
+        ++p;
+        pbeg = pend;
+        pend = D.pair_hoff[p + 1];
+        fresh = true;
+      }
+      if (fresh) {
+        fresh = false;
+        const uint32_t eaj = srow[p - p0];
+        a = eaj & GC_ID;
+        fsa = nib(eaj);
+        skip_sa = fsa && pkey(s, a, D.bits) < K;
+        arow = D.P.col + D.P.off[a];
+      }
+      const uint32_t eab = arow[f - pbeg], b = eab & GC_ID;
+      uint32_t h = (b * 2654435761u) >> (32 - tb), sv;
+      while (true) {
+        sv = tab[h];
+        if (sv == EMPTY || (sv & GC_ID) == b) break;
+        h = (h + 1) & tmask;
+      }
+      if (sv != EMPTY && b != s) {
+        const uint32_t fab = nib(eab);
+        if (!(skip_sa || (fab && pkey(a, b, D.bits) < K) || ((sv >> 30) & 1u)))
+          acc += delta_of(fe | fsa | fab | ((sv >> 28) & 3u));
+      }
+    }
+  }
+  if (cur_g >= 0) add_sig(D, cur_g, SG_C4, acc);
+}
+
 // ------------------------------------------------ T(v) in the region path
 // After the triangle kernels of a region (or whole-graph) pass, t holds the
 // triangles of every upper entry (id order) of the region per version.  A
@@ -912,8 +1062,12 @@ void launch_delta(const DeltaArgs& D, int slots, hipStream_t s) {
   hipLaunchKernelGGL(k_delta_plan_fin, dim3(256), dim3(TPB), 0, s, D);
   exclusive_scan_i32_to_i64(D.c4_nch, D.c4_off, D.ce_cap, D.scan_tmp, s);
   fill_u32((uint32_t*)D.pair_len, 0u, D.pair_cap, s);
+  fill_u32((uint32_t*)D.pair_hlen, 0u, D.pair_cap, s);
   hipLaunchKernelGGL(k_delta_c4_pairs, dim3(1024), dim3(TPB), 0, s, D);
   exclusive_scan_i32_to_i64(D.pair_len, D.pair_off, D.pair_cap, D.scan_tmp, s);
+  exclusive_scan_i32_to_i64(D.pair_hlen, D.pair_hoff, D.pair_cap, D.scan_tmp, s);
+  hipLaunchKernelGGL(k_delta_hitems, dim3(256), dim3(TPB), 0, s, D);
+  exclusive_scan_i32_to_i64(D.tv_items, D.tv_ioff, D.tcap, D.scan_tmp, s);
   unsigned long long* sorted =
       radix_sort_u64(D.ae, D.ae_alt, D.sort_tmp, D.ae_cap, D.dc + DC_AFF_TOTAL, 2 * D.bits, s);
   hipLaunchKernelGGL(k_delta_aff, dim3(4096), dim3(TPB), 0, s, D, (const unsigned long long*)sorted);
@@ -921,6 +1075,7 @@ void launch_delta(const DeltaArgs& D, int slots, hipStream_t s) {
   hipLaunchKernelGGL(k_delta_tv, dim3(1024), dim3(TPB), 0, s, D, (const unsigned long long*)sorted);
   hipLaunchKernelGGL(k_delta_c4, dim3(4096), dim3(TPB), 0, s, D);
   hipLaunchKernelGGL(k_delta_c4_merge, dim3(4096), dim3(TPB), 0, s, D);
+  hipLaunchKernelGGL(k_delta_c4_hash, dim3(256), dim3(C4H_T), 0, s, D);
 }
 
 void launch_tv_region(int nv, const RegionDev& R, const int32_t* rlist, const unsigned long long* c,

@@ -175,7 +175,7 @@ void launch_combine(int nv, const unsigned long long* sig, long long* state, lon
 // capi.cpp: thread-local error text read by gc_last_error()
 // delta.hip: edge-local update of the Sigma terms of a one-batch pass
 enum { DC_EDGES = 0, DC_AFF, DC_AFF_TOTAL, DC_AFF_NEED, DC_SLOT_NEED, DC_QTRI, DC_QC4, DC_PAIR_NEED, DC_MERGE,
-       DC_HS, DC_HITEMS, DC_HEAVY, DC_QK4, DC_COUNT };
+       DC_HS, DC_HITEMS, DC_HEAVY, DC_QK4, DC_QH, DC_COUNT };
 // 4-cliques of changed edges with many common neighbours, spread over the
 // workgroups in chunks: the common neighbours of such edges (with their
 // flags), the edges, and the chunks (fixed capacities; an edge that does not
@@ -186,6 +186,15 @@ constexpr int64_t K4_HS_CAP = 1 << 22;  // stored common neighbours
 constexpr int64_t K4_HE_CAP = 1 << 14;  // split edges
 constexpr int64_t K4_IT_CAP = 1 << 18;  // chunks
 constexpr int32_t TV_CHUNK = 4096;      // entries of a touched row per piece in the edge-local degree passes
+// 4-cycle pairs (e, a) with a shorter N(a) that is not merged, counted
+// against an LDS hash table of N(o): rows N(o) of at most C4H_MAX entries
+// (table of C4H_SLOTS, load <= 1/2); work in chunks of at least
+// C4H_CHUNK_MIN entries of the walked rows and four times |N(o)| (the
+// table build)
+constexpr int C4H_SLOTS = 32768;
+constexpr int32_t C4H_MAX = 16384;
+constexpr int64_t C4H_CHUNK_MIN = 16384;
+constexpr int C4H_T = 1024;
 struct DeltaArgs {
   PoolDev P;                          // union view left by the tombstone merge
   int64_t N;
@@ -225,6 +234,8 @@ struct DeltaArgs {
   int64_t* tv_ioff;                   // [tcap + 1] exclusive scan of tv_items
   int64_t tcap;                       // touched rows the two arrays cover (>= the touched count)
   int64_t* pair_off;                  // [pair_cap + 1] exclusive scan of pair_len
+  int32_t* pair_hlen;                 // [pair_cap] entries of N(a) walked against the hash of N(o) (0: other ways)
+  int64_t* pair_hoff;                 // [pair_cap + 1] exclusive scan of pair_hlen
   int64_t pair_cap;
   void* scan_tmp;                     // scan scratch for max(ce_cap, pair_cap) + 1 entries
 };

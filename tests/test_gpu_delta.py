@@ -183,3 +183,40 @@ def test_delta_pair_room_regrow_keeps_vertex_triangles():
             oracle_apply(E, n, *b)
             say("  batch %d retries %d" % (j, st["retries"]))
             assert got == native.static_counts(n, *esorted(E)), "batch %d" % j
+
+
+def test_delta_tabled_pairs_hash_and_index():
+    """4-cycle pairs (e, a) with a short N(a) against the row of a hub: one
+    hub of 3000 neighbours (N(a) walked against an LDS hash table of the hub's
+    row) and one of 20000 (above the table's 16384 entries: the hub's row
+    searched lane by lane), with changed edges at both hubs whose other ends
+    have short rows, plus a ring and chords so that the paths s - a - b - hub
+    exist; insertions, deletions and re-insertions."""
+    from paper_2308_14493_amd.graphlet4 import Graph
+    say("case delta tabled pairs")
+    rng = np.random.default_rng(41)
+    n = 25000
+    E = {(0, w) for w in range(1, 20001)} | {(w, 20001) for w in range(1, 6001, 2)}
+    E |= {(w, w + 1) for w in range(1, n - 1)}
+    for a, b in rng.integers(1, n, (3000, 2)).tolist():
+        if a != b:
+            E.add((min(a, b), max(a, b)))
+    ins1 = [(21000 + j, 0) for j in range(60)] + [(21500 + j, 20001) for j in range(40)]
+    batches = [
+        ([u for u, v in ins1], [v for u, v in ins1], [0, 0, 7], [5, 9, 20001]),
+        ([0, 20001, 22000], [5, 21003, 0], [21000, 21001, 21502], [0, 0, 20001]),
+        ([21000 + j for j in range(0, 60, 3)], [0] * 20, [21000 + j for j in range(1, 60, 3)], [0] * 20),
+    ]
+    with Graph(n, *esorted(E), delta=1) as g:
+        for j, b in enumerate(batches):
+            b = [np.array(x, np.int32) for x in b]
+            got, st = g.apply_batch(*b, stats=True)
+            assert st["delta"] == 1
+            oracle_apply(E, n, *b)
+            assert got == native.static_counts(n, *esorted(E)), "batch %d" % j
+        for j in range(3):
+            b = messy(n, E, rng, 200)
+            got = g.apply_batch(*b)
+            oracle_apply(E, n, *b)
+            assert got == native.static_counts(n, *esorted(E)), "messy batch %d" % j
+        assert g.recount() == g.counts()

@@ -113,6 +113,21 @@ __device__ __forceinline__ void wave_window_common(const uint32_t* __restrict__ 
   }
 }
 
+// Work items [first, first + QCHUNK) taken by a wave from a shared counter,
+// so that waves which met light items take more (a fixed share per wave
+// leaves the kernel waiting for the wave that drew the heaviest ones);
+// returns the first item, the same on every lane.  One item at a time: the
+// items in flight stay a moving window of consecutive ones, whose rows
+// (one changed edge's opposite row, one vertex's row) the waves share in L2
+// (chunks of 16 spread the waves over the item space: both kernels slower
+// by half and more).
+constexpr int64_t QCHUNK = 1;
+__device__ __forceinline__ int64_t wave_take(unsigned long long* ctr_) {
+  unsigned long long c = 0;
+  if (lane_id() == 0) c = atomicAdd(ctr_, 1ull);
+  return (int64_t)__shfl(c, 0) * QCHUNK;
+}
+
 // degree of v in version x (0 before, 1 after): touched rows carry flags and
 // have their two degrees in dd; the others have none
 __device__ __forceinline__ int64_t deg_of(const DeltaArgs& D, uint32_t v, int x) {
@@ -480,10 +495,10 @@ __global__ void k_delta_aff(DeltaArgs D, const unsigned long long* __restrict__ 
   const int64_t na = ctr(D.dc, DC_AFF_TOTAL);
   const unsigned long long idmask = (1ull << D.bits) - 1ull;
   const int l = lane_id();
-  const int64_t w0 = gtid() >> 6, ws = gstride() >> 6;
   int64_t s3 = 0, s4 = 0, s5 = 0;
   int cur_g = -1;
-  for (int64_t i = w0; i < na; i += ws) {
+  for (int64_t i0 = wave_take(&D.dc[DC_QAFF]); i0 < na; i0 = wave_take(&D.dc[DC_QAFF]))
+  for (int64_t i = i0; i < min(na, i0 + QCHUNK); ++i) {
     const unsigned long long key = keys[i];
     if (i > 0 && keys[i - 1] == key) continue;
     const uint32_t x = (uint32_t)(key >> D.bits), y = (uint32_t)(key & idmask);
@@ -814,10 +829,10 @@ __global__ __launch_bounds__(TPB) void k_delta_c4_merge(DeltaArgs D) {
   if (D.bstats[BS_RETRY]) return;
   const int64_t nm = ctr(D.dc, DC_MERGE);
   const unsigned long long idmask = (1ull << D.bits) - 1ull;
-  const int64_t w0 = gtid() >> 6, ws = gstride() >> 6;
   int64_t acc = 0;
   int cur_g = -1;
-  for (int64_t m = w0; m < nm; m += ws) {
+  for (int64_t m0 = wave_take(&D.dc[DC_QMERGE]); m0 < nm; m0 = wave_take(&D.dc[DC_QMERGE]))
+  for (int64_t m = m0; m < min(nm, m0 + QCHUNK); ++m) {
     const int64_t p = D.pair_merge[m];
     const int32_t i = D.pair_edge[p];
     const unsigned long long ek = D.ce[i];

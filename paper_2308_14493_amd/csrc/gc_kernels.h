@@ -175,7 +175,7 @@ void launch_combine(int nv, const unsigned long long* sig, long long* state, lon
 // capi.cpp: thread-local error text read by gc_last_error()
 // delta.hip: edge-local update of the Sigma terms of a one-batch pass
 enum { DC_EDGES = 0, DC_AFF, DC_AFF_TOTAL, DC_AFF_NEED, DC_SLOT_NEED, DC_QTRI, DC_QC4, DC_PAIR_NEED, DC_MERGE,
-       DC_HS, DC_HITEMS, DC_HEAVY, DC_QK4, DC_QH, DC_COUNT };
+       DC_HS, DC_HITEMS, DC_HEAVY, DC_QK4, DC_QH, DC_QAFF, DC_QMERGE, DC_COUNT };
 // 4-cliques of changed edges with many common neighbours, spread over the
 // workgroups in chunks: the common neighbours of such edges (with their
 // flags), the edges, and the chunks (fixed capacities; an edge that does not

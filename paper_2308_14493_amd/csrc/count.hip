@@ -104,6 +104,16 @@ __device__ __forceinline__ int seg_of(int32_t excl, int32_t idx) {
 }
 
 __device__ __forceinline__ int32_t rdl32(int32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+// Vertices of a per-wave tier taken QV_CHUNK at a time from a shared
+// counter instead of a fixed stride per wave, so that the waves that drew
+// light vertices take more; returns the first, the same on every lane.
+constexpr int64_t QV_CHUNK = 16;
+__device__ __forceinline__ int64_t wave_take(const unsigned long long* ctr_, int64_t chunk) {
+  unsigned long long c = 0;
+  if ((__lane_id()) == 0) c = atomicAdd((unsigned long long*)ctr_, 1ull);
+  return (int64_t)__shfl(c, 0) * chunk;
+}
 __device__ __forceinline__ int64_t rdl64(int64_t v, int lane) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), lane);
@@ -326,7 +336,8 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
   int64_t kacc[NV];
   zerov<NV>(kacc);
   int64_t ent = 0;  // entries of N+(u) and of the lists probed (algorithmic reads)
-  for (int64_t it = (int64_t)blockIdx.x * TS_WAVES + w; it < n; it += (int64_t)gridDim.x * TS_WAVES) {
+  for (int64_t i0 = wave_take(A.c + C_QTS, QV_CHUNK); i0 < n; i0 = wave_take(A.c + C_QTS, QV_CHUNK))
+  for (int64_t it = i0; it < min(n, i0 + QV_CHUNK); ++it) {
     const int32_t u = list[it];
     const int g = A.gid[u];
     if (g != cur_g) {
@@ -946,7 +957,8 @@ __global__ __launch_bounds__(256) void k_c4_small(CountArgs A) {
   zerov<NV>(acc);
   for (int s = l; s < C4S_SLOTS; s += 64) { hkey[w][s] = -1; hcnt[w][s] = 0; }
   wave_sync();
-  for (int64_t it = (int64_t)blockIdx.x * C4S_WAVES + w; it < n; it += (int64_t)gridDim.x * C4S_WAVES) {
+  for (int64_t i0 = wave_take(A.c + C_QC4S, QV_CHUNK); i0 < n; i0 = wave_take(A.c + C_QC4S, QV_CHUNK))
+  for (int64_t it = i0; it < min(n, i0 + QV_CHUNK); ++it) {
     const int32_t v = list[it];
     const int g = A.gid[v];
     if (g != cur_g) { if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_C4, acc); cur_g = g; }
@@ -990,7 +1002,13 @@ __global__ __launch_bounds__(256) void k_c4_mid(CountArgs A) {
   zerov<NV>(acc);
   for (int s = threadIdx.x; s < C4M_SLOTS; s += blockDim.x) { hkey[s] = -1; hcnt[s] = 0; }
   __syncthreads();
-  for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+  __shared__ int64_t item_s;
+  while (true) {
+    __syncthreads();
+    if (threadIdx.x == 0) item_s = (int64_t)atomicAdd((unsigned long long*)(A.c + C_QC4M), 1ull);
+    __syncthreads();
+    const int64_t it = item_s;
+    if (it >= n) break;
     const int32_t v = list[it];
     const int g = A.gid[v];
     if (g != cur_g) { if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_C4, acc); cur_g = g; }

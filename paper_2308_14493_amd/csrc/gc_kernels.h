@@ -17,8 +17,11 @@ enum {
   C_MAXLOW,       // max lower degree in the large 4-cycle tier
   C_LIST0,        // C_LIST0 + L_*: work list sizes
   C_QHEAD = C_LIST0 + 12,  // dynamic queue head of the large 4-cycle tier
-  C_QTRI,                  // C_QTRI + k: queue head of list L_TRI_1 + k
-  C_COUNT = C_QTRI + 8
+  C_QTRI,                  // C_QTRI + k: queue head of list L_TRI_1 + k (k < 6)
+  C_QTS = C_QTRI + 6,      // queue heads of the small triangle tier and of the small and mid 4-cycle tiers
+  C_QC4S,
+  C_QC4M,
+  C_COUNT
 };
 // Work lists: triangles by out-degree (<= 64 one wave per vertex, then the
 // workgroup tiers (64,128] (128,256] (256,512] (512,1024] (1024,TRI_LDS_MAX]

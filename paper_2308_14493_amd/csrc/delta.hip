@@ -26,8 +26,11 @@
 //   K4          per changed edge e = (u, v): pairs {w, x} of common
 //               neighbours S(e) joined by an edge;
 //   C4          per changed edge: paths s - a - b - o closing the cycle with
-//               e = (s, o), each pair (s, a) walking the shorter of N(a),
-//               N(o) and searching the other.
+//               e = (s, o), from the common ids of N(a) and N(o) for each
+//               pair (s, a): rows of similar length merged by a wave, a
+//               shorter N(a) walked against an LDS hash table of a small
+//               enough N(o), the others by walking the shorter row and
+//               searching the other.
 #include "gc_kernels.h"
 
 namespace {

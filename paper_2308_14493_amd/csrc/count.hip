@@ -105,14 +105,20 @@ __device__ __forceinline__ int seg_of(int32_t excl, int32_t idx) {
 
 __device__ __forceinline__ int32_t rdl32(int32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
-// Vertices of a per-wave tier taken QV_CHUNK at a time from a shared
-// counter instead of a fixed stride per wave, so that the waves that drew
-// light vertices take more; returns the first, the same on every lane.
+// Vertices of a per-wave tier in chunks of up to QV_CHUNK (as many as the
+// list holds per wave of the grid, so that a short list still uses every
+// wave): a wave's first chunk is its own index (no atomic: waves without one
+// leave at once), later ones come from a shared counter counting on from the
+// grid's wave count, so that the waves that drew light vertices take more
+// than a fixed stride would give them.  Returns the same chunk on every lane.
 constexpr int64_t QV_CHUNK = 16;
-__device__ __forceinline__ int64_t wave_take(const unsigned long long* ctr_, int64_t chunk) {
+__device__ __forceinline__ int64_t qv_chunk(int64_t n, int64_t nwaves) {
+  return max((int64_t)1, min(QV_CHUNK, n / max(nwaves, (int64_t)1)));
+}
+__device__ __forceinline__ int64_t wave_next_chunk(const unsigned long long* ctr_, int64_t nwaves) {
   unsigned long long c = 0;
   if ((__lane_id()) == 0) c = atomicAdd((unsigned long long*)ctr_, 1ull);
-  return (int64_t)__shfl(c, 0) * chunk;
+  return nwaves + (int64_t)__shfl(c, 0);
 }
 __device__ __forceinline__ int64_t rdl64(int64_t v, int lane) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
@@ -336,8 +342,9 @@ __global__ __launch_bounds__(256) void k_tri_small(CountArgs A) {
   int64_t kacc[NV];
   zerov<NV>(kacc);
   int64_t ent = 0;  // entries of N+(u) and of the lists probed (algorithmic reads)
-  for (int64_t i0 = wave_take(A.c + C_QTS, QV_CHUNK); i0 < n; i0 = wave_take(A.c + C_QTS, QV_CHUNK))
-  for (int64_t it = i0; it < min(n, i0 + QV_CHUNK); ++it) {
+  const int64_t nwv = (int64_t)gridDim.x * TS_WAVES, cq = qv_chunk(n, nwv);
+  for (int64_t ch = (int64_t)blockIdx.x * TS_WAVES + w; ch * cq < n; ch = wave_next_chunk(A.c + C_QTS, nwv))
+  for (int64_t it = ch * cq; it < min(n, (ch + 1) * cq); ++it) {
     const int32_t u = list[it];
     const int g = A.gid[u];
     if (g != cur_g) {
@@ -957,8 +964,9 @@ __global__ __launch_bounds__(256) void k_c4_small(CountArgs A) {
   zerov<NV>(acc);
   for (int s = l; s < C4S_SLOTS; s += 64) { hkey[w][s] = -1; hcnt[w][s] = 0; }
   wave_sync();
-  for (int64_t i0 = wave_take(A.c + C_QC4S, QV_CHUNK); i0 < n; i0 = wave_take(A.c + C_QC4S, QV_CHUNK))
-  for (int64_t it = i0; it < min(n, i0 + QV_CHUNK); ++it) {
+  // a fixed stride: the vertices of this tier are uniformly light (a shared
+  // counter costs more than it balances)
+  for (int64_t it = (int64_t)blockIdx.x * C4S_WAVES + w; it < n; it += (int64_t)gridDim.x * C4S_WAVES) {
     const int32_t v = list[it];
     const int g = A.gid[v];
     if (g != cur_g) { if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_C4, acc); cur_g = g; }
@@ -1002,13 +1010,10 @@ __global__ __launch_bounds__(256) void k_c4_mid(CountArgs A) {
   zerov<NV>(acc);
   for (int s = threadIdx.x; s < C4M_SLOTS; s += blockDim.x) { hkey[s] = -1; hcnt[s] = 0; }
   __syncthreads();
+  // first vertex by block index (no atomic: blocks without one leave at
+  // once), later ones from the shared counter counting on from the grid size
   __shared__ int64_t item_s;
-  while (true) {
-    __syncthreads();
-    if (threadIdx.x == 0) item_s = (int64_t)atomicAdd((unsigned long long*)(A.c + C_QC4M), 1ull);
-    __syncthreads();
-    const int64_t it = item_s;
-    if (it >= n) break;
+  for (int64_t it = blockIdx.x; it < n; it = item_s) {
     const int32_t v = list[it];
     const int g = A.gid[v];
     if (g != cur_g) { if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_C4, acc); cur_g = g; }
@@ -1028,6 +1033,8 @@ __global__ __launch_bounds__(256) void k_c4_mid(CountArgs A) {
         hkey[s] = -1; hcnt[s] = 0;
       }
     }
+    __syncthreads();
+    if (threadIdx.x == 0) item_s = (int64_t)gridDim.x + (int64_t)atomicAdd((unsigned long long*)(A.c + C_QC4M), 1ull);
     __syncthreads();
   }
   if (cur_g >= 0) flushv<NV>(A.sig, cur_g, SG_C4, acc);

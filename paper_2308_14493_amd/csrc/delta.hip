@@ -116,19 +116,20 @@ __device__ __forceinline__ void wave_window_common(const uint32_t* __restrict__ 
   }
 }
 
-// Work items [first, first + QCHUNK) taken by a wave from a shared counter,
-// so that waves which met light items take more (a fixed share per wave
-// leaves the kernel waiting for the wave that drew the heaviest ones);
-// returns the first item, the same on every lane.  One item at a time: the
-// items in flight stay a moving window of consecutive ones, whose rows
+// Work items for the waves of a grid: each wave's first item is its own
+// index (no atomic, so a small input costs no contention: waves without an
+// item leave at once), and a wave that finished one takes the next from a
+// shared counter counting on from the grid's wave count, so that waves which
+// met light items take more (a fixed share per wave leaves the kernel
+// waiting for the wave that drew the heaviest ones).  One item at a time:
+// the items in flight stay a moving window of consecutive ones, whose rows
 // (one changed edge's opposite row, one vertex's row) the waves share in L2
-// (chunks of 16 spread the waves over the item space: both kernels slower
-// by half and more).
-constexpr int64_t QCHUNK = 1;
-__device__ __forceinline__ int64_t wave_take(unsigned long long* ctr_) {
+// (chunks of 16 spread the waves over the item space: both kernels slower by
+// half and more).  Returns the same item on every lane.
+__device__ __forceinline__ int64_t wave_next(unsigned long long* ctr_, int64_t nwaves) {
   unsigned long long c = 0;
   if (lane_id() == 0) c = atomicAdd(ctr_, 1ull);
-  return (int64_t)__shfl(c, 0) * QCHUNK;
+  return nwaves + (int64_t)__shfl(c, 0);
 }
 
 // degree of v in version x (0 before, 1 after): touched rows carry flags and
@@ -500,8 +501,8 @@ __global__ void k_delta_aff(DeltaArgs D, const unsigned long long* __restrict__ 
   const int l = lane_id();
   int64_t s3 = 0, s4 = 0, s5 = 0;
   int cur_g = -1;
-  for (int64_t i0 = wave_take(&D.dc[DC_QAFF]); i0 < na; i0 = wave_take(&D.dc[DC_QAFF]))
-  for (int64_t i = i0; i < min(na, i0 + QCHUNK); ++i) {
+  const int64_t nwv = gstride() >> 6;
+  for (int64_t i = gtid() >> 6; i < na; i = wave_next(&D.dc[DC_QAFF], nwv)) {
     const unsigned long long key = keys[i];
     if (i > 0 && keys[i - 1] == key) continue;
     const uint32_t x = (uint32_t)(key >> D.bits), y = (uint32_t)(key & idmask);
@@ -834,8 +835,8 @@ __global__ __launch_bounds__(TPB) void k_delta_c4_merge(DeltaArgs D) {
   const unsigned long long idmask = (1ull << D.bits) - 1ull;
   int64_t acc = 0;
   int cur_g = -1;
-  for (int64_t m0 = wave_take(&D.dc[DC_QMERGE]); m0 < nm; m0 = wave_take(&D.dc[DC_QMERGE]))
-  for (int64_t m = m0; m < min(nm, m0 + QCHUNK); ++m) {
+  const int64_t nwv = gstride() >> 6;
+  for (int64_t m = gtid() >> 6; m < nm; m = wave_next(&D.dc[DC_QMERGE], nwv)) {
     const int64_t p = D.pair_merge[m];
     const int32_t i = D.pair_edge[p];
     const unsigned long long ek = D.ce[i];

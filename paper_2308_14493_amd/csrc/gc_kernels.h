@@ -18,8 +18,7 @@ enum {
   C_LIST0,        // C_LIST0 + L_*: work list sizes
   C_QHEAD = C_LIST0 + 12,  // dynamic queue head of the large 4-cycle tier
   C_QTRI,                  // C_QTRI + k: queue head of list L_TRI_1 + k (k < 6)
-  C_QTS = C_QTRI + 6,      // queue heads of the small triangle tier and of the small and mid 4-cycle tiers
-  C_QC4S,
+  C_QTS = C_QTRI + 6,      // queue heads of the small triangle tier and of the mid 4-cycle tier
   C_QC4M,
   C_COUNT
 };

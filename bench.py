@@ -403,8 +403,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md but not built)" % args.gpus,
+        print("bench.py: runs on one GPU; --gpus %d is not supported "
+              "(sharding a graph over several GPUs is not implemented)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 

@@ -229,6 +229,9 @@ struct gc_graph {
   int64_t mode_n[16][2] = {};
   double region_ms_all = 0;
   int64_t region_n_all = 0;
+  // least wall ms of an edge-local one-batch pass (< 0: none yet), taken as
+  // the fixed cost of that kind (launches, ingest, purge, result copy)
+  double delta_ms_min = -1;
   // mean wall ms of multi-version passes by their number of batches
   double multi_ms[GC_NV_MAX] = {};
   int64_t multi_n[GC_NV_MAX] = {};
@@ -1048,21 +1051,26 @@ void size_delta(gc_graph* G, int64_t cap_t, int64_t ae_need, int64_t slot_need, 
 int settle_delta(gc_graph* G, const PassPlan& L, BatchWork& W);
 
 // Expected wall ms of the two kinds of one-batch pass (< 0: no estimate):
-// region, this bucket's mean, else the mean of all region passes;
-// edge-local, this bucket's mean, else the nearest measured bucket's scaled
-// by the batch size.
+// region, this bucket's mean, else the mean of all region passes (its cost
+// hardly depends on the batch); edge-local, affine in the batch size: the
+// fixed cost F (the fastest edge-local pass seen) plus a per-update cost
+// fitted to this bucket's mean, else the nearest measured bucket's,
+// (ms - F) / size.  A half-decade spans sizes 3.2x apart and the edge-local
+// work grows with the changed pairs, so even the own bucket's mean is scaled
+// to the batch; and scaling a small bucket's time in proportion would
+// charge the large batch its fixed cost many times over.
 void pass_estimates(const gc_graph* G, int b, int64_t total, double& est_r, double& est_d) {
   const int64_t* n = G->mode_n[b];
   est_r = n[0] > 0 ? G->mode_ms[b][0] : (G->region_n_all > 0 ? G->region_ms_all : -1.0);
   est_d = -1;
-  if (n[1] > 0) {
-    est_d = G->mode_ms[b][1];
-  } else {
-    for (int k = 1; k < 16 && est_d < 0; ++k)
-      for (int bb : {b - k, b + k})
-        if (bb >= 0 && bb < 16 && G->mode_n[bb][1] > 0 && est_d < 0)
-          est_d = G->mode_ms[bb][1] * (double)std::max<int64_t>(total, 1) / std::max(1.0, G->mode_sz[bb][1]);
-  }
+  int nb = n[1] > 0 ? b : -1;
+  for (int k = 1; k < 16 && nb < 0; ++k)
+    for (int bb : {b - k, b + k})
+      if (bb >= 0 && bb < 16 && G->mode_n[bb][1] > 0 && nb < 0) nb = bb;
+  if (nb < 0) return;
+  const double ms = G->mode_ms[nb][1];
+  const double F = G->delta_ms_min >= 0 ? std::min(G->delta_ms_min, ms) : ms;
+  est_d = F + (ms - F) * (double)std::max<int64_t>(total, 1) / std::max(1.0, G->mode_sz[nb][1]);
 }
 
 int size_bucket(int64_t total) {
@@ -1070,31 +1078,24 @@ int size_bucket(int64_t total) {
 }
 
 // Edge-local or region pass for a batch of `total` updates in half-decade
-// `b`: the kind with the smaller expected wall time.  Region time: this
-// bucket's mean, else the mean of all region passes (it hardly depends on
-// the batch).  Edge-local time: this bucket's mean, else the nearest
-// measured bucket's scaled by the batch size (its work grows with the
-// changed pairs), else a first try for batches of at most 1000 updates (also
-// while no region pass has been measured).
-// Both kinds measured in a bucket: every 32nd pass there tries the other.
-// A bucket with no edge-local pass yet tries one while the carried-over
-// estimate is within 1.5x of the region's.
+// `b`: the kind with the smaller expected wall time (pass_estimates), else
+// a first try edge-local for batches of at most 1000 updates (also while no
+// region pass has been measured).  Both kinds measured in a bucket: every
+// 32nd pass there tries the other.  A bucket with no edge-local pass yet
+// tries one while the carried-over estimate is within 1.25x of the region's
+// (a per-update cost taken from other sizes is rough).
 bool choose_delta(gc_graph* G, int b, int64_t total) {
   const int64_t* n = G->mode_n[b];
   // nothing measured for the region kind yet: small batches start edge-local
   if (G->region_n_all == 0) return total <= 1000;
-  if (n[0] > 0 && n[1] > 0) {
-    const bool d = G->mode_ms[b][1] < G->mode_ms[b][0];
-    return (n[0] + n[1]) % 32 == 31 ? !d : d;
-  }
   double est_r, est_d;
   pass_estimates(G, b, total, est_r, est_d);
   if (est_d < 0) return total <= 1000;
-  // an edge-local estimate carried over from another bucket scales that
-  // bucket's time (fixed costs included) by the batch size, so it runs
-  // high for larger batches: the first edge-local try in a bucket is taken
-  // while it is within 1.5x of the region estimate
-  if (n[1] == 0) return est_d < 1.5 * est_r;
+  if (n[0] > 0 && n[1] > 0) {
+    const bool d = est_d < est_r;
+    return (n[0] + n[1]) % 32 == 31 ? !d : d;
+  }
+  if (n[1] == 0) return est_d < 1.25 * est_r;
   return est_d < est_r;
 }
 
@@ -1508,6 +1509,7 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
     avg = cnt == 0 ? ms : 0.75 * avg + 0.25 * ms;
     sz = cnt == 0 ? (double)L.total : 0.75 * sz + 0.25 * (double)L.total;
     ++cnt;
+    if (L.delta) G->delta_ms_min = G->delta_ms_min < 0 ? ms : std::min(G->delta_ms_min, ms);
     if (!L.delta) {
       G->region_ms_all = G->region_n_all == 0 ? ms : 0.75 * G->region_ms_all + 0.25 * ms;
       ++G->region_n_all;

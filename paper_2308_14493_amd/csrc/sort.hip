@@ -8,6 +8,8 @@
 //             rank within a wave by 8 ballots, across waves through LDS)
 // Counts may live on the device so that the whole sort is capturable with a
 // size known only to earlier kernels; tiles beyond the count exit at once.
+// Sorts whose capacity fits one workgroup's LDS run as one kernel
+// (k_rs_small).
 #include "gc_internal.h"
 
 namespace {
@@ -124,6 +126,76 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const unsigned long l
     run[tid] += add;
     __syncthreads();
   }
+}
+
+// Sorts of at most RSS_MAX keys (the ingest of batches of up to a few
+// thousand updates) in one workgroup: the keys stay in LDS through every
+// digit, each digit a stable counting sort (digit histogram by LDS atomics,
+// its exclusive scan by one wave, then the tile's ranking of k_rs_scatter in
+// rounds of RSS_T consecutive keys), so a sort is one launch instead of four
+// per digit.  Same digits, same stable order: the result equals the
+// multi-block sort's, and lands in the same buffer.
+constexpr int RSS_T = 1024;
+constexpr int RSS_MAX = 4096;
+constexpr int RSS_WAVES = RSS_T / 64;
+
+__global__ __launch_bounds__(RSS_T) void k_rs_small(const unsigned long long* keys,
+                                                    unsigned long long* out, int64_t max_count,
+                                                    const unsigned long long* d_count, int bits) {
+  __shared__ unsigned long long buf[2][RSS_MAX];
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[RSS_WAVES][256];
+  const int32_t count = (int32_t)rs_count(max_count, d_count);  // <= max_count <= RSS_MAX
+  const int tid = threadIdx.x, w = tid >> 6, l = lane_id();
+  for (int32_t i = tid; i < count; i += RSS_T) buf[0][i] = keys[i];
+  for (int k = tid; k < RSS_WAVES * 256; k += RSS_T) (&wcnt[0][0])[k] = 0u;
+  int cur = 0;
+  for (int shift = 0; shift < bits; shift += 8) {
+    const unsigned long long* src = buf[cur];
+    unsigned long long* dst = buf[cur ^ 1];
+    if (tid < 256) { hist[tid] = 0u; run[tid] = 0u; }
+    __syncthreads();
+    for (int32_t i = tid; i < count; i += RSS_T) atomicAdd(&hist[(uint32_t)(src[i] >> shift) & 255u], 1u);
+    __syncthreads();
+    if (w == 0) {  // exclusive scan of the 256 digit counts, four per lane
+      uint32_t c[4], t = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) { c[k] = hist[4 * l + k]; t += c[k]; }
+      uint32_t before = (uint32_t)wave_incl_scan32((int32_t)t) - t;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) { hist[4 * l + k] = before; before += c[k]; }
+    }
+    __syncthreads();
+    for (int32_t r0 = 0; r0 < count; r0 += RSS_T) {
+      const int32_t i = r0 + tid;
+      const bool valid = i < count;
+      const unsigned long long key = valid ? src[i] : 0ull;
+      const uint32_t d = (uint32_t)(key >> shift) & 255u;
+      uint64_t same = __ballot(valid);
+      for (int b = 0; b < 8; ++b) {
+        const uint64_t bb = __ballot((d >> b) & 1u);
+        same &= ((d >> b) & 1u) ? bb : ~bb;
+      }
+      const uint32_t wrank = (uint32_t)__popcll(same & lanemask_lt());
+      if (valid && (same & lanemask_lt()) == 0) wcnt[w][d] = (uint32_t)__popcll(same);
+      __syncthreads();
+      if (valid) {
+        uint32_t before = hist[d] + run[d];
+        for (int k = 0; k < w; ++k) before += wcnt[k][d];
+        dst[before + wrank] = key;
+      }
+      __syncthreads();
+      if (tid < 256) {
+        uint32_t add = 0;
+        for (int k = 0; k < RSS_WAVES; ++k) { add += wcnt[k][tid]; wcnt[k][tid] = 0u; }
+        run[tid] += add;
+      }
+      __syncthreads();
+    }
+    cur ^= 1;
+  }
+  for (int32_t i = tid; i < count; i += RSS_T) out[i] = buf[cur][i];
 }
 
 // ------------------------------------------------------------- scans
@@ -246,6 +318,11 @@ unsigned long long* radix_sort_u64(unsigned long long* keys, unsigned long long*
                                    int64_t max_count, const unsigned long long* d_count, int bits,
                                    hipStream_t s) {
   if (max_count <= 0 || bits <= 0) return keys;
+  if (max_count <= RSS_MAX) {
+    unsigned long long* out = radix_sort_result(keys, alt, max_count, bits);
+    hipLaunchKernelGGL(k_rs_small, dim3(1), dim3(RSS_T), 0, s, keys, out, max_count, d_count, bits);
+    return out;
+  }
   int64_t nblk = rs_nblk(max_count);
   uint32_t* hist = (uint32_t*)tmp;
   uint32_t* totals = hist + nblk * 256;

@@ -1325,9 +1325,13 @@ void apply(gc_graph* G, const gc_batch_desc* b, int nb, bool dev, bool seq, int6
   size_count_scratch(G, L.nv, L.union_bound);
   if (L.delta) {
     // at the demand per update seen so far (within 2^26 entries a list: a
-    // larger demand is met by the retry, which sizes for the batch at hand)
+    // larger demand is met by the retry, which sizes for the batch at hand);
+    // a common-neighbour slot holds the shorter row of a changed edge, at
+    // most about the largest lower degree counted (ids follow the degree
+    // order, so a hub's neighbours are nearly all below it)
     const double lim = (double)(1ll << 26);
-    size_delta(G, L.cap_t, (int64_t)std::min(lim, 1.25 * G->ae_per_update * (double)L.cap_t), 0,
+    size_delta(G, L.cap_t, (int64_t)std::min(lim, 1.25 * G->ae_per_update * (double)L.cap_t),
+               std::min<int64_t>(1ll << 26, G->seen_maxlow + G->seen_maxlow / 4 + 64),
                (int64_t)std::min(lim, 1.25 * G->pair_per_update * (double)L.cap_t));
   }
   // arena reserve: enough for every touched row to move

@@ -8,7 +8,9 @@
   (GC_ESTATE) instead of counting on a half-applied graph;
 * the global-scratch triangle tier (out-degree above the LDS tiers) and the
   per-version rebuild of a vertex with more version-specific edges than its
-  exception list holds, on dense graphs checked through the complement.
+  exception list holds, on dense graphs checked through the complement;
+* batches at the capacity edges of the one-workgroup sort (4096 keys, and
+  one past it), edge-local and region passes.
 """
 import numpy as np
 import pytest
@@ -206,3 +208,37 @@ def test_tier_trials_autotune_exact():
     kept = seen[-1]
     assert kept[0] in (64, 32) and (kept[1], kept[2]) in [(t[1], t[2]) for t in trials]
     assert seen[-2] == kept
+
+
+@pytest.mark.parametrize("delta", [1, -1])
+def test_sort_capacity_edges_exact(delta):
+    """Batches whose key counts sit at the edges of the one-workgroup sort:
+    2048 + 2048 updates (4096 keys: its capacity, full), 2049 + 2047 (the
+    keys and insertions then take the multi-block sort, the deletions the
+    small one), one insertion, and deletions only; no self-loops, so every
+    update is a key.  Edge-local and region passes, oracle after each."""
+    from paper_2308_14493_amd.graphlet4 import Graph
+    from graphgen import rmat_graph
+    say("case sort capacity edges delta=%d" % delta)
+    n, s, d, samp = rmat_graph(12, 8, 77)
+    E = set(zip(s.tolist(), d.tolist()))
+    rng = np.random.default_rng(78)
+
+    def batch(ni, nd):
+        iu = rng.integers(0, n, ni).astype(np.int32)
+        iv = ((iu + 1 + rng.integers(0, n - 1, ni)) % n).astype(np.int32)  # never equal to iu
+        el = sorted(E)
+        pick = rng.choice(len(el), nd, replace=False)
+        du = np.array([el[k][1] for k in pick], np.int32)  # reversed orientation on purpose
+        dv = np.array([el[k][0] for k in pick], np.int32)
+        return iu, iv, du, dv
+
+    with Graph(n, s, d, delta=delta) as g:
+        for ni, nd in [(2048, 2048), (2049, 2047), (1, 0), (0, 300), (2048, 2048)]:
+            b = batch(ni, nd)
+            got = g.apply_batch(*b)
+            oracle_apply(E, n, *b)
+            es, ed = esorted(E)
+            want = native.static_counts(n, es, ed)
+            say("  %d + %d updates: equal %s" % (ni, nd, got == want))
+            assert got == want

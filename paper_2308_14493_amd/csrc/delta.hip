@@ -1080,11 +1080,11 @@ void launch_delta(const DeltaArgs& D, int slots, hipStream_t s) {
   hipLaunchKernelGGL(k_delta_c4_plan, dim3(2048), dim3(TPB), 0, s, D);
   hipLaunchKernelGGL(k_delta_plan_fin, dim3(256), dim3(TPB), 0, s, D);
   exclusive_scan_i32_to_i64(D.c4_nch, D.c4_off, D.ce_cap, D.scan_tmp, s);
-  fill_u32((uint32_t*)D.pair_len, 0u, D.pair_cap, s);
-  fill_u32((uint32_t*)D.pair_hlen, 0u, D.pair_cap, s);
+  // every pair below the count c4_off[ce_cap] gets both lengths, and only
+  // offsets up to that count are read: no clearing, scans up to the count
   hipLaunchKernelGGL(k_delta_c4_pairs, dim3(1024), dim3(TPB), 0, s, D);
-  exclusive_scan_i32_to_i64(D.pair_len, D.pair_off, D.pair_cap, D.scan_tmp, s);
-  exclusive_scan_i32_to_i64(D.pair_hlen, D.pair_hoff, D.pair_cap, D.scan_tmp, s);
+  exclusive_scan_i32_to_i64_count(D.pair_len, D.pair_off, D.pair_cap, D.c4_off + D.ce_cap, D.scan_tmp, s);
+  exclusive_scan_i32_to_i64_count(D.pair_hlen, D.pair_hoff, D.pair_cap, D.c4_off + D.ce_cap, D.scan_tmp, s);
   hipLaunchKernelGGL(k_delta_hitems, dim3(256), dim3(TPB), 0, s, D);
   exclusive_scan_i32_to_i64(D.tv_items, D.tv_ioff, D.tcap, D.scan_tmp, s);
   unsigned long long* sorted =

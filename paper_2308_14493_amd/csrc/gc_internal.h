@@ -181,6 +181,10 @@ unsigned long long* radix_sort_result(unsigned long long* keys, unsigned long lo
 size_t scan_tmp_bytes(int64_t n);
 // out[i] = sum_{j<i} in[j] for i in [0, n]; out has n + 1 entries.
 void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t s);
+// the same over the first min(*d_n, n) entries (a count known only on the
+// device); out[*d_n] and out[n] get the total, entries in between are left
+void exclusive_scan_i32_to_i64_count(const int32_t* in, int64_t* out, int64_t n, const int64_t* d_n, void* tmp,
+                                     hipStream_t s);
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t s);
 
 // fill helpers (kernels, capturable)

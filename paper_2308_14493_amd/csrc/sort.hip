@@ -203,15 +203,25 @@ constexpr int SC_THREADS = 1024;
 constexpr int SC_ITEMS = 4;
 constexpr int SC_TILE = SC_THREADS * SC_ITEMS;
 
+// Scans may take their element count from the device (d_n, at most the
+// capacity n the grid is sized for): entries from the count on are neither
+// read nor written, and the total goes to out[count] and out[n].
+__device__ __forceinline__ int64_t scan_count(int64_t n, const int64_t* d_n) {
+  if (!d_n) return n;
+  const int64_t c = *d_n;
+  return c < 0 ? 0 : (c < n ? c : n);
+}
+
 template <class TIn>
 __global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const TIn* __restrict__ in, int64_t n,
-                                                            int64_t* __restrict__ bsum) {
+                                                            const int64_t* d_n, int64_t* __restrict__ bsum) {
   __shared__ int64_t ws[SC_THREADS / 64];
   const int64_t base = (int64_t)blockIdx.x * SC_TILE;
+  const int64_t nn = scan_count(n, d_n);
   int64_t s = 0;
   for (int k = 0; k < SC_ITEMS; ++k) {
     int64_t i = base + (int64_t)k * SC_THREADS + threadIdx.x;
-    if (i < n) s += (int64_t)in[i];
+    if (i < nn) s += (int64_t)in[i];
   }
   s = wave_sum64(s);
   if (lane_id() == 0) ws[threadIdx.x >> 6] = s;
@@ -247,16 +257,17 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_top(int64_t* __restrict__ b
 
 template <class TIn>
 __global__ __launch_bounds__(SC_THREADS) void k_scan_down(const TIn* __restrict__ in, int64_t n,
-                                                          const int64_t* __restrict__ bsum,
+                                                          const int64_t* d_n, const int64_t* __restrict__ bsum,
                                                           int64_t* __restrict__ out) {
   __shared__ int64_t ws[SC_THREADS / 64];
   // each thread owns SC_ITEMS consecutive elements
   const int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
+  const int64_t nn = scan_count(n, d_n);
   int64_t v[SC_ITEMS];
   int64_t s = 0;
   for (int k = 0; k < SC_ITEMS; ++k) {
     int64_t i = base + k;
-    v[k] = i < n ? (int64_t)in[i] : 0;
+    v[k] = i < nn ? (int64_t)in[i] : 0;
     s += v[k];
   }
   int64_t inc = wave_incl_scan64(s);
@@ -268,11 +279,14 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_down(const TIn* __restrict_
   int64_t run = before + inc - s;
   for (int k = 0; k < SC_ITEMS; ++k) {
     int64_t i = base + k;
-    if (i < n) out[i] = run;
+    if (i < nn) out[i] = run;
     run += v[k];
   }
-  // total at out[n]
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SC_THREADS - 1) out[n] = run;
+  // total at out[n] (and at out[count])
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SC_THREADS - 1) {
+    out[n] = run;
+    if (nn < n) out[nn] = run;
+  }
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
@@ -297,13 +311,13 @@ __global__ void k_fill_u64_count(unsigned long long* p, unsigned long long v, co
 inline int64_t rs_nblk(int64_t max_count) { return (max_count + RS_TILE - 1) / RS_TILE; }
 
 template <class TIn>
-void scan_impl(const TIn* in, int64_t* out, int64_t n, void* tmp, hipStream_t s) {
+void scan_impl(const TIn* in, int64_t* out, int64_t n, void* tmp, hipStream_t s, const int64_t* d_n = nullptr) {
   int64_t nb = (n + SC_TILE - 1) / SC_TILE;
   if (nb == 0) nb = 1;
   int64_t* bsum = (int64_t*)tmp;
-  hipLaunchKernelGGL(k_scan_reduce<TIn>, dim3((unsigned)nb), dim3(SC_THREADS), 0, s, in, n, bsum);
+  hipLaunchKernelGGL(k_scan_reduce<TIn>, dim3((unsigned)nb), dim3(SC_THREADS), 0, s, in, n, d_n, bsum);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SC_THREADS), 0, s, bsum, nb);
-  hipLaunchKernelGGL(k_scan_down<TIn>, dim3((unsigned)nb), dim3(SC_THREADS), 0, s, in, n, bsum, out);
+  hipLaunchKernelGGL(k_scan_down<TIn>, dim3((unsigned)nb), dim3(SC_THREADS), 0, s, in, n, d_n, bsum, out);
 }
 
 }  // namespace
@@ -352,6 +366,10 @@ size_t scan_tmp_bytes(int64_t n) { return (size_t)((n + SC_TILE - 1) / SC_TILE +
 
 void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t s) {
   scan_impl<int32_t>(in, out, n, tmp, s);
+}
+void exclusive_scan_i32_to_i64_count(const int32_t* in, int64_t* out, int64_t n, const int64_t* d_n, void* tmp,
+                                     hipStream_t s) {
+  scan_impl<int32_t>(in, out, n, tmp, s, d_n);
 }
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t s) {
   scan_impl<int64_t>(in, out, n, tmp, s);

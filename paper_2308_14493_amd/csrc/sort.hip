@@ -7,7 +7,8 @@
 //   scatter : stable rank inside the tile (16 rounds of 256 consecutive keys;
 //             rank within a wave by 8 ballots, across waves through LDS)
 // Counts may live on the device so that the whole sort is capturable with a
-// size known only to earlier kernels; tiles beyond the count exit at once.
+// size known only to earlier kernels; tiles beyond the count exit at once,
+// and the histogram scans read only the tiles that hold keys.
 // Sorts whose capacity fits one workgroup's LDS run as one kernel
 // (k_rs_small).
 #include "gc_internal.h"
@@ -31,30 +32,36 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const unsigned long long
   __shared__ uint32_t h[256];
   const int64_t count = rs_count(max_count, d_count);
   const int64_t blk = blockIdx.x;
+  const int64_t base = blk * RS_TILE;
+  if (base >= count) return;  // tiles past the count are not scanned (uniform per block)
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = blk * RS_TILE;
-  if (base < count) {
-    for (int r = 0; r < RS_ROUNDS; ++r) {
-      int64_t i = base + r * RS_THREADS + threadIdx.x;
-      if (i < count) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
-    }
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    int64_t i = base + r * RS_THREADS + threadIdx.x;
+    if (i < count) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
   }
   __syncthreads();
   hist[(int64_t)threadIdx.x * nblk + blk] = h[threadIdx.x];
 }
 
+// tiles holding keys: the histogram rows are read only that far
+__device__ __forceinline__ int64_t rs_tiles(int64_t max_count, const unsigned long long* d_count) {
+  return (rs_count(max_count, d_count) + RS_TILE - 1) / RS_TILE;
+}
+
 // One block per digit: exclusive scan of that digit's row; row total out.
 __global__ __launch_bounds__(1024) void k_rs_rowscan(uint32_t* __restrict__ hist, int64_t nblk,
-                                                     uint32_t* __restrict__ totals) {
+                                                     uint32_t* __restrict__ totals, int64_t max_count,
+                                                     const unsigned long long* d_count) {
   __shared__ uint32_t wsum[16];
   __shared__ uint32_t carry;
   uint32_t* row = hist + (int64_t)blockIdx.x * nblk;
+  const int64_t nt = rs_tiles(max_count, d_count);
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
-  for (int64_t base = 0; base < nblk; base += 1024) {
+  for (int64_t base = 0; base < nt; base += 1024) {
     int64_t i = base + threadIdx.x;
-    uint32_t v = i < nblk ? row[i] : 0u;
+    uint32_t v = i < nt ? row[i] : 0u;
     int32_t inc = wave_incl_scan32((int32_t)v);
     const int w = threadIdx.x >> 6;
     if (lane_id() == 63) wsum[w] = (uint32_t)inc;
@@ -62,7 +69,7 @@ __global__ __launch_bounds__(1024) void k_rs_rowscan(uint32_t* __restrict__ hist
     uint32_t before = 0;
     for (int k = 0; k < w; ++k) before += wsum[k];
     uint32_t c = carry;
-    if (i < nblk) row[i] = c + before + (uint32_t)inc - v;
+    if (i < nt) row[i] = c + before + (uint32_t)inc - v;
     __syncthreads();
     if (threadIdx.x == 1023) carry = c + before + (uint32_t)inc;
     __syncthreads();
@@ -71,17 +78,22 @@ __global__ __launch_bounds__(1024) void k_rs_rowscan(uint32_t* __restrict__ hist
 }
 
 __global__ __launch_bounds__(256) void k_rs_addtotals(uint32_t* __restrict__ hist, int64_t nblk,
-                                                      const uint32_t* __restrict__ totals) {
+                                                      const uint32_t* __restrict__ totals, int64_t max_count,
+                                                      const unsigned long long* d_count) {
   __shared__ uint32_t pre[256];
+  const int64_t nt = rs_tiles(max_count, d_count);
+  if (nt == 0) return;  // uniform
   if (threadIdx.x == 0) {
     uint32_t s = 0;
     for (int d = 0; d < 256; ++d) { pre[d] = s; s += totals[d]; }
   }
   __syncthreads();
-  const int64_t total = nblk * 256;
+  const int64_t total = nt * 256;  // digit d, tile b < nt: hist[d * nblk + b]
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x)
-    hist[i] += pre[i / nblk];
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t d = i / nt;
+    hist[d * nblk + (i - d * nt)] += pre[d];
+  }
 }
 
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const unsigned long long* __restrict__ keys,
@@ -345,10 +357,10 @@ unsigned long long* radix_sort_u64(unsigned long long* keys, unsigned long long*
   for (int shift = 0; shift < bits; shift += 8) {
     hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(RS_THREADS), 0, s, src, max_count, d_count,
                        shift, hist, nblk);
-    hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(1024), 0, s, hist, nblk, totals);
+    hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(1024), 0, s, hist, nblk, totals, max_count, d_count);
     unsigned g = (unsigned)((nblk * 256 + 255) / 256);
     if (g > 4096) g = 4096;
-    hipLaunchKernelGGL(k_rs_addtotals, dim3(g), dim3(256), 0, s, hist, nblk, totals);
+    hipLaunchKernelGGL(k_rs_addtotals, dim3(g), dim3(256), 0, s, hist, nblk, totals, max_count, d_count);
     hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(RS_THREADS), 0, s, src, dst, max_count,
                        d_count, shift, hist, nblk);
     unsigned long long* t = src; src = dst; dst = t;

@@ -1,6 +1,7 @@
 """GPU parity at the stated sizes of the workloads, with the library's
 default knobs (no environment overrides): the plain per-batch path after
-every batch, and the pool of 256 graphs in one pass, against counts stored by
+every batch, the scale-22 stream with every batch edge-local or every batch
+a region pass, and the pool of 256 graphs in one pass, against counts stored by
 tests/golden/make_scale.py, which calls only the oracle (static recount of
 the whole graph after every batch) and the input generators.  The inputs are
 drawn again here from the same seeds; their digest must equal the stored one
@@ -104,3 +105,34 @@ def test_pool256_one_round():
         assert over > 0
     finally:
         pool.close()
+
+
+@pytest.fixture(scope="module")
+def s22_stream():
+    w, _, _ = wl.rmat_s22_bench_stream(total=25)
+    return w
+
+
+@pytest.mark.parametrize("delta", [1, -1])
+def test_rmat_s22_stream_one_pass_kind(s22_stream, delta):
+    """R-MAT scale 22, ef 16 (n = 4,194,304, m = 67,108,864) and its 25
+    batches of log-uniform size in [10, 1e5], every batch through the same
+    kind of pass (1: edge-local, also for batches of 57,032 updates; -1:
+    region or whole-graph), against the oracle's counts before and after
+    the stream."""
+    from paper_2308_14493_amd.graphlet4 import Graph
+    say("case rmat_s22 stream delta=%d" % delta)
+    w = s22_stream
+    gold = golden("scale_rmat_s22_bench.json")
+    assert gold["steps"] == [0, 25]
+    assert wl.prefix_digest(w, 0) == gold["prefix_sha256"][0], "graph differs from the stored one"
+    assert wl.prefix_digest(w, 25) == gold["prefix_sha256"][1], "batches differ from the stored ones"
+    with Graph(w.n, w.src, w.dst, delta=delta) as g:
+        assert g.counts() == gold["counts"][0], "initial counts"
+        for j, b in enumerate(w.batches):
+            got, st = g.apply_batch(*b, stats=True)
+            assert st["delta"] == (1 if delta == 1 else 0)
+        say("  after %d batches: equal %s" % (len(w.batches), got == gold["counts"][1]))
+        assert got == gold["counts"][1], "counts after the stream"
+        assert g.info()["m"] == gold["m"][1]
+        check_int64(g, got)

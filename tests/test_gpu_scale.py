@@ -45,12 +45,12 @@ def check_int64(g, want, graph=0):
         assert bool(mask >> c & 1) == (want[c] > INT64_MAX), "class %d overflow bit" % c
 
 
-def run_stream(w, gold, dev_every=0):
+def run_stream(w, gold, dev_every=0, delta=None):
     from paper_2308_14493_amd.graphlet4 import Graph
     assert wl.workload_digest(w) == gold["input_sha256"], "inputs differ from the stored ones"
     steps = gold["steps"]
     assert steps == list(range(len(w.batches) + 1))
-    with Graph(w.n, w.src, w.dst) as g:
+    with Graph(w.n, w.src, w.dst, delta=delta) as g:
         assert g.counts() == gold["counts"][0], "initial counts"
         check_int64(g, gold["counts"][0])
         for j, b in enumerate(w.batches):
@@ -60,26 +60,32 @@ def run_stream(w, gold, dev_every=0):
                 got, st = g.apply_batch_dev(*db, stats=True)
             else:
                 got, st = g.apply_batch(*b, stats=True)
-            say("%s batch %d (%d updates, whole %d): %s" % (w.name, j, b[0].size + b[2].size, st["whole_graph"],
-                                                          got == gold["counts"][j + 1]))
+            say("%s batch %d (%d updates, whole %d, edge-local %d): %s" % (
+                w.name, j, b[0].size + b[2].size, st["whole_graph"], st["delta"], got == gold["counts"][j + 1]))
             assert got == gold["counts"][j + 1], "counts after batch %d" % j
+            if delta == 1:
+                assert st["delta"] == 1
             assert g.info()["m"] == gold["m"][j + 1]
             assert g.last_int64 == [x & (2**64 - 1) for x in got]
             check_int64(g, got)
 
 
-def test_rmat_s18_ef8_every_batch():
+@pytest.mark.parametrize("delta", [None, 1])
+def test_rmat_s18_ef8_every_batch(delta):
     """R-MAT scale 18, ef 8; ten batches each of 1k, 10k and 100k updates;
-    every third batch through the device-array entry point."""
-    say("case rmat_s18_ef8 stream")
-    run_stream(wl.rmat_s18_stream(), golden("scale_rmat_s18_ef8.json"), dev_every=3)
+    every third batch through the device-array entry point; the pass kind
+    chosen by the library, or every batch edge-local."""
+    say("case rmat_s18_ef8 stream delta=%s" % delta)
+    run_stream(wl.rmat_s18_stream(), golden("scale_rmat_s18_ef8.json"), dev_every=3, delta=delta)
 
 
-def test_chung_lu_2_4m_every_batch():
+@pytest.mark.parametrize("delta", [None, 1])
+def test_chung_lu_2_4m_every_batch(delta):
     """Chung-Lu n = 2.4M, m = 5M, gamma 2.1: hubs of tens of thousands of
-    neighbours, batches of 1e3, 1e4 and 1e5 degree-proportional updates."""
-    say("case chung_lu 2.4M/5M stream")
-    run_stream(wl.chung_lu_stream(), golden("scale_chung_lu.json"))
+    neighbours, batches of 1e3, 1e4 and 1e5 degree-proportional updates; the
+    pass kind chosen by the library, or every batch edge-local."""
+    say("case chung_lu 2.4M/5M stream delta=%s" % delta)
+    run_stream(wl.chung_lu_stream(), golden("scale_chung_lu.json"), delta=delta)
 
 
 def test_pool256_one_round():

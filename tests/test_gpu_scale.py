@@ -88,15 +88,17 @@ def test_chung_lu_2_4m_every_batch(delta):
     run_stream(wl.chung_lu_stream(), golden("scale_chung_lu.json"), delta=delta)
 
 
-def test_pool256_one_round():
+@pytest.mark.parametrize("delta", [None, 1])
+def test_pool256_one_round(delta):
     """The 256-graph pool: initial counts and the counts after one batch per
-    graph in one pooled pass, graph by graph."""
+    graph in one pooled pass (the pass kind chosen by the library, or
+    edge-local), graph by graph."""
     from paper_2308_14493_amd.graphlet4 import Graph
-    say("case pool256")
+    say("case pool256 delta=%s" % delta)
     gold = golden("scale_pool256.json")
     graphs = wl.pool256()
     assert wl.pool_digest(graphs) == gold["input_sha256"]
-    pool = Graph.pool([x["n"] for x in graphs], [x["src"] for x in graphs], [x["dst"] for x in graphs])
+    pool = Graph.pool([x["n"] for x in graphs], [x["src"] for x in graphs], [x["dst"] for x in graphs], delta=delta)
     try:
         for i in range(len(graphs)):
             assert pool.counts(i) == gold["counts_initial"][i], "graph %d initial" % i

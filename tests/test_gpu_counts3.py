@@ -1,7 +1,9 @@
 """GPU: the induced 3-vertex counts (triangle, 2-path, edge + isolated,
 empty) of the resident graph against the oracle (brute force over 3-subsets
-where small, else its static recount) after every batch, single graphs and
-a pool; at the R-MAT scale-18 size the four counts must add up to C(n, 3)."""
+where small, else its static recount) after every batch, single graphs (the
+pass kind chosen by the library, every batch edge-local, every batch a
+region pass) and a pool; at the R-MAT scale-18 size the four counts must add
+up to C(n, 3)."""
 import math
 
 import numpy as np
@@ -19,13 +21,14 @@ def esorted(E):
     return (np.array([u for u, v in E], np.int32), np.array([v for u, v in E], np.int32))
 
 
-def test_counts3_er150_brute_force():
+@pytest.mark.parametrize("delta", [None, 1, -1])
+def test_counts3_er150_brute_force(delta):
     from paper_2308_14493_amd.graphlet4 import Graph
-    print("case counts3 er150", flush=True)
+    print("case counts3 er150 delta=%s" % delta, flush=True)
     n = 150
     s, d = erdos_renyi(n, 6 / 149, 0)
     E = set(zip(s.tolist(), d.tolist()))
-    with Graph(n, s, d) as g:
+    with Graph(n, s, d, delta=delta) as g:
         assert g.counts3() == native.brute3_counts(n, s, d)
         for b in er_batches(n, s, d):
             g.apply_batch(*b)
@@ -33,13 +36,14 @@ def test_counts3_er150_brute_force():
             assert g.counts3() == native.brute3_counts(n, *esorted(E))
 
 
+@pytest.mark.parametrize("delta", [None, 1, -1])
 @pytest.mark.parametrize("scale,ef,seed", [(12, 8, 71), (14, 16, 72)])
-def test_counts3_rmat_messy(scale, ef, seed):
+def test_counts3_rmat_messy(scale, ef, seed, delta):
     from paper_2308_14493_amd.graphlet4 import Graph
-    print("case counts3 rmat scale=%d" % scale, flush=True)
+    print("case counts3 rmat scale=%d delta=%s" % (scale, delta), flush=True)
     n, s, d, samp = rmat_graph(scale, ef, seed)
     E = set(zip(s.tolist(), d.tolist()))
-    with Graph(n, s, d) as g:
+    with Graph(n, s, d, delta=delta) as g:
         for k, b in enumerate(rmat_batches(n, s, d, samp, [50, 3000, 20000], seed + 1)):
             if k == 1:
                 b = raw_noise_batch(n, *esorted(E), 300, seed + 2)

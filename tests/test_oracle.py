@@ -357,3 +357,40 @@ def test_vertex_removal_vs_subset_brute():
         assert native.static_counts(n2, s2, d2) == want
         with pytest.raises(BatchRejected):
             remove_vertices(E2, live, [min(S)])
+
+
+# Per class (order of the eleven counts): edges e(c), 2-paths w(c) (pairs of
+# edges sharing an end) and triangles tau(c) inside the induced subgraph.
+E_OF = [3, 3, 4, 4, 5, 6, 3, 2, 2, 1, 0]
+W_OF = [2, 3, 4, 5, 8, 12, 3, 1, 0, 0, 0]
+TAU_OF = [0, 0, 0, 1, 2, 4, 1, 0, 0, 0, 0]
+
+
+@pytest.mark.parametrize("kind,seed", [("rmat10", 5), ("rmat11", 6), ("er1500", 7)])
+def test_weighted_identities(kind, seed):
+    """Counting the 4-subsets by what they contain: each edge lies in
+    C(n-2, 2) of them, each 2-path in n-3 and each triangle in n-3, so
+    sum_c e(c) I_c = m C(n-2, 2), sum_c w(c) I_c = W (n-3) with W the 2-paths
+    of the graph, and sum_c tau(c) I_c = T (n-3).  m, W and T come from the
+    degrees and a dense adjacency product, independently of the oracle, on
+    graphs too large for brute force (n up to 2048)."""
+    if kind == "rmat10":
+        n, s, d, _ = rmat_graph(10, 16, seed)
+    elif kind == "rmat11":
+        n, s, d, _ = rmat_graph(11, 8, seed)
+    else:
+        n = 1500
+        s, d = erdos_renyi(n, 0.02, seed)
+    I = native.static_counts(n, s, d)
+    m = int(s.size)
+    deg = np.bincount(s, minlength=n) + np.bincount(d, minlength=n)
+    W = int(sum(int(x) * (int(x) - 1) // 2 for x in deg))
+    A = np.zeros((n, n))
+    A[s, d] = 1.0
+    A[d, s] = 1.0
+    T = int(round(float((A @ A)[s, d].sum()) / 3))  # common neighbours per edge, each triangle thrice
+    assert sum(I) == C(n, 4)
+    assert sum(e * x for e, x in zip(E_OF, I)) == m * C(n - 2, 2)
+    assert sum(w * x for w, x in zip(W_OF, I)) == W * (n - 3)
+    assert sum(t * x for t, x in zip(TAU_OF, I)) == T * (n - 3)
+    assert T > 0

@@ -394,3 +394,10 @@ def test_weighted_identities(kind, seed):
     assert sum(w * x for w, x in zip(W_OF, I)) == W * (n - 3)
     assert sum(t * x for t, x in zip(TAU_OF, I)) == T * (n - 3)
     assert T > 0
+    # the 3-vertex classes (triangle, 2-path, edge + isolated, empty): each
+    # edge lies in n - 2 triples, each 2-path in one, each triangle in one
+    I3 = native.static_counts3(n, s, d)
+    assert sum(I3) == C(n, 3)
+    assert 3 * I3[0] + 2 * I3[1] + I3[2] == m * (n - 2)
+    assert 3 * I3[0] + I3[1] == W
+    assert I3[0] == T

@@ -10,6 +10,7 @@ equality of all eleven classes, and the int64 view (low 64 bits plus the
 overflow mask) is checked against the exact value.
 """
 import json
+import math
 import os
 
 import numpy as np
@@ -21,6 +22,9 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 INT64_MAX = 2**63 - 1
+# edges and 2-paths inside each of the eleven classes (in count order)
+E_OF = [3, 3, 4, 4, 5, 6, 3, 2, 2, 1, 0]
+W_OF = [2, 3, 4, 5, 8, 12, 3, 1, 0, 0, 0]
 
 
 def say(*a):
@@ -135,12 +139,24 @@ def test_rmat_s22_stream_one_pass_kind(s22_stream, delta):
     assert gold["steps"] == [0, 25]
     assert wl.prefix_digest(w, 0) == gold["prefix_sha256"][0], "graph differs from the stored one"
     assert wl.prefix_digest(w, 25) == gold["prefix_sha256"][1], "batches differ from the stored ones"
-    with Graph(w.n, w.src, w.dst, delta=delta) as g:
+    n = w.n
+    with Graph(n, w.src, w.dst, delta=delta) as g:
         assert g.counts() == gold["counts"][0], "initial counts"
         for j, b in enumerate(w.batches):
             got, st = g.apply_batch(*b, stats=True)
             assert st["delta"] == (1 if delta == 1 else 0)
+            # between the stored points, identities that hold for any graph:
+            # the classes partition the 4-subsets, and each edge lies in
+            # C(n-2, 2) of them
+            m = g.info()["m"]
+            assert sum(got) == math.comb(n, 4), "batch %d: sum" % j
+            assert sum(e * x for e, x in zip(E_OF, got)) == m * math.comb(n - 2, 2), "batch %d: edges" % j
         say("  after %d batches: equal %s" % (len(w.batches), got == gold["counts"][1]))
         assert got == gold["counts"][1], "counts after the stream"
         assert g.info()["m"] == gold["m"][1]
         check_int64(g, got)
+        # each 2-path lies in n - 3 of the 4-subsets; W from the exported edges
+        es, ed = g.edges()
+        deg = np.bincount(es, minlength=n).astype(np.int64) + np.bincount(ed, minlength=n)
+        W = int((deg * (deg - 1) // 2).sum())
+        assert sum(x * c for x, c in zip(W_OF, got)) == W * (n - 3)

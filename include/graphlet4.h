@@ -332,6 +332,18 @@ int gc_graph_footprint(int64_t n, const int32_t* src, const int32_t* dst, int64_
  * (library interface). */
 int gc_graph_replays(const gc_graph* g, int64_t* captures, int64_t* launches);
 
+/* Copies what the online autotuner of src has learned into dst: the
+ * hub-window threshold and the tier thresholds with their trials (the tier
+ * thresholds only when dst's are not fixed by gc_options.tiers), the
+ * whole-graph switch per batch-size decade, the measured costs of region,
+ * edge-local and multi-version passes, and the edge-local list demand per
+ * update.  A new handle on the same or a similar graph then skips the trials
+ * and starts from those measurements.  Speed knobs only: counts do not
+ * change, whatever the two graphs.  Host state only (no device work); call
+ * it while neither handle is in use by another thread.  GC_EINVAL for a
+ * NULL handle (library interface, not in the paper). */
+int gc_copy_tuning(gc_graph* dst, const gc_graph* src);
+
 /* Frees the handle and its device memory (library interface). */
 int gc_graph_free(gc_graph* g);
 

@@ -2139,6 +2139,41 @@ int gc_graph_replays(const gc_graph* g, int64_t* captures, int64_t* launches) {
   });
 }
 
+int gc_copy_tuning(gc_graph* dst, const gc_graph* src) {
+  return guard([&] {
+    if (!dst || !src) raise(GC_EINVAL, "NULL argument");
+    if (dst == src) return;
+    // hub-window threshold and its trials
+    dst->tune_cands = src->tune_cands;
+    dst->tune_ms = src->tune_ms;
+    dst->tune_wedges = src->tune_wedges;
+    dst->tune_next = src->tune_next;
+    dst->dense_min_best = src->dense_min_best;
+    // tier thresholds and their trials (unless the destination's are forced)
+    if (!dst->tiers_forced) {
+      dst->tier_cands = src->tier_cands;
+      dst->tier_tri_cost = src->tier_tri_cost;
+      dst->tier_c4_cost = src->tier_c4_cost;
+      dst->tier_next = src->tier_next;
+      std::copy(src->tiers_best, src->tiers_best + 3, dst->tiers_best);
+      std::copy(src->tiers_best, src->tiers_best + 3, dst->tiers_now);
+    }
+    // whole-graph switch, pass-kind and multi-version cost models, and the
+    // edge-local list demand per update
+    std::copy(src->region_frac, src->region_frac + 8, dst->region_frac);
+    std::copy(&src->mode_ms[0][0], &src->mode_ms[0][0] + 32, &dst->mode_ms[0][0]);
+    std::copy(&src->mode_sz[0][0], &src->mode_sz[0][0] + 32, &dst->mode_sz[0][0]);
+    std::copy(&src->mode_n[0][0], &src->mode_n[0][0] + 32, &dst->mode_n[0][0]);
+    dst->region_ms_all = src->region_ms_all;
+    dst->region_n_all = src->region_n_all;
+    dst->delta_ms_min = src->delta_ms_min;
+    std::copy(src->multi_ms, src->multi_ms + GC_NV_MAX, dst->multi_ms);
+    std::copy(src->multi_n, src->multi_n + GC_NV_MAX, dst->multi_n);
+    dst->ae_per_update = src->ae_per_update;
+    dst->pair_per_update = src->pair_per_update;
+  });
+}
+
 int gc_graph_free(gc_graph* g) {
   if (!g) return GC_OK;
   (void)hipSetDevice(g->device);

@@ -63,7 +63,7 @@ _lib = None
 EXPORTS = ["gc_options_default", "gc_graph_init", "gc_pool_init", "gc_apply_batch", "gc_apply_batch_dev",
            "gc_apply_batch_dev_noalloc",
            "gc_apply_batches", "gc_apply_batch_seq", "gc_add_vertices", "gc_remove_vertices", "gc_get_counts", "gc_get_counts_exact", "gc_get_counts3", "gc_recount_exact", "gc_graph_info",
-           "gc_export_edges", "gc_graph_footprint", "gc_graph_replays", "gc_graph_free", "gc_strerror", "gc_last_error",
+           "gc_export_edges", "gc_graph_footprint", "gc_graph_replays", "gc_copy_tuning", "gc_graph_free", "gc_strerror", "gc_last_error",
            "gc_server_opts_default", "gc_server_create", "gc_server_add_graph", "gc_server_submit",
            "gc_server_wait", "gc_server_counts", "gc_server_destroy"]
 
@@ -105,6 +105,7 @@ def load(path: str = LIB_PATH):
     lib.gc_graph_info.argtypes = [_P, ctypes.POINTER(_I32), _I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]
     lib.gc_export_edges.argtypes = [_P, _I32, _P, _P, _I64, ctypes.POINTER(_I64)]
     lib.gc_graph_replays.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]
+    lib.gc_copy_tuning.argtypes = [_P, _P]
     lib.gc_graph_footprint.argtypes = [_I64, _P, _P, _I64, ctypes.POINTER(Options), ctypes.POINTER(_I64)]
     lib.gc_graph_free.argtypes = [_P]
     lib.gc_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
@@ -303,6 +304,11 @@ class Graph:
                                       ctypes.cast(sts, _P) if stats else None))
         rows = [[int(x) for x in out[j]] for j in range(nb)]
         return (rows, [sts[j].as_dict() for j in range(nb)]) if stats else rows
+
+    def copy_tuning(self, src):
+        """gc_copy_tuning: start from what the autotuner of handle `src` has
+        learned (speed knobs only; counts do not change)."""
+        _check(load().gc_copy_tuning(self._h, src._h))
 
     def graph_replays(self):
         """(passes captured as HIP graphs, passes launched from captured graphs)."""

@@ -43,6 +43,7 @@ def test_error_strings_without_device():
     assert lib.gc_options_default(ctypes.byref(o)) == 0
     assert o.radius == 2 and abs(o.slack - 0.25) < 1e-6
     assert lib.gc_options_default(None) == -1
+    assert lib.gc_copy_tuning(None, None) == -1
 
 
 def test_server_admission_refusal_without_device():

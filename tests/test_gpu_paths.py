@@ -242,3 +242,35 @@ def test_sort_capacity_edges_exact(delta):
             want = native.static_counts(n, es, ed)
             say("  %d + %d updates: equal %s" % (ni, nd, got == want))
             assert got == want
+
+
+def test_copy_tuning_skips_trials():
+    """gc_copy_tuning: a second handle on the same graph takes over what the
+    first one's autotuner learned (its trials done on ten region passes), so
+    its first pass already runs with the first handle's knobs; counts stay
+    exact on both."""
+    from paper_2308_14493_amd.graphlet4 import Graph
+    from graphgen import rmat_batches, rmat_graph
+    say("case copy tuning")
+    n, s, d, samp = rmat_graph(12, 16, 93)
+    E = set(zip(s.tolist(), d.tolist()))
+    batches = rmat_batches(n, s, d, samp, [300] * 12 + [500], 94)
+    with Graph(n, s, d, delta=-1) as a:
+        seen = set()
+        for b in batches[:12]:
+            _, st = a.apply_batch(*b, stats=True)
+            oracle_apply(E, n, *b)
+            seen.add((st["c4_dense_min"], st["tri_small_max"], st["c4_small_max"], st["c4_mid_max"]))
+        assert len(seen) > 1, "the autotuner tried no knobs"
+        es, ed = esorted(E)
+        with Graph(n, es, ed, delta=-1) as b2:
+            b2.copy_tuning(a)
+            last = batches[12]
+            ga, sa = a.apply_batch(*last, stats=True)
+            gb, sb = b2.apply_batch(*last, stats=True)
+            oracle_apply(E, n, *last)
+            want = native.static_counts(n, *esorted(E))
+            knobs = lambda x: (x["c4_dense_min"], x["tri_small_max"], x["c4_small_max"], x["c4_mid_max"])
+            say("  knobs seen %s; copied %s, source %s" % (sorted(seen), knobs(sb), knobs(sa)))
+            assert ga == want and gb == want
+            assert knobs(sb) == knobs(sa)
